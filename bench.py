@@ -1,0 +1,186 @@
+"""Benchmark: D3Q27 mixture lattice Boltzmann step on one MI355X.
+
+Workload: the binary Kelvin--Helmholtz shear layer on a 256^3 periodic grid
+(molar masses 2 and 28, u_x = +-0.1 with tanh profiles, seeded noise), FP32
+population storage. A step is one pass of the whole path: moments, stencil
+field, collide-and-stream over all 16.8 M nodes.
+
+Prints one JSON line (the last line of stdout) with MLUPS, the HBM roofline of
+the dominant kernel (timed with HIP events on the library's stream), the other
+storage precisions measured side by side with their per-field error against the
+FP32 run, and the FP64 CPU oracle timed on a bounded crop of the same workload.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32|fp32_fp32|fp16|bf16|fp64]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+REC_FIELDS = 5               # node record: Phi_x, Phi_y, Phi_z, omega, C_p
+G_FIELDS = 3
+
+
+def algorithmic_bytes(M: int, s_bytes: int, r_bytes: int) -> dict:
+    """Bytes each kernel must move per node (every value read or written once)."""
+    L = M + 1
+    pops = L * 27 * s_bytes
+    return {
+        "k_moments": pops + REC_FIELDS * r_bytes,
+        "k_gfield": 4 * r_bytes + G_FIELDS * r_bytes,
+        "k_collide": 2 * pops + 4 * r_bytes,
+        "step": 3 * pops + 16 * r_bytes,
+        "method_min": 2 * pops,
+    }
+
+
+def record_bytes(precision: int, mc) -> int:
+    return 8 if precision in (mc.MCLBM_FP64, mc.MCLBM_FP32) else 4
+
+
+def time_run(mc, params, fields, precision, steps, warmup):
+    import torch
+
+    sim = mc.Sim(params, precision)
+    sim.init_fields(**fields)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    sim.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stats = {}
+    for k in (mc.MCLBM_K_MOMENTS, mc.MCLBM_K_GFIELD, mc.MCLBM_K_COLLIDE):
+        ms, launches, name = sim.kernel_stats(k)
+        stats[name] = {"total_ms": ms, "launches": launches, "avg_ms": ms / max(launches, 1)}
+    sim.set_timing(False)
+    return sim, t1 - t0, stats
+
+
+def cpu_baseline(seconds_target: float = 15.0):
+    """The FP64 oracle, unchanged, on a 64 x 64 x 16 crop of the shear layer
+    (same recipe, smaller box), timed over whole steps."""
+    from oracle import oracle as O
+    from paper_2004_11286_amd import workloads as W
+
+    O.build()
+    params, fields = W.shear_layer(nx=64, ny=64, nz=16)
+    o = O.OracleSim(params)
+    o.init_fields(**fields)
+    o.step(1)                                  # first touch
+    n = 64 * 64 * 16
+    steps, elapsed = 0, 0.0
+    while elapsed < seconds_target and steps < 200:
+        t0 = time.perf_counter()
+        o.step(1)
+        elapsed += time.perf_counter() - t0
+        steps += 1
+    return {"value": n * steps / elapsed / 1e6, "unit": "MLUPS", "cores": O.threads(), "kind": "oracle",
+            "sample": f"FP64 oracle, {steps} steps of a 64x64x16 crop of the shear-layer recipe "
+                      f"({elapsed:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--n", type=int, default=256, help="cube edge")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
+              "(the multi-GPU slab decomposition is a design, not an implementation)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2004_11286_amd import mclbm as mc
+    from paper_2004_11286_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    params, fields = W.shear_layer(nx=args.n, ny=args.n, nz=args.n)
+    M = params["M"]
+    n = args.n ** 3
+    prec = mc.PRECISIONS[args.precision]
+    sim, elapsed, stats = time_run(mc, params, fields, prec, args.steps, args.warmup)
+    mlups = n * args.steps / elapsed / 1e6
+    sb, rb = mc.STORAGE_BYTES[prec], record_bytes(prec, mc)
+    ab = algorithmic_bytes(M, sb, rb)
+    col = stats["k_collide"]
+    achieved = ab["k_collide"] * n / (col["avg_ms"] * 1e-3) / 1e9
+    kernel_gbs = {k: ab[k] * n / (v["avg_ms"] * 1e-3) / 1e9 for k, v in stats.items()}
+    ref = sim.read_moments()
+    base_count = sim.step_count
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+
+    variants = {}
+    if not args.no_variants:
+        for name in ("fp32_fp32", "fp16", "bf16"):
+            if mc.PRECISIONS[name] == prec:
+                continue
+            v, el, st = time_run(mc, params, fields, mc.PRECISIONS[name], args.steps, args.warmup)
+            assert v.step_count == base_count
+            got = v.read_moments()
+            errs = {}
+            for k in ("X", "rho", "u", "p", "T"):
+                den = np.abs(ref[k]).max()
+                errs[k] = float(np.abs(got[k] - ref[k]).max() / den)
+            variants[name] = {"MLUPS": n * args.steps / el / 1e6, "speedup_vs_" + args.precision:
+                              (n * args.steps / el / 1e6) / mlups,
+                              "rel_linf_vs_" + args.precision: errs,
+                              "collide_avg_ms": st["k_collide"]["avg_ms"]}
+            v.close()
+            del v
+            torch.cuda.empty_cache()
+
+    cpu = None if args.no_cpu else cpu_baseline()
+    out = {
+        "metric": "D3Q27 mixture MLUPS & % HBM roofline; FP16-store and surrogate vs FP32 plain",
+        "value": mlups,
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "f32-store/f64-collide", "fp32_fp32": "f32", "fp64": "f64",
+                  "fp16": "f16-store/f32-collide", "bf16": "bf16-store/f32-collide"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"binary Kelvin-Helmholtz shear layer {args.n}^3 periodic, D3Q27, "
+                               f"{M} species + momentum + energy lattices, strong coupling",
+                   "nodes": n, "species": M, "precision": args.precision, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": "k_collide", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_node": ab["k_collide"]},
+        "kernels": {k: {"avg_ms": v["avg_ms"], "launches": v["launches"], "GBs": kernel_gbs[k],
+                        "algorithmic_bytes_per_node": ab[k]} for k, v in stats.items()},
+        "step_effective_GBs": {"step_bytes_per_node": ab["step"], "GBs": ab["step"] * mlups * 1e6 / 1e9,
+                               "method_min_bytes_per_node": ab["method_min"],
+                               "method_min_frac": ab["method_min"] * mlups * 1e6 / 1e9 / HBM_PEAK_GBS},
+        "variants": variants,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,135 @@
+/*
+ * mclbm.h -- C ABI of libmclbm, the MI355X (gfx950) implementation of the time
+ * step of the consistent multicomponent lattice Boltzmann model of Sawant,
+ * Dorschner and Karlin (arXiv 2004.11286): M species population sets relaxing
+ * under the Stefan--Maxwell kinetic model (Sec. 2), a compressible mixture
+ * momentum lattice and an energy lattice (Sec. 3), all on D3Q27, strongly
+ * coupled (Sec. 3.6.2), fused stream-and-collide over every node.
+ *
+ * Conventions for every call:
+ *   - Return value: MCLBM_OK (0) on success, a negative MCLBM_E* code on error;
+ *     mclbm_last_error() then describes the failure. No exception crosses the ABI.
+ *   - Units: lattice units, dt = dx = 1, universal gas constant R_U = 1 (a species
+ *     of molar mass m_a has gas constant 1/m_a), constant specific heats with
+ *     T_0 = 0 (Sec. 4.1).
+ *   - Field layout: structure of arrays, x fastest: node n = x + nx (y + ny z).
+ *     A field with C components is C consecutive planes of nx*ny*nz doubles.
+ *   - Ownership: the caller owns every buffer it passes, including the device
+ *     workspace; the library never frees them. The context is owned by the
+ *     library (mclbm_destroy).
+ *   - Streams: every call is ordered on the HIP stream given at creation; calls
+ *     that return data to the host synchronise that stream. Calls on one context
+ *     are not thread safe.
+ *   - Species M (the last) is slaved to the mixture (strong coupling, Sec. 3.6.2):
+ *     its density and momentum are the deficits of the mixture's. Order species so
+ *     that the last one carries most of the mass everywhere.
+ */
+#ifndef MCLBM_H
+#define MCLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes */
+#define MCLBM_OK 0
+#define MCLBM_EARG (-1)        /* invalid argument or size                         */
+#define MCLBM_ESTATE (-2)      /* infeasible state (T <= 0, R_a T + u^2 >= 1, ...) */
+#define MCLBM_EDEVICE (-3)     /* HIP runtime error                                */
+#define MCLBM_ENAN (-4)        /* non-finite value or negative slaved density      */
+#define MCLBM_EUNSUPPORTED (-6)/* configuration not compiled into this library     */
+
+/* Storage and arithmetic precision of the populations (mclbm_params.precision). */
+#define MCLBM_FP64 0      /* FP64 storage, FP64 collision                                   */
+#define MCLBM_FP32 1      /* FP32 storage, FP64 collision (same FMA rate as non-packed FP32) */
+#define MCLBM_FP32_FP32 2 /* FP32 storage, FP32 collision                                   */
+#define MCLBM_FP16 3      /* FP16 storage of scaled deviations, FP32 collision               */
+#define MCLBM_BF16 4      /* BF16 storage of scaled deviations, FP32 collision               */
+
+/* Kernel identifiers for mclbm_kernel_stats. */
+#define MCLBM_K_MOMENTS 0  /* moments of every lattice -> node record {Phi, omega, C_p} */
+#define MCLBM_K_GFIELD 1   /* G_a = (1/omega - 1/2) d_a Phi_a (inner derivative of eq Xalpha) */
+#define MCLBM_K_COLLIDE 2  /* collisions of all lattices + streaming                      */
+
+typedef struct mclbm_ctx mclbm_ctx;
+
+/* Problem description. Arrays are read during mclbm_create only. */
+typedef struct {
+  int32_t M;           /* species count (2, 3 or 4 in this build)                     */
+  int32_t nx, ny, nz;  /* lattice size; nx*ny*nz < 2^31                               */
+  int32_t wall_x;      /* 0: periodic in x; 1: half-way bounce-back walls at both x ends
+                          (Sec. 4.2); y and z are always periodic                      */
+  int32_t precision;   /* MCLBM_FP64 .. MCLBM_BF16                                    */
+  int32_t reserved0, reserved1;   /* must be 0                                        */
+  const double *molar_mass;  /* [M] molar masses m_a > 0                              */
+  const double *cv;          /* [M] mass-based specific heats C_{a,v} > 0             */
+  const double *D;           /* [M*M] symmetric binary diffusivities D_ab > 0, row major,
+                                diagonal included (the sums of eqs tau and fStar run over
+                                b = a)                                                 */
+  const double *mu;          /* [M] species dynamic viscosities (Wilke mixing, Sec. 3.4) */
+  const double *lambda;      /* [M] species thermal conductivities (Mathur mixing)    */
+} mclbm_params;
+
+/* Device workspace bytes a context with these parameters needs (0 on bad input). */
+size_t mclbm_workspace_bytes(const mclbm_params *p);
+
+/* Create a context on the current HIP device. dev_workspace: device memory of at
+ * least mclbm_workspace_bytes(p) bytes, 256-byte aligned, borrowed until
+ * mclbm_destroy. hip_stream: a hipStream_t (NULL = the null stream). */
+int mclbm_create(const mclbm_params *p, void *dev_workspace, size_t bytes, void *hip_stream,
+                 mclbm_ctx **out);
+
+void mclbm_destroy(mclbm_ctx *c);
+
+/* Message of the last error on this context; with c == NULL, of the last failed
+ * mclbm_create or mclbm_workspace_bytes on this thread. */
+const char *mclbm_last_error(const mclbm_ctx *c);
+
+/* Set every lattice to the local equilibrium of the given fields (the paper is
+ * silent on initial populations; the species k-populations equal the equilibria
+ * there, Sec. 2.5.2 eq fixed). X [M][n] mole fractions (each node sums to 1),
+ * p [n] pressure, T [n] temperature, u [3][n] velocity. on_device = 1: the four
+ * pointers are device memory; 0: host memory. Resets the step counter. */
+int mclbm_init_fields(mclbm_ctx *c, const double *X, const double *p, const double *T,
+                      const double *u, int on_device);
+
+/* Advance nsteps time steps (moments, stencil, collide-and-stream per step),
+ * asynchronously on the context's stream. */
+int mclbm_step(mclbm_ctx *c, int64_t nsteps);
+
+/* Macroscopic fields of the current state (Secs. 2.1, 2.5.3, 3.2): X [M][n],
+ * rho [n], u [3][n], p [n], T [n] as doubles; any pointer may be NULL. on_device
+ * as in mclbm_init_fields. Synchronises the stream. */
+int mclbm_read_moments(mclbm_ctx *c, double *X, double *rho, double *u, double *p, double *T,
+                       int on_device);
+
+/* Domain sums in FP64, out [M+5]: rho_1 .. rho_M (rho_M slaved), rho, rho u_x,
+ * rho u_y, rho u_z, rho E. Returns MCLBM_ENAN if any node holds a non-finite
+ * value or a negative slaved density. Synchronises the stream. */
+int mclbm_conservation(mclbm_ctx *c, double *out);
+
+/* Number of time steps since the last mclbm_init_fields or mclbm_load. */
+int64_t mclbm_step_count(const mclbm_ctx *c);
+
+/* Checkpoint: the population state, the reference tables and the step count,
+ * copied to / from a host buffer of mclbm_state_bytes(c) bytes. Restoring into a
+ * context created with the same parameters resumes bit for bit. */
+size_t mclbm_state_bytes(const mclbm_ctx *c);
+int mclbm_save(mclbm_ctx *c, void *host_buf, size_t bytes);
+int mclbm_load(mclbm_ctx *c, const void *host_buf, size_t bytes);
+
+/* Per-kernel timing with HIP events recorded on the context's stream around each
+ * launch of mclbm_step while enabled. mclbm_kernel_stats synchronises, returns the
+ * summed milliseconds and launch count of kernel k (MCLBM_K_*) since timing was
+ * enabled, and its name. */
+int mclbm_set_timing(mclbm_ctx *c, int enable);
+int mclbm_kernel_stats(mclbm_ctx *c, int32_t kernel, double *total_ms, int64_t *launches,
+                       const char **name);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

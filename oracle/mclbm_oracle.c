@@ -453,7 +453,7 @@ static void compute_nonlocal(oracle_sim *s)
   init_w13();
   /* G_k = (1/omega - 1/2) d_k Phi_k at the nodes and at one ghost layer beyond
    * each x end (there Phi and omega are the mirrored values). */
-#pragma omp parallel for schedule(static) if (n > 4096)
+#pragma omp parallel for schedule(static) if (n >= 512)
   for (int z = 0; z < nz; ++z)
     for (int y = 0; y < ny; ++y)
       for (int x = -1; x <= nx; ++x)
@@ -463,7 +463,7 @@ static void compute_nonlocal(oracle_sim *s)
           s->G[gidx(s, k, x, y, z)] = (1.0 / omega - 0.5) * iso_deriv(node_field_get, &phi, x, y, z, k);
         }
   /* X_k = - d_k G_k (eq Xalpha, dt = 1) and the mass-fraction gradients */
-#pragma omp parallel for schedule(static) if (n > 4096)
+#pragma omp parallel for schedule(static) if (n >= 512)
   for (int z = 0; z < nz; ++z)
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x) {
@@ -655,7 +655,7 @@ static void stream(oracle_sim *s)
 {
   const int nx = s->nx, ny = s->ny, nz = s->nz;
   const int L = s->M + 2;
-#pragma omp parallel for schedule(static) if (s->n > 4096)
+#pragma omp parallel for schedule(static) if (s->n >= 512)
   for (int z = 0; z < nz; ++z)
     for (int l = 0; l < L; ++l) {
       if (l == s->M - 1 && !s->keep_slaved) continue;
@@ -682,7 +682,7 @@ static int one_step(oracle_sim *s)
   const int M = s->M;
   int bad = 0;
   /* 1-2: moments and the node fields needed by the non-local terms */
-#pragma omp parallel for schedule(static) reduction(| : bad) if (n > 4096)
+#pragma omp parallel for schedule(static) reduction(| : bad) if (n >= 512)
   for (long node = 0; node < n; ++node) {
     state_t st;
     node_state(s, s->pop, node, &st);
@@ -700,7 +700,7 @@ static int one_step(oracle_sim *s)
   compute_nonlocal(s);
   /* 4-6: collisions */
   int rc = 0;
-#pragma omp parallel for schedule(static) reduction(min : rc) if (n > 4096)
+#pragma omp parallel for schedule(static) reduction(min : rc) if (n >= 512)
   for (long node = 0; node < n; ++node) {
     int r = collide_node(s, node);
     if (r < rc) rc = r;

@@ -1,0 +1,6 @@
+// inst_fp64.hip -- kernels with double storage and double arithmetic.
+#include "kernels.hpp"
+
+namespace mclbm {
+bool pick_fp64(int M, int walls, kern::Ops& o) { return kern::pick_m<double, double>(M, walls, o); }
+}  // namespace mclbm

@@ -1,0 +1,79 @@
+// lattice.hpp -- D3Q27 velocity set, product-form triplets and the per-context
+// parameter block shared by the device kernels of libmclbm.
+//
+// Velocity index i = 9 (c_x + 1) + 3 (c_y + 1) + (c_z + 1), so the opposite
+// direction is 26 - i. All loops over i are fully unrolled, which turns every
+// c_{i,a} below into a compile-time constant.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+namespace mclbm {
+
+constexpr int Q = 27;
+constexpr int MAXM = 8;           // species per context
+constexpr int MAXL = MAXM + 1;    // stored lattices: M-1 species, momentum f, energy g
+
+__host__ __device__ constexpr int cx(int i) { return i / 9 - 1; }
+__host__ __device__ constexpr int cy(int i) { return (i / 3) % 3 - 1; }
+__host__ __device__ constexpr int cz(int i) { return i % 3 - 1; }
+__host__ __device__ constexpr int cc(int i, int a) { return a == 0 ? cx(i) : (a == 1 ? cy(i) : cz(i)); }
+__host__ __device__ constexpr int csq(int i) { return cx(i) * cx(i) + cy(i) * cy(i) + cz(i) * cz(i); }
+__host__ __device__ constexpr int opp(int i) { return 26 - i; }
+
+// Values of a one-dimensional triplet at c = -1, 0, +1.
+template <typename R>
+struct Trip {
+  R m, z, p;
+  __host__ __device__ constexpr R operator()(int c) const { return c < 0 ? m : (c == 0 ? z : p); }
+};
+
+// Psi_{-1,0,+1}(xi, zeta) of the product-form equilibrium (Sec. 2.4).
+template <typename R>
+__host__ __device__ inline Trip<R> psi_trip(R xi, R zeta)
+{
+  R s = xi * xi + zeta;
+  return {(s - xi) * R(0.5), R(1) - s, (s + xi) * R(0.5)};
+}
+
+// Psi(u) - Psi(u + V) per component, written without cancellation:
+// c = 0: (u+V)^2 - u^2 = V (2u + V); c = +-1: (-+V - V (2u + V)) / 2.
+template <typename R>
+__host__ __device__ inline Trip<R> psi_diff_trip(R u, R V)
+{
+  R s = V * (R(2) * u + V);
+  return {(V - s) * R(0.5), s, (-V - s) * R(0.5)};
+}
+
+// Weight triplet w_{-1,0,+1}(theta) = (theta/2, 1 - theta, theta/2), eq w0.
+template <typename R>
+__host__ __device__ inline Trip<R> w_trip(R theta)
+{
+  return {theta * R(0.5), R(1) - theta, theta * R(0.5)};
+}
+
+// Weights at theta = 1/3 used by the isotropic derivative 3 sum_i w_i c_i phi(x + c_i).
+__host__ __device__ constexpr double w13_1d(int c) { return c == 0 ? 2.0 / 3.0 : 1.0 / 6.0; }
+__host__ __device__ constexpr double w13(int i) { return w13_1d(cx(i)) * w13_1d(cy(i)) * w13_1d(cz(i)); }
+
+// Per-context constants, resident in device memory and read through uniform loads.
+// Populations are stored as scaled deviations d = s_l (f - f_ref,l,i) from a
+// symmetric reference equilibrium (zero velocity), so f_ref,i = f_ref,opp(i).
+template <typename R>
+struct Params {
+  int32_t M, nx, ny, nz;
+  int32_t wall_x, pad0, pad1, pad2;
+  int64_t n;
+  R m[MAXM], inv_m[MAXM], cv[MAXM], cp[MAXM];
+  R mu[MAXM], lam[MAXM], inv_lam[MAXM];
+  R invD[MAXM][MAXM];     // 1 / D_ab
+  R phi[MAXM][MAXM];      // Wilke's phi_ab
+  R ref[MAXL][Q];         // reference populations f_ref
+  R ref0[MAXL];           // sum_i f_ref (zeroth moment)
+  R ref2[MAXL];           // sum_i f_ref c_ia^2 (diagonal second moment, isotropic)
+  R scale[MAXL], inv_scale[MAXL];
+  R pivot_tiny;           // |pivot| at or below this: species absent, V_a = 0
+};
+
+}  // namespace mclbm

@@ -1,0 +1,113 @@
+// params_host.hpp -- host-side construction of the per-context parameter block:
+// species data, Wilke factors, and the reference equilibria that the stored
+// population deviations are taken from.
+#pragma once
+
+#include <cmath>
+#include <cstring>
+
+#include "lattice.hpp"
+
+namespace mclbm {
+
+struct HostSpecies {
+  int M;
+  double m[MAXM], cv[MAXM], mu[MAXM], lam[MAXM];
+  double D[MAXM][MAXM];
+};
+
+// Mean state used for the reference equilibria (zero velocity).
+struct RefState {
+  double X[MAXM];
+  double p, T;
+};
+
+// Wilke's phi_ab (Sec. 3.4, eq wilkePhi).
+inline double wilke_phi(const HostSpecies& h, int a, int b)
+{
+  double num = 1.0 + std::sqrt((h.mu[a] / h.mu[b]) * std::sqrt(h.m[b] / h.m[a]));
+  return num * num / (std::sqrt(8.0) * std::sqrt(1.0 + h.m[a] / h.m[b]));
+}
+
+// Reference populations of every stored lattice at the mean state, zero
+// velocity: species rho_a Psi(0, R_a T), momentum rho Psi(0, R T), energy the
+// energy-lattice equilibrium with zero flux. All are symmetric under c -> -c.
+inline void reference_tables(const HostSpecies& h, const RefState& rs, double ref[MAXL][Q], double ref0[MAXL],
+                             double ref2[MAXL])
+{
+  const int M = h.M;
+  double mmix = 0.0;
+  for (int a = 0; a < M; ++a) mmix += rs.X[a] * h.m[a];
+  const double Rg = 1.0 / mmix;
+  const double rho = rs.p / (Rg * rs.T);
+  double Cv = 0.0;
+  for (int a = 0; a < M; ++a) Cv += rs.X[a] * h.m[a] / mmix * h.cv[a];
+  std::memset(ref, 0, sizeof(double) * MAXL * Q);
+  auto fill_psi = [&](int l, double dens, double zeta) {
+    Trip<double> t = psi_trip<double>(0.0, zeta);
+    for (int i = 0; i < Q; ++i) ref[l][i] = dens * t(cx(i)) * t(cy(i)) * t(cz(i));
+  };
+  for (int a = 0; a < M - 1; ++a) fill_psi(a, rho * rs.X[a] * h.m[a] / mmix, rs.T / h.m[a]);
+  fill_psi(M - 1, rho, Rg * rs.T);
+  {
+    const double theta = Rg * rs.T;
+    const double rhoE = rho * Cv * rs.T;
+    const double rt2 = rho * theta * theta;
+    const double zf = (1.0 - 3.0 * theta) * 0.5 / theta;
+    const Trip<double> wt = w_trip<double>(theta);
+    for (int i = 0; i < Q; ++i) {
+      const double w = wt(cx(i)) * wt(cy(i)) * wt(cz(i));
+      double bz = 0.0;
+      if (csq(i) == 0) bz = 3.0 * zf * rt2;
+      if (csq(i) == 1) bz = -0.5 * zf * rt2;
+      ref[M][i] = w * (rhoE + rt2 * (csq(i) - 3.0 * theta) * 0.5 / (theta * theta)) + bz;
+    }
+  }
+  for (int l = 0; l <= M; ++l) {
+    ref0[l] = 0.0;
+    ref2[l] = 0.0;
+    for (int i = 0; i < Q; ++i) {
+      ref0[l] += ref[l][i];
+      ref2[l] += ref[l][i] * cx(i) * cx(i);
+    }
+  }
+}
+
+// Fill a parameter block. scale[l] multiplies stored deviations (1 for FP64 and
+// FP32 storage; a range-fitting factor for 16-bit storage).
+template <typename R>
+inline void fill_params(Params<R>& P, const HostSpecies& h, int nx, int ny, int nz, int wall_x,
+                        const double ref[MAXL][Q], const double ref0[MAXL], const double ref2[MAXL],
+                        const double scale[MAXL], double pivot_tiny)
+{
+  std::memset(&P, 0, sizeof(P));
+  P.M = h.M;
+  P.nx = nx;
+  P.ny = ny;
+  P.nz = nz;
+  P.wall_x = wall_x;
+  P.n = (int64_t)nx * ny * nz;
+  for (int a = 0; a < h.M; ++a) {
+    P.m[a] = R(h.m[a]);
+    P.inv_m[a] = R(1.0 / h.m[a]);
+    P.cv[a] = R(h.cv[a]);
+    P.cp[a] = R(h.cv[a] + 1.0 / h.m[a]);       // Mayer: C_{a,p} - C_{a,v} = R_a
+    P.mu[a] = R(h.mu[a]);
+    P.lam[a] = R(h.lam[a]);
+    P.inv_lam[a] = R(1.0 / h.lam[a]);
+    for (int b = 0; b < h.M; ++b) {
+      P.invD[a][b] = R(1.0 / h.D[a][b]);
+      P.phi[a][b] = R(wilke_phi(h, a, b));
+    }
+  }
+  for (int l = 0; l <= h.M; ++l) {
+    for (int i = 0; i < Q; ++i) P.ref[l][i] = R(ref[l][i]);
+    P.ref0[l] = R(ref0[l]);
+    P.ref2[l] = R(ref2[l]);
+    P.scale[l] = R(scale[l]);
+    P.inv_scale[l] = R(1.0 / scale[l]);
+  }
+  P.pivot_tiny = R(pivot_tiny);
+}
+
+}  // namespace mclbm

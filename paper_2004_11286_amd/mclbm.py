@@ -1,0 +1,280 @@
+"""Thin ctypes binding of libmclbm (include/mclbm.h).
+
+Functions keep the C names and only marshal arguments; every step of the time
+step runs in the library's HIP kernels. PyTorch supplies device memory (the
+workspace and optional device field buffers) and the HIP stream.
+
+Importing this module raises if ``libmclbm.so`` has not been built: there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmclbm.so")
+
+MCLBM_OK = 0
+MCLBM_EARG = -1
+MCLBM_ESTATE = -2
+MCLBM_EDEVICE = -3
+MCLBM_ENAN = -4
+MCLBM_EUNSUPPORTED = -6
+
+MCLBM_FP64 = 0
+MCLBM_FP32 = 1
+MCLBM_FP32_FP32 = 2
+MCLBM_FP16 = 3
+MCLBM_BF16 = 4
+PRECISIONS = {"fp64": MCLBM_FP64, "fp32": MCLBM_FP32, "fp32_fp32": MCLBM_FP32_FP32,
+              "fp16": MCLBM_FP16, "bf16": MCLBM_BF16}
+STORAGE_BYTES = {MCLBM_FP64: 8, MCLBM_FP32: 4, MCLBM_FP32_FP32: 4, MCLBM_FP16: 2, MCLBM_BF16: 2}
+
+MCLBM_K_MOMENTS = 0
+MCLBM_K_GFIELD = 1
+MCLBM_K_COLLIDE = 2
+
+EXPORTS = ["mclbm_workspace_bytes", "mclbm_create", "mclbm_destroy", "mclbm_last_error",
+           "mclbm_init_fields", "mclbm_step", "mclbm_read_moments", "mclbm_conservation",
+           "mclbm_step_count", "mclbm_state_bytes", "mclbm_save", "mclbm_load",
+           "mclbm_set_timing", "mclbm_kernel_stats"]
+
+
+class mclbm_params(C.Structure):
+    _fields_ = [
+        ("M", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+        ("wall_x", C.c_int32), ("precision", C.c_int32), ("reserved0", C.c_int32),
+        ("reserved1", C.c_int32),
+        ("molar_mass", C.POINTER(C.c_double)), ("cv", C.POINTER(C.c_double)),
+        ("D", C.POINTER(C.c_double)), ("mu", C.POINTER(C.c_double)),
+        ("lam", C.POINTER(C.c_double)),
+    ]
+
+
+class MclbmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libmclbm error {code}: {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2004_11286_amd.build` "
+                          "(there is no CPU fallback)")
+    L = C.CDLL(LIB_PATH)
+    dp = C.POINTER(C.c_double)
+    vp = C.c_void_p
+    P = C.POINTER(mclbm_params)
+    L.mclbm_workspace_bytes.argtypes = [P]
+    L.mclbm_workspace_bytes.restype = C.c_size_t
+    L.mclbm_create.argtypes = [P, vp, C.c_size_t, vp, C.POINTER(vp)]
+    L.mclbm_destroy.argtypes = [vp]
+    L.mclbm_destroy.restype = None
+    L.mclbm_last_error.argtypes = [vp]
+    L.mclbm_last_error.restype = C.c_char_p
+    L.mclbm_init_fields.argtypes = [vp, vp, vp, vp, vp, C.c_int]
+    L.mclbm_step.argtypes = [vp, C.c_int64]
+    L.mclbm_read_moments.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int]
+    L.mclbm_conservation.argtypes = [vp, dp]
+    L.mclbm_step_count.argtypes = [vp]
+    L.mclbm_step_count.restype = C.c_int64
+    L.mclbm_state_bytes.argtypes = [vp]
+    L.mclbm_state_bytes.restype = C.c_size_t
+    L.mclbm_save.argtypes = [vp, vp, C.c_size_t]
+    L.mclbm_load.argtypes = [vp, vp, C.c_size_t]
+    L.mclbm_set_timing.argtypes = [vp, C.c_int]
+    L.mclbm_kernel_stats.argtypes = [vp, C.c_int32, dp, C.POINTER(C.c_int64), C.POINTER(C.c_char_p)]
+    return L
+
+
+lib = _load()
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def make_params(params: dict, precision: int):
+    """mclbm_params from a workload dict; returns (struct, arrays kept alive)."""
+    M = int(params["M"])
+    arrs = [_f64(params["molar_mass"]), _f64(params["cv"]), _f64(params["D"]).reshape(M * M),
+            _f64(params["mu"]), _f64(params["lambda"])]
+    dp = C.POINTER(C.c_double)
+    p = mclbm_params(M, int(params["nx"]), int(params["ny"]), int(params["nz"]),
+                     int(params.get("wall_x", 0)), int(precision), 0, 0,
+                     *[a.ctypes.data_as(dp) for a in arrs])
+    return p, arrs
+
+
+def _check(ctx, rc: int):
+    if rc != MCLBM_OK:
+        msg = lib.mclbm_last_error(ctx)
+        raise MclbmError(rc, msg.decode() if msg else "")
+
+
+# ------------------------------------------------------------------ C-named calls
+def mclbm_workspace_bytes(params: dict, precision: int) -> int:
+    p, _keep = make_params(params, precision)
+    n = lib.mclbm_workspace_bytes(C.byref(p))
+    if n == 0:
+        raise MclbmError(MCLBM_EARG, lib.mclbm_last_error(None).decode())
+    return int(n)
+
+
+def mclbm_create(params: dict, precision: int, workspace_ptr: int, nbytes: int, stream: int) -> C.c_void_p:
+    p, _keep = make_params(params, precision)
+    h = C.c_void_p()
+    _check(None, lib.mclbm_create(C.byref(p), C.c_void_p(workspace_ptr), nbytes, C.c_void_p(stream),
+                                  C.byref(h)))
+    return h
+
+
+def mclbm_destroy(ctx) -> None:
+    lib.mclbm_destroy(ctx)
+
+
+def mclbm_last_error(ctx) -> str:
+    m = lib.mclbm_last_error(ctx)
+    return m.decode() if m else ""
+
+
+def mclbm_init_fields(ctx, X_ptr: int, p_ptr: int, T_ptr: int, u_ptr: int, on_device: int) -> None:
+    _check(ctx, lib.mclbm_init_fields(ctx, C.c_void_p(X_ptr), C.c_void_p(p_ptr), C.c_void_p(T_ptr),
+                                      C.c_void_p(u_ptr), int(on_device)))
+
+
+def mclbm_step(ctx, nsteps: int) -> None:
+    _check(ctx, lib.mclbm_step(ctx, int(nsteps)))
+
+
+def mclbm_read_moments(ctx, X_ptr, rho_ptr, u_ptr, p_ptr, T_ptr, on_device: int) -> None:
+    ptrs = [C.c_void_p(v) if v else None for v in (X_ptr, rho_ptr, u_ptr, p_ptr, T_ptr)]
+    _check(ctx, lib.mclbm_read_moments(ctx, *ptrs, int(on_device)))
+
+
+def mclbm_conservation(ctx, M: int) -> np.ndarray:
+    out = np.zeros(M + 5)
+    _check(ctx, lib.mclbm_conservation(ctx, out.ctypes.data_as(C.POINTER(C.c_double))))
+    return out
+
+
+def mclbm_step_count(ctx) -> int:
+    return int(lib.mclbm_step_count(ctx))
+
+
+def mclbm_state_bytes(ctx) -> int:
+    return int(lib.mclbm_state_bytes(ctx))
+
+
+def mclbm_save(ctx) -> bytearray:
+    n = mclbm_state_bytes(ctx)
+    buf = bytearray(n)
+    _check(ctx, lib.mclbm_save(ctx, (C.c_char * n).from_buffer(buf), n))
+    return buf
+
+
+def mclbm_load(ctx, buf: bytearray) -> None:
+    n = len(buf)
+    _check(ctx, lib.mclbm_load(ctx, (C.c_char * n).from_buffer(buf), n))
+
+
+def mclbm_set_timing(ctx, enable: bool) -> None:
+    _check(ctx, lib.mclbm_set_timing(ctx, int(bool(enable))))
+
+
+def mclbm_kernel_stats(ctx, kernel: int):
+    ms = C.c_double()
+    launches = C.c_int64()
+    name = C.c_char_p()
+    _check(ctx, lib.mclbm_kernel_stats(ctx, int(kernel), C.byref(ms), C.byref(launches), C.byref(name)))
+    return ms.value, launches.value, name.value.decode()
+
+
+# ------------------------------------------------------------------ convenience wrapper
+class Sim:
+    """A context plus its torch-owned device workspace on ``device``."""
+
+    def __init__(self, params: dict, precision: int | str = MCLBM_FP32, device: str = "cuda:0", stream=None):
+        import torch
+
+        if isinstance(precision, str):
+            precision = PRECISIONS[precision]
+        self.params = dict(params)
+        self.precision = int(precision)
+        self.M = int(params["M"])
+        self.nx, self.ny, self.nz = int(params["nx"]), int(params["ny"]), int(params["nz"])
+        self.n = self.nx * self.ny * self.nz
+        self.device = torch.device(device)
+        nbytes = mclbm_workspace_bytes(params, self.precision)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        with torch.cuda.device(self.device):
+            self.ctx = mclbm_create(params, self.precision, self.workspace.data_ptr(), nbytes,
+                                    self.stream.cuda_stream)
+
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            mclbm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init_fields(self, X, p, T, u):
+        """Fields as numpy arrays (host) or CUDA tensors (device), shaped [..., nz, ny, nx]."""
+        import torch
+
+        if all(isinstance(a, torch.Tensor) and a.is_cuda for a in (X, p, T, u)):
+            t = [a.to(torch.float64).contiguous() for a in (X, p, T, u)]
+            mclbm_init_fields(self.ctx, *[a.data_ptr() for a in t], 1)
+            return
+        a = [_f64(v) for v in (X, p, T, u)]
+        assert a[0].size == self.M * self.n and a[3].size == 3 * self.n
+        mclbm_init_fields(self.ctx, *[v.ctypes.data for v in a], 0)
+
+    def step(self, nsteps: int = 1):
+        mclbm_step(self.ctx, nsteps)
+
+    def read_moments(self, on_device: bool = False) -> dict:
+        if on_device:
+            import torch
+
+            kw = dict(dtype=torch.float64, device=self.device)
+            out = {"X": torch.empty((self.M,) + self.shape, **kw), "rho": torch.empty(self.shape, **kw),
+                   "u": torch.empty((3,) + self.shape, **kw), "p": torch.empty(self.shape, **kw),
+                   "T": torch.empty(self.shape, **kw)}
+            mclbm_read_moments(self.ctx, *[out[k].data_ptr() for k in ("X", "rho", "u", "p", "T")], 1)
+            return out
+        out = {"X": np.zeros((self.M,) + self.shape), "rho": np.zeros(self.shape),
+               "u": np.zeros((3,) + self.shape), "p": np.zeros(self.shape), "T": np.zeros(self.shape)}
+        mclbm_read_moments(self.ctx, *[out[k].ctypes.data for k in ("X", "rho", "u", "p", "T")], 0)
+        return out
+
+    def conservation(self) -> np.ndarray:
+        return mclbm_conservation(self.ctx, self.M)
+
+    @property
+    def step_count(self) -> int:
+        return mclbm_step_count(self.ctx)
+
+    def save(self) -> bytearray:
+        return mclbm_save(self.ctx)
+
+    def load(self, buf) -> None:
+        mclbm_load(self.ctx, buf)
+
+    def set_timing(self, enable: bool) -> None:
+        mclbm_set_timing(self.ctx, enable)
+
+    def kernel_stats(self, kernel: int):
+        return mclbm_kernel_stats(self.ctx, kernel)

@@ -1,0 +1,57 @@
+"""Helpers shared by the GPU tests: per-field comparison and checkpoint decoding."""
+from __future__ import annotations
+
+import numpy as np
+
+FIELDS = ("X", "rho", "u", "p", "T")
+
+# Checkpoint header written by mclbm_save (see mclbm.hip): magic[8], 6 int32,
+# int64 step count, ref[9][27], ref0[9], ref2[9], scale[9] (doubles).
+_HDR = np.dtype([("magic", "S8"), ("M", "<i4"), ("nx", "<i4"), ("ny", "<i4"), ("nz", "<i4"),
+                 ("wall_x", "<i4"), ("precision", "<i4"), ("steps", "<i8"),
+                 ("ref", "<f8", (9, 27)), ("ref0", "<f8", (9,)), ("ref2", "<f8", (9,)),
+                 ("scale", "<f8", (9,))])
+_STORE = {0: np.float64, 1: np.float32, 2: np.float32, 3: np.float16}
+
+
+def rel_linf(a: np.ndarray, b: np.ndarray) -> float:
+    """max |a - b| / max |b| (absolute when b is identically zero)."""
+    den = float(np.abs(b).max())
+    return float(np.abs(a - b).max() / (den if den > 0 else 1.0))
+
+
+def field_errors(gpu: dict, ref: dict) -> dict:
+    return {k: rel_linf(np.asarray(gpu[k]), np.asarray(ref[k])) for k in FIELDS}
+
+
+def decode_checkpoint(buf) -> tuple[dict, np.ndarray]:
+    """Header dict and the stored values as an array [L][27][nz][ny][nx] (no copy)."""
+    h = np.frombuffer(buf, dtype=_HDR, count=1)[0]
+    M, nx, ny, nz, prec = int(h["M"]), int(h["nx"]), int(h["ny"]), int(h["nz"]), int(h["precision"])
+    if prec == 4:
+        raw = np.frombuffer(buf, dtype=np.uint16, offset=_HDR.itemsize, count=(M + 1) * 27 * nx * ny * nz)
+        vals = (raw.astype(np.uint32) << 16).view(np.float32)
+    else:
+        vals = np.frombuffer(buf, dtype=_STORE[prec], offset=_HDR.itemsize, count=(M + 1) * 27 * nx * ny * nz)
+    hdr = {k: h[k] for k in _HDR.names}
+    return hdr, vals.reshape(M + 1, 27, nz, ny, nx)
+
+
+def oracle_window(hdr: dict, vals: np.ndarray, center, radius: int) -> np.ndarray:
+    """Absolute populations of a periodic (2 radius + 1)^3 window around ``center``
+    in the oracle's layout [(M+2)][27][w][w][w]; the slaved species' lattice
+    (never read under strong coupling) is left at zero."""
+    M = int(hdr["M"])
+    nz, ny, nx = vals.shape[2:]
+    x0, y0, z0 = center
+    ix = np.arange(x0 - radius, x0 + radius + 1) % nx
+    iy = np.arange(y0 - radius, y0 + radius + 1) % ny
+    iz = np.arange(z0 - radius, z0 + radius + 1) % nz
+    w = 2 * radius + 1
+    out = np.zeros((M + 2, 27, w, w, w))
+    sub = vals[np.ix_(np.arange(M + 1), np.arange(27), iz, iy, ix)].astype(np.float64)
+    for l in range(M + 1):
+        f = hdr["ref"][l][:, None, None, None] + sub[l] / hdr["scale"][l]
+        dst = l if l < M - 1 else l + 1          # GPU lattices: species 1..M-1, f, g
+        out[dst] = f
+    return out
