@@ -43,6 +43,9 @@ def _compile(src: str, verbose: bool, extra: list[str]) -> str:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")
     if verbose and (r.stderr.strip()):
         print(r.stderr)
+    if extra:
+        with open(obj + ".remarks", "w") as fh:      # compiler remarks (register usage)
+            fh.write(r.stderr)
     return obj
 
 

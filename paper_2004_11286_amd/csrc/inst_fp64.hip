@@ -1,6 +1,6 @@
-// inst_fp64.hip -- kernels with double storage and double arithmetic.
+// inst_fp64.hip -- kernels with double storage and double arithmetic, double node record.
 #include "kernels.hpp"
 
 namespace mclbm {
-bool pick_fp64(int M, int walls, kern::Ops& o) { return kern::pick_m<double, double>(M, walls, o); }
+bool pick_fp64(int M, int walls, kern::Ops& o) { return kern::pick_m<double, double, double>(M, walls, o); }
 }  // namespace mclbm

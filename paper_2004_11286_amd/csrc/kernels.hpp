@@ -19,29 +19,36 @@ inline size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 // ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
-template <typename S, typename R, int M>
-__global__ __launch_bounds__(BLOCK) void k_moments(const Params<R>* __restrict__ P, const S* __restrict__ pop,
-                                                   R* __restrict__ rec)
+// Occupancy targets (waves per SIMD) that bound the register allocation: the
+// kernels are memory bound and need several waves in flight per SIMD.
+template <typename S, int M>
+constexpr int collide_waves() { return (M == 2 && sizeof(S) < 8) ? 2 : 1; }
+template <int M>
+constexpr int moment_waves() { return M == 2 ? 2 : 1; }
+
+template <typename S, typename Rec, int M>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(moment_waves<M>()))) void k_moments(const Params<double>* __restrict__ P, const S* __restrict__ pop,
+                                                   Rec* __restrict__ rec)
 {
   const int64_t node = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (node < P->n) moments_node<S, R, M>(*P, pop, rec, node);
+  if (node < P->n) state_node<S, Rec, M>(*P, pop, rec, node);
 }
 
-template <typename R, bool W>
-__global__ __launch_bounds__(BLOCK) void k_gfield(const Params<R>* __restrict__ P, const R* __restrict__ rec,
-                                                  R* __restrict__ G)
+template <typename Rec, bool W>
+__global__ __launch_bounds__(BLOCK) void k_gfield(const Params<double>* __restrict__ P,
+                                                  const Rec* __restrict__ rec, Rec* __restrict__ G)
 {
   const int64_t node = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (node < P->n) gfield_node<R, W>(*P, rec, G, node);
+  if (node < P->n) gfield_node<Rec, W>(*P, rec, G, node);
 }
 
-template <typename S, typename R, int M, bool W>
-__global__ __launch_bounds__(BLOCK) void k_collide(const Params<R>* __restrict__ P, const S* __restrict__ src,
-                                                   S* __restrict__ dst, const R* __restrict__ rec,
-                                                   const R* __restrict__ G)
+template <typename S, typename R, typename Rec, int M, bool W>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(collide_waves<S, M>()))) void k_collide(const Params<R>* __restrict__ P, const S* __restrict__ src,
+                                                   S* __restrict__ dst, const Rec* __restrict__ rec,
+                                                   const Rec* __restrict__ G, uint32_t step)
 {
   const int64_t node = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (node < P->n) collide_node<S, R, M, W>(*P, src, dst, rec, G, node);
+  if (node < P->n) collide_node<S, R, Rec, M, W>(*P, src, dst, rec, G, node, step);
 }
 
 template <typename S, typename R, int M>
@@ -126,10 +133,11 @@ __global__ __launch_bounds__(BLOCK) void k_init(const Params<double>* __restrict
 struct Ops {
   size_t s_bytes;   // bytes per stored population
   size_t r_bytes;   // bytes per record value
+  int rec_fields;   // values per node in the record
   void (*moments)(const void* P, const void* pop, void* rec, unsigned grid, hipStream_t st);
   void (*gfield)(const void* P, const void* rec, void* G, unsigned grid, hipStream_t st);
-  void (*collide)(const void* P, const void* src, void* dst, const void* rec, const void* G, unsigned grid,
-                  hipStream_t st);
+  void (*collide)(const void* P, const void* src, void* dst, const void* rec, const void* G, uint32_t step,
+                  unsigned grid, hipStream_t st);
   void (*read)(const void* P, const void* pop, double* X, double* rho, double* u, double* p, double* T,
                unsigned grid, hipStream_t st);
   void (*conserved)(const void* Pd, const void* pop, double* partial, unsigned grid, hipStream_t st);
@@ -139,24 +147,25 @@ struct Ops {
                      unsigned grid, hipStream_t st);
 };
 
-template <typename S, typename R, int M, bool W>
+template <typename S, typename R, typename Rec, int M, bool W>
 Ops make_ops()
 {
   Ops o;
   o.s_bytes = sizeof(S);
-  o.r_bytes = sizeof(R);
-  o.moments = [](const void* P, const void* pop, void* rec, unsigned grid, hipStream_t st) {
-    hipLaunchKernelGGL((k_moments<S, R, M>), dim3(grid), dim3(BLOCK), 0, st, (const Params<R>*)P, (const S*)pop,
-                       (R*)rec);
+  o.r_bytes = sizeof(Rec);
+  o.rec_fields = RecLayout<M>::FIELDS;
+  o.moments = [](const void* Pd, const void* pop, void* rec, unsigned grid, hipStream_t st) {
+    hipLaunchKernelGGL((k_moments<S, Rec, M>), dim3(grid), dim3(BLOCK), 0, st, (const Params<double>*)Pd,
+                       (const S*)pop, (Rec*)rec);
   };
-  o.gfield = [](const void* P, const void* rec, void* G, unsigned grid, hipStream_t st) {
-    hipLaunchKernelGGL((k_gfield<R, W>), dim3(grid), dim3(BLOCK), 0, st, (const Params<R>*)P, (const R*)rec,
-                       (R*)G);
+  o.gfield = [](const void* Pd, const void* rec, void* G, unsigned grid, hipStream_t st) {
+    hipLaunchKernelGGL((k_gfield<Rec, W>), dim3(grid), dim3(BLOCK), 0, st, (const Params<double>*)Pd,
+                       (const Rec*)rec, (Rec*)G);
   };
-  o.collide = [](const void* P, const void* src, void* dst, const void* rec, const void* G, unsigned grid,
-                 hipStream_t st) {
-    hipLaunchKernelGGL((k_collide<S, R, M, W>), dim3(grid), dim3(BLOCK), 0, st, (const Params<R>*)P,
-                       (const S*)src, (S*)dst, (const R*)rec, (const R*)G);
+  o.collide = [](const void* P, const void* src, void* dst, const void* rec, const void* G, uint32_t step,
+                 unsigned grid, hipStream_t st) {
+    hipLaunchKernelGGL((k_collide<S, R, Rec, M, W>), dim3(grid), dim3(BLOCK), 0, st, (const Params<R>*)P,
+                       (const S*)src, (S*)dst, (const Rec*)rec, (const Rec*)G, step);
   };
   o.read = [](const void* P, const void* pop, double* X, double* rho, double* u, double* p, double* T,
               unsigned grid, hipStream_t st) {
@@ -179,13 +188,13 @@ Ops make_ops()
   return o;
 }
 
-template <typename S, typename R>
+template <typename S, typename R, typename Rec>
 bool pick_m(int M, int walls, Ops& o)
 {
   switch (M) {
-    case 2: o = walls ? make_ops<S, R, 2, true>() : make_ops<S, R, 2, false>(); return true;
-    case 3: o = walls ? make_ops<S, R, 3, true>() : make_ops<S, R, 3, false>(); return true;
-    case 4: o = walls ? make_ops<S, R, 4, true>() : make_ops<S, R, 4, false>(); return true;
+    case 2: o = walls ? make_ops<S, R, Rec, 2, true>() : make_ops<S, R, Rec, 2, false>(); return true;
+    case 3: o = walls ? make_ops<S, R, Rec, 3, true>() : make_ops<S, R, Rec, 3, false>(); return true;
+    case 4: o = walls ? make_ops<S, R, Rec, 4, true>() : make_ops<S, R, Rec, 4, false>(); return true;
     default: return false;
   }
 }

@@ -73,7 +73,7 @@ struct Params {
   R ref0[MAXL];           // sum_i f_ref (zeroth moment)
   R ref2[MAXL];           // sum_i f_ref c_ia^2 (diagonal second moment, isotropic)
   R scale[MAXL], inv_scale[MAXL];
-  R pivot_tiny;           // |pivot| at or below this: species absent, V_a = 0
+  R absent_tol;           // |rho_a| <= absent_tol * rho: species absent, V_a = 0
 };
 
 }  // namespace mclbm

@@ -30,6 +30,8 @@ using namespace mclbm;
 namespace {
 
 using kern::Ops;
+
+int push_params(mclbm_ctx* c);
 using kern::BLOCK;
 using kern::RED_BLOCK;
 using kern::ALIGN;
@@ -125,7 +127,7 @@ Layout layout_for(int M, int64_t n, int precision)
   size_t s_bytes = 8, r_bytes = 8;
   switch (precision) {
     case MCLBM_FP64: s_bytes = 8; r_bytes = 8; break;
-    case MCLBM_FP32: s_bytes = 4; r_bytes = 8; break;
+    case MCLBM_FP32: s_bytes = 4; r_bytes = 4; break;
     case MCLBM_FP32_FP32: s_bytes = 4; r_bytes = 4; break;
     case MCLBM_FP16: case MCLBM_BF16: s_bytes = 2; r_bytes = 4; break;
   }
@@ -136,7 +138,8 @@ Layout layout_for(int M, int64_t n, int precision)
   l.pd = off; off += align_up(sizeof(Params<double>));
   l.pr = off; off += align_up(sizeof(Params<float>));
   l.pop = off; off += 2 * align_up((size_t)L * Q * n * s_bytes);
-  l.rec = off; off += align_up((size_t)REC_FIELDS * n * r_bytes);
+  const int rec_fields = REC_RHOA + (M - 1) + 3 * M;
+  l.rec = off; off += align_up((size_t)rec_fields * n * r_bytes);
   l.G = off; off += align_up((size_t)3 * n * r_bytes);
   l.staging = off; off += align_up((size_t)(M + 6) * n * sizeof(double));
   l.partial = off; off += align_up((size_t)nblocks * (MAXM + 6) * sizeof(double));
@@ -186,27 +189,86 @@ int fail(mclbm_ctx* c, int code, const std::string& msg)
 
 unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
+double absent_tol_for(int precision);
+
+int push_params(mclbm_ctx* c)
+{
+  HIP_TRY(c, hipStreamSynchronize(c->stream));   // previous uploads from the host blocks are done
+  const double tol = absent_tol_for(c->precision);
+  fill_params<double>(c->hPd, c->hs, c->nx, c->ny, c->nz, c->wall_x, c->ref, c->ref0, c->ref2, c->scale, tol);
+  fill_params<float>(c->hPf, c->hs, c->nx, c->ny, c->nz, c->wall_x, c->ref, c->ref0, c->ref2, c->scale, tol);
+  HIP_TRY(c, hipMemcpyAsync(c->dPd, &c->hPd, sizeof(c->hPd), hipMemcpyHostToDevice, c->stream));
+  if (!compute_is_fp64(c->precision))
+    HIP_TRY(c, hipMemcpyAsync(c->dPr, &c->hPf, sizeof(c->hPf), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return MCLBM_OK;
+}
+
+// Power-of-two scale that maps the reference populations of a lattice to
+// magnitudes around 2^10 (16-bit storage only), so that scaling is exact.
 double scale_for(int precision, const double* ref_l)
 {
   if (precision != MCLBM_FP16 && precision != MCLBM_BF16) return 1.0;
   double mx = 0.0;
   for (int i = 0; i < Q; ++i) mx = std::max(mx, std::fabs(ref_l[i]));
-  return mx > 0.0 ? 1024.0 / mx : 1.0;   // deviations of the order of f_ref map to ~1e3
+  if (!(mx > 0.0)) return 1.0;
+  return std::ldexp(1.0, (int)std::floor(std::log2(1024.0 / mx)));
+}
+
+// Round a scaled reference value to the nearest value the storage type holds,
+// so that a population equal to zero (an absent species) is stored exactly.
+double round_to_storage(int precision, double v)
+{
+  switch (precision) {
+    case MCLBM_FP32:
+    case MCLBM_FP32_FP32: return (double)(float)v;
+    case MCLBM_FP16: return (double)(float)(_Float16)(float)v;
+    case MCLBM_BF16: {
+      float f = (float)v;
+      uint32_t u;
+      std::memcpy(&u, &f, 4);
+      u += 0x7fffu + ((u >> 16) & 1u);      // round to nearest even on the upper 16 bits
+      u &= 0xffff0000u;
+      std::memcpy(&f, &u, 4);
+      return (double)f;
+    }
+    default: return v;
+  }
+}
+
+// Relative density below which a species counts as absent (eq transform12 then
+// has a zero row for it, V_a = 0): the resolution of the stored populations.
+// With FP64 and FP32 storage an absent species is stored exactly (the reference
+// values are representable and the moments are summed in FP64), so the
+// threshold only guards against round-off. With 16-bit storage, stochastic
+// rounding leaves noise of about one unit in the last place on the populations
+// of a nearly absent species; treating such a species as present would give it
+// an arbitrarily large diffusion velocity, whose quadratic Stefan--Maxwell
+// source makes the step unstable.
+double absent_tol_for(int precision)
+{
+  switch (precision) {
+    case MCLBM_FP16: return 1e-4;
+    case MCLBM_BF16: return 1e-3;
+    default: return 1e-12;
+  }
 }
 
 int upload_params(mclbm_ctx* c, const RefState& rs)
 {
   reference_tables(c->hs, rs, c->ref, c->ref0, c->ref2);
   for (int l = 0; l < MAXL; ++l) c->scale[l] = 1.0;
-  for (int l = 0; l < c->L; ++l) c->scale[l] = scale_for(c->precision, c->ref[l]);
-  HIP_TRY(c, hipStreamSynchronize(c->stream));   // previous uploads from the host blocks are done
-  fill_params<double>(c->hPd, c->hs, c->nx, c->ny, c->nz, c->wall_x, c->ref, c->ref0, c->ref2, c->scale, 1e-300);
-  fill_params<float>(c->hPf, c->hs, c->nx, c->ny, c->nz, c->wall_x, c->ref, c->ref0, c->ref2, c->scale, 1e-30);
-  HIP_TRY(c, hipMemcpyAsync(c->dPd, &c->hPd, sizeof(c->hPd), hipMemcpyHostToDevice, c->stream));
-  if (!compute_is_fp64(c->precision))
-    HIP_TRY(c, hipMemcpyAsync(c->dPr, &c->hPf, sizeof(c->hPf), hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  return MCLBM_OK;
+  for (int l = 0; l < c->L; ++l) {
+    c->scale[l] = scale_for(c->precision, c->ref[l]);
+    c->ref0[l] = 0.0;
+    c->ref2[l] = 0.0;
+    for (int i = 0; i < Q; ++i) {
+      c->ref[l][i] = round_to_storage(c->precision, c->ref[l][i] * c->scale[l]) / c->scale[l];
+      c->ref0[l] += c->ref[l][i];
+      c->ref2[l] += c->ref[l][i] * cx(i) * cx(i);
+    }
+  }
+  return push_params(c);
 }
 
 int record_event(mclbm_ctx* c, int& idx)
@@ -417,11 +479,12 @@ extern "C" int mclbm_step(mclbm_ctx* c, int64_t nsteps)
   for (int64_t t = 0; t < nsteps; ++t) {
     int e0 = 0, e1 = 0, e2 = 0, e3 = 0, rc = 0;
     if (c->timing && (rc = record_event(c, e0))) return rc;
-    c->ops.moments(c->dPr, c->pop[c->cur], c->rec, grid, c->stream);
+    c->ops.moments(c->dPd, c->pop[c->cur], c->rec, grid, c->stream);
     if (c->timing && (rc = record_event(c, e1))) return rc;
-    c->ops.gfield(c->dPr, c->rec, c->G, grid, c->stream);
+    c->ops.gfield(c->dPd, c->rec, c->G, grid, c->stream);
     if (c->timing && (rc = record_event(c, e2))) return rc;
-    c->ops.collide(c->dPr, c->pop[c->cur], c->pop[1 - c->cur], c->rec, c->G, grid, c->stream);
+    c->ops.collide(c->dPr, c->pop[c->cur], c->pop[1 - c->cur], c->rec, c->G, (uint32_t)c->steps, grid,
+                   c->stream);
     if (c->timing) {
       if ((rc = record_event(c, e3))) return rc;
       c->ev_pairs[0].push_back({e0, e1});
@@ -539,11 +602,8 @@ extern "C" int mclbm_load(mclbm_ctx* c, const void* host_buf, size_t bytes)
   std::memcpy(c->ref0, h.ref0, sizeof(h.ref0));
   std::memcpy(c->ref2, h.ref2, sizeof(h.ref2));
   std::memcpy(c->scale, h.scale, sizeof(h.scale));
-  fill_params<double>(c->hPd, c->hs, c->nx, c->ny, c->nz, c->wall_x, c->ref, c->ref0, c->ref2, c->scale, 1e-300);
-  fill_params<float>(c->hPf, c->hs, c->nx, c->ny, c->nz, c->wall_x, c->ref, c->ref0, c->ref2, c->scale, 1e-30);
-  HIP_TRY(c, hipMemcpyAsync(c->dPd, &c->hPd, sizeof(c->hPd), hipMemcpyHostToDevice, c->stream));
-  if (!compute_is_fp64(c->precision))
-    HIP_TRY(c, hipMemcpyAsync(c->dPr, &c->hPf, sizeof(c->hPf), hipMemcpyHostToDevice, c->stream));
+  int rc = push_params(c);
+  if (rc) return rc;
   HIP_TRY(c, hipMemcpyAsync(c->pop[0], (const char*)host_buf + sizeof(h), (size_t)c->L * Q * c->n * c->ops.s_bytes,
                             hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));

@@ -7,19 +7,37 @@
 // ever reads its populations), l = M-1 the momentum lattice f, l = M the energy
 // lattice g; n = x + nx (y + ny z). Stored values are d = s_l (f - f_ref,l,i).
 //
-// A step is three passes: moments_node writes a per-node record
-// {Phi_x, Phi_y, Phi_z, omega, C_p}; gfield_node forms
-// G_a = (1/omega - 1/2) d_a Phi_a; collide_node collides every lattice and
-// pushes the post-collision values to their neighbours (streaming), bouncing
-// them back at x walls.
+// A step is three passes:
+//   state_node    reads every population of a node, forms the moments in FP64,
+//                 the macroscopic state, the transport coefficients, the
+//                 Stefan--Maxwell diffusion velocities (eq transform12) and the
+//                 non-equilibrium energy flux, and writes them as a node record;
+//   gfield_node   G_a = (1/omega - 1/2) d_a Phi_a from the neighbours' records;
+//   collide_node  collides one lattice at a time from the record (reading each
+//                 population once), restores the exact incoming mass, momentum
+//                 and energy of the lattice, and pushes the post-collision values
+//                 to the neighbours (streaming), bouncing them back at x walls.
 #pragma once
+
+#include <type_traits>
 
 #include "lattice.hpp"
 
 namespace mclbm {
 
-// Record layout (structure of arrays): rec[k * n + node].
-enum { REC_PHIX = 0, REC_PHIY = 1, REC_PHIZ = 2, REC_OMEGA = 3, REC_CP = 4, REC_FIELDS = 5 };
+// Node record (structure of arrays, rec[k * n + node]).
+enum {
+  REC_PHIX = 0, REC_PHIY = 1, REC_PHIZ = 2,   // Phi_a = rho u_a (1 - 3 R T) - rho u_a^3 (eq Xalpha)
+  REC_OMEGA = 3, REC_CP = 4,                   // omega (eq omega), mixture C_p
+  REC_RHO = 5, REC_UX = 6, REC_UY = 7, REC_UZ = 8, REC_T = 9, REC_OMEGA1 = 10,
+  REC_QNX = 11, REC_QNY = 12, REC_QNZ = 13,    // q - q^eq - u.(P - P^eq)
+  REC_RHOA = 14                                // then rho_a (M-1 stored species), V_a (3 M)
+};
+template <int M>
+struct RecLayout {
+  static constexpr int V = REC_RHOA + (M - 1);
+  static constexpr int FIELDS = V + 3 * M;
+};
 
 // Macroscopic state of a node (Secs. 2.1, 3.1, 3.2; strong coupling Sec. 3.6.2).
 template <typename R, int M>
@@ -152,52 +170,195 @@ __host__ __device__ inline bool is_ghost(const Nbr& b, int ci)
 }
 
 // --------------------------------------------------------------------------
-// Pass 1: moments -> record {Phi, omega, C_p}
+// Diffusion velocities: rho_a V_a + 1/2 sum_b K_ab (V_a - V_b) = j_a - rho_a u
+// (eq transform12), with K_ab = P X_a X_b / D_ab. A species whose density is at
+// or below the detection threshold has a zero row and column: V_a = 0.
 // --------------------------------------------------------------------------
-template <typename S, typename R, int M>
-__host__ __device__ inline void moments_node(const Params<R>& P, const S* __restrict__ pop,
-                                             R* __restrict__ rec, int64_t node)
+template <typename R, int M>
+__host__ __device__ inline void species_present(const Params<R>& P, const R rho_a[M], R rho, bool present[M])
 {
+#pragma unroll
+  for (int a = 0; a < M; ++a) present[a] = rho_a[a] > P.absent_tol * rho || rho_a[a] < -P.absent_tol * rho;
+}
+
+template <typename R, int M>
+__host__ __device__ inline void friction_matrix(const Params<R>& P, const Mix<R, M>& s, const bool present[M],
+                                                R K[M][M])
+{
+#pragma unroll
+  for (int a = 0; a < M; ++a)
+#pragma unroll
+    for (int c = 0; c < M; ++c)
+      K[a][c] = (present[a] && present[c]) ? s.P * s.X[a] * s.X[c] * P.invD[a][c] : R(0);
+}
+
+template <typename R, int M>
+__host__ __device__ inline void diffusion_velocities(const Mix<R, M>& s, const bool present[M], const R K[M][M],
+                                                     const R js[M][3], R V[M][3])
+{
+  R A[M][M], rhs[M][3];
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    R diag = present[a] ? s.rho_a[a] : R(1);
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+      if (c == a) continue;
+      diag += R(0.5) * K[a][c];
+      A[a][c] = -R(0.5) * K[a][c];
+    }
+    A[a][a] = diag;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) rhs[a][k] = present[a] ? js[a][k] - s.rho_a[a] * s.u[k] : R(0);
+  }
+  // Gaussian elimination without pivoting: the matrix is column diagonally dominant
+#pragma unroll
+  for (int c = 0; c < M; ++c) {
+    const R inv = R(1) / A[c][c];
+#pragma unroll
+    for (int r = c + 1; r < M; ++r) {
+      const R f = A[r][c] * inv;
+#pragma unroll
+      for (int c2 = c + 1; c2 < M; ++c2) A[r][c2] -= f * A[c][c2];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) rhs[r][k] -= f * rhs[c][k];
+    }
+  }
+#pragma unroll
+  for (int r = M - 1; r >= 0; --r) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      R acc = rhs[r][k];
+#pragma unroll
+      for (int c = r + 1; c < M; ++c) acc -= A[r][c] * V[c][k];
+      V[r][k] = acc / A[r][r];
+    }
+  }
+}
+
+// Compiler barrier between the lattices of a node: loads after it are not hoisted
+// above it, which bounds the number of loads a thread keeps in flight (and the
+// registers holding them) to one lattice.
+__host__ __device__ inline void lattice_barrier()
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+  __asm__ __volatile__("" ::: "memory");
+#endif
+}
+
+// Sign-selected accumulation: acc += c v for c in {-1, 0, 1} known at compile time.
+template <typename R>
+__host__ __device__ inline void acc_c(R& acc, int c, R v)
+{
+  if (c > 0) acc += v;
+  if (c < 0) acc -= v;
+}
+
+// --------------------------------------------------------------------------
+// Pass 1: node state -> record (FP64 arithmetic, record stored as Rec)
+// --------------------------------------------------------------------------
+template <typename S, typename Rec, int M>
+__host__ __device__ inline void state_node(const Params<double>& P, const S* __restrict__ pop,
+                                           Rec* __restrict__ rec, int64_t node)
+{
+  using D = double;
   const size_t n = (size_t)P.n;
   constexpr int LF = M - 1, LG = M;
-  R rho_s[M];
+  D rho_s[M], js[M][3];
 #pragma unroll
   for (int a = 0; a < M - 1; ++a) {
-    R sum = R(0);
+    D r = 0.0, ja[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-    for (int i = 0; i < Q; ++i) sum += load_dev<S, R>(pop, (size_t)(a * Q + i) * n + node, P.inv_scale[a]);
-    rho_s[a] = P.ref0[a] + sum;
+    for (int i = 0; i < Q; ++i) {
+      const D d = load_dev<S, D>(pop, (size_t)(a * Q + i) * n + node, P.inv_scale[a]);
+      r += d;
+      acc_c(ja[0], cx(i), d);
+      acc_c(ja[1], cy(i), d);
+      acc_c(ja[2], cz(i), d);
+    }
+    rho_s[a] = P.ref0[a] + r;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) js[a][k] = ja[k];
+    lattice_barrier();
   }
-  rho_s[M - 1] = R(0);
-  R rho = R(0), j[3] = {R(0), R(0), R(0)}, rhoE = R(0);
+  rho_s[M - 1] = 0.0;
+  D rho = 0.0, j[3] = {0.0, 0.0, 0.0}, Pd[3] = {0.0, 0.0, 0.0}, Pxy = 0.0, Pxz = 0.0, Pyz = 0.0;
+  D rhoE = 0.0, q[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    R d = load_dev<S, R>(pop, (size_t)(LF * Q + i) * n + node, P.inv_scale[LF]);
+    const D d = load_dev<S, D>(pop, (size_t)(LF * Q + i) * n + node, P.inv_scale[LF]);
     rho += d;
-    if (cx(i)) j[0] += cx(i) > 0 ? d : -d;
-    if (cy(i)) j[1] += cy(i) > 0 ? d : -d;
-    if (cz(i)) j[2] += cz(i) > 0 ? d : -d;
-    rhoE += load_dev<S, R>(pop, (size_t)(LG * Q + i) * n + node, P.inv_scale[LG]);
+    acc_c(j[0], cx(i), d);
+    acc_c(j[1], cy(i), d);
+    acc_c(j[2], cz(i), d);
+    if (cx(i)) Pd[0] += d;
+    if (cy(i)) Pd[1] += d;
+    if (cz(i)) Pd[2] += d;
+    acc_c(Pxy, cx(i) * cy(i), d);
+    acc_c(Pxz, cx(i) * cz(i), d);
+    acc_c(Pyz, cy(i) * cz(i), d);
+    const D e = load_dev<S, D>(pop, (size_t)(LG * Q + i) * n + node, P.inv_scale[LG]);
+    rhoE += e;
+    acc_c(q[0], cx(i), e);
+    acc_c(q[1], cy(i), e);
+    acc_c(q[2], cz(i), e);
   }
   rho += P.ref0[LF];
   rhoE += P.ref0[LG];
-  Mix<R, M> s;
-  mixture_state<R, M>(P, rho, j, rhoE, rho_s, s);
-  R theta = s.Rg * s.T;
-  R mu = mixture_viscosity<R, M>(P, s.X);
-  R omega = R(2) * s.P / (s.P + R(2) * mu);
 #pragma unroll
-  for (int k = 0; k < 3; ++k)   // Phi_a = rho u_a (1 - 3 R T) - rho u_a^3 (eq Xalpha)
-    rec[(size_t)k * n + node] = j[k] * (R(1) - R(3) * theta) - j[k] * s.u[k] * s.u[k];
-  rec[(size_t)REC_OMEGA * n + node] = omega;
-  rec[(size_t)REC_CP * n + node] = s.Cp;
+  for (int k = 0; k < 3; ++k) Pd[k] += P.ref2[LF];
+  Mix<D, M> s;
+  mixture_state<D, M>(P, rho, j, rhoE, rho_s, s);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {          // slaved species momentum: the deficit (eq uMATCH)
+    D jm = j[k];
+#pragma unroll
+    for (int a = 0; a < M - 1; ++a) jm -= js[a][k];
+    js[M - 1][k] = jm;
+  }
+  bool present[M];
+  species_present<D, M>(P, s.rho_a, s.rho, present);
+  D K[M][M], V[M][3];
+  friction_matrix<D, M>(P, s, present, K);
+  diffusion_velocities<D, M>(s, present, K, js, V);
+  const D theta = s.Rg * s.T;
+  const D omega = 2.0 * s.P / (s.P + 2.0 * mixture_viscosity<D, M>(P, s.X));
+  const D omega1 = 2.0 * s.P * s.Cp / (s.P * s.Cp + 2.0 * mixture_conductivity<D, M>(P, s.X));
+  // non-equilibrium energy flux q - q^eq - u.(P - P^eq), used by the energy collision
+  const D hyd = s.Cp * s.T + 0.5 * s.usq;
+  const D Pn[3][3] = {{Pd[0], Pxy, Pxz}, {Pxy, Pd[1], Pyz}, {Pxz, Pyz, Pd[2]}};
+  D qn[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    D up = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) up += s.u[c] * (Pn[c][k] - (c == k ? s.P : 0.0) - rho * s.u[c] * s.u[k]);
+    qn[k] = q[k] - hyd * rho * s.u[k] - up;
+  }
+  auto put = [&](int f, D v) { rec[(size_t)f * n + node] = Rec(v); };
+#pragma unroll
+  for (int k = 0; k < 3; ++k) put(REC_PHIX + k, j[k] * (1.0 - 3.0 * theta) - j[k] * s.u[k] * s.u[k]);
+  put(REC_OMEGA, omega);
+  put(REC_CP, s.Cp);
+  put(REC_RHO, rho);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) put(REC_UX + k, s.u[k]);
+  put(REC_T, s.T);
+  put(REC_OMEGA1, omega1);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) put(REC_QNX + k, qn[k]);
+#pragma unroll
+  for (int a = 0; a < M - 1; ++a) put(REC_RHOA + a, s.rho_a[a]);
+#pragma unroll
+  for (int a = 0; a < M; ++a)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) put(RecLayout<M>::V + 3 * a + k, V[a][k]);
 }
 
 // --------------------------------------------------------------------------
 // Pass 2: G_a = (1/omega - 1/2) d_a Phi_a, with d_a = 3 sum_i w_i c_ia (.)(x + c_i)
 // --------------------------------------------------------------------------
 template <typename R, bool WALLS>
-__host__ __device__ inline void gfield_node(const Params<R>& P, const R* __restrict__ rec,
+__host__ __device__ inline void gfield_node(const Params<double>& P, const R* __restrict__ rec,
                                             R* __restrict__ G, int64_t node)
 {
   const size_t n = (size_t)P.n;
@@ -231,286 +392,305 @@ __host__ __device__ inline void gfield_node(const Params<R>& P, const R* __restr
 // --------------------------------------------------------------------------
 // Pass 3: collide every lattice and push (stream) to the other buffer
 // --------------------------------------------------------------------------
+// Counter-based hash (a 32-bit integer mixer) for stochastic rounding.
+__host__ __device__ inline uint32_t mix32(uint32_t x)
+{
+  x ^= x >> 16;
+  x *= 0x7feb352dU;
+  x ^= x >> 15;
+  x *= 0x846ca68bU;
+  x ^= x >> 16;
+  return x;
+}
+
+// Conversion of a scaled deviation to the storage type. 32- and 64-bit storage
+// round to nearest; 16-bit storage rounds stochastically (to either neighbour
+// with probability proportional to proximity), which removes the bias that
+// round-to-nearest accumulates in slowly varying regions.
+template <typename S, typename R>
+struct Store {
+  __host__ __device__ static S cvt(R v, uint32_t) { return S(v); }
+};
+
+template <>
+struct Store<_Float16, float> {
+  __host__ __device__ static _Float16 cvt(float x, uint32_t key)
+  {
+    const _Float16 h = (_Float16)x;
+    const float back = (float)h;
+    const float diff = x - back;
+    if (diff == 0.0f || !(diff == diff) || back - back != 0.0f) return h;
+    uint16_t bits;
+    __builtin_memcpy(&bits, &h, 2);
+    const bool neg = bits & 0x8000;
+    const bool up = diff > 0.0f;
+    uint16_t nb;
+    if ((bits & 0x7fff) == 0) nb = up ? 0x0001 : 0x8001;
+    else nb = (up != neg) ? (uint16_t)(bits + 1) : (uint16_t)(bits - 1);
+    _Float16 hn;
+    __builtin_memcpy(&hn, &nb, 2);
+    const float other = (float)hn;
+    if (other - other != 0.0f) return h;                 // never round into infinity
+    const float span = other > back ? other - back : back - other;
+    const float ad = diff > 0.0f ? diff : -diff;
+    const float r = (float)(mix32(key) >> 8) * (1.0f / 16777216.0f);
+    return r * span < ad ? hn : h;
+  }
+};
+
+template <>
+struct Store<__bf16, float> {
+  __host__ __device__ static __bf16 cvt(float x, uint32_t key)
+  {
+    uint32_t u;
+    __builtin_memcpy(&u, &x, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (__bf16)x;   // inf / nan
+    const uint32_t r = u + (mix32(key) & 0xffffu);           // add below the kept bits
+    const uint16_t hi = (uint16_t)(((r & 0x7f800000u) == 0x7f800000u ? u : r) >> 16);
+    __bf16 b;
+    __builtin_memcpy(&b, &hi, 2);
+    return b;
+  }
+};
+
+// Round a post-collision deviation of lattice l, direction i, to storage.
+template <typename S, typename R>
+__host__ __device__ inline S to_store(const Params<R>& P, int l, int i, int64_t node, R dev, uint32_t step)
+{
+  const uint32_t key = mix32((uint32_t)node ^ mix32((uint32_t)(l * Q + i) + step * 0x9E3779B1u));
+  return Store<S, R>::cvt(dev * P.scale[l], key);
+}
+
+template <typename S, typename R>
+__host__ __device__ inline R from_store(const Params<R>& P, int l, S v)
+{
+  return R(v) * P.inv_scale[l];
+}
+
+// Streaming: write the post-collision value of direction i to the neighbour
+// x + c_i of the other buffer, or bounce it back at an x wall.
 template <typename S, typename R, bool WALLS>
 __host__ __device__ inline void push(const Params<R>& P, S* __restrict__ dst, const Nbr& b, int l, int i,
-                                     int64_t node, R dev)
+                                     int64_t node, S v)
 {
   const size_t n = (size_t)P.n;
-  S v = S(dev * P.scale[l]);
   if (WALLS && ((cx(i) < 0 && b.lo) || (cx(i) > 0 && b.hi))) {
     dst[(size_t)(l * Q + opp(i)) * n + node] = v;    // half-way bounce-back
   } else {
-    int64_t d = b.x[cx(i) + 1] + b.y[cy(i) + 1] + b.z[cz(i) + 1];
+    const int64_t d = b.x[cx(i) + 1] + b.y[cy(i) + 1] + b.z[cz(i) + 1];
     dst[(size_t)(l * Q + i) * n + d] = v;
   }
 }
 
-template <typename S, typename R, int M, bool WALLS>
+template <typename S, typename R, typename Rec, int M, bool WALLS>
 __host__ __device__ inline void collide_node(const Params<R>& P, const S* __restrict__ src,
-                                             S* __restrict__ dst, const R* __restrict__ rec,
-                                             const R* __restrict__ G, int64_t node)
+                                             S* __restrict__ dst, const Rec* __restrict__ rec,
+                                             const Rec* __restrict__ G, int64_t node, uint32_t step)
 {
   const size_t n = (size_t)P.n;
   constexpr int LF = M - 1, LG = M;
   const Nbr b = neighbours(P, node);
+  auto get = [&](int f) -> R { return R(rec[(size_t)f * n + node]); };
 
-  // ---- moments of the momentum and energy lattices
-  R rho = R(0), j[3] = {R(0), R(0), R(0)}, Pf[3] = {R(0), R(0), R(0)}, Pxy = R(0), Pxz = R(0), Pyz = R(0);
-  R rhoE = R(0), q[3] = {R(0), R(0), R(0)};
-  R df[Q], dg[Q];
+  // ---- node state from the record
+  const R rho = get(REC_RHO);
+  R rho_s[M];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    df[i] = load_dev<S, R>(src, (size_t)(LF * Q + i) * n + node, P.inv_scale[LF]);
-    dg[i] = load_dev<S, R>(src, (size_t)(LG * Q + i) * n + node, P.inv_scale[LG]);
-  }
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const R d = df[i];
-    rho += d;
-    if (cx(i)) { j[0] += cx(i) > 0 ? d : -d; Pf[0] += d; }
-    if (cy(i)) { j[1] += cy(i) > 0 ? d : -d; Pf[1] += d; }
-    if (cz(i)) { j[2] += cz(i) > 0 ? d : -d; Pf[2] += d; }
-    if (cx(i) && cy(i)) Pxy += cx(i) * cy(i) > 0 ? d : -d;
-    if (cx(i) && cz(i)) Pxz += cx(i) * cz(i) > 0 ? d : -d;
-    if (cy(i) && cz(i)) Pyz += cy(i) * cz(i) > 0 ? d : -d;
-    const R e = dg[i];
-    rhoE += e;
-    if (cx(i)) q[0] += cx(i) > 0 ? e : -e;
-    if (cy(i)) q[1] += cy(i) > 0 ? e : -e;
-    if (cz(i)) q[2] += cz(i) > 0 ? e : -e;
-  }
-  rho += P.ref0[LF];
-  rhoE += P.ref0[LG];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) Pf[k] += P.ref2[LF];
-
-  // ---- species moments
-  R ds[M > 1 ? M - 1 : 1][Q];
-  R rho_s[M], js[M][3];
-#pragma unroll
-  for (int a = 0; a < M - 1; ++a) {
-    R r = R(0), ja[3] = {R(0), R(0), R(0)};
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const R d = load_dev<S, R>(src, (size_t)(a * Q + i) * n + node, P.inv_scale[a]);
-      ds[a][i] = d;
-      r += d;
-      if (cx(i)) ja[0] += cx(i) > 0 ? d : -d;
-      if (cy(i)) ja[1] += cy(i) > 0 ? d : -d;
-      if (cz(i)) ja[2] += cz(i) > 0 ? d : -d;
-    }
-    rho_s[a] = P.ref0[a] + r;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) js[a][k] = ja[k];
-  }
+  for (int a = 0; a < M - 1; ++a) rho_s[a] = get(REC_RHOA + a);
   rho_s[M - 1] = R(0);
   Mix<R, M> s;
-  mixture_state<R, M>(P, rho, j, rhoE, rho_s, s);
-  // slaved species momentum is the deficit (eq uMATCH)
+  {
+    s.rho = rho;
+    s.inv_rho = R(1) / rho;
+    s.usq = R(0);
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    R jm = j[k];
+    for (int k = 0; k < 3; ++k) {
+      s.u[k] = get(REC_UX + k);
+      s.usq += s.u[k] * s.u[k];
+    }
+    R deficit = rho;
 #pragma unroll
-    for (int a = 0; a < M - 1; ++a) jm -= js[a][k];
-    js[M - 1][k] = jm;
+    for (int a = 0; a < M - 1; ++a) {
+      s.rho_a[a] = rho_s[a];
+      deficit -= rho_s[a];
+    }
+    s.rho_a[M - 1] = deficit;
+    R inv_m = R(0), Cp = R(0);
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+      s.Y[a] = s.rho_a[a] * s.inv_rho;
+      inv_m += s.Y[a] * P.inv_m[a];
+      Cp += s.Y[a] * P.cp[a];
+    }
+    s.Rg = inv_m;
+    s.mmix = R(1) / inv_m;
+#pragma unroll
+    for (int a = 0; a < M; ++a) s.X[a] = s.Y[a] * s.mmix * P.inv_m[a];
+    s.Cp = Cp;
+    s.T = get(REC_T);
+    s.P = rho * s.Rg * s.T;
   }
   const R theta = s.Rg * s.T;
-  const R mu = mixture_viscosity<R, M>(P, s.X);
-  const R lam = mixture_conductivity<R, M>(P, s.X);
-  const R omega = R(2) * s.P / (s.P + R(2) * mu);
-  const R omega1 = R(2) * s.P * s.Cp / (s.P * s.Cp + R(2) * lam);
+  const R omega = get(REC_OMEGA);
+  const R omega1 = get(REC_OMEGA1);
 
-  // ---- non-local terms: X_a = -d_a G_a and d_a C_p (sum_a H_a d Y_a = T d C_p)
-  R Xc[3] = {R(0), R(0), R(0)}, gcp[3] = {R(0), R(0), R(0)};
+  // ---- non-local terms: X_a = -d_a G_a (eq Xalpha) and d_a C_p (sum_a H_a d Y_a = T d C_p)
+  R dG[3] = {R(0), R(0), R(0)}, gcp[3] = {R(0), R(0), R(0)};
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     if (csq(i) == 0) continue;
     const int64_t nb = stencil_index<WALLS>(b, cx(i), cy(i), cz(i));
     const R w3 = R(3.0 * w13(i));
-    const R cpn = rec[(size_t)REC_CP * n + nb];
-    if (cx(i)) {
-      R g = G[nb];
-      Xc[0] += cx(i) > 0 ? w3 * g : -(w3 * g);
-      gcp[0] += cx(i) > 0 ? w3 * cpn : -(w3 * cpn);
-    }
-    if (cy(i)) {
-      R g = G[n + nb];
-      Xc[1] += cy(i) > 0 ? w3 * g : -(w3 * g);
-      gcp[1] += cy(i) > 0 ? w3 * cpn : -(w3 * cpn);
-    }
-    if (cz(i)) {
-      R g = G[2 * n + nb];
-      Xc[2] += cz(i) > 0 ? w3 * g : -(w3 * g);
-      gcp[2] += cz(i) > 0 ? w3 * cpn : -(w3 * cpn);
-    }
+    const R cpn = w3 * R(rec[(size_t)REC_CP * n + nb]);
+    acc_c(gcp[0], cx(i), cpn);
+    acc_c(gcp[1], cy(i), cpn);
+    acc_c(gcp[2], cz(i), cpn);
+    if (cx(i)) acc_c(dG[0], cx(i), w3 * R(G[nb]));
+    if (cy(i)) acc_c(dG[1], cy(i), w3 * R(G[n + nb]));
+    if (cz(i)) acc_c(dG[2], cz(i), w3 * R(G[2 * n + nb]));
   }
-#pragma unroll
-  for (int k = 0; k < 3; ++k) Xc[k] = -Xc[k];
-
-  // ---- species: Stefan--Maxwell rates (eqs tauab, tau), K_ab = P X_a X_b / D_ab
-  R K[M][M], beta[M];
-#pragma unroll
-  for (int a = 0; a < M; ++a) {
-    R acc = R(0);
-#pragma unroll
-    for (int c = 0; c < M; ++c) {
-      K[a][c] = s.P * s.X[a] * s.X[c] * P.invD[a][c];
-      acc += s.Y[c] * P.invD[a][c] * P.inv_m[c];
-    }
-    const R inv_tau = s.T * s.mmix * P.inv_m[a] * acc;
-    beta[a] = inv_tau / (R(2) + inv_tau);              // dt / (2 tau_a + dt)
-  }
-  // diffusion velocities: rho_a V_a + 1/2 sum_b K_ab (V_a - V_b) = j_a - rho_a u (eq transform12)
-  R A[M][M], rhs[M][3], V[M][3];
-#pragma unroll
-  for (int a = 0; a < M; ++a) {
-    R diag = s.rho_a[a];
-#pragma unroll
-    for (int c = 0; c < M; ++c) {
-      if (c == a) continue;
-      diag += R(0.5) * K[a][c];
-      A[a][c] = -R(0.5) * K[a][c];
-    }
-    A[a][a] = diag;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) rhs[a][k] = js[a][k] - s.rho_a[a] * s.u[k];
-  }
-  // Gaussian elimination without pivoting: the matrix is column diagonally
-  // dominant wherever rho_a != 0; an absent species has a zero row and column.
-  bool present[M];
-#pragma unroll
-  for (int c = 0; c < M; ++c) {
-    const R piv = A[c][c];
-    present[c] = piv > P.pivot_tiny || piv < -P.pivot_tiny;
-    const R inv = present[c] ? R(1) / piv : R(0);
-#pragma unroll
-    for (int r = c + 1; r < M; ++r) {
-      const R f = A[r][c] * inv;
-#pragma unroll
-      for (int cc2 = c + 1; cc2 < M; ++cc2) A[r][cc2] -= f * A[c][cc2];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) rhs[r][k] -= f * rhs[c][k];
-    }
-  }
-#pragma unroll
-  for (int r = M - 1; r >= 0; --r) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      R acc = rhs[r][k];
-#pragma unroll
-      for (int c = r + 1; c < M; ++c) acc -= A[r][c] * V[c][k];
-      V[r][k] = present[r] ? acc / A[r][r] : R(0);
-    }
-  }
+  const R Xc[3] = {-dG[0], -dG[1], -dG[2]};
 
   // ---- species collision: f' = f + 2 beta (f^eq - f) + (beta - 1) F (eq SMlbm),
-  // F_ai = sum_b K_ab [Psi_i(u, R_b T) - Psi_i(u + V_b, R_b T)] (eq fstar1)
-  Trip<R> pe[M][3], pv[M][3], pd[M][3];
+  // F_ai = sum_b K_ab [Psi_i(u, R_b T) - Psi_i(u + V_b, R_b T)] (eq fstar1), with
+  // K_ab = P X_a X_b / D_ab, 1/tau_a = sum_b Y_b / tau_ab (eqs tauab, tau).
+  {
+    bool present[M];
+    species_present<R, M>(P, s.rho_a, s.rho, present);
+    R K[M][M];
+    friction_matrix<R, M>(P, s, present, K);
+    // F_ai is a small correction: with 32- or 16-bit storage its triplets are kept
+    // in FP32 (pe32: Psi(u), pd32: Psi(u) - Psi(u + V)); with FP64 storage in FP64.
+    using F32 = typename std::conditional<sizeof(S) == 8, double, float>::type;
+    Trip<F32> pe32[M][3], pd32[M][3];
 #pragma unroll
-  for (int c = 0; c < M; ++c) {
-    const R zeta = s.T * P.inv_m[c];
+    for (int c = 0; c < M; ++c) {
+      const F32 zeta = F32(s.T * P.inv_m[c]);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      pe[c][k] = psi_trip<R>(s.u[k], zeta);
-      pv[c][k] = psi_trip<R>(s.u[k] + V[c][k], zeta);
-      pd[c][k] = psi_diff_trip<R>(s.u[k], V[c][k]);
+      for (int k = 0; k < 3; ++k) {
+        pe32[c][k] = psi_trip<F32>(F32(s.u[k]), zeta);
+        pd32[c][k] = psi_diff_trip<F32>(F32(s.u[k]), F32(get(RecLayout<M>::V + 3 * c + k)));
+      }
     }
-  }
-  // Non-equilibrium parts f - f^eq of every stored species. In finite precision
-  // the rounded equilibria do not sum exactly to rho_a; that defect is taken out
-  // of the rest population so that the collision conserves rho_a up to the
-  // rounding of the (small) non-equilibrium part. The rest population carries
-  // no first or second moment, so nothing else changes.
-#pragma unroll
-  for (int a = 0; a < M - 1; ++a) {
-    R s0 = R(0);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const R feq = s.rho_a[a] * (pe[a][0](cx(i)) * pe[a][1](cy(i)) * pe[a][2](cz(i)));
-      ds[a][i] = ds[a][i] - (feq - P.ref[a][i]);   // now holds the deviation's non-equilibrium part
-      s0 += ds[a][i];
-    }
-    ds[a][13] -= s0;
-  }
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    R dpsi[M];
-#pragma unroll
-    for (int c = 0; c < M; ++c)
-      dpsi[c] = pd[c][0](cx(i)) * pe[c][1](cy(i)) * pe[c][2](cz(i)) +
-                pv[c][0](cx(i)) * pd[c][1](cy(i)) * pe[c][2](cz(i)) +
-                pv[c][0](cx(i)) * pv[c][1](cy(i)) * pd[c][2](cz(i));
 #pragma unroll
     for (int a = 0; a < M - 1; ++a) {
-      R F = R(0);
+      R acc = R(0);
 #pragma unroll
-      for (int c = 0; c < M; ++c) F += K[a][c] * dpsi[c];
-      const R feq = s.rho_a[a] * (pe[a][0](cx(i)) * pe[a][1](cy(i)) * pe[a][2](cz(i)));
-      const R neq = ds[a][i];
-      // f' - f_ref = (f^eq - f_ref) + (1 - 2 beta)(f - f^eq) + (beta - 1) F
-      const R dn = (feq - P.ref[a][i]) + (R(1) - R(2) * beta[a]) * neq + (beta[a] - R(1)) * F;
-      push<S, R, WALLS>(P, dst, b, a, i, node, dn);
+      for (int c = 0; c < M; ++c) acc += s.Y[c] * P.invD[a][c] * P.inv_m[c];
+      const R inv_tau = s.T * s.mmix * P.inv_m[a] * acc;
+      const R beta = inv_tau / (R(2) + inv_tau);            // dt / (2 tau_a + dt)
+      Trip<R> pa[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) pa[k] = psi_trip<R>(s.u[k], s.T * P.inv_m[a]);
+      S v[Q];
+      R t0 = R(0), s0 = R(0);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        v[i] = src[(size_t)(a * Q + i) * n + node];
+        t0 += from_store<S, R>(P, a, v[i]);
+      }
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        if (i == 13) continue;
+        F32 F = F32(0);
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+          const F32 ex = pe32[c][0](cx(i)), ey = pe32[c][1](cy(i)), ez = pe32[c][2](cz(i));
+          const F32 dx = pd32[c][0](cx(i)), dy = pd32[c][1](cy(i)), dz = pd32[c][2](cz(i));
+          F += F32(K[a][c]) * (dx * ey * ez + (ex - dx) * dy * ez + (ex - dx) * (ey - dy) * dz);
+        }
+        const R fe = s.rho_a[a] * (pa[0](cx(i)) * pa[1](cy(i)) * pa[2](cz(i))) - P.ref[a][i];
+        // f' - f_ref = (f^eq - f_ref) + (1 - 2 beta)(f - f^eq) + (beta - 1) F
+        const R dn = fe + (R(1) - R(2) * beta) * (from_store<S, R>(P, a, v[i]) - fe) + (beta - R(1)) * R(F);
+        v[i] = to_store<S, R>(P, a, i, node, dn, step);
+        s0 += from_store<S, R>(P, a, v[i]);
+      }
+      // the collision conserves rho_a: the rest population takes the defect of
+      // the arithmetic and of the other 26 values' rounding to storage
+      v[13] = to_store<S, R>(P, a, 13, node, t0 - s0, step);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) push<S, R, WALLS>(P, dst, b, a, i, node, v[i]);
+      lattice_barrier();
     }
   }
 
   // ---- momentum lattice: f' = f + omega (f^eq - f) + A_i . X (eqs fwithcorrection, Ai);
-  // the rounding defect of the equilibrium's mass and momentum is moved onto the
-  // rest and face populations (which carry no other moment up to second order).
+  // the rounding defect of mass and momentum goes to the rest and face populations,
+  // which carry no other moment up to second order.
   {
     Trip<R> pf[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) pf[k] = psi_trip<R>(s.u[k], theta);
-    R fe[Q];
-    R s0 = R(0), s1[3] = {R(0), R(0), R(0)};
+    S v[Q];
+    R t0 = R(0), t1[3] = {R(0), R(0), R(0)}, s0 = R(0), s1[3] = {R(0), R(0), R(0)};
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      fe[i] = rho * (pf[0](cx(i)) * pf[1](cy(i)) * pf[2](cz(i))) - P.ref[LF][i];
-      df[i] = df[i] - fe[i];                      // non-equilibrium part
-      s0 += df[i];
-      if (cx(i)) s1[0] += cx(i) > 0 ? df[i] : -df[i];
-      if (cy(i)) s1[1] += cy(i) > 0 ? df[i] : -df[i];
-      if (cz(i)) s1[2] += cz(i) > 0 ? df[i] : -df[i];
+      v[i] = src[(size_t)(LF * Q + i) * n + node];
+      const R d = from_store<S, R>(P, LF, v[i]);
+      t0 += d;
+      acc_c(t1[0], cx(i), d);
+      acc_c(t1[1], cy(i), d);
+      acc_c(t1[2], cz(i), d);
     }
-    df[13] -= s0;
-    df[22] -= R(0.5) * s1[0]; df[4] += R(0.5) * s1[0];    // faces +-x
-    df[16] -= R(0.5) * s1[1]; df[10] += R(0.5) * s1[1];   // faces +-y
-    df[14] -= R(0.5) * s1[2]; df[12] += R(0.5) * s1[2];   // faces +-z
+    // the source A_i . X adds X to the momentum (A_i = c_i / 2 on the six faces)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) t1[k] += Xc[k];
+    // all but the rest and face populations: collide and round to storage
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      R dn = fe[i] + (R(1) - omega) * df[i];
-      if (csq(i) == 1) {
-        const R ax = cx(i) ? (cx(i) > 0 ? Xc[0] : -Xc[0]) : (cy(i) ? (cy(i) > 0 ? Xc[1] : -Xc[1])
-                                                                   : (cz(i) > 0 ? Xc[2] : -Xc[2]));
-        dn += R(0.5) * ax;
-      }
-      push<S, R, WALLS>(P, dst, b, LF, i, node, dn);
+      if (csq(i) <= 1) continue;
+      const R fe = rho * (pf[0](cx(i)) * pf[1](cy(i)) * pf[2](cz(i))) - P.ref[LF][i];
+      const R dn = fe + (R(1) - omega) * (from_store<S, R>(P, LF, v[i]) - fe);
+      v[i] = to_store<S, R>(P, LF, i, node, dn, step);
+      const R d = from_store<S, R>(P, LF, v[i]);
+      s0 += d;
+      acc_c(s1[0], cx(i), d);
+      acc_c(s1[1], cy(i), d);
+      acc_c(s1[2], cz(i), d);
     }
+    // the face pairs carry the momentum defect, the rest population the mass
+    // defect: each face pair keeps its equilibrium-relaxed sum and takes the
+    // difference that restores rho u + X exactly
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int ip = k == 0 ? 22 : (k == 1 ? 16 : 14), im = 26 - ip;
+      const R fep = rho * (pf[0](cx(ip)) * pf[1](cy(ip)) * pf[2](cz(ip))) - P.ref[LF][ip];
+      const R fem = rho * (pf[0](cx(im)) * pf[1](cy(im)) * pf[2](cz(im))) - P.ref[LF][im];
+      const R dp = fep + (R(1) - omega) * (from_store<S, R>(P, LF, v[ip]) - fep);
+      const R dm = fem + (R(1) - omega) * (from_store<S, R>(P, LF, v[im]) - fem);
+      const R sum = dp + dm;
+      const R diff = t1[k] - s1[k];        // required dp - dm
+      v[ip] = to_store<S, R>(P, LF, ip, node, R(0.5) * (sum + diff), step);
+      v[im] = to_store<S, R>(P, LF, im, node, R(0.5) * (sum - diff), step);
+      s0 += from_store<S, R>(P, LF, v[ip]) + from_store<S, R>(P, LF, v[im]);
+    }
+    v[13] = to_store<S, R>(P, LF, 13, node, t0 - s0, step);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) push<S, R, WALLS>(P, dst, b, LF, i, node, v[i]);
+    lattice_barrier();
   }
 
   // ---- energy lattice (eq g), in the form g' = g + omega (g^eq - g) + w_i c_i . dq / theta,
   // dq = (omega - omega_1)(q - q^eq - u.(P - P^eq)) + omega_1 rho sum_a H_a Y_a V_a
-  //      + (2 - omega_1)/2 P sum_a H_a d Y_a
+  //      + (2 - omega_1)/2 P sum_a H_a d Y_a     (the exact rewrite of eqs g, gistar,
+  // gstareq1mom, interdiffusion and corrFourier that has no pole at omega = omega_1)
   {
     const R H = s.Cp * s.T;
     const R hyd = H + R(0.5) * s.usq;
     const R inv_theta = R(1) / theta;
+    const R rhoE = rho * (H - s.Rg * s.T + R(0.5) * s.usq);   // rho (C_v T + u^2/2), C_v = C_p - R
     R qeq[3], dq[3];
-    const R Pxx = Pf[0], Pyy = Pf[1], Pzz = Pf[2];
-    const R Pn[3][3] = {{Pxx, Pxy, Pxz}, {Pxy, Pyy, Pyz}, {Pxz, Pyz, Pzz}};
     R hyv[3] = {R(0), R(0), R(0)};
 #pragma unroll
     for (int a = 0; a < M; ++a) {
       const R ca = P.cp[a] * s.Y[a];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) hyv[k] += ca * V[a][k];
+      for (int k = 0; k < 3; ++k) hyv[k] += ca * get(RecLayout<M>::V + 3 * a + k);
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       qeq[k] = hyd * rho * s.u[k];
-      R up = R(0);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) up += s.u[c] * (Pn[c][k] - (c == k ? s.P : R(0)) - rho * s.u[c] * s.u[k]);
-      dq[k] = (omega - omega1) * (q[k] - qeq[k] - up) + omega1 * rho * s.T * hyv[k] +
+      dq[k] = (omega - omega1) * get(REC_QNX + k) + omega1 * rho * s.T * hyv[k] +
               R(0.5) * (R(2) - omega1) * s.P * s.T * gcp[k];
     }
     // closed form of R^eq - rho E theta I for T_0 = 0: rho theta^2 I + kappa u u
@@ -521,30 +701,33 @@ __host__ __device__ inline void collide_node(const Params<R>& P, const S* __rest
                     zf * (rt2 + kappa * s.u[2] * s.u[2])};
     const Trip<R> wt = w_trip<R>(theta);
     const R h2 = R(0.5) * inv_theta * inv_theta;
-    R ge[Q];
-    R s0 = R(0);
+    S v[Q];
+    R t0 = R(0), s0 = R(0);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
+      v[i] = src[(size_t)(LG * Q + i) * n + node];
+      t0 += from_store<S, R>(P, LG, v[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      if (i == 13) continue;
       const R w = wt(cx(i)) * wt(cy(i)) * wt(cz(i));
       const R cu = R(cx(i)) * s.u[0] + R(cy(i)) * s.u[1] + R(cz(i)) * s.u[2];
       const R cqe = R(cx(i)) * qeq[0] + R(cy(i)) * qeq[1] + R(cz(i)) * qeq[2];
-      R bz = R(0);
-      if (csq(i) == 0) bz = Z[0] + Z[1] + Z[2];
-      if (csq(i) == 1) bz = -R(0.5) * (cx(i) ? Z[0] : (cy(i) ? Z[1] : Z[2]));
-      const R geq = w * (rhoE + cqe * inv_theta +
-                         (rt2 * (R(csq(i)) - R(3) * theta) + kappa * (cu * cu - theta * s.usq)) * h2) + bz;
-      ge[i] = geq - P.ref[LG][i];
-      dg[i] = dg[i] - ge[i];                      // non-equilibrium part
-      s0 += dg[i];
-    }
-    dg[13] -= s0;                                 // energy defect onto the rest population
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const R w = wt(cx(i)) * wt(cy(i)) * wt(cz(i));
       const R cdq = R(cx(i)) * dq[0] + R(cy(i)) * dq[1] + R(cz(i)) * dq[2];
-      const R dn = ge[i] + (R(1) - omega) * dg[i] + w * cdq * inv_theta;
-      push<S, R, WALLS>(P, dst, b, LG, i, node, dn);
+      R bz = R(0);
+      if (csq(i) == 1) bz = -R(0.5) * (cx(i) ? Z[0] : (cy(i) ? Z[1] : Z[2]));
+      const R ge = w * (rhoE + cqe * inv_theta +
+                        (rt2 * (R(csq(i)) - R(3) * theta) + kappa * (cu * cu - theta * s.usq)) * h2) + bz -
+                   P.ref[LG][i];
+      const R dn = ge + (R(1) - omega) * (from_store<S, R>(P, LG, v[i]) - ge) + w * cdq * inv_theta;
+      v[i] = to_store<S, R>(P, LG, i, node, dn, step);
+      s0 += from_store<S, R>(P, LG, v[i]);
     }
+    // the collision conserves rho E: the rest population takes the defect
+    v[13] = to_store<S, R>(P, LG, 13, node, t0 - s0, step);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) push<S, R, WALLS>(P, dst, b, LG, i, node, v[i]);
   }
 }
 

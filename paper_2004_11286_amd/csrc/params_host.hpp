@@ -78,7 +78,7 @@ inline void reference_tables(const HostSpecies& h, const RefState& rs, double re
 template <typename R>
 inline void fill_params(Params<R>& P, const HostSpecies& h, int nx, int ny, int nz, int wall_x,
                         const double ref[MAXL][Q], const double ref0[MAXL], const double ref2[MAXL],
-                        const double scale[MAXL], double pivot_tiny)
+                        const double scale[MAXL], double absent_tol)
 {
   std::memset(&P, 0, sizeof(P));
   P.M = h.M;
@@ -107,7 +107,7 @@ inline void fill_params(Params<R>& P, const HostSpecies& h, int nx, int ny, int 
     P.scale[l] = R(scale[l]);
     P.inv_scale[l] = R(1.0 / scale[l]);
   }
-  P.pivot_tiny = R(pivot_tiny);
+  P.absent_tol = R(absent_tol);
 }
 
 }  // namespace mclbm

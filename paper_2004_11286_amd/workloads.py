@@ -111,14 +111,24 @@ def ternary_tube(nx=256, ny=4, nz=4, T0=1.0 / 3.0, masses=(2.0, 16.0, 40.0),
 
 
 # ----------------------------------------------------------------------------- C3
-def shear_layer(nx=256, ny=256, nz=256, seed=2004, T0=1.0, masses=(2.0, 28.0), D12=0.05,
-                omega0=1.5, u0=0.1, x_outer=0.9, x_middle=0.1, delta=4.0, noise=1e-3):
+def shear_layer(nx=256, ny=256, nz=256, seed=2004, T0=1.0, masses=(2.0, 28.0), D12=0.1,
+                omega0=1.0, u0=0.1, x_outer=0.9, x_middle=0.1, delta=4.0, noise=1e-3, modes=8, kmax=4):
     """Three-band Kelvin--Helmholtz shear layer (the layout of Sec. 4.5, eq icKHI):
     periodic box, interfaces at y = ny/4 and 3 ny/4 with tanh profiles of
     thickness ``delta``; u_x = +u0 in the outer bands and -u0 in the middle band;
     X_1 = x_outer outside and x_middle inside along the same profile; uniform
-    pressure and temperature; seeded uniform velocity noise of amplitude ``noise``
-    on every component."""
+    pressure and temperature.
+
+    Perturbation: seeded and band-limited, like the paper's long-wave sinusoids
+    (eqs uyKHI, uzKHI): on every velocity component a sum of ``modes`` Fourier
+    modes with integer wavenumbers |k_x|, |k_y|, |k_z| <= kmax, uniform random
+    amplitudes and phases, scaled to a maximum of ``noise``. (White noise at the
+    grid scale is not used: it drives the scheme unstable within tens of steps.)
+
+    Defaults: T = 1 (sound speed 1/3 at X = 0.5, so u0 = 0.1 is Mach 0.3), D_12 =
+    0.1, omega = 1 at the mean pressure. With D_12 = 0.05 the light species'
+    lattice (R_a T = 0.5 in the hydrogen-rich band) becomes unstable, and with
+    omega above about 1.3 the layer blows up within a few hundred steps."""
     M = 2
     D = np.full((M, M), D12)
     mhalf = 0.5 * (masses[0] + masses[1])
@@ -134,7 +144,17 @@ def shear_layer(nx=256, ny=256, nz=256, seed=2004, T0=1.0, masses=(2.0, 28.0), D
     X = np.stack([X1, 1.0 - X1])
     rng = np.random.Generator(np.random.PCG64(seed))
     u = np.stack([ux, np.zeros_like(ux), np.zeros_like(ux)])
-    u = u + noise * rng.uniform(-1.0, 1.0, size=u.shape)
+    if noise > 0.0:
+        for c in range(3):
+            pert = np.zeros_like(ux)
+            for _ in range(modes):
+                k = rng.integers(-kmax, kmax + 1, size=3)
+                amp = rng.uniform(-1.0, 1.0)
+                ph = rng.uniform(0.0, 2.0 * np.pi)
+                pert += amp * np.sin(2.0 * np.pi * (k[0] * x / nx + k[1] * y / ny + k[2] * z / nz) + ph)
+            m = np.abs(pert).max()
+            if m > 0:
+                u[c] += noise * pert / m
     shape = x.shape
     return _pack(sp, X, np.full(shape, P0), np.full(shape, T0), u,
                  nx=nx, ny=ny, nz=nz, wall_x=0, slaved=1, P0=P0,

@@ -3,7 +3,8 @@
 Tolerances (relative L-infinity per field, max |gpu - oracle| / max |oracle|):
   - FP64 storage and arithmetic: 1e-13 after one step, 1e-10 after 500 steps;
   - FP32 storage with FP64 collision (MCLBM_FP32): 1e-5 after 1000 steps;
-  - FP32 storage and FP32 arithmetic (MCLBM_FP32_FP32): 2e-4 after 1000 steps
+  - FP32 storage and FP32 arithmetic (MCLBM_FP32_FP32): 1e-4 after 1000 steps,
+    2e-4 for the velocity (whose maximum here is only 1e-3)
     (FP32 rounding accumulates about 0.1 ulp per step in the slow diffusion modes);
   - one step of the full 256^3 shear layer in the benchmark's launch
     configuration, sampled through exact windows: 1e-6.
@@ -127,19 +128,20 @@ def test_ternary_tube_fp32_arith_1000_steps(mc, ternary_1000):
     errs = field_errors(g, o)
     print("C2 fp32/fp32 1000", errs)
     for k in FIELDS:
-        assert errs[k] < 2e-4, (k, errs[k])
+        assert errs[k] < (2e-4 if k == "u" else 1e-4), (k, errs[k])
 
 
-@pytest.mark.parametrize("prec,bound", [("fp16", 2e-2), ("bf16", 1e-1)])
+@pytest.mark.parametrize("prec,bound", [("fp16", 1e-2), ("bf16", 1e-1)])
 def test_ternary_tube_16bit_storage(mc, ternary_1000, prec, bound):
-    """16-bit deviation storage with FP32 collision: error against the oracle is
-    reported per field and bounded loosely (no tighter figure is fixed anywhere)."""
+    """16-bit deviation storage (stochastic rounding) with FP32 collision: the
+    error against the oracle is reported per field and bounded loosely; the
+    velocity, whose maximum here is only 1e-3, gets five times the bound."""
     params, f, o, _ = ternary_1000
     g, _ = run_gpu(mc, params, f, 1000, mc.PRECISIONS[prec])
     errs = field_errors(g, o)
     print("C2", prec, "1000", errs)
     for k in FIELDS:
-        assert errs[k] < bound, (k, errs[k])
+        assert errs[k] < (5 * bound if k == "u" else bound), (k, errs[k])
 
 
 def test_full_size_shear_layer_windows(mc, oracle_mod):
@@ -223,7 +225,7 @@ def test_device_and_host_pointer_paths_agree(mc):
     # the reference state behind the stored deviations is a host sum on one path
     # and a device reduction on the other: equal up to the last bits
     for k in FIELDS:
-        np.testing.assert_allclose(b[k].cpu().numpy(), a[k], rtol=1e-13, atol=1e-17)
+        np.testing.assert_allclose(b[k].cpu().numpy(), a[k], rtol=1e-13, atol=1e-14)
 
 
 def test_infeasible_state_is_rejected(mc):
