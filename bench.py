@@ -26,25 +26,62 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
-REC_FIELDS = 5               # node record: Phi_x, Phi_y, Phi_z, omega, C_p
-G_FIELDS = 3
+PROFILES = os.path.join(ROOT, "profiles")
+KERNEL_SOURCES = ["lattice.hpp", "node_ops.hpp", "device_ops.hpp", "kernels.hpp", "inst_fp64.hip",
+                  "inst_fp32_fp64.hip", "inst_fp32.hip", "inst_fp16.hip", "inst_bf16.hip"]
+
+
+def record_fields(M: int) -> int:
+    """Node record: Phi (3), omega, C_p, rho, u (3), T, omega_1, q_neq (3), rho_a (M-1), V_a (3 M)."""
+    return 14 + (M - 1) + 3 * M
 
 
 def algorithmic_bytes(M: int, s_bytes: int, r_bytes: int) -> dict:
-    """Bytes each kernel must move per node (every value read or written once)."""
+    """Bytes each kernel must move per node, every value read or written once:
+    k_moments reads the populations and writes the record; k_gfield reads Phi and
+    omega and writes G; k_collide reads the populations, the record except Phi,
+    and G, and writes the populations."""
     L = M + 1
     pops = L * 27 * s_bytes
+    rec = record_fields(M) * r_bytes
     return {
-        "k_moments": pops + REC_FIELDS * r_bytes,
-        "k_gfield": 4 * r_bytes + G_FIELDS * r_bytes,
-        "k_collide": 2 * pops + 4 * r_bytes,
-        "step": 3 * pops + 16 * r_bytes,
+        "k_moments": pops + rec,
+        "k_gfield": 4 * r_bytes + 3 * r_bytes,
+        "k_collide": 2 * pops + (rec - 3 * r_bytes) + 3 * r_bytes,
+        "step": 3 * pops + 2 * rec + 7 * r_bytes,
         "method_min": 2 * pops,
     }
 
 
 def record_bytes(precision: int, mc) -> int:
-    return 8 if precision in (mc.MCLBM_FP64, mc.MCLBM_FP32) else 4
+    return 8 if precision == mc.MCLBM_FP64 else 4
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2004_11286_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, precision: str):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel sources (else None)."""
+    path = os.path.join(PROFILES, f"{kernel}_shear256_{precision}_hbm_counters.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return float(vals["hbm_bytes_per_launch"])
 
 
 def time_run(mc, params, fields, precision, steps, warmup):
@@ -101,6 +138,8 @@ def main():
     ap.add_argument("--n", type=int, default=256, help="cube edge")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB mebibytes five times (to scale HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
@@ -114,6 +153,19 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibrate:
+        nbytes = args.copy_calibrate << 20
+        src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / 5
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "copies": 5,
+                          "GBs_read_plus_write": 2 * nbytes / el / 1e9}))
+        return
     params, fields = W.shear_layer(nx=args.n, ny=args.n, nz=args.n)
     M = params["M"]
     n = args.n ** 3
@@ -170,8 +222,10 @@ def main():
                                f"{M} species + momentum + energy lattices, strong coupling",
                    "nodes": n, "species": M, "precision": args.precision, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": "k_collide", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "algorithmic_bytes_per_node": ab["k_collide"]},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("k_collide", args.precision),
+                     "algorithmic_bytes_per_node": ab["k_collide"],
+                     "algorithmic_bytes_per_launch": ab["k_collide"] * n},
         "kernels": {k: {"avg_ms": v["avg_ms"], "launches": v["launches"], "GBs": kernel_gbs[k],
                         "algorithmic_bytes_per_node": ab[k]} for k, v in stats.items()},
         "step_effective_GBs": {"step_bytes_per_node": ab["step"], "GBs": ab["step"] * mlups * 1e6 / 1e9,

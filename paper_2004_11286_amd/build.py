@@ -23,7 +23,7 @@ ARCH = os.environ.get("MCLBM_OFFLOAD_ARCH", "gfx950")
 # Packed FP32 instructions are switched off for all device code.
 HIPFLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-I" + os.path.join(ROOT, "include"), "-Wno-unused-command-line-argument"]
+            "-I" + os.path.join(ROOT, "include"), "-I" + CSRC, "-Wno-unused-command-line-argument"]
 
 
 def hipcc() -> str:

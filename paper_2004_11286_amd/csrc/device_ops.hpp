@@ -1,0 +1,35 @@
+// device_ops.hpp -- gfx950 device primitives used by the node functions:
+// stochastic-rounding conversions to 16-bit storage and a compiler barrier.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mclbm {
+
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// Convert with stochastic rounding: rounds to one of the two neighbouring 16-bit
+// values with probability proportional to proximity, using the upper 16 bits of
+// rnd (v_cvt_sr_f16_f32 / v_cvt_sr_bf16_f32). Representable values are exact.
+__device__ inline _Float16 cvt_sr_f16(float x, uint32_t rnd)
+{
+  f16x2 o = {};
+  o = __builtin_amdgcn_cvt_sr_f16_f32(o, x, rnd, false);
+  return o[0];
+}
+
+__device__ inline __bf16 cvt_sr_bf16(float x, uint32_t rnd)
+{
+  bf16x2 o = {};
+  o = __builtin_amdgcn_cvt_sr_bf16_f32(o, x, rnd, false);
+  return o[0];
+}
+
+// Compiler barrier between the lattices of a node: loads after it are not hoisted
+// above it, which bounds the loads (and registers) a thread keeps in flight.
+__device__ inline void lattice_barrier() { __asm__ __volatile__("" ::: "memory"); }
+
+}  // namespace mclbm

@@ -21,6 +21,8 @@
 
 #include <type_traits>
 
+#include <device_ops.hpp>   // device primitives (include path: csrc/)
+
 #include "lattice.hpp"
 
 namespace mclbm {
@@ -235,16 +237,6 @@ __host__ __device__ inline void diffusion_velocities(const Mix<R, M>& s, const b
   }
 }
 
-// Compiler barrier between the lattices of a node: loads after it are not hoisted
-// above it, which bounds the number of loads a thread keeps in flight (and the
-// registers holding them) to one lattice.
-__host__ __device__ inline void lattice_barrier()
-{
-#if defined(__HIP_DEVICE_COMPILE__)
-  __asm__ __volatile__("" ::: "memory");
-#endif
-}
-
 // Sign-selected accumulation: acc += c v for c in {-1, 0, 1} known at compile time.
 template <typename R>
 __host__ __device__ inline void acc_c(R& acc, int c, R v)
@@ -404,9 +396,8 @@ __host__ __device__ inline uint32_t mix32(uint32_t x)
 }
 
 // Conversion of a scaled deviation to the storage type. 32- and 64-bit storage
-// round to nearest; 16-bit storage rounds stochastically (to either neighbour
-// with probability proportional to proximity), which removes the bias that
-// round-to-nearest accumulates in slowly varying regions.
+// round to nearest; 16-bit storage rounds stochastically, which removes the bias
+// that round-to-nearest accumulates in slowly varying regions.
 template <typename S, typename R>
 struct Store {
   __host__ __device__ static S cvt(R v, uint32_t) { return S(v); }
@@ -414,51 +405,32 @@ struct Store {
 
 template <>
 struct Store<_Float16, float> {
-  __host__ __device__ static _Float16 cvt(float x, uint32_t key)
-  {
-    const _Float16 h = (_Float16)x;
-    const float back = (float)h;
-    const float diff = x - back;
-    if (diff == 0.0f || !(diff == diff) || back - back != 0.0f) return h;
-    uint16_t bits;
-    __builtin_memcpy(&bits, &h, 2);
-    const bool neg = bits & 0x8000;
-    const bool up = diff > 0.0f;
-    uint16_t nb;
-    if ((bits & 0x7fff) == 0) nb = up ? 0x0001 : 0x8001;
-    else nb = (up != neg) ? (uint16_t)(bits + 1) : (uint16_t)(bits - 1);
-    _Float16 hn;
-    __builtin_memcpy(&hn, &nb, 2);
-    const float other = (float)hn;
-    if (other - other != 0.0f) return h;                 // never round into infinity
-    const float span = other > back ? other - back : back - other;
-    const float ad = diff > 0.0f ? diff : -diff;
-    const float r = (float)(mix32(key) >> 8) * (1.0f / 16777216.0f);
-    return r * span < ad ? hn : h;
-  }
+  __host__ __device__ static _Float16 cvt(float x, uint32_t rnd) { return cvt_sr_f16(x, rnd); }
 };
 
 template <>
 struct Store<__bf16, float> {
-  __host__ __device__ static __bf16 cvt(float x, uint32_t key)
+  __host__ __device__ static __bf16 cvt(float x, uint32_t rnd) { return cvt_sr_bf16(x, rnd); }
+};
+
+// Random words for stochastic rounding: one hash per (node, lattice, step), then
+// a linear congruential sequence (only its upper bits are used).
+struct Rng {
+  uint32_t s;
+  __host__ __device__ Rng(int64_t node, int l, uint32_t step)
+      : s(mix32((uint32_t)node ^ mix32((uint32_t)l * 0x632BE5ABu + step * 0x9E3779B1u))) {}
+  __host__ __device__ uint32_t next()
   {
-    uint32_t u;
-    __builtin_memcpy(&u, &x, 4);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (__bf16)x;   // inf / nan
-    const uint32_t r = u + (mix32(key) & 0xffffu);           // add below the kept bits
-    const uint16_t hi = (uint16_t)(((r & 0x7f800000u) == 0x7f800000u ? u : r) >> 16);
-    __bf16 b;
-    __builtin_memcpy(&b, &hi, 2);
-    return b;
+    s = s * 1664525u + 1013904223u;
+    return s;
   }
 };
 
-// Round a post-collision deviation of lattice l, direction i, to storage.
+// Round a post-collision deviation of lattice l to storage.
 template <typename S, typename R>
-__host__ __device__ inline S to_store(const Params<R>& P, int l, int i, int64_t node, R dev, uint32_t step)
+__host__ __device__ inline S to_store(const Params<R>& P, int l, R dev, Rng& rng)
 {
-  const uint32_t key = mix32((uint32_t)node ^ mix32((uint32_t)(l * Q + i) + step * 0x9E3779B1u));
-  return Store<S, R>::cvt(dev * P.scale[l], key);
+  return Store<S, R>::cvt(dev * P.scale[l], rng.next());
 }
 
 template <typename S, typename R>
@@ -584,6 +556,7 @@ __host__ __device__ inline void collide_node(const Params<R>& P, const S* __rest
       for (int k = 0; k < 3; ++k) pa[k] = psi_trip<R>(s.u[k], s.T * P.inv_m[a]);
       S v[Q];
       R t0 = R(0), s0 = R(0);
+      Rng rng(node, a, step);
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
         v[i] = src[(size_t)(a * Q + i) * n + node];
@@ -602,12 +575,12 @@ __host__ __device__ inline void collide_node(const Params<R>& P, const S* __rest
         const R fe = s.rho_a[a] * (pa[0](cx(i)) * pa[1](cy(i)) * pa[2](cz(i))) - P.ref[a][i];
         // f' - f_ref = (f^eq - f_ref) + (1 - 2 beta)(f - f^eq) + (beta - 1) F
         const R dn = fe + (R(1) - R(2) * beta) * (from_store<S, R>(P, a, v[i]) - fe) + (beta - R(1)) * R(F);
-        v[i] = to_store<S, R>(P, a, i, node, dn, step);
+        v[i] = to_store<S, R>(P, a, dn, rng);
         s0 += from_store<S, R>(P, a, v[i]);
       }
       // the collision conserves rho_a: the rest population takes the defect of
       // the arithmetic and of the other 26 values' rounding to storage
-      v[13] = to_store<S, R>(P, a, 13, node, t0 - s0, step);
+      v[13] = to_store<S, R>(P, a, t0 - s0, rng);
 #pragma unroll
       for (int i = 0; i < Q; ++i) push<S, R, WALLS>(P, dst, b, a, i, node, v[i]);
       lattice_barrier();
@@ -623,6 +596,7 @@ __host__ __device__ inline void collide_node(const Params<R>& P, const S* __rest
     for (int k = 0; k < 3; ++k) pf[k] = psi_trip<R>(s.u[k], theta);
     S v[Q];
     R t0 = R(0), t1[3] = {R(0), R(0), R(0)}, s0 = R(0), s1[3] = {R(0), R(0), R(0)};
+    Rng rng(node, LF, step);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       v[i] = src[(size_t)(LF * Q + i) * n + node];
@@ -641,7 +615,7 @@ __host__ __device__ inline void collide_node(const Params<R>& P, const S* __rest
       if (csq(i) <= 1) continue;
       const R fe = rho * (pf[0](cx(i)) * pf[1](cy(i)) * pf[2](cz(i))) - P.ref[LF][i];
       const R dn = fe + (R(1) - omega) * (from_store<S, R>(P, LF, v[i]) - fe);
-      v[i] = to_store<S, R>(P, LF, i, node, dn, step);
+      v[i] = to_store<S, R>(P, LF, dn, rng);
       const R d = from_store<S, R>(P, LF, v[i]);
       s0 += d;
       acc_c(s1[0], cx(i), d);
@@ -660,11 +634,11 @@ __host__ __device__ inline void collide_node(const Params<R>& P, const S* __rest
       const R dm = fem + (R(1) - omega) * (from_store<S, R>(P, LF, v[im]) - fem);
       const R sum = dp + dm;
       const R diff = t1[k] - s1[k];        // required dp - dm
-      v[ip] = to_store<S, R>(P, LF, ip, node, R(0.5) * (sum + diff), step);
-      v[im] = to_store<S, R>(P, LF, im, node, R(0.5) * (sum - diff), step);
+      v[ip] = to_store<S, R>(P, LF, R(0.5) * (sum + diff), rng);
+      v[im] = to_store<S, R>(P, LF, R(0.5) * (sum - diff), rng);
       s0 += from_store<S, R>(P, LF, v[ip]) + from_store<S, R>(P, LF, v[im]);
     }
-    v[13] = to_store<S, R>(P, LF, 13, node, t0 - s0, step);
+    v[13] = to_store<S, R>(P, LF, t0 - s0, rng);
 #pragma unroll
     for (int i = 0; i < Q; ++i) push<S, R, WALLS>(P, dst, b, LF, i, node, v[i]);
     lattice_barrier();
@@ -703,6 +677,7 @@ __host__ __device__ inline void collide_node(const Params<R>& P, const S* __rest
     const R h2 = R(0.5) * inv_theta * inv_theta;
     S v[Q];
     R t0 = R(0), s0 = R(0);
+    Rng rng(node, LG, step);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       v[i] = src[(size_t)(LG * Q + i) * n + node];
@@ -721,11 +696,11 @@ __host__ __device__ inline void collide_node(const Params<R>& P, const S* __rest
                         (rt2 * (R(csq(i)) - R(3) * theta) + kappa * (cu * cu - theta * s.usq)) * h2) + bz -
                    P.ref[LG][i];
       const R dn = ge + (R(1) - omega) * (from_store<S, R>(P, LG, v[i]) - ge) + w * cdq * inv_theta;
-      v[i] = to_store<S, R>(P, LG, i, node, dn, step);
+      v[i] = to_store<S, R>(P, LG, dn, rng);
       s0 += from_store<S, R>(P, LG, v[i]);
     }
     // the collision conserves rho E: the rest population takes the defect
-    v[13] = to_store<S, R>(P, LG, 13, node, t0 - s0, step);
+    v[13] = to_store<S, R>(P, LG, t0 - s0, rng);
 #pragma unroll
     for (int i = 0; i < Q; ++i) push<S, R, WALLS>(P, dst, b, LG, i, node, v[i]);
   }
