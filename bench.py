@@ -129,6 +129,55 @@ def cpu_baseline(seconds_target: float = 15.0):
                       f"({elapsed:.1f} s)"}
 
 
+def ensemble_bench(mc, steps: int = 50, seq_steps: int = 10, trial_steps: int = 10):
+    """The batched ensemble: 512 independent ternary tubes, L ~ U{32..256} x 16 x
+    16 with walls (18.9 M nodes), FP32 storage, all tubes in one context.
+    Aggregate MLUPS of the autotuned batched launch, of plain batched launches,
+    of a replayed HIP graph, and of one launch triplet per tube and step (the
+    unbatched reference), all timed with HIP events on the context's stream."""
+    import torch
+
+    from paper_2004_11286_amd import workloads as W
+
+    tubes = W.tube_ensemble()
+    b = mc.Batch([p for p, _ in tubes], mc.MCLBM_FP32)
+    b.init_fields([f for _, f in tubes])
+    n = b.n
+
+    def timed(k, **launch):
+        b.set_launch(**launch)
+        b.step(2 if not launch.get("graph_steps") else launch["graph_steps"])   # warm-up / graph build
+        if b.step_count % 2:
+            b.step(1)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(b.stream)
+        b.step(k)
+        e1.record(b.stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        return {"MLUPS": n * k / (ms * 1e-3) / 1e6, "ms_per_step": ms / k}
+
+    base = dict(variant=0, swizzle=0, order=0, graph_steps=0, sequential=0)
+    out = {"workload": "512 ternary tubes L~U{32..256}x16x16 with walls, FP32 storage, one context",
+           "nodes": n, "tubes": len(tubes)}
+    out["sequential"] = timed(seq_steps, **dict(base, sequential=1))
+    out["batched"] = timed(steps, **base)
+    out["batched_graph"] = timed(steps, **dict(base, graph_steps=10))
+    report = b.autotune(trial_steps)
+    out["autotune_report"] = report.strip().splitlines()
+    chosen = b.launch()
+    out["autotuned"] = timed(steps, **chosen)
+    out["autotuned"]["launch"] = chosen
+    out["speedup_batched_vs_sequential"] = out["autotuned"]["MLUPS"] / out["sequential"]["MLUPS"]
+    c = b.conservation()
+    out["finite"] = bool(np.isfinite(c).all())
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,6 +187,7 @@ def main():
     ap.add_argument("--n", type=int, default=256, help="cube edge")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes five times (to scale HBM counters)")
     args = ap.parse_args()
@@ -203,6 +253,7 @@ def main():
             del v
             torch.cuda.empty_cache()
 
+    ensemble = None if args.no_ensemble else ensemble_bench(mc)
     cpu = None if args.no_cpu else cpu_baseline()
     out = {
         "metric": "D3Q27 mixture MLUPS & % HBM roofline; FP16-store and surrogate vs FP32 plain",
@@ -232,6 +283,7 @@ def main():
                                "method_min_bytes_per_node": ab["method_min"],
                                "method_min_frac": ab["method_min"] * mlups * 1e6 / 1e9 / HBM_PEAK_GBS},
         "variants": variants,
+        "ensemble": ensemble,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

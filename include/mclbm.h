@@ -23,6 +23,14 @@
  *   - Species M (the last) is slaved to the mixture (strong coupling, Sec. 3.6.2):
  *     its density and momentum are the deficits of the mixture's. Order species so
  *     that the last one carries most of the mass everywhere.
+ *   - Batches: a context holds one or more independent lattices ("tubes", the
+ *     Loschmidt-tube setting of Sec. 4.2 repeated with different mixtures). All
+ *     tubes of a context share M, wall_x and precision; sizes and species data
+ *     differ per tube. Every per-node array of the calls below is the
+ *     concatenation over the tubes, in creation order, of that tube's own array
+ *     in the single-tube layout: a field with C components holds, for tube t,
+ *     C * n_t values at offset C * (n_0 + ... + n_{t-1}). A context made with
+ *     mclbm_create is a batch of one tube.
  */
 #ifndef MCLBM_H
 #define MCLBM_H
@@ -76,13 +84,27 @@ typedef struct {
 /* Device workspace bytes a context with these parameters needs (0 on bad input). */
 size_t mclbm_workspace_bytes(const mclbm_params *p);
 
+/* Workspace bytes of a batch of ntubes independent tubes (0 on bad input). */
+size_t mclbm_batch_workspace_bytes(const mclbm_params *tubes, int32_t ntubes);
+
 /* Create a context on the current HIP device. dev_workspace: device memory of at
  * least mclbm_workspace_bytes(p) bytes, 256-byte aligned, borrowed until
  * mclbm_destroy. hip_stream: a hipStream_t (NULL = the null stream). */
 int mclbm_create(const mclbm_params *p, void *dev_workspace, size_t bytes, void *hip_stream,
                  mclbm_ctx **out);
 
+/* Create a context over ntubes independent tubes (tubes[t] describes tube t;
+ * M, wall_x and precision must agree). Workspace and stream as in mclbm_create.
+ * Each step advances every tube; a tube's results are bit for bit those of a
+ * context of that tube alone. */
+int mclbm_batch_create(const mclbm_params *tubes, int32_t ntubes, void *dev_workspace, size_t bytes,
+                       void *hip_stream, mclbm_ctx **out);
+
 void mclbm_destroy(mclbm_ctx *c);
+
+/* Number of tubes, and total number of nodes over all tubes. */
+int32_t mclbm_tube_count(const mclbm_ctx *c);
+int64_t mclbm_node_count(const mclbm_ctx *c);
 
 /* Message of the last error on this context; with c == NULL, of the last failed
  * mclbm_create or mclbm_workspace_bytes on this thread. */
@@ -106,10 +128,15 @@ int mclbm_step(mclbm_ctx *c, int64_t nsteps);
 int mclbm_read_moments(mclbm_ctx *c, double *X, double *rho, double *u, double *p, double *T,
                        int on_device);
 
-/* Domain sums in FP64, out [M+5]: rho_1 .. rho_M (rho_M slaved), rho, rho u_x,
- * rho u_y, rho u_z, rho E. Returns MCLBM_ENAN if any node holds a non-finite
- * value or a negative slaved density. Synchronises the stream. */
+/* Domain sums in FP64 per tube, out [ntubes][M+5]: rho_1 .. rho_M (rho_M slaved),
+ * rho, rho u_x, rho u_y, rho u_z, rho E. Returns MCLBM_ENAN if any node holds a
+ * non-finite value or a negative slaved density. Synchronises the stream. */
 int mclbm_conservation(mclbm_ctx *c, double *out);
+
+/* The fields a trajectory keeps, in FP32: out [M+4][n] per tube (X_1 .. X_M, T,
+ * u_x, u_y, u_z), concatenated over tubes. on_device as in mclbm_init_fields.
+ * Synchronises the stream. */
+int mclbm_read_fields_f32(mclbm_ctx *c, float *out, int on_device);
 
 /* Number of time steps since the last mclbm_init_fields or mclbm_load. */
 int64_t mclbm_step_count(const mclbm_ctx *c);
@@ -128,6 +155,28 @@ int mclbm_load(mclbm_ctx *c, const void *host_buf, size_t bytes);
 int mclbm_set_timing(mclbm_ctx *c, int enable);
 int mclbm_kernel_stats(mclbm_ctx *c, int32_t kernel, double *total_ms, int64_t *launches,
                        const char **name);
+
+/* How mclbm_step launches its kernels. Every choice computes bit for bit the same
+ * step; only the time differs. */
+typedef struct {
+  int32_t variant;      /* occupancy variant of the moments and collide kernels, 0 or 1 */
+  int32_t swizzle;      /* 1: each XCD takes a contiguous run of blocks                  */
+  int32_t order;        /* 0: tubes in the given order; 1: longest tube first            */
+  int32_t graph_steps;  /* 0: launch each kernel of each step; K > 0 (even): replay a
+                           HIP graph of K captured steps (not while timing is enabled)   */
+  int32_t sequential;   /* 1: launch every tube on its own (the unbatched reference)     */
+  int32_t reserved[3];  /* must be 0                                                     */
+} mclbm_launch;
+
+int mclbm_get_launch(const mclbm_ctx *c, mclbm_launch *out);
+int mclbm_set_launch(mclbm_ctx *c, const mclbm_launch *in);
+
+/* Time every batched launch choice (variant x swizzle x order x graph on/off)
+ * over trial_steps steps each on the current state, keep the fastest, and write
+ * a text table of the candidates (milliseconds per step) to report (may be NULL).
+ * The trial steps are ordinary steps: the state and the step count advance by
+ * (number of candidates) * trial_steps. Synchronises the stream. */
+int mclbm_autotune(mclbm_ctx *c, int32_t trial_steps, char *report, size_t report_len);
 
 #ifdef __cplusplus
 }

@@ -17,51 +17,128 @@ constexpr size_t ALIGN = 256;
 inline size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 // ---------------------------------------------------------------------------
+// Tubes and launches
+// ---------------------------------------------------------------------------
+// A context holds one or more independent lattices ("tubes"). Tube t owns the
+// node range [base, base + n_t) of every buffer, laid out exactly as a context
+// of that single tube would be (pop[l][i][n_t], rec[k][n_t], ...), and its own
+// parameter block P[t]. Launches are in blocks of BLOCK nodes; a block never
+// straddles two tubes.
+struct Tube {
+  int64_t base;          // first node of the tube in the concatenated buffers
+  int32_t first_block;   // first block of the tube in a launch over all tubes
+  int32_t nblocks;
+};
+
+struct Launch {
+  const Tube* tubes;
+  const int32_t* blk_tube;   // tube of every block (read when ntubes > 1)
+  int32_t ntubes;
+  int32_t block0;            // added to the block index: a launch over one tube
+  int32_t swizzle;           // give each XCD a contiguous run of blocks
+  int32_t pad;
+};
+
+// Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD
+// b mod 8). Renumbering so that XCD k takes blocks [k q, (k+1) q) keeps the
+// neighbours a block's stencils read in the same XCD's L2.
+__device__ inline uint32_t xcd_block(uint32_t b, uint32_t nb)
+{
+  constexpr uint32_t NXCD = 8;
+  const uint32_t q = nb / NXCD;
+  if (b >= q * NXCD) return b;
+  return (b % NXCD) * q + b / NXCD;
+}
+
+struct Where {
+  int t;
+  int64_t base, node;
+  uint32_t block;        // logical block in a launch over all tubes
+};
+
+__device__ inline Where locate(const Launch& Ln)
+{
+  uint32_t b = blockIdx.x;
+  if (Ln.swizzle) b = xcd_block(b, gridDim.x);
+  b += (uint32_t)Ln.block0;
+  const int t = Ln.ntubes > 1 ? Ln.blk_tube[b] : 0;
+  const Tube tb = Ln.tubes[t];
+  return {t, tb.base, (int64_t)(b - (uint32_t)tb.first_block) * BLOCK + threadIdx.x, b};
+}
+
+// Step number for the stochastic-rounding seeds: a constant in eager launches,
+// a device counter plus the position inside a replayed graph.
+struct StepNo {
+  const uint32_t* ctr;
+  uint32_t add;
+};
+
+__device__ inline uint32_t step_of(const StepNo& s) { return s.add + (s.ctr ? *s.ctr : 0u); }
+
+// ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
 // Occupancy targets (waves per SIMD) that bound the register allocation: the
-// kernels are memory bound and need several waves in flight per SIMD.
-template <typename S, int M>
-constexpr int collide_waves() { return (M == 2 && sizeof(S) < 8) ? 2 : 1; }
-template <int M>
-constexpr int moment_waves() { return M == 2 ? 2 : 1; }
+// kernels are memory bound and need several waves in flight per SIMD. Variant
+// 1 is the other choice (the autotuner measures both).
+template <typename S, int M, int V>
+constexpr int collide_waves() { return ((M == 2 && sizeof(S) < 8) ? 2 : 1) == 2 ? 2 - V : 1 + V; }
+template <int M, int V>
+constexpr int moment_waves() { return (M == 2 ? 2 : 1) == 2 ? 2 - V : 1 + V; }
 
-template <typename S, typename Rec, int M>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(moment_waves<M>()))) void k_moments(const Params<double>* __restrict__ P, const S* __restrict__ pop,
+template <int M>
+constexpr size_t pop_stride() { return (size_t)(M + 1) * Q; }   // populations per node (stored lattices)
+
+template <typename S, typename Rec, int M, int V>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(moment_waves<M, V>()))) void k_moments(const Params<double>* __restrict__ P, Launch Ln, const S* __restrict__ pop,
                                                    Rec* __restrict__ rec)
 {
-  const int64_t node = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (node < P->n) state_node<S, Rec, M>(*P, pop, rec, node);
+  const Where w = locate(Ln);
+  const Params<double>& Pt = P[w.t];
+  if (w.node < Pt.n)
+    state_node<S, Rec, M>(Pt, pop + pop_stride<M>() * w.base, rec + (size_t)RecLayout<M>::FIELDS * w.base, w.node);
 }
 
 template <typename Rec, bool W>
-__global__ __launch_bounds__(BLOCK) void k_gfield(const Params<double>* __restrict__ P,
-                                                  const Rec* __restrict__ rec, Rec* __restrict__ G)
+__global__ __launch_bounds__(BLOCK) void k_gfield(const Params<double>* __restrict__ P, Launch Ln,
+                                                  const Rec* __restrict__ rec, Rec* __restrict__ G, int rec_fields)
 {
-  const int64_t node = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (node < P->n) gfield_node<Rec, W>(*P, rec, G, node);
+  const Where w = locate(Ln);
+  const Params<double>& Pt = P[w.t];
+  if (w.node < Pt.n) gfield_node<Rec, W>(Pt, rec + (size_t)rec_fields * w.base, G + 3 * w.base, w.node);
 }
 
-template <typename S, typename R, typename Rec, int M, bool W>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(collide_waves<S, M>()))) void k_collide(const Params<R>* __restrict__ P, const S* __restrict__ src,
+template <typename S, typename R, typename Rec, int M, bool W, int V>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(collide_waves<S, M, V>()))) void k_collide(const Params<R>* __restrict__ P, Launch Ln, const S* __restrict__ src,
                                                    S* __restrict__ dst, const Rec* __restrict__ rec,
-                                                   const Rec* __restrict__ G, uint32_t step)
+                                                   const Rec* __restrict__ G, StepNo sn)
 {
-  const int64_t node = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (node < P->n) collide_node<S, R, Rec, M, W>(*P, src, dst, rec, G, node, step);
+  const Where w = locate(Ln);
+  const Params<R>& Pt = P[w.t];
+  if (w.node < Pt.n) {
+    const size_t po = pop_stride<M>() * w.base;
+    collide_node<S, R, Rec, M, W>(Pt, src + po, dst + po, rec + (size_t)RecLayout<M>::FIELDS * w.base,
+                                  G + 3 * w.base, w.node, step_of(sn));
+  }
 }
+
+template <typename T>
+__device__ inline T* seg(T* p, int64_t off) { return p ? p + off : p; }
 
 template <typename S, typename R, int M>
-__global__ __launch_bounds__(BLOCK) void k_read(const Params<R>* __restrict__ P, const S* __restrict__ pop,
+__global__ __launch_bounds__(BLOCK) void k_read(const Params<R>* __restrict__ P, Launch Ln, const S* __restrict__ pop,
                                                 double* X, double* rho, double* u, double* p, double* T)
 {
-  const int64_t node = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (node < P->n) read_node<S, R, M>(*P, pop, node, X, rho, u, p, T);
+  const Where w = locate(Ln);
+  const Params<R>& Pt = P[w.t];
+  if (w.node < Pt.n)
+    read_node<S, R, M>(Pt, pop + pop_stride<M>() * w.base, w.node, seg(X, M * w.base), seg(rho, w.base),
+                       seg(u, 3 * w.base), seg(p, w.base), seg(T, w.base));
 }
 
-// Block sum of NV doubles per thread into out[blockIdx.x * NV + k] (fixed order).
+// Block sum of NV doubles per thread into out[slot * NV + k] (fixed order).
 template <int NV>
-__device__ inline void block_sum(const double (&v)[NV], double* out)
+__device__ inline void block_sum(const double (&v)[NV], double* out, uint32_t slot)
 {
   __shared__ double part[RED_BLOCK / 64][NV];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -77,26 +154,31 @@ __device__ inline void block_sum(const double (&v)[NV], double* out)
     double s = 0.0;
 #pragma unroll
     for (int w = 0; w < RED_BLOCK / 64; ++w) s += part[w][threadIdx.x];
-    out[(size_t)blockIdx.x * NV + threadIdx.x] = s;
+    out[(size_t)slot * NV + threadIdx.x] = s;
   }
 }
 
+static_assert(RED_BLOCK == BLOCK, "reductions use the launch blocks of the tubes");
+
 template <typename S, int M>
-__global__ __launch_bounds__(RED_BLOCK) void k_conserved(const Params<double>* __restrict__ P,
+__global__ __launch_bounds__(RED_BLOCK) void k_conserved(const Params<double>* __restrict__ P, Launch Ln,
                                                          const S* __restrict__ pop, double* __restrict__ partial)
 {
   constexpr int NV = M + 6;
   double v[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) v[k] = 0.0;
-  const int64_t node = (int64_t)blockIdx.x * RED_BLOCK + threadIdx.x;
-  if (node < P->n) conserved_node<S, M>(*P, pop, node, v);
-  block_sum<NV>(v, partial);
+  const Where w = locate(Ln);
+  const Params<double>& Pt = P[w.t];
+  if (w.node < Pt.n) conserved_node<S, M>(Pt, pop + pop_stride<M>() * w.base, w.node, v);
+  block_sum<NV>(v, partial, w.block);
 }
 
-// Sums of the initial fields (X_a, p, T) for the reference state.
+// Sums of the initial fields (X_a, p, T) per tube, for the reference states
+// (the parameter blocks are not filled yet: tube sizes come from tube_n).
 template <int M>
-__global__ __launch_bounds__(RED_BLOCK) void k_field_sums(int64_t n, const double* __restrict__ X,
+__global__ __launch_bounds__(RED_BLOCK) void k_field_sums(const int64_t* __restrict__ tube_n, Launch Ln,
+                                                          const double* __restrict__ X,
                                                           const double* __restrict__ p,
                                                           const double* __restrict__ T, double* __restrict__ partial)
 {
@@ -104,48 +186,72 @@ __global__ __launch_bounds__(RED_BLOCK) void k_field_sums(int64_t n, const doubl
   double v[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) v[k] = 0.0;
-  const int64_t node = (int64_t)blockIdx.x * RED_BLOCK + threadIdx.x;
-  if (node < n) {
+  const Where w = locate(Ln);
+  const int64_t n = tube_n[w.t];
+  if (w.node < n) {
 #pragma unroll
-    for (int a = 0; a < M; ++a) v[a] = X[(size_t)a * n + node];
-    v[M] = p[node];
-    v[M + 1] = T[node];
+    for (int a = 0; a < M; ++a) v[a] = X[(size_t)M * w.base + (size_t)a * n + w.node];
+    v[M] = p[w.base + w.node];
+    v[M + 1] = T[w.base + w.node];
   }
-  block_sum<NV>(v, partial);
+  block_sum<NV>(v, partial, w.block);
 }
 
 template <typename S, int M>
-__global__ __launch_bounds__(BLOCK) void k_init(const Params<double>* __restrict__ P, const double* __restrict__ X,
-                                                const double* __restrict__ p, const double* __restrict__ T,
-                                                const double* __restrict__ u, S* __restrict__ pop,
-                                                int* __restrict__ block_bad)
+__global__ __launch_bounds__(BLOCK) void k_init(const Params<double>* __restrict__ P, Launch Ln,
+                                                const double* __restrict__ X, const double* __restrict__ p,
+                                                const double* __restrict__ T, const double* __restrict__ u,
+                                                S* __restrict__ pop, int* __restrict__ block_bad)
 {
-  const int64_t node = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const Where w = locate(Ln);
+  const Params<double>& Pt = P[w.t];
   int bad = 0;
-  if (node < P->n) bad = init_node<S, M>(*P, X, p, T, u, pop, node);
+  if (w.node < Pt.n)
+    bad = init_node<S, M>(Pt, X + (size_t)M * w.base, p + w.base, T + w.base, u + 3 * w.base,
+                          pop + pop_stride<M>() * w.base, w.node);
   bad = __syncthreads_or(bad);
-  if (threadIdx.x == 0) block_bad[blockIdx.x] = bad;
+  if (threadIdx.x == 0) block_bad[w.block] = bad;
 }
 
 // ---------------------------------------------------------------------------
-// Dispatch over (storage, arithmetic, species count, walls)
+// Dispatch over (storage, arithmetic, species count, walls, occupancy variant)
 // ---------------------------------------------------------------------------
+constexpr int NVARIANT = 2;
+
 struct Ops {
   size_t s_bytes;   // bytes per stored population
   size_t r_bytes;   // bytes per record value
   int rec_fields;   // values per node in the record
-  void (*moments)(const void* P, const void* pop, void* rec, unsigned grid, hipStream_t st);
-  void (*gfield)(const void* P, const void* rec, void* G, unsigned grid, hipStream_t st);
-  void (*collide)(const void* P, const void* src, void* dst, const void* rec, const void* G, uint32_t step,
-                  unsigned grid, hipStream_t st);
-  void (*read)(const void* P, const void* pop, double* X, double* rho, double* u, double* p, double* T,
-               unsigned grid, hipStream_t st);
-  void (*conserved)(const void* Pd, const void* pop, double* partial, unsigned grid, hipStream_t st);
-  void (*init)(const void* Pd, const double* X, const double* p, const double* T, const double* u, void* pop,
-               int* bad, unsigned grid, hipStream_t st);
-  void (*field_sums)(int64_t n, const double* X, const double* p, const double* T, double* partial,
-                     unsigned grid, hipStream_t st);
+  void (*moments[NVARIANT])(const void* P, const Launch& ln, const void* pop, void* rec, unsigned grid,
+                            hipStream_t st);
+  void (*gfield)(const void* P, const Launch& ln, const void* rec, void* G, int rec_fields, unsigned grid,
+                 hipStream_t st);
+  void (*collide[NVARIANT])(const void* P, const Launch& ln, const void* src, void* dst, const void* rec,
+                            const void* G, StepNo sn, unsigned grid, hipStream_t st);
+  void (*read)(const void* P, const Launch& ln, const void* pop, double* X, double* rho, double* u, double* p,
+               double* T, unsigned grid, hipStream_t st);
+  void (*conserved)(const void* Pd, const Launch& ln, const void* pop, double* partial, unsigned grid,
+                    hipStream_t st);
+  void (*init)(const void* Pd, const Launch& ln, const double* X, const double* p, const double* T,
+               const double* u, void* pop, int* bad, unsigned grid, hipStream_t st);
+  void (*field_sums)(const int64_t* tube_n, const Launch& ln, const double* X, const double* p, const double* T,
+                     double* partial, unsigned grid, hipStream_t st);
 };
+
+template <typename S, typename Rec, int M, int V>
+void launch_moments(const void* Pd, const Launch& ln, const void* pop, void* rec, unsigned grid, hipStream_t st)
+{
+  hipLaunchKernelGGL((k_moments<S, Rec, M, V>), dim3(grid), dim3(BLOCK), 0, st, (const Params<double>*)Pd, ln,
+                     (const S*)pop, (Rec*)rec);
+}
+
+template <typename S, typename R, typename Rec, int M, bool W, int V>
+void launch_collide(const void* P, const Launch& ln, const void* src, void* dst, const void* rec, const void* G,
+                    StepNo sn, unsigned grid, hipStream_t st)
+{
+  hipLaunchKernelGGL((k_collide<S, R, Rec, M, W, V>), dim3(grid), dim3(BLOCK), 0, st, (const Params<R>*)P, ln,
+                     (const S*)src, (S*)dst, (const Rec*)rec, (const Rec*)G, sn);
+}
 
 template <typename S, typename R, typename Rec, int M, bool W>
 Ops make_ops()
@@ -154,36 +260,33 @@ Ops make_ops()
   o.s_bytes = sizeof(S);
   o.r_bytes = sizeof(Rec);
   o.rec_fields = RecLayout<M>::FIELDS;
-  o.moments = [](const void* Pd, const void* pop, void* rec, unsigned grid, hipStream_t st) {
-    hipLaunchKernelGGL((k_moments<S, Rec, M>), dim3(grid), dim3(BLOCK), 0, st, (const Params<double>*)Pd,
-                       (const S*)pop, (Rec*)rec);
+  o.moments[0] = launch_moments<S, Rec, M, 0>;
+  o.moments[1] = launch_moments<S, Rec, M, 1>;
+  o.collide[0] = launch_collide<S, R, Rec, M, W, 0>;
+  o.collide[1] = launch_collide<S, R, Rec, M, W, 1>;
+  o.gfield = [](const void* Pd, const Launch& ln, const void* rec, void* G, int rec_fields, unsigned grid,
+                hipStream_t st) {
+    hipLaunchKernelGGL((k_gfield<Rec, W>), dim3(grid), dim3(BLOCK), 0, st, (const Params<double>*)Pd, ln,
+                       (const Rec*)rec, (Rec*)G, rec_fields);
   };
-  o.gfield = [](const void* Pd, const void* rec, void* G, unsigned grid, hipStream_t st) {
-    hipLaunchKernelGGL((k_gfield<Rec, W>), dim3(grid), dim3(BLOCK), 0, st, (const Params<double>*)Pd,
-                       (const Rec*)rec, (Rec*)G);
+  o.read = [](const void* P, const Launch& ln, const void* pop, double* X, double* rho, double* u, double* p,
+              double* T, unsigned grid, hipStream_t st) {
+    hipLaunchKernelGGL((k_read<S, R, M>), dim3(grid), dim3(BLOCK), 0, st, (const Params<R>*)P, ln, (const S*)pop,
+                       X, rho, u, p, T);
   };
-  o.collide = [](const void* P, const void* src, void* dst, const void* rec, const void* G, uint32_t step,
-                 unsigned grid, hipStream_t st) {
-    hipLaunchKernelGGL((k_collide<S, R, Rec, M, W>), dim3(grid), dim3(BLOCK), 0, st, (const Params<R>*)P,
-                       (const S*)src, (S*)dst, (const Rec*)rec, (const Rec*)G, step);
-  };
-  o.read = [](const void* P, const void* pop, double* X, double* rho, double* u, double* p, double* T,
-              unsigned grid, hipStream_t st) {
-    hipLaunchKernelGGL((k_read<S, R, M>), dim3(grid), dim3(BLOCK), 0, st, (const Params<R>*)P, (const S*)pop, X,
-                       rho, u, p, T);
-  };
-  o.conserved = [](const void* Pd, const void* pop, double* partial, unsigned grid, hipStream_t st) {
-    hipLaunchKernelGGL((k_conserved<S, M>), dim3(grid), dim3(RED_BLOCK), 0, st, (const Params<double>*)Pd,
+  o.conserved = [](const void* Pd, const Launch& ln, const void* pop, double* partial, unsigned grid,
+                   hipStream_t st) {
+    hipLaunchKernelGGL((k_conserved<S, M>), dim3(grid), dim3(RED_BLOCK), 0, st, (const Params<double>*)Pd, ln,
                        (const S*)pop, partial);
   };
-  o.init = [](const void* Pd, const double* X, const double* p, const double* T, const double* u, void* pop,
-              int* bad, unsigned grid, hipStream_t st) {
-    hipLaunchKernelGGL((k_init<S, M>), dim3(grid), dim3(BLOCK), 0, st, (const Params<double>*)Pd, X, p, T, u,
+  o.init = [](const void* Pd, const Launch& ln, const double* X, const double* p, const double* T,
+              const double* u, void* pop, int* bad, unsigned grid, hipStream_t st) {
+    hipLaunchKernelGGL((k_init<S, M>), dim3(grid), dim3(BLOCK), 0, st, (const Params<double>*)Pd, ln, X, p, T, u,
                        (S*)pop, bad);
   };
-  o.field_sums = [](int64_t n, const double* X, const double* p, const double* T, double* partial, unsigned grid,
-                    hipStream_t st) {
-    hipLaunchKernelGGL((k_field_sums<M>), dim3(grid), dim3(RED_BLOCK), 0, st, n, X, p, T, partial);
+  o.field_sums = [](const int64_t* tube_n, const Launch& ln, const double* X, const double* p, const double* T,
+                    double* partial, unsigned grid, hipStream_t st) {
+    hipLaunchKernelGGL((k_field_sums<M>), dim3(grid), dim3(RED_BLOCK), 0, st, tube_n, ln, X, p, T, partial);
   };
   return o;
 }
@@ -198,7 +301,6 @@ bool pick_m(int M, int walls, Ops& o)
     default: return false;
   }
 }
-
 
 }  // namespace kern
 

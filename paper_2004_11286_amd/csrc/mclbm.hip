@@ -1,16 +1,17 @@
-// mclbm.hip -- HIP kernels for gfx950 and the C ABI of libmclbm (include/mclbm.h).
+// mclbm.hip -- context management and the C ABI of libmclbm (include/mclbm.h).
 //
-// One time step = three launches over all nodes, one thread per node:
-//   k_moments  read 27 (M+1) populations -> record {Phi_x, Phi_y, Phi_z, omega, C_p}
-//   k_gfield   G_a = (1/omega - 1/2) d_a Phi_a from the record of the 18 neighbours
+// One time step = three launches over all nodes of all tubes, one thread per node:
+//   k_moments  read 27 (M+1) populations -> node record (FP64 state, Sec. 2.5.3,
+//              3.2, 3.4: Phi, omega, C_p, rho, u, T, omega_1, q_neq, rho_a, V_a)
+//   k_gfield   G_a = (1/omega - 1/2) d_a Phi_a from the records of the neighbours
 //   k_collide  read the populations again, X_a = -d_a G_a and d C_p from the
 //              neighbours, collide every lattice, push to the neighbours of the
 //              other buffer (bounce-back at x walls)
 // The two reads of the populations are forced by the non-local terms of the
 // momentum and energy collisions, which need the neighbours' moments at the same
 // time level (eqs Xalpha and corrFourier). Populations are laid out as
-// pop[l][i][z][y][x] so that a wavefront's 64 lanes read and write 64 consecutive
-// values of one (lattice, direction) plane.
+// pop[l][i][z][y][x] per tube so that a wavefront's 64 lanes read and write 64
+// consecutive values of one (lattice, direction) plane.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -18,6 +19,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -29,31 +31,60 @@ using namespace mclbm;
 
 namespace {
 
-using kern::Ops;
-
-int push_params(mclbm_ctx* c);
-using kern::BLOCK;
-using kern::RED_BLOCK;
 using kern::ALIGN;
 using kern::align_up;
+using kern::BLOCK;
+using kern::Launch;
+using kern::Ops;
+using kern::RED_BLOCK;
+using kern::StepNo;
 
-// Deterministic second stage: out[k] = sum over blocks of partial[b][k].
-__global__ __launch_bounds__(RED_BLOCK) void k_reduce_partials(const double* __restrict__ partial, int64_t nblocks,
-                                                               int nv, double* __restrict__ out)
+// Deterministic second stage of the reductions: out[t][k] = sum over the blocks
+// of tube t of partial[b][k], in a fixed order. One block per tube.
+__global__ __launch_bounds__(RED_BLOCK) void k_reduce_tubes(const double* __restrict__ partial,
+                                                            const kern::Tube* __restrict__ tubes, int nv,
+                                                            double* __restrict__ out)
 {
   __shared__ double buf[RED_BLOCK];
+  const kern::Tube tb = tubes[blockIdx.x];
   for (int k = 0; k < nv; ++k) {
     double s = 0.0;
-    for (int64_t b = threadIdx.x; b < nblocks; b += RED_BLOCK) s += partial[(size_t)b * nv + k];
+    for (int64_t b = threadIdx.x; b < tb.nblocks; b += RED_BLOCK)
+      s += partial[(size_t)(tb.first_block + b) * nv + k];
     buf[threadIdx.x] = s;
     __syncthreads();
     for (int w = RED_BLOCK / 2; w > 0; w >>= 1) {
       if ((int)threadIdx.x < w) buf[threadIdx.x] += buf[threadIdx.x + w];
       __syncthreads();
     }
-    if (threadIdx.x == 0) out[k] = buf[0];
+    if (threadIdx.x == 0) out[(size_t)blockIdx.x * nv + k] = buf[0];
     __syncthreads();
   }
+}
+
+// Device step counter of graph replays (single thread, vector stores).
+__global__ void k_counter_set(uint32_t* ctr, uint32_t v)
+{
+  if (threadIdx.x == 0 && blockIdx.x == 0) *ctr = v;
+}
+__global__ void k_counter_add(uint32_t* ctr, uint32_t v)
+{
+  if (threadIdx.x == 0 && blockIdx.x == 0) *ctr += v;
+}
+
+// FP32 trajectory fields from the double read-back: out[(M+4) base + k n_t + node].
+__global__ __launch_bounds__(BLOCK) void k_pack_f32(Launch ln, const int64_t* __restrict__ tube_n, int M,
+                                                   const double* __restrict__ X, const double* __restrict__ T,
+                                                   const double* __restrict__ u, float* __restrict__ out)
+{
+  const kern::Where w = kern::locate(ln);
+  const int64_t n = tube_n[w.t];
+  if (w.node >= n) return;
+  const int64_t b = w.base, i = w.node;
+  float* o = out + (size_t)(M + 4) * b;
+  for (int a = 0; a < M; ++a) o[(size_t)a * n + i] = (float)X[(size_t)M * b + (size_t)a * n + i];
+  o[(size_t)M * n + i] = (float)T[b + i];
+  for (int k = 0; k < 3; ++k) o[(size_t)(M + 1 + k) * n + i] = (float)u[3 * b + (size_t)k * n + i];
 }
 
 bool pick_ops(int precision, int M, int walls, Ops& o)
@@ -74,23 +105,36 @@ thread_local std::string g_last_error;
 
 const char* kernel_names[3] = {"k_moments", "k_gfield", "k_collide"};
 
+struct TubeHost {
+  int nx = 0, ny = 0, nz = 0;
+  int64_t n = 0, base = 0;
+  HostSpecies hs{};
+  double ref[MAXL][Q] = {};
+  double ref0[MAXL] = {}, ref2[MAXL] = {}, scale[MAXL] = {};
+};
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // Context
 // ---------------------------------------------------------------------------
 struct mclbm_ctx {
-  int M = 0, nx = 0, ny = 0, nz = 0, wall_x = 0, precision = 0, L = 0;
-  int64_t n = 0;
-  HostSpecies hs{};
+  int M = 0, wall_x = 0, precision = 0, L = 0, ntubes = 0;
+  int64_t n = 0;            // nodes over all tubes
+  int64_t nblocks = 0;      // launch blocks over all tubes
+  std::vector<TubeHost> tubes;
   Ops ops{};
   hipStream_t stream = nullptr;
   int device = 0;
   // workspace regions
   char* ws = nullptr;
   size_t ws_bytes = 0;
-  void* dPd = nullptr;      // Params<double>
-  void* dPr = nullptr;      // Params<R> (R = float) or alias of dPd
+  void* dPd = nullptr;      // Params<double>[ntubes]
+  void* dPr = nullptr;      // Params<float>[ntubes], or alias of dPd
+  kern::Tube* dTubes = nullptr;
+  int32_t* dBlkTube = nullptr;
+  int64_t* dTubeN = nullptr;
+  uint32_t* dStepCtr = nullptr;
   void* pop[2] = {nullptr, nullptr};
   void* rec = nullptr;
   void* G = nullptr;
@@ -101,11 +145,17 @@ struct mclbm_ctx {
   int cur = 0;
   int64_t steps = 0;
   bool initialised = false;
-  // host copies of the parameter blocks (kept alive for asynchronous uploads)
-  Params<double> hPd{};
-  Params<float> hPf{};
-  double ref[MAXL][Q] = {};
-  double ref0[MAXL] = {}, ref2[MAXL] = {}, scale[MAXL] = {};
+  // host copies (kept alive for asynchronous uploads)
+  std::vector<Params<double>> hPd;
+  std::vector<Params<float>> hPf;
+  std::vector<kern::Tube> hTubes;
+  std::vector<int32_t> hBlkTube;
+  std::vector<int64_t> hTubeN;
+  // launch configuration
+  mclbm_launch lc{};
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int gsteps = 0;           // steps in the instantiated graph
   std::string err;
   // timing
   bool timing = false;
@@ -119,37 +169,56 @@ struct mclbm_ctx {
 namespace {
 
 struct Layout {
-  size_t pd, pr, pop, rec, G, staging, partial, reduced, bad, total;
+  size_t pd, pr, tubes, blk, tube_n, ctr, pop, rec, G, staging, partial, reduced, bad, total;
+  int64_t n, nblocks;
 };
 
-Layout layout_for(int M, int64_t n, int precision)
+size_t storage_bytes(int precision)
 {
-  size_t s_bytes = 8, r_bytes = 8;
   switch (precision) {
-    case MCLBM_FP64: s_bytes = 8; r_bytes = 8; break;
-    case MCLBM_FP32: s_bytes = 4; r_bytes = 4; break;
-    case MCLBM_FP32_FP32: s_bytes = 4; r_bytes = 4; break;
-    case MCLBM_FP16: case MCLBM_BF16: s_bytes = 2; r_bytes = 4; break;
+    case MCLBM_FP64: return 8;
+    case MCLBM_FP16: case MCLBM_BF16: return 2;
+    default: return 4;
   }
-  const int L = M + 1;
-  const int64_t nblocks = (n + RED_BLOCK - 1) / RED_BLOCK;
+}
+
+size_t record_bytes(int precision) { return precision == MCLBM_FP64 ? 8 : 4; }
+
+Layout layout_for(const mclbm_params* tp, int ntubes)
+{
+  const int M = tp[0].M, precision = tp[0].precision;
   Layout l{};
-  size_t off = 0;
-  l.pd = off; off += align_up(sizeof(Params<double>));
-  l.pr = off; off += align_up(sizeof(Params<float>));
-  l.pop = off; off += 2 * align_up((size_t)L * Q * n * s_bytes);
+  l.n = 0;
+  l.nblocks = 0;
+  for (int t = 0; t < ntubes; ++t) {
+    const int64_t n = (int64_t)tp[t].nx * tp[t].ny * tp[t].nz;
+    l.n += n;
+    l.nblocks += (n + BLOCK - 1) / BLOCK;
+  }
+  const size_t s_bytes = storage_bytes(precision), r_bytes = record_bytes(precision);
+  const int L = M + 1;
   const int rec_fields = REC_RHOA + (M - 1) + 3 * M;
-  l.rec = off; off += align_up((size_t)rec_fields * n * r_bytes);
-  l.G = off; off += align_up((size_t)3 * n * r_bytes);
-  l.staging = off; off += align_up((size_t)(M + 6) * n * sizeof(double));
-  l.partial = off; off += align_up((size_t)nblocks * (MAXM + 6) * sizeof(double));
-  l.reduced = off; off += align_up((MAXM + 6) * sizeof(double));
-  l.bad = off; off += align_up((size_t)((n + BLOCK - 1) / BLOCK) * sizeof(int));
+  size_t off = 0;
+  l.pd = off; off += align_up(sizeof(Params<double>) * ntubes);
+  l.pr = off; off += align_up(sizeof(Params<float>) * ntubes);
+  l.tubes = off; off += align_up(sizeof(kern::Tube) * ntubes);
+  l.blk = off; off += align_up(sizeof(int32_t) * l.nblocks);
+  l.tube_n = off; off += align_up(sizeof(int64_t) * ntubes);
+  l.ctr = off; off += align_up(sizeof(uint32_t));
+  l.pop = off; off += 2 * align_up((size_t)L * Q * l.n * s_bytes);
+  l.rec = off; off += align_up((size_t)rec_fields * l.n * r_bytes);
+  l.G = off; off += align_up((size_t)3 * l.n * r_bytes);
+  // staging: fields of init_fields / read_moments ((M+6) n doubles), or the
+  // doubles of read_fields_f32 followed by its packed floats ((M+4) n each)
+  l.staging = off; off += align_up((size_t)(2 * M + 8) * l.n * sizeof(double));
+  l.partial = off; off += align_up((size_t)l.nblocks * (MAXM + 6) * sizeof(double));
+  l.reduced = off; off += align_up((size_t)ntubes * (MAXM + 6) * sizeof(double));
+  l.bad = off; off += align_up((size_t)l.nblocks * sizeof(int));
   l.total = off;
   return l;
 }
 
-int validate(const mclbm_params* p, std::string& err)
+int validate_one(const mclbm_params* p, std::string& err)
 {
   if (!p) { err = "params is NULL"; return MCLBM_EARG; }
   if (p->M < 2 || p->M > MAXM) { err = "M must be in 2..8"; return MCLBM_EARG; }
@@ -175,6 +244,30 @@ int validate(const mclbm_params* p, std::string& err)
   return MCLBM_OK;
 }
 
+int validate(const mclbm_params* tp, int ntubes, std::string& err)
+{
+  if (!tp) { err = "params is NULL"; return MCLBM_EARG; }
+  if (ntubes < 1) { err = "ntubes must be positive"; return MCLBM_EARG; }
+  int64_t total = 0, blocks = 0;
+  for (int t = 0; t < ntubes; ++t) {
+    int rc = validate_one(&tp[t], err);
+    if (rc != MCLBM_OK) {
+      if (ntubes > 1) err = "tube " + std::to_string(t) + ": " + err;
+      return rc;
+    }
+    if (tp[t].M != tp[0].M || tp[t].wall_x != tp[0].wall_x || tp[t].precision != tp[0].precision) {
+      err = "all tubes of a batch must share M, wall_x and precision";
+      return MCLBM_EARG;
+    }
+    const int64_t n = (int64_t)tp[t].nx * tp[t].ny * tp[t].nz;
+    total += n;
+    blocks += (n + BLOCK - 1) / BLOCK;
+  }
+  if (blocks >= ((int64_t)1 << 31) / BLOCK) { err = "too many nodes in the batch"; return MCLBM_EARG; }
+  (void)total;
+  return MCLBM_OK;
+}
+
 int fail(mclbm_ctx* c, int code, const std::string& msg)
 {
   if (c) c->err = msg; else g_last_error = msg;
@@ -187,19 +280,60 @@ int fail(mclbm_ctx* c, int code, const std::string& msg)
     if (e_ != hipSuccess) return fail((ctx), MCLBM_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
-
 double absent_tol_for(int precision);
+
+// Launch over every block of every tube.
+Launch launch_all(const mclbm_ctx* c)
+{
+  return Launch{c->dTubes, c->dBlkTube, c->ntubes, 0, c->lc.swizzle, 0};
+}
+
+// Launch over the blocks of tube t only.
+Launch launch_one(const mclbm_ctx* c, int t)
+{
+  return Launch{c->dTubes, c->dBlkTube, c->ntubes, c->hTubes[t].first_block, c->lc.swizzle, 0};
+}
 
 int push_params(mclbm_ctx* c)
 {
   HIP_TRY(c, hipStreamSynchronize(c->stream));   // previous uploads from the host blocks are done
   const double tol = absent_tol_for(c->precision);
-  fill_params<double>(c->hPd, c->hs, c->nx, c->ny, c->nz, c->wall_x, c->ref, c->ref0, c->ref2, c->scale, tol);
-  fill_params<float>(c->hPf, c->hs, c->nx, c->ny, c->nz, c->wall_x, c->ref, c->ref0, c->ref2, c->scale, tol);
-  HIP_TRY(c, hipMemcpyAsync(c->dPd, &c->hPd, sizeof(c->hPd), hipMemcpyHostToDevice, c->stream));
+  for (int t = 0; t < c->ntubes; ++t) {
+    const TubeHost& th = c->tubes[t];
+    fill_params<double>(c->hPd[t], th.hs, th.nx, th.ny, th.nz, c->wall_x, th.ref, th.ref0, th.ref2, th.scale, tol);
+    fill_params<float>(c->hPf[t], th.hs, th.nx, th.ny, th.nz, c->wall_x, th.ref, th.ref0, th.ref2, th.scale, tol);
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->dPd, c->hPd.data(), sizeof(Params<double>) * c->ntubes, hipMemcpyHostToDevice,
+                            c->stream));
   if (!compute_is_fp64(c->precision))
-    HIP_TRY(c, hipMemcpyAsync(c->dPr, &c->hPf, sizeof(c->hPf), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->dPr, c->hPf.data(), sizeof(Params<float>) * c->ntubes, hipMemcpyHostToDevice,
+                              c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return MCLBM_OK;
+}
+
+// Block numbering of the tubes: blocks of the tubes follow each other in the
+// launch order (given, or longest first); the memory layout does not change.
+int push_block_map(mclbm_ctx* c)
+{
+  std::vector<int> order(c->ntubes);
+  std::iota(order.begin(), order.end(), 0);
+  if (c->lc.order == 1)
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return c->tubes[a].n > c->tubes[b].n; });
+  int32_t blk = 0;
+  for (int t : order) {
+    const int32_t nb = (int32_t)((c->tubes[t].n + BLOCK - 1) / BLOCK);
+    c->hTubes[t].base = c->tubes[t].base;
+    c->hTubes[t].first_block = blk;
+    c->hTubes[t].nblocks = nb;
+    for (int32_t b = 0; b < nb; ++b) c->hBlkTube[blk + b] = t;
+    blk += nb;
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->dTubes, c->hTubes.data(), sizeof(kern::Tube) * c->ntubes, hipMemcpyHostToDevice,
+                            c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->dBlkTube, c->hBlkTube.data(), sizeof(int32_t) * c->nblocks, hipMemcpyHostToDevice,
+                            c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return MCLBM_OK;
 }
@@ -254,18 +388,22 @@ double absent_tol_for(int precision)
   }
 }
 
-int upload_params(mclbm_ctx* c, const RefState& rs)
+// Reference tables of every tube from its mean state, rounded to storage.
+int upload_params(mclbm_ctx* c, const std::vector<RefState>& rs)
 {
-  reference_tables(c->hs, rs, c->ref, c->ref0, c->ref2);
-  for (int l = 0; l < MAXL; ++l) c->scale[l] = 1.0;
-  for (int l = 0; l < c->L; ++l) {
-    c->scale[l] = scale_for(c->precision, c->ref[l]);
-    c->ref0[l] = 0.0;
-    c->ref2[l] = 0.0;
-    for (int i = 0; i < Q; ++i) {
-      c->ref[l][i] = round_to_storage(c->precision, c->ref[l][i] * c->scale[l]) / c->scale[l];
-      c->ref0[l] += c->ref[l][i];
-      c->ref2[l] += c->ref[l][i] * cx(i) * cx(i);
+  for (int t = 0; t < c->ntubes; ++t) {
+    TubeHost& th = c->tubes[t];
+    reference_tables(th.hs, rs[t], th.ref, th.ref0, th.ref2);
+    for (int l = 0; l < MAXL; ++l) th.scale[l] = 1.0;
+    for (int l = 0; l < c->L; ++l) {
+      th.scale[l] = scale_for(c->precision, th.ref[l]);
+      th.ref0[l] = 0.0;
+      th.ref2[l] = 0.0;
+      for (int i = 0; i < Q; ++i) {
+        th.ref[l][i] = round_to_storage(c->precision, th.ref[l][i] * th.scale[l]) / th.scale[l];
+        th.ref0[l] += th.ref[l][i];
+        th.ref2[l] += th.ref[l][i] * cx(i) * cx(i);
+      }
     }
   }
   return push_params(c);
@@ -307,47 +445,170 @@ int check_launch(mclbm_ctx* c, const char* what)
   return MCLBM_OK;
 }
 
+void drop_graph(mclbm_ctx* c)
+{
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  c->gexec = nullptr;
+  c->gsteps = 0;
+}
+
+// The launches of one step from buffer `from` on stream st.
+void enqueue_step(mclbm_ctx* c, int from, StepNo sn, hipStream_t st)
+{
+  const int v = c->lc.variant;
+  const int rf = c->ops.rec_fields;
+  if (!c->lc.sequential) {
+    const Launch ln = launch_all(c);
+    const unsigned grid = (unsigned)c->nblocks;
+    c->ops.moments[v](c->dPd, ln, c->pop[from], c->rec, grid, st);
+    c->ops.gfield(c->dPd, ln, c->rec, c->G, rf, grid, st);
+    c->ops.collide[v](c->dPr, ln, c->pop[from], c->pop[1 - from], c->rec, c->G, sn, grid, st);
+    return;
+  }
+  for (int t = 0; t < c->ntubes; ++t) {
+    const Launch ln = launch_one(c, t);
+    const unsigned grid = (unsigned)c->hTubes[t].nblocks;
+    c->ops.moments[v](c->dPd, ln, c->pop[from], c->rec, grid, st);
+    c->ops.gfield(c->dPd, ln, c->rec, c->G, rf, grid, st);
+    c->ops.collide[v](c->dPr, ln, c->pop[from], c->pop[1 - from], c->rec, c->G, sn, grid, st);
+  }
+}
+
+// One eager step, with per-kernel events when timing is enabled (batched only).
+int eager_step(mclbm_ctx* c)
+{
+  const StepNo sn{nullptr, (uint32_t)c->steps};
+  int rc = 0;
+  if (c->timing && !c->lc.sequential) {
+    const int v = c->lc.variant;
+    const Launch ln = launch_all(c);
+    const unsigned grid = (unsigned)c->nblocks;
+    int e0 = 0, e1 = 0, e2 = 0, e3 = 0;
+    if ((rc = record_event(c, e0))) return rc;
+    c->ops.moments[v](c->dPd, ln, c->pop[c->cur], c->rec, grid, c->stream);
+    if ((rc = record_event(c, e1))) return rc;
+    c->ops.gfield(c->dPd, ln, c->rec, c->G, c->ops.rec_fields, grid, c->stream);
+    if ((rc = record_event(c, e2))) return rc;
+    c->ops.collide[v](c->dPr, ln, c->pop[c->cur], c->pop[1 - c->cur], c->rec, c->G, sn, grid, c->stream);
+    if ((rc = record_event(c, e3))) return rc;
+    c->ev_pairs[0].push_back({e0, e1});
+    c->ev_pairs[1].push_back({e1, e2});
+    c->ev_pairs[2].push_back({e2, e3});
+  } else {
+    enqueue_step(c, c->cur, sn, c->stream);
+  }
+  rc = check_launch(c, "mclbm_step");
+  if (rc) return rc;
+  c->cur = 1 - c->cur;
+  c->steps += 1;
+  if (c->timing && c->ev_used > 3000 && (rc = harvest_timing(c))) return rc;
+  return MCLBM_OK;
+}
+
+// Capture K steps starting from buffer 0 into a graph on a private stream
+// (kernel nodes only; the step counter is advanced by a kernel, not a memset).
+int build_graph(mclbm_ctx* c, int K)
+{
+  drop_graph(c);
+  if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+  for (int j = 0; j < K; ++j) enqueue_step(c, j & 1, StepNo{c->dStepCtr, (uint32_t)j}, c->cap_stream);
+  hipLaunchKernelGGL(k_counter_add, dim3(1), dim3(64), 0, c->cap_stream, c->dStepCtr, (uint32_t)K);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+  if (e != hipSuccess) return fail(c, MCLBM_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    c->gexec = nullptr;
+    return fail(c, MCLBM_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  c->gsteps = K;
+  return MCLBM_OK;
+}
+
+int graph_steps(mclbm_ctx* c, int64_t& nsteps)
+{
+  const int K = c->lc.graph_steps;
+  if (nsteps > 0 && c->cur == 1) {             // replays start from buffer 0
+    int rc = eager_step(c);
+    if (rc) return rc;
+    --nsteps;
+  }
+  const int64_t chunks = nsteps / K;
+  if (chunks == 0) return MCLBM_OK;
+  if (c->gsteps != K) {
+    int rc = build_graph(c, K);
+    if (rc) return rc;
+  }
+  hipLaunchKernelGGL(k_counter_set, dim3(1), dim3(64), 0, c->stream, c->dStepCtr, (uint32_t)c->steps);
+  int rc = check_launch(c, "k_counter_set");
+  if (rc) return rc;
+  for (int64_t k = 0; k < chunks; ++k) {
+    HIP_TRY(c, hipGraphLaunch(c->gexec, c->stream));
+    c->steps += K;
+  }
+  nsteps -= chunks * K;
+  return MCLBM_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
-extern "C" size_t mclbm_workspace_bytes(const mclbm_params* p)
+extern "C" size_t mclbm_batch_workspace_bytes(const mclbm_params* tubes, int32_t ntubes)
 {
   std::string err;
-  if (validate(p, err) != MCLBM_OK) {
+  if (validate(tubes, ntubes, err) != MCLBM_OK) {
     g_last_error = err;
     return 0;
   }
-  return layout_for(p->M, (int64_t)p->nx * p->ny * p->nz, p->precision).total;
+  return layout_for(tubes, ntubes).total;
 }
 
-extern "C" int mclbm_create(const mclbm_params* p, void* dev_workspace, size_t bytes, void* hip_stream,
-                            mclbm_ctx** out)
+extern "C" size_t mclbm_workspace_bytes(const mclbm_params* p) { return mclbm_batch_workspace_bytes(p, 1); }
+
+extern "C" int mclbm_batch_create(const mclbm_params* tp, int32_t ntubes, void* dev_workspace, size_t bytes,
+                                  void* hip_stream, mclbm_ctx** out)
 {
   if (!out) return fail(nullptr, MCLBM_EARG, "out is NULL");
   *out = nullptr;
   std::string err;
-  int rc = validate(p, err);
+  int rc = validate(tp, ntubes, err);
   if (rc != MCLBM_OK) return fail(nullptr, rc, err);
-  const int64_t n = (int64_t)p->nx * p->ny * p->nz;
-  Layout lay = layout_for(p->M, n, p->precision);
+  const Layout lay = layout_for(tp, ntubes);
   if (!dev_workspace) return fail(nullptr, MCLBM_EARG, "workspace is NULL");
   if (((uintptr_t)dev_workspace) % ALIGN) return fail(nullptr, MCLBM_EARG, "workspace must be 256-byte aligned");
   if (bytes < lay.total) return fail(nullptr, MCLBM_EARG, "workspace too small");
   mclbm_ctx* c = new (std::nothrow) mclbm_ctx();
   if (!c) return fail(nullptr, MCLBM_EARG, "out of host memory");
-  c->M = p->M; c->nx = p->nx; c->ny = p->ny; c->nz = p->nz; c->wall_x = p->wall_x;
-  c->precision = p->precision; c->L = p->M + 1; c->n = n;
-  c->hs.M = p->M;
-  for (int a = 0; a < p->M; ++a) {
-    c->hs.m[a] = p->molar_mass[a];
-    c->hs.cv[a] = p->cv[a];
-    c->hs.mu[a] = p->mu[a];
-    c->hs.lam[a] = p->lambda[a];
-    for (int b = 0; b < p->M; ++b) c->hs.D[a][b] = p->D[a * p->M + b];
+  c->M = tp[0].M;
+  c->wall_x = tp[0].wall_x;
+  c->precision = tp[0].precision;
+  c->L = c->M + 1;
+  c->ntubes = ntubes;
+  c->n = lay.n;
+  c->nblocks = lay.nblocks;
+  c->tubes.resize(ntubes);
+  int64_t base = 0;
+  for (int t = 0; t < ntubes; ++t) {
+    const mclbm_params* p = &tp[t];
+    TubeHost& th = c->tubes[t];
+    th.nx = p->nx; th.ny = p->ny; th.nz = p->nz;
+    th.n = (int64_t)p->nx * p->ny * p->nz;
+    th.base = base;
+    base += th.n;
+    th.hs.M = p->M;
+    for (int a = 0; a < p->M; ++a) {
+      th.hs.m[a] = p->molar_mass[a];
+      th.hs.cv[a] = p->cv[a];
+      th.hs.mu[a] = p->mu[a];
+      th.hs.lam[a] = p->lambda[a];
+      for (int b = 0; b < p->M; ++b) th.hs.D[a][b] = p->D[a * p->M + b];
+    }
   }
-  if (!pick_ops(p->precision, p->M, p->wall_x, c->ops)) {
+  if (!pick_ops(c->precision, c->M, c->wall_x, c->ops)) {
     delete c;
     return fail(nullptr, MCLBM_EUNSUPPORTED, "no kernels compiled for this configuration");
   }
@@ -357,10 +618,15 @@ extern "C" int mclbm_create(const mclbm_params* p, void* dev_workspace, size_t b
     return fail(nullptr, MCLBM_EDEVICE, "hipGetDevice failed");
   }
   char* ws = (char*)dev_workspace;
-  c->ws = ws; c->ws_bytes = bytes;
+  c->ws = ws;
+  c->ws_bytes = bytes;
   c->dPd = ws + lay.pd;
-  c->dPr = compute_is_fp64(p->precision) ? c->dPd : (void*)(ws + lay.pr);
-  const size_t popb = align_up((size_t)c->L * Q * n * c->ops.s_bytes);
+  c->dPr = compute_is_fp64(c->precision) ? c->dPd : (void*)(ws + lay.pr);
+  c->dTubes = (kern::Tube*)(ws + lay.tubes);
+  c->dBlkTube = (int32_t*)(ws + lay.blk);
+  c->dTubeN = (int64_t*)(ws + lay.tube_n);
+  c->dStepCtr = (uint32_t*)(ws + lay.ctr);
+  const size_t popb = align_up((size_t)c->L * Q * c->n * c->ops.s_bytes);
   c->pop[0] = ws + lay.pop;
   c->pop[1] = ws + lay.pop + popb;
   c->rec = ws + lay.rec;
@@ -369,14 +635,40 @@ extern "C" int mclbm_create(const mclbm_params* p, void* dev_workspace, size_t b
   c->partial = (double*)(ws + lay.partial);
   c->reduced = (double*)(ws + lay.reduced);
   c->bad = (int*)(ws + lay.bad);
+  c->hPd.resize(ntubes);
+  c->hPf.resize(ntubes);
+  c->hTubes.resize(ntubes);
+  c->hBlkTube.resize(c->nblocks);
+  c->hTubeN.resize(ntubes);
+  for (int t = 0; t < ntubes; ++t) c->hTubeN[t] = c->tubes[t].n;
+  rc = push_block_map(c);
+  if (rc == MCLBM_OK) {
+    hipError_t e = hipMemcpyAsync(c->dTubeN, c->hTubeN.data(), sizeof(int64_t) * ntubes, hipMemcpyHostToDevice,
+                                  c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) rc = fail(c, MCLBM_EDEVICE, hipGetErrorString(e));
+  }
+  if (rc != MCLBM_OK) {
+    g_last_error = c->err;
+    delete c;
+    return rc;
+  }
   *out = c;
   return MCLBM_OK;
+}
+
+extern "C" int mclbm_create(const mclbm_params* p, void* dev_workspace, size_t bytes, void* hip_stream,
+                            mclbm_ctx** out)
+{
+  return mclbm_batch_create(p, 1, dev_workspace, bytes, hip_stream, out);
 }
 
 extern "C" void mclbm_destroy(mclbm_ctx* c)
 {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  drop_graph(c);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;
 }
@@ -386,15 +678,20 @@ extern "C" const char* mclbm_last_error(const mclbm_ctx* c)
   return c ? c->err.c_str() : g_last_error.c_str();
 }
 
+extern "C" int32_t mclbm_tube_count(const mclbm_ctx* c) { return c ? c->ntubes : -1; }
+
+extern "C" int64_t mclbm_node_count(const mclbm_ctx* c) { return c ? c->n : -1; }
+
 namespace {
 
-// Reduce NV values from per-block partials to host out[NV].
-int reduce_to_host(mclbm_ctx* c, int64_t nblocks, int nv, double* out)
+// Reduce NV values per tube from the per-block partials to host out[ntubes][nv].
+int reduce_to_host(mclbm_ctx* c, int nv, double* out)
 {
-  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(RED_BLOCK), 0, c->stream, c->partial, nblocks, nv, c->reduced);
-  int rc = check_launch(c, "k_reduce_partials");
+  hipLaunchKernelGGL(k_reduce_tubes, dim3(c->ntubes), dim3(RED_BLOCK), 0, c->stream, c->partial, c->dTubes, nv,
+                     c->reduced);
+  int rc = check_launch(c, "k_reduce_tubes");
   if (rc) return rc;
-  HIP_TRY(c, hipMemcpyAsync(out, c->reduced, sizeof(double) * nv, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(out, c->reduced, sizeof(double) * nv * c->ntubes, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return MCLBM_OK;
 }
@@ -407,62 +704,72 @@ extern "C" int mclbm_init_fields(mclbm_ctx* c, const double* X, const double* p,
   if (!c) return MCLBM_EARG;
   if (!X || !p || !T || !u) return fail(c, MCLBM_EARG, "field pointers must be given");
   const int M = c->M;
-  const int64_t n = c->n;
+  const int64_t N = c->n;
   const double *dX = X, *dp = p, *dT = T, *du = u;
-  RefState rs{};
+  std::vector<RefState> rs(c->ntubes);
   if (!on_device) {
-    // host fields: validate, compute the reference state here, stage to the device
-    double sum[MAXM + 2] = {};
-    for (int64_t i = 0; i < n; ++i) {
-      double xs = 0.0;
-      for (int a = 0; a < M; ++a) {
-        const double v = X[(size_t)a * n + i];
-        if (!(v >= 0.0)) return fail(c, MCLBM_EARG, "mole fractions must be non-negative");
-        xs += v;
-        sum[a] += v;
+    // host fields: validate, compute each tube's reference state here, stage to the device
+    for (int t = 0; t < c->ntubes; ++t) {
+      const TubeHost& th = c->tubes[t];
+      const int64_t n = th.n;
+      const double* Xt = X + (size_t)M * th.base;
+      double sum[MAXM + 2] = {};
+      for (int64_t i = 0; i < n; ++i) {
+        double xs = 0.0;
+        for (int a = 0; a < M; ++a) {
+          const double v = Xt[(size_t)a * n + i];
+          if (!(v >= 0.0)) return fail(c, MCLBM_EARG, "mole fractions must be non-negative");
+          xs += v;
+          sum[a] += v;
+        }
+        if (std::fabs(xs - 1.0) > 1e-9) return fail(c, MCLBM_EARG, "mole fractions must sum to 1");
+        sum[M] += p[th.base + i];
+        sum[M + 1] += T[th.base + i];
       }
-      if (std::fabs(xs - 1.0) > 1e-9) return fail(c, MCLBM_EARG, "mole fractions must sum to 1");
-      sum[M] += p[i];
-      sum[M + 1] += T[i];
+      for (int a = 0; a < M; ++a) rs[t].X[a] = sum[a] / n;
+      rs[t].p = sum[M] / n;
+      rs[t].T = sum[M + 1] / n;
     }
-    for (int a = 0; a < M; ++a) rs.X[a] = sum[a] / n;
-    rs.p = sum[M] / n;
-    rs.T = sum[M + 1] / n;
     double* st = c->staging;
-    HIP_TRY(c, hipMemcpyAsync(st, X, sizeof(double) * M * n, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(st + (size_t)M * n, p, sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(st + (size_t)(M + 1) * n, T, sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(st + (size_t)(M + 2) * n, u, sizeof(double) * 3 * n, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(st, X, sizeof(double) * M * N, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(st + (size_t)M * N, p, sizeof(double) * N, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(st + (size_t)(M + 1) * N, T, sizeof(double) * N, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(st + (size_t)(M + 2) * N, u, sizeof(double) * 3 * N, hipMemcpyHostToDevice, c->stream));
     dX = st;
-    dp = st + (size_t)M * n;
-    dT = st + (size_t)(M + 1) * n;
-    du = st + (size_t)(M + 2) * n;
+    dp = st + (size_t)M * N;
+    dT = st + (size_t)(M + 1) * N;
+    du = st + (size_t)(M + 2) * N;
   } else {
-    const int64_t nb = grid_for(n, RED_BLOCK);
-    c->ops.field_sums(n, dX, dp, dT, c->partial, (unsigned)nb, c->stream);
+    c->ops.field_sums(c->dTubeN, launch_all(c), dX, dp, dT, c->partial, (unsigned)c->nblocks, c->stream);
     int rc = check_launch(c, "k_field_sums");
     if (rc) return rc;
-    double sum[MAXM + 2] = {};
-    rc = reduce_to_host(c, nb, M + 2, sum);
+    std::vector<double> sum((size_t)c->ntubes * (M + 2));
+    rc = reduce_to_host(c, M + 2, sum.data());
     if (rc) return rc;
-    for (int a = 0; a < M; ++a) rs.X[a] = sum[a] / n;
-    rs.p = sum[M] / n;
-    rs.T = sum[M + 1] / n;
-    double xs = 0.0;
-    for (int a = 0; a < M; ++a) xs += rs.X[a];
-    if (!(std::fabs(xs - 1.0) < 1e-6) || !(rs.p > 0) || !(rs.T > 0))
-      return fail(c, MCLBM_EARG, "fields are not a valid state (mean mole fractions, p, T)");
+    for (int t = 0; t < c->ntubes; ++t) {
+      const double n = (double)c->tubes[t].n;
+      const double* s = &sum[(size_t)t * (M + 2)];
+      double xs = 0.0;
+      for (int a = 0; a < M; ++a) {
+        rs[t].X[a] = s[a] / n;
+        xs += rs[t].X[a];
+      }
+      rs[t].p = s[M] / n;
+      rs[t].T = s[M + 1] / n;
+      if (!(std::fabs(xs - 1.0) < 1e-6) || !(rs[t].p > 0) || !(rs[t].T > 0))
+        return fail(c, MCLBM_EARG, "fields are not a valid state (mean mole fractions, p, T)");
+    }
   }
+  // the tube sizes of k_init come from the parameter blocks
   int rc = upload_params(c, rs);
   if (rc) return rc;
-  const unsigned grid = grid_for(n, BLOCK);
-  c->ops.init(c->dPd, dX, dp, dT, du, c->pop[0], c->bad, grid, c->stream);
+  c->ops.init(c->dPd, launch_all(c), dX, dp, dT, du, c->pop[0], c->bad, (unsigned)c->nblocks, c->stream);
   rc = check_launch(c, "k_init");
   if (rc) return rc;
-  std::vector<int> bad(grid);
-  HIP_TRY(c, hipMemcpyAsync(bad.data(), c->bad, sizeof(int) * grid, hipMemcpyDeviceToHost, c->stream));
+  std::vector<int> bad(c->nblocks);
+  HIP_TRY(c, hipMemcpyAsync(bad.data(), c->bad, sizeof(int) * c->nblocks, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  for (unsigned b = 0; b < grid; ++b)
+  for (int64_t b = 0; b < c->nblocks; ++b)
     if (bad[b]) return fail(c, MCLBM_ESTATE, "infeasible initial state: need T > 0, p > 0, R_a T + u^2 < 1");
   c->cur = 0;
   c->steps = 0;
@@ -475,27 +782,13 @@ extern "C" int mclbm_step(mclbm_ctx* c, int64_t nsteps)
   if (!c) return MCLBM_EARG;
   if (!c->initialised) return fail(c, MCLBM_EARG, "mclbm_init_fields or mclbm_load first");
   if (nsteps < 0) return fail(c, MCLBM_EARG, "nsteps must be non-negative");
-  const unsigned grid = grid_for(c->n, BLOCK);
-  for (int64_t t = 0; t < nsteps; ++t) {
-    int e0 = 0, e1 = 0, e2 = 0, e3 = 0, rc = 0;
-    if (c->timing && (rc = record_event(c, e0))) return rc;
-    c->ops.moments(c->dPd, c->pop[c->cur], c->rec, grid, c->stream);
-    if (c->timing && (rc = record_event(c, e1))) return rc;
-    c->ops.gfield(c->dPd, c->rec, c->G, grid, c->stream);
-    if (c->timing && (rc = record_event(c, e2))) return rc;
-    c->ops.collide(c->dPr, c->pop[c->cur], c->pop[1 - c->cur], c->rec, c->G, (uint32_t)c->steps, grid,
-                   c->stream);
-    if (c->timing) {
-      if ((rc = record_event(c, e3))) return rc;
-      c->ev_pairs[0].push_back({e0, e1});
-      c->ev_pairs[1].push_back({e1, e2});
-      c->ev_pairs[2].push_back({e2, e3});
-    }
-    rc = check_launch(c, "mclbm_step");
+  if (c->lc.graph_steps > 0 && !c->timing) {
+    int rc = graph_steps(c, nsteps);
     if (rc) return rc;
-    c->cur = 1 - c->cur;
-    c->steps += 1;
-    if (c->timing && c->ev_used > 3000 && (rc = harvest_timing(c))) return rc;
+  }
+  for (int64_t t = 0; t < nsteps; ++t) {
+    int rc = eager_step(c);
+    if (rc) return rc;
   }
   return MCLBM_OK;
 }
@@ -505,11 +798,11 @@ extern "C" int mclbm_read_moments(mclbm_ctx* c, double* X, double* rho, double* 
 {
   if (!c) return MCLBM_EARG;
   if (!c->initialised) return fail(c, MCLBM_EARG, "no state yet");
-  const int64_t n = c->n;
+  const int64_t N = c->n;
   const int M = c->M;
-  const unsigned grid = grid_for(n, BLOCK);
+  const unsigned grid = (unsigned)c->nblocks;
   if (on_device) {
-    c->ops.read(c->dPr, c->pop[c->cur], X, rho, u, p, T, grid, c->stream);
+    c->ops.read(c->dPr, launch_all(c), c->pop[c->cur], X, rho, u, p, T, grid, c->stream);
     int rc = check_launch(c, "k_read");
     if (rc) return rc;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -517,19 +810,48 @@ extern "C" int mclbm_read_moments(mclbm_ctx* c, double* X, double* rho, double* 
   }
   double* st = c->staging;
   double* sX = st;
-  double* srho = st + (size_t)M * n;
-  double* su = st + (size_t)(M + 1) * n;
-  double* sp = st + (size_t)(M + 4) * n;
-  double* sT = st + (size_t)(M + 5) * n;
-  c->ops.read(c->dPr, c->pop[c->cur], X ? sX : nullptr, rho ? srho : nullptr, u ? su : nullptr, p ? sp : nullptr,
-              T ? sT : nullptr, grid, c->stream);
+  double* srho = st + (size_t)M * N;
+  double* su = st + (size_t)(M + 1) * N;
+  double* sp = st + (size_t)(M + 4) * N;
+  double* sT = st + (size_t)(M + 5) * N;
+  c->ops.read(c->dPr, launch_all(c), c->pop[c->cur], X ? sX : nullptr, rho ? srho : nullptr, u ? su : nullptr,
+              p ? sp : nullptr, T ? sT : nullptr, grid, c->stream);
   int rc = check_launch(c, "k_read");
   if (rc) return rc;
-  if (X) HIP_TRY(c, hipMemcpyAsync(X, sX, sizeof(double) * M * n, hipMemcpyDeviceToHost, c->stream));
-  if (rho) HIP_TRY(c, hipMemcpyAsync(rho, srho, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
-  if (u) HIP_TRY(c, hipMemcpyAsync(u, su, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, c->stream));
-  if (p) HIP_TRY(c, hipMemcpyAsync(p, sp, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
-  if (T) HIP_TRY(c, hipMemcpyAsync(T, sT, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+  if (X) HIP_TRY(c, hipMemcpyAsync(X, sX, sizeof(double) * M * N, hipMemcpyDeviceToHost, c->stream));
+  if (rho) HIP_TRY(c, hipMemcpyAsync(rho, srho, sizeof(double) * N, hipMemcpyDeviceToHost, c->stream));
+  if (u) HIP_TRY(c, hipMemcpyAsync(u, su, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, c->stream));
+  if (p) HIP_TRY(c, hipMemcpyAsync(p, sp, sizeof(double) * N, hipMemcpyDeviceToHost, c->stream));
+  if (T) HIP_TRY(c, hipMemcpyAsync(T, sT, sizeof(double) * N, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return MCLBM_OK;
+}
+
+extern "C" int mclbm_read_fields_f32(mclbm_ctx* c, float* out, int on_device)
+{
+  if (!c) return MCLBM_EARG;
+  if (!out) return fail(c, MCLBM_EARG, "out is NULL");
+  if (!c->initialised) return fail(c, MCLBM_EARG, "no state yet");
+  const int64_t N = c->n;
+  const int M = c->M;
+  double* st = c->staging;
+  double* sX = st;
+  double* su = st + (size_t)M * N;
+  double* sT = st + (size_t)(M + 3) * N;
+  // the packed FP32 fields reuse the staging area behind the doubles
+  float* sF = (float*)(st + (size_t)(M + 4) * N);
+  static_assert(sizeof(float) * 2 == sizeof(double), "staging holds (M+4) floats in 2 doubles");
+  const unsigned grid = (unsigned)c->nblocks;
+  c->ops.read(c->dPr, launch_all(c), c->pop[c->cur], sX, nullptr, su, nullptr, sT, grid, c->stream);
+  int rc = check_launch(c, "k_read");
+  if (rc) return rc;
+  float* dst = on_device ? out : sF;
+  hipLaunchKernelGGL(k_pack_f32, dim3(grid), dim3(BLOCK), 0, c->stream, launch_all(c), c->dTubeN, M, sX, sT, su,
+                     dst);
+  rc = check_launch(c, "k_pack_f32");
+  if (rc) return rc;
+  if (!on_device)
+    HIP_TRY(c, hipMemcpyAsync(out, sF, sizeof(float) * (M + 4) * N, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return MCLBM_OK;
 }
@@ -539,15 +861,18 @@ extern "C" int mclbm_conservation(mclbm_ctx* c, double* out)
   if (!c || !out) return c ? fail(c, MCLBM_EARG, "out is NULL") : MCLBM_EARG;
   if (!c->initialised) return fail(c, MCLBM_EARG, "no state yet");
   const int nv = c->M + 6;
-  const int64_t nb = grid_for(c->n, RED_BLOCK);
-  c->ops.conserved(c->dPd, c->pop[c->cur], c->partial, (unsigned)nb, c->stream);
+  c->ops.conserved(c->dPd, launch_all(c), c->pop[c->cur], c->partial, (unsigned)c->nblocks, c->stream);
   int rc = check_launch(c, "k_conserved");
   if (rc) return rc;
-  double tmp[MAXM + 6];
-  rc = reduce_to_host(c, nb, nv, tmp);
+  std::vector<double> tmp((size_t)c->ntubes * nv);
+  rc = reduce_to_host(c, nv, tmp.data());
   if (rc) return rc;
-  for (int k = 0; k < c->M + 5; ++k) out[k] = tmp[k];
-  if (tmp[c->M + 5] != 0.0) return fail(c, MCLBM_ENAN, "non-finite value or negative slaved density in the state");
+  bool flagged = false;
+  for (int t = 0; t < c->ntubes; ++t) {
+    for (int k = 0; k < c->M + 5; ++k) out[(size_t)t * (c->M + 5) + k] = tmp[(size_t)t * nv + k];
+    flagged = flagged || tmp[(size_t)t * nv + c->M + 5] != 0.0;
+  }
+  if (flagged) return fail(c, MCLBM_ENAN, "non-finite value or negative slaved density in the state");
   return MCLBM_OK;
 }
 
@@ -556,16 +881,22 @@ extern "C" int64_t mclbm_step_count(const mclbm_ctx* c) { return c ? c->steps : 
 namespace {
 struct CkptHeader {
   char magic[8];
-  int32_t M, nx, ny, nz, wall_x, precision;
+  int32_t M, wall_x, precision, ntubes;
   int64_t steps;
+};
+struct CkptTube {
+  int32_t nx, ny, nz, pad;
   double ref[MAXL][Q], ref0[MAXL], ref2[MAXL], scale[MAXL];
 };
+const char kMagic[8] = "MCLBMv2";
+
+size_t header_bytes(const mclbm_ctx* c) { return sizeof(CkptHeader) + sizeof(CkptTube) * c->ntubes; }
 }  // namespace
 
 extern "C" size_t mclbm_state_bytes(const mclbm_ctx* c)
 {
   if (!c) return 0;
-  return sizeof(CkptHeader) + (size_t)c->L * Q * c->n * c->ops.s_bytes;
+  return header_bytes(c) + (size_t)c->L * Q * c->n * c->ops.s_bytes;
 }
 
 extern "C" int mclbm_save(mclbm_ctx* c, void* host_buf, size_t bytes)
@@ -574,15 +905,22 @@ extern "C" int mclbm_save(mclbm_ctx* c, void* host_buf, size_t bytes)
   if (!c->initialised) return fail(c, MCLBM_EARG, "no state yet");
   if (bytes < mclbm_state_bytes(c)) return fail(c, MCLBM_EARG, "buffer too small");
   CkptHeader h{};
-  std::memcpy(h.magic, "MCLBMv1", 8);
-  h.M = c->M; h.nx = c->nx; h.ny = c->ny; h.nz = c->nz; h.wall_x = c->wall_x; h.precision = c->precision;
+  std::memcpy(h.magic, kMagic, 8);
+  h.M = c->M; h.wall_x = c->wall_x; h.precision = c->precision; h.ntubes = c->ntubes;
   h.steps = c->steps;
-  std::memcpy(h.ref, c->ref, sizeof(h.ref));
-  std::memcpy(h.ref0, c->ref0, sizeof(h.ref0));
-  std::memcpy(h.ref2, c->ref2, sizeof(h.ref2));
-  std::memcpy(h.scale, c->scale, sizeof(h.scale));
-  std::memcpy(host_buf, &h, sizeof(h));
-  HIP_TRY(c, hipMemcpyAsync((char*)host_buf + sizeof(h), c->pop[c->cur], (size_t)c->L * Q * c->n * c->ops.s_bytes,
+  char* dst = (char*)host_buf;
+  std::memcpy(dst, &h, sizeof(h));
+  for (int t = 0; t < c->ntubes; ++t) {
+    const TubeHost& th = c->tubes[t];
+    CkptTube ct{};
+    ct.nx = th.nx; ct.ny = th.ny; ct.nz = th.nz;
+    std::memcpy(ct.ref, th.ref, sizeof(ct.ref));
+    std::memcpy(ct.ref0, th.ref0, sizeof(ct.ref0));
+    std::memcpy(ct.ref2, th.ref2, sizeof(ct.ref2));
+    std::memcpy(ct.scale, th.scale, sizeof(ct.scale));
+    std::memcpy(dst + sizeof(h) + sizeof(CkptTube) * t, &ct, sizeof(ct));
+  }
+  HIP_TRY(c, hipMemcpyAsync(dst + header_bytes(c), c->pop[c->cur], (size_t)c->L * Q * c->n * c->ops.s_bytes,
                             hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return MCLBM_OK;
@@ -592,19 +930,29 @@ extern "C" int mclbm_load(mclbm_ctx* c, const void* host_buf, size_t bytes)
 {
   if (!c || !host_buf) return c ? fail(c, MCLBM_EARG, "buffer is NULL") : MCLBM_EARG;
   if (bytes < mclbm_state_bytes(c)) return fail(c, MCLBM_EARG, "buffer too small");
+  const char* src = (const char*)host_buf;
   CkptHeader h;
-  std::memcpy(&h, host_buf, sizeof(h));
-  if (std::memcmp(h.magic, "MCLBMv1", 8) != 0 || h.M != c->M || h.nx != c->nx || h.ny != c->ny || h.nz != c->nz ||
-      h.wall_x != c->wall_x || h.precision != c->precision)
+  std::memcpy(&h, src, sizeof(h));
+  if (std::memcmp(h.magic, kMagic, 8) != 0 || h.M != c->M || h.wall_x != c->wall_x || h.precision != c->precision ||
+      h.ntubes != c->ntubes)
     return fail(c, MCLBM_EARG, "checkpoint does not match this context");
+  std::vector<CkptTube> ct(c->ntubes);
+  for (int t = 0; t < c->ntubes; ++t) {
+    std::memcpy(&ct[t], src + sizeof(h) + sizeof(CkptTube) * t, sizeof(CkptTube));
+    if (ct[t].nx != c->tubes[t].nx || ct[t].ny != c->tubes[t].ny || ct[t].nz != c->tubes[t].nz)
+      return fail(c, MCLBM_EARG, "checkpoint does not match this context");
+  }
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  std::memcpy(c->ref, h.ref, sizeof(h.ref));
-  std::memcpy(c->ref0, h.ref0, sizeof(h.ref0));
-  std::memcpy(c->ref2, h.ref2, sizeof(h.ref2));
-  std::memcpy(c->scale, h.scale, sizeof(h.scale));
+  for (int t = 0; t < c->ntubes; ++t) {
+    TubeHost& th = c->tubes[t];
+    std::memcpy(th.ref, ct[t].ref, sizeof(th.ref));
+    std::memcpy(th.ref0, ct[t].ref0, sizeof(th.ref0));
+    std::memcpy(th.ref2, ct[t].ref2, sizeof(th.ref2));
+    std::memcpy(th.scale, ct[t].scale, sizeof(th.scale));
+  }
   int rc = push_params(c);
   if (rc) return rc;
-  HIP_TRY(c, hipMemcpyAsync(c->pop[0], (const char*)host_buf + sizeof(h), (size_t)c->L * Q * c->n * c->ops.s_bytes,
+  HIP_TRY(c, hipMemcpyAsync(c->pop[0], src + header_bytes(c), (size_t)c->L * Q * c->n * c->ops.s_bytes,
                             hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->cur = 0;
@@ -636,5 +984,94 @@ extern "C" int mclbm_kernel_stats(mclbm_ctx* c, int32_t kernel, double* total_ms
   if (total_ms) *total_ms = c->acc_ms[kernel];
   if (launches) *launches = c->acc_launches[kernel];
   if (name) *name = kernel_names[kernel];
+  return MCLBM_OK;
+}
+
+extern "C" int mclbm_get_launch(const mclbm_ctx* c, mclbm_launch* out)
+{
+  if (!c || !out) return MCLBM_EARG;
+  *out = c->lc;
+  return MCLBM_OK;
+}
+
+extern "C" int mclbm_set_launch(mclbm_ctx* c, const mclbm_launch* in)
+{
+  if (!c) return MCLBM_EARG;
+  if (!in) return fail(c, MCLBM_EARG, "launch is NULL");
+  if (in->variant < 0 || in->variant >= kern::NVARIANT) return fail(c, MCLBM_EARG, "variant must be 0 or 1");
+  if ((in->swizzle | in->sequential) & ~1) return fail(c, MCLBM_EARG, "swizzle and sequential are 0 or 1");
+  if (in->order != 0 && in->order != 1) return fail(c, MCLBM_EARG, "order must be 0 or 1");
+  if (in->graph_steps < 0 || (in->graph_steps & 1) || in->graph_steps > 100000)
+    return fail(c, MCLBM_EARG, "graph_steps must be an even number in 0..100000");
+  for (int k = 0; k < 3; ++k)
+    if (in->reserved[k]) return fail(c, MCLBM_EARG, "reserved fields must be 0");
+  const bool remap = in->order != c->lc.order;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  drop_graph(c);
+  c->lc = *in;
+  if (remap) return push_block_map(c);
+  return MCLBM_OK;
+}
+
+extern "C" int mclbm_autotune(mclbm_ctx* c, int32_t trial_steps, char* report, size_t report_len)
+{
+  if (!c) return MCLBM_EARG;
+  if (!c->initialised) return fail(c, MCLBM_EARG, "mclbm_init_fields or mclbm_load first");
+  if (trial_steps < 2) return fail(c, MCLBM_EARG, "trial_steps must be at least 2");
+  if (c->timing) return fail(c, MCLBM_EARG, "disable timing before autotuning");
+  const int G = trial_steps & ~1;
+  std::vector<mclbm_launch> cands;
+  for (int order = 0; order < (c->ntubes > 1 ? 2 : 1); ++order)
+    for (int v = 0; v < kern::NVARIANT; ++v)
+      for (int sw = 0; sw < 2; ++sw)
+        for (int g = 0; g < 2; ++g) {
+          mclbm_launch l{};
+          l.variant = v;
+          l.swizzle = sw;
+          l.order = order;
+          l.graph_steps = g ? G : 0;
+          cands.push_back(l);
+        }
+  hipEvent_t e0, e1;
+  HIP_TRY(c, hipEventCreate(&e0));
+  HIP_TRY(c, hipEventCreate(&e1));
+  std::string rep = "variant swizzle order graph_steps ms_per_step\n";
+  double best = 1e300;
+  mclbm_launch best_l = c->lc;
+  int rc = MCLBM_OK;
+  for (const mclbm_launch& l : cands) {
+    if ((rc = mclbm_set_launch(c, &l))) break;
+    // first launches of this choice (graph build, caches), then start from buffer 0
+    if ((rc = mclbm_step(c, l.graph_steps ? G : 2))) break;
+    if (c->cur == 1 && (rc = mclbm_step(c, 1))) break;
+    if (hipEventRecord(e0, c->stream) != hipSuccess) { rc = fail(c, MCLBM_EDEVICE, "hipEventRecord"); break; }
+    if ((rc = mclbm_step(c, G))) break;
+    if (hipEventRecord(e1, c->stream) != hipSuccess) { rc = fail(c, MCLBM_EDEVICE, "hipEventRecord"); break; }
+    if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(c, MCLBM_EDEVICE, "hipEventSynchronize"); break; }
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = fail(c, MCLBM_EDEVICE, "hipEventElapsedTime"); break; }
+    const double per = ms / G;
+    char line[128];
+    std::snprintf(line, sizeof line, "%d %d %d %d %.6f\n", l.variant, l.swizzle, l.order, l.graph_steps, per);
+    rep += line;
+    if (per < best) {
+      best = per;
+      best_l = l;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  rc = mclbm_set_launch(c, &best_l);
+  if (rc) return rc;
+  char line[128];
+  std::snprintf(line, sizeof line, "chosen %d %d %d %d %.6f\n", best_l.variant, best_l.swizzle, best_l.order,
+                best_l.graph_steps, best);
+  rep += line;
+  if (report && report_len > 0) {
+    const size_t k = std::min(report_len - 1, rep.size());
+    std::memcpy(report, rep.data(), k);
+    report[k] = '\0';
+  }
   return MCLBM_OK;
 }

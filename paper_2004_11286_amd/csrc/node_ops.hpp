@@ -51,7 +51,7 @@ struct Mix {
 
 // rho_s[0..M-2]: stored species densities; the slaved species takes the deficit.
 template <typename R, int M>
-__host__ __device__ inline void mixture_state(const Params<R>& P, R rho, const R j[3], R rhoE,
+__host__ __device__ __forceinline__ void mixture_state(const Params<R>& P, R rho, const R j[3], R rhoE,
                                               const R rho_s[M], Mix<R, M>& s)
 {
   s.rho = rho;
@@ -90,7 +90,7 @@ __host__ __device__ inline void mixture_state(const Params<R>& P, R rho, const R
 
 // Wilke's mixture viscosity and Mathur's mixture conductivity (Sec. 3.4).
 template <typename R, int M>
-__host__ __device__ inline R mixture_viscosity(const Params<R>& P, const R X[M])
+__host__ __device__ __forceinline__ R mixture_viscosity(const Params<R>& P, const R X[M])
 {
   R mu = R(0);
 #pragma unroll
@@ -104,7 +104,7 @@ __host__ __device__ inline R mixture_viscosity(const Params<R>& P, const R X[M])
 }
 
 template <typename R, int M>
-__host__ __device__ inline R mixture_conductivity(const Params<R>& P, const R X[M])
+__host__ __device__ __forceinline__ R mixture_conductivity(const Params<R>& P, const R X[M])
 {
   R lin = R(0), harm = R(0);
 #pragma unroll
@@ -116,7 +116,7 @@ __host__ __device__ inline R mixture_conductivity(const Params<R>& P, const R X[
 }
 
 template <typename S, typename R>
-__host__ __device__ inline R load_dev(const S* __restrict__ p, size_t idx, R inv_scale)
+__host__ __device__ __forceinline__ R load_dev(const S* __restrict__ p, size_t idx, R inv_scale)
 {
   return R(p[idx]) * inv_scale;
 }
@@ -128,7 +128,7 @@ struct Nbr {
 };
 
 template <typename R>
-__host__ __device__ inline Nbr neighbours(const Params<R>& P, int64_t node)
+__host__ __device__ __forceinline__ Nbr neighbours(const Params<R>& P, int64_t node)
 {
   Nbr b;
   // node counts fit in 32 bits (checked at context creation): 32-bit division
@@ -155,7 +155,7 @@ __host__ __device__ inline Nbr neighbours(const Params<R>& P, int64_t node)
 
 // Stencil neighbour index: at an x wall the ghost node mirrors the boundary node.
 template <bool WALLS>
-__host__ __device__ inline int64_t stencil_index(const Nbr& b, int ci, int cj, int ck)
+__host__ __device__ __forceinline__ int64_t stencil_index(const Nbr& b, int ci, int cj, int ck)
 {
   int64_t xi = b.x[ci + 1];
   if (WALLS) {
@@ -166,7 +166,7 @@ __host__ __device__ inline int64_t stencil_index(const Nbr& b, int ci, int cj, i
 }
 
 template <bool WALLS>
-__host__ __device__ inline bool is_ghost(const Nbr& b, int ci)
+__host__ __device__ __forceinline__ bool is_ghost(const Nbr& b, int ci)
 {
   return WALLS && ((ci < 0 && b.lo) || (ci > 0 && b.hi));
 }
@@ -177,14 +177,14 @@ __host__ __device__ inline bool is_ghost(const Nbr& b, int ci)
 // or below the detection threshold has a zero row and column: V_a = 0.
 // --------------------------------------------------------------------------
 template <typename R, int M>
-__host__ __device__ inline void species_present(const Params<R>& P, const R rho_a[M], R rho, bool present[M])
+__host__ __device__ __forceinline__ void species_present(const Params<R>& P, const R rho_a[M], R rho, bool present[M])
 {
 #pragma unroll
   for (int a = 0; a < M; ++a) present[a] = rho_a[a] > P.absent_tol * rho || rho_a[a] < -P.absent_tol * rho;
 }
 
 template <typename R, int M>
-__host__ __device__ inline void friction_matrix(const Params<R>& P, const Mix<R, M>& s, const bool present[M],
+__host__ __device__ __forceinline__ void friction_matrix(const Params<R>& P, const Mix<R, M>& s, const bool present[M],
                                                 R K[M][M])
 {
 #pragma unroll
@@ -195,7 +195,7 @@ __host__ __device__ inline void friction_matrix(const Params<R>& P, const Mix<R,
 }
 
 template <typename R, int M>
-__host__ __device__ inline void diffusion_velocities(const Mix<R, M>& s, const bool present[M], const R K[M][M],
+__host__ __device__ __forceinline__ void diffusion_velocities(const Mix<R, M>& s, const bool present[M], const R K[M][M],
                                                      const R js[M][3], R V[M][3])
 {
   R A[M][M], rhs[M][3];
@@ -239,7 +239,7 @@ __host__ __device__ inline void diffusion_velocities(const Mix<R, M>& s, const b
 
 // Sign-selected accumulation: acc += c v for c in {-1, 0, 1} known at compile time.
 template <typename R>
-__host__ __device__ inline void acc_c(R& acc, int c, R v)
+__host__ __device__ __forceinline__ void acc_c(R& acc, int c, R v)
 {
   if (c > 0) acc += v;
   if (c < 0) acc -= v;
@@ -249,7 +249,7 @@ __host__ __device__ inline void acc_c(R& acc, int c, R v)
 // Pass 1: node state -> record (FP64 arithmetic, record stored as Rec)
 // --------------------------------------------------------------------------
 template <typename S, typename Rec, int M>
-__host__ __device__ inline void state_node(const Params<double>& P, const S* __restrict__ pop,
+__host__ __device__ __forceinline__ void state_node(const Params<double>& P, const S* __restrict__ pop,
                                            Rec* __restrict__ rec, int64_t node)
 {
   using D = double;
@@ -350,7 +350,7 @@ __host__ __device__ inline void state_node(const Params<double>& P, const S* __r
 // Pass 2: G_a = (1/omega - 1/2) d_a Phi_a, with d_a = 3 sum_i w_i c_ia (.)(x + c_i)
 // --------------------------------------------------------------------------
 template <typename R, bool WALLS>
-__host__ __device__ inline void gfield_node(const Params<double>& P, const R* __restrict__ rec,
+__host__ __device__ __forceinline__ void gfield_node(const Params<double>& P, const R* __restrict__ rec,
                                             R* __restrict__ G, int64_t node)
 {
   const size_t n = (size_t)P.n;
@@ -385,7 +385,7 @@ __host__ __device__ inline void gfield_node(const Params<double>& P, const R* __
 // Pass 3: collide every lattice and push (stream) to the other buffer
 // --------------------------------------------------------------------------
 // Counter-based hash (a 32-bit integer mixer) for stochastic rounding.
-__host__ __device__ inline uint32_t mix32(uint32_t x)
+__host__ __device__ __forceinline__ uint32_t mix32(uint32_t x)
 {
   x ^= x >> 16;
   x *= 0x7feb352dU;
@@ -428,13 +428,13 @@ struct Rng {
 
 // Round a post-collision deviation of lattice l to storage.
 template <typename S, typename R>
-__host__ __device__ inline S to_store(const Params<R>& P, int l, R dev, Rng& rng)
+__host__ __device__ __forceinline__ S to_store(const Params<R>& P, int l, R dev, Rng& rng)
 {
   return Store<S, R>::cvt(dev * P.scale[l], rng.next());
 }
 
 template <typename S, typename R>
-__host__ __device__ inline R from_store(const Params<R>& P, int l, S v)
+__host__ __device__ __forceinline__ R from_store(const Params<R>& P, int l, S v)
 {
   return R(v) * P.inv_scale[l];
 }
@@ -442,7 +442,7 @@ __host__ __device__ inline R from_store(const Params<R>& P, int l, S v)
 // Streaming: write the post-collision value of direction i to the neighbour
 // x + c_i of the other buffer, or bounce it back at an x wall.
 template <typename S, typename R, bool WALLS>
-__host__ __device__ inline void push(const Params<R>& P, S* __restrict__ dst, const Nbr& b, int l, int i,
+__host__ __device__ __forceinline__ void push(const Params<R>& P, S* __restrict__ dst, const Nbr& b, int l, int i,
                                      int64_t node, S v)
 {
   const size_t n = (size_t)P.n;
@@ -455,7 +455,7 @@ __host__ __device__ inline void push(const Params<R>& P, S* __restrict__ dst, co
 }
 
 template <typename S, typename R, typename Rec, int M, bool WALLS>
-__host__ __device__ inline void collide_node(const Params<R>& P, const S* __restrict__ src,
+__host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const S* __restrict__ src,
                                              S* __restrict__ dst, const Rec* __restrict__ rec,
                                              const Rec* __restrict__ G, int64_t node, uint32_t step)
 {
@@ -710,7 +710,7 @@ __host__ __device__ inline void collide_node(const Params<R>& P, const S* __rest
 // Read-back of the macroscopic fields
 // --------------------------------------------------------------------------
 template <typename S, typename R, int M>
-__host__ __device__ inline void read_node(const Params<R>& P, const S* __restrict__ pop, int64_t node,
+__host__ __device__ __forceinline__ void read_node(const Params<R>& P, const S* __restrict__ pop, int64_t node,
                                           double* X, double* rho_o, double* u, double* p, double* T)
 {
   const size_t n = (size_t)P.n;
@@ -753,7 +753,7 @@ __host__ __device__ inline void read_node(const Params<R>& P, const S* __restric
 // Initialisation at the local equilibrium of (X_a, p, T, u), computed in FP64
 // --------------------------------------------------------------------------
 template <typename S, int M>
-__host__ __device__ inline int init_node(const Params<double>& P, const double* X,
+__host__ __device__ __forceinline__ int init_node(const Params<double>& P, const double* X,
                                          const double* p, const double* T, const double* u, S* __restrict__ pop,
                                          int64_t node)
 {
@@ -833,7 +833,7 @@ __host__ __device__ inline int init_node(const Params<double>& P, const double* 
 // plus a flag for non-finite values or a negative slaved density.
 // --------------------------------------------------------------------------
 template <typename S, int M>
-__host__ __device__ inline void conserved_node(const Params<double>& P, const S* __restrict__ pop,
+__host__ __device__ __forceinline__ void conserved_node(const Params<double>& P, const S* __restrict__ pop,
                                                int64_t node, double* out /*[M+6]*/)
 {
   const size_t n = (size_t)P.n;

@@ -37,10 +37,12 @@ MCLBM_K_MOMENTS = 0
 MCLBM_K_GFIELD = 1
 MCLBM_K_COLLIDE = 2
 
-EXPORTS = ["mclbm_workspace_bytes", "mclbm_create", "mclbm_destroy", "mclbm_last_error",
-           "mclbm_init_fields", "mclbm_step", "mclbm_read_moments", "mclbm_conservation",
-           "mclbm_step_count", "mclbm_state_bytes", "mclbm_save", "mclbm_load",
-           "mclbm_set_timing", "mclbm_kernel_stats"]
+EXPORTS = ["mclbm_workspace_bytes", "mclbm_batch_workspace_bytes", "mclbm_create", "mclbm_batch_create",
+           "mclbm_destroy", "mclbm_last_error", "mclbm_tube_count", "mclbm_node_count",
+           "mclbm_init_fields", "mclbm_step", "mclbm_read_moments", "mclbm_read_fields_f32",
+           "mclbm_conservation", "mclbm_step_count", "mclbm_state_bytes", "mclbm_save", "mclbm_load",
+           "mclbm_set_timing", "mclbm_kernel_stats", "mclbm_get_launch", "mclbm_set_launch",
+           "mclbm_autotune"]
 
 
 class mclbm_params(C.Structure):
@@ -52,6 +54,14 @@ class mclbm_params(C.Structure):
         ("D", C.POINTER(C.c_double)), ("mu", C.POINTER(C.c_double)),
         ("lam", C.POINTER(C.c_double)),
     ]
+
+
+class mclbm_launch(C.Structure):
+    _fields_ = [("variant", C.c_int32), ("swizzle", C.c_int32), ("order", C.c_int32),
+                ("graph_steps", C.c_int32), ("sequential", C.c_int32), ("reserved", C.c_int32 * 3)]
+
+
+LAUNCH_KEYS = ("variant", "swizzle", "order", "graph_steps", "sequential")
 
 
 class MclbmError(RuntimeError):
@@ -71,6 +81,17 @@ def _load():
     L.mclbm_workspace_bytes.argtypes = [P]
     L.mclbm_workspace_bytes.restype = C.c_size_t
     L.mclbm_create.argtypes = [P, vp, C.c_size_t, vp, C.POINTER(vp)]
+    L.mclbm_batch_workspace_bytes.argtypes = [P, C.c_int32]
+    L.mclbm_batch_workspace_bytes.restype = C.c_size_t
+    L.mclbm_batch_create.argtypes = [P, C.c_int32, vp, C.c_size_t, vp, C.POINTER(vp)]
+    L.mclbm_tube_count.argtypes = [vp]
+    L.mclbm_tube_count.restype = C.c_int32
+    L.mclbm_node_count.argtypes = [vp]
+    L.mclbm_node_count.restype = C.c_int64
+    L.mclbm_read_fields_f32.argtypes = [vp, vp, C.c_int]
+    L.mclbm_get_launch.argtypes = [vp, C.POINTER(mclbm_launch)]
+    L.mclbm_set_launch.argtypes = [vp, C.POINTER(mclbm_launch)]
+    L.mclbm_autotune.argtypes = [vp, C.c_int32, C.c_char_p, C.c_size_t]
     L.mclbm_destroy.argtypes = [vp]
     L.mclbm_destroy.restype = None
     L.mclbm_last_error.argtypes = [vp]
@@ -109,6 +130,16 @@ def make_params(params: dict, precision: int):
     return p, arrs
 
 
+def make_param_array(tubes: list, precision: int):
+    """Array of mclbm_params for a batch; returns (array, arrays kept alive)."""
+    arr = (mclbm_params * len(tubes))()
+    keep = []
+    for t, params in enumerate(tubes):
+        arr[t], k = make_params(params, precision)
+        keep.append(k)
+    return arr, keep
+
+
 def _check(ctx, rc: int):
     if rc != MCLBM_OK:
         msg = lib.mclbm_last_error(ctx)
@@ -130,6 +161,53 @@ def mclbm_create(params: dict, precision: int, workspace_ptr: int, nbytes: int, 
     _check(None, lib.mclbm_create(C.byref(p), C.c_void_p(workspace_ptr), nbytes, C.c_void_p(stream),
                                   C.byref(h)))
     return h
+
+
+def mclbm_batch_workspace_bytes(tubes: list, precision: int) -> int:
+    arr, _keep = make_param_array(tubes, precision)
+    n = lib.mclbm_batch_workspace_bytes(arr, len(tubes))
+    if n == 0:
+        raise MclbmError(MCLBM_EARG, lib.mclbm_last_error(None).decode())
+    return int(n)
+
+
+def mclbm_batch_create(tubes: list, precision: int, workspace_ptr: int, nbytes: int, stream: int) -> C.c_void_p:
+    arr, _keep = make_param_array(tubes, precision)
+    h = C.c_void_p()
+    _check(None, lib.mclbm_batch_create(arr, len(tubes), C.c_void_p(workspace_ptr), nbytes, C.c_void_p(stream),
+                                        C.byref(h)))
+    return h
+
+
+def mclbm_tube_count(ctx) -> int:
+    return int(lib.mclbm_tube_count(ctx))
+
+
+def mclbm_node_count(ctx) -> int:
+    return int(lib.mclbm_node_count(ctx))
+
+
+def mclbm_read_fields_f32(ctx, out_ptr: int, on_device: int) -> None:
+    _check(ctx, lib.mclbm_read_fields_f32(ctx, C.c_void_p(out_ptr), int(on_device)))
+
+
+def mclbm_get_launch(ctx) -> dict:
+    lc = mclbm_launch()
+    _check(ctx, lib.mclbm_get_launch(ctx, C.byref(lc)))
+    return {k: int(getattr(lc, k)) for k in LAUNCH_KEYS}
+
+
+def mclbm_set_launch(ctx, **kw) -> None:
+    cur = mclbm_get_launch(ctx)
+    cur.update({k: int(v) for k, v in kw.items()})
+    lc = mclbm_launch(*[cur[k] for k in LAUNCH_KEYS])
+    _check(ctx, lib.mclbm_set_launch(ctx, C.byref(lc)))
+
+
+def mclbm_autotune(ctx, trial_steps: int) -> str:
+    buf = C.create_string_buffer(4096)
+    _check(ctx, lib.mclbm_autotune(ctx, int(trial_steps), buf, len(buf)))
+    return buf.value.decode()
 
 
 def mclbm_destroy(ctx) -> None:
@@ -156,7 +234,8 @@ def mclbm_read_moments(ctx, X_ptr, rho_ptr, u_ptr, p_ptr, T_ptr, on_device: int)
 
 
 def mclbm_conservation(ctx, M: int) -> np.ndarray:
-    out = np.zeros(M + 5)
+    """Per-tube FP64 sums, shape [ntubes][M+5]."""
+    out = np.zeros((mclbm_tube_count(ctx), M + 5))
     _check(ctx, lib.mclbm_conservation(ctx, out.ctypes.data_as(C.POINTER(C.c_double))))
     return out
 
@@ -261,11 +340,127 @@ class Sim:
         return out
 
     def conservation(self) -> np.ndarray:
+        return mclbm_conservation(self.ctx, self.M)[0]
+
+    @property
+    def step_count(self) -> int:
+        return mclbm_step_count(self.ctx)
+
+    def launch(self) -> dict:
+        return mclbm_get_launch(self.ctx)
+
+    def set_launch(self, **kw) -> None:
+        mclbm_set_launch(self.ctx, **kw)
+
+    def autotune(self, trial_steps: int = 10) -> str:
+        return mclbm_autotune(self.ctx, trial_steps)
+
+    def save(self) -> bytearray:
+        return mclbm_save(self.ctx)
+
+    def load(self, buf) -> None:
+        mclbm_load(self.ctx, buf)
+
+    def set_timing(self, enable: bool) -> None:
+        mclbm_set_timing(self.ctx, enable)
+
+    def kernel_stats(self, kernel: int):
+        return mclbm_kernel_stats(self.ctx, kernel)
+
+
+class Batch:
+    """A context over independent tubes (one workload dict each) plus its
+    torch-owned workspace. Per-node arrays are the concatenation over tubes of
+    each tube's own array (see include/mclbm.h); the helpers below split and
+    join them."""
+
+    def __init__(self, tubes: list, precision: int | str = MCLBM_FP32, device: str = "cuda:0", stream=None):
+        import torch
+
+        if isinstance(precision, str):
+            precision = PRECISIONS[precision]
+        self.tubes = [dict(t) for t in tubes]
+        self.precision = int(precision)
+        self.M = int(tubes[0]["M"])
+        self.shapes = [(int(t["nz"]), int(t["ny"]), int(t["nx"])) for t in tubes]
+        self.sizes = [int(np.prod(s)) for s in self.shapes]
+        self.offsets = np.concatenate([[0], np.cumsum(self.sizes)]).astype(np.int64)
+        self.n = int(self.offsets[-1])
+        self.device = torch.device(device)
+        nbytes = mclbm_batch_workspace_bytes(self.tubes, self.precision)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        with torch.cuda.device(self.device):
+            self.ctx = mclbm_batch_create(self.tubes, self.precision, self.workspace.data_ptr(), nbytes,
+                                          self.stream.cuda_stream)
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            mclbm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- layout helpers
+    def join(self, per_tube: list, comps: int) -> np.ndarray:
+        """Concatenate per-tube arrays of shape [comps, nz, ny, nx] (or [nz, ny, nx])."""
+        return np.concatenate([_f64(a).reshape(comps * n) for a, n in zip(per_tube, self.sizes)])
+
+    def split(self, flat: np.ndarray, comps: int) -> list:
+        out = []
+        for t, sh in enumerate(self.shapes):
+            a = flat[comps * self.offsets[t]:comps * self.offsets[t + 1]]
+            out.append(a.reshape(((comps,) if comps > 1 else ()) + sh))
+        return out
+
+    def init_fields(self, fields: list):
+        """fields: one dict (X, p, T, u) per tube, numpy arrays."""
+        X = self.join([f["X"] for f in fields], self.M)
+        p = self.join([f["p"] for f in fields], 1)
+        T = self.join([f["T"] for f in fields], 1)
+        u = self.join([f["u"] for f in fields], 3)
+        mclbm_init_fields(self.ctx, X.ctypes.data, p.ctypes.data, T.ctypes.data, u.ctypes.data, 0)
+
+    def step(self, nsteps: int = 1):
+        mclbm_step(self.ctx, nsteps)
+
+    def read_moments(self) -> list:
+        """One dict of numpy fields per tube."""
+        flat = {"X": np.zeros(self.M * self.n), "rho": np.zeros(self.n), "u": np.zeros(3 * self.n),
+                "p": np.zeros(self.n), "T": np.zeros(self.n)}
+        mclbm_read_moments(self.ctx, *[flat[k].ctypes.data for k in ("X", "rho", "u", "p", "T")], 0)
+        comps = {"X": self.M, "rho": 1, "u": 3, "p": 1, "T": 1}
+        parts = {k: self.split(v, comps[k]) for k, v in flat.items()}
+        return [{k: parts[k][t] for k in flat} for t in range(len(self.shapes))]
+
+    def read_fields_f32(self, out=None):
+        """FP32 trajectory fields (X_1..X_M, T, u) into a CUDA tensor of M+4 values per node."""
+        import torch
+
+        if out is None:
+            out = torch.empty((self.M + 4) * self.n, dtype=torch.float32, device=self.device)
+        mclbm_read_fields_f32(self.ctx, out.data_ptr(), 1)
+        return out
+
+    def conservation(self) -> np.ndarray:
         return mclbm_conservation(self.ctx, self.M)
 
     @property
     def step_count(self) -> int:
         return mclbm_step_count(self.ctx)
+
+    def launch(self) -> dict:
+        return mclbm_get_launch(self.ctx)
+
+    def set_launch(self, **kw) -> None:
+        mclbm_set_launch(self.ctx, **kw)
+
+    def autotune(self, trial_steps: int = 10) -> str:
+        return mclbm_autotune(self.ctx, trial_steps)
 
     def save(self) -> bytearray:
         return mclbm_save(self.ctx)

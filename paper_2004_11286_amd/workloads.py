@@ -162,29 +162,41 @@ def shear_layer(nx=256, ny=256, nz=256, seed=2004, T0=1.0, masses=(2.0, 28.0), D
 
 
 # ----------------------------------------------------------------------------- C4
+SLAVED_MIN_Y = 0.3           # minimum mass fraction of the slaved species in the ensemble
 ENSEMBLE_MASSES = (2.0, 16.0, 28.0, 40.0)
 
 
 def tube_ensemble(ntubes=512, ny=16, nz=16, lmin=32, lmax=256, seed=11286, T0=1.0 / 3.0,
-                  omega0=1.0):
+                  omega0=1.0, min_slaved_y=SLAVED_MIN_Y):
     """Independent ternary tubes with walls at both x ends (the Loschmidt-tube
     structure of Sec. 4.2), one species set and composition per tube: three
     distinct molar masses from {2, 16, 28, 40}, D_ab ~ U[0.01, 0.1], left and
     right mole fractions ~ Dirichlet(1, 1, 1), uniform pressure giving mean
     density 1, T = 1/3, zero velocity. The slaved species is the one with the
-    largest minimum mass fraction. Returns a list of (params, fields)."""
+    largest minimum mass fraction. Strong coupling (Sec. 3.6.2) needs the slaved
+    species to carry a good part of the mass everywhere: compositions whose
+    slaved species falls below ``min_slaved_y`` in mass fraction on either side
+    are drawn again. Of unconditioned Dirichlet(1, 1, 1) draws about 10% have the
+    slaved species under 0.2 and 23% under 0.3 somewhere; in the oracle itself,
+    tubes whose slaved species was near 0.1 to 0.2 on one side went negative at
+    the interface within a hundred steps.
+    Returns a list of (params, fields)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     tubes = []
     for _ in range(ntubes):
         L = int(rng.integers(lmin, lmax + 1))
         masses = np.sort(rng.choice(ENSEMBLE_MASSES, size=3, replace=False))
         d = rng.uniform(0.01, 0.1, size=3)
-        xl = rng.dirichlet([1.0, 1.0, 1.0])
-        xr = rng.dirichlet([1.0, 1.0, 1.0])
+        while True:
+            xl = rng.dirichlet([1.0, 1.0, 1.0])
+            xr = rng.dirichlet([1.0, 1.0, 1.0])
+            yl = xl * masses / np.dot(xl, masses)
+            yr = xr * masses / np.dot(xr, masses)
+            ymin = np.minimum(yl, yr)
+            if ymin.max() >= min_slaved_y:
+                break
         # order species so the slaved one (largest minimum mass fraction) is last
-        yl = xl * masses / np.dot(xl, masses)
-        yr = xr * masses / np.dot(xr, masses)
-        order = np.argsort(np.minimum(yl, yr), kind="stable")
+        order = np.argsort(ymin, kind="stable")
         masses, xl, xr = masses[order], xl[order], xr[order]
         Doff = {}
         pairs = [(0, 1), (0, 2), (1, 2)]

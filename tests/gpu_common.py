@@ -5,12 +5,14 @@ import numpy as np
 
 FIELDS = ("X", "rho", "u", "p", "T")
 
-# Checkpoint header written by mclbm_save (see mclbm.hip): magic[8], 6 int32,
-# int64 step count, ref[9][27], ref0[9], ref2[9], scale[9] (doubles).
-_HDR = np.dtype([("magic", "S8"), ("M", "<i4"), ("nx", "<i4"), ("ny", "<i4"), ("nz", "<i4"),
-                 ("wall_x", "<i4"), ("precision", "<i4"), ("steps", "<i8"),
-                 ("ref", "<f8", (9, 27)), ("ref0", "<f8", (9,)), ("ref2", "<f8", (9,)),
-                 ("scale", "<f8", (9,))])
+# Checkpoint written by mclbm_save (see mclbm.hip): a header (magic[8], M,
+# wall_x, precision, ntubes as int32, int64 step count), then per tube its size
+# and reference tables, then the stored populations of all tubes.
+_HDR = np.dtype([("magic", "S8"), ("M", "<i4"), ("wall_x", "<i4"), ("precision", "<i4"),
+                 ("ntubes", "<i4"), ("steps", "<i8")])
+_TUBE = np.dtype([("nx", "<i4"), ("ny", "<i4"), ("nz", "<i4"), ("pad", "<i4"),
+                  ("ref", "<f8", (9, 27)), ("ref0", "<f8", (9,)), ("ref2", "<f8", (9,)),
+                  ("scale", "<f8", (9,))])
 _STORE = {0: np.float64, 1: np.float32, 2: np.float32, 3: np.float16}
 
 
@@ -24,17 +26,24 @@ def field_errors(gpu: dict, ref: dict) -> dict:
     return {k: rel_linf(np.asarray(gpu[k]), np.asarray(ref[k])) for k in FIELDS}
 
 
-def decode_checkpoint(buf) -> tuple[dict, np.ndarray]:
-    """Header dict and the stored values as an array [L][27][nz][ny][nx] (no copy)."""
+def decode_checkpoint(buf, tube: int = 0) -> tuple[dict, np.ndarray]:
+    """Header dict of one tube and its stored values as an array [L][27][nz][ny][nx]."""
     h = np.frombuffer(buf, dtype=_HDR, count=1)[0]
-    M, nx, ny, nz, prec = int(h["M"]), int(h["nx"]), int(h["ny"]), int(h["nz"]), int(h["precision"])
+    M, prec, ntubes = int(h["M"]), int(h["precision"]), int(h["ntubes"])
+    tubes = np.frombuffer(buf, dtype=_TUBE, count=ntubes, offset=_HDR.itemsize)
+    sizes = [int(t["nx"]) * int(t["ny"]) * int(t["nz"]) for t in tubes]
+    start = (M + 1) * 27 * sum(sizes[:tube])
+    count = (M + 1) * 27 * sizes[tube]
+    off = _HDR.itemsize + _TUBE.itemsize * ntubes
     if prec == 4:
-        raw = np.frombuffer(buf, dtype=np.uint16, offset=_HDR.itemsize, count=(M + 1) * 27 * nx * ny * nz)
+        raw = np.frombuffer(buf, dtype=np.uint16, offset=off, count=start + count)[start:]
         vals = (raw.astype(np.uint32) << 16).view(np.float32)
     else:
-        vals = np.frombuffer(buf, dtype=_STORE[prec], offset=_HDR.itemsize, count=(M + 1) * 27 * nx * ny * nz)
+        vals = np.frombuffer(buf, dtype=_STORE[prec], offset=off, count=start + count)[start:]
+    t = tubes[tube]
     hdr = {k: h[k] for k in _HDR.names}
-    return hdr, vals.reshape(M + 1, 27, nz, ny, nx)
+    hdr.update({k: t[k] for k in _TUBE.names})
+    return hdr, vals.reshape(M + 1, 27, int(t["nz"]), int(t["ny"]), int(t["nx"]))
 
 
 def oracle_window(hdr: dict, vals: np.ndarray, center, radius: int) -> np.ndarray:

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_functions():
     src = open(os.path.join(ROOT, "include", "mclbm.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(mclbm_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(mclbm_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -64,3 +64,42 @@ def test_create_rejects_bad_workspace():
         m.mclbm_create(p, 1, 0, 1 << 30, 0)                   # NULL workspace
     with pytest.raises(m.MclbmError):
         m.mclbm_create(p, 1, 0x1000, 16, 0)                   # too small (never dereferenced)
+
+
+def test_batch_workspace_and_validation():
+    m = pytest.importorskip("paper_2004_11286_amd.mclbm")
+    tubes = [t for t, _ in W.tube_ensemble(ntubes=5, ny=4, nz=4, lmin=8, lmax=40)]
+    total = m.mclbm_batch_workspace_bytes(tubes, 1)
+    singles = [m.mclbm_workspace_bytes(t, 1) for t in tubes]
+    n = sum(t["nx"] * t["ny"] * t["nz"] for t in tubes)
+    assert total > 2 * 27 * 4 * n * 4                        # two FP32 buffers of 4 lattices
+    assert total < sum(singles)                              # one set of staging buffers
+    # a batch of one tube is a single context
+    assert m.mclbm_batch_workspace_bytes(tubes[:1], 1) == singles[0]
+    mixed = [tubes[0], dict(W.binary_interdiffusion(nx=8, ny=4, nz=4)[0])]
+    with pytest.raises(m.MclbmError) as e:
+        m.mclbm_batch_workspace_bytes(mixed, 1)               # M differs
+    assert "share" in str(e.value)
+    periodic = dict(tubes[1])
+    periodic["wall_x"] = 0
+    with pytest.raises(m.MclbmError):
+        m.mclbm_batch_workspace_bytes([tubes[0], periodic], 1)
+    bad = dict(tubes[2])
+    bad["D"] = np.array(bad["D"]) * np.array([[1, 1, 1], [1, 1, 2], [1, 1, 1]])
+    with pytest.raises(m.MclbmError) as e:
+        m.mclbm_batch_workspace_bytes([tubes[0], tubes[1], bad], 1)
+    assert "tube 2" in str(e.value)
+    with pytest.raises(m.MclbmError):
+        m.mclbm_batch_workspace_bytes([], 1)
+
+
+def test_launch_struct_matches_header():
+    m = pytest.importorskip("paper_2004_11286_amd.mclbm")
+    import ctypes
+
+    src = open(os.path.join(ROOT, "include", "mclbm.h")).read()
+    body = re.search(r"typedef struct \{([^{}]*)\} mclbm_launch;", src).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = re.findall(r"int32_t\s+(\w+)(?:\[(\d+)\])?;", body)
+    assert [f for f, _ in fields] == [f for f, *_ in m.mclbm_launch._fields_]
+    assert ctypes.sizeof(m.mclbm_launch) == 4 * sum(int(k or 1) for _, k in fields)
