@@ -1,0 +1,184 @@
+"""FP64 reference of the learned surrogate (test infrastructure only).
+
+Plain numpy, written from the definitions, not from the GPU kernels:
+
+- a 3x3x3 convolution, output o = b[o] + sum over taps (dz, dy, dx) and input
+  channels i of W[tap][o][i] * in[i](z + dz, y + dy, x + dx), tap = 9 (dz+1) +
+  3 (dy+1) + (dx+1), with zero padding outside the x ends of a tube and periodic
+  wrapping in y and z;
+- the network: layer 0 maps C field channels to the hidden width, ReLU between
+  layers, the last layer maps back to C; its input is the normalised fields
+  (f - shift) * scale, its output the change of the normalised fields;
+- the mean squared error and its gradient by the chain rule (the gradient of a
+  convolution with respect to its input is the convolution with the transposed
+  weights on the reversed offsets; with respect to the weights, the correlation
+  of the output gradient with the shifted input);
+- Adam as published by Kingma and Ba (bias-corrected first and second moments);
+- the mole residual: at uniform pressure the moles of species s in a tube are
+  proportional to sum_x X_s / T.
+
+Optionally the forward and backward passes round to BF16 (round to nearest
+even) at the points where the GPU kernels store BF16 (the packed input, the
+weights, the hidden activations, the activation gradients), so that a
+comparison isolates the FP32-versus-FP64 accumulation.
+
+Pins (tests/test_surrogate_oracle.py): brute-force loops, the adjoint identity,
+central finite differences of the loss, the closed-form first Adam step,
+equivariance under periodic shifts.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+NTAP = 27
+
+
+def tap_offset(tap: int):
+    return tap // 9 - 1, (tap // 3) % 3 - 1, tap % 3 - 1
+
+
+def bf16(a: np.ndarray) -> np.ndarray:
+    """Round to BF16 (nearest even) through FP32, returned as float64."""
+    f = np.asarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def shift(x: np.ndarray, dz: int, dy: int, dx: int) -> np.ndarray:
+    """s[..., z, y, x] = x[..., z + dz, y + dy, x + dx]: periodic in z and y,
+    zero outside the x range."""
+    s = np.roll(x, shift=(-dz, -dy), axis=(-3, -2))
+    if dx == 0:
+        return s.copy()
+    out = np.zeros_like(s)
+    if dx == 1:
+        out[..., :-1] = s[..., 1:]
+    else:
+        out[..., 1:] = s[..., :-1]
+    return out
+
+
+def conv(x: np.ndarray, W: np.ndarray, b: np.ndarray | None) -> np.ndarray:
+    """x [Cin][nz][ny][nx], W [27][Cout][Cin], b [Cout] -> [Cout][nz][ny][nx]."""
+    y = np.zeros((W.shape[1],) + x.shape[1:])
+    for tap in range(NTAP):
+        y += np.tensordot(W[tap], shift(x, *tap_offset(tap)), axes=(1, 0))
+    if b is not None:
+        y += b[:, None, None, None]
+    return y
+
+
+def conv_input_grad(dy: np.ndarray, W: np.ndarray) -> np.ndarray:
+    """Adjoint of conv with respect to x: sum_tap W[tap]^T dy(. - d_tap)."""
+    dx = np.zeros((W.shape[2],) + dy.shape[1:])
+    for tap in range(NTAP):
+        dz_, dy_, dx_ = tap_offset(tap)
+        dx += np.tensordot(W[tap].T, shift(dy, -dz_, -dy_, -dx_), axes=(1, 0))
+    return dx
+
+
+def conv_weight_grad(dy: np.ndarray, x: np.ndarray):
+    """dW[tap][o][i] = sum_nodes dy[o] x[i](. + d_tap); db[o] = sum_nodes dy[o]."""
+    Cout, Cin = dy.shape[0], x.shape[0]
+    dW = np.zeros((NTAP, Cout, Cin))
+    dyf = dy.reshape(Cout, -1)
+    for tap in range(NTAP):
+        dW[tap] = dyf @ shift(x, *tap_offset(tap)).reshape(Cin, -1).T
+    return dW, dyf.sum(axis=1)
+
+
+# ------------------------------------------------------------------ network
+def layer_shapes(C: int, depth: int, width: int = 64):
+    ins = [C] + [width] * (depth - 1)
+    outs = [width] * (depth - 1) + [C]
+    return list(zip(outs, ins))
+
+
+def param_count(C: int, depth: int, width: int = 64) -> int:
+    return sum(NTAP * o * i + o for o, i in layer_shapes(C, depth, width))
+
+
+def unflatten(params: np.ndarray, C: int, depth: int, width: int = 64):
+    """Flat parameters (layer by layer: W[tap][out][in], then b[out]) -> list of (W, b)."""
+    out, k = [], 0
+    for o, i in layer_shapes(C, depth, width):
+        W = params[k:k + NTAP * o * i].reshape(NTAP, o, i)
+        k += NTAP * o * i
+        b = params[k:k + o]
+        k += o
+        out.append((np.asarray(W, dtype=np.float64), np.asarray(b, dtype=np.float64)))
+    assert k == params.size
+    return out
+
+
+def flatten(layers) -> np.ndarray:
+    return np.concatenate([np.concatenate([W.ravel(), b.ravel()]) for W, b in layers])
+
+
+def he_init(C: int, depth: int, seed: int, width: int = 64, gain: float = 1.0) -> np.ndarray:
+    """Seeded He-normal weights, zero biases (the starting point of training)."""
+    rng = np.random.default_rng(seed)
+    layers = []
+    for k, (o, i) in enumerate(layer_shapes(C, depth, width)):
+        std = np.sqrt(2.0 / (NTAP * i)) * (gain if k < depth - 1 else 0.1 * gain)
+        layers.append((rng.normal(0.0, std, (NTAP, o, i)), np.zeros(o)))
+    return flatten(layers).astype(np.float32)
+
+
+def forward(params, f, norm, C, depth, width=64, round_bf16=False):
+    """One tube: f [C][nz][ny][nx] fields -> (y raw output, pred fields, cache)."""
+    layers = unflatten(np.asarray(params, dtype=np.float64), C, depth, width)
+    rnd = bf16 if round_bf16 else (lambda a: a)
+    a = rnd((f - norm["in_shift"][:, None, None, None]) * norm["in_scale"][:, None, None, None])
+    acts = [a]
+    for k, (W, b) in enumerate(layers):
+        z = conv(acts[-1], rnd(W), b)
+        if k < depth - 1:
+            acts.append(rnd(np.maximum(z, 0.0)))
+        else:
+            y = z
+    pred = f + y * norm["out_scale"][:, None, None, None]
+    return y, pred, acts
+
+
+def loss_and_grad(params, tubes_f, tubes_target, norm, C, depth, width=64, weight=None, round_bf16=False):
+    """Mean over all nodes of all tubes of sum_c w_c (y_c - r_c)^2 with
+    r = (target - f) / out_scale, and its gradient with respect to the flat
+    parameters (same order)."""
+    layers = unflatten(np.asarray(params, dtype=np.float64), C, depth, width)
+    w = np.ones(C) if weight is None else np.asarray(weight, dtype=np.float64)
+    rnd = bf16 if round_bf16 else (lambda a: a)
+    N = sum(f[0].size for f in tubes_f)
+    total = 0.0
+    grads = [(np.zeros_like(W), np.zeros_like(b)) for W, b in layers]
+    for f, tgt in zip(tubes_f, tubes_target):
+        y, _, acts = forward(params, f, norm, C, depth, width, round_bf16)
+        r = (tgt - f) / norm["out_scale"][:, None, None, None]
+        e = y - r
+        total += float(np.sum(w[:, None, None, None] * e * e))
+        d = rnd(2.0 * w[:, None, None, None] * e / N)
+        for k in range(depth - 1, -1, -1):
+            W, _ = layers[k]
+            dW, db = conv_weight_grad(d, acts[k])
+            grads[k][0][...] += dW
+            grads[k][1][...] += db
+            if k > 0:
+                d = rnd(conv_input_grad(d, rnd(W)) * (acts[k] > 0))
+    return total / N, flatten(grads)
+
+
+def adam(params, grad, m, v, step, lr, b1, b2, eps):
+    """One Adam step (Kingma and Ba): returns new (params, m, v); step counts from 1."""
+    m = b1 * m + (1.0 - b1) * grad
+    v = b2 * v + (1.0 - b2) * grad * grad
+    mhat = m / (1.0 - b1 ** step)
+    vhat = v / (1.0 - b2 ** step)
+    return params - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
+def mole_residual(a: np.ndarray, b: np.ndarray, M: int) -> float:
+    """max_s |sum X_s/T (b) - sum X_s/T (a)| / sum X_s/T (a) for one tube's fields [C][...]."""
+    sa = np.array([np.sum(a[s] / a[M]) for s in range(M)])
+    sb = np.array([np.sum(b[s] / b[M]) for s in range(M)])
+    return float(np.max(np.abs(sb - sa) / np.abs(sa)))

@@ -1,0 +1,142 @@
+"""Pins of the surrogate's FP64 reference against what the definitions fix:
+brute-force index loops, the adjoint identity of the convolution, central
+finite differences of the loss, the closed-form first Adam step, and
+equivariance under periodic shifts in y and z."""
+import numpy as np
+import pytest
+
+from oracle import surrogate_oracle as S
+
+
+def brute_conv(x, W, b):
+    Cin, nz, ny, nx = x.shape
+    Cout = W.shape[1]
+    y = np.zeros((Cout, nz, ny, nx))
+    for o in range(Cout):
+        for z in range(nz):
+            for yy in range(ny):
+                for xx in range(nx):
+                    s = b[o]
+                    for tap in range(27):
+                        dz, dy, dx = tap // 9 - 1, (tap // 3) % 3 - 1, tap % 3 - 1
+                        xi = xx + dx
+                        if xi < 0 or xi >= nx:
+                            continue              # zero padding at the walls
+                        zi, yi = (z + dz) % nz, (yy + dy) % ny
+                        for i in range(Cin):
+                            s += W[tap, o, i] * x[i, zi, yi, xi]
+                    y[o, z, yy, xx] = s
+    return y
+
+
+def test_conv_matches_brute_force_loops():
+    rng = np.random.default_rng(0)
+    x = rng.normal(size=(3, 3, 4, 5))
+    W = rng.normal(size=(27, 2, 3))
+    b = rng.normal(size=2)
+    np.testing.assert_allclose(S.conv(x, W, b), brute_conv(x, W, b), rtol=1e-12, atol=1e-12)
+
+
+def test_conv_single_tap_is_a_shift():
+    """One unit weight on tap (dz, dy, dx) = (0, 0, +1): y(x) = in(x + 1), zero at the last x."""
+    x = np.arange(2 * 2 * 3 * 4, dtype=float).reshape(2, 2, 3, 4)
+    W = np.zeros((27, 2, 2))
+    W[9 * 1 + 3 * 1 + 2, 0, 0] = 1.0            # tap (0, 0, +1)
+    assert S.tap_offset(14) == (0, 0, 1)
+    y = S.conv(x, W, None)
+    np.testing.assert_array_equal(y[0, :, :, :-1], x[0, :, :, 1:])
+    np.testing.assert_array_equal(y[0, :, :, -1], 0.0)
+    np.testing.assert_array_equal(y[1], 0.0)
+
+
+def test_conv_input_grad_is_the_adjoint():
+    rng = np.random.default_rng(1)
+    x = rng.normal(size=(4, 3, 5, 6))
+    W = rng.normal(size=(27, 3, 4))
+    dy = rng.normal(size=(3, 3, 5, 6))
+    lhs = np.sum(S.conv(x, W, None) * dy)
+    rhs = np.sum(x * S.conv_input_grad(dy, W))
+    assert lhs == pytest.approx(rhs, rel=1e-12)
+
+
+def test_conv_is_equivariant_to_periodic_shifts():
+    rng = np.random.default_rng(2)
+    x = rng.normal(size=(2, 4, 5, 6))
+    W = rng.normal(size=(27, 3, 2))
+    b = rng.normal(size=3)
+    y = S.conv(x, W, b)
+    xs = np.roll(x, (1, 2), axis=(1, 2))
+    np.testing.assert_allclose(S.conv(xs, W, b), np.roll(y, (1, 2), axis=(1, 2)), rtol=1e-12, atol=1e-12)
+
+
+def _tiny_problem(seed=3, C=3, depth=3, width=4):
+    rng = np.random.default_rng(seed)
+    shapes = [(C, 3, 2, 5), (C, 2, 3, 4)]
+    fs = [rng.uniform(0.2, 1.0, size=s) for s in shapes]
+    tg = [f + 0.05 * rng.normal(size=f.shape) for f in fs]
+    norm = {"in_shift": np.full(C, 0.5), "in_scale": np.full(C, 2.0), "out_scale": np.full(C, 0.1)}
+    p = S.he_init(C, depth, seed, width=width, gain=3.0).astype(np.float64)
+    p += 0.1 * rng.normal(size=p.size)         # biases non-zero, ReLUs mixed
+    return fs, tg, norm, p
+
+
+def test_loss_gradient_matches_central_differences():
+    C, depth, width = 3, 3, 4
+    fs, tg, norm, p = _tiny_problem(C=C, depth=depth, width=width)
+    w = np.array([1.0, 0.5, 2.0])
+    L, g = S.loss_and_grad(p, fs, tg, norm, C, depth, width, weight=w)
+    rng = np.random.default_rng(4)
+    idx = rng.choice(p.size, 40, replace=False)
+    h = 1e-6
+    for k in idx:
+        pp, pm = p.copy(), p.copy()
+        pp[k] += h
+        pm[k] -= h
+        Lp, _ = S.loss_and_grad(pp, fs, tg, norm, C, depth, width, weight=w)
+        Lm, _ = S.loss_and_grad(pm, fs, tg, norm, C, depth, width, weight=w)
+        fd = (Lp - Lm) / (2 * h)
+        assert g[k] == pytest.approx(fd, rel=1e-5, abs=1e-9), k
+
+
+def test_loss_is_zero_for_a_perfect_prediction():
+    """All weights zero and the target equal to the fields: y = 0 = r."""
+    C, depth, width = 3, 3, 4
+    fs, _, norm, p = _tiny_problem(C=C, depth=depth, width=width)
+    L, g = S.loss_and_grad(np.zeros_like(p), fs, fs, norm, C, depth, width)
+    assert L == 0.0 and np.all(g == 0.0)
+
+
+def test_adam_first_step_closed_form():
+    """With zero moments the bias-corrected first step is -lr g / (|g| + eps)."""
+    rng = np.random.default_rng(5)
+    p0 = rng.normal(size=50)
+    g = rng.normal(size=50)
+    p1, m, v = S.adam(p0, g, np.zeros(50), np.zeros(50), 1, 1e-3, 0.9, 0.999, 1e-8)
+    np.testing.assert_allclose(p1, p0 - 1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+    np.testing.assert_allclose(m, 0.1 * g)
+    np.testing.assert_allclose(v, 0.001 * g * g)
+
+
+def test_bf16_rounding():
+    """BF16 keeps 7 fraction bits: the spacing at 1 is 2^-7."""
+    vals = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 2 ** -9, 1.0 + 3 * 2 ** -9, 1.0 + 2 ** -7 + 2 ** -8, -2.5, 3.0e-5])
+    r = S.bf16(vals)
+    assert r[0] == 1.0
+    assert r[1] == 1.0                            # halfway: to the even neighbour 1
+    assert r[2] == 1.0                            # below halfway
+    assert r[3] == 1.0 + 2 ** -7                  # above halfway
+    assert r[4] == 1.0 + 2 ** -6                  # halfway: to the even neighbour 1 + 2^-6
+    assert r[5] == -2.5
+    assert abs(r[6] - 3.0e-5) <= 3.0e-5 * 2 ** -8
+
+
+def test_mole_residual_definition():
+    rng = np.random.default_rng(6)
+    a = rng.uniform(0.1, 1.0, size=(5, 2, 2, 7))
+    assert S.mole_residual(a, a, 3) == 0.0
+    b = a.copy()
+    b[1] *= 1.01                                  # species 2 gains 1 % everywhere
+    assert S.mole_residual(a, b, 3) == pytest.approx(0.01, rel=1e-12)
+    c = a.copy()
+    c[3] *= 2.0                                   # doubling T halves every species' moles
+    assert S.mole_residual(a, c, 3) == pytest.approx(0.5, rel=1e-12)
