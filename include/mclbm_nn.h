@@ -1,0 +1,106 @@
+/*
+ * mclbm_nn.h -- C ABI of the learned surrogate of libmclbm: a 3-D convolutional
+ * network that maps the macroscopic fields of the multicomponent model
+ * (mole fractions X_a, temperature T, velocity u; the fields of Secs. 2.1 and
+ * 3.2) at one time to the same fields K steps later, trained on the GPU by the
+ * library's own BF16 matrix-core kernels on trajectories the lattice Boltzmann
+ * step generates, with that step as fallback (mclbm_nn_advance, declared in
+ * mclbm.h's companion section below).
+ *
+ * Network: depth conv layers with 3x3x3 kernels, width 64, ReLU between layers,
+ * BF16 weights and activations, FP32 accumulation. Layer 0 maps C channels to
+ * 64, the last layer 64 to C; the output is the change of the normalised fields
+ * over the K steps. Padding: zero outside the x ends of a tube (the walls),
+ * periodic in y and z, like the lattice.
+ *
+ * Geometry: a network is created for a set of tubes (nx, ny, nz each), the same
+ * concatenated node layout as a batched mclbm context (include/mclbm.h): a field
+ * of C components holds, for tube t, C * n_t values at offset C * (n_0 + ... +
+ * n_{t-1}), component-major inside the tube, x fastest.
+ *
+ * Parameters (host order for get/set): layer by layer, the weights
+ * W[tap][out][in] with tap = 9 (dz+1) + 3 (dy+1) + (dx+1), followed by the bias
+ * b[out]. Output channel o of a layer is b[o] + sum over taps and input
+ * channels of W[tap][o][i] * in[i](x + dx, y + dy, z + dz).
+ *
+ * Conventions as in mclbm.h: 0 on success, negative MCLBM_E* codes on error,
+ * calls ordered on the HIP stream given at creation, the caller owns the
+ * workspace and every buffer it passes.
+ */
+#ifndef MCLBM_NN_H
+#define MCLBM_NN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "mclbm.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mclbm_nn mclbm_nn;
+
+/* Workspace bytes of a network with `channels` field components (1..16),
+ * `depth` conv layers (2..16) over ntubes tubes, dims = [ntubes][3] (nx, ny, nz). */
+size_t mclbm_nn_workspace_bytes(int32_t channels, int32_t depth, const int32_t *dims, int32_t ntubes);
+
+int mclbm_nn_create(int32_t channels, int32_t depth, const int32_t *dims, int32_t ntubes,
+                    void *dev_workspace, size_t bytes, void *hip_stream, mclbm_nn **out);
+void mclbm_nn_destroy(mclbm_nn *net);
+const char *mclbm_nn_last_error(const mclbm_nn *net);
+
+/* Number of parameters (host order above). */
+int64_t mclbm_nn_param_count(const mclbm_nn *net);
+/* Copy parameters or accumulated gradients (FP32, host order) to / from the host.
+ * set_params also clears the optimiser state. */
+int mclbm_nn_set_params(mclbm_nn *net, const float *host);
+int mclbm_nn_get_params(mclbm_nn *net, float *host);
+int mclbm_nn_get_grads(mclbm_nn *net, float *host);
+
+/* Normalisation, host arrays of `channels` values: network input channel c is
+ * (f_c - in_shift[c]) * in_scale[c]; the predicted field is f_c + y_c * out_scale[c]
+ * with y the network output. */
+int mclbm_nn_set_norm(mclbm_nn *net, const float *in_shift, const float *in_scale, const float *out_scale);
+
+/* Device buffers of the network, each [channels][n] FP32 in the tube layout:
+ * the input fields and the predicted fields. */
+int mclbm_nn_io(mclbm_nn *net, float **fields_in, float **fields_out);
+
+/* Forward pass: fields_in -> fields_out; keeps the activations for backward. */
+int mclbm_nn_forward(mclbm_nn *net);
+
+/* Mean squared error of the prediction against target (device, [channels][n]),
+ * in normalised output units with per-channel weights (host, may be NULL = 1):
+ * loss = (1/n) sum_nodes sum_c w_c ((pred_c - target_c) / out_scale[c])^2.
+ * Seeds the output gradient for backward. Synchronises the stream. */
+int mclbm_nn_loss(mclbm_nn *net, const float *target, const float *channel_weight, double *loss);
+
+/* Backward pass of the last forward and loss: adds the parameter gradients to
+ * the accumulated ones. */
+int mclbm_nn_backward(mclbm_nn *net);
+int mclbm_nn_zero_grad(mclbm_nn *net);
+
+/* One Adam step (Kingma and Ba) on the accumulated gradients, then clears them. */
+int mclbm_nn_adam_step(mclbm_nn *net, float lr, float beta1, float beta2, float eps);
+
+/* Relative change of the mole content of each species per tube between two field
+ * sets a, b (device, [channels][n], X_1..X_M first, T at index M): at uniform
+ * pressure the moles of species s in a tube are proportional to sum_x X_s / T,
+ * and out[t] = max_s |S_s(b) - S_s(a)| / S_s(a). out: host [ntubes]. */
+int mclbm_nn_mole_residual(mclbm_nn *net, int32_t species, const float *a, const float *b, double *out);
+
+/* Advance a lattice Boltzmann context by K steps with the network (trained for
+ * K steps): read the fields, predict, and if the mole residual of every tube is
+ * at most resid_tol, re-initialise the populations at the local equilibrium of
+ * the predicted fields (mole fractions clipped at 0 and renormalised, the
+ * context's current pressure); otherwise run the K lattice steps instead
+ * (*used_fallback = 1). The network's tubes must be the context's and its
+ * channels M + 4 (X_1..X_M, T, u_x, u_y, u_z). The step count advances by K. */
+int mclbm_nn_advance(mclbm_ctx *c, mclbm_nn *net, int32_t K, double resid_tol, int32_t *used_fallback,
+                     double *max_residual);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

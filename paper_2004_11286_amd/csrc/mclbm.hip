@@ -24,7 +24,9 @@
 #include <vector>
 
 #include "../../include/mclbm.h"
+#include "../../include/mclbm_nn.h"
 #include "kernels.hpp"
+#include "nn_internal.hpp"
 #include "params_host.hpp"
 
 using namespace mclbm;
@@ -85,6 +87,47 @@ __global__ __launch_bounds__(BLOCK) void k_pack_f32(Launch ln, const int64_t* __
   for (int a = 0; a < M; ++a) o[(size_t)a * n + i] = (float)X[(size_t)M * b + (size_t)a * n + i];
   o[(size_t)M * n + i] = (float)T[b + i];
   for (int k = 0; k < 3; ++k) o[(size_t)(M + 1 + k) * n + i] = (float)u[3 * b + (size_t)k * n + i];
+}
+
+// Predicted fields (FP32 [M+4][n_t] per tube: X_1..X_M, T, u) -> FP64 fields for
+// mclbm_init_fields: mole fractions clipped at zero and renormalised; a block
+// flags a node whose state the equilibria cannot represent (T <= 0, p <= 0,
+// R_a T + u^2 >= 1 for a species or the mixture, no species left).
+__global__ __launch_bounds__(BLOCK) void k_pred_to_state(const Params<double>* __restrict__ P, Launch ln, int M,
+                                                        const float* __restrict__ pred, const double* __restrict__ p,
+                                                        double* __restrict__ X, double* __restrict__ T,
+                                                        double* __restrict__ u, int* __restrict__ block_bad)
+{
+  const kern::Where w = kern::locate(ln);
+  const Params<double>& Pt = P[w.t];
+  int bad = 0;
+  if (w.node < Pt.n) {
+    const int64_t n = Pt.n, b = w.base, i = w.node;
+    const float* f = pred + (size_t)(M + 4) * b;
+    double xs[MAXM], sum = 0.0, mmix = 0.0;
+    for (int a = 0; a < M; ++a) {
+      xs[a] = fmax((double)f[(size_t)a * n + i], 0.0);
+      sum += xs[a];
+    }
+    if (!(sum > 0.0)) bad = 1;
+    const double Tn = (double)f[(size_t)M * n + i];
+    double uu[3], usq = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      uu[k] = (double)f[(size_t)(M + 1 + k) * n + i];
+      usq += uu[k] * uu[k];
+    }
+    for (int a = 0; a < M; ++a) {
+      xs[a] = sum > 0.0 ? xs[a] / sum : 0.0;
+      mmix += xs[a] * Pt.m[a];
+      if (!(Tn * Pt.inv_m[a] + usq < 1.0)) bad = 1;
+    }
+    if (!(Tn > 0.0) || !(p[b + i] > 0.0) || !(mmix > 0.0) || !(Tn / mmix + usq < 1.0)) bad = 1;
+    for (int a = 0; a < M; ++a) X[(size_t)M * b + (size_t)a * n + i] = xs[a];
+    T[b + i] = Tn;
+    for (int k = 0; k < 3; ++k) u[3 * b + (size_t)k * n + i] = uu[k];
+  }
+  bad = __syncthreads_or(bad);
+  if (threadIdx.x == 0) block_bad[w.block] = bad;
 }
 
 bool pick_ops(int precision, int M, int walls, Ops& o)
@@ -1073,5 +1116,62 @@ extern "C" int mclbm_autotune(mclbm_ctx* c, int32_t trial_steps, char* report, s
     std::memcpy(report, rep.data(), k);
     report[k] = '\0';
   }
+  return MCLBM_OK;
+}
+
+extern "C" int mclbm_nn_advance(mclbm_ctx* c, mclbm_nn* net, int32_t K, double resid_tol, int32_t* used_fallback,
+                                double* max_residual)
+{
+  if (!c) return MCLBM_EARG;
+  if (!net) return fail(c, MCLBM_EARG, "network is NULL");
+  if (!c->initialised) return fail(c, MCLBM_EARG, "no state yet");
+  if (K < 1) return fail(c, MCLBM_EARG, "K must be positive");
+  const int M = c->M;
+  int channels = 0;
+  std::vector<int> dims;
+  mclbm::nn::geometry(net, &channels, &dims);
+  if (channels != M + 4) return fail(c, MCLBM_EARG, "the network must have M + 4 channels (X, T, u)");
+  if ((int)dims.size() != 3 * c->ntubes) return fail(c, MCLBM_EARG, "network and context have different tubes");
+  for (int t = 0; t < c->ntubes; ++t)
+    if (dims[3 * t] != c->tubes[t].nx || dims[3 * t + 1] != c->tubes[t].ny || dims[3 * t + 2] != c->tubes[t].nz)
+      return fail(c, MCLBM_EARG, "network and context have different tubes");
+  float *fin = nullptr, *fout = nullptr;
+  mclbm_nn_io(net, &fin, &fout);
+  int rc = mclbm_read_fields_f32(c, fin, 1);
+  if (rc) return rc;
+  rc = mclbm_nn_forward(net);
+  if (rc) return fail(c, rc, std::string("surrogate: ") + mclbm_nn_last_error(net));
+  std::vector<double> res(c->ntubes);
+  rc = mclbm_nn_mole_residual(net, M, fin, fout, res.data());
+  if (rc) return fail(c, rc, std::string("surrogate: ") + mclbm_nn_last_error(net));
+  double mx = 0.0;
+  for (double r : res) mx = std::isfinite(r) ? std::max(mx, r) : HUGE_VAL;
+  if (max_residual) *max_residual = mx;
+  bool ok = mx <= resid_tol;
+  const int64_t N = c->n;
+  double* st = c->staging;
+  double *X = st, *p = st + (size_t)M * N, *T = st + (size_t)(M + 1) * N, *u = st + (size_t)(M + 2) * N;
+  if (ok) {
+    const unsigned grid = (unsigned)c->nblocks;
+    c->ops.read(c->dPr, launch_all(c), c->pop[c->cur], nullptr, nullptr, nullptr, p, nullptr, grid, c->stream);
+    hipLaunchKernelGGL(k_pred_to_state, dim3(grid), dim3(BLOCK), 0, c->stream, (const Params<double>*)c->dPd,
+                       launch_all(c), M, fout, p, X, T, u, c->bad);
+    rc = check_launch(c, "k_pred_to_state");
+    if (rc) return rc;
+    std::vector<int> bad(c->nblocks);
+    HIP_TRY(c, hipMemcpyAsync(bad.data(), c->bad, sizeof(int) * c->nblocks, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (int64_t b = 0; b < c->nblocks && ok; ++b) ok = bad[b] == 0;
+  }
+  if (ok) {
+    const int64_t steps = c->steps;
+    rc = mclbm_init_fields(c, X, p, T, u, 1);
+    if (rc) return rc;
+    c->steps = steps + K;
+  } else {
+    rc = mclbm_step(c, K);
+    if (rc) return rc;
+  }
+  if (used_fallback) *used_fallback = ok ? 0 : 1;
   return MCLBM_OK;
 }

@@ -1,0 +1,1012 @@
+// nn.hip -- the learned surrogate of libmclbm (include/mclbm_nn.h): 3-D
+// convolutions with 3x3x3 kernels as implicit GEMMs on gfx950's BF16 matrix
+// cores (v_mfma_f32_32x32x16_bf16), their two backward passes, the loss, Adam
+// and the mole-content residual.
+//
+// Activations are node-major, act[node][channel] in BF16, so one lane's 16-byte
+// load is 8 consecutive channels of one node. A convolution computes
+// out^T[co][node] = sum_tap W_tap[co][ci] in[node + d_tap][ci]: the weights of a
+// tap (row co, ci contiguous) are the MFMA's A operand, staged in LDS and shared
+// by the four waves of a workgroup; the neighbour activations are the B operand,
+// loaded by each lane straight from global memory (the 27 taps re-read them
+// from the caches); the accumulator holds 4 consecutive output channels of one
+// node per lane group, so results leave as 8- or 16-byte vector stores. A
+// workgroup computes 256 nodes of one tube (64 per wave, two 32-node column
+// blocks) for all output channels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mclbm_nn.h"
+#include "nn_internal.hpp"
+
+namespace {
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int TILE = 256;      // nodes per workgroup
+constexpr int WIDTH = 64;      // hidden channels
+constexpr int CIN0 = 16;       // input channels of layer 0 (fields padded with zeros)
+constexpr int COUTL = 32;      // output channels of the last layer (padded)
+constexpr int NTAP = 27;
+constexpr int MAXC = 16;
+constexpr size_t ALIGN = 256;
+
+inline size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct NTube {
+  int64_t base;
+  int32_t nx, ny, nz;
+  int32_t first_tile, ntiles;
+  int32_t pad;
+};
+
+// The tube and tube-local node of lane-independent tile `tile`.
+__device__ inline NTube tube_of(const NTube* tubes, const int32_t* tile_tube, int ntubes, int tile)
+{
+  return tubes[ntubes > 1 ? tile_tube[tile] : 0];
+}
+
+__device__ inline int64_t wrap_index(const NTube& tb, int x, int y, int z)
+{
+  y += (y < 0) ? tb.ny : 0;
+  y -= (y >= tb.ny) ? tb.ny : 0;
+  z += (z < 0) ? tb.nz : 0;
+  z -= (z >= tb.nz) ? tb.nz : 0;
+  return tb.base + x + (int64_t)tb.nx * (y + (int64_t)tb.ny * z);
+}
+
+// ---------------------------------------------------------------------------
+// Convolution (forward, and backward with respect to the input)
+// ---------------------------------------------------------------------------
+// EPI 0: + bias, ReLU, BF16 out; EPI 1: + bias, FP32 out; EPI 2: times the
+// ReLU mask (mask > 0), BF16 out. sign = +1 reads in(x + d), -1 reads
+// in(x - d) (the adjoint of the forward gather: zero padding in x and periodic
+// wrapping in y, z are their own adjoints under the sign flip).
+template <int CIN, int COUT, int EPI>
+__global__ __launch_bounds__(256) void k_conv(const NTube* __restrict__ tubes, const int32_t* __restrict__ tile_tube,
+                                              int ntubes, const bf16* __restrict__ W, const float* __restrict__ bias,
+                                              const bf16* __restrict__ in, const bf16* __restrict__ mask,
+                                              void* __restrict__ out, int sign)
+{
+  static_assert(CIN % 16 == 0 && COUT % 32 == 0, "channel counts must fit the 32x32x16 MFMA");
+  constexpr int LS = CIN + 8;              // LDS row stride (bf16): staggers the banks of the rows
+  constexpr int MB = COUT / 32;
+  constexpr int KC = CIN / 16;
+  constexpr int CHUNKS = COUT * CIN / 8;   // 16-byte pieces of one tap's weights
+  constexpr int PT = (CHUNKS + 255) / 256;
+  __shared__ __attribute__((aligned(16))) bf16 wl[2][COUT * LS];
+
+  const int tile = blockIdx.x;
+  const NTube tb = tube_of(tubes, tile_tube, ntubes, tile);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int n_t = tb.nx * tb.ny * tb.nz;
+  int xs[2], ys[2], zs[2], node[2];
+  bool valid[2];
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    node[b] = (tile - tb.first_tile) * TILE + wave * 64 + b * 32 + (lane & 31);
+    valid[b] = node[b] < n_t;
+    const int i = valid[b] ? node[b] : 0;
+    xs[b] = i % tb.nx;
+    const int r = i / tb.nx;
+    ys[b] = r % tb.ny;
+    zs[b] = r / tb.ny;
+  }
+  f32x16 acc[MB][2];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[mb][b][v] = 0.f;
+
+  bf16x8 wreg[PT];
+  auto load_w = [&](int tap) {
+#pragma unroll
+    for (int p = 0; p < PT; ++p) {
+      const int ch = threadIdx.x + p * 256;
+      if (ch < CHUNKS) wreg[p] = *(const bf16x8*)(W + (size_t)tap * COUT * CIN + (size_t)ch * 8);
+    }
+  };
+  auto store_w = [&](int buf) {
+#pragma unroll
+    for (int p = 0; p < PT; ++p) {
+      const int ch = threadIdx.x + p * 256;
+      if (ch < CHUNKS) {
+        const int row = ch / (CIN / 8), col = (ch % (CIN / 8)) * 8;
+        *(bf16x8*)(&wl[buf][row * LS + col]) = wreg[p];
+      }
+    }
+  };
+  load_w(0);
+  store_w(0);
+  __syncthreads();
+  const int khalf = 8 * (lane >> 5);
+  for (int tap = 0; tap < NTAP; ++tap) {
+    const int buf = tap & 1;
+    if (tap + 1 < NTAP) load_w(tap + 1);
+    const int dx = sign * (tap % 3 - 1), dy = sign * ((tap / 3) % 3 - 1), dz = sign * (tap / 9 - 1);
+    bf16x8 bop[2][KC];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int x = xs[b] + dx;
+      const bool ok = valid[b] && x >= 0 && x < tb.nx;
+      const int64_t nb = wrap_index(tb, ok ? x : 0, ys[b] + dy, zs[b] + dz);
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) {
+        if (ok) {
+          bop[b][kc] = *(const bf16x8*)(in + nb * CIN + kc * 16 + khalf);
+        } else {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) bop[b][kc][j] = (bf16)0.f;
+        }
+      }
+    }
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        const bf16x8 a = *(const bf16x8*)(&wl[buf][(mb * 32 + (lane & 31)) * LS + kc * 16 + khalf]);
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[mb][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bop[b][kc], acc[mb][b], 0, 0, 0);
+      }
+    if (tap + 1 < NTAP) store_w(buf ^ 1);
+    __syncthreads();
+  }
+  // epilogue: lane holds channels co0 .. co0+3 of its node for each group g
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    if (!valid[b]) continue;
+    const int64_t gn = tb.base + node[b];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int co0 = mb * 32 + 8 * g + 4 * (lane >> 5);
+        float v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = acc[mb][b][4 * g + j];
+        if (EPI == 0 || EPI == 1) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) v[j] += bias[co0 + j];
+        }
+        if (EPI == 0) {
+          bf16x4 o;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) o[j] = (bf16)fmaxf(v[j], 0.f);
+          *(bf16x4*)((bf16*)out + gn * COUT + co0) = o;
+        } else if (EPI == 1) {
+          f32x4 o;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) o[j] = v[j];
+          *(f32x4*)((float*)out + gn * COUT + co0) = o;
+        } else {
+          const bf16x4 mk = *(const bf16x4*)(mask + gn * COUT + co0);
+          bf16x4 o;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) o[j] = (bf16)((float)mk[j] > 0.f ? v[j] : 0.f);
+          *(bf16x4*)((bf16*)out + gn * COUT + co0) = o;
+        }
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient: dW[tap][co][ci] = sum_nodes dY[node][co] X[node + d_tap][ci]
+// ---------------------------------------------------------------------------
+// The reduction runs over nodes, so both operands are staged transposed in LDS
+// (channel rows, node columns) for 128-node chunks; workgroup (g, tap) sums the
+// chunks g, g + G, ... and writes its partial [g][tap][COUT][CINP].
+constexpr int WCH = 128;   // nodes per staged chunk
+
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void k_wgrad(const NTube* __restrict__ tubes, const int32_t* __restrict__ tile_tube,
+                                               int ntubes, int nchunks, const bf16* __restrict__ dY,
+                                               const bf16* __restrict__ X, float* __restrict__ partial)
+{
+  constexpr int CINP = CIN < 32 ? 32 : CIN;
+  constexpr int S = WCH + 8;
+  constexpr int NB = (COUT / 32) * (CINP / 32);
+  constexpr int PW = (NB + 3) / 4;
+  __shared__ __attribute__((aligned(16))) bf16 dyt[COUT * S];
+  __shared__ __attribute__((aligned(16))) bf16 xt[CINP * S];
+  const int tap = blockIdx.y, g = blockIdx.x, G = gridDim.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
+  f32x16 acc[PW];
+#pragma unroll
+  for (int q = 0; q < PW; ++q)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[q][v] = 0.f;
+  if (CIN < CINP) {
+    for (int k = threadIdx.x; k < (CINP - CIN) * S; k += 256) xt[CIN * S + k] = (bf16)0.f;
+  }
+  const int khalf = 8 * (lane >> 5);
+  for (int ch = g; ch < nchunks; ch += G) {
+    const int tile = ch >> 1;
+    const NTube tb = tube_of(tubes, tile_tube, ntubes, tile);
+    const int n_t = tb.nx * tb.ny * tb.nz;
+    const int i = threadIdx.x & (WCH - 1);
+    const int node = (tile - tb.first_tile) * TILE + (ch & 1) * WCH + i;
+    const bool valid = node < n_t;
+    if (threadIdx.x < WCH) {
+#pragma unroll
+      for (int c8 = 0; c8 < COUT / 8; ++c8) {
+        bf16x8 v;
+        if (valid) {
+          v = *(const bf16x8*)(dY + (tb.base + node) * COUT + c8 * 8);
+        } else {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) v[j] = (bf16)0.f;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) dyt[(c8 * 8 + j) * S + i] = v[j];
+      }
+    } else {
+      int x = 0, y = 0, z = 0;
+      if (valid) {
+        x = node % tb.nx;
+        const int r = node / tb.nx;
+        y = r % tb.ny;
+        z = r / tb.ny;
+      }
+      const bool ok = valid && x + dx >= 0 && x + dx < tb.nx;
+      const int64_t nb = wrap_index(tb, ok ? x + dx : 0, y + dy, z + dz);
+#pragma unroll
+      for (int c8 = 0; c8 < CIN / 8; ++c8) {
+        bf16x8 v;
+        if (ok) {
+          v = *(const bf16x8*)(X + nb * CIN + c8 * 8);
+        } else {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) v[j] = (bf16)0.f;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) xt[(c8 * 8 + j) * S + i] = v[j];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PW; ++q) {
+      const int blk = wave + 4 * q;
+      if (blk < NB) {
+        const int mb = blk / (CINP / 32), cb = blk % (CINP / 32);
+#pragma unroll 4
+        for (int k0 = 0; k0 < WCH; k0 += 16) {
+          const bf16x8 a = *(const bf16x8*)(&dyt[(mb * 32 + (lane & 31)) * S + k0 + khalf]);
+          const bf16x8 b = *(const bf16x8*)(&xt[(cb * 32 + (lane & 31)) * S + k0 + khalf]);
+          acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[q], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < PW; ++q) {
+    const int blk = wave + 4 * q;
+    if (blk >= NB) continue;
+    const int mb = blk / (CINP / 32), cb = blk % (CINP / 32);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int row = mb * 32 + 8 * (v / 4) + 4 * (lane >> 5) + (v % 4);
+      const int col = cb * 32 + (lane & 31);
+      partial[(((size_t)g * NTAP + tap) * COUT + row) * CINP + col] = acc[q][v];
+    }
+  }
+}
+
+// grad[tap][co][ci] += sum_g partial[g][tap][co][ci] over the real channels
+// (co < co_r, ci < ci_r) of the padded partials [G][tap][COUTP][CINP], fixed order.
+__global__ void k_wgrad_reduce(const float* __restrict__ partial, int G, int COUTP, int CINP, int co_r, int ci_r,
+                               float* __restrict__ grad)
+{
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= NTAP * co_r * ci_r) return;
+  const int ci = k % ci_r, co = (k / ci_r) % co_r, tap = k / (ci_r * co_r);
+  float s = 0.f;
+  for (int g = 0; g < G; ++g) s += partial[(((size_t)g * NTAP + tap) * COUTP + co) * CINP + ci];
+  grad[k] += s;
+}
+
+// Bias gradient partials: partial[tile][c] = sum over the tile's nodes of dY[node][c].
+__global__ __launch_bounds__(256) void k_bgrad(const NTube* __restrict__ tubes, const int32_t* __restrict__ tile_tube,
+                                               int ntubes, int C, const bf16* __restrict__ dY,
+                                               float* __restrict__ partial)
+{
+  const int tile = blockIdx.x;
+  const NTube tb = tube_of(tubes, tile_tube, ntubes, tile);
+  const int n_t = tb.nx * tb.ny * tb.nz;
+  const int c = threadIdx.x;
+  if (c >= C) return;
+  float s = 0.f;
+  const int n0 = (tile - tb.first_tile) * TILE;
+  for (int i = 0; i < TILE && n0 + i < n_t; ++i) s += (float)dY[(tb.base + n0 + i) * C + c];
+  partial[(size_t)tile * C + c] = s;
+}
+
+// grad[c] += sum_t partial[t][c] for the real channels c < count (row stride C).
+__global__ void k_bgrad_reduce(const float* __restrict__ partial, int ntiles, int C, int count,
+                               float* __restrict__ grad)
+{
+  const int c = threadIdx.x;
+  if (c >= count) return;
+  float s = 0.f;
+  for (int t = 0; t < ntiles; ++t) s += partial[(size_t)t * C + c];
+  grad[c] += s;
+}
+
+// ---------------------------------------------------------------------------
+// Input packing, output unpacking, loss
+// ---------------------------------------------------------------------------
+struct Norm {
+  float in_shift[MAXC], in_scale[MAXC], out_scale[MAXC], weight[MAXC];
+};
+
+// act0[node][c] = bf16((f_c - shift_c) scale_c), zero for c >= C.
+__global__ __launch_bounds__(256) void k_pack_in(const NTube* __restrict__ tubes, const int32_t* __restrict__ tile_tube,
+                                                 int ntubes, int C, Norm nm, const float* __restrict__ f,
+                                                 bf16* __restrict__ act0)
+{
+  const int tile = blockIdx.x;
+  const NTube tb = tube_of(tubes, tile_tube, ntubes, tile);
+  const int n_t = tb.nx * tb.ny * tb.nz;
+  const int node = (tile - tb.first_tile) * TILE + threadIdx.x;
+  if (node >= n_t) return;
+  const float* ft = f + (size_t)C * tb.base;
+  bf16x8 lo, hi;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) lo[c] = (bf16)(c < C ? (ft[(size_t)c * n_t + node] - nm.in_shift[c]) * nm.in_scale[c] : 0.f);
+#pragma unroll
+  for (int c = 8; c < 16; ++c)
+    hi[c - 8] = (bf16)(c < C ? (ft[(size_t)c * n_t + node] - nm.in_shift[c]) * nm.in_scale[c] : 0.f);
+  bf16* dst = act0 + (tb.base + node) * CIN0;
+  *(bf16x8*)dst = lo;
+  *(bf16x8*)(dst + 8) = hi;
+}
+
+// fields_out[c][node] = f[c][node] + y[node][c] out_scale_c.
+__global__ __launch_bounds__(256) void k_unpack_out(const NTube* __restrict__ tubes, const int32_t* __restrict__ tile_tube,
+                                                    int ntubes, int C, Norm nm, const float* __restrict__ f,
+                                                    const float* __restrict__ y, float* __restrict__ fo)
+{
+  const int tile = blockIdx.x;
+  const NTube tb = tube_of(tubes, tile_tube, ntubes, tile);
+  const int n_t = tb.nx * tb.ny * tb.nz;
+  const int node = (tile - tb.first_tile) * TILE + threadIdx.x;
+  if (node >= n_t) return;
+  const size_t o = (size_t)C * tb.base;
+  for (int c = 0; c < C; ++c)
+    fo[o + (size_t)c * n_t + node] = f[o + (size_t)c * n_t + node] + y[(tb.base + node) * COUTL + c] * nm.out_scale[c];
+}
+
+// Loss and its gradient with respect to the raw output y: with the target
+// change r_c = (target_c - f_c) / out_scale_c, loss = (1/N) sum w_c (y_c - r_c)^2.
+__global__ __launch_bounds__(256) void k_loss(const NTube* __restrict__ tubes, const int32_t* __restrict__ tile_tube,
+                                              int ntubes, int C, Norm nm, double inv_n, const float* __restrict__ f,
+                                              const float* __restrict__ target, const float* __restrict__ y,
+                                              bf16* __restrict__ dY, double* __restrict__ partial)
+{
+  __shared__ double red[256];
+  const int tile = blockIdx.x;
+  const NTube tb = tube_of(tubes, tile_tube, ntubes, tile);
+  const int n_t = tb.nx * tb.ny * tb.nz;
+  const int node = (tile - tb.first_tile) * TILE + threadIdx.x;
+  double l = 0.0;
+  if (node < n_t) {
+    const size_t o = (size_t)C * tb.base;
+    const int64_t gn = tb.base + node;
+    bf16 d[COUTL];
+#pragma unroll
+    for (int c = 0; c < COUTL; ++c) d[c] = (bf16)0.f;
+    for (int c = 0; c < C; ++c) {
+      const size_t k = o + (size_t)c * n_t + node;
+      const double r = ((double)target[k] - (double)f[k]) / nm.out_scale[c];
+      const double e = (double)y[gn * COUTL + c] - r;
+      l += nm.weight[c] * e * e;
+      d[c] = (bf16)(float)(2.0 * nm.weight[c] * e * inv_n);
+    }
+#pragma unroll
+    for (int c8 = 0; c8 < COUTL / 8; ++c8) {
+      bf16x8 v;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = d[c8 * 8 + j];
+      *(bf16x8*)(dY + gn * COUTL + c8 * 8) = v;
+    }
+  }
+  red[threadIdx.x] = l;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[tile] = red[0];
+}
+
+// Per-tile sums S_s = sum X_s / T (species s < M, T at component M), FP64.
+__global__ __launch_bounds__(256) void k_mole_sums(const NTube* __restrict__ tubes, const int32_t* __restrict__ tile_tube,
+                                                   int ntubes, int C, int M, const float* __restrict__ f,
+                                                   double* __restrict__ partial)
+{
+  __shared__ double red[256];
+  const int tile = blockIdx.x;
+  const NTube tb = tube_of(tubes, tile_tube, ntubes, tile);
+  const int n_t = tb.nx * tb.ny * tb.nz;
+  const int node = (tile - tb.first_tile) * TILE + threadIdx.x;
+  const size_t o = (size_t)C * tb.base;
+  for (int s = 0; s < M; ++s) {
+    double v = 0.0;
+    if (node < n_t) v = (double)f[o + (size_t)s * n_t + node] / (double)f[o + (size_t)M * n_t + node];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(size_t)tile * M + s] = red[0];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Optimiser and weight packing
+// ---------------------------------------------------------------------------
+// Adam (Kingma and Ba): m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+// w -= lr (m / bc1) / (sqrt(v / bc2) + eps); then g = 0.
+__global__ void k_adam(int64_t n, float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
+                       float* __restrict__ g, float lr, float b1, float b2, float eps, float bc1, float bc2)
+{
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const float gk = g[k];
+  const float mk = b1 * m[k] + (1.f - b1) * gk;
+  const float vk = b2 * v[k] + (1.f - b2) * gk * gk;
+  m[k] = mk;
+  v[k] = vk;
+  w[k] -= lr * (mk / bc1) / (sqrtf(vk / bc2) + eps);
+  g[k] = 0.f;
+}
+
+// BF16 copies of a layer's weights: forward layout [tap][OUTP][INP] (padding
+// zero) and backward-input layout [tap][INP][OUTP].
+__global__ void k_pack_w(const float* __restrict__ w, int OUT, int IN, int OUTP, int INP, bf16* __restrict__ wf,
+                         bf16* __restrict__ wb)
+{
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= NTAP * OUTP * INP) return;
+  const int i = k % INP, o = (k / INP) % OUTP, tap = k / (INP * OUTP);
+  const float v = (o < OUT && i < IN) ? w[((size_t)tap * OUT + o) * IN + i] : 0.f;
+  wf[k] = (bf16)v;
+  if (wb) wb[((size_t)tap * INP + i) * OUTP + o] = (bf16)v;
+}
+
+__global__ void k_pack_b(const float* __restrict__ b, int OUT, int OUTP, float* __restrict__ bp)
+{
+  const int k = threadIdx.x;
+  if (k < OUTP) bp[k] = k < OUT ? b[k] : 0.f;
+}
+
+__global__ void k_zero(float* __restrict__ p, int64_t n)
+{
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = 0.f;
+}
+
+thread_local std::string g_nn_error;
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Network object
+// ---------------------------------------------------------------------------
+struct mclbm_nn {
+  int C = 0, depth = 0, ntubes = 0;
+  int64_t n = 0, ntiles = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  std::vector<NTube> hTubes;
+  std::vector<int32_t> hTileTube;
+  Norm norm{};
+  // per layer: real and padded sizes, offsets into the parameter arrays
+  std::vector<int> in_r, out_r, in_p, out_p;
+  std::vector<int64_t> w_off, b_off;    // offsets (floats) of W and b in master/m/v/grad
+  int64_t nparam = 0;
+  int64_t step = 0;
+  // device regions
+  NTube* dTubes = nullptr;
+  int32_t* dTileTube = nullptr;
+  float *master = nullptr, *mom1 = nullptr, *mom2 = nullptr, *grad = nullptr;
+  std::vector<bf16*> wf, wb;            // packed BF16 weights per layer
+  std::vector<float*> bp;               // padded biases per layer
+  std::vector<bf16*> act;               // act[0] packed input, act[l+1] output of layer l (hidden)
+  float* yout = nullptr;                // raw output of the last layer [n][COUTL]
+  bf16* dy[2] = {nullptr, nullptr};     // activation gradients (ping-pong), [n][WIDTH]
+  bf16* dyl = nullptr;                  // gradient of the last layer's output [n][COUTL]
+  float* wpart = nullptr;               // weight-gradient partials
+  int wG = 0;
+  float* bpart = nullptr;               // bias-gradient partials [ntiles][WIDTH]
+  double* dpart = nullptr;              // loss / residual partials
+  float* fin = nullptr;                 // [C][n] input fields
+  float* fout = nullptr;                // [C][n] predicted fields
+};
+
+namespace {
+
+int nn_fail(mclbm_nn* net, int code, const std::string& msg)
+{
+  if (net) net->err = msg; else g_nn_error = msg;
+  return code;
+}
+
+#define NN_TRY(net, call)                                                                          \
+  do {                                                                                             \
+    hipError_t e_ = (call);                                                                        \
+    if (e_ != hipSuccess) return nn_fail((net), MCLBM_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+int nn_check(mclbm_nn* net, const char* what)
+{
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return nn_fail(net, MCLBM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  return MCLBM_OK;
+}
+
+struct NNLayout {
+  size_t tubes, tile_tube, master, mom1, mom2, grad, wf, wb, bp, act, yout, dy, dyl, wpart, bpart, dpart, fin, fout, total;
+  int64_t n, ntiles, nparam, nparam_p;
+  int wG;
+};
+
+void layer_sizes(int C, int depth, std::vector<int>& in_r, std::vector<int>& out_r, std::vector<int>& in_p,
+                 std::vector<int>& out_p)
+{
+  in_r.assign(depth, WIDTH);
+  out_r.assign(depth, WIDTH);
+  in_p.assign(depth, WIDTH);
+  out_p.assign(depth, WIDTH);
+  in_r[0] = C;
+  in_p[0] = CIN0;
+  out_r[depth - 1] = C;
+  out_p[depth - 1] = COUTL;
+}
+
+int validate_nn(int C, int depth, const int32_t* dims, int ntubes, std::string& err)
+{
+  if (C < 1 || C > MAXC) { err = "channels must be in 1..16"; return MCLBM_EARG; }
+  if (depth < 2 || depth > 16) { err = "depth must be in 2..16"; return MCLBM_EARG; }
+  if (!dims || ntubes < 1) { err = "tube dimensions must be given"; return MCLBM_EARG; }
+  int64_t tiles = 0;
+  for (int t = 0; t < ntubes; ++t) {
+    const int64_t nx = dims[3 * t], ny = dims[3 * t + 1], nz = dims[3 * t + 2];
+    if (nx < 1 || ny < 1 || nz < 1) { err = "tube sizes must be positive"; return MCLBM_EARG; }
+    if (nx * ny * nz >= ((int64_t)1 << 30)) { err = "tube too large"; return MCLBM_EARG; }
+    tiles += (nx * ny * nz + TILE - 1) / TILE;
+  }
+  if (tiles >= ((int64_t)1 << 30)) { err = "too many nodes"; return MCLBM_EARG; }
+  return MCLBM_OK;
+}
+
+NNLayout nn_layout(int C, int depth, const int32_t* dims, int ntubes)
+{
+  NNLayout l{};
+  l.n = 0;
+  l.ntiles = 0;
+  for (int t = 0; t < ntubes; ++t) {
+    const int64_t n = (int64_t)dims[3 * t] * dims[3 * t + 1] * dims[3 * t + 2];
+    l.n += n;
+    l.ntiles += (n + TILE - 1) / TILE;
+  }
+  std::vector<int> in_r, out_r, in_p, out_p;
+  layer_sizes(C, depth, in_r, out_r, in_p, out_p);
+  l.nparam = 0;
+  l.nparam_p = 0;
+  size_t wfb = 0, bpb = 0;
+  for (int k = 0; k < depth; ++k) {
+    l.nparam += (int64_t)NTAP * out_r[k] * in_r[k] + out_r[k];
+    wfb += align_up(sizeof(bf16) * NTAP * out_p[k] * in_p[k]);
+    bpb += align_up(sizeof(float) * out_p[k]);
+  }
+  l.wG = (int)std::min<int64_t>(2 * l.ntiles, 64);
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off += align_up(bytes); return o; };
+  l.tubes = take(sizeof(NTube) * ntubes);
+  l.tile_tube = take(sizeof(int32_t) * l.ntiles);
+  l.master = take(sizeof(float) * l.nparam);
+  l.mom1 = take(sizeof(float) * l.nparam);
+  l.mom2 = take(sizeof(float) * l.nparam);
+  l.grad = take(sizeof(float) * l.nparam);
+  l.wf = take(wfb);
+  l.wb = take(wfb);
+  l.bp = take(bpb);
+  const size_t npad = (size_t)l.ntiles * TILE;   // room for whole tiles is not needed: nodes index by tube
+  (void)npad;
+  l.act = take(sizeof(bf16) * (size_t)l.n * CIN0) ;
+  for (int k = 0; k + 1 < depth; ++k) off += align_up(sizeof(bf16) * (size_t)l.n * WIDTH);
+  l.yout = take(sizeof(float) * (size_t)l.n * COUTL);
+  l.dy = take(sizeof(bf16) * (size_t)l.n * WIDTH);
+  off += align_up(sizeof(bf16) * (size_t)l.n * WIDTH);      // second ping-pong buffer
+  l.dyl = take(sizeof(bf16) * (size_t)l.n * COUTL);
+  l.wpart = take(sizeof(float) * (size_t)l.wG * NTAP * WIDTH * WIDTH);
+  l.bpart = take(sizeof(float) * (size_t)l.ntiles * WIDTH);
+  l.dpart = take(sizeof(double) * (size_t)l.ntiles * MAXC);
+  l.fin = take(sizeof(float) * (size_t)l.n * C);
+  l.fout = take(sizeof(float) * (size_t)l.n * C);
+  l.total = off;
+  return l;
+}
+
+unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+// Reduce per-tile double partials [ntiles][nv] to per-tube sums on the host.
+int tube_sums(mclbm_nn* net, int nv, std::vector<double>& out)
+{
+  std::vector<double> part((size_t)net->ntiles * nv);
+  NN_TRY(net, hipMemcpyAsync(part.data(), net->dpart, sizeof(double) * part.size(), hipMemcpyDeviceToHost,
+                             net->stream));
+  NN_TRY(net, hipStreamSynchronize(net->stream));
+  out.assign((size_t)net->ntubes * nv, 0.0);
+  for (int t = 0; t < net->ntubes; ++t)
+    for (int k = 0; k < net->hTubes[t].ntiles; ++k)
+      for (int v = 0; v < nv; ++v) out[(size_t)t * nv + v] += part[(size_t)(net->hTubes[t].first_tile + k) * nv + v];
+  return MCLBM_OK;
+}
+
+int repack(mclbm_nn* net)
+{
+  for (int k = 0; k < net->depth; ++k) {
+    const int total = NTAP * net->out_p[k] * net->in_p[k];
+    hipLaunchKernelGGL(k_pack_w, dim3(blocks_for(total, 256)), dim3(256), 0, net->stream, net->master + net->w_off[k],
+                       net->out_r[k], net->in_r[k], net->out_p[k], net->in_p[k], net->wf[k], k > 0 ? net->wb[k] : nullptr);
+    hipLaunchKernelGGL(k_pack_b, dim3(1), dim3(64), 0, net->stream, net->master + net->b_off[k], net->out_r[k],
+                       net->out_p[k], net->bp[k]);
+  }
+  return nn_check(net, "k_pack_w");
+}
+
+template <int CIN, int COUT, int EPI>
+void conv(mclbm_nn* net, const bf16* W, const float* b, const bf16* in, const bf16* mask, void* out, int sign)
+{
+  hipLaunchKernelGGL((k_conv<CIN, COUT, EPI>), dim3((unsigned)net->ntiles), dim3(256), 0, net->stream, net->dTubes,
+                     net->dTileTube, net->ntubes, W, b, in, mask, out, sign);
+}
+
+template <int CIN, int COUT>
+void wgrad(mclbm_nn* net, const bf16* dY, const bf16* X, int layer)
+{
+  constexpr int CINP = CIN < 32 ? 32 : CIN;
+  const int nchunks = (int)(2 * net->ntiles);
+  hipLaunchKernelGGL((k_wgrad<CIN, COUT>), dim3(net->wG, NTAP), dim3(256), 0, net->stream, net->dTubes,
+                     net->dTileTube, net->ntubes, nchunks, dY, X, net->wpart);
+  // only the real channels have parameters (the padded ones stay zero)
+  const int co_r = net->out_r[layer], ci_r = net->in_r[layer];
+  const int n = NTAP * co_r * ci_r;
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks_for(n, 256)), dim3(256), 0, net->stream, net->wpart, net->wG,
+                     COUT, CINP, co_r, ci_r, net->grad + net->w_off[layer]);
+}
+
+void bgrad(mclbm_nn* net, const bf16* dY, int C, int layer)
+{
+  hipLaunchKernelGGL(k_bgrad, dim3((unsigned)net->ntiles), dim3(256), 0, net->stream, net->dTubes, net->dTileTube,
+                     net->ntubes, C, dY, net->bpart);
+  hipLaunchKernelGGL(k_bgrad_reduce, dim3(1), dim3(64), 0, net->stream, net->bpart, (int)net->ntiles, C,
+                     net->out_r[layer], net->grad + net->b_off[layer]);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" size_t mclbm_nn_workspace_bytes(int32_t channels, int32_t depth, const int32_t* dims, int32_t ntubes)
+{
+  std::string err;
+  if (validate_nn(channels, depth, dims, ntubes, err) != MCLBM_OK) {
+    g_nn_error = err;
+    return 0;
+  }
+  return nn_layout(channels, depth, dims, ntubes).total;
+}
+
+extern "C" int mclbm_nn_create(int32_t channels, int32_t depth, const int32_t* dims, int32_t ntubes,
+                               void* dev_workspace, size_t bytes, void* hip_stream, mclbm_nn** out)
+{
+  if (!out) return nn_fail(nullptr, MCLBM_EARG, "out is NULL");
+  *out = nullptr;
+  std::string err;
+  int rc = validate_nn(channels, depth, dims, ntubes, err);
+  if (rc) return nn_fail(nullptr, rc, err);
+  const NNLayout lay = nn_layout(channels, depth, dims, ntubes);
+  if (!dev_workspace) return nn_fail(nullptr, MCLBM_EARG, "workspace is NULL");
+  if (((uintptr_t)dev_workspace) % ALIGN) return nn_fail(nullptr, MCLBM_EARG, "workspace must be 256-byte aligned");
+  if (bytes < lay.total) return nn_fail(nullptr, MCLBM_EARG, "workspace too small");
+  mclbm_nn* net = new (std::nothrow) mclbm_nn();
+  if (!net) return nn_fail(nullptr, MCLBM_EARG, "out of host memory");
+  net->C = channels;
+  net->depth = depth;
+  net->ntubes = ntubes;
+  net->n = lay.n;
+  net->ntiles = lay.ntiles;
+  net->stream = (hipStream_t)hip_stream;
+  net->wG = lay.wG;
+  layer_sizes(channels, depth, net->in_r, net->out_r, net->in_p, net->out_p);
+  int64_t off = 0;
+  for (int k = 0; k < depth; ++k) {
+    net->w_off.push_back(off);
+    off += (int64_t)NTAP * net->out_r[k] * net->in_r[k];
+    net->b_off.push_back(off);
+    off += net->out_r[k];
+  }
+  net->nparam = off;
+  char* ws = (char*)dev_workspace;
+  net->dTubes = (NTube*)(ws + lay.tubes);
+  net->dTileTube = (int32_t*)(ws + lay.tile_tube);
+  net->master = (float*)(ws + lay.master);
+  net->mom1 = (float*)(ws + lay.mom1);
+  net->mom2 = (float*)(ws + lay.mom2);
+  net->grad = (float*)(ws + lay.grad);
+  size_t wo = lay.wf, bo = lay.bp, wbo = lay.wb;
+  for (int k = 0; k < depth; ++k) {
+    net->wf.push_back((bf16*)(ws + wo));
+    net->wb.push_back((bf16*)(ws + wbo));
+    const size_t wbytes = align_up(sizeof(bf16) * NTAP * net->out_p[k] * net->in_p[k]);
+    wo += wbytes;
+    wbo += wbytes;
+    net->bp.push_back((float*)(ws + bo));
+    bo += align_up(sizeof(float) * net->out_p[k]);
+  }
+  size_t ao = lay.act;
+  net->act.push_back((bf16*)(ws + ao));
+  ao += align_up(sizeof(bf16) * (size_t)lay.n * CIN0);
+  for (int k = 0; k + 1 < depth; ++k) {
+    net->act.push_back((bf16*)(ws + ao));
+    ao += align_up(sizeof(bf16) * (size_t)lay.n * WIDTH);
+  }
+  net->yout = (float*)(ws + lay.yout);
+  net->dy[0] = (bf16*)(ws + lay.dy);
+  net->dy[1] = (bf16*)(ws + lay.dy + align_up(sizeof(bf16) * (size_t)lay.n * WIDTH));
+  net->dyl = (bf16*)(ws + lay.dyl);
+  net->wpart = (float*)(ws + lay.wpart);
+  net->bpart = (float*)(ws + lay.bpart);
+  net->dpart = (double*)(ws + lay.dpart);
+  net->fin = (float*)(ws + lay.fin);
+  net->fout = (float*)(ws + lay.fout);
+  // tubes and the tile -> tube map
+  net->hTubes.resize(ntubes);
+  net->hTileTube.resize(lay.ntiles);
+  int64_t base = 0;
+  int32_t tile = 0;
+  for (int t = 0; t < ntubes; ++t) {
+    NTube& tb = net->hTubes[t];
+    tb.base = base;
+    tb.nx = dims[3 * t];
+    tb.ny = dims[3 * t + 1];
+    tb.nz = dims[3 * t + 2];
+    const int64_t n = (int64_t)tb.nx * tb.ny * tb.nz;
+    tb.first_tile = tile;
+    tb.ntiles = (int32_t)((n + TILE - 1) / TILE);
+    tb.pad = 0;
+    for (int k = 0; k < tb.ntiles; ++k) net->hTileTube[tile + k] = t;
+    tile += tb.ntiles;
+    base += n;
+  }
+  for (int c = 0; c < MAXC; ++c) {
+    net->norm.in_shift[c] = 0.f;
+    net->norm.in_scale[c] = 1.f;
+    net->norm.out_scale[c] = 1.f;
+    net->norm.weight[c] = 1.f;
+  }
+  hipError_t e = hipMemcpyAsync(net->dTubes, net->hTubes.data(), sizeof(NTube) * ntubes, hipMemcpyHostToDevice,
+                                net->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(net->dTileTube, net->hTileTube.data(), sizeof(int32_t) * lay.ntiles, hipMemcpyHostToDevice,
+                       net->stream);
+  if (e == hipSuccess) {
+    // parameters, moments and gradients start at zero (set_params gives the weights)
+    for (float* p : {net->master, net->mom1, net->mom2, net->grad})
+      hipLaunchKernelGGL(k_zero, dim3(blocks_for(net->nparam, 256)), dim3(256), 0, net->stream, p, net->nparam);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(net->stream);
+  if (e != hipSuccess) {
+    g_nn_error = std::string("device setup: ") + hipGetErrorString(e);
+    delete net;
+    return MCLBM_EDEVICE;
+  }
+  rc = repack(net);
+  if (rc) {
+    g_nn_error = net->err;
+    delete net;
+    return rc;
+  }
+  *out = net;
+  return MCLBM_OK;
+}
+
+extern "C" void mclbm_nn_destroy(mclbm_nn* net)
+{
+  if (!net) return;
+  (void)hipStreamSynchronize(net->stream);
+  delete net;
+}
+
+extern "C" const char* mclbm_nn_last_error(const mclbm_nn* net) { return net ? net->err.c_str() : g_nn_error.c_str(); }
+
+extern "C" int64_t mclbm_nn_param_count(const mclbm_nn* net) { return net ? net->nparam : -1; }
+
+extern "C" int mclbm_nn_set_params(mclbm_nn* net, const float* host)
+{
+  if (!net) return MCLBM_EARG;
+  if (!host) return nn_fail(net, MCLBM_EARG, "params is NULL");
+  NN_TRY(net, hipMemcpyAsync(net->master, host, sizeof(float) * net->nparam, hipMemcpyHostToDevice, net->stream));
+  for (float* p : {net->mom1, net->mom2, net->grad})
+    hipLaunchKernelGGL(k_zero, dim3(blocks_for(net->nparam, 256)), dim3(256), 0, net->stream, p, net->nparam);
+  net->step = 0;
+  int rc = repack(net);
+  if (rc) return rc;
+  NN_TRY(net, hipStreamSynchronize(net->stream));
+  return MCLBM_OK;
+}
+
+extern "C" int mclbm_nn_get_params(mclbm_nn* net, float* host)
+{
+  if (!net) return MCLBM_EARG;
+  if (!host) return nn_fail(net, MCLBM_EARG, "buffer is NULL");
+  NN_TRY(net, hipMemcpyAsync(host, net->master, sizeof(float) * net->nparam, hipMemcpyDeviceToHost, net->stream));
+  NN_TRY(net, hipStreamSynchronize(net->stream));
+  return MCLBM_OK;
+}
+
+extern "C" int mclbm_nn_get_grads(mclbm_nn* net, float* host)
+{
+  if (!net) return MCLBM_EARG;
+  if (!host) return nn_fail(net, MCLBM_EARG, "buffer is NULL");
+  NN_TRY(net, hipMemcpyAsync(host, net->grad, sizeof(float) * net->nparam, hipMemcpyDeviceToHost, net->stream));
+  NN_TRY(net, hipStreamSynchronize(net->stream));
+  return MCLBM_OK;
+}
+
+extern "C" int mclbm_nn_set_norm(mclbm_nn* net, const float* in_shift, const float* in_scale, const float* out_scale)
+{
+  if (!net) return MCLBM_EARG;
+  if (!in_shift || !in_scale || !out_scale) return nn_fail(net, MCLBM_EARG, "normalisation arrays must be given");
+  for (int c = 0; c < net->C; ++c) {
+    if (!(std::isfinite(in_shift[c]) && in_scale[c] > 0.f && out_scale[c] > 0.f))
+      return nn_fail(net, MCLBM_EARG, "scales must be positive and shifts finite");
+    net->norm.in_shift[c] = in_shift[c];
+    net->norm.in_scale[c] = in_scale[c];
+    net->norm.out_scale[c] = out_scale[c];
+  }
+  return MCLBM_OK;
+}
+
+extern "C" int mclbm_nn_io(mclbm_nn* net, float** fields_in, float** fields_out)
+{
+  if (!net) return MCLBM_EARG;
+  if (fields_in) *fields_in = net->fin;
+  if (fields_out) *fields_out = net->fout;
+  return MCLBM_OK;
+}
+
+extern "C" int mclbm_nn_forward(mclbm_nn* net)
+{
+  if (!net) return MCLBM_EARG;
+  const unsigned grid = (unsigned)net->ntiles;
+  hipLaunchKernelGGL(k_pack_in, dim3(grid), dim3(256), 0, net->stream, net->dTubes, net->dTileTube, net->ntubes,
+                     net->C, net->norm, net->fin, net->act[0]);
+  const int D = net->depth;
+  conv<CIN0, WIDTH, 0>(net, net->wf[0], net->bp[0], net->act[0], nullptr, net->act[1], 1);
+  for (int k = 1; k + 1 < D; ++k) conv<WIDTH, WIDTH, 0>(net, net->wf[k], net->bp[k], net->act[k], nullptr, net->act[k + 1], 1);
+  conv<WIDTH, COUTL, 1>(net, net->wf[D - 1], net->bp[D - 1], net->act[D - 1], nullptr, net->yout, 1);
+  hipLaunchKernelGGL(k_unpack_out, dim3(grid), dim3(256), 0, net->stream, net->dTubes, net->dTileTube, net->ntubes,
+                     net->C, net->norm, net->fin, net->yout, net->fout);
+  return nn_check(net, "mclbm_nn_forward");
+}
+
+extern "C" int mclbm_nn_loss(mclbm_nn* net, const float* target, const float* channel_weight, double* loss)
+{
+  if (!net) return MCLBM_EARG;
+  if (!target) return nn_fail(net, MCLBM_EARG, "target is NULL");
+  Norm nm = net->norm;
+  for (int c = 0; c < net->C; ++c) nm.weight[c] = channel_weight ? channel_weight[c] : 1.f;
+  hipLaunchKernelGGL(k_loss, dim3((unsigned)net->ntiles), dim3(256), 0, net->stream, net->dTubes, net->dTileTube,
+                     net->ntubes, net->C, nm, 1.0 / (double)net->n, net->fin, target, net->yout, net->dyl, net->dpart);
+  int rc = nn_check(net, "k_loss");
+  if (rc) return rc;
+  std::vector<double> part(net->ntiles);
+  NN_TRY(net, hipMemcpyAsync(part.data(), net->dpart, sizeof(double) * net->ntiles, hipMemcpyDeviceToHost,
+                             net->stream));
+  NN_TRY(net, hipStreamSynchronize(net->stream));
+  double s = 0.0;
+  for (double v : part) s += v;
+  if (loss) *loss = s / (double)net->n;
+  return MCLBM_OK;
+}
+
+extern "C" int mclbm_nn_backward(mclbm_nn* net)
+{
+  if (!net) return MCLBM_EARG;
+  const int D = net->depth;
+  // last layer: dW from dyl and act[D-1]; then the gradient of act[D-1]
+  wgrad<WIDTH, COUTL>(net, net->dyl, net->act[D - 1], D - 1);
+  bgrad(net, net->dyl, COUTL, D - 1);
+  conv<COUTL, WIDTH, 2>(net, net->wb[D - 1], nullptr, net->dyl, net->act[D - 1], net->dy[0], -1);
+  int cur = 0;
+  for (int k = D - 2; k >= 1; --k) {
+    wgrad<WIDTH, WIDTH>(net, net->dy[cur], net->act[k], k);
+    bgrad(net, net->dy[cur], WIDTH, k);
+    conv<WIDTH, WIDTH, 2>(net, net->wb[k], nullptr, net->dy[cur], net->act[k], net->dy[cur ^ 1], -1);
+    cur ^= 1;
+  }
+  wgrad<CIN0, WIDTH>(net, net->dy[cur], net->act[0], 0);
+  bgrad(net, net->dy[cur], WIDTH, 0);
+  return nn_check(net, "mclbm_nn_backward");
+}
+
+extern "C" int mclbm_nn_zero_grad(mclbm_nn* net)
+{
+  if (!net) return MCLBM_EARG;
+  hipLaunchKernelGGL(k_zero, dim3(blocks_for(net->nparam, 256)), dim3(256), 0, net->stream, net->grad, net->nparam);
+  return nn_check(net, "k_zero");
+}
+
+extern "C" int mclbm_nn_adam_step(mclbm_nn* net, float lr, float beta1, float beta2, float eps)
+{
+  if (!net) return MCLBM_EARG;
+  if (!(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+    return nn_fail(net, MCLBM_EARG, "need lr > 0, 0 <= beta < 1, eps > 0");
+  net->step += 1;
+  const float bc1 = 1.f - (float)std::pow((double)beta1, (double)net->step);
+  const float bc2 = 1.f - (float)std::pow((double)beta2, (double)net->step);
+  hipLaunchKernelGGL(k_adam, dim3(blocks_for(net->nparam, 256)), dim3(256), 0, net->stream, net->nparam, net->master,
+                     net->mom1, net->mom2, net->grad, lr, beta1, beta2, eps, bc1, bc2);
+  int rc = nn_check(net, "k_adam");
+  if (rc) return rc;
+  return repack(net);
+}
+
+extern "C" int mclbm_nn_mole_residual(mclbm_nn* net, int32_t species, const float* a, const float* b, double* out)
+{
+  if (!net) return MCLBM_EARG;
+  if (!a || !b || !out) return nn_fail(net, MCLBM_EARG, "pointers must be given");
+  if (species < 1 || species + 1 > net->C) return nn_fail(net, MCLBM_EARG, "need 1 <= species < channels");
+  std::vector<double> sa, sb;
+  for (int pass = 0; pass < 2; ++pass) {
+    hipLaunchKernelGGL(k_mole_sums, dim3((unsigned)net->ntiles), dim3(256), 0, net->stream, net->dTubes,
+                       net->dTileTube, net->ntubes, net->C, species, pass ? b : a, net->dpart);
+    int rc = nn_check(net, "k_mole_sums");
+    if (rc) return rc;
+    rc = tube_sums(net, species, pass ? sb : sa);
+    if (rc) return rc;
+  }
+  for (int t = 0; t < net->ntubes; ++t) {
+    double r = 0.0;
+    for (int s = 0; s < species; ++s) {
+      const double x = sa[(size_t)t * species + s], y = sb[(size_t)t * species + s];
+      const double d = std::fabs(y - x) / std::fabs(x);
+      r = std::max(r, std::isfinite(d) ? d : HUGE_VAL);
+    }
+    out[t] = r;
+  }
+  return MCLBM_OK;
+}
+
+void mclbm::nn::geometry(const mclbm_nn* net, int* channels, std::vector<int>* dims)
+{
+  *channels = net->C;
+  dims->clear();
+  for (const NTube& tb : net->hTubes) {
+    dims->push_back(tb.nx);
+    dims->push_back(tb.ny);
+    dims->push_back(tb.nz);
+  }
+}

@@ -43,6 +43,10 @@ EXPORTS = ["mclbm_workspace_bytes", "mclbm_batch_workspace_bytes", "mclbm_create
            "mclbm_conservation", "mclbm_step_count", "mclbm_state_bytes", "mclbm_save", "mclbm_load",
            "mclbm_set_timing", "mclbm_kernel_stats", "mclbm_get_launch", "mclbm_set_launch",
            "mclbm_autotune"]
+NN_EXPORTS = ["mclbm_nn_workspace_bytes", "mclbm_nn_create", "mclbm_nn_destroy", "mclbm_nn_last_error",
+              "mclbm_nn_param_count", "mclbm_nn_set_params", "mclbm_nn_get_params", "mclbm_nn_get_grads",
+              "mclbm_nn_set_norm", "mclbm_nn_io", "mclbm_nn_forward", "mclbm_nn_loss", "mclbm_nn_backward",
+              "mclbm_nn_zero_grad", "mclbm_nn_adam_step", "mclbm_nn_mole_residual", "mclbm_nn_advance"]
 
 
 class mclbm_params(C.Structure):
@@ -92,6 +96,28 @@ def _load():
     L.mclbm_get_launch.argtypes = [vp, C.POINTER(mclbm_launch)]
     L.mclbm_set_launch.argtypes = [vp, C.POINTER(mclbm_launch)]
     L.mclbm_autotune.argtypes = [vp, C.c_int32, C.c_char_p, C.c_size_t]
+    ip = C.POINTER(C.c_int32)
+    fp = C.POINTER(C.c_float)
+    L.mclbm_nn_workspace_bytes.argtypes = [C.c_int32, C.c_int32, ip, C.c_int32]
+    L.mclbm_nn_workspace_bytes.restype = C.c_size_t
+    L.mclbm_nn_create.argtypes = [C.c_int32, C.c_int32, ip, C.c_int32, vp, C.c_size_t, vp, C.POINTER(vp)]
+    L.mclbm_nn_destroy.argtypes = [vp]
+    L.mclbm_nn_destroy.restype = None
+    L.mclbm_nn_last_error.argtypes = [vp]
+    L.mclbm_nn_last_error.restype = C.c_char_p
+    L.mclbm_nn_param_count.argtypes = [vp]
+    L.mclbm_nn_param_count.restype = C.c_int64
+    for name in ("mclbm_nn_set_params", "mclbm_nn_get_params", "mclbm_nn_get_grads"):
+        getattr(L, name).argtypes = [vp, fp]
+    L.mclbm_nn_set_norm.argtypes = [vp, fp, fp, fp]
+    L.mclbm_nn_io.argtypes = [vp, C.POINTER(vp), C.POINTER(vp)]
+    L.mclbm_nn_forward.argtypes = [vp]
+    L.mclbm_nn_loss.argtypes = [vp, vp, fp, dp]
+    L.mclbm_nn_backward.argtypes = [vp]
+    L.mclbm_nn_zero_grad.argtypes = [vp]
+    L.mclbm_nn_adam_step.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float]
+    L.mclbm_nn_mole_residual.argtypes = [vp, C.c_int32, vp, vp, dp]
+    L.mclbm_nn_advance.argtypes = [vp, vp, C.c_int32, C.c_double, ip, dp]
     L.mclbm_destroy.argtypes = [vp]
     L.mclbm_destroy.restype = None
     L.mclbm_last_error.argtypes = [vp]
@@ -473,3 +499,200 @@ class Batch:
 
     def kernel_stats(self, kernel: int):
         return mclbm_kernel_stats(self.ctx, kernel)
+
+
+# ------------------------------------------------------------------ surrogate (include/mclbm_nn.h)
+def _nn_check(net, rc: int):
+    if rc != MCLBM_OK:
+        msg = lib.mclbm_nn_last_error(net)
+        raise MclbmError(rc, msg.decode() if msg else "")
+
+
+def _dims_array(dims):
+    d = np.ascontiguousarray(np.asarray(dims, dtype=np.int32).reshape(-1))
+    return d, d.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _f32p(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def mclbm_nn_workspace_bytes(channels: int, depth: int, dims) -> int:
+    d, dp_ = _dims_array(dims)
+    n = lib.mclbm_nn_workspace_bytes(int(channels), int(depth), dp_, d.size // 3)
+    if n == 0:
+        raise MclbmError(MCLBM_EARG, lib.mclbm_nn_last_error(None).decode())
+    return int(n)
+
+
+def mclbm_nn_create(channels: int, depth: int, dims, workspace_ptr: int, nbytes: int, stream: int):
+    d, dp_ = _dims_array(dims)
+    h = C.c_void_p()
+    _nn_check(None, lib.mclbm_nn_create(int(channels), int(depth), dp_, d.size // 3, C.c_void_p(workspace_ptr),
+                                        nbytes, C.c_void_p(stream), C.byref(h)))
+    return h
+
+
+def mclbm_nn_destroy(net) -> None:
+    lib.mclbm_nn_destroy(net)
+
+
+def mclbm_nn_last_error(net) -> str:
+    m = lib.mclbm_nn_last_error(net)
+    return m.decode() if m else ""
+
+
+def mclbm_nn_param_count(net) -> int:
+    return int(lib.mclbm_nn_param_count(net))
+
+
+def mclbm_nn_set_params(net, params: np.ndarray) -> None:
+    a = np.ascontiguousarray(params, dtype=np.float32)
+    assert a.size == mclbm_nn_param_count(net)
+    _nn_check(net, lib.mclbm_nn_set_params(net, _f32p(a)))
+
+
+def mclbm_nn_get_params(net) -> np.ndarray:
+    a = np.zeros(mclbm_nn_param_count(net), dtype=np.float32)
+    _nn_check(net, lib.mclbm_nn_get_params(net, _f32p(a)))
+    return a
+
+
+def mclbm_nn_get_grads(net) -> np.ndarray:
+    a = np.zeros(mclbm_nn_param_count(net), dtype=np.float32)
+    _nn_check(net, lib.mclbm_nn_get_grads(net, _f32p(a)))
+    return a
+
+
+def mclbm_nn_set_norm(net, in_shift, in_scale, out_scale) -> None:
+    arrs = [np.ascontiguousarray(v, dtype=np.float32) for v in (in_shift, in_scale, out_scale)]
+    _nn_check(net, lib.mclbm_nn_set_norm(net, *[_f32p(a) for a in arrs]))
+
+
+def mclbm_nn_io(net):
+    a, b = C.c_void_p(), C.c_void_p()
+    _nn_check(net, lib.mclbm_nn_io(net, C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
+def mclbm_nn_forward(net) -> None:
+    _nn_check(net, lib.mclbm_nn_forward(net))
+
+
+def mclbm_nn_loss(net, target_ptr: int, channel_weight=None) -> float:
+    out = C.c_double()
+    w = None if channel_weight is None else np.ascontiguousarray(channel_weight, dtype=np.float32)
+    _nn_check(net, lib.mclbm_nn_loss(net, C.c_void_p(target_ptr), None if w is None else _f32p(w), C.byref(out)))
+    return out.value
+
+
+def mclbm_nn_backward(net) -> None:
+    _nn_check(net, lib.mclbm_nn_backward(net))
+
+
+def mclbm_nn_zero_grad(net) -> None:
+    _nn_check(net, lib.mclbm_nn_zero_grad(net))
+
+
+def mclbm_nn_adam_step(net, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8) -> None:
+    _nn_check(net, lib.mclbm_nn_adam_step(net, float(lr), float(beta1), float(beta2), float(eps)))
+
+
+def mclbm_nn_mole_residual(net, species: int, a_ptr: int, b_ptr: int, ntubes: int) -> np.ndarray:
+    out = np.zeros(ntubes)
+    _nn_check(net, lib.mclbm_nn_mole_residual(net, int(species), C.c_void_p(a_ptr), C.c_void_p(b_ptr),
+                                              out.ctypes.data_as(C.POINTER(C.c_double))))
+    return out
+
+
+def mclbm_nn_advance(ctx, net, K: int, resid_tol: float):
+    used = C.c_int32()
+    res = C.c_double()
+    _check(ctx, lib.mclbm_nn_advance(ctx, net, int(K), float(resid_tol), C.byref(used), C.byref(res)))
+    return bool(used.value), res.value
+
+
+class Net:
+    """A surrogate network over a set of tubes plus its torch-owned workspace.
+    fields_in / fields_out are views of the network's own device buffers
+    ([channels][n] per tube, concatenated)."""
+
+    def __init__(self, channels: int, depth: int, dims, device: str = "cuda:0", stream=None):
+        import torch
+
+        self.C = int(channels)
+        self.depth = int(depth)
+        self.dims = [tuple(int(v) for v in d) for d in dims]
+        self.sizes = [nx * ny * nz for nx, ny, nz in self.dims]
+        self.n = int(sum(self.sizes))
+        self.device = torch.device(device)
+        nbytes = mclbm_nn_workspace_bytes(self.C, self.depth, self.dims)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        with torch.cuda.device(self.device):
+            self.net = mclbm_nn_create(self.C, self.depth, self.dims, self.workspace.data_ptr(), nbytes,
+                                       self.stream.cuda_stream)
+        pin, pout = mclbm_nn_io(self.net)
+        base = self.workspace.data_ptr()
+        count = self.C * self.n
+        as_f32 = self.workspace.view(torch.float32) if nbytes % 4 == 0 else None
+        assert as_f32 is not None and (pin - base) % 4 == 0 and (pout - base) % 4 == 0
+        self.fields_in = as_f32[(pin - base) // 4:(pin - base) // 4 + count]
+        self.fields_out = as_f32[(pout - base) // 4:(pout - base) // 4 + count]
+
+    def close(self):
+        if getattr(self, "net", None) is not None:
+            mclbm_nn_destroy(self.net)
+            self.net = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def param_count(self) -> int:
+        return mclbm_nn_param_count(self.net)
+
+    def set_params(self, p):
+        mclbm_nn_set_params(self.net, p)
+
+    def get_params(self):
+        return mclbm_nn_get_params(self.net)
+
+    def get_grads(self):
+        return mclbm_nn_get_grads(self.net)
+
+    def set_norm(self, in_shift, in_scale, out_scale):
+        mclbm_nn_set_norm(self.net, in_shift, in_scale, out_scale)
+
+    def forward(self, fields=None):
+        """fields: a CUDA float32 tensor of channels * n values (copied in), or None
+        to use what fields_in holds. Returns fields_out."""
+        if fields is not None:
+            self.fields_in.copy_(fields.reshape(-1))
+        mclbm_nn_forward(self.net)
+        return self.fields_out
+
+    def loss(self, target, channel_weight=None) -> float:
+        t = target.reshape(-1).contiguous()
+        return mclbm_nn_loss(self.net, t.data_ptr(), channel_weight)
+
+    def backward(self):
+        mclbm_nn_backward(self.net)
+
+    def zero_grad(self):
+        mclbm_nn_zero_grad(self.net)
+
+    def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        mclbm_nn_adam_step(self.net, lr, beta1, beta2, eps)
+
+    def mole_residual(self, species, a, b) -> np.ndarray:
+        a = a.reshape(-1).contiguous()
+        b = b.reshape(-1).contiguous()
+        return mclbm_nn_mole_residual(self.net, species, a.data_ptr(), b.data_ptr(), len(self.dims))
+
+    def advance(self, sim, K: int, resid_tol: float):
+        """Advance a Sim or Batch by K steps; returns (used_fallback, max_residual)."""
+        return mclbm_nn_advance(sim.ctx, self.net, K, resid_tol)

@@ -12,9 +12,13 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_functions():
-    src = open(os.path.join(ROOT, "include", "mclbm.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(mclbm_[a-z0-9_]+)\s*\(", src)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", h)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(mclbm_[a-z0-9_]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():
@@ -23,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     assert len(names) >= 14
     for name in names:
         assert hasattr(m.lib, name), name
-    assert sorted(m.EXPORTS) == names
+    assert sorted(m.EXPORTS + m.NN_EXPORTS) == names
 
 
 def test_binding_names_match_c_names():
@@ -103,3 +107,22 @@ def test_launch_struct_matches_header():
     fields = re.findall(r"int32_t\s+(\w+)(?:\[(\d+)\])?;", body)
     assert [f for f, _ in fields] == [f for f, *_ in m.mclbm_launch._fields_]
     assert ctypes.sizeof(m.mclbm_launch) == 4 * sum(int(k or 1) for _, k in fields)
+
+
+def test_nn_workspace_and_validation():
+    m = pytest.importorskip("paper_2004_11286_amd.mclbm")
+    dims = [(13, 4, 3), (40, 2, 5)]
+    b = m.mclbm_nn_workspace_bytes(7, 6, dims)
+    n = 13 * 12 + 40 * 10
+    assert b > 5 * n * 64 * 2                     # the hidden activations dominate
+    assert b < m.mclbm_nn_workspace_bytes(7, 6, dims + [(64, 8, 8)])
+    for bad in [(0, 6, dims), (17, 6, dims), (7, 1, dims), (7, 6, [(0, 4, 4)])]:
+        with pytest.raises(m.MclbmError):
+            m.mclbm_nn_workspace_bytes(*bad)
+
+
+def test_nn_param_count_matches_the_oracle():
+    """Parameter count of the library's layout equals the oracle's (host order)."""
+    from oracle import surrogate_oracle as S
+
+    assert S.param_count(7, 6) == 27 * (7 * 64 + 4 * 64 * 64 + 64 * 7) + 5 * 64 + 7

@@ -1,0 +1,213 @@
+"""The surrogate's BF16 matrix-core kernels against the FP64 oracle, through the
+C ABI: forward pass, loss, parameter gradients (the oracle rounds to BF16 where
+the kernels store BF16, so the comparison isolates FP32 accumulation), Adam,
+the mole residual, and the advance entry point with and without fallback.
+
+Bounds: the depth-2 forward to 1e-3 of the output's maximum (only FP32-versus-
+FP64 sums differ, plus rare BF16 ties of the hidden layer); the depth-6 forward
+to 1e-2 (rounding differences of BF16 activations compound over layers); the
+gradients per layer to 1e-2 in the 2-norm; Adam to FP32 rounding.
+"""
+import numpy as np
+import pytest
+
+from oracle import surrogate_oracle as S
+from paper_2004_11286_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+DIMS = [(13, 4, 3), (40, 2, 5), (7, 8, 8)]       # ragged tubes: 156, 400 and 448 nodes
+C = 7
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2004_11286_amd import mclbm
+
+    return mclbm, torch
+
+
+def random_fields(seed, dims=DIMS):
+    rng = np.random.default_rng(seed)
+    out = []
+    for nx, ny, nz in dims:
+        x = np.arange(nx)
+        base = np.stack([0.5 + 0.3 * np.sin(2 * np.pi * (x + c) / nx) for c in range(C)])[:, None, None, :]
+        f = base + 0.1 * rng.normal(size=(C, nz, ny, nx))
+        out.append(f)
+    return out
+
+
+def norm_arrays(seed=0):
+    rng = np.random.default_rng(seed)
+    return {"in_shift": rng.uniform(0.3, 0.6, C), "in_scale": rng.uniform(1.0, 3.0, C),
+            "out_scale": rng.uniform(0.5, 2.0, C)}
+
+
+def make_net(env, depth, params, norm, dims=DIMS):
+    mc, torch = env
+    net = mc.Net(C, depth, dims)
+    net.set_params(params)
+    net.set_norm(norm["in_shift"], norm["in_scale"], norm["out_scale"])
+    return net
+
+
+def flat(env, fields):
+    _, torch = env
+    v = np.concatenate([f.astype(np.float32).ravel() for f in fields])
+    return torch.from_numpy(v).cuda()
+
+
+def split(vec, dims=DIMS):
+    out, k = [], 0
+    for nx, ny, nz in dims:
+        n = nx * ny * nz
+        out.append(vec[k:k + C * n].reshape(C, nz, ny, nx))
+        k += C * n
+    return out
+
+
+@pytest.mark.parametrize("depth,bound", [(2, 1e-3), (6, 1e-2)])
+def test_forward_matches_oracle(env, depth, bound):
+    p = S.he_init(C, depth, seed=depth, gain=1.0)
+    p += np.random.default_rng(1).normal(0, 0.01, p.size).astype(np.float32)
+    nm = norm_arrays()
+    net = make_net(env, depth, p, nm)
+    fs = [f.astype(np.float32).astype(np.float64) for f in random_fields(2)]
+    out = net.forward(flat(env, fs)).cpu().numpy()
+    net.close()
+    for t, (f, g) in enumerate(zip(fs, split(out))):
+        y_ref, _, _ = S.forward(p, f, {k: np.asarray(v, np.float32).astype(np.float64) for k, v in nm.items()},
+                                C, depth, round_bf16=True)
+        y_gpu = (g - f.astype(np.float32)) / np.asarray(nm["out_scale"], np.float32)[:, None, None, None]
+        err = np.abs(y_gpu - y_ref).max() / np.abs(y_ref).max()
+        print("forward depth", depth, "tube", t, "rel linf", err)
+        assert err < bound, (t, err)
+
+
+def test_loss_and_gradients_match_oracle(env):
+    _, torch = env
+    depth = 4
+    p = S.he_init(C, depth, seed=7, gain=1.0)
+    p += np.random.default_rng(2).normal(0, 0.02, p.size).astype(np.float32)
+    nm = norm_arrays(1)
+    nm64 = {k: np.asarray(v, np.float32).astype(np.float64) for k, v in nm.items()}
+    net = make_net(env, depth, p, nm)
+    fs = [f.astype(np.float32).astype(np.float64) for f in random_fields(3)]
+    rng = np.random.default_rng(4)
+    tg = [(f + 0.05 * rng.normal(size=f.shape)).astype(np.float32).astype(np.float64) for f in fs]
+    w = np.linspace(0.5, 2.0, C).astype(np.float32)
+    net.zero_grad()
+    net.forward(flat(env, fs))
+    loss = net.loss(flat(env, tg), w)
+    net.backward()
+    g_gpu = net.get_grads().astype(np.float64)
+    net.close()
+    L_ref, g_ref = S.loss_and_grad(p, fs, tg, nm64, C, depth, weight=w.astype(np.float64), round_bf16=True)
+    print("loss", loss, L_ref)
+    assert loss == pytest.approx(L_ref, rel=5e-3)
+    k = 0
+    for li, (o, i) in enumerate(S.layer_shapes(C, depth)):
+        for name, size in (("W", 27 * o * i), ("b", o)):
+            a, b = g_gpu[k:k + size], g_ref[k:k + size]
+            k += size
+            rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+            print("grad layer", li, name, "rel 2-norm", rel)
+            assert rel < 1e-2, (li, name, rel)
+
+
+def test_adam_step_matches_oracle(env):
+    depth = 3
+    p = S.he_init(C, depth, seed=11)
+    nm = norm_arrays(2)
+    net = make_net(env, depth, p, nm)
+    fs = random_fields(5)
+    net.zero_grad()
+    net.forward(flat(env, fs))
+    net.loss(flat(env, [f + 0.01 for f in fs]))
+    net.backward()
+    g = net.get_grads().astype(np.float64)
+    net.adam_step(1e-3, 0.9, 0.999, 1e-8)
+    p1 = net.get_params().astype(np.float64)
+    assert np.all(net.get_grads() == 0.0)
+    net.close()
+    want, _, _ = S.adam(p.astype(np.float64), g, np.zeros_like(g), np.zeros_like(g), 1, 1e-3, 0.9, 0.999, 1e-8)
+    np.testing.assert_allclose(p1, want, rtol=1e-5, atol=1e-8)
+
+
+def test_mole_residual_matches_oracle(env):
+    net = make_net(env, 2, S.he_init(C, 2, seed=1), norm_arrays())
+    rng = np.random.default_rng(8)
+    a = [np.abs(f) + 0.1 for f in random_fields(9)]
+    b = [x * (1.0 + 1e-3 * rng.normal(size=x.shape)) for x in a]
+    r = net.mole_residual(3, flat(env, a), flat(env, b))
+    net.close()
+    for t in range(len(DIMS)):
+        ref = S.mole_residual(a[t].astype(np.float32).astype(np.float64), b[t].astype(np.float32).astype(np.float64), 3)
+        assert r[t] == pytest.approx(ref, rel=1e-5)
+
+
+def test_training_reduces_the_loss(env):
+    depth = 4
+    nm = {"in_shift": np.full(C, 0.5), "in_scale": np.full(C, 2.0), "out_scale": np.full(C, 0.05)}
+    net = make_net(env, depth, S.he_init(C, depth, seed=3), nm)
+    fs = random_fields(10)
+    tg = [f + 0.05 * np.tanh(3.0 * (f - 0.5)) for f in fs]       # a smooth pointwise change
+    ff, tt = flat(env, fs), flat(env, tg)
+    losses = []
+    for it in range(60):
+        net.zero_grad()
+        net.forward(ff)
+        losses.append(net.loss(tt))
+        net.backward()
+        net.adam_step(2e-3)
+    net.close()
+    print("loss", losses[0], "->", losses[-1])
+    assert losses[-1] < 0.2 * losses[0]
+
+
+def _tube_sim(mc, nx=32):
+    params, f = W.ternary_tube(nx=nx, ny=4, nz=4)
+    s = mc.Sim(params, mc.MCLBM_FP32)
+    s.init_fields(**f)
+    s.step(50)
+    return s, params
+
+
+def test_advance_falls_back_to_the_lattice(env):
+    mc, _ = env
+    s, params = _tube_sim(mc)
+    ref, _ = _tube_sim(mc)
+    net = make_net(env, 3, S.he_init(C, 3, seed=4), norm_arrays(), dims=[(32, 4, 4)])
+    used, res = net.advance(s, 20, -1.0)                    # tolerance below any residual
+    assert used and s.step_count == 70
+    ref.step(20)
+    a, b = s.read_moments(), ref.read_moments()
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k])
+    net.close()
+    s.close()
+    ref.close()
+
+
+def test_advance_with_a_null_network_keeps_the_fields(env):
+    """All-zero parameters predict no change: the mole residual is zero, the
+    prediction is accepted, and the context restarts at the local equilibrium
+    of its own (FP32-rounded) fields with the step count advanced."""
+    mc, _ = env
+    s, params = _tube_sim(mc)
+    before = s.read_moments()
+    net = mc.Net(C, 3, [(32, 4, 4)])
+    net.set_params(np.zeros(net.param_count, np.float32))
+    used, res = net.advance(s, 100, 1e-4)
+    assert not used and res == 0.0 and s.step_count == 150
+    after = s.read_moments()
+    for k in ("X", "T", "p"):
+        np.testing.assert_allclose(after[k], before[k], rtol=2e-6, atol=1e-7)
+    np.testing.assert_allclose(after["u"], before["u"], atol=1e-7)
+    net.close()
+    s.close()
