@@ -4,13 +4,21 @@
  * (mole fractions X_a, temperature T, velocity u; the fields of Secs. 2.1 and
  * 3.2) at one time to the same fields K steps later, trained on the GPU by the
  * library's own BF16 matrix-core kernels on trajectories the lattice Boltzmann
- * step generates, with that step as fallback (mclbm_nn_advance, declared in
- * mclbm.h's companion section below).
+ * step generates, with that step as fallback (mclbm_nn_advance below).
  *
  * Network: depth conv layers with 3x3x3 kernels, width 64, ReLU between layers,
- * BF16 weights and activations, FP32 accumulation. Layer 0 maps C channels to
- * 64, the last layer 64 to C; the output is the change of the normalised fields
- * over the K steps. Padding: zero outside the x ends of a tube (the walls),
+ * BF16 weights and activations, FP32 accumulation. Layer 0 maps the C field
+ * channels, P second terms and S conditioning channels to 64, the last layer 64
+ * to C. BF16 resolves a normalised input to about 3 significant digits; the
+ * first P field channels are therefore also given as a second BF16 term, the
+ * rounding remainder of the first times 256, whose layer-0 weights are those of
+ * the field divided by 256 (tied, exact in BF16), so the matrix cores see about
+ * 16 significant bits of these fields (hi + lo / 256) with no extra
+ * parameters. The
+ * output is the change of the normalised fields over the K steps. The
+ * conditioning channels are constant per tube (for instance the tube's molar
+ * masses and diffusivities, which the fields alone do not reveal but which
+ * decide how they evolve). Padding: zero outside the x ends of a tube (the walls),
  * periodic in y and z, like the lattice.
  *
  * Geometry: a network is created for a set of tubes (nx, ny, nz each), the same
@@ -41,12 +49,15 @@ extern "C" {
 
 typedef struct mclbm_nn mclbm_nn;
 
-/* Workspace bytes of a network with `channels` field components (1..16),
- * `depth` conv layers (2..16) over ntubes tubes, dims = [ntubes][3] (nx, ny, nz). */
-size_t mclbm_nn_workspace_bytes(int32_t channels, int32_t depth, const int32_t *dims, int32_t ntubes);
+/* Workspace bytes of a network with `channels` field components C, `two_term`
+ * of them (the leading ones) also given as a second term P, `conditioning`
+ * per-tube constants S (C + P + S <= 16, P <= C), `depth` conv layers (2..16)
+ * over ntubes tubes, dims = [ntubes][3] (nx, ny, nz). */
+size_t mclbm_nn_workspace_bytes(int32_t channels, int32_t two_term, int32_t conditioning, int32_t depth,
+                                const int32_t *dims, int32_t ntubes);
 
-int mclbm_nn_create(int32_t channels, int32_t depth, const int32_t *dims, int32_t ntubes,
-                    void *dev_workspace, size_t bytes, void *hip_stream, mclbm_nn **out);
+int mclbm_nn_create(int32_t channels, int32_t two_term, int32_t conditioning, int32_t depth, const int32_t *dims,
+                    int32_t ntubes, void *dev_workspace, size_t bytes, void *hip_stream, mclbm_nn **out);
 void mclbm_nn_destroy(mclbm_nn *net);
 const char *mclbm_nn_last_error(const mclbm_nn *net);
 
@@ -62,6 +73,10 @@ int mclbm_nn_get_grads(mclbm_nn *net, float *host);
  * (f_c - in_shift[c]) * in_scale[c]; the predicted field is f_c + y_c * out_scale[c]
  * with y the network output. */
 int mclbm_nn_set_norm(mclbm_nn *net, const float *in_shift, const float *in_scale, const float *out_scale);
+
+/* Conditioning values, host [ntubes][conditioning], used as given (already
+ * normalised); all zero after creation. */
+int mclbm_nn_set_conditioning(mclbm_nn *net, const float *host);
 
 /* Device buffers of the network, each [channels][n] FP32 in the tube layout:
  * the input fields and the predicted fields. */

@@ -89,20 +89,21 @@ def conv_weight_grad(dy: np.ndarray, x: np.ndarray):
 
 
 # ------------------------------------------------------------------ network
-def layer_shapes(C: int, depth: int, width: int = 64):
-    ins = [C] + [width] * (depth - 1)
+def layer_shapes(C: int, depth: int, width: int = 64, S: int = 0):
+    """S counts every extra input channel of layer 0 (second terms and conditioning)."""
+    ins = [C + S] + [width] * (depth - 1)
     outs = [width] * (depth - 1) + [C]
     return list(zip(outs, ins))
 
 
-def param_count(C: int, depth: int, width: int = 64) -> int:
-    return sum(NTAP * o * i + o for o, i in layer_shapes(C, depth, width))
+def param_count(C: int, depth: int, width: int = 64, S: int = 0) -> int:
+    return sum(NTAP * o * i + o for o, i in layer_shapes(C, depth, width, S))
 
 
-def unflatten(params: np.ndarray, C: int, depth: int, width: int = 64):
+def unflatten(params: np.ndarray, C: int, depth: int, width: int = 64, S: int = 0):
     """Flat parameters (layer by layer: W[tap][out][in], then b[out]) -> list of (W, b)."""
     out, k = [], 0
-    for o, i in layer_shapes(C, depth, width):
+    for o, i in layer_shapes(C, depth, width, S):
         W = params[k:k + NTAP * o * i].reshape(NTAP, o, i)
         k += NTAP * o * i
         b = params[k:k + o]
@@ -116,23 +117,62 @@ def flatten(layers) -> np.ndarray:
     return np.concatenate([np.concatenate([W.ravel(), b.ravel()]) for W, b in layers])
 
 
-def he_init(C: int, depth: int, seed: int, width: int = 64, gain: float = 1.0) -> np.ndarray:
+def he_init(C: int, depth: int, seed: int, width: int = 64, gain: float = 1.0, S: int = 0) -> np.ndarray:
     """Seeded He-normal weights, zero biases (the starting point of training)."""
     rng = np.random.default_rng(seed)
     layers = []
-    for k, (o, i) in enumerate(layer_shapes(C, depth, width)):
+    for k, (o, i) in enumerate(layer_shapes(C, depth, width, S)):
         std = np.sqrt(2.0 / (NTAP * i)) * (gain if k < depth - 1 else 0.1 * gain)
         layers.append((rng.normal(0.0, std, (NTAP, o, i)), np.zeros(o)))
     return flatten(layers).astype(np.float32)
 
 
-def forward(params, f, norm, C, depth, width=64, round_bf16=False):
-    """One tube: f [C][nz][ny][nx] fields -> (y raw output, pred fields, cache)."""
-    layers = unflatten(np.asarray(params, dtype=np.float64), C, depth, width)
+def two_term(v: np.ndarray):
+    """hi = bf16(v), lo = bf16((v - hi) 256), v taken in FP32 first: hi + lo / 256
+    carries about 16 significant bits of v."""
+    v32 = np.asarray(v, dtype=np.float32).astype(np.float64)
+    hi = bf16(v32)
+    return hi, bf16((v32 - hi) * 256.0)
+
+
+def expand_first(W: np.ndarray, C: int, P: int) -> np.ndarray:
+    """Layer-0 weights over the input columns [fields, second terms, conditioning]:
+    a second term reuses its field's weights divided by 256."""
+    if P == 0:
+        return W
+    return np.concatenate([W[:, :, :C], W[:, :, :P] / 256.0, W[:, :, C:]], axis=2)
+
+
+def fold_first(g: np.ndarray, C: int, P: int) -> np.ndarray:
+    """Gradient with respect to the expanded layer-0 weights -> the parameters."""
+    if P == 0:
+        return g
+    out = np.concatenate([g[:, :, :C], g[:, :, C + P:]], axis=2)
+    out[:, :, :P] += g[:, :, C:C + P] / 256.0
+    return out
+
+
+def forward(params, f, norm, C, depth, width=64, round_bf16=False, cond=None, P=0):
+    """One tube: f [C][nz][ny][nx] fields, cond [S] constants of the tube, P
+    leading field channels also given as a second BF16 term (tied weights) ->
+    (y raw output, pred fields, cache)."""
+    S = 0 if cond is None else len(cond)
+    layers = unflatten(np.asarray(params, dtype=np.float64), C, depth, width, S)
     rnd = bf16 if round_bf16 else (lambda a: a)
-    a = rnd((f - norm["in_shift"][:, None, None, None]) * norm["in_scale"][:, None, None, None])
+    v = (f - norm["in_shift"][:, None, None, None]) * norm["in_scale"][:, None, None, None]
+    if P:
+        hi, lo = two_term(v)
+        a = np.concatenate([hi, lo[:P]])
+    else:
+        a = rnd(v)
+    if S:
+        a = np.concatenate([a, np.broadcast_to(np.asarray(cond, dtype=np.float64)[:, None, None, None],
+                                               (S,) + f.shape[1:])])
+    a = rnd(a)
     acts = [a]
     for k, (W, b) in enumerate(layers):
+        if k == 0:
+            W = expand_first(W, C, P)
         z = conv(acts[-1], rnd(W), b)
         if k < depth - 1:
             acts.append(rnd(np.maximum(z, 0.0)))
@@ -142,18 +182,21 @@ def forward(params, f, norm, C, depth, width=64, round_bf16=False):
     return y, pred, acts
 
 
-def loss_and_grad(params, tubes_f, tubes_target, norm, C, depth, width=64, weight=None, round_bf16=False):
+def loss_and_grad(params, tubes_f, tubes_target, norm, C, depth, width=64, weight=None, round_bf16=False,
+                  tubes_cond=None, P=0):
     """Mean over all nodes of all tubes of sum_c w_c (y_c - r_c)^2 with
     r = (target - f) / out_scale, and its gradient with respect to the flat
     parameters (same order)."""
-    layers = unflatten(np.asarray(params, dtype=np.float64), C, depth, width)
+    S = 0 if tubes_cond is None else len(tubes_cond[0])
+    layers = unflatten(np.asarray(params, dtype=np.float64), C, depth, width, S)
     w = np.ones(C) if weight is None else np.asarray(weight, dtype=np.float64)
     rnd = bf16 if round_bf16 else (lambda a: a)
     N = sum(f[0].size for f in tubes_f)
     total = 0.0
     grads = [(np.zeros_like(W), np.zeros_like(b)) for W, b in layers]
-    for f, tgt in zip(tubes_f, tubes_target):
-        y, _, acts = forward(params, f, norm, C, depth, width, round_bf16)
+    for t, (f, tgt) in enumerate(zip(tubes_f, tubes_target)):
+        cond = None if tubes_cond is None else tubes_cond[t]
+        y, _, acts = forward(params, f, norm, C, depth, width, round_bf16, cond, P)
         r = (tgt - f) / norm["out_scale"][:, None, None, None]
         e = y - r
         total += float(np.sum(w[:, None, None, None] * e * e))
@@ -161,6 +204,8 @@ def loss_and_grad(params, tubes_f, tubes_target, norm, C, depth, width=64, weigh
         for k in range(depth - 1, -1, -1):
             W, _ = layers[k]
             dW, db = conv_weight_grad(d, acts[k])
+            if k == 0:
+                dW = fold_first(dW, C, P)
             grads[k][0][...] += dW
             grads[k][1][...] += db
             if k > 0:

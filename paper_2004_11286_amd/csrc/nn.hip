@@ -306,17 +306,25 @@ __global__ __launch_bounds__(256) void k_wgrad(const NTube* __restrict__ tubes, 
   }
 }
 
-// grad[tap][co][ci] += sum_g partial[g][tap][co][ci] over the real channels
-// (co < co_r, ci < ci_r) of the padded partials [G][tap][COUTP][CINP], fixed order.
+// grad[tap][co][j] += sum_g partial[g][tap][co][col] over the parameters of a
+// layer (co < co_r, j < ci_r) from the padded partials [G][tap][COUTP][CINP],
+// fixed order. With second terms (P > 0, layer 0) parameter column j < C also
+// collects column C + j (j < P) divided by 256, and the conditioning
+// parameters j >= C sit at column j + P.
 __global__ void k_wgrad_reduce(const float* __restrict__ partial, int G, int COUTP, int CINP, int co_r, int ci_r,
-                               float* __restrict__ grad)
+                               int C, int P, float* __restrict__ grad)
 {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= NTAP * co_r * ci_r) return;
-  const int ci = k % ci_r, co = (k / ci_r) % co_r, tap = k / (ci_r * co_r);
-  float s = 0.f;
-  for (int g = 0; g < G; ++g) s += partial[(((size_t)g * NTAP + tap) * COUTP + co) * CINP + ci];
-  grad[k] += s;
+  const int j = k % ci_r, co = (k / ci_r) % co_r, tap = k / (ci_r * co_r);
+  const int col = (P > 0 && j >= C) ? j + P : j;
+  float s = 0.f, s2 = 0.f;
+  for (int g = 0; g < G; ++g) {
+    const size_t row = (((size_t)g * NTAP + tap) * COUTP + co) * CINP;
+    s += partial[row + col];
+    if (P > 0 && j < P) s2 += partial[row + C + j];
+  }
+  grad[k] += s + s2 * (1.f / 256.f);
 }
 
 // Bias gradient partials: partial[tile][c] = sum over the tile's nodes of dY[node][c].
@@ -353,23 +361,36 @@ struct Norm {
   float in_shift[MAXC], in_scale[MAXC], out_scale[MAXC], weight[MAXC];
 };
 
-// act0[node][c] = bf16((f_c - shift_c) scale_c), zero for c >= C.
+// act0[node][c]: for c < C the normalised field v_c = (f_c - shift_c) scale_c
+// in BF16 (hi_c); for C <= c < C + P the second term lo = bf16((v - hi) 256)
+// of field c - C; for C + P <= c < C + P + S the tube's conditioning values;
+// zero above.
 __global__ __launch_bounds__(256) void k_pack_in(const NTube* __restrict__ tubes, const int32_t* __restrict__ tile_tube,
-                                                 int ntubes, int C, Norm nm, const float* __restrict__ f,
-                                                 bf16* __restrict__ act0)
+                                                 int ntubes, int C, int P, int S, Norm nm, const float* __restrict__ f,
+                                                 const float* __restrict__ cond, bf16* __restrict__ act0)
 {
   const int tile = blockIdx.x;
-  const NTube tb = tube_of(tubes, tile_tube, ntubes, tile);
+  const int t = ntubes > 1 ? tile_tube[tile] : 0;
+  const NTube tb = tubes[t];
   const int n_t = tb.nx * tb.ny * tb.nz;
   const int node = (tile - tb.first_tile) * TILE + threadIdx.x;
   if (node >= n_t) return;
   const float* ft = f + (size_t)C * tb.base;
+  auto value = [&](int c) -> float {
+    if (c < C) return (ft[(size_t)c * n_t + node] - nm.in_shift[c]) * nm.in_scale[c];
+    if (c < C + P) {
+      const int k = c - C;
+      const float v = (ft[(size_t)k * n_t + node] - nm.in_shift[k]) * nm.in_scale[k];
+      return (v - (float)(bf16)v) * 256.f;
+    }
+    if (c < C + P + S) return cond[(size_t)t * S + (c - C - P)];
+    return 0.f;
+  };
   bf16x8 lo, hi;
 #pragma unroll
-  for (int c = 0; c < 8; ++c) lo[c] = (bf16)(c < C ? (ft[(size_t)c * n_t + node] - nm.in_shift[c]) * nm.in_scale[c] : 0.f);
+  for (int c = 0; c < 8; ++c) lo[c] = (bf16)value(c);
 #pragma unroll
-  for (int c = 8; c < 16; ++c)
-    hi[c - 8] = (bf16)(c < C ? (ft[(size_t)c * n_t + node] - nm.in_shift[c]) * nm.in_scale[c] : 0.f);
+  for (int c = 8; c < 16; ++c) hi[c - 8] = (bf16)value(c);
   bf16* dst = act0 + (tb.base + node) * CIN0;
   *(bf16x8*)dst = lo;
   *(bf16x8*)(dst + 8) = hi;
@@ -477,15 +498,33 @@ __global__ void k_adam(int64_t n, float* __restrict__ w, float* __restrict__ m, 
   g[k] = 0.f;
 }
 
+// Input column i of layer 0 -> parameter column, and its weight factor: the
+// field columns c < C are parameters c, the second terms C <= i < C + P reuse
+// the weights of fields i - C divided by 256 (hi + lo / 256 is the field), the
+// conditioning columns follow. Other layers (P = 0) map i to i.
+__device__ inline int tied_column(int i, int IN, int C, int P, float& factor)
+{
+  factor = 1.f;
+  if (P == 0) return i < IN ? i : -1;
+  if (i < C) return i;
+  if (i < C + P) {
+    factor = 1.f / 256.f;
+    return i - C;
+  }
+  return i - P < IN ? i - P : -1;
+}
+
 // BF16 copies of a layer's weights: forward layout [tap][OUTP][INP] (padding
 // zero) and backward-input layout [tap][INP][OUTP].
-__global__ void k_pack_w(const float* __restrict__ w, int OUT, int IN, int OUTP, int INP, bf16* __restrict__ wf,
-                         bf16* __restrict__ wb)
+__global__ void k_pack_w(const float* __restrict__ w, int OUT, int IN, int OUTP, int INP, int C, int P,
+                         bf16* __restrict__ wf, bf16* __restrict__ wb)
 {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= NTAP * OUTP * INP) return;
   const int i = k % INP, o = (k / INP) % OUTP, tap = k / (INP * OUTP);
-  const float v = (o < OUT && i < IN) ? w[((size_t)tap * OUT + o) * IN + i] : 0.f;
+  float factor;
+  const int src = tied_column(i, IN, C, P, factor);
+  const float v = (o < OUT && src >= 0) ? w[((size_t)tap * OUT + o) * IN + src] * factor : 0.f;
   wf[k] = (bf16)v;
   if (wb) wb[((size_t)tap * INP + i) * OUTP + o] = (bf16)v;
 }
@@ -510,7 +549,7 @@ thread_local std::string g_nn_error;
 // Network object
 // ---------------------------------------------------------------------------
 struct mclbm_nn {
-  int C = 0, depth = 0, ntubes = 0;
+  int C = 0, P = 0, S = 0, depth = 0, ntubes = 0;
   int64_t n = 0, ntiles = 0;
   hipStream_t stream = nullptr;
   std::string err;
@@ -536,6 +575,7 @@ struct mclbm_nn {
   int wG = 0;
   float* bpart = nullptr;               // bias-gradient partials [ntiles][WIDTH]
   double* dpart = nullptr;              // loss / residual partials
+  float* cond = nullptr;                // [ntubes][S] conditioning values
   float* fin = nullptr;                 // [C][n] input fields
   float* fout = nullptr;                // [C][n] predicted fields
 };
@@ -562,27 +602,31 @@ int nn_check(mclbm_nn* net, const char* what)
 }
 
 struct NNLayout {
-  size_t tubes, tile_tube, master, mom1, mom2, grad, wf, wb, bp, act, yout, dy, dyl, wpart, bpart, dpart, fin, fout, total;
+  size_t tubes, tile_tube, master, mom1, mom2, grad, wf, wb, bp, act, yout, dy, dyl, wpart, bpart, dpart, cond, fin, fout,
+      total;
   int64_t n, ntiles, nparam, nparam_p;
   int wG;
 };
 
-void layer_sizes(int C, int depth, std::vector<int>& in_r, std::vector<int>& out_r, std::vector<int>& in_p,
+void layer_sizes(int C, int P, int S, int depth, std::vector<int>& in_r, std::vector<int>& out_r, std::vector<int>& in_p,
                  std::vector<int>& out_p)
 {
   in_r.assign(depth, WIDTH);
   out_r.assign(depth, WIDTH);
   in_p.assign(depth, WIDTH);
   out_p.assign(depth, WIDTH);
-  in_r[0] = C;
+  in_r[0] = C + S;            // parameters; the second terms reuse the field weights
   in_p[0] = CIN0;
   out_r[depth - 1] = C;
   out_p[depth - 1] = COUTL;
 }
 
-int validate_nn(int C, int depth, const int32_t* dims, int ntubes, std::string& err)
+int validate_nn(int C, int P, int S, int depth, const int32_t* dims, int ntubes, std::string& err)
 {
-  if (C < 1 || C > MAXC) { err = "channels must be in 1..16"; return MCLBM_EARG; }
+  if (C < 1 || P < 0 || P > C || S < 0 || C + P + S > MAXC) {
+    err = "need channels >= 1, 0 <= two_term <= channels, conditioning >= 0, channels + two_term + conditioning <= 16";
+    return MCLBM_EARG;
+  }
   if (depth < 2 || depth > 16) { err = "depth must be in 2..16"; return MCLBM_EARG; }
   if (!dims || ntubes < 1) { err = "tube dimensions must be given"; return MCLBM_EARG; }
   int64_t tiles = 0;
@@ -596,7 +640,7 @@ int validate_nn(int C, int depth, const int32_t* dims, int ntubes, std::string& 
   return MCLBM_OK;
 }
 
-NNLayout nn_layout(int C, int depth, const int32_t* dims, int ntubes)
+NNLayout nn_layout(int C, int P, int S, int depth, const int32_t* dims, int ntubes)
 {
   NNLayout l{};
   l.n = 0;
@@ -607,7 +651,7 @@ NNLayout nn_layout(int C, int depth, const int32_t* dims, int ntubes)
     l.ntiles += (n + TILE - 1) / TILE;
   }
   std::vector<int> in_r, out_r, in_p, out_p;
-  layer_sizes(C, depth, in_r, out_r, in_p, out_p);
+  layer_sizes(C, P, S, depth, in_r, out_r, in_p, out_p);
   l.nparam = 0;
   l.nparam_p = 0;
   size_t wfb = 0, bpb = 0;
@@ -639,6 +683,7 @@ NNLayout nn_layout(int C, int depth, const int32_t* dims, int ntubes)
   l.wpart = take(sizeof(float) * (size_t)l.wG * NTAP * WIDTH * WIDTH);
   l.bpart = take(sizeof(float) * (size_t)l.ntiles * WIDTH);
   l.dpart = take(sizeof(double) * (size_t)l.ntiles * MAXC);
+  l.cond = take(sizeof(float) * (size_t)ntubes * (S > 0 ? S : 1));
   l.fin = take(sizeof(float) * (size_t)l.n * C);
   l.fout = take(sizeof(float) * (size_t)l.n * C);
   l.total = off;
@@ -666,7 +711,8 @@ int repack(mclbm_nn* net)
   for (int k = 0; k < net->depth; ++k) {
     const int total = NTAP * net->out_p[k] * net->in_p[k];
     hipLaunchKernelGGL(k_pack_w, dim3(blocks_for(total, 256)), dim3(256), 0, net->stream, net->master + net->w_off[k],
-                       net->out_r[k], net->in_r[k], net->out_p[k], net->in_p[k], net->wf[k], k > 0 ? net->wb[k] : nullptr);
+                       net->out_r[k], net->in_r[k], net->out_p[k], net->in_p[k], k == 0 ? net->C : net->in_r[k],
+                       k == 0 ? net->P : 0, net->wf[k], k > 0 ? net->wb[k] : nullptr);
     hipLaunchKernelGGL(k_pack_b, dim3(1), dim3(64), 0, net->stream, net->master + net->b_off[k], net->out_r[k],
                        net->out_p[k], net->bp[k]);
   }
@@ -691,7 +737,8 @@ void wgrad(mclbm_nn* net, const bf16* dY, const bf16* X, int layer)
   const int co_r = net->out_r[layer], ci_r = net->in_r[layer];
   const int n = NTAP * co_r * ci_r;
   hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks_for(n, 256)), dim3(256), 0, net->stream, net->wpart, net->wG,
-                     COUT, CINP, co_r, ci_r, net->grad + net->w_off[layer]);
+                     COUT, CINP, co_r, ci_r, layer == 0 ? net->C : ci_r, layer == 0 ? net->P : 0,
+                     net->grad + net->w_off[layer]);
 }
 
 void bgrad(mclbm_nn* net, const bf16* dY, int C, int layer)
@@ -707,38 +754,42 @@ void bgrad(mclbm_nn* net, const bf16* dY, int C, int layer)
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
-extern "C" size_t mclbm_nn_workspace_bytes(int32_t channels, int32_t depth, const int32_t* dims, int32_t ntubes)
+extern "C" size_t mclbm_nn_workspace_bytes(int32_t channels, int32_t two_term, int32_t conditioning, int32_t depth,
+                                           const int32_t* dims, int32_t ntubes)
 {
   std::string err;
-  if (validate_nn(channels, depth, dims, ntubes, err) != MCLBM_OK) {
+  if (validate_nn(channels, two_term, conditioning, depth, dims, ntubes, err) != MCLBM_OK) {
     g_nn_error = err;
     return 0;
   }
-  return nn_layout(channels, depth, dims, ntubes).total;
+  return nn_layout(channels, two_term, conditioning, depth, dims, ntubes).total;
 }
 
-extern "C" int mclbm_nn_create(int32_t channels, int32_t depth, const int32_t* dims, int32_t ntubes,
-                               void* dev_workspace, size_t bytes, void* hip_stream, mclbm_nn** out)
+extern "C" int mclbm_nn_create(int32_t channels, int32_t two_term, int32_t conditioning, int32_t depth,
+                               const int32_t* dims, int32_t ntubes, void* dev_workspace, size_t bytes,
+                               void* hip_stream, mclbm_nn** out)
 {
   if (!out) return nn_fail(nullptr, MCLBM_EARG, "out is NULL");
   *out = nullptr;
   std::string err;
-  int rc = validate_nn(channels, depth, dims, ntubes, err);
+  int rc = validate_nn(channels, two_term, conditioning, depth, dims, ntubes, err);
   if (rc) return nn_fail(nullptr, rc, err);
-  const NNLayout lay = nn_layout(channels, depth, dims, ntubes);
+  const NNLayout lay = nn_layout(channels, two_term, conditioning, depth, dims, ntubes);
   if (!dev_workspace) return nn_fail(nullptr, MCLBM_EARG, "workspace is NULL");
   if (((uintptr_t)dev_workspace) % ALIGN) return nn_fail(nullptr, MCLBM_EARG, "workspace must be 256-byte aligned");
   if (bytes < lay.total) return nn_fail(nullptr, MCLBM_EARG, "workspace too small");
   mclbm_nn* net = new (std::nothrow) mclbm_nn();
   if (!net) return nn_fail(nullptr, MCLBM_EARG, "out of host memory");
   net->C = channels;
+  net->P = two_term;
+  net->S = conditioning;
   net->depth = depth;
   net->ntubes = ntubes;
   net->n = lay.n;
   net->ntiles = lay.ntiles;
   net->stream = (hipStream_t)hip_stream;
   net->wG = lay.wG;
-  layer_sizes(channels, depth, net->in_r, net->out_r, net->in_p, net->out_p);
+  layer_sizes(channels, two_term, conditioning, depth, net->in_r, net->out_r, net->in_p, net->out_p);
   int64_t off = 0;
   for (int k = 0; k < depth; ++k) {
     net->w_off.push_back(off);
@@ -778,6 +829,7 @@ extern "C" int mclbm_nn_create(int32_t channels, int32_t depth, const int32_t* d
   net->wpart = (float*)(ws + lay.wpart);
   net->bpart = (float*)(ws + lay.bpart);
   net->dpart = (double*)(ws + lay.dpart);
+  net->cond = (float*)(ws + lay.cond);
   net->fin = (float*)(ws + lay.fin);
   net->fout = (float*)(ws + lay.fout);
   // tubes and the tile -> tube map
@@ -814,6 +866,8 @@ extern "C" int mclbm_nn_create(int32_t channels, int32_t depth, const int32_t* d
     // parameters, moments and gradients start at zero (set_params gives the weights)
     for (float* p : {net->master, net->mom1, net->mom2, net->grad})
       hipLaunchKernelGGL(k_zero, dim3(blocks_for(net->nparam, 256)), dim3(256), 0, net->stream, p, net->nparam);
+    const int64_t nc = (int64_t)ntubes * (conditioning > 0 ? conditioning : 1);
+    hipLaunchKernelGGL(k_zero, dim3(blocks_for(nc, 256)), dim3(256), 0, net->stream, net->cond, nc);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(net->stream);
@@ -889,6 +943,17 @@ extern "C" int mclbm_nn_set_norm(mclbm_nn* net, const float* in_shift, const flo
   return MCLBM_OK;
 }
 
+extern "C" int mclbm_nn_set_conditioning(mclbm_nn* net, const float* host)
+{
+  if (!net) return MCLBM_EARG;
+  if (!host) return nn_fail(net, MCLBM_EARG, "conditioning is NULL");
+  if (net->S == 0) return MCLBM_OK;
+  NN_TRY(net, hipMemcpyAsync(net->cond, host, sizeof(float) * net->ntubes * net->S, hipMemcpyHostToDevice,
+                             net->stream));
+  NN_TRY(net, hipStreamSynchronize(net->stream));
+  return MCLBM_OK;
+}
+
 extern "C" int mclbm_nn_io(mclbm_nn* net, float** fields_in, float** fields_out)
 {
   if (!net) return MCLBM_EARG;
@@ -902,7 +967,7 @@ extern "C" int mclbm_nn_forward(mclbm_nn* net)
   if (!net) return MCLBM_EARG;
   const unsigned grid = (unsigned)net->ntiles;
   hipLaunchKernelGGL(k_pack_in, dim3(grid), dim3(256), 0, net->stream, net->dTubes, net->dTileTube, net->ntubes,
-                     net->C, net->norm, net->fin, net->act[0]);
+                     net->C, net->P, net->S, net->norm, net->fin, net->cond, net->act[0]);
   const int D = net->depth;
   conv<CIN0, WIDTH, 0>(net, net->wf[0], net->bp[0], net->act[0], nullptr, net->act[1], 1);
   for (int k = 1; k + 1 < D; ++k) conv<WIDTH, WIDTH, 0>(net, net->wf[k], net->bp[k], net->act[k], nullptr, net->act[k + 1], 1);

@@ -45,7 +45,7 @@ EXPORTS = ["mclbm_workspace_bytes", "mclbm_batch_workspace_bytes", "mclbm_create
            "mclbm_autotune"]
 NN_EXPORTS = ["mclbm_nn_workspace_bytes", "mclbm_nn_create", "mclbm_nn_destroy", "mclbm_nn_last_error",
               "mclbm_nn_param_count", "mclbm_nn_set_params", "mclbm_nn_get_params", "mclbm_nn_get_grads",
-              "mclbm_nn_set_norm", "mclbm_nn_io", "mclbm_nn_forward", "mclbm_nn_loss", "mclbm_nn_backward",
+              "mclbm_nn_set_norm", "mclbm_nn_set_conditioning", "mclbm_nn_io", "mclbm_nn_forward", "mclbm_nn_loss", "mclbm_nn_backward",
               "mclbm_nn_zero_grad", "mclbm_nn_adam_step", "mclbm_nn_mole_residual", "mclbm_nn_advance"]
 
 
@@ -98,9 +98,11 @@ def _load():
     L.mclbm_autotune.argtypes = [vp, C.c_int32, C.c_char_p, C.c_size_t]
     ip = C.POINTER(C.c_int32)
     fp = C.POINTER(C.c_float)
-    L.mclbm_nn_workspace_bytes.argtypes = [C.c_int32, C.c_int32, ip, C.c_int32]
+    L.mclbm_nn_workspace_bytes.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, ip, C.c_int32]
     L.mclbm_nn_workspace_bytes.restype = C.c_size_t
-    L.mclbm_nn_create.argtypes = [C.c_int32, C.c_int32, ip, C.c_int32, vp, C.c_size_t, vp, C.POINTER(vp)]
+    L.mclbm_nn_create.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, ip, C.c_int32, vp, C.c_size_t, vp,
+                                  C.POINTER(vp)]
+    L.mclbm_nn_set_conditioning.argtypes = [vp, fp]
     L.mclbm_nn_destroy.argtypes = [vp]
     L.mclbm_nn_destroy.restype = None
     L.mclbm_nn_last_error.argtypes = [vp]
@@ -517,20 +519,27 @@ def _f32p(a):
     return a.ctypes.data_as(C.POINTER(C.c_float))
 
 
-def mclbm_nn_workspace_bytes(channels: int, depth: int, dims) -> int:
+def mclbm_nn_workspace_bytes(channels: int, two_term: int, conditioning: int, depth: int, dims) -> int:
     d, dp_ = _dims_array(dims)
-    n = lib.mclbm_nn_workspace_bytes(int(channels), int(depth), dp_, d.size // 3)
+    n = lib.mclbm_nn_workspace_bytes(int(channels), int(two_term), int(conditioning), int(depth), dp_, d.size // 3)
     if n == 0:
         raise MclbmError(MCLBM_EARG, lib.mclbm_nn_last_error(None).decode())
     return int(n)
 
 
-def mclbm_nn_create(channels: int, depth: int, dims, workspace_ptr: int, nbytes: int, stream: int):
+def mclbm_nn_create(channels: int, two_term: int, conditioning: int, depth: int, dims, workspace_ptr: int,
+                    nbytes: int, stream: int):
     d, dp_ = _dims_array(dims)
     h = C.c_void_p()
-    _nn_check(None, lib.mclbm_nn_create(int(channels), int(depth), dp_, d.size // 3, C.c_void_p(workspace_ptr),
-                                        nbytes, C.c_void_p(stream), C.byref(h)))
+    _nn_check(None, lib.mclbm_nn_create(int(channels), int(two_term), int(conditioning), int(depth), dp_,
+                                        d.size // 3, C.c_void_p(workspace_ptr), nbytes, C.c_void_p(stream),
+                                        C.byref(h)))
     return h
+
+
+def mclbm_nn_set_conditioning(net, values: np.ndarray) -> None:
+    a = np.ascontiguousarray(values, dtype=np.float32)
+    _nn_check(net, lib.mclbm_nn_set_conditioning(net, _f32p(a)))
 
 
 def mclbm_nn_destroy(net) -> None:
@@ -617,21 +626,24 @@ class Net:
     fields_in / fields_out are views of the network's own device buffers
     ([channels][n] per tube, concatenated)."""
 
-    def __init__(self, channels: int, depth: int, dims, device: str = "cuda:0", stream=None):
+    def __init__(self, channels: int, depth: int, dims, conditioning: int = 0, two_term: int = 0,
+                 device: str = "cuda:0", stream=None):
         import torch
 
         self.C = int(channels)
+        self.P = int(two_term)
+        self.S = int(conditioning)
         self.depth = int(depth)
         self.dims = [tuple(int(v) for v in d) for d in dims]
         self.sizes = [nx * ny * nz for nx, ny, nz in self.dims]
         self.n = int(sum(self.sizes))
         self.device = torch.device(device)
-        nbytes = mclbm_nn_workspace_bytes(self.C, self.depth, self.dims)
+        nbytes = mclbm_nn_workspace_bytes(self.C, self.P, self.S, self.depth, self.dims)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         with torch.cuda.device(self.device):
-            self.net = mclbm_nn_create(self.C, self.depth, self.dims, self.workspace.data_ptr(), nbytes,
-                                       self.stream.cuda_stream)
+            self.net = mclbm_nn_create(self.C, self.P, self.S, self.depth, self.dims, self.workspace.data_ptr(),
+                                       nbytes, self.stream.cuda_stream)
         pin, pout = mclbm_nn_io(self.net)
         base = self.workspace.data_ptr()
         count = self.C * self.n
@@ -666,6 +678,10 @@ class Net:
 
     def set_norm(self, in_shift, in_scale, out_scale):
         mclbm_nn_set_norm(self.net, in_shift, in_scale, out_scale)
+
+    def set_conditioning(self, values):
+        """values: [ntubes][conditioning] floats."""
+        mclbm_nn_set_conditioning(self.net, values)
 
     def forward(self, fields=None):
         """fields: a CUDA float32 tensor of channels * n values (copied in), or None

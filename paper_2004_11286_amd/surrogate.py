@@ -1,0 +1,262 @@
+"""The learned surrogate end to end: trajectories from a batched ensemble of
+tubes, normalisation from the data, training, and evaluation against the
+lattice Boltzmann step (the judge of its error).
+
+Only orchestration lives here: every field read-back, forward and backward
+pass, loss, optimiser step, residual and lattice step is a call into the C ABI
+of libmclbm (include/mclbm.h, include/mclbm_nn.h); torch holds the snapshot
+tensors on the device.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import mclbm as mc
+
+DEPTH = 6
+K_DEFAULT = 100
+LR = 5e-4
+
+
+def channels(M: int) -> int:
+    return M + 4                      # X_1..X_M, T, u_x, u_y, u_z
+
+
+def conditioning(params: dict) -> np.ndarray:
+    """Per-tube constants the evolution depends on but the fields do not show:
+    molar masses / 40 and the off-diagonal diffusivities / 0.1."""
+    M = int(params["M"])
+    m = np.asarray(params["molar_mass"], dtype=np.float64) / 40.0
+    D = np.asarray(params["D"], dtype=np.float64)
+    iu = np.triu_indices(M, 1)
+    return np.concatenate([m, D[iu] / 0.1]).astype(np.float32)
+
+
+def trajectories(tubes: list, K: int = K_DEFAULT, nsnap: int = 50, precision: int = mc.MCLBM_FP32):
+    """Run the tubes as one batched context and keep the FP32 fields every K
+    steps: a device tensor [nsnap + 1][(M+4) n] and the tube sizes."""
+    import torch
+
+    b = mc.Batch([p for p, _ in tubes], precision)
+    b.init_fields([f for _, f in tubes])
+    C = channels(b.M)
+    snaps = torch.empty((nsnap + 1, C * b.n), dtype=torch.float32, device=b.device)
+    b.read_fields_f32(out=snaps[0])
+    for j in range(nsnap):
+        b.step(K)
+        b.read_fields_f32(out=snaps[j + 1])
+    torch.cuda.synchronize()
+    dims = [(s[2], s[1], s[0]) for s in b.shapes]
+    b.close()
+    return snaps, dims
+
+
+def channel_stats(snaps, dims, C: int):
+    """Per-channel mean and standard deviation of the fields and of their change
+    over one interval (host, from a subsample of nodes)."""
+    x = snaps.cpu().numpy()
+    sizes = [nx * ny * nz for nx, ny, nz in dims]
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    per_c = [[] for _ in range(C)]
+    per_d = [[] for _ in range(C)]
+    for t, n in enumerate(sizes):
+        seg = x[:, C * off[t]:C * off[t + 1]].reshape(x.shape[0], C, n)[:, :, ::max(1, n // 256)]
+        for c in range(C):
+            per_c[c].append(seg[:, c].ravel())
+            per_d[c].append((seg[1:, c] - seg[:-1, c]).ravel())
+    mean = np.array([np.concatenate(v).mean() for v in per_c])
+    std = np.array([np.concatenate(v).std() for v in per_c])
+    dstd = np.array([np.concatenate(v).std() for v in per_d])
+    return mean, std, dstd
+
+
+IN_FLOOR = 1e-3      # smallest input spread used for scaling (T and u vary by ~1e-3)
+OUT_FLOOR = 1e-4     # smallest output unit (a channel that never changes, e.g. u_y in a 1-D tube)
+
+
+def norm_from_stats(mean, std, dstd):
+    """Inputs to zero mean and unit spread, outputs in units of the typical
+    change; floors keep channels that (almost) never vary from being blown up
+    to round-off."""
+    in_scale = 1.0 / np.maximum(std, IN_FLOOR)
+    out_scale = np.maximum(dstd, OUT_FLOOR)
+    return {"in_shift": mean.astype(np.float32), "in_scale": in_scale.astype(np.float32),
+            "out_scale": out_scale.astype(np.float32)}
+
+
+def he_init(C: int, S: int, depth: int, seed: int) -> np.ndarray:
+    """He-normal weights for the ReLU layers, a small last layer, zero biases
+    (host order of include/mclbm_nn.h)."""
+    rng = np.random.default_rng(seed)
+    width = 64
+    ins = [C + S] + [width] * (depth - 1)
+    outs = [width] * (depth - 1) + [C]
+    parts = []
+    for k, (o, i) in enumerate(zip(outs, ins)):
+        std = np.sqrt(2.0 / (27 * i)) * (1.0 if k < depth - 1 else 0.1)
+        parts += [rng.normal(0.0, std, 27 * o * i), np.zeros(o)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def build_net(dims, tubes_params, norm, M: int, depth: int = DEPTH, params=None, seed: int = 0):
+    """The surrogate over these tubes: the M mole fractions also as second BF16
+    terms, the tube constants as conditioning channels."""
+    C = channels(M)
+    cond = np.stack([conditioning(p) for p in tubes_params])
+    net = mc.Net(C, depth, dims, conditioning=cond.shape[1], two_term=M)
+    net.set_conditioning(cond)
+    net.set_norm(norm["in_shift"], norm["in_scale"], norm["out_scale"])
+    net.set_params(he_init(C, cond.shape[1], depth, seed) if params is None else params)
+    return net
+
+
+def channel_weights(M: int) -> np.ndarray:
+    """The mole fractions are what the surrogate is judged on."""
+    return np.array([1.0] * M + [0.2] + [0.1] * 3, dtype=np.float32)
+
+
+def pair_weights(snaps, dims, out_scale, M: int, floor: float = 1e-2) -> np.ndarray:
+    """Channel weights per snapshot pair: for the mole fractions, the base weight
+    divided by the pair's mean squared change in output units, so that late, slow
+    intervals count as much as early ones (a relative error); T and u keep their
+    base weights. Returns [nsnap][C]."""
+    x = snaps.cpu().numpy()
+    C = channels(M)
+    sizes = [nx * ny * nz for nx, ny, nz in dims]
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    base = channel_weights(M).astype(np.float64)
+    out = np.zeros((x.shape[0] - 1, C), dtype=np.float32)
+    for j in range(x.shape[0] - 1):
+        acc = np.zeros(C)
+        cnt = 0
+        for t, n in enumerate(sizes):
+            a = x[j, C * off[t]:C * off[t + 1]].reshape(C, n)[:, ::max(1, n // 256)].astype(np.float64)
+            b = x[j + 1, C * off[t]:C * off[t + 1]].reshape(C, n)[:, ::max(1, n // 256)].astype(np.float64)
+            acc += np.sum(((b - a) / np.asarray(out_scale, np.float64)[:, None]) ** 2, axis=1)
+            cnt += a.shape[1]
+        ms = acc / cnt
+        w = base.copy()
+        w[:M] = base[:M] / np.maximum(ms[:M], floor)
+        out[j] = w.astype(np.float32)
+    return out
+
+
+def train(net, snaps, iters: int, lr: float = LR, seed: int = 0, log_every: int = 0, weights=None):
+    """Adam on random (t, t + K) snapshot pairs of all tubes at once, with a
+    cosine learning-rate decay. weights: per-pair channel weights [nsnap][C]
+    (default: the base channel weights). Returns the loss history."""
+    rng = np.random.default_rng(seed)
+    base = channel_weights(net.C - 4)
+    losses = []
+    nsnap = snaps.shape[0] - 1
+    for it in range(iters):
+        j = int(rng.integers(0, nsnap))
+        w = base if weights is None else weights[j]
+        net.fields_in.copy_(snaps[j])
+        net.forward()
+        losses.append(net.loss(snaps[j + 1], w))
+        net.backward()
+        lr_it = lr * 0.5 * (1.0 + np.cos(np.pi * it / iters)) + 0.02 * lr
+        net.adam_step(lr_it)
+        if log_every and (it + 1) % log_every == 0:
+            print(f"  iter {it + 1}: loss {np.mean(losses[-log_every:]):.4g}", flush=True)
+    return losses
+
+
+def evaluate(params, norm, eval_tubes, K: int = K_DEFAULT, starts=(0, 500, 2000), depth: int = DEPTH,
+             resid_tol: float = 1e-4):
+    """Judge the surrogate by the lattice: from the same state at each start
+    time, K lattice steps against one network hop. Reports the mole-fraction
+    error (L-infinity over all tubes), that of the persistence prediction (no
+    change), the mole residual, and the times of the hop (read, forward, residual
+    and re-initialisation through mclbm_nn_advance) and of the K lattice steps."""
+    import torch
+
+    b = mc.Batch([p for p, _ in eval_tubes], mc.MCLBM_FP32)
+    ref = mc.Batch([p for p, _ in eval_tubes], mc.MCLBM_FP32)
+    dims = [(s[2], s[1], s[0]) for s in b.shapes]
+    M = b.M
+    C = channels(M)
+    net = build_net(dims, [p for p, _ in eval_tubes], norm, M, depth, params)
+    fields = [f for _, f in eval_tubes]
+    out = []
+    for t0 in starts:
+        for x in (b, ref):
+            x.init_fields(fields)
+            x.step(t0)
+        # lattice reference: K steps, timed on the stream
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start = ref.read_fields_f32().clone()
+        e0.record(ref.stream)
+        ref.step(K)
+        e1.record(ref.stream)
+        e1.synchronize()
+        t_lbm = e0.elapsed_time(e1)
+        want = ref.read_fields_f32().clone()
+        # network prediction from the same state (forward only, for the error)
+        net.fields_in.copy_(start)
+        net.forward()
+        torch.cuda.synchronize()
+        pred = net.fields_out.clone()
+        res = net.mole_residual(M, start, pred)
+        # the advance entry point end to end (timed on the stream)
+        e0.record(b.stream)
+        used, res_adv = net.advance(b, K, resid_tol)
+        e1.record(b.stream)
+        e1.synchronize()
+        t_adv = e0.elapsed_time(e1)
+        # forward pass alone
+        e0.record(net.stream)
+        net.forward()
+        e1.record(net.stream)
+        e1.synchronize()
+        t_fwd = e0.elapsed_time(e1)
+
+        def xerr(a):
+            ea, eb = a.cpu().numpy(), want.cpu().numpy()
+            errs = []
+            off = 0
+            for nx, ny, nz in dims:
+                n = nx * ny * nz
+                A = ea[C * off:C * (off + n)].reshape(C, n)
+                B = eb[C * off:C * (off + n)].reshape(C, n)
+                errs.append(np.abs(A[:M] - B[:M]).max())
+                off += n
+            return float(max(errs))
+
+        out.append({"t0": int(t0), "K": int(K), "X_linf": xerr(pred), "X_linf_persistence": xerr(start),
+                     "mole_residual_max": float(np.max(res)), "accepted": not used,
+                     "ms_lattice": t_lbm, "ms_advance": t_adv, "ms_forward": t_fwd})
+    net.close()
+    b.close()
+    ref.close()
+    return out
+
+
+def conv_flops_per_node(C: int, S: int, depth: int = DEPTH, width: int = 64) -> float:
+    """Multiply-adds x 2 of one forward pass per node over the real input
+    channels of layer 0 (fields, second terms and conditioning: C + S)."""
+    ins = [C + S] + [width] * (depth - 1)
+    outs = [width] * (depth - 1) + [C]
+    return float(sum(2 * 27 * o * i for o, i in zip(outs, ins)))
+
+
+def timed_train_step(net, snaps, reps: int = 5):
+    """Milliseconds of one forward + loss + backward + Adam step (mean of reps)."""
+    import torch
+
+    w = channel_weights(net.C - 4)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    net.fields_in.copy_(snaps[0])
+    t0 = time.perf_counter()
+    e0.record(net.stream)
+    for _ in range(reps):
+        net.forward()
+        net.loss(snaps[1], w)
+        net.backward()
+        net.adam_step(1e-6)
+    e1.record(net.stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps, (time.perf_counter() - t0) * 1e3 / reps

@@ -112,11 +112,13 @@ def test_launch_struct_matches_header():
 def test_nn_workspace_and_validation():
     m = pytest.importorskip("paper_2004_11286_amd.mclbm")
     dims = [(13, 4, 3), (40, 2, 5)]
-    b = m.mclbm_nn_workspace_bytes(7, 6, dims)
+    b = m.mclbm_nn_workspace_bytes(7, 0, 0, 6, dims)
     n = 13 * 12 + 40 * 10
     assert b > 5 * n * 64 * 2                     # the hidden activations dominate
-    assert b < m.mclbm_nn_workspace_bytes(7, 6, dims + [(64, 8, 8)])
-    for bad in [(0, 6, dims), (17, 6, dims), (7, 1, dims), (7, 6, [(0, 4, 4)])]:
+    assert b < m.mclbm_nn_workspace_bytes(7, 0, 0, 6, dims + [(64, 8, 8)])
+    assert m.mclbm_nn_workspace_bytes(7, 3, 6, 6, dims) >= b
+    for bad in [(0, 0, 0, 6, dims), (17, 0, 0, 6, dims), (7, 0, 10, 6, dims), (7, 8, 0, 6, dims),
+                (7, 3, 7, 6, dims), (7, 0, 0, 1, dims), (7, 0, 0, 6, [(0, 4, 4)])]:
         with pytest.raises(m.MclbmError):
             m.mclbm_nn_workspace_bytes(*bad)
 
@@ -126,3 +128,4 @@ def test_nn_param_count_matches_the_oracle():
     from oracle import surrogate_oracle as S
 
     assert S.param_count(7, 6) == 27 * (7 * 64 + 4 * 64 * 64 + 64 * 7) + 5 * 64 + 7
+    assert S.param_count(7, 6, S=6) == 27 * (13 * 64 + 4 * 64 * 64 + 64 * 7) + 5 * 64 + 7

@@ -48,9 +48,11 @@ def norm_arrays(seed=0):
             "out_scale": rng.uniform(0.5, 2.0, C)}
 
 
-def make_net(env, depth, params, norm, dims=DIMS):
+def make_net(env, depth, params, norm, dims=DIMS, cond=None, two_term=0):
     mc, torch = env
-    net = mc.Net(C, depth, dims)
+    net = mc.Net(C, depth, dims, conditioning=0 if cond is None else len(cond[0]), two_term=two_term)
+    if cond is not None:
+        net.set_conditioning(np.asarray(cond, np.float32))
     net.set_params(params)
     net.set_norm(norm["in_shift"], norm["in_scale"], norm["out_scale"])
     return net
@@ -89,14 +91,43 @@ def test_forward_matches_oracle(env, depth, bound):
         assert err < bound, (t, err)
 
 
-def test_loss_and_gradients_match_oracle(env):
+def test_forward_with_conditioning_matches_oracle(env):
+    """Three second input terms and six per-tube constants as extra input
+    channels of layer 0."""
+    depth, Sn, Pn = 3, 6, 3
+    p = S.he_init(C, depth, seed=21, S=Sn)
+    p += np.random.default_rng(5).normal(0, 0.01, p.size).astype(np.float32)
+    nm = norm_arrays(3)
+    cond = np.random.default_rng(6).uniform(-1, 1, (len(DIMS), Sn)).astype(np.float32)
+    net = make_net(env, depth, p, nm, cond=cond, two_term=Pn)
+    fs = [f.astype(np.float32).astype(np.float64) for f in random_fields(12)]
+    out = net.forward(flat(env, fs)).cpu().numpy()
+    net.close()
+    nm64 = {k: np.asarray(v, np.float32).astype(np.float64) for k, v in nm.items()}
+    for t, (f, g) in enumerate(zip(fs, split(out))):
+        y_ref, _, _ = S.forward(p, f, nm64, C, depth, round_bf16=True, cond=cond[t].astype(np.float64), P=Pn)
+        y_gpu = (g - f.astype(np.float32)) / nm64["out_scale"][:, None, None, None]
+        err = np.abs(y_gpu - y_ref).max() / np.abs(y_ref).max()
+        print("conditioned forward tube", t, "rel linf", err)
+        assert err < 5e-3, (t, err)
+    # the conditioning matters: the same fields with other constants give another output
+    net2 = make_net(env, depth, p, nm, cond=-cond, two_term=Pn)
+    out2 = net2.forward(flat(env, fs)).cpu().numpy()
+    net2.close()
+    assert np.abs(out2 - out).max() > 1e-3
+
+
+@pytest.mark.parametrize("Pn,Sn", [(0, 0), (3, 6)])
+def test_loss_and_gradients_match_oracle(env, Pn, Sn):
+    """Including the tied second terms and the conditioning channels of layer 0."""
     _, torch = env
     depth = 4
-    p = S.he_init(C, depth, seed=7, gain=1.0)
+    p = S.he_init(C, depth, seed=7, gain=1.0, S=Sn)
     p += np.random.default_rng(2).normal(0, 0.02, p.size).astype(np.float32)
     nm = norm_arrays(1)
     nm64 = {k: np.asarray(v, np.float32).astype(np.float64) for k, v in nm.items()}
-    net = make_net(env, depth, p, nm)
+    cond = np.random.default_rng(3).uniform(-1, 1, (len(DIMS), Sn)).astype(np.float32) if Sn else None
+    net = make_net(env, depth, p, nm, cond=cond, two_term=Pn)
     fs = [f.astype(np.float32).astype(np.float64) for f in random_fields(3)]
     rng = np.random.default_rng(4)
     tg = [(f + 0.05 * rng.normal(size=f.shape)).astype(np.float32).astype(np.float64) for f in fs]
@@ -107,11 +138,12 @@ def test_loss_and_gradients_match_oracle(env):
     net.backward()
     g_gpu = net.get_grads().astype(np.float64)
     net.close()
-    L_ref, g_ref = S.loss_and_grad(p, fs, tg, nm64, C, depth, weight=w.astype(np.float64), round_bf16=True)
+    L_ref, g_ref = S.loss_and_grad(p, fs, tg, nm64, C, depth, weight=w.astype(np.float64), round_bf16=True,
+                                   tubes_cond=None if cond is None else [c.astype(np.float64) for c in cond], P=Pn)
     print("loss", loss, L_ref)
     assert loss == pytest.approx(L_ref, rel=5e-3)
     k = 0
-    for li, (o, i) in enumerate(S.layer_shapes(C, depth)):
+    for li, (o, i) in enumerate(S.layer_shapes(C, depth, S=Sn)):
         for name, size in (("W", 27 * o * i), ("b", o)):
             a, b = g_gpu[k:k + size], g_ref[k:k + size]
             k += size
@@ -211,3 +243,32 @@ def test_advance_with_a_null_network_keeps_the_fields(env):
     np.testing.assert_allclose(after["u"], before["u"], atol=1e-7)
     net.close()
     s.close()
+
+
+def test_trained_on_lattice_trajectories(env):
+    """End to end on a small ensemble: trajectories from one batched context,
+    training by the library's kernels, then judged by the lattice on held-out
+    tubes. The trained network must beat the persistence prediction (no change)
+    where the fields change most (the first interval) and its forward pass must
+    be faster than the K lattice steps it replaces; the advance entry point must
+    fall back to the lattice whenever the mole residual exceeds the tolerance."""
+    from paper_2004_11286_amd import surrogate as SG
+
+    mc, torch = env
+    train_tubes = W.tube_ensemble(ntubes=32, ny=4, nz=4, seed=11286)
+    snaps, dims = SG.trajectories(train_tubes, K=100, nsnap=20)
+    mean, std, dstd = SG.channel_stats(snaps, dims, C)
+    norm = SG.norm_from_stats(mean, std, dstd)
+    net = SG.build_net(dims, [p for p, _ in train_tubes], norm, 3)
+    pw = SG.pair_weights(snaps, dims, norm["out_scale"], 3)
+    losses = SG.train(net, snaps, 1500, lr=3e-4, weights=pw)
+    params = net.get_params()
+    net.close()
+    print("loss", np.mean(losses[:50]), "->", np.mean(losses[-50:]))
+    assert np.mean(losses[-100:]) < 0.5 * np.mean(losses[:100])
+    eval_tubes = W.tube_ensemble(ntubes=4, ny=8, nz=8, lmin=128, lmax=128, seed=2025)
+    res = SG.evaluate(params, norm, eval_tubes, K=100, starts=(0,), resid_tol=1e-4)[0]
+    print(res)
+    assert res["X_linf"] < 0.7 * res["X_linf_persistence"]
+    assert res["ms_forward"] < res["ms_lattice"]
+    assert res["accepted"] == (res["mole_residual_max"] <= 1e-4)

@@ -98,6 +98,37 @@ def test_loss_gradient_matches_central_differences():
         assert g[k] == pytest.approx(fd, rel=1e-5, abs=1e-9), k
 
 
+def test_gradient_with_second_terms_and_conditioning():
+    """Tied second-term weights and conditioning channels: the folded gradient
+    still matches central differences."""
+    C, depth, width, P = 3, 3, 4, 2
+    fs, tg, norm, _ = _tiny_problem(C=C, depth=depth, width=width)
+    cond = [np.array([0.3, -0.7]), np.array([1.1, 0.2])]
+    p = S.he_init(C, depth, 9, width=width, gain=3.0, S=2).astype(np.float64)
+    p += 0.1 * np.random.default_rng(10).normal(size=p.size)
+    L, g = S.loss_and_grad(p, fs, tg, norm, C, depth, width, tubes_cond=cond, P=P)
+    idx = list(range(0, 27 * width * (C + 2), 7))[:40]          # layer-0 weights, all column kinds
+    h = 1e-6
+    for k in idx:
+        pp, pm = p.copy(), p.copy()
+        pp[k] += h
+        pm[k] -= h
+        Lp, _ = S.loss_and_grad(pp, fs, tg, norm, C, depth, width, tubes_cond=cond, P=P)
+        Lm, _ = S.loss_and_grad(pm, fs, tg, norm, C, depth, width, tubes_cond=cond, P=P)
+        assert g[k] == pytest.approx((Lp - Lm) / (2 * h), rel=1e-5, abs=1e-9), k
+
+
+def test_second_terms_carry_the_fields_exactly():
+    """With tied weights, a layer-0 output equals the convolution of hi + lo / 256."""
+    rng = np.random.default_rng(11)
+    v = rng.normal(size=(3, 2, 3, 5))
+    W = rng.normal(size=(27, 4, 3))
+    hi, lo = S.two_term(v)
+    a = np.concatenate([hi, lo])
+    np.testing.assert_allclose(S.conv(a, S.expand_first(W, 3, 3), None), S.conv(hi + lo / 256, W, None),
+                               rtol=1e-12, atol=1e-12)
+
+
 def test_loss_is_zero_for_a_perfect_prediction():
     """All weights zero and the target equal to the fields: y = 0 = r."""
     C, depth, width = 3, 3, 4
@@ -140,3 +171,13 @@ def test_mole_residual_definition():
     c = a.copy()
     c[3] *= 2.0                                   # doubling T halves every species' moles
     assert S.mole_residual(a, c, 3) == pytest.approx(0.5, rel=1e-12)
+
+
+def test_two_term_encoding_resolves_16_bits():
+    rng = np.random.default_rng(7)
+    v = rng.normal(0, 2, 10000)
+    hi, lo = S.two_term(v)
+    v32 = v.astype(np.float32).astype(np.float64)
+    assert np.all(S.bf16(hi) == hi) and np.all(S.bf16(lo) == lo)
+    assert np.abs(v32 - hi).max() <= np.abs(v32).max() * 2 ** -8          # one term: ~8 bits
+    assert np.all(np.abs(v32 - (hi + lo / 256)) <= np.abs(v32) * 2 ** -15)  # two terms: ~16 bits
