@@ -84,6 +84,27 @@ def measured_traffic(kernel: str, precision: str):
     return float(vals["hbm_bytes_per_launch"])
 
 
+def copy_ceiling_gbs(gib: int = 4, reps: int = 10) -> float:
+    """Read + write bandwidth of a plain device-to-device copy (the runtime's copy
+    kernel), the practical streaming ceiling next to the 8 TB/s peak."""
+    import torch
+
+    n = gib << 28
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 8.0 * n / (ms * 1e-3) / 1e9
+
+
 def time_run(mc, params, fields, precision, steps, warmup):
     import torch
 
@@ -178,6 +199,63 @@ def ensemble_bench(mc, steps: int = 50, seq_steps: int = 10, trial_steps: int = 
     return out
 
 
+BF16_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix-core peak
+
+
+def surrogate_bench(train_iters: int = 3000):
+    """The learned surrogate: trained by the library's BF16 MFMA kernels on
+    trajectories of a 64-tube ensemble (every 100 steps up to 5000), then judged
+    by the lattice on eight held-out 128 x 32 x 32 ternary tubes (1 M nodes):
+    mole-fraction L-infinity error of one 100-step hop, the same for the
+    persistence prediction, the mole residual and whether the advance entry
+    point accepted the hop (residual <= 1e-4) or fell back to the lattice, and
+    the times of the forward pass, of the whole advance and of the 100 lattice
+    steps. The conv roofline: forward FLOP / forward time against the BF16 peak."""
+    from paper_2004_11286_amd import surrogate as SG
+    from paper_2004_11286_amd import workloads as W
+
+    t0 = time.perf_counter()
+    train_tubes = W.tube_ensemble(ntubes=64, ny=4, nz=4, seed=11286)
+    snaps, dims = SG.trajectories(train_tubes, K=100, nsnap=50)
+    M = 3
+    C = SG.channels(M)
+    mean, std, dstd = SG.channel_stats(snaps, dims, C)
+    norm = SG.norm_from_stats(mean, std, dstd)
+    net = SG.build_net(dims, [p for p, _ in train_tubes], norm, M)
+    ms_train_step, _ = SG.timed_train_step(net, snaps)
+    net.set_params(SG.he_init(C, 6, SG.DEPTH, 0))
+    pw = SG.pair_weights(snaps, dims, norm["out_scale"], M)
+    losses = SG.train(net, snaps, train_iters, lr=3e-4, weights=pw)
+    params = net.get_params()
+    n_train = sum(a * b * c for a, b, c in dims)
+    net.close()
+    del snaps
+    train_s = time.perf_counter() - t0
+    eval_tubes = W.tube_ensemble(ntubes=8, ny=32, nz=32, lmin=128, lmax=128, seed=2025)
+    res = SG.evaluate(params, norm, eval_tubes, K=100, starts=(0, 1000), resid_tol=1e-4)
+    n_eval = sum(p["nx"] * p["ny"] * p["nz"] for p, _ in eval_tubes)
+    flops = SG.conv_flops_per_node(C, M + 6) * n_eval
+    ms_fwd = float(np.median([r["ms_forward"] for r in res]))
+    achieved = flops / (ms_fwd * 1e-3) / 1e12
+    train_flops = 3 * SG.conv_flops_per_node(C, M + 6) * n_train
+    return {
+        "workload": "train: 64 ternary tubes L~U{32..256}x4x4, 50 snapshots every 100 steps; "
+                    "apply: 8 held-out ternary tubes 128x32x32, one 100-step hop",
+        "network": {"layers": SG.DEPTH, "width": 64, "kernel": "3x3x3", "params": int(params.size),
+                    "input": "X_a, T, u (+ second BF16 terms of X_a, 6 tube constants)",
+                    "dtype": "bf16 weights/activations, fp32 accumulate"},
+        "train": {"iters": train_iters, "seconds": train_s, "loss_first100": float(np.mean(losses[:100])),
+                  "loss_last100": float(np.mean(losses[-100:])), "ms_per_step": ms_train_step,
+                  "TFLOPs_per_step_approx": train_flops / (ms_train_step * 1e-3) / 1e12},
+        "eval": res,
+        "speedup_forward_vs_lattice": float(np.median([r["ms_lattice"] / r["ms_forward"] for r in res])),
+        "speedup_advance_vs_lattice": float(np.median([r["ms_lattice"] / r["ms_advance"] for r in res])),
+        "roofline_conv_forward": {"bound": "mfma", "achieved": achieved, "peak": BF16_PEAK_TFLOPS,
+                                  "unit": "TFLOP/s", "frac": achieved / BF16_PEAK_TFLOPS,
+                                  "flop_per_node": SG.conv_flops_per_node(C, M + 6), "nodes": n_eval},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,6 +266,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--surrogate-iters", type=int, default=3000)
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes five times (to scale HBM counters)")
     args = ap.parse_args()
@@ -216,6 +296,7 @@ def main():
         print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "copies": 5,
                           "GBs_read_plus_write": 2 * nbytes / el / 1e9}))
         return
+    copy_gbs = copy_ceiling_gbs()
     params, fields = W.shear_layer(nx=args.n, ny=args.n, nz=args.n)
     M = params["M"]
     n = args.n ** 3
@@ -254,6 +335,7 @@ def main():
             torch.cuda.empty_cache()
 
     ensemble = None if args.no_ensemble else ensemble_bench(mc)
+    surrogate = None if args.no_surrogate else surrogate_bench(args.surrogate_iters)
     cpu = None if args.no_cpu else cpu_baseline()
     out = {
         "metric": "D3Q27 mixture MLUPS & % HBM roofline; FP16-store and surrogate vs FP32 plain",
@@ -276,7 +358,8 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic("k_collide", args.precision),
                      "algorithmic_bytes_per_node": ab["k_collide"],
-                     "algorithmic_bytes_per_launch": ab["k_collide"] * n},
+                     "algorithmic_bytes_per_launch": ab["k_collide"] * n,
+                     "plain_copy_GBs": copy_gbs, "frac_of_plain_copy": achieved / copy_gbs},
         "kernels": {k: {"avg_ms": v["avg_ms"], "launches": v["launches"], "GBs": kernel_gbs[k],
                         "algorithmic_bytes_per_node": ab[k]} for k, v in stats.items()},
         "step_effective_GBs": {"step_bytes_per_node": ab["step"], "GBs": ab["step"] * mlups * 1e6 / 1e9,
@@ -284,6 +367,7 @@ def main():
                                "method_min_frac": ab["method_min"] * mlups * 1e6 / 1e9 / HBM_PEAK_GBS},
         "variants": variants,
         "ensemble": ensemble,
+        "surrogate": surrogate,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

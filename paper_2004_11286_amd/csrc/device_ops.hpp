@@ -1,5 +1,6 @@
 // device_ops.hpp -- gfx950 device primitives used by the node functions:
-// stochastic-rounding conversions to 16-bit storage and a compiler barrier.
+// stochastic-rounding conversions to 16-bit storage, streaming loads and a
+// compiler barrier.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -27,6 +28,12 @@ __device__ inline __bf16 cvt_sr_bf16(float x, uint32_t rnd)
   o = __builtin_amdgcn_cvt_sr_bf16_f32(o, x, rnd, false);
   return o[0];
 }
+
+// Load of a value that is read once and not again soon (the populations a
+// collision consumes): a nontemporal load, which keeps the caches for the
+// neighbour stencils of the node records.
+template <typename T>
+__device__ inline T stream_load(const T* p) { return __builtin_nontemporal_load(p); }
 
 // Compiler barrier between the lattices of a node: loads after it are not hoisted
 // above it, which bounds the loads (and registers) a thread keeps in flight.

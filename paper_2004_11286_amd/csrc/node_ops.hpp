@@ -559,7 +559,7 @@ __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const 
       Rng rng(node, a, step);
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
-        v[i] = src[(size_t)(a * Q + i) * n + node];
+        v[i] = stream_load(&src[(size_t)(a * Q + i) * n + node]);
         t0 += from_store<S, R>(P, a, v[i]);
       }
 #pragma unroll
@@ -599,7 +599,7 @@ __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const 
     Rng rng(node, LF, step);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      v[i] = src[(size_t)(LF * Q + i) * n + node];
+      v[i] = stream_load(&src[(size_t)(LF * Q + i) * n + node]);
       const R d = from_store<S, R>(P, LF, v[i]);
       t0 += d;
       acc_c(t1[0], cx(i), d);
@@ -680,7 +680,7 @@ __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const 
     Rng rng(node, LG, step);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      v[i] = src[(size_t)(LG * Q + i) * n + node];
+      v[i] = stream_load(&src[(size_t)(LG * Q + i) * n + node]);
       t0 += from_store<S, R>(P, LG, v[i]);
     }
 #pragma unroll
