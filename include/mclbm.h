@@ -133,8 +133,8 @@ int mclbm_read_moments(mclbm_ctx *c, double *X, double *rho, double *u, double *
  * non-finite value or a negative slaved density. Synchronises the stream. */
 int mclbm_conservation(mclbm_ctx *c, double *out);
 
-/* The fields a trajectory keeps, in FP32: out [M+4][n] per tube (X_1 .. X_M, T,
- * u_x, u_y, u_z), concatenated over tubes. on_device as in mclbm_init_fields.
+/* The fields a trajectory keeps, in FP32: out [M+5][n] per tube (X_1 .. X_M, T,
+ * u_x, u_y, u_z, p), concatenated over tubes. on_device as in mclbm_init_fields.
  * Synchronises the stream. */
 int mclbm_read_fields_f32(mclbm_ctx *c, float *out, int on_device);
 

@@ -49,10 +49,10 @@ extern "C" {
 
 typedef struct mclbm_nn mclbm_nn;
 
-/* Workspace bytes of a network with `channels` field components C, `two_term`
- * of them (the leading ones) also given as a second term P, `conditioning`
- * per-tube constants S (C + P + S <= 16, P <= C), `depth` conv layers (2..16)
- * over ntubes tubes, dims = [ntubes][3] (nx, ny, nz). */
+/* Workspace bytes of a network with `channels` field components C (<= 16),
+ * `two_term` of them (the leading ones) also given as a second term P (<= C),
+ * `conditioning` per-tube constants S (C + P + S <= 32), `depth` conv layers
+ * (2..16) over ntubes tubes, dims = [ntubes][3] (nx, ny, nz). */
 size_t mclbm_nn_workspace_bytes(int32_t channels, int32_t two_term, int32_t conditioning, int32_t depth,
                                 const int32_t *dims, int32_t ntubes);
 
@@ -99,19 +99,22 @@ int mclbm_nn_zero_grad(mclbm_nn *net);
 /* One Adam step (Kingma and Ba) on the accumulated gradients, then clears them. */
 int mclbm_nn_adam_step(mclbm_nn *net, float lr, float beta1, float beta2, float eps);
 
-/* Relative change of the mole content of each species per tube between two field
- * sets a, b (device, [channels][n], X_1..X_M first, T at index M): at uniform
- * pressure the moles of species s in a tube are proportional to sum_x X_s / T,
- * and out[t] = max_s |S_s(b) - S_s(a)| / S_s(a). out: host [ntubes]. */
+/* Relative change of the moles of each species per tube between two field sets
+ * a, b (device, [channels][n] in the layout of mclbm_read_fields_f32: X_1..X_M,
+ * T at index M, p at index M + 4): with R_U = 1 the molar density of species s
+ * is rho_s / m_s = p X_s / T, so the tube's moles are S_s = sum_x p X_s / T,
+ * exactly what the lattice conserves; out[t] = max_s |S_s(b) - S_s(a)| / S_s(a).
+ * out: host [ntubes]. Needs channels >= species + 5. */
 int mclbm_nn_mole_residual(mclbm_nn *net, int32_t species, const float *a, const float *b, double *out);
 
 /* Advance a lattice Boltzmann context by K steps with the network (trained for
  * K steps): read the fields, predict, and if the mole residual of every tube is
  * at most resid_tol, re-initialise the populations at the local equilibrium of
- * the predicted fields (mole fractions clipped at 0 and renormalised, the
- * context's current pressure); otherwise run the K lattice steps instead
+ * the predicted fields (mole fractions clipped at 0 and renormalised);
+ * otherwise run the K lattice steps instead
  * (*used_fallback = 1). The network's tubes must be the context's and its
- * channels M + 4 (X_1..X_M, T, u_x, u_y, u_z). The step count advances by K. */
+ * channels M + 5 (X_1..X_M, T, u_x, u_y, u_z, p: the layout of
+ * mclbm_read_fields_f32). The step count advances by K. */
 int mclbm_nn_advance(mclbm_ctx *c, mclbm_nn *net, int32_t K, double resid_tol, int32_t *used_fallback,
                      double *max_residual);
 

@@ -14,8 +14,8 @@ Plain numpy, written from the definitions, not from the GPU kernels:
   weights on the reversed offsets; with respect to the weights, the correlation
   of the output gradient with the shifted input);
 - Adam as published by Kingma and Ba (bias-corrected first and second moments);
-- the mole residual: at uniform pressure the moles of species s in a tube are
-  proportional to sum_x X_s / T.
+- the mole residual: with R_U = 1 the molar density of species s is
+  rho_s / m_s = p X_s / T, so a tube's moles are sum_x p X_s / T.
 
 Optionally the forward and backward passes round to BF16 (round to nearest
 even) at the points where the GPU kernels store BF16 (the packed input, the
@@ -223,7 +223,8 @@ def adam(params, grad, m, v, step, lr, b1, b2, eps):
 
 
 def mole_residual(a: np.ndarray, b: np.ndarray, M: int) -> float:
-    """max_s |sum X_s/T (b) - sum X_s/T (a)| / sum X_s/T (a) for one tube's fields [C][...]."""
-    sa = np.array([np.sum(a[s] / a[M]) for s in range(M)])
-    sb = np.array([np.sum(b[s] / b[M]) for s in range(M)])
+    """max_s |S_s(b) - S_s(a)| / S_s(a), S_s = sum p X_s / T, for one tube's fields
+    [C][...] laid out X_1..X_M, T, u_x, u_y, u_z, p."""
+    sa = np.array([np.sum(a[M + 4] * a[s] / a[M]) for s in range(M)])
+    sb = np.array([np.sum(b[M + 4] * b[s] / b[M]) for s in range(M)])
     return float(np.max(np.abs(sb - sa) / np.abs(sa)))

@@ -74,28 +74,31 @@ __global__ void k_counter_add(uint32_t* ctr, uint32_t v)
   if (threadIdx.x == 0 && blockIdx.x == 0) *ctr += v;
 }
 
-// FP32 trajectory fields from the double read-back: out[(M+4) base + k n_t + node].
+// FP32 trajectory fields from the double read-back: out[(M+5) base + k n_t + node],
+// k = X_1..X_M, T, u_x, u_y, u_z, p.
 __global__ __launch_bounds__(BLOCK) void k_pack_f32(Launch ln, const int64_t* __restrict__ tube_n, int M,
                                                    const double* __restrict__ X, const double* __restrict__ T,
-                                                   const double* __restrict__ u, float* __restrict__ out)
+                                                   const double* __restrict__ u, const double* __restrict__ p,
+                                                   float* __restrict__ out)
 {
   const kern::Where w = kern::locate(ln);
   const int64_t n = tube_n[w.t];
   if (w.node >= n) return;
   const int64_t b = w.base, i = w.node;
-  float* o = out + (size_t)(M + 4) * b;
+  float* o = out + (size_t)(M + 5) * b;
   for (int a = 0; a < M; ++a) o[(size_t)a * n + i] = (float)X[(size_t)M * b + (size_t)a * n + i];
   o[(size_t)M * n + i] = (float)T[b + i];
   for (int k = 0; k < 3; ++k) o[(size_t)(M + 1 + k) * n + i] = (float)u[3 * b + (size_t)k * n + i];
+  o[(size_t)(M + 4) * n + i] = (float)p[b + i];
 }
 
-// Predicted fields (FP32 [M+4][n_t] per tube: X_1..X_M, T, u) -> FP64 fields for
-// mclbm_init_fields: mole fractions clipped at zero and renormalised; a block
-// flags a node whose state the equilibria cannot represent (T <= 0, p <= 0,
-// R_a T + u^2 >= 1 for a species or the mixture, no species left).
+// Predicted fields (FP32 [M+5][n_t] per tube: X_1..X_M, T, u, p) -> FP64 fields
+// for mclbm_init_fields: mole fractions clipped at zero and renormalised; a
+// block flags a node whose state the equilibria cannot represent (T <= 0,
+// p <= 0, R_a T + u^2 >= 1 for a species or the mixture, no species left).
 __global__ __launch_bounds__(BLOCK) void k_pred_to_state(const Params<double>* __restrict__ P, Launch ln, int M,
-                                                        const float* __restrict__ pred, const double* __restrict__ p,
-                                                        double* __restrict__ X, double* __restrict__ T,
+                                                        const float* __restrict__ pred, double* __restrict__ X,
+                                                        double* __restrict__ p, double* __restrict__ T,
                                                         double* __restrict__ u, int* __restrict__ block_bad)
 {
   const kern::Where w = kern::locate(ln);
@@ -103,7 +106,7 @@ __global__ __launch_bounds__(BLOCK) void k_pred_to_state(const Params<double>* _
   int bad = 0;
   if (w.node < Pt.n) {
     const int64_t n = Pt.n, b = w.base, i = w.node;
-    const float* f = pred + (size_t)(M + 4) * b;
+    const float* f = pred + (size_t)(M + 5) * b;
     double xs[MAXM], sum = 0.0, mmix = 0.0;
     for (int a = 0; a < M; ++a) {
       xs[a] = fmax((double)f[(size_t)a * n + i], 0.0);
@@ -121,9 +124,11 @@ __global__ __launch_bounds__(BLOCK) void k_pred_to_state(const Params<double>* _
       mmix += xs[a] * Pt.m[a];
       if (!(Tn * Pt.inv_m[a] + usq < 1.0)) bad = 1;
     }
-    if (!(Tn > 0.0) || !(p[b + i] > 0.0) || !(mmix > 0.0) || !(Tn / mmix + usq < 1.0)) bad = 1;
+    const double pn = (double)f[(size_t)(M + 4) * n + i];
+    if (!(Tn > 0.0) || !(pn > 0.0) || !(mmix > 0.0) || !(Tn / mmix + usq < 1.0)) bad = 1;
     for (int a = 0; a < M; ++a) X[(size_t)M * b + (size_t)a * n + i] = xs[a];
     T[b + i] = Tn;
+    p[b + i] = pn;
     for (int k = 0; k < 3; ++k) u[3 * b + (size_t)k * n + i] = uu[k];
   }
   bad = __syncthreads_or(bad);
@@ -252,7 +257,7 @@ Layout layout_for(const mclbm_params* tp, int ntubes)
   l.rec = off; off += align_up((size_t)rec_fields * l.n * r_bytes);
   l.G = off; off += align_up((size_t)3 * l.n * r_bytes);
   // staging: fields of init_fields / read_moments ((M+6) n doubles), or the
-  // doubles of read_fields_f32 followed by its packed floats ((M+4) n each)
+  // doubles of read_fields_f32 followed by its packed floats ((M+5) n each)
   l.staging = off; off += align_up((size_t)(2 * M + 8) * l.n * sizeof(double));
   l.partial = off; off += align_up((size_t)l.nblocks * (MAXM + 6) * sizeof(double));
   l.reduced = off; off += align_up((size_t)ntubes * (MAXM + 6) * sizeof(double));
@@ -881,20 +886,22 @@ extern "C" int mclbm_read_fields_f32(mclbm_ctx* c, float* out, int on_device)
   double* sX = st;
   double* su = st + (size_t)M * N;
   double* sT = st + (size_t)(M + 3) * N;
-  // the packed FP32 fields reuse the staging area behind the doubles
-  float* sF = (float*)(st + (size_t)(M + 4) * N);
-  static_assert(sizeof(float) * 2 == sizeof(double), "staging holds (M+4) floats in 2 doubles");
+  double* sp = st + (size_t)(M + 4) * N;
+  // the packed FP32 fields reuse the staging area behind the doubles:
+  // 1.5 (M + 5) n doubles <= (2 M + 8) n for M >= 1
+  float* sF = (float*)(st + (size_t)(M + 5) * N);
+  static_assert(sizeof(float) * 2 == sizeof(double), "staging holds (M+5) floats in (M+5)/2 doubles");
   const unsigned grid = (unsigned)c->nblocks;
-  c->ops.read(c->dPr, launch_all(c), c->pop[c->cur], sX, nullptr, su, nullptr, sT, grid, c->stream);
+  c->ops.read(c->dPr, launch_all(c), c->pop[c->cur], sX, nullptr, su, sp, sT, grid, c->stream);
   int rc = check_launch(c, "k_read");
   if (rc) return rc;
   float* dst = on_device ? out : sF;
-  hipLaunchKernelGGL(k_pack_f32, dim3(grid), dim3(BLOCK), 0, c->stream, launch_all(c), c->dTubeN, M, sX, sT, su,
+  hipLaunchKernelGGL(k_pack_f32, dim3(grid), dim3(BLOCK), 0, c->stream, launch_all(c), c->dTubeN, M, sX, sT, su, sp,
                      dst);
   rc = check_launch(c, "k_pack_f32");
   if (rc) return rc;
   if (!on_device)
-    HIP_TRY(c, hipMemcpyAsync(out, sF, sizeof(float) * (M + 4) * N, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(out, sF, sizeof(float) * (M + 5) * N, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return MCLBM_OK;
 }
@@ -1130,7 +1137,7 @@ extern "C" int mclbm_nn_advance(mclbm_ctx* c, mclbm_nn* net, int32_t K, double r
   int channels = 0;
   std::vector<int> dims;
   mclbm::nn::geometry(net, &channels, &dims);
-  if (channels != M + 4) return fail(c, MCLBM_EARG, "the network must have M + 4 channels (X, T, u)");
+  if (channels != M + 5) return fail(c, MCLBM_EARG, "the network must have M + 5 channels (X, T, u, p)");
   if ((int)dims.size() != 3 * c->ntubes) return fail(c, MCLBM_EARG, "network and context have different tubes");
   for (int t = 0; t < c->ntubes; ++t)
     if (dims[3 * t] != c->tubes[t].nx || dims[3 * t + 1] != c->tubes[t].ny || dims[3 * t + 2] != c->tubes[t].nz)
@@ -1153,9 +1160,8 @@ extern "C" int mclbm_nn_advance(mclbm_ctx* c, mclbm_nn* net, int32_t K, double r
   double *X = st, *p = st + (size_t)M * N, *T = st + (size_t)(M + 1) * N, *u = st + (size_t)(M + 2) * N;
   if (ok) {
     const unsigned grid = (unsigned)c->nblocks;
-    c->ops.read(c->dPr, launch_all(c), c->pop[c->cur], nullptr, nullptr, nullptr, p, nullptr, grid, c->stream);
     hipLaunchKernelGGL(k_pred_to_state, dim3(grid), dim3(BLOCK), 0, c->stream, (const Params<double>*)c->dPd,
-                       launch_all(c), M, fout, p, X, T, u, c->bad);
+                       launch_all(c), M, fout, X, p, T, u, c->bad);
     rc = check_launch(c, "k_pred_to_state");
     if (rc) return rc;
     std::vector<int> bad(c->nblocks);

@@ -35,7 +35,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int TILE = 256;      // nodes per workgroup
 constexpr int WIDTH = 64;      // hidden channels
-constexpr int CIN0 = 16;       // input channels of layer 0 (fields padded with zeros)
+constexpr int CIN0 = 32;       // input channels of layer 0 (fields, second terms, conditioning, zeros)
 constexpr int COUTL = 32;      // output channels of the last layer (padded)
 constexpr int NTAP = 27;
 constexpr int MAXC = 16;
@@ -386,14 +386,14 @@ __global__ __launch_bounds__(256) void k_pack_in(const NTube* __restrict__ tubes
     if (c < C + P + S) return cond[(size_t)t * S + (c - C - P)];
     return 0.f;
   };
-  bf16x8 lo, hi;
-#pragma unroll
-  for (int c = 0; c < 8; ++c) lo[c] = (bf16)value(c);
-#pragma unroll
-  for (int c = 8; c < 16; ++c) hi[c - 8] = (bf16)value(c);
   bf16* dst = act0 + (tb.base + node) * CIN0;
-  *(bf16x8*)dst = lo;
-  *(bf16x8*)(dst + 8) = hi;
+#pragma unroll
+  for (int c8 = 0; c8 < CIN0 / 8; ++c8) {
+    bf16x8 v;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = (bf16)value(c8 * 8 + j);
+    *(bf16x8*)(dst + c8 * 8) = v;
+  }
 }
 
 // fields_out[c][node] = f[c][node] + y[node][c] out_scale_c.
@@ -454,7 +454,8 @@ __global__ __launch_bounds__(256) void k_loss(const NTube* __restrict__ tubes, c
   if (threadIdx.x == 0) partial[tile] = red[0];
 }
 
-// Per-tile sums S_s = sum X_s / T (species s < M, T at component M), FP64.
+// Per-tile moles S_s = sum p X_s / T (species s < M, T at component M, p at
+// component M + 4), FP64.
 __global__ __launch_bounds__(256) void k_mole_sums(const NTube* __restrict__ tubes, const int32_t* __restrict__ tile_tube,
                                                    int ntubes, int C, int M, const float* __restrict__ f,
                                                    double* __restrict__ partial)
@@ -467,7 +468,9 @@ __global__ __launch_bounds__(256) void k_mole_sums(const NTube* __restrict__ tub
   const size_t o = (size_t)C * tb.base;
   for (int s = 0; s < M; ++s) {
     double v = 0.0;
-    if (node < n_t) v = (double)f[o + (size_t)s * n_t + node] / (double)f[o + (size_t)M * n_t + node];
+    if (node < n_t)
+      v = (double)f[o + (size_t)(M + 4) * n_t + node] * (double)f[o + (size_t)s * n_t + node] /
+          (double)f[o + (size_t)M * n_t + node];
     red[threadIdx.x] = v;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
@@ -623,8 +626,9 @@ void layer_sizes(int C, int P, int S, int depth, std::vector<int>& in_r, std::ve
 
 int validate_nn(int C, int P, int S, int depth, const int32_t* dims, int ntubes, std::string& err)
 {
-  if (C < 1 || P < 0 || P > C || S < 0 || C + P + S > MAXC) {
-    err = "need channels >= 1, 0 <= two_term <= channels, conditioning >= 0, channels + two_term + conditioning <= 16";
+  if (C < 1 || C > MAXC || P < 0 || P > C || S < 0 || C + P + S > CIN0) {
+    err = "need 1 <= channels <= 16, 0 <= two_term <= channels, conditioning >= 0, "
+          "channels + two_term + conditioning <= 32";
     return MCLBM_EARG;
   }
   if (depth < 2 || depth > 16) { err = "depth must be in 2..16"; return MCLBM_EARG; }
@@ -1043,7 +1047,7 @@ extern "C" int mclbm_nn_mole_residual(mclbm_nn* net, int32_t species, const floa
 {
   if (!net) return MCLBM_EARG;
   if (!a || !b || !out) return nn_fail(net, MCLBM_EARG, "pointers must be given");
-  if (species < 1 || species + 1 > net->C) return nn_fail(net, MCLBM_EARG, "need 1 <= species < channels");
+  if (species < 1 || species + 5 > net->C) return nn_fail(net, MCLBM_EARG, "need 1 <= species <= channels - 5");
   std::vector<double> sa, sb;
   for (int pass = 0; pass < 2; ++pass) {
     hipLaunchKernelGGL(k_mole_sums, dim3((unsigned)net->ntiles), dim3(256), 0, net->stream, net->dTubes,

@@ -466,11 +466,11 @@ class Batch:
         return [{k: parts[k][t] for k in flat} for t in range(len(self.shapes))]
 
     def read_fields_f32(self, out=None):
-        """FP32 trajectory fields (X_1..X_M, T, u) into a CUDA tensor of M+4 values per node."""
+        """FP32 trajectory fields (X_1..X_M, T, u, p) into a CUDA tensor of M+5 values per node."""
         import torch
 
         if out is None:
-            out = torch.empty((self.M + 4) * self.n, dtype=torch.float32, device=self.device)
+            out = torch.empty((self.M + 5) * self.n, dtype=torch.float32, device=self.device)
         mclbm_read_fields_f32(self.ctx, out.data_ptr(), 1)
         return out
 

@@ -21,7 +21,7 @@ LR = 5e-4
 
 
 def channels(M: int) -> int:
-    return M + 4                      # X_1..X_M, T, u_x, u_y, u_z
+    return M + 5                      # X_1..X_M, T, u_x, u_y, u_z, p
 
 
 def conditioning(params: dict) -> np.ndarray:
@@ -36,7 +36,7 @@ def conditioning(params: dict) -> np.ndarray:
 
 def trajectories(tubes: list, K: int = K_DEFAULT, nsnap: int = 50, precision: int = mc.MCLBM_FP32):
     """Run the tubes as one batched context and keep the FP32 fields every K
-    steps: a device tensor [nsnap + 1][(M+4) n] and the tube sizes."""
+    steps: a device tensor [nsnap + 1][(M+5) n] and the tube sizes."""
     import torch
 
     b = mc.Batch([p for p, _ in tubes], precision)
@@ -114,7 +114,7 @@ def build_net(dims, tubes_params, norm, M: int, depth: int = DEPTH, params=None,
 
 def channel_weights(M: int) -> np.ndarray:
     """The mole fractions are what the surrogate is judged on."""
-    return np.array([1.0] * M + [0.2] + [0.1] * 3, dtype=np.float32)
+    return np.array([1.0] * M + [0.2] + [0.1] * 3 + [0.2], dtype=np.float32)
 
 
 def pair_weights(snaps, dims, out_scale, M: int, floor: float = 1e-2) -> np.ndarray:
@@ -148,7 +148,7 @@ def train(net, snaps, iters: int, lr: float = LR, seed: int = 0, log_every: int 
     cosine learning-rate decay. weights: per-pair channel weights [nsnap][C]
     (default: the base channel weights). Returns the loss history."""
     rng = np.random.default_rng(seed)
-    base = channel_weights(net.C - 4)
+    base = channel_weights(net.C - 5)
     losses = []
     nsnap = snaps.shape[0] - 1
     for it in range(iters):
@@ -253,7 +253,7 @@ def timed_train_step(net, snaps, reps: int = 5):
     """Milliseconds of one forward + loss + backward + Adam step (mean of reps)."""
     import torch
 
-    w = channel_weights(net.C - 4)
+    w = channel_weights(net.C - 5)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     net.fields_in.copy_(snaps[0])
     t0 = time.perf_counter()

@@ -117,8 +117,9 @@ def test_nn_workspace_and_validation():
     assert b > 5 * n * 64 * 2                     # the hidden activations dominate
     assert b < m.mclbm_nn_workspace_bytes(7, 0, 0, 6, dims + [(64, 8, 8)])
     assert m.mclbm_nn_workspace_bytes(7, 3, 6, 6, dims) >= b
-    for bad in [(0, 0, 0, 6, dims), (17, 0, 0, 6, dims), (7, 0, 10, 6, dims), (7, 8, 0, 6, dims),
-                (7, 3, 7, 6, dims), (7, 0, 0, 1, dims), (7, 0, 0, 6, [(0, 4, 4)])]:
+    assert m.mclbm_nn_workspace_bytes(8, 3, 6, 6, dims) > 0            # 17 input channels fit in 32
+    for bad in [(0, 0, 0, 6, dims), (17, 0, 0, 6, dims), (16, 16, 1, 6, dims), (7, 8, 0, 6, dims),
+                (7, 0, -1, 6, dims), (7, 0, 0, 1, dims), (7, 0, 0, 6, [(0, 4, 4)])]:
         with pytest.raises(m.MclbmError):
             m.mclbm_nn_workspace_bytes(*bad)
 

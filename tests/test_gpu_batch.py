@@ -134,10 +134,10 @@ def test_trajectory_fields_f32(mc):
     flat = b.read_fields_f32().cpu().numpy()
     mom = b.read_moments()
     M = b.M
-    parts = b.split(flat, M + 4)
+    parts = b.split(flat, M + 5)
     b.close()
     for t in range(len(tubes)):
-        want = np.concatenate([mom[t]["X"], mom[t]["T"][None], mom[t]["u"]]).astype(np.float32)
+        want = np.concatenate([mom[t]["X"], mom[t]["T"][None], mom[t]["u"], mom[t]["p"][None]]).astype(np.float32)
         np.testing.assert_array_equal(parts[t], want)
 
 

@@ -17,7 +17,7 @@ from paper_2004_11286_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 DIMS = [(13, 4, 3), (40, 2, 5), (7, 8, 8)]       # ragged tubes: 156, 400 and 448 nodes
-C = 7
+C = 8                                            # X_1..X_3, T, u (3), p
 
 
 @pytest.fixture(scope="module")

@@ -162,8 +162,9 @@ def test_bf16_rounding():
 
 
 def test_mole_residual_definition():
+    """Fields X_1..X_3, T, u (3), p: the moles are sum p X_s / T."""
     rng = np.random.default_rng(6)
-    a = rng.uniform(0.1, 1.0, size=(5, 2, 2, 7))
+    a = rng.uniform(0.1, 1.0, size=(8, 2, 2, 7))
     assert S.mole_residual(a, a, 3) == 0.0
     b = a.copy()
     b[1] *= 1.01                                  # species 2 gains 1 % everywhere
@@ -171,6 +172,10 @@ def test_mole_residual_definition():
     c = a.copy()
     c[3] *= 2.0                                   # doubling T halves every species' moles
     assert S.mole_residual(a, c, 3) == pytest.approx(0.5, rel=1e-12)
+    d = a.copy()
+    d[7] *= 2.0
+    d[3] *= 2.0                                   # p and T doubled together: same moles
+    assert S.mole_residual(a, d, 3) == pytest.approx(0.0, abs=1e-14)
 
 
 def test_two_term_encoding_resolves_16_bits():
