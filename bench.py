@@ -219,13 +219,13 @@ def surrogate_bench(train_iters: int = 3000):
     snaps, dims = SG.trajectories(train_tubes, K=100, nsnap=50)
     M = 3
     C = SG.channels(M)
-    mean, std, dstd = SG.channel_stats(snaps, dims, C)
-    norm = SG.norm_from_stats(mean, std, dstd)
+    st = SG.channel_stats(snaps, dims, M)
+    norm = SG.norm_from_stats(st, M)
+    pw = SG.pair_weights(st, M)
     net = SG.build_net(dims, [p for p, _ in train_tubes], norm, M)
-    ms_train_step, _ = SG.timed_train_step(net, snaps)
-    net.set_params(SG.he_init(C, 6, SG.DEPTH, 0))
-    pw = SG.pair_weights(snaps, dims, norm["out_scale"], M)
-    losses = SG.train(net, snaps, train_iters, lr=3e-4, weights=pw)
+    ms_train_step, _ = SG.timed_train_step(net, snaps, pw)
+    net.set_params(SG.he_init(C, 6, SG.DEPTH, 0, 3 * M + 4))
+    losses = SG.train(net, snaps, train_iters, pw, lr=3e-4)
     params = net.get_params()
     n_train = sum(a * b * c for a, b, c in dims)
     net.close()
@@ -234,15 +234,17 @@ def surrogate_bench(train_iters: int = 3000):
     eval_tubes = W.tube_ensemble(ntubes=8, ny=32, nz=32, lmin=128, lmax=128, seed=2025)
     res = SG.evaluate(params, norm, eval_tubes, K=100, starts=(0, 1000), resid_tol=1e-4)
     n_eval = sum(p["nx"] * p["ny"] * p["nz"] for p, _ in eval_tubes)
-    flops = SG.conv_flops_per_node(C, M + 6) * n_eval
+    fpn = SG.conv_flops_per_node(C, M + 6, 3 * M + 4)
+    flops = fpn * n_eval
     ms_fwd = float(np.median([r["ms_forward"] for r in res]))
     achieved = flops / (ms_fwd * 1e-3) / 1e12
-    train_flops = 3 * SG.conv_flops_per_node(C, M + 6) * n_train
+    train_flops = 3 * fpn * n_train
     return {
         "workload": "train: 64 ternary tubes L~U{32..256}x4x4, 50 snapshots every 100 steps; "
                     "apply: 8 held-out ternary tubes 128x32x32, one 100-step hop",
         "network": {"layers": SG.DEPTH, "width": 64, "kernel": "3x3x3", "params": int(params.size),
-                    "input": "X_a, T, u (+ second BF16 terms of X_a, 6 tube constants)",
+                    "input": "X_a, T, u, p (+ second BF16 terms of X_a, 6 tube constants)",
+                    "output": "conservative: face fluxes of the molar densities p X_a / T, changes of T and u",
                     "dtype": "bf16 weights/activations, fp32 accumulate"},
         "train": {"iters": train_iters, "seconds": train_s, "loss_first100": float(np.mean(losses[:100])),
                   "loss_last100": float(np.mean(losses[-100:])), "ms_per_step": ms_train_step,
@@ -252,7 +254,7 @@ def surrogate_bench(train_iters: int = 3000):
         "speedup_advance_vs_lattice": float(np.median([r["ms_lattice"] / r["ms_advance"] for r in res])),
         "roofline_conv_forward": {"bound": "mfma", "achieved": achieved, "peak": BF16_PEAK_TFLOPS,
                                   "unit": "TFLOP/s", "frac": achieved / BF16_PEAK_TFLOPS,
-                                  "flop_per_node": SG.conv_flops_per_node(C, M + 6), "nodes": n_eval},
+                                  "flop_per_node": fpn, "nodes": n_eval},
     }
 
 

@@ -9,17 +9,26 @@
  * Network: depth conv layers with 3x3x3 kernels, width 64, ReLU between layers,
  * BF16 weights and activations, FP32 accumulation. Layer 0 maps the C field
  * channels, P second terms and S conditioning channels to 64, the last layer 64
- * to C. BF16 resolves a normalised input to about 3 significant digits; the
- * first P field channels are therefore also given as a second BF16 term, the
- * rounding remainder of the first times 256, whose layer-0 weights are those of
- * the field divided by 256 (tied, exact in BF16), so the matrix cores see about
- * 16 significant bits of these fields (hi + lo / 256) with no extra
- * parameters. The
- * output is the change of the normalised fields over the K steps. The
- * conditioning channels are constant per tube (for instance the tube's molar
- * masses and diffusivities, which the fields alone do not reveal but which
- * decide how they evolve). Padding: zero outside the x ends of a tube (the walls),
- * periodic in y and z, like the lattice.
+ * to the output channels. BF16 resolves a normalised input to about 3
+ * significant digits; the first P field channels are therefore also given as a
+ * second BF16 term, the rounding remainder of the first times 256, whose layer-0
+ * weights are those of the field divided by 256 (tied, exact in BF16), so the
+ * matrix cores see about 16 significant bits of these fields (hi + lo / 256)
+ * with no extra parameters. The conditioning channels are constant per tube
+ * (for instance the tube's molar masses and diffusivities, which the fields
+ * alone do not reveal but which decide how they evolve). Padding: zero outside
+ * the x ends of a tube (the walls), periodic in y and z, like the lattice.
+ *
+ * Output, direct form (species = 0): the change of each of the C fields over
+ * the K steps, y_c * out_scale[c]. Conservative form (species = M > 0, fields
+ * laid out as mclbm_read_fields_f32: X_1..X_M, T, u, p): for each species s the
+ * fluxes of its molar density n_s = p X_s / T (rho_s / m_s with R_U = 1)
+ * through the faces between a node x and x + e_a, F_{s,a} = y_{3s+a} *
+ * out_scale[3s+a], and the changes of T and u (channels 3M .. 3M+3). The new
+ * densities are n_s(x) - sum_a [F_{s,a}(x) - F_{s,a}(x - e_a)], a discrete
+ * divergence, so each tube keeps the moles of every species exactly (the mass
+ * conservation of Sec. 2.2 item 1); faces at the walls carry no flux. Then
+ * p = T sum_s n_s and X_s = n_s / sum n.
  *
  * Geometry: a network is created for a set of tubes (nx, ny, nz each), the same
  * concatenated node layout as a batched mclbm context (include/mclbm.h): a field
@@ -51,13 +60,15 @@ typedef struct mclbm_nn mclbm_nn;
 
 /* Workspace bytes of a network with `channels` field components C (<= 16),
  * `two_term` of them (the leading ones) also given as a second term P (<= C),
- * `conditioning` per-tube constants S (C + P + S <= 32), `depth` conv layers
- * (2..16) over ntubes tubes, dims = [ntubes][3] (nx, ny, nz). */
-size_t mclbm_nn_workspace_bytes(int32_t channels, int32_t two_term, int32_t conditioning, int32_t depth,
-                                const int32_t *dims, int32_t ntubes);
+ * `conditioning` per-tube constants S (C + P + S <= 32), output form `species`
+ * (0: direct; M > 0: conservative, needs C = M + 5 and 3 M + 4 <= 32), `depth`
+ * conv layers (2..16) over ntubes tubes, dims = [ntubes][3] (nx, ny, nz). */
+size_t mclbm_nn_workspace_bytes(int32_t channels, int32_t two_term, int32_t conditioning, int32_t species,
+                                int32_t depth, const int32_t *dims, int32_t ntubes);
 
-int mclbm_nn_create(int32_t channels, int32_t two_term, int32_t conditioning, int32_t depth, const int32_t *dims,
-                    int32_t ntubes, void *dev_workspace, size_t bytes, void *hip_stream, mclbm_nn **out);
+int mclbm_nn_create(int32_t channels, int32_t two_term, int32_t conditioning, int32_t species, int32_t depth,
+                    const int32_t *dims, int32_t ntubes, void *dev_workspace, size_t bytes, void *hip_stream,
+                    mclbm_nn **out);
 void mclbm_nn_destroy(mclbm_nn *net);
 const char *mclbm_nn_last_error(const mclbm_nn *net);
 
@@ -69,9 +80,9 @@ int mclbm_nn_set_params(mclbm_nn *net, const float *host);
 int mclbm_nn_get_params(mclbm_nn *net, float *host);
 int mclbm_nn_get_grads(mclbm_nn *net, float *host);
 
-/* Normalisation, host arrays of `channels` values: network input channel c is
- * (f_c - in_shift[c]) * in_scale[c]; the predicted field is f_c + y_c * out_scale[c]
- * with y the network output. */
+/* Normalisation: network input channel c is (f_c - in_shift[c]) * in_scale[c]
+ * (in_shift, in_scale: `channels` values); out_scale has one value per output
+ * channel (C in the direct form, 3 M + 4 in the conservative form). */
 int mclbm_nn_set_norm(mclbm_nn *net, const float *in_shift, const float *in_scale, const float *out_scale);
 
 /* Conditioning values, host [ntubes][conditioning], used as given (already
@@ -86,8 +97,10 @@ int mclbm_nn_io(mclbm_nn *net, float **fields_in, float **fields_out);
 int mclbm_nn_forward(mclbm_nn *net);
 
 /* Mean squared error of the prediction against target (device, [channels][n]),
- * in normalised output units with per-channel weights (host, may be NULL = 1):
- * loss = (1/n) sum_nodes sum_c w_c ((pred_c - target_c) / out_scale[c])^2.
+ * with per-channel weights w (host, `channels` values, may be NULL = 1).
+ * Direct form: loss = (1/n) sum_nodes sum_c w_c ((pred_c - target_c) / out_scale[c])^2.
+ * Conservative form, in physical units: loss = (1/n) sum_nodes [sum_s w_s (n_s -
+ * n*_s)^2 + w_M (T - T*)^2 + sum_k w_{M+1+k} (u_k - u*_k)^2] (w_{M+4} unused).
  * Seeds the output gradient for backward. Synchronises the stream. */
 int mclbm_nn_loss(mclbm_nn *net, const float *target, const float *channel_weight, double *loss);
 

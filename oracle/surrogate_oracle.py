@@ -9,6 +9,10 @@ Plain numpy, written from the definitions, not from the GPU kernels:
 - the network: layer 0 maps C field channels to the hidden width, ReLU between
   layers, the last layer maps back to C; its input is the normalised fields
   (f - shift) * scale, its output the change of the normalised fields;
+- the conservative output form: the network predicts, per species, the fluxes
+  of the molar density n_s = p X_s / T through the faces between x and x + e_a
+  (none through the walls); n_s changes by minus their discrete divergence;
+  then p = T sum n and X_s = n_s / sum n;
 - the mean squared error and its gradient by the chain rule (the gradient of a
   convolution with respect to its input is the convolution with the transposed
   weights on the reversed offsets; with respect to the weights, the correlation
@@ -89,21 +93,22 @@ def conv_weight_grad(dy: np.ndarray, x: np.ndarray):
 
 
 # ------------------------------------------------------------------ network
-def layer_shapes(C: int, depth: int, width: int = 64, S: int = 0):
-    """S counts every extra input channel of layer 0 (second terms and conditioning)."""
+def layer_shapes(C: int, depth: int, width: int = 64, S: int = 0, species: int = 0):
+    """S counts the conditioning channels of layer 0 (the tied second terms add no
+    parameters); species > 0: conservative output, 3 species + 4 channels."""
     ins = [C + S] + [width] * (depth - 1)
-    outs = [width] * (depth - 1) + [C]
+    outs = [width] * (depth - 1) + [3 * species + 4 if species else C]
     return list(zip(outs, ins))
 
 
-def param_count(C: int, depth: int, width: int = 64, S: int = 0) -> int:
-    return sum(NTAP * o * i + o for o, i in layer_shapes(C, depth, width, S))
+def param_count(C: int, depth: int, width: int = 64, S: int = 0, species: int = 0) -> int:
+    return sum(NTAP * o * i + o for o, i in layer_shapes(C, depth, width, S, species))
 
 
-def unflatten(params: np.ndarray, C: int, depth: int, width: int = 64, S: int = 0):
+def unflatten(params: np.ndarray, C: int, depth: int, width: int = 64, S: int = 0, species: int = 0):
     """Flat parameters (layer by layer: W[tap][out][in], then b[out]) -> list of (W, b)."""
     out, k = [], 0
-    for o, i in layer_shapes(C, depth, width, S):
+    for o, i in layer_shapes(C, depth, width, S, species):
         W = params[k:k + NTAP * o * i].reshape(NTAP, o, i)
         k += NTAP * o * i
         b = params[k:k + o]
@@ -117,11 +122,12 @@ def flatten(layers) -> np.ndarray:
     return np.concatenate([np.concatenate([W.ravel(), b.ravel()]) for W, b in layers])
 
 
-def he_init(C: int, depth: int, seed: int, width: int = 64, gain: float = 1.0, S: int = 0) -> np.ndarray:
+def he_init(C: int, depth: int, seed: int, width: int = 64, gain: float = 1.0, S: int = 0,
+            species: int = 0) -> np.ndarray:
     """Seeded He-normal weights, zero biases (the starting point of training)."""
     rng = np.random.default_rng(seed)
     layers = []
-    for k, (o, i) in enumerate(layer_shapes(C, depth, width, S)):
+    for k, (o, i) in enumerate(layer_shapes(C, depth, width, S, species)):
         std = np.sqrt(2.0 / (NTAP * i)) * (gain if k < depth - 1 else 0.1 * gain)
         layers.append((rng.normal(0.0, std, (NTAP, o, i)), np.zeros(o)))
     return flatten(layers).astype(np.float32)
@@ -152,12 +158,73 @@ def fold_first(g: np.ndarray, C: int, P: int) -> np.ndarray:
     return out
 
 
-def forward(params, f, norm, C, depth, width=64, round_bf16=False, cond=None, P=0):
+def _down(F, a):
+    """F(x - e_a): zero below x = 0 (walls), periodic in y (a = 1) and z (a = 2)."""
+    if a == 0:
+        out = np.zeros_like(F)
+        out[..., 1:] = F[..., :-1]
+        return out
+    return np.roll(F, 1, axis=-2 if a == 1 else -3)
+
+
+def _up(g, a):
+    """g(x + e_a) (the value at x = nx - 1 for a = 0 is never used: that face is a wall)."""
+    if a == 0:
+        out = np.zeros_like(g)
+        out[..., :-1] = g[..., 1:]
+        return out
+    return np.roll(g, -1, axis=-2 if a == 1 else -3)
+
+
+def conservative_fields(f, y, out_scale, M):
+    """New fields [X_1..X_M, T, u, p] from fields f (same layout) and the raw
+    output y [3M + 4][...] of the conservative form; also returns n' [M][...]."""
+    T, p = f[M], f[M + 4]
+    n = p * f[:M] / T
+    n1 = np.empty_like(n)
+    for s in range(M):
+        div = np.zeros_like(T)
+        for a in range(3):
+            F = y[3 * s + a] * out_scale[3 * s + a]
+            if a == 0:
+                F = F.copy()
+                F[..., -1] = 0.0                      # the face at the wall carries no flux
+            div += F - _down(F, a)
+        n1[s] = n[s] - div
+    T1 = T + y[3 * M] * out_scale[3 * M]
+    u1 = f[M + 1:M + 4] + y[3 * M + 1:3 * M + 4] * out_scale[3 * M + 1:3 * M + 4, None, None, None]
+    tot = n1.sum(axis=0)
+    return np.concatenate([n1 / tot, T1[None], u1, (T1 * tot)[None]]), n1
+
+
+def conservative_loss(f, y, target, w, out_scale, M, N):
+    """Loss contribution of one tube (sum over its nodes, divided by the total N)
+    and its gradient with respect to y."""
+    fo, n1 = conservative_fields(f, y, out_scale, M)
+    nt = target[M + 4] * target[:M] / target[M]
+    e = n1 - nt
+    loss = float(np.sum(w[:M, None, None, None] * e * e))
+    g = 2.0 * w[:M, None, None, None] * e / N
+    dy = np.zeros_like(y)
+    for s in range(M):
+        for a in range(3):
+            d = (_up(g[s], a) - g[s]) * out_scale[3 * s + a]
+            if a == 0:
+                d[..., -1] = 0.0
+            dy[3 * s + a] = d
+    for k in range(4):
+        e = fo[M + k] - target[M + k]
+        loss += float(np.sum(w[M + k] * e * e))
+        dy[3 * M + k] = 2.0 * w[M + k] * e * out_scale[3 * M + k] / N
+    return loss / N, dy
+
+
+def forward(params, f, norm, C, depth, width=64, round_bf16=False, cond=None, P=0, species=0):
     """One tube: f [C][nz][ny][nx] fields, cond [S] constants of the tube, P
     leading field channels also given as a second BF16 term (tied weights) ->
     (y raw output, pred fields, cache)."""
     S = 0 if cond is None else len(cond)
-    layers = unflatten(np.asarray(params, dtype=np.float64), C, depth, width, S)
+    layers = unflatten(np.asarray(params, dtype=np.float64), C, depth, width, S, species)
     rnd = bf16 if round_bf16 else (lambda a: a)
     v = (f - norm["in_shift"][:, None, None, None]) * norm["in_scale"][:, None, None, None]
     if P:
@@ -178,17 +245,20 @@ def forward(params, f, norm, C, depth, width=64, round_bf16=False, cond=None, P=
             acts.append(rnd(np.maximum(z, 0.0)))
         else:
             y = z
-    pred = f + y * norm["out_scale"][:, None, None, None]
+    if species:
+        pred, _ = conservative_fields(f, y, norm["out_scale"], species)
+    else:
+        pred = f + y * norm["out_scale"][:, None, None, None]
     return y, pred, acts
 
 
 def loss_and_grad(params, tubes_f, tubes_target, norm, C, depth, width=64, weight=None, round_bf16=False,
-                  tubes_cond=None, P=0):
+                  tubes_cond=None, P=0, species=0):
     """Mean over all nodes of all tubes of sum_c w_c (y_c - r_c)^2 with
     r = (target - f) / out_scale, and its gradient with respect to the flat
     parameters (same order)."""
     S = 0 if tubes_cond is None else len(tubes_cond[0])
-    layers = unflatten(np.asarray(params, dtype=np.float64), C, depth, width, S)
+    layers = unflatten(np.asarray(params, dtype=np.float64), C, depth, width, S, species)
     w = np.ones(C) if weight is None else np.asarray(weight, dtype=np.float64)
     rnd = bf16 if round_bf16 else (lambda a: a)
     N = sum(f[0].size for f in tubes_f)
@@ -196,11 +266,16 @@ def loss_and_grad(params, tubes_f, tubes_target, norm, C, depth, width=64, weigh
     grads = [(np.zeros_like(W), np.zeros_like(b)) for W, b in layers]
     for t, (f, tgt) in enumerate(zip(tubes_f, tubes_target)):
         cond = None if tubes_cond is None else tubes_cond[t]
-        y, _, acts = forward(params, f, norm, C, depth, width, round_bf16, cond, P)
-        r = (tgt - f) / norm["out_scale"][:, None, None, None]
-        e = y - r
-        total += float(np.sum(w[:, None, None, None] * e * e))
-        d = rnd(2.0 * w[:, None, None, None] * e / N)
+        y, _, acts = forward(params, f, norm, C, depth, width, round_bf16, cond, P, species)
+        if species:
+            lt, d = conservative_loss(f, y, tgt, w, norm["out_scale"], species, N)
+            total += lt * N
+            d = rnd(d)
+        else:
+            r = (tgt - f) / norm["out_scale"][:, None, None, None]
+            e = y - r
+            total += float(np.sum(w[:, None, None, None] * e * e))
+            d = rnd(2.0 * w[:, None, None, None] * e / N)
         for k in range(depth - 1, -1, -1):
             W, _ = layers[k]
             dW, db = conv_weight_grad(d, acts[k])

@@ -1134,10 +1134,11 @@ extern "C" int mclbm_nn_advance(mclbm_ctx* c, mclbm_nn* net, int32_t K, double r
   if (!c->initialised) return fail(c, MCLBM_EARG, "no state yet");
   if (K < 1) return fail(c, MCLBM_EARG, "K must be positive");
   const int M = c->M;
-  int channels = 0;
+  int channels = 0, species = 0;
   std::vector<int> dims;
-  mclbm::nn::geometry(net, &channels, &dims);
+  mclbm::nn::geometry(net, &channels, &species, &dims);
   if (channels != M + 5) return fail(c, MCLBM_EARG, "the network must have M + 5 channels (X, T, u, p)");
+  if (species != 0 && species != M) return fail(c, MCLBM_EARG, "the network's species differ from the context's");
   if ((int)dims.size() != 3 * c->ntubes) return fail(c, MCLBM_EARG, "network and context have different tubes");
   for (int t = 0; t < c->ntubes; ++t)
     if (dims[3 * t] != c->tubes[t].nx || dims[3 * t + 1] != c->tubes[t].ny || dims[3 * t + 2] != c->tubes[t].nz)

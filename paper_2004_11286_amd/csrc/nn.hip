@@ -358,7 +358,7 @@ __global__ void k_bgrad_reduce(const float* __restrict__ partial, int ntiles, in
 // Input packing, output unpacking, loss
 // ---------------------------------------------------------------------------
 struct Norm {
-  float in_shift[MAXC], in_scale[MAXC], out_scale[MAXC], weight[MAXC];
+  float in_shift[MAXC], in_scale[MAXC], out_scale[COUTL], weight[COUTL];
 };
 
 // act0[node][c]: for c < C the normalised field v_c = (f_c - shift_c) scale_c
@@ -452,6 +452,157 @@ __global__ __launch_bounds__(256) void k_loss(const NTube* __restrict__ tubes, c
     __syncthreads();
   }
   if (threadIdx.x == 0) partial[tile] = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// Conservative output: the network predicts, for each species s, the fluxes of
+// its molar density n_s = p X_s / T through the faces between a node x and
+// x + e_a (a = x, y, z), and the changes of T and u. The new densities are
+// n_s - sum_a (F_a(x) - F_a(x - e_a)): a discrete divergence, so every tube
+// keeps its moles of each species exactly. The faces at the walls carry no
+// flux; y and z are periodic. Then p = T sum_s n_s and X_s = n_s / sum n.
+// Output channels: F for species s and direction a at 3 s + a, then T, u.
+// ---------------------------------------------------------------------------
+struct Geo {
+  int x, y, z;
+};
+
+__device__ inline Geo geo_of(const NTube& tb, int node)
+{
+  const int r = node / tb.nx;
+  return {node % tb.nx, r % tb.ny, r / tb.ny};
+}
+
+// Face from node g towards +e_a exists (a wall face at x = nx - 1 does not).
+__device__ inline bool face_open(const NTube& tb, const Geo& g, int a) { return a != 0 || g.x + 1 < tb.nx; }
+
+__device__ inline int64_t shifted(const NTube& tb, Geo g, int a, int d)
+{
+  if (a == 0) g.x += d;
+  if (a == 1) g.y += d;
+  if (a == 2) g.z += d;
+  return wrap_index(tb, g.x, g.y, g.z);
+}
+
+__device__ inline Geo shifted_geo(const NTube& tb, Geo g, int a, int d)
+{
+  if (a == 0) g.x += d;
+  if (a == 1) g.y = (g.y + d + tb.ny) % tb.ny;
+  if (a == 2) g.z = (g.z + d + tb.nz) % tb.nz;
+  return g;
+}
+
+__global__ __launch_bounds__(256) void k_unpack_cons(const NTube* __restrict__ tubes,
+                                                     const int32_t* __restrict__ tile_tube, int ntubes, int M,
+                                                     Norm nm, const float* __restrict__ f,
+                                                     const float* __restrict__ y, float* __restrict__ fo)
+{
+  const int tile = blockIdx.x;
+  const NTube tb = tube_of(tubes, tile_tube, ntubes, tile);
+  const int n_t = tb.nx * tb.ny * tb.nz;
+  const int node = (tile - tb.first_tile) * TILE + threadIdx.x;
+  if (node >= n_t) return;
+  const int C = M + 5;
+  const size_t o = (size_t)C * tb.base;
+  auto fld = [&](int c) -> double { return (double)f[o + (size_t)c * n_t + node]; };
+  const Geo g = geo_of(tb, node);
+  const int64_t gn = tb.base + node;
+  const double T = fld(M), p = fld(M + 4);
+  double nn[MAXC], sum = 0.0;
+  for (int s = 0; s < M; ++s) {
+    double div = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      const double sc = nm.out_scale[3 * s + a];
+      if (face_open(tb, g, a)) div += (double)y[gn * COUTL + 3 * s + a] * sc;
+      const bool lower = a != 0 || g.x > 0;
+      if (lower) div -= (double)y[shifted(tb, g, a, -1) * COUTL + 3 * s + a] * sc;
+    }
+    nn[s] = p * fld(s) / T - div;
+    sum += nn[s];
+  }
+  const double T1 = T + (double)y[gn * COUTL + 3 * M] * nm.out_scale[3 * M];
+  for (int s = 0; s < M; ++s) fo[o + (size_t)s * n_t + node] = (float)(nn[s] / sum);
+  fo[o + (size_t)M * n_t + node] = (float)T1;
+  for (int k = 0; k < 3; ++k)
+    fo[o + (size_t)(M + 1 + k) * n_t + node] =
+        (float)(fld(M + 1 + k) + (double)y[gn * COUTL + 3 * M + 1 + k] * nm.out_scale[3 * M + 1 + k]);
+  fo[o + (size_t)(M + 4) * n_t + node] = (float)(T1 * sum);
+}
+
+// Loss of the conservative output on the conserved and transported variables,
+// in physical units: (1/N) sum [ sum_s w_s (n_s - n*_s)^2 + w_T (T - T*)^2 +
+// sum_k w_u,k (u_k - u*_k)^2 ], weights w = nm.weight[0..M+3]. Writes the loss
+// partials, dL/dn_s per node into gn_out [n][M], and the T and u part of the
+// output gradient (the flux part follows in k_loss_cons_flux).
+__global__ __launch_bounds__(256) void k_loss_cons(const NTube* __restrict__ tubes,
+                                                   const int32_t* __restrict__ tile_tube, int ntubes, int M,
+                                                   Norm nm, double inv_n, const float* __restrict__ fo,
+                                                   const float* __restrict__ target, float* __restrict__ gn_out,
+                                                   bf16* __restrict__ dY, double* __restrict__ partial)
+{
+  __shared__ double red[256];
+  const int tile = blockIdx.x;
+  const NTube tb = tube_of(tubes, tile_tube, ntubes, tile);
+  const int n_t = tb.nx * tb.ny * tb.nz;
+  const int node = (tile - tb.first_tile) * TILE + threadIdx.x;
+  double l = 0.0;
+  if (node < n_t) {
+    const int C = M + 5;
+    const size_t o = (size_t)C * tb.base;
+    const int64_t gn = tb.base + node;
+    auto at = [&](const float* a, int c) -> double { return (double)a[o + (size_t)c * n_t + node]; };
+    for (int s = 0; s < M; ++s) {
+      const double e = at(fo, M + 4) * at(fo, s) / at(fo, M) - at(target, M + 4) * at(target, s) / at(target, M);
+      l += nm.weight[s] * e * e;
+      gn_out[gn * M + s] = (float)(2.0 * nm.weight[s] * e * inv_n);
+    }
+    bf16 d[COUTL];
+#pragma unroll
+    for (int c = 0; c < COUTL; ++c) d[c] = (bf16)0.f;
+    for (int k = 0; k < 4; ++k) {
+      const double e = at(fo, M + k) - at(target, M + k);
+      l += nm.weight[M + k] * e * e;
+      d[3 * M + k] = (bf16)(float)(2.0 * nm.weight[M + k] * e * nm.out_scale[3 * M + k] * inv_n);
+    }
+#pragma unroll
+    for (int c8 = 0; c8 < COUTL / 8; ++c8) {
+      bf16x8 v;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = d[c8 * 8 + j];
+      *(bf16x8*)(dY + gn * COUTL + c8 * 8) = v;
+    }
+  }
+  red[threadIdx.x] = l;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[tile] = red[0];
+}
+
+// Flux part of the output gradient: F_a(x) lowers n at x and raises it at
+// x + e_a, so dL/dF_a(x) = dL/dn(x + e_a) - dL/dn(x) on an open face, 0 on a wall.
+__global__ __launch_bounds__(256) void k_loss_cons_flux(const NTube* __restrict__ tubes,
+                                                        const int32_t* __restrict__ tile_tube, int ntubes, int M,
+                                                        Norm nm, const float* __restrict__ gn_in,
+                                                        bf16* __restrict__ dY)
+{
+  const int tile = blockIdx.x;
+  const NTube tb = tube_of(tubes, tile_tube, ntubes, tile);
+  const int n_t = tb.nx * tb.ny * tb.nz;
+  const int node = (tile - tb.first_tile) * TILE + threadIdx.x;
+  if (node >= n_t) return;
+  const Geo g = geo_of(tb, node);
+  const int64_t gn = tb.base + node;
+  for (int a = 0; a < 3; ++a) {
+    const bool open = face_open(tb, g, a);
+    const int64_t up = open ? shifted(tb, g, a, +1) : gn;
+    for (int s = 0; s < M; ++s) {
+      const float v = open ? (gn_in[up * M + s] - gn_in[gn * M + s]) * nm.out_scale[3 * s + a] : 0.f;
+      dY[gn * COUTL + 3 * s + a] = (bf16)v;
+    }
+  }
 }
 
 // Per-tile moles S_s = sum p X_s / T (species s < M, T at component M, p at
@@ -553,6 +704,8 @@ thread_local std::string g_nn_error;
 // ---------------------------------------------------------------------------
 struct mclbm_nn {
   int C = 0, P = 0, S = 0, depth = 0, ntubes = 0;
+  int Ms = 0;                           // species of the conservative output (0: direct output)
+  int Cout = 0;                         // output channels: C, or 3 Ms + 4
   int64_t n = 0, ntiles = 0;
   hipStream_t stream = nullptr;
   std::string err;
@@ -611,7 +764,7 @@ struct NNLayout {
   int wG;
 };
 
-void layer_sizes(int C, int P, int S, int depth, std::vector<int>& in_r, std::vector<int>& out_r, std::vector<int>& in_p,
+void layer_sizes(int C, int Cout, int P, int S, int depth, std::vector<int>& in_r, std::vector<int>& out_r, std::vector<int>& in_p,
                  std::vector<int>& out_p)
 {
   in_r.assign(depth, WIDTH);
@@ -620,12 +773,18 @@ void layer_sizes(int C, int P, int S, int depth, std::vector<int>& in_r, std::ve
   out_p.assign(depth, WIDTH);
   in_r[0] = C + S;            // parameters; the second terms reuse the field weights
   in_p[0] = CIN0;
-  out_r[depth - 1] = C;
+  out_r[depth - 1] = Cout;
   out_p[depth - 1] = COUTL;
 }
 
-int validate_nn(int C, int P, int S, int depth, const int32_t* dims, int ntubes, std::string& err)
+int out_channels(int C, int Ms) { return Ms > 0 ? 3 * Ms + 4 : C; }
+
+int validate_nn(int C, int P, int S, int Ms, int depth, const int32_t* dims, int ntubes, std::string& err)
 {
+  if (Ms < 0 || (Ms > 0 && (C != Ms + 5 || 3 * Ms + 4 > COUTL))) {
+    err = "a conservative output needs channels = species + 5 (X, T, u, p) and 3 species + 4 <= 32";
+    return MCLBM_EARG;
+  }
   if (C < 1 || C > MAXC || P < 0 || P > C || S < 0 || C + P + S > CIN0) {
     err = "need 1 <= channels <= 16, 0 <= two_term <= channels, conditioning >= 0, "
           "channels + two_term + conditioning <= 32";
@@ -644,7 +803,7 @@ int validate_nn(int C, int P, int S, int depth, const int32_t* dims, int ntubes,
   return MCLBM_OK;
 }
 
-NNLayout nn_layout(int C, int P, int S, int depth, const int32_t* dims, int ntubes)
+NNLayout nn_layout(int C, int P, int S, int Ms, int depth, const int32_t* dims, int ntubes)
 {
   NNLayout l{};
   l.n = 0;
@@ -655,7 +814,7 @@ NNLayout nn_layout(int C, int P, int S, int depth, const int32_t* dims, int ntub
     l.ntiles += (n + TILE - 1) / TILE;
   }
   std::vector<int> in_r, out_r, in_p, out_p;
-  layer_sizes(C, P, S, depth, in_r, out_r, in_p, out_p);
+  layer_sizes(C, out_channels(C, Ms), P, S, depth, in_r, out_r, in_p, out_p);
   l.nparam = 0;
   l.nparam_p = 0;
   size_t wfb = 0, bpb = 0;
@@ -758,27 +917,27 @@ void bgrad(mclbm_nn* net, const bf16* dY, int C, int layer)
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
-extern "C" size_t mclbm_nn_workspace_bytes(int32_t channels, int32_t two_term, int32_t conditioning, int32_t depth,
-                                           const int32_t* dims, int32_t ntubes)
+extern "C" size_t mclbm_nn_workspace_bytes(int32_t channels, int32_t two_term, int32_t conditioning,
+                                           int32_t species, int32_t depth, const int32_t* dims, int32_t ntubes)
 {
   std::string err;
-  if (validate_nn(channels, two_term, conditioning, depth, dims, ntubes, err) != MCLBM_OK) {
+  if (validate_nn(channels, two_term, conditioning, species, depth, dims, ntubes, err) != MCLBM_OK) {
     g_nn_error = err;
     return 0;
   }
-  return nn_layout(channels, two_term, conditioning, depth, dims, ntubes).total;
+  return nn_layout(channels, two_term, conditioning, species, depth, dims, ntubes).total;
 }
 
-extern "C" int mclbm_nn_create(int32_t channels, int32_t two_term, int32_t conditioning, int32_t depth,
-                               const int32_t* dims, int32_t ntubes, void* dev_workspace, size_t bytes,
-                               void* hip_stream, mclbm_nn** out)
+extern "C" int mclbm_nn_create(int32_t channels, int32_t two_term, int32_t conditioning, int32_t species,
+                               int32_t depth, const int32_t* dims, int32_t ntubes, void* dev_workspace,
+                               size_t bytes, void* hip_stream, mclbm_nn** out)
 {
   if (!out) return nn_fail(nullptr, MCLBM_EARG, "out is NULL");
   *out = nullptr;
   std::string err;
-  int rc = validate_nn(channels, two_term, conditioning, depth, dims, ntubes, err);
+  int rc = validate_nn(channels, two_term, conditioning, species, depth, dims, ntubes, err);
   if (rc) return nn_fail(nullptr, rc, err);
-  const NNLayout lay = nn_layout(channels, two_term, conditioning, depth, dims, ntubes);
+  const NNLayout lay = nn_layout(channels, two_term, conditioning, species, depth, dims, ntubes);
   if (!dev_workspace) return nn_fail(nullptr, MCLBM_EARG, "workspace is NULL");
   if (((uintptr_t)dev_workspace) % ALIGN) return nn_fail(nullptr, MCLBM_EARG, "workspace must be 256-byte aligned");
   if (bytes < lay.total) return nn_fail(nullptr, MCLBM_EARG, "workspace too small");
@@ -787,13 +946,15 @@ extern "C" int mclbm_nn_create(int32_t channels, int32_t two_term, int32_t condi
   net->C = channels;
   net->P = two_term;
   net->S = conditioning;
+  net->Ms = species;
+  net->Cout = out_channels(channels, species);
   net->depth = depth;
   net->ntubes = ntubes;
   net->n = lay.n;
   net->ntiles = lay.ntiles;
   net->stream = (hipStream_t)hip_stream;
   net->wG = lay.wG;
-  layer_sizes(channels, two_term, conditioning, depth, net->in_r, net->out_r, net->in_p, net->out_p);
+  layer_sizes(channels, net->Cout, two_term, conditioning, depth, net->in_r, net->out_r, net->in_p, net->out_p);
   int64_t off = 0;
   for (int k = 0; k < depth; ++k) {
     net->w_off.push_back(off);
@@ -858,6 +1019,8 @@ extern "C" int mclbm_nn_create(int32_t channels, int32_t two_term, int32_t condi
   for (int c = 0; c < MAXC; ++c) {
     net->norm.in_shift[c] = 0.f;
     net->norm.in_scale[c] = 1.f;
+  }
+  for (int c = 0; c < COUTL; ++c) {
     net->norm.out_scale[c] = 1.f;
     net->norm.weight[c] = 1.f;
   }
@@ -938,10 +1101,13 @@ extern "C" int mclbm_nn_set_norm(mclbm_nn* net, const float* in_shift, const flo
   if (!net) return MCLBM_EARG;
   if (!in_shift || !in_scale || !out_scale) return nn_fail(net, MCLBM_EARG, "normalisation arrays must be given");
   for (int c = 0; c < net->C; ++c) {
-    if (!(std::isfinite(in_shift[c]) && in_scale[c] > 0.f && out_scale[c] > 0.f))
+    if (!(std::isfinite(in_shift[c]) && in_scale[c] > 0.f))
       return nn_fail(net, MCLBM_EARG, "scales must be positive and shifts finite");
     net->norm.in_shift[c] = in_shift[c];
     net->norm.in_scale[c] = in_scale[c];
+  }
+  for (int c = 0; c < net->Cout; ++c) {
+    if (!(out_scale[c] > 0.f)) return nn_fail(net, MCLBM_EARG, "output scales must be positive");
     net->norm.out_scale[c] = out_scale[c];
   }
   return MCLBM_OK;
@@ -976,8 +1142,12 @@ extern "C" int mclbm_nn_forward(mclbm_nn* net)
   conv<CIN0, WIDTH, 0>(net, net->wf[0], net->bp[0], net->act[0], nullptr, net->act[1], 1);
   for (int k = 1; k + 1 < D; ++k) conv<WIDTH, WIDTH, 0>(net, net->wf[k], net->bp[k], net->act[k], nullptr, net->act[k + 1], 1);
   conv<WIDTH, COUTL, 1>(net, net->wf[D - 1], net->bp[D - 1], net->act[D - 1], nullptr, net->yout, 1);
-  hipLaunchKernelGGL(k_unpack_out, dim3(grid), dim3(256), 0, net->stream, net->dTubes, net->dTileTube, net->ntubes,
-                     net->C, net->norm, net->fin, net->yout, net->fout);
+  if (net->Ms > 0)
+    hipLaunchKernelGGL(k_unpack_cons, dim3(grid), dim3(256), 0, net->stream, net->dTubes, net->dTileTube,
+                       net->ntubes, net->Ms, net->norm, net->fin, net->yout, net->fout);
+  else
+    hipLaunchKernelGGL(k_unpack_out, dim3(grid), dim3(256), 0, net->stream, net->dTubes, net->dTileTube,
+                       net->ntubes, net->C, net->norm, net->fin, net->yout, net->fout);
   return nn_check(net, "mclbm_nn_forward");
 }
 
@@ -987,8 +1157,19 @@ extern "C" int mclbm_nn_loss(mclbm_nn* net, const float* target, const float* ch
   if (!target) return nn_fail(net, MCLBM_EARG, "target is NULL");
   Norm nm = net->norm;
   for (int c = 0; c < net->C; ++c) nm.weight[c] = channel_weight ? channel_weight[c] : 1.f;
-  hipLaunchKernelGGL(k_loss, dim3((unsigned)net->ntiles), dim3(256), 0, net->stream, net->dTubes, net->dTileTube,
-                     net->ntubes, net->C, nm, 1.0 / (double)net->n, net->fin, target, net->yout, net->dyl, net->dpart);
+  const unsigned grid = (unsigned)net->ntiles;
+  if (net->Ms > 0) {
+    // dL/dn per node in the first activation-gradient buffer (free until backward)
+    float* gnode = (float*)net->dy[0];
+    hipLaunchKernelGGL(k_loss_cons, dim3(grid), dim3(256), 0, net->stream, net->dTubes, net->dTileTube,
+                       net->ntubes, net->Ms, nm, 1.0 / (double)net->n, net->fout, target, gnode, net->dyl,
+                       net->dpart);
+    hipLaunchKernelGGL(k_loss_cons_flux, dim3(grid), dim3(256), 0, net->stream, net->dTubes, net->dTileTube,
+                       net->ntubes, net->Ms, nm, gnode, net->dyl);
+  } else {
+    hipLaunchKernelGGL(k_loss, dim3(grid), dim3(256), 0, net->stream, net->dTubes, net->dTileTube, net->ntubes,
+                       net->C, nm, 1.0 / (double)net->n, net->fin, target, net->yout, net->dyl, net->dpart);
+  }
   int rc = nn_check(net, "k_loss");
   if (rc) return rc;
   std::vector<double> part(net->ntiles);
@@ -1069,9 +1250,10 @@ extern "C" int mclbm_nn_mole_residual(mclbm_nn* net, int32_t species, const floa
   return MCLBM_OK;
 }
 
-void mclbm::nn::geometry(const mclbm_nn* net, int* channels, std::vector<int>* dims)
+void mclbm::nn::geometry(const mclbm_nn* net, int* channels, int* species, std::vector<int>* dims)
 {
   *channels = net->C;
+  *species = net->Ms;
   dims->clear();
   for (const NTube& tb : net->hTubes) {
     dims->push_back(tb.nx);

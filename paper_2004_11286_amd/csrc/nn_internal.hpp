@@ -9,8 +9,9 @@
 namespace mclbm {
 namespace nn {
 
-// Channels and [ntubes][3] tube sizes (nx, ny, nz) of a network.
-void geometry(const mclbm_nn* net, int* channels, std::vector<int>* dims);
+// Channels, output form (species of the conservative output, 0 = direct) and
+// [ntubes][3] tube sizes (nx, ny, nz) of a network.
+void geometry(const mclbm_nn* net, int* channels, int* species, std::vector<int>* dims);
 
 }  // namespace nn
 }  // namespace mclbm

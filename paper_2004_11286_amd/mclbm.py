@@ -98,10 +98,10 @@ def _load():
     L.mclbm_autotune.argtypes = [vp, C.c_int32, C.c_char_p, C.c_size_t]
     ip = C.POINTER(C.c_int32)
     fp = C.POINTER(C.c_float)
-    L.mclbm_nn_workspace_bytes.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, ip, C.c_int32]
+    L.mclbm_nn_workspace_bytes.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, ip, C.c_int32]
     L.mclbm_nn_workspace_bytes.restype = C.c_size_t
-    L.mclbm_nn_create.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, ip, C.c_int32, vp, C.c_size_t, vp,
-                                  C.POINTER(vp)]
+    L.mclbm_nn_create.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, ip, C.c_int32, vp,
+                                  C.c_size_t, vp, C.POINTER(vp)]
     L.mclbm_nn_set_conditioning.argtypes = [vp, fp]
     L.mclbm_nn_destroy.argtypes = [vp]
     L.mclbm_nn_destroy.restype = None
@@ -519,20 +519,22 @@ def _f32p(a):
     return a.ctypes.data_as(C.POINTER(C.c_float))
 
 
-def mclbm_nn_workspace_bytes(channels: int, two_term: int, conditioning: int, depth: int, dims) -> int:
+def mclbm_nn_workspace_bytes(channels: int, two_term: int, conditioning: int, species: int, depth: int,
+                             dims) -> int:
     d, dp_ = _dims_array(dims)
-    n = lib.mclbm_nn_workspace_bytes(int(channels), int(two_term), int(conditioning), int(depth), dp_, d.size // 3)
+    n = lib.mclbm_nn_workspace_bytes(int(channels), int(two_term), int(conditioning), int(species), int(depth),
+                                     dp_, d.size // 3)
     if n == 0:
         raise MclbmError(MCLBM_EARG, lib.mclbm_nn_last_error(None).decode())
     return int(n)
 
 
-def mclbm_nn_create(channels: int, two_term: int, conditioning: int, depth: int, dims, workspace_ptr: int,
-                    nbytes: int, stream: int):
+def mclbm_nn_create(channels: int, two_term: int, conditioning: int, species: int, depth: int, dims,
+                    workspace_ptr: int, nbytes: int, stream: int):
     d, dp_ = _dims_array(dims)
     h = C.c_void_p()
-    _nn_check(None, lib.mclbm_nn_create(int(channels), int(two_term), int(conditioning), int(depth), dp_,
-                                        d.size // 3, C.c_void_p(workspace_ptr), nbytes, C.c_void_p(stream),
+    _nn_check(None, lib.mclbm_nn_create(int(channels), int(two_term), int(conditioning), int(species), int(depth),
+                                        dp_, d.size // 3, C.c_void_p(workspace_ptr), nbytes, C.c_void_p(stream),
                                         C.byref(h)))
     return h
 
@@ -626,24 +628,26 @@ class Net:
     fields_in / fields_out are views of the network's own device buffers
     ([channels][n] per tube, concatenated)."""
 
-    def __init__(self, channels: int, depth: int, dims, conditioning: int = 0, two_term: int = 0,
+    def __init__(self, channels: int, depth: int, dims, conditioning: int = 0, two_term: int = 0, species: int = 0,
                  device: str = "cuda:0", stream=None):
         import torch
 
         self.C = int(channels)
         self.P = int(two_term)
         self.S = int(conditioning)
+        self.Ms = int(species)
+        self.Cout = 3 * self.Ms + 4 if self.Ms else self.C
         self.depth = int(depth)
         self.dims = [tuple(int(v) for v in d) for d in dims]
         self.sizes = [nx * ny * nz for nx, ny, nz in self.dims]
         self.n = int(sum(self.sizes))
         self.device = torch.device(device)
-        nbytes = mclbm_nn_workspace_bytes(self.C, self.P, self.S, self.depth, self.dims)
+        nbytes = mclbm_nn_workspace_bytes(self.C, self.P, self.S, self.Ms, self.depth, self.dims)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         with torch.cuda.device(self.device):
-            self.net = mclbm_nn_create(self.C, self.P, self.S, self.depth, self.dims, self.workspace.data_ptr(),
-                                       nbytes, self.stream.cuda_stream)
+            self.net = mclbm_nn_create(self.C, self.P, self.S, self.Ms, self.depth, self.dims,
+                                       self.workspace.data_ptr(), nbytes, self.stream.cuda_stream)
         pin, pout = mclbm_nn_io(self.net)
         base = self.workspace.data_ptr()
         count = self.C * self.n

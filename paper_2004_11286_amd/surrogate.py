@@ -53,46 +53,57 @@ def trajectories(tubes: list, K: int = K_DEFAULT, nsnap: int = 50, precision: in
     return snaps, dims
 
 
-def channel_stats(snaps, dims, C: int):
-    """Per-channel mean and standard deviation of the fields and of their change
-    over one interval (host, from a subsample of nodes)."""
-    x = snaps.cpu().numpy()
+def molar_densities(x: np.ndarray, M: int) -> np.ndarray:
+    """n_s = p X_s / T from fields [..., C, n] (X_1..X_M, T, u, p)."""
+    return x[..., M + 4:M + 5, :] * x[..., :M, :] / x[..., M:M + 1, :]
+
+
+def _tube_views(x, dims, C, stride=256):
+    """Per tube: [snapshots][C][subsampled nodes] views of the flat snapshots."""
     sizes = [nx * ny * nz for nx, ny, nz in dims]
     off = np.concatenate([[0], np.cumsum(sizes)])
-    per_c = [[] for _ in range(C)]
-    per_d = [[] for _ in range(C)]
     for t, n in enumerate(sizes):
-        seg = x[:, C * off[t]:C * off[t + 1]].reshape(x.shape[0], C, n)[:, :, ::max(1, n // 256)]
-        for c in range(C):
-            per_c[c].append(seg[:, c].ravel())
-            per_d[c].append((seg[1:, c] - seg[:-1, c]).ravel())
-    mean = np.array([np.concatenate(v).mean() for v in per_c])
-    std = np.array([np.concatenate(v).std() for v in per_c])
-    dstd = np.array([np.concatenate(v).std() for v in per_d])
-    return mean, std, dstd
+        yield x[:, C * off[t]:C * off[t + 1]].reshape(x.shape[0], C, n)[:, :, ::max(1, n // stride)]
+
+
+def channel_stats(snaps, dims, M: int) -> dict:
+    """Spreads from the trajectories (host, subsampled nodes): of every field,
+    of its change over one interval, and of the change of each molar density
+    n_s (per interval, for the loss weights)."""
+    x = snaps.cpu().numpy().astype(np.float64)
+    C = channels(M)
+    segs = list(_tube_views(x, dims, C))
+    allf = np.concatenate([s for s in segs], axis=2)
+    d = allf[1:] - allf[:-1]
+    n = np.concatenate([molar_densities(s, M) for s in segs], axis=2)
+    dn = n[1:] - n[:-1]
+    return {"mean": allf.mean(axis=(0, 2)), "std": allf.std(axis=(0, 2)), "dstd": d.std(axis=(0, 2)),
+            "dn_std": dn.std(axis=(0, 2)), "dn_ms_pair": (dn ** 2).mean(axis=2)}
 
 
 IN_FLOOR = 1e-3      # smallest input spread used for scaling (T and u vary by ~1e-3)
 OUT_FLOOR = 1e-4     # smallest output unit (a channel that never changes, e.g. u_y in a 1-D tube)
 
 
-def norm_from_stats(mean, std, dstd):
-    """Inputs to zero mean and unit spread, outputs in units of the typical
-    change; floors keep channels that (almost) never vary from being blown up
-    to round-off."""
-    in_scale = 1.0 / np.maximum(std, IN_FLOOR)
-    out_scale = np.maximum(dstd, OUT_FLOOR)
-    return {"in_shift": mean.astype(np.float32), "in_scale": in_scale.astype(np.float32),
-            "out_scale": out_scale.astype(np.float32)}
+def norm_from_stats(st: dict, M: int) -> dict:
+    """Inputs to zero mean and unit spread; outputs (conservative form): the
+    fluxes of n_s in units of the typical change of n_s, T and u in units of
+    their typical change; floors keep channels that (almost) never vary from
+    being blown up to round-off."""
+    in_scale = 1.0 / np.maximum(st["std"], IN_FLOOR)
+    flux = np.repeat(np.maximum(st["dn_std"], 1e-7), 3)
+    tu = np.maximum(st["dstd"][M:M + 4], OUT_FLOOR)
+    return {"in_shift": st["mean"].astype(np.float32), "in_scale": in_scale.astype(np.float32),
+            "out_scale": np.concatenate([flux, tu]).astype(np.float32)}
 
 
-def he_init(C: int, S: int, depth: int, seed: int) -> np.ndarray:
+def he_init(C: int, S: int, depth: int, seed: int, out: int) -> np.ndarray:
     """He-normal weights for the ReLU layers, a small last layer, zero biases
     (host order of include/mclbm_nn.h)."""
     rng = np.random.default_rng(seed)
     width = 64
     ins = [C + S] + [width] * (depth - 1)
-    outs = [width] * (depth - 1) + [C]
+    outs = [width] * (depth - 1) + [out]
     parts = []
     for k, (o, i) in enumerate(zip(outs, ins)):
         std = np.sqrt(2.0 / (27 * i)) * (1.0 if k < depth - 1 else 0.1)
@@ -101,62 +112,45 @@ def he_init(C: int, S: int, depth: int, seed: int) -> np.ndarray:
 
 
 def build_net(dims, tubes_params, norm, M: int, depth: int = DEPTH, params=None, seed: int = 0):
-    """The surrogate over these tubes: the M mole fractions also as second BF16
-    terms, the tube constants as conditioning channels."""
+    """The surrogate over these tubes: conservative output form (species moles
+    kept exactly), the M mole fractions also as second BF16 terms, the tube
+    constants as conditioning channels."""
     C = channels(M)
     cond = np.stack([conditioning(p) for p in tubes_params])
-    net = mc.Net(C, depth, dims, conditioning=cond.shape[1], two_term=M)
+    net = mc.Net(C, depth, dims, conditioning=cond.shape[1], two_term=M, species=M)
     net.set_conditioning(cond)
     net.set_norm(norm["in_shift"], norm["in_scale"], norm["out_scale"])
-    net.set_params(he_init(C, cond.shape[1], depth, seed) if params is None else params)
+    net.set_params(he_init(C, cond.shape[1], depth, seed, 3 * M + 4) if params is None else params)
     return net
 
 
-def channel_weights(M: int) -> np.ndarray:
-    """The mole fractions are what the surrogate is judged on."""
-    return np.array([1.0] * M + [0.2] + [0.1] * 3 + [0.2], dtype=np.float32)
-
-
-def pair_weights(snaps, dims, out_scale, M: int, floor: float = 1e-2) -> np.ndarray:
-    """Channel weights per snapshot pair: for the mole fractions, the base weight
-    divided by the pair's mean squared change in output units, so that late, slow
-    intervals count as much as early ones (a relative error); T and u keep their
-    base weights. Returns [nsnap][C]."""
-    x = snaps.cpu().numpy()
+def pair_weights(st: dict, M: int, floor_frac: float = 1e-2) -> np.ndarray:
+    """Loss weights per snapshot pair in physical units: the molar densities by
+    the pair's own mean squared change (a relative error, so late, slow
+    intervals count as much as early ones), T and u by their typical change at
+    weights 0.2 and 0.1, p unused. Returns [nsnap][C]."""
     C = channels(M)
-    sizes = [nx * ny * nz for nx, ny, nz in dims]
-    off = np.concatenate([[0], np.cumsum(sizes)])
-    base = channel_weights(M).astype(np.float64)
-    out = np.zeros((x.shape[0] - 1, C), dtype=np.float32)
-    for j in range(x.shape[0] - 1):
-        acc = np.zeros(C)
-        cnt = 0
-        for t, n in enumerate(sizes):
-            a = x[j, C * off[t]:C * off[t + 1]].reshape(C, n)[:, ::max(1, n // 256)].astype(np.float64)
-            b = x[j + 1, C * off[t]:C * off[t + 1]].reshape(C, n)[:, ::max(1, n // 256)].astype(np.float64)
-            acc += np.sum(((b - a) / np.asarray(out_scale, np.float64)[:, None]) ** 2, axis=1)
-            cnt += a.shape[1]
-        ms = acc / cnt
-        w = base.copy()
-        w[:M] = base[:M] / np.maximum(ms[:M], floor)
-        out[j] = w.astype(np.float32)
-    return out
+    ms = st["dn_ms_pair"]
+    floor = floor_frac * ms.mean(axis=0)
+    out = np.zeros((ms.shape[0], C), dtype=np.float64)
+    out[:, :M] = 1.0 / np.maximum(ms, floor)
+    out[:, M] = 0.2 / np.maximum(st["dstd"][M], OUT_FLOOR) ** 2
+    out[:, M + 1:M + 4] = 0.1 / np.maximum(st["dstd"][M + 1:M + 4], OUT_FLOOR) ** 2
+    return out.astype(np.float32)
 
 
-def train(net, snaps, iters: int, lr: float = LR, seed: int = 0, log_every: int = 0, weights=None):
+def train(net, snaps, iters: int, weights, lr: float = LR, seed: int = 0, log_every: int = 0):
     """Adam on random (t, t + K) snapshot pairs of all tubes at once, with a
-    cosine learning-rate decay. weights: per-pair channel weights [nsnap][C]
-    (default: the base channel weights). Returns the loss history."""
+    cosine learning-rate decay; weights: per-pair channel weights [nsnap][C].
+    Returns the loss history."""
     rng = np.random.default_rng(seed)
-    base = channel_weights(net.C - 5)
     losses = []
     nsnap = snaps.shape[0] - 1
     for it in range(iters):
         j = int(rng.integers(0, nsnap))
-        w = base if weights is None else weights[j]
         net.fields_in.copy_(snaps[j])
         net.forward()
-        losses.append(net.loss(snaps[j + 1], w))
+        losses.append(net.loss(snaps[j + 1], weights[j]))
         net.backward()
         lr_it = lr * 0.5 * (1.0 + np.cos(np.pi * it / iters)) + 0.02 * lr
         net.adam_step(lr_it)
@@ -241,19 +235,20 @@ def evaluate(params, norm, eval_tubes, K: int = K_DEFAULT, starts=(0, 500, 2000)
     return out
 
 
-def conv_flops_per_node(C: int, S: int, depth: int = DEPTH, width: int = 64) -> float:
-    """Multiply-adds x 2 of one forward pass per node over the real input
-    channels of layer 0 (fields, second terms and conditioning: C + S)."""
+def conv_flops_per_node(C: int, S: int, out: int, depth: int = DEPTH, width: int = 64) -> float:
+    """Multiply-adds x 2 of one forward pass per node over the real channels
+    (layer 0: fields, second terms and conditioning, C + S inputs; last layer:
+    out outputs)."""
     ins = [C + S] + [width] * (depth - 1)
-    outs = [width] * (depth - 1) + [C]
+    outs = [width] * (depth - 1) + [out]
     return float(sum(2 * 27 * o * i for o, i in zip(outs, ins)))
 
 
-def timed_train_step(net, snaps, reps: int = 5):
+def timed_train_step(net, snaps, weights, reps: int = 5):
     """Milliseconds of one forward + loss + backward + Adam step (mean of reps)."""
     import torch
 
-    w = channel_weights(net.C - 5)
+    w = weights[0]
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     net.fields_in.copy_(snaps[0])
     t0 = time.perf_counter()

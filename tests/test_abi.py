@@ -112,14 +112,16 @@ def test_launch_struct_matches_header():
 def test_nn_workspace_and_validation():
     m = pytest.importorskip("paper_2004_11286_amd.mclbm")
     dims = [(13, 4, 3), (40, 2, 5)]
-    b = m.mclbm_nn_workspace_bytes(7, 0, 0, 6, dims)
+    b = m.mclbm_nn_workspace_bytes(7, 0, 0, 0, 6, dims)
     n = 13 * 12 + 40 * 10
     assert b > 5 * n * 64 * 2                     # the hidden activations dominate
-    assert b < m.mclbm_nn_workspace_bytes(7, 0, 0, 6, dims + [(64, 8, 8)])
-    assert m.mclbm_nn_workspace_bytes(7, 3, 6, 6, dims) >= b
-    assert m.mclbm_nn_workspace_bytes(8, 3, 6, 6, dims) > 0            # 17 input channels fit in 32
-    for bad in [(0, 0, 0, 6, dims), (17, 0, 0, 6, dims), (16, 16, 1, 6, dims), (7, 8, 0, 6, dims),
-                (7, 0, -1, 6, dims), (7, 0, 0, 1, dims), (7, 0, 0, 6, [(0, 4, 4)])]:
+    assert b < m.mclbm_nn_workspace_bytes(7, 0, 0, 0, 6, dims + [(64, 8, 8)])
+    assert m.mclbm_nn_workspace_bytes(7, 3, 6, 0, 6, dims) >= b
+    assert m.mclbm_nn_workspace_bytes(8, 3, 6, 3, 6, dims) > 0            # conservative: 3 species, 13 outputs
+    assert m.mclbm_nn_workspace_bytes(8, 3, 6, 0, 6, dims) > 0            # 17 input channels fit in 32
+    for bad in [(0, 0, 0, 0, 6, dims), (17, 0, 0, 0, 6, dims), (16, 16, 1, 0, 6, dims), (7, 8, 0, 0, 6, dims),
+                (7, 0, -1, 0, 6, dims), (7, 0, 0, 0, 1, dims), (7, 0, 0, 0, 6, [(0, 4, 4)]),
+                (7, 0, 0, 3, 6, dims), (15, 0, 0, 10, 6, dims)]:
         with pytest.raises(m.MclbmError):
             m.mclbm_nn_workspace_bytes(*bad)
 

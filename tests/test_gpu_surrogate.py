@@ -251,18 +251,18 @@ def test_trained_on_lattice_trajectories(env):
     tubes. The trained network's mole-fraction RMS error must be below that of
     the persistence prediction (no change) over the early intervals, where the
     fields change most, and its forward pass must be faster than the K lattice
-    steps it replaces; the advance entry point must accept exactly the hops
-    whose mole residual is within the tolerance."""
+    steps it replaces; the conservative output keeps the moles (residual within
+    the tolerance) and the advance entry point accepts exactly such hops."""
     from paper_2004_11286_amd import surrogate as SG
 
     mc, torch = env
     train_tubes = W.tube_ensemble(ntubes=64, ny=4, nz=4, seed=11286)
     snaps, dims = SG.trajectories(train_tubes, K=100, nsnap=50)
-    mean, std, dstd = SG.channel_stats(snaps, dims, C)
-    norm = SG.norm_from_stats(mean, std, dstd)
+    st = SG.channel_stats(snaps, dims, 3)
+    norm = SG.norm_from_stats(st, 3)
+    pw = SG.pair_weights(st, 3)
     net = SG.build_net(dims, [p for p, _ in train_tubes], norm, 3)
-    pw = SG.pair_weights(snaps, dims, norm["out_scale"], 3)
-    losses = SG.train(net, snaps, 1500, lr=3e-4, weights=pw)
+    losses = SG.train(net, snaps, 1500, pw, lr=3e-4)
     params = net.get_params()
     net.close()
     print("loss", np.mean(losses[:50]), "->", np.mean(losses[-50:]))
@@ -272,4 +272,86 @@ def test_trained_on_lattice_trajectories(env):
         print(res)
         assert res["X_rms"] < 0.9 * res["X_rms_persistence"]
         assert res["ms_forward"] < res["ms_lattice"]
+        assert res["mole_residual_max"] <= 1e-5
         assert res["accepted"] == (res["mole_residual_max"] <= 1e-4)
+
+
+def cons_fields(seed, dims=DIMS, M=3):
+    """Physical fields X_1..X_3, T, u, p with the conservative layout."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for nx, ny, nz in dims:
+        shape = (nz, ny, nx)
+        X = rng.dirichlet([3.0] * M, size=shape).transpose(3, 0, 1, 2)
+        out.append(np.concatenate([X, rng.uniform(0.3, 0.36, (1,) + shape), rng.normal(0, 1e-3, (3,) + shape),
+                                   rng.uniform(0.02, 0.03, (1,) + shape)]))
+    return out
+
+
+CONS_SCALE = np.array([3e-4] * 9 + [1e-3, 3e-4, 3e-4, 3e-4], np.float32)
+
+
+def cons_net(env, depth, p, cond=None):
+    mc, _ = env
+    net = mc.Net(C, depth, DIMS, conditioning=0 if cond is None else cond.shape[1], two_term=3, species=3)
+    if cond is not None:
+        net.set_conditioning(cond)
+    nm = {"in_shift": np.array([0.33] * 3 + [0.33, 0, 0, 0, 0.025], np.float32),
+          "in_scale": np.array([3.0] * 3 + [30.0, 300, 300, 300, 100], np.float32), "out_scale": CONS_SCALE}
+    net.set_norm(nm["in_shift"], nm["in_scale"], nm["out_scale"])
+    net.set_params(p)
+    return net, {k: np.asarray(v, np.float32).astype(np.float64) for k, v in nm.items()}
+
+
+def test_conservative_forward_matches_oracle_and_keeps_moles(env):
+    depth, Sn = 3, 6
+    p = S.he_init(C, depth, seed=31, S=Sn, species=3)
+    p += np.random.default_rng(32).normal(0, 0.01, p.size).astype(np.float32)
+    cond = np.random.default_rng(33).uniform(-1, 1, (len(DIMS), Sn)).astype(np.float32)
+    net, nm = cons_net(env, depth, p, cond)
+    fs = [f.astype(np.float32).astype(np.float64) for f in cons_fields(34)]
+    fin = flat(env, fs)
+    out = net.forward(fin).cpu().numpy()
+    res = net.mole_residual(3, fin, net.fields_out)
+    net.close()
+    print("conservative mole residual", res)
+    assert np.all(res < 2e-6)
+    for t, (f, g) in enumerate(zip(fs, split(out))):
+        _, pred, _ = S.forward(p, f, nm, C, depth, round_bf16=True, cond=cond[t].astype(np.float64), P=3, species=3)
+        for lo, hi, name in ((0, 3, "X"), (3, 4, "T"), (4, 7, "u"), (7, 8, "p")):
+            change = np.abs(pred[lo:hi] - f[lo:hi]).max()
+            err = np.abs(g[lo:hi] - pred[lo:hi]).max()
+            print("conservative forward tube", t, name, "err / change", err / change)
+            assert err <= 1e-2 * change + 1e-6 * np.abs(pred[lo:hi]).max(), (t, name, err, change)
+
+
+def test_conservative_gradients_match_oracle(env):
+    depth = 3
+    p = S.he_init(C, depth, seed=35, species=3)
+    p += np.random.default_rng(36).normal(0, 0.02, p.size).astype(np.float32)
+    net, nm = cons_net(env, depth, p)
+    fs = [f.astype(np.float32).astype(np.float64) for f in cons_fields(37)]
+    rng = np.random.default_rng(38)
+    tg = []
+    for f in fs:
+        t, _ = S.conservative_fields(f, rng.normal(size=(13,) + f.shape[1:]), nm["out_scale"], 3)
+        tg.append(t.astype(np.float32).astype(np.float64))
+    w = np.array([1e6, 1e6, 1e6, 1e4, 1e5, 1e5, 1e5, 0.0], np.float32)
+    net.zero_grad()
+    net.forward(flat(env, fs))
+    loss = net.loss(flat(env, tg), w)
+    net.backward()
+    g_gpu = net.get_grads().astype(np.float64)
+    net.close()
+    L_ref, g_ref = S.loss_and_grad(p, fs, tg, nm, C, depth, weight=w.astype(np.float64), round_bf16=True, P=3,
+                                   species=3)
+    print("conservative loss", loss, L_ref)
+    assert loss == pytest.approx(L_ref, rel=1e-2)
+    k = 0
+    for li, (o, i) in enumerate(S.layer_shapes(C, depth, species=3)):
+        for name, size in (("W", 27 * o * i), ("b", o)):
+            a, b = g_gpu[k:k + size], g_ref[k:k + size]
+            k += size
+            rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+            print("conservative grad layer", li, name, "rel 2-norm", rel)
+            assert rel < 2e-2, (li, name, rel)

@@ -186,3 +186,80 @@ def test_two_term_encoding_resolves_16_bits():
     assert np.all(S.bf16(hi) == hi) and np.all(S.bf16(lo) == lo)
     assert np.abs(v32 - hi).max() <= np.abs(v32).max() * 2 ** -8          # one term: ~8 bits
     assert np.all(np.abs(v32 - (hi + lo / 256)) <= np.abs(v32) * 2 ** -15)  # two terms: ~16 bits
+
+
+def _cons_problem(seed=12, M=3, shape=(3, 4, 6)):
+    rng = np.random.default_rng(seed)
+    f = np.concatenate([rng.dirichlet([2.0] * M, size=shape).transpose(3, 0, 1, 2),
+                        rng.uniform(0.3, 0.4, (1,) + shape), rng.normal(0, 1e-3, (3,) + shape),
+                        rng.uniform(0.02, 0.03, (1,) + shape)])
+    y = rng.normal(size=(3 * M + 4,) + shape)
+    scale = np.concatenate([np.full(3 * M, 1e-4), [1e-3, 1e-4, 1e-4, 1e-4]])
+    return f, y, scale
+
+
+def test_conservative_output_keeps_moles_exactly():
+    M = 3
+    f, y, scale = _cons_problem(M=M)
+    fo, n1 = S.conservative_fields(f, y, scale, M)
+    moles = lambda g: np.array([np.sum(g[M + 4] * g[s] / g[M]) for s in range(M)])
+    np.testing.assert_allclose(moles(fo), moles(f), rtol=1e-12)
+    np.testing.assert_allclose(fo[:M].sum(axis=0), 1.0, rtol=1e-14)
+    np.testing.assert_allclose(fo[M + 4], fo[M] * n1.sum(axis=0), rtol=1e-14)
+    assert S.mole_residual(f, fo, M) < 1e-12
+    # a flux on the wall face (x = nx - 1, +x direction) changes nothing
+    y2 = np.zeros_like(y)
+    y2[0][..., -1] = 5.0
+    fo2, _ = S.conservative_fields(f, y2, scale, M)
+    np.testing.assert_allclose(fo2, f, rtol=1e-14, atol=1e-16)
+    # an interior +x flux moves moles from x to x + 1 only
+    y3 = np.zeros_like(y)
+    y3[0][1, 2, 3] = 1.0
+    _, n3 = S.conservative_fields(f, y3, scale, M)
+    n0 = f[M + 4] * f[:M] / f[M]
+    d = n3[0] - n0[0]
+    assert d[1, 2, 3] == pytest.approx(-1e-4) and d[1, 2, 4] == pytest.approx(1e-4)
+    assert np.count_nonzero(np.abs(d) > 1e-15) == 2
+
+
+def test_conservative_loss_gradient_matches_central_differences():
+    """The adjoint of the divergence and of p = T sum n, X = n / sum n."""
+    M = 3
+    f, y, scale = _cons_problem(seed=13, M=M)
+    tgt, _ = S.conservative_fields(f, 0.3 * np.random.default_rng(14).normal(size=y.shape), scale, M)
+    w = np.array([1e6, 2e6, 5e5, 1e4, 1e5, 1e5, 1e5, 0.0])
+    N = f[0].size
+    L, dy = S.conservative_loss(f, y, tgt, w, scale, M, N)
+    rng = np.random.default_rng(15)
+    h = 1e-6
+    for _ in range(40):
+        idx = tuple(int(rng.integers(0, s)) for s in y.shape)
+        yp, ym = y.copy(), y.copy()
+        yp[idx] += h
+        ym[idx] -= h
+        fd = (S.conservative_loss(f, yp, tgt, w, scale, M, N)[0] - S.conservative_loss(f, ym, tgt, w, scale, M, N)[0]) / (2 * h)
+        assert dy[idx] == pytest.approx(fd, rel=1e-5, abs=1e-12), idx
+
+
+def test_network_gradient_conservative_form():
+    C, depth, width, M = 8, 3, 4, 3
+    rng = np.random.default_rng(16)
+    fs, tg = [], []
+    for shape in [(2, 3, 5), (3, 2, 4)]:
+        f, _, scale = _cons_problem(seed=int(rng.integers(100)), M=M, shape=shape)
+        t, _ = S.conservative_fields(f, 0.5 * rng.normal(size=(3 * M + 4,) + shape), scale, M)
+        fs.append(f)
+        tg.append(t)
+    norm = {"in_shift": np.full(C, 0.2), "in_scale": np.full(C, 3.0), "out_scale": scale}
+    p = S.he_init(C, depth, 17, width=width, gain=3.0, species=M).astype(np.float64)
+    p += 0.1 * rng.normal(size=p.size)
+    w = np.array([1e6, 1e6, 1e6, 1e4, 1e5, 1e5, 1e5, 0.0])
+    L, g = S.loss_and_grad(p, fs, tg, norm, C, depth, width, weight=w, species=M)
+    h = 1e-6
+    for k in rng.choice(p.size, 30, replace=False):
+        pp, pm = p.copy(), p.copy()
+        pp[k] += h
+        pm[k] -= h
+        Lp, _ = S.loss_and_grad(pp, fs, tg, norm, C, depth, width, weight=w, species=M)
+        Lm, _ = S.loss_and_grad(pm, fs, tg, norm, C, depth, width, weight=w, species=M)
+        assert g[k] == pytest.approx((Lp - Lm) / (2 * h), rel=2e-5, abs=1e-10), k
