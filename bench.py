@@ -179,12 +179,13 @@ def ensemble_bench(mc, steps: int = 50, seq_steps: int = 10, trial_steps: int = 
         ms = e0.elapsed_time(e1)
         return {"MLUPS": n * k / (ms * 1e-3) / 1e6, "ms_per_step": ms / k}
 
-    base = dict(variant=0, swizzle=0, order=0, graph_steps=0, sequential=0)
+    base = dict(variant=0, swizzle=0, order=0, graph_steps=0, sequential=0, split=0)
     out = {"workload": "512 ternary tubes L~U{32..256}x16x16 with walls, FP32 storage, one context",
            "nodes": n, "tubes": len(tubes)}
     out["sequential"] = timed(seq_steps, **dict(base, sequential=1))
     out["batched"] = timed(steps, **base)
     out["batched_graph"] = timed(steps, **dict(base, graph_steps=10))
+    out["batched_split"] = timed(steps, **dict(base, split=1))
     report = b.autotune(trial_steps)
     out["autotune_report"] = report.strip().splitlines()
     chosen = b.launch()
@@ -202,7 +203,7 @@ def ensemble_bench(mc, steps: int = 50, seq_steps: int = 10, trial_steps: int = 
 BF16_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix-core peak
 
 
-def surrogate_bench(train_iters: int = 3000):
+def surrogate_bench(train_iters: int = 6000):
     """The learned surrogate: trained by the library's BF16 MFMA kernels on
     trajectories of a 64-tube ensemble (every 100 steps up to 5000), then judged
     by the lattice on eight held-out 128 x 32 x 32 ternary tubes (1 M nodes):
@@ -269,7 +270,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
-    ap.add_argument("--surrogate-iters", type=int, default=3000)
+    ap.add_argument("--surrogate-iters", type=int, default=6000)
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes five times (to scale HBM counters)")
     args = ap.parse_args()

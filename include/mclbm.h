@@ -157,7 +157,10 @@ int mclbm_kernel_stats(mclbm_ctx *c, int32_t kernel, double *total_ms, int64_t *
                        const char **name);
 
 /* How mclbm_step launches its kernels. Every choice computes bit for bit the same
- * step; only the time differs. */
+ * step, except split, whose two kernels are compiled separately and may fuse a
+ * multiply-add differently: its results agree to rounding (and, with 16-bit
+ * storage, to the stochastic rounding that such a last-bit difference can flip).
+ * Only the time differs. */
 typedef struct {
   int32_t variant;      /* occupancy variant of the moments and collide kernels, 0 or 1 */
   int32_t swizzle;      /* 1: each XCD takes a contiguous run of blocks                  */
@@ -165,17 +168,21 @@ typedef struct {
   int32_t graph_steps;  /* 0: launch each kernel of each step; K > 0 (even): replay a
                            HIP graph of K captured steps (not while timing is enabled)   */
   int32_t sequential;   /* 1: launch every tube on its own (the unbatched reference)     */
-  int32_t reserved[3];  /* must be 0                                                     */
+  int32_t split;        /* 1: collide the species lattices, then the momentum and energy
+                           lattices, in two launches with fewer registers each
+                           (occupancy variant 0)                                        */
+  int32_t reserved[2];  /* must be 0                                                     */
 } mclbm_launch;
 
 int mclbm_get_launch(const mclbm_ctx *c, mclbm_launch *out);
 int mclbm_set_launch(mclbm_ctx *c, const mclbm_launch *in);
 
-/* Time every batched launch choice (variant x swizzle x order x graph on/off)
- * over trial_steps steps each on the current state, keep the fastest, and write
- * a text table of the candidates (milliseconds per step) to report (may be NULL).
- * The trial steps are ordinary steps: the state and the step count advance by
- * (number of candidates) * trial_steps. Synchronises the stream. */
+/* Time every batched launch choice ((variant, split) in {(0,0), (1,0), (0,1)} x
+ * swizzle x order x graph on/off) over trial_steps steps each on the current
+ * state, keep the fastest, and write a text table of the candidates
+ * (milliseconds per step) to report (may be NULL). The trial steps are ordinary
+ * steps: the state and the step count advance by about (number of candidates) *
+ * 2 trial_steps. Synchronises the stream. */
 int mclbm_autotune(mclbm_ctx *c, int32_t trial_steps, char *report, size_t report_len);
 
 #ifdef __cplusplus

@@ -108,8 +108,13 @@ __global__ __launch_bounds__(BLOCK) void k_gfield(const Params<double>* __restri
   if (w.node < Pt.n) gfield_node<Rec, W>(Pt, rec + (size_t)rec_fields * w.base, G + 3 * w.base, w.node);
 }
 
-template <typename S, typename R, typename Rec, int M, bool W, int V>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(collide_waves<S, M, V>()))) void k_collide(const Params<R>* __restrict__ P, Launch Ln, const S* __restrict__ src,
+// PART 0: all lattices; 1 and 2: the species lattices, then the momentum and
+// energy lattices, as two launches with fewer registers each (a launch choice).
+template <typename S, int M, int V, int PART>
+constexpr int collide_part_waves() { return PART == 0 ? collide_waves<S, M, V>() : 2; }
+
+template <typename S, typename R, typename Rec, int M, bool W, int V, int PART>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(collide_part_waves<S, M, V, PART>()))) void k_collide(const Params<R>* __restrict__ P, Launch Ln, const S* __restrict__ src,
                                                    S* __restrict__ dst, const Rec* __restrict__ rec,
                                                    const Rec* __restrict__ G, StepNo sn)
 {
@@ -117,8 +122,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(collide_w
   const Params<R>& Pt = P[w.t];
   if (w.node < Pt.n) {
     const size_t po = pop_stride<M>() * w.base;
-    collide_node<S, R, Rec, M, W>(Pt, src + po, dst + po, rec + (size_t)RecLayout<M>::FIELDS * w.base,
-                                  G + 3 * w.base, w.node, step_of(sn));
+    collide_node<S, R, Rec, M, W, PART>(Pt, src + po, dst + po, rec + (size_t)RecLayout<M>::FIELDS * w.base,
+                                        G + 3 * w.base, w.node, step_of(sn));
   }
 }
 
@@ -228,6 +233,9 @@ struct Ops {
                  hipStream_t st);
   void (*collide[NVARIANT])(const void* P, const Launch& ln, const void* src, void* dst, const void* rec,
                             const void* G, StepNo sn, unsigned grid, hipStream_t st);
+  // split collision: [0] species lattices, [1] momentum and energy lattices
+  void (*collide_split[2])(const void* P, const Launch& ln, const void* src, void* dst, const void* rec,
+                           const void* G, StepNo sn, unsigned grid, hipStream_t st);
   void (*read)(const void* P, const Launch& ln, const void* pop, double* X, double* rho, double* u, double* p,
                double* T, unsigned grid, hipStream_t st);
   void (*conserved)(const void* Pd, const Launch& ln, const void* pop, double* partial, unsigned grid,
@@ -245,12 +253,12 @@ void launch_moments(const void* Pd, const Launch& ln, const void* pop, void* rec
                      (const S*)pop, (Rec*)rec);
 }
 
-template <typename S, typename R, typename Rec, int M, bool W, int V>
+template <typename S, typename R, typename Rec, int M, bool W, int V, int PART>
 void launch_collide(const void* P, const Launch& ln, const void* src, void* dst, const void* rec, const void* G,
                     StepNo sn, unsigned grid, hipStream_t st)
 {
-  hipLaunchKernelGGL((k_collide<S, R, Rec, M, W, V>), dim3(grid), dim3(BLOCK), 0, st, (const Params<R>*)P, ln,
-                     (const S*)src, (S*)dst, (const Rec*)rec, (const Rec*)G, sn);
+  hipLaunchKernelGGL((k_collide<S, R, Rec, M, W, V, PART>), dim3(grid), dim3(BLOCK), 0, st, (const Params<R>*)P,
+                     ln, (const S*)src, (S*)dst, (const Rec*)rec, (const Rec*)G, sn);
 }
 
 template <typename S, typename R, typename Rec, int M, bool W>
@@ -262,8 +270,10 @@ Ops make_ops()
   o.rec_fields = RecLayout<M>::FIELDS;
   o.moments[0] = launch_moments<S, Rec, M, 0>;
   o.moments[1] = launch_moments<S, Rec, M, 1>;
-  o.collide[0] = launch_collide<S, R, Rec, M, W, 0>;
-  o.collide[1] = launch_collide<S, R, Rec, M, W, 1>;
+  o.collide[0] = launch_collide<S, R, Rec, M, W, 0, 0>;
+  o.collide[1] = launch_collide<S, R, Rec, M, W, 1, 0>;
+  o.collide_split[0] = launch_collide<S, R, Rec, M, W, 0, 1>;
+  o.collide_split[1] = launch_collide<S, R, Rec, M, W, 0, 2>;
   o.gfield = [](const void* Pd, const Launch& ln, const void* rec, void* G, int rec_fields, unsigned grid,
                 hipStream_t st) {
     hipLaunchKernelGGL((k_gfield<Rec, W>), dim3(grid), dim3(BLOCK), 0, st, (const Params<double>*)Pd, ln,

@@ -500,26 +500,34 @@ void drop_graph(mclbm_ctx* c)
   c->gsteps = 0;
 }
 
+// Collision and streaming from buffer `from`: one launch, or the species
+// lattices and the momentum and energy lattices in two (they write disjoint
+// lattices of the other buffer).
+void collide(mclbm_ctx* c, const Launch& ln, int from, StepNo sn, unsigned grid, hipStream_t st)
+{
+  if (c->lc.split) {
+    c->ops.collide_split[0](c->dPr, ln, c->pop[from], c->pop[1 - from], c->rec, c->G, sn, grid, st);
+    c->ops.collide_split[1](c->dPr, ln, c->pop[from], c->pop[1 - from], c->rec, c->G, sn, grid, st);
+  } else {
+    c->ops.collide[c->lc.variant](c->dPr, ln, c->pop[from], c->pop[1 - from], c->rec, c->G, sn, grid, st);
+  }
+}
+
 // The launches of one step from buffer `from` on stream st.
 void enqueue_step(mclbm_ctx* c, int from, StepNo sn, hipStream_t st)
 {
   const int v = c->lc.variant;
   const int rf = c->ops.rec_fields;
-  if (!c->lc.sequential) {
-    const Launch ln = launch_all(c);
-    const unsigned grid = (unsigned)c->nblocks;
+  auto one = [&](const Launch& ln, unsigned grid) {
     c->ops.moments[v](c->dPd, ln, c->pop[from], c->rec, grid, st);
     c->ops.gfield(c->dPd, ln, c->rec, c->G, rf, grid, st);
-    c->ops.collide[v](c->dPr, ln, c->pop[from], c->pop[1 - from], c->rec, c->G, sn, grid, st);
+    collide(c, ln, from, sn, grid, st);
+  };
+  if (!c->lc.sequential) {
+    one(launch_all(c), (unsigned)c->nblocks);
     return;
   }
-  for (int t = 0; t < c->ntubes; ++t) {
-    const Launch ln = launch_one(c, t);
-    const unsigned grid = (unsigned)c->hTubes[t].nblocks;
-    c->ops.moments[v](c->dPd, ln, c->pop[from], c->rec, grid, st);
-    c->ops.gfield(c->dPd, ln, c->rec, c->G, rf, grid, st);
-    c->ops.collide[v](c->dPr, ln, c->pop[from], c->pop[1 - from], c->rec, c->G, sn, grid, st);
-  }
+  for (int t = 0; t < c->ntubes; ++t) one(launch_one(c, t), (unsigned)c->hTubes[t].nblocks);
 }
 
 // One eager step, with per-kernel events when timing is enabled (batched only).
@@ -537,7 +545,7 @@ int eager_step(mclbm_ctx* c)
     if ((rc = record_event(c, e1))) return rc;
     c->ops.gfield(c->dPd, ln, c->rec, c->G, c->ops.rec_fields, grid, c->stream);
     if ((rc = record_event(c, e2))) return rc;
-    c->ops.collide[v](c->dPr, ln, c->pop[c->cur], c->pop[1 - c->cur], c->rec, c->G, sn, grid, c->stream);
+    collide(c, ln, c->cur, sn, grid, c->stream);
     if ((rc = record_event(c, e3))) return rc;
     c->ev_pairs[0].push_back({e0, e1});
     c->ev_pairs[1].push_back({e1, e2});
@@ -1049,11 +1057,13 @@ extern "C" int mclbm_set_launch(mclbm_ctx* c, const mclbm_launch* in)
   if (!c) return MCLBM_EARG;
   if (!in) return fail(c, MCLBM_EARG, "launch is NULL");
   if (in->variant < 0 || in->variant >= kern::NVARIANT) return fail(c, MCLBM_EARG, "variant must be 0 or 1");
-  if ((in->swizzle | in->sequential) & ~1) return fail(c, MCLBM_EARG, "swizzle and sequential are 0 or 1");
+  if ((in->swizzle | in->sequential | in->split) & ~1)
+    return fail(c, MCLBM_EARG, "swizzle, sequential and split are 0 or 1");
+  if (in->split && in->variant != 0) return fail(c, MCLBM_EARG, "the split collision has occupancy variant 0 only");
   if (in->order != 0 && in->order != 1) return fail(c, MCLBM_EARG, "order must be 0 or 1");
   if (in->graph_steps < 0 || (in->graph_steps & 1) || in->graph_steps > 100000)
     return fail(c, MCLBM_EARG, "graph_steps must be an even number in 0..100000");
-  for (int k = 0; k < 3; ++k)
+  for (int k = 0; k < 2; ++k)
     if (in->reserved[k]) return fail(c, MCLBM_EARG, "reserved fields must be 0");
   const bool remap = in->order != c->lc.order;
   HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -1071,12 +1081,14 @@ extern "C" int mclbm_autotune(mclbm_ctx* c, int32_t trial_steps, char* report, s
   if (c->timing) return fail(c, MCLBM_EARG, "disable timing before autotuning");
   const int G = trial_steps & ~1;
   std::vector<mclbm_launch> cands;
+  const int vs[3][2] = {{0, 0}, {1, 0}, {0, 1}};   // (variant, split)
   for (int order = 0; order < (c->ntubes > 1 ? 2 : 1); ++order)
-    for (int v = 0; v < kern::NVARIANT; ++v)
+    for (const auto& vsp : vs)
       for (int sw = 0; sw < 2; ++sw)
         for (int g = 0; g < 2; ++g) {
           mclbm_launch l{};
-          l.variant = v;
+          l.variant = vsp[0];
+          l.split = vsp[1];
           l.swizzle = sw;
           l.order = order;
           l.graph_steps = g ? G : 0;
@@ -1085,7 +1097,7 @@ extern "C" int mclbm_autotune(mclbm_ctx* c, int32_t trial_steps, char* report, s
   hipEvent_t e0, e1;
   HIP_TRY(c, hipEventCreate(&e0));
   HIP_TRY(c, hipEventCreate(&e1));
-  std::string rep = "variant swizzle order graph_steps ms_per_step\n";
+  std::string rep = "variant split swizzle order graph_steps ms_per_step\n";
   double best = 1e300;
   mclbm_launch best_l = c->lc;
   int rc = MCLBM_OK;
@@ -1102,7 +1114,8 @@ extern "C" int mclbm_autotune(mclbm_ctx* c, int32_t trial_steps, char* report, s
     if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = fail(c, MCLBM_EDEVICE, "hipEventElapsedTime"); break; }
     const double per = ms / G;
     char line[128];
-    std::snprintf(line, sizeof line, "%d %d %d %d %.6f\n", l.variant, l.swizzle, l.order, l.graph_steps, per);
+    std::snprintf(line, sizeof line, "%d %d %d %d %d %.6f\n", l.variant, l.split, l.swizzle, l.order, l.graph_steps,
+                  per);
     rep += line;
     if (per < best) {
       best = per;
@@ -1115,8 +1128,8 @@ extern "C" int mclbm_autotune(mclbm_ctx* c, int32_t trial_steps, char* report, s
   rc = mclbm_set_launch(c, &best_l);
   if (rc) return rc;
   char line[128];
-  std::snprintf(line, sizeof line, "chosen %d %d %d %d %.6f\n", best_l.variant, best_l.swizzle, best_l.order,
-                best_l.graph_steps, best);
+  std::snprintf(line, sizeof line, "chosen %d %d %d %d %d %.6f\n", best_l.variant, best_l.split, best_l.swizzle,
+                best_l.order, best_l.graph_steps, best);
   rep += line;
   if (report && report_len > 0) {
     const size_t k = std::min(report_len - 1, rep.size());

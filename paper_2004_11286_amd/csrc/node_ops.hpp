@@ -454,7 +454,9 @@ __host__ __device__ __forceinline__ void push(const Params<R>& P, S* __restrict_
   }
 }
 
-template <typename S, typename R, typename Rec, int M, bool WALLS>
+// PART selects the lattices: 0 all, 1 the stored species lattices, 2 the momentum
+// and energy lattices (a split collision in two launches computes the same step).
+template <typename S, typename R, typename Rec, int M, bool WALLS, int PART = 0>
 __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const S* __restrict__ src,
                                              S* __restrict__ dst, const Rec* __restrict__ rec,
                                              const Rec* __restrict__ G, int64_t node, uint32_t step)
@@ -508,6 +510,7 @@ __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const 
 
   // ---- non-local terms: X_a = -d_a G_a (eq Xalpha) and d_a C_p (sum_a H_a d Y_a = T d C_p)
   R dG[3] = {R(0), R(0), R(0)}, gcp[3] = {R(0), R(0), R(0)};
+  if constexpr (PART != 1) {
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     if (csq(i) == 0) continue;
@@ -521,12 +524,13 @@ __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const 
     if (cy(i)) acc_c(dG[1], cy(i), w3 * R(G[n + nb]));
     if (cz(i)) acc_c(dG[2], cz(i), w3 * R(G[2 * n + nb]));
   }
+  }
   const R Xc[3] = {-dG[0], -dG[1], -dG[2]};
 
   // ---- species collision: f' = f + 2 beta (f^eq - f) + (beta - 1) F (eq SMlbm),
   // F_ai = sum_b K_ab [Psi_i(u, R_b T) - Psi_i(u + V_b, R_b T)] (eq fstar1), with
   // K_ab = P X_a X_b / D_ab, 1/tau_a = sum_b Y_b / tau_ab (eqs tauab, tau).
-  {
+  if constexpr (PART != 2) {
     bool present[M];
     species_present<R, M>(P, s.rho_a, s.rho, present);
     R K[M][M];
@@ -590,7 +594,7 @@ __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const 
   // ---- momentum lattice: f' = f + omega (f^eq - f) + A_i . X (eqs fwithcorrection, Ai);
   // the rounding defect of mass and momentum goes to the rest and face populations,
   // which carry no other moment up to second order.
-  {
+  if constexpr (PART != 1) {
     Trip<R> pf[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) pf[k] = psi_trip<R>(s.u[k], theta);
@@ -648,7 +652,7 @@ __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const 
   // dq = (omega - omega_1)(q - q^eq - u.(P - P^eq)) + omega_1 rho sum_a H_a Y_a V_a
   //      + (2 - omega_1)/2 P sum_a H_a d Y_a     (the exact rewrite of eqs g, gistar,
   // gstareq1mom, interdiffusion and corrFourier that has no pole at omega = omega_1)
-  {
+  if constexpr (PART != 1) {
     const R H = s.Cp * s.T;
     const R hyd = H + R(0.5) * s.usq;
     const R inv_theta = R(1) / theta;

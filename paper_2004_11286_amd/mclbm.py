@@ -62,10 +62,11 @@ class mclbm_params(C.Structure):
 
 class mclbm_launch(C.Structure):
     _fields_ = [("variant", C.c_int32), ("swizzle", C.c_int32), ("order", C.c_int32),
-                ("graph_steps", C.c_int32), ("sequential", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("graph_steps", C.c_int32), ("sequential", C.c_int32), ("split", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
 
-LAUNCH_KEYS = ("variant", "swizzle", "order", "graph_steps", "sequential")
+LAUNCH_KEYS = ("variant", "swizzle", "order", "graph_steps", "sequential", "split")
 
 
 class MclbmError(RuntimeError):
