@@ -212,3 +212,36 @@ def test_full_size_ensemble_sampled_tubes(mc, oracle_mod):
         print("ensemble tube", t, params["nx"], errs)
         for k in FIELDS:
             assert errs[k] < (1e-5 if k == "u" else 1e-6), (t, k, errs[k])
+
+
+def test_batch_checkpoint_resume_is_bitwise(mc):
+    tubes = small_ensemble(n=5, seed=12)
+    b = mc.Batch([p for p, _ in tubes], mc.MCLBM_FP16)
+    b.init_fields([f for _, f in tubes])
+    b.step(7)
+    buf = b.save()
+    b.step(6)
+    a = b.read_moments()
+    b.load(buf)
+    assert b.step_count == 7
+    b.step(6)
+    c = b.read_moments()
+    b.close()
+    for t in range(len(tubes)):
+        for k in FIELDS:
+            np.testing.assert_array_equal(a[t][k], c[t][k])
+    # a checkpoint does not load into a batch of other tubes
+    other = mc.Batch([p for p, _ in small_ensemble(n=5, seed=13)], mc.MCLBM_FP16)
+    with pytest.raises(mc.MclbmError):
+        other.load(buf)
+    other.close()
+
+
+def test_launch_arguments_are_checked(mc):
+    tubes = small_ensemble(n=2, seed=14)
+    b = mc.Batch([p for p, _ in tubes], mc.MCLBM_FP32)
+    for bad in (dict(variant=2), dict(graph_steps=3), dict(swizzle=2), dict(split=1, variant=1), dict(order=2)):
+        with pytest.raises(mc.MclbmError):
+            b.set_launch(**bad)
+    b.set_launch(variant=0, split=0)
+    b.close()

@@ -355,3 +355,24 @@ def test_conservative_gradients_match_oracle(env):
             rel = np.linalg.norm(a - b) / np.linalg.norm(b)
             print("conservative grad layer", li, name, "rel 2-norm", rel)
             assert rel < 2e-2, (li, name, rel)
+
+
+def test_network_arguments_are_checked(env):
+    mc, torch = env
+    net = mc.Net(C, 3, DIMS, species=3)
+    with pytest.raises(mc.MclbmError):
+        net.set_norm(np.ones(C), -np.ones(C), np.ones(13))           # negative input scale
+    with pytest.raises(mc.MclbmError):
+        net.set_norm(np.ones(C), np.ones(C), np.zeros(13))           # zero output scale
+    with pytest.raises(mc.MclbmError):
+        net.adam_step(0.0)                                            # learning rate must be positive
+    # the advance entry point refuses a context with other tubes or species
+    params, f = W.ternary_tube(nx=16, ny=2, nz=2)
+    s = mc.Sim(params, mc.MCLBM_FP32)
+    s.init_fields(**f)
+    with pytest.raises(mc.MclbmError):
+        net.advance(s, 10, 1e-4)
+    s.close()
+    net.close()
+    with pytest.raises(mc.MclbmError):
+        mc.Net(7, 3, DIMS, species=3)                                 # conservative form needs M + 5 channels
