@@ -185,6 +185,15 @@ int mclbm_set_launch(mclbm_ctx *c, const mclbm_launch *in);
  * 2 trial_steps. Synchronises the stream. */
 int mclbm_autotune(mclbm_ctx *c, int32_t trial_steps, char *report, size_t report_len);
 
+/* Streaming copy of `bytes` bytes (a multiple of 16; both pointers 16-byte
+ * aligned device memory, not overlapping) from src to dst, ordered on hip_stream
+ * (NULL: the default stream): 16-byte nontemporal loads and stores, the access
+ * kind of the population streams. It touches no lattice state; timing it gives the
+ * read + write rate the memory sustains, the practical ceiling beside the peak
+ * bandwidth. MCLBM_EARG for a bad size or alignment, MCLBM_EDEVICE if the launch
+ * fails. */
+int mclbm_stream_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,5 +1,5 @@
 // device_ops.hpp -- gfx950 device primitives used by the node functions:
-// stochastic-rounding conversions to 16-bit storage, streaming loads and a
+// stochastic-rounding conversions to 16-bit storage, streaming loads and stores, and a
 // compiler barrier.
 #pragma once
 
@@ -34,6 +34,13 @@ __device__ inline __bf16 cvt_sr_bf16(float x, uint32_t rnd)
 // neighbour stencils of the node records.
 template <typename T>
 __device__ inline T stream_load(const T* p) { return __builtin_nontemporal_load(p); }
+
+// Store of a value the next kernel reads once (the node records): a nontemporal
+// store, which streams whole aligned runs to memory without displacing cached
+// lines. Not for the streaming pushes, whose runs are shifted by one node: those
+// rely on the cache to merge the stores of neighbouring wavefronts into lines.
+template <typename T>
+__device__ inline void stream_store(T* p, T v) { __builtin_nontemporal_store(v, p); }
 
 // Compiler barrier between the lattices of a node: loads after it are not hoisted
 // above it, which bounds the loads (and registers) a thread keeps in flight.

@@ -1195,3 +1195,30 @@ extern "C" int mclbm_nn_advance(mclbm_ctx* c, mclbm_nn* net, int32_t K, double r
   if (used_fallback) *used_fallback = ok ? 0 : 1;
   return MCLBM_OK;
 }
+
+// --------------------------------------------------------------------------
+// Streaming copy (the read + write ceiling of the memory system)
+// --------------------------------------------------------------------------
+namespace {
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) k_stream_copy(const f32x4* __restrict__ src, f32x4* __restrict__ dst,
+                                                     size_t n16)
+{
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+    stream_store(dst + i, stream_load(src + i));
+}
+}  // namespace
+
+extern "C" int mclbm_stream_copy(void* dst, const void* src, size_t bytes, void* hip_stream)
+{
+  if (!dst || !src || bytes % 16 || ((uintptr_t)dst | (uintptr_t)src) % 16) return MCLBM_EARG;
+  const char *d = (const char*)dst, *s = (const char*)src;
+  if (d < s + bytes && s < d + bytes) return MCLBM_EARG;
+  if (bytes == 0) return MCLBM_OK;
+  // a grid-stride loop over 8 blocks per compute unit: 2048 blocks of 256 threads
+  hipLaunchKernelGGL(k_stream_copy, dim3(2048), dim3(256), 0, (hipStream_t)hip_stream, (const f32x4*)src,
+                     (f32x4*)dst, bytes / 16);
+  return hipGetLastError() == hipSuccess ? MCLBM_OK : MCLBM_EDEVICE;
+}

@@ -326,7 +326,7 @@ __host__ __device__ __forceinline__ void state_node(const Params<double>& P, con
     for (int c = 0; c < 3; ++c) up += s.u[c] * (Pn[c][k] - (c == k ? s.P : 0.0) - rho * s.u[c] * s.u[k]);
     qn[k] = q[k] - hyd * rho * s.u[k] - up;
   }
-  auto put = [&](int f, D v) { rec[(size_t)f * n + node] = Rec(v); };
+  auto put = [&](int f, D v) { stream_store(&rec[(size_t)f * n + node], Rec(v)); };
 #pragma unroll
   for (int k = 0; k < 3; ++k) put(REC_PHIX + k, j[k] * (1.0 - 3.0 * theta) - j[k] * s.u[k] * s.u[k]);
   put(REC_OMEGA, omega);
@@ -378,7 +378,7 @@ __host__ __device__ __forceinline__ void gfield_node(const Params<double>& P, co
   R om = rec[(size_t)REC_OMEGA * n + node];
   R f = R(1) / om - R(0.5);
 #pragma unroll
-  for (int k = 0; k < 3; ++k) G[(size_t)k * n + node] = f * dphi[k];
+  for (int k = 0; k < 3; ++k) stream_store(&G[(size_t)k * n + node], R(f * dphi[k]));
 }
 
 // --------------------------------------------------------------------------
@@ -450,7 +450,8 @@ __host__ __device__ __forceinline__ void push(const Params<R>& P, S* __restrict_
     dst[(size_t)(l * Q + opp(i)) * n + node] = v;    // half-way bounce-back
   } else {
     const int64_t d = b.x[cx(i) + 1] + b.y[cy(i) + 1] + b.z[cz(i) + 1];
-    dst[(size_t)(l * Q + i) * n + d] = v;
+    dst[(size_t)(l * Q + i) * n + d] = v;    // plain store: the shifted pushes of a wavefront
+                                              // merge into whole lines in the cache
   }
 }
 

@@ -42,7 +42,7 @@ EXPORTS = ["mclbm_workspace_bytes", "mclbm_batch_workspace_bytes", "mclbm_create
            "mclbm_init_fields", "mclbm_step", "mclbm_read_moments", "mclbm_read_fields_f32",
            "mclbm_conservation", "mclbm_step_count", "mclbm_state_bytes", "mclbm_save", "mclbm_load",
            "mclbm_set_timing", "mclbm_kernel_stats", "mclbm_get_launch", "mclbm_set_launch",
-           "mclbm_autotune"]
+           "mclbm_autotune", "mclbm_stream_copy"]
 NN_EXPORTS = ["mclbm_nn_workspace_bytes", "mclbm_nn_create", "mclbm_nn_destroy", "mclbm_nn_last_error",
               "mclbm_nn_param_count", "mclbm_nn_set_params", "mclbm_nn_get_params", "mclbm_nn_get_grads",
               "mclbm_nn_set_norm", "mclbm_nn_set_conditioning", "mclbm_nn_io", "mclbm_nn_forward", "mclbm_nn_loss", "mclbm_nn_backward",
@@ -79,6 +79,12 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2004_11286_amd.build` "
                           "(there is no CPU fallback)")
+    # torch ships its own HIP runtime under the unversioned file names its libraries
+    # ask for; loaded first, it is the process's one and this library binds to it by
+    # its soname. Loaded the other way round, the process would hold two runtimes and
+    # device memory from torch would be foreign to this library.
+    import torch  # noqa: F401
+
     L = C.CDLL(LIB_PATH)
     dp = C.POINTER(C.c_double)
     vp = C.c_void_p
@@ -137,6 +143,7 @@ def _load():
     L.mclbm_load.argtypes = [vp, vp, C.c_size_t]
     L.mclbm_set_timing.argtypes = [vp, C.c_int]
     L.mclbm_kernel_stats.argtypes = [vp, C.c_int32, dp, C.POINTER(C.c_int64), C.POINTER(C.c_char_p)]
+    L.mclbm_stream_copy.argtypes = [vp, vp, C.c_size_t, vp]
     return L
 
 
@@ -167,6 +174,20 @@ def make_param_array(tubes: list, precision: int):
         arr[t], k = make_params(params, precision)
         keep.append(k)
     return arr, keep
+
+
+def mclbm_stream_copy(dst_ptr: int, src_ptr: int, nbytes: int, stream: int = 0) -> None:
+    rc = lib.mclbm_stream_copy(C.c_void_p(dst_ptr), C.c_void_p(src_ptr), nbytes, C.c_void_p(stream or None))
+    if rc != MCLBM_OK:
+        raise MclbmError(rc, "mclbm_stream_copy: size not a multiple of 16, misaligned or overlapping buffers")
+
+
+def stream_copy(dst, src, stream=None) -> None:
+    """mclbm_stream_copy of the bytes of device tensor src into dst (same size)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes or not (src.is_cuda and dst.is_cuda):
+        raise ValueError("stream_copy needs two device tensors of the same size")
+    mclbm_stream_copy(dst.data_ptr(), src.data_ptr(), nbytes, 0 if stream is None else stream.cuda_stream)
 
 
 def _check(ctx, rc: int):

@@ -132,3 +132,29 @@ def test_nn_param_count_matches_the_oracle():
 
     assert S.param_count(7, 6) == 27 * (7 * 64 + 4 * 64 * 64 + 64 * 7) + 5 * 64 + 7
     assert S.param_count(7, 6, S=6) == 27 * (13 * 64 + 4 * 64 * 64 + 64 * 7) + 5 * 64 + 7
+
+
+def test_stream_copy_rejects_bad_sizes_without_a_device():
+    m = pytest.importorskip("paper_2004_11286_amd.mclbm")
+    with pytest.raises(m.MclbmError):
+        m.mclbm_stream_copy(4096, 8192, 15)          # not a multiple of 16
+    with pytest.raises(m.MclbmError):
+        m.mclbm_stream_copy(4100, 8192, 16)          # misaligned
+    with pytest.raises(m.MclbmError):
+        m.mclbm_stream_copy(4096, 4096 + 16, 64)     # overlapping
+    with pytest.raises(m.MclbmError):
+        m.mclbm_stream_copy(0, 4096, 16)             # null
+
+
+def test_binding_loads_torch_runtime_first():
+    # importing the package before torch must still leave one HIP runtime in the process
+    import subprocess
+    import sys
+
+    code = ("import paper_2004_11286_amd.mclbm, sys; "
+            "maps = open('/proc/self/maps').read(); "
+            "paths = {l.split()[-1] for l in maps.splitlines() if 'libamdhip64' in l}; "
+            "print(len(paths)); sys.exit(0 if len(paths) == 1 else 1)")
+    r = subprocess.run([sys.executable, "-c", code], cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stdout + r.stderr

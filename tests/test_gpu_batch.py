@@ -245,3 +245,15 @@ def test_launch_arguments_are_checked(mc):
             b.set_launch(**bad)
     b.set_launch(variant=0, split=0)
     b.close()
+
+
+@pytest.mark.gpu
+def test_stream_copy_is_exact(mc):
+    import torch
+
+    for n in (4, 1000, (1 << 20) + 12):               # float counts: multiples of 4 (16 bytes)
+        a = torch.randn(n, device="cuda")
+        b = torch.full_like(a, float("nan"))
+        mc.stream_copy(b, a)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), n
