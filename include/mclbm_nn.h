@@ -16,8 +16,10 @@
  * matrix cores see about 16 significant bits of these fields (hi + lo / 256)
  * with no extra parameters. The conditioning channels are constant per tube
  * (for instance the tube's molar masses and diffusivities, which the fields
- * alone do not reveal but which decide how they evolve). Padding: zero outside
- * the x ends of a tube (the walls), periodic in y and z, like the lattice.
+ * alone do not reveal but which decide how they evolve). Padding: at the x ends
+ * of a tube (its walls) every layer replicates the wall node, the mirror image a
+ * wall without flux implies (the method of images); periodic in y and z, like the
+ * lattice.
  *
  * Output, direct form (species = 0): the change of each of the C fields over
  * the K steps, y_c * out_scale[c]. Conservative form (species = M > 0, fields
@@ -100,7 +102,13 @@ int mclbm_nn_forward(mclbm_nn *net);
  * with per-channel weights w (host, `channels` values, may be NULL = 1).
  * Direct form: loss = (1/n) sum_nodes sum_c w_c ((pred_c - target_c) / out_scale[c])^2.
  * Conservative form, in physical units: loss = (1/n) sum_nodes [sum_s w_s (n_s -
- * n*_s)^2 + w_M (T - T*)^2 + sum_k w_{M+1+k} (u_k - u*_k)^2] (w_{M+4} unused).
+ * n*_s)^2 + w_M (T - T*)^2 + sum_k w_{M+1+k} (u_k - u*_k)^2 + w_{M+4} sum_s
+ * (F_{s,x} - F*_{s,x})^2], the last sum over the open x faces (the p slot of the
+ * weights, which this form does not fit, weights the x fluxes). F*_{s,x}(x) =
+ * -sum_{x' <= x} (n*_s - n_s)(x') along each x row: on a tube with walls and fields
+ * uniform in y and z, the fluxes that produce the target change. The divergence
+ * alone cannot see a uniform offset of the fluxes on every interior face, which
+ * only the wall nodes then feel; this term fixes it.
  * Seeds the output gradient for backward. Synchronises the stream. */
 int mclbm_nn_loss(mclbm_nn *net, const float *target, const float *channel_weight, double *loss);
 

@@ -4,8 +4,9 @@ Plain numpy, written from the definitions, not from the GPU kernels:
 
 - a 3x3x3 convolution, output o = b[o] + sum over taps (dz, dy, dx) and input
   channels i of W[tap][o][i] * in[i](z + dz, y + dy, x + dx), tap = 9 (dz+1) +
-  3 (dy+1) + (dx+1), with zero padding outside the x ends of a tube and periodic
-  wrapping in y and z;
+  3 (dy+1) + (dx+1), with periodic wrapping in y and z and, at the x ends of a
+  tube (its walls), replicate padding: the value outside a wall is that of the
+  wall node, the mirror image that a wall without flux implies;
 - the network: layer 0 maps C field channels to the hidden width, ReLU between
   layers, the last layer maps back to C; its input is the normalised fields
   (f - shift) * scale, its output the change of the normalised fields;
@@ -14,9 +15,12 @@ Plain numpy, written from the definitions, not from the GPU kernels:
   (none through the walls); n_s changes by minus their discrete divergence;
   then p = T sum n and X_s = n_s / sum n;
 - the mean squared error and its gradient by the chain rule (the gradient of a
-  convolution with respect to its input is the convolution with the transposed
-  weights on the reversed offsets; with respect to the weights, the correlation
-  of the output gradient with the shifted input);
+  convolution with respect to its input is the adjoint gather, the transposed
+  weights scattered back along the tap offsets; with respect to the weights, the
+  correlation of the output gradient with the shifted input); in the
+  conservative form also the error of the fluxes through the x faces against
+  those the target change implies on a walled tube with fields uniform in y and
+  z, which fixes the uniform flux offset that the divergence cannot see;
 - Adam as published by Kingma and Ba (bias-corrected first and second moments);
 - the mole residual: with R_U = 1 the molar density of species s is
   rho_s / m_s = p X_s / T, so a tube's moles are sum_x p X_s / T.
@@ -50,17 +54,23 @@ def bf16(a: np.ndarray) -> np.ndarray:
 
 
 def shift(x: np.ndarray, dz: int, dy: int, dx: int) -> np.ndarray:
-    """s[..., z, y, x] = x[..., z + dz, y + dy, x + dx]: periodic in z and y,
-    zero outside the x range."""
+    """s[..., z, y, x] = x[..., z + dz, y + dy, clamp(x + dx)]: periodic in z and
+    y, the x index clamped to [0, nx - 1] (replicate padding at the walls)."""
     s = np.roll(x, shift=(-dz, -dy), axis=(-3, -2))
-    if dx == 0:
-        return s.copy()
-    out = np.zeros_like(s)
-    if dx == 1:
-        out[..., :-1] = s[..., 1:]
-    else:
-        out[..., 1:] = s[..., :-1]
-    return out
+    nx = s.shape[-1]
+    idx = np.clip(np.arange(nx) + dx, 0, nx - 1)
+    return s[..., idx]
+
+
+def shift_adjoint(g: np.ndarray, dz: int, dy: int, dx: int) -> np.ndarray:
+    """Adjoint of shift: out[..., z + dz, y + dy, clamp(x + dx)] += g[..., z, y, x],
+    so the values gathered twice at a wall (its own and its ghost's) send both
+    contributions back to the wall node."""
+    nx = g.shape[-1]
+    idx = np.clip(np.arange(nx) + dx, 0, nx - 1)
+    out = np.zeros_like(g)
+    np.add.at(out, (Ellipsis, idx), g)        # scatter along x (repeated indices add)
+    return np.roll(out, shift=(dz, dy), axis=(-3, -2))
 
 
 def conv(x: np.ndarray, W: np.ndarray, b: np.ndarray | None) -> np.ndarray:
@@ -74,11 +84,10 @@ def conv(x: np.ndarray, W: np.ndarray, b: np.ndarray | None) -> np.ndarray:
 
 
 def conv_input_grad(dy: np.ndarray, W: np.ndarray) -> np.ndarray:
-    """Adjoint of conv with respect to x: sum_tap W[tap]^T dy(. - d_tap)."""
+    """Adjoint of conv with respect to x: sum_tap shift_adjoint(W[tap]^T dy, d_tap)."""
     dx = np.zeros((W.shape[2],) + dy.shape[1:])
     for tap in range(NTAP):
-        dz_, dy_, dx_ = tap_offset(tap)
-        dx += np.tensordot(W[tap].T, shift(dy, -dz_, -dy_, -dx_), axes=(1, 0))
+        dx += shift_adjoint(np.tensordot(W[tap].T, dy, axes=(1, 0)), *tap_offset(tap))
     return dx
 
 
@@ -216,6 +225,19 @@ def conservative_loss(f, y, target, w, out_scale, M, N):
         e = fo[M + k] - target[M + k]
         loss += float(np.sum(w[M + k] * e * e))
         dy[3 * M + k] = 2.0 * w[M + k] * e * out_scale[3 * M + k] / N
+    # the x-flux term, weight w[M + 4] (the p slot, which this form does not fit):
+    # on a tube with walls and fields uniform in y and z, the flux of n_s through
+    # the face between x and x + 1 that the target change implies is minus the
+    # change summed from the left wall up to x (nothing enters through the wall)
+    wf = w[M + 4] if len(w) > M + 4 else 0.0
+    if wf:
+        n0 = f[M + 4] * f[:M] / f[M]
+        Fstar = -np.cumsum(nt - n0, axis=-1)
+        for s in range(M):
+            e = y[3 * s] * out_scale[3 * s] - Fstar[s]
+            e[..., -1] = 0.0                          # the wall face: no flux, not fitted
+            loss += float(np.sum(wf * e * e))
+            dy[3 * s] += 2.0 * wf * e * out_scale[3 * s] / N
     return loss / N, dy
 
 

@@ -69,9 +69,13 @@ __device__ inline int64_t wrap_index(const NTube& tb, int x, int y, int z)
 // Convolution (forward, and backward with respect to the input)
 // ---------------------------------------------------------------------------
 // EPI 0: + bias, ReLU, BF16 out; EPI 1: + bias, FP32 out; EPI 2: times the
-// ReLU mask (mask > 0), BF16 out. sign = +1 reads in(x + d), -1 reads
-// in(x - d) (the adjoint of the forward gather: zero padding in x and periodic
-// wrapping in y, z are their own adjoints under the sign flip).
+// ReLU mask (mask > 0), BF16 out. sign = +1 is the forward gather, in(x + d)
+// with x clamped to the tube (replicate padding at the walls) and y, z wrapped;
+// sign = -1 its adjoint, in(x - d) with nothing from outside the tube, plus, at
+// a wall node, the ghost's share: the forward took the ghost value of tap
+// dx = -1 at x = 0 (dx = +1 at x = nx - 1) from the wall node itself, so that
+// node's gradient also collects in(wall node) under the same tap. The two
+// operands of that tap are added in FP32 and rounded to BF16 once.
 template <int CIN, int COUT, int EPI>
 __global__ __launch_bounds__(256) void k_conv(const NTube* __restrict__ tubes, const int32_t* __restrict__ tile_tube,
                                               int ntubes, const bf16* __restrict__ W, const float* __restrict__ bias,
@@ -140,16 +144,33 @@ __global__ __launch_bounds__(256) void k_conv(const NTube* __restrict__ tubes, c
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
       const int x = xs[b] + dx;
-      const bool ok = valid[b] && x >= 0 && x < tb.nx;
-      const int64_t nb = wrap_index(tb, ok ? x : 0, ys[b] + dy, zs[b] + dz);
+      bool ok, extra = false;
+      int xr;
+      if (sign > 0) {
+        xr = x < 0 ? 0 : (x >= tb.nx ? tb.nx - 1 : x);
+        ok = valid[b];
+      } else {
+        ok = valid[b] && x >= 0 && x < tb.nx;
+        xr = ok ? x : 0;
+        extra = valid[b] && ((xs[b] == 0 && dx == 1) || (xs[b] == tb.nx - 1 && dx == -1));
+      }
+      const int64_t nb = wrap_index(tb, xr, ys[b] + dy, zs[b] + dz);
+      const int64_t ne = wrap_index(tb, xs[b], ys[b] + dy, zs[b] + dz);
 #pragma unroll
       for (int kc = 0; kc < KC; ++kc) {
+        bf16x8 v;
         if (ok) {
-          bop[b][kc] = *(const bf16x8*)(in + nb * CIN + kc * 16 + khalf);
+          v = *(const bf16x8*)(in + nb * CIN + kc * 16 + khalf);
         } else {
 #pragma unroll
-          for (int j = 0; j < 8; ++j) bop[b][kc][j] = (bf16)0.f;
+          for (int j = 0; j < 8; ++j) v[j] = (bf16)0.f;
         }
+        if (extra) {
+          const bf16x8 e = *(const bf16x8*)(in + ne * CIN + kc * 16 + khalf);
+#pragma unroll
+          for (int j = 0; j < 8; ++j) v[j] = (bf16)((float)v[j] + (float)e[j]);
+        }
+        bop[b][kc] = v;
       }
     }
 #pragma unroll
@@ -204,6 +225,7 @@ __global__ __launch_bounds__(256) void k_conv(const NTube* __restrict__ tubes, c
 
 // ---------------------------------------------------------------------------
 // Weight gradient: dW[tap][co][ci] = sum_nodes dY[node][co] X[node + d_tap][ci]
+// (the forward's gather: x clamped to the tube, y and z wrapped)
 // ---------------------------------------------------------------------------
 // The reduction runs over nodes, so both operands are staged transposed in LDS
 // (channel rows, node columns) for 128-node chunks; workgroup (g, tap) sums the
@@ -261,8 +283,9 @@ __global__ __launch_bounds__(256) void k_wgrad(const NTube* __restrict__ tubes, 
         y = r % tb.ny;
         z = r / tb.ny;
       }
-      const bool ok = valid && x + dx >= 0 && x + dx < tb.nx;
-      const int64_t nb = wrap_index(tb, ok ? x + dx : 0, y + dy, z + dz);
+      const bool ok = valid;                 // replicate padding: x clamped to the tube
+      const int xx = x + dx < 0 ? 0 : (x + dx >= tb.nx ? tb.nx - 1 : x + dx);
+      const int64_t nb = wrap_index(tb, xx, y + dy, z + dz);
 #pragma unroll
       for (int c8 = 0; c8 < CIN / 8; ++c8) {
         bf16x8 v;
@@ -529,15 +552,46 @@ __global__ __launch_bounds__(256) void k_unpack_cons(const NTube* __restrict__ t
   fo[o + (size_t)(M + 4) * n_t + node] = (float)(T1 * sum);
 }
 
+// Target fluxes through the x faces: along each x row of a tube, F*_s(x) =
+// -sum_{x' <= x} (n*_s - n_s)(x'), with n = p X / T of the input fields f and of
+// the target. On a tube with walls and fields uniform in y and z this is the one
+// flux field whose divergence gives the target change (zero through the left
+// wall); it pins the uniform flux offset that the divergence alone cannot see.
+// The thread at the start of a row (x = 0) scans it in FP64. Output fs [n][M].
+__global__ __launch_bounds__(256) void k_flux_target(const NTube* __restrict__ tubes,
+                                                     const int32_t* __restrict__ tile_tube, int ntubes, int M,
+                                                     const float* __restrict__ f, const float* __restrict__ target,
+                                                     float* __restrict__ fs)
+{
+  const int tile = blockIdx.x;
+  const NTube tb = tube_of(tubes, tile_tube, ntubes, tile);
+  const int n_t = tb.nx * tb.ny * tb.nz;
+  const int node = (tile - tb.first_tile) * TILE + threadIdx.x;
+  if (node >= n_t || node % tb.nx != 0) return;
+  const size_t o = (size_t)(M + 5) * tb.base;
+  for (int s = 0; s < M; ++s) {
+    double acc = 0.0;
+    for (int x = 0; x < tb.nx; ++x) {
+      const int k = node + x;
+      auto at = [&](const float* a, int c) -> double { return (double)a[o + (size_t)c * n_t + k]; };
+      acc -= at(target, M + 4) * at(target, s) / at(target, M) - at(f, M + 4) * at(f, s) / at(f, M);
+      fs[(tb.base + k) * M + s] = (float)acc;
+    }
+  }
+}
+
 // Loss of the conservative output on the conserved and transported variables,
 // in physical units: (1/N) sum [ sum_s w_s (n_s - n*_s)^2 + w_T (T - T*)^2 +
-// sum_k w_u,k (u_k - u*_k)^2 ], weights w = nm.weight[0..M+3]. Writes the loss
-// partials, dL/dn_s per node into gn_out [n][M], and the T and u part of the
-// output gradient (the flux part follows in k_loss_cons_flux).
+// sum_k w_u,k (u_k - u*_k)^2 + w_F sum_s (F_s,x - F*_s,x)^2 (open x faces) ],
+// weights w = nm.weight[0..M+4] (w_F in the p slot, which this form does not
+// fit), F* from k_flux_target. Writes the loss partials, dL/dn_s per node into
+// gn_out [n][M], and the T and u part of the output gradient (the flux part
+// follows in k_loss_cons_flux).
 __global__ __launch_bounds__(256) void k_loss_cons(const NTube* __restrict__ tubes,
                                                    const int32_t* __restrict__ tile_tube, int ntubes, int M,
                                                    Norm nm, double inv_n, const float* __restrict__ fo,
-                                                   const float* __restrict__ target, float* __restrict__ gn_out,
+                                                   const float* __restrict__ target, const float* __restrict__ y,
+                                                   const float* __restrict__ fs, float* __restrict__ gn_out,
                                                    bf16* __restrict__ dY, double* __restrict__ partial)
 {
   __shared__ double red[256];
@@ -555,6 +609,13 @@ __global__ __launch_bounds__(256) void k_loss_cons(const NTube* __restrict__ tub
       const double e = at(fo, M + 4) * at(fo, s) / at(fo, M) - at(target, M + 4) * at(target, s) / at(target, M);
       l += nm.weight[s] * e * e;
       gn_out[gn * M + s] = (float)(2.0 * nm.weight[s] * e * inv_n);
+    }
+    const double wf = nm.weight[M + 4];
+    if (wf != 0.0 && node % tb.nx + 1 < tb.nx) {
+      for (int s = 0; s < M; ++s) {
+        const double e = (double)y[gn * COUTL + 3 * s] * nm.out_scale[3 * s] - (double)fs[gn * M + s];
+        l += wf * e * e;
+      }
     }
     bf16 d[COUTL];
 #pragma unroll
@@ -582,10 +643,12 @@ __global__ __launch_bounds__(256) void k_loss_cons(const NTube* __restrict__ tub
 }
 
 // Flux part of the output gradient: F_a(x) lowers n at x and raises it at
-// x + e_a, so dL/dF_a(x) = dL/dn(x + e_a) - dL/dn(x) on an open face, 0 on a wall.
+// x + e_a, so dL/dF_a(x) = dL/dn(x + e_a) - dL/dn(x) on an open face, 0 on a wall;
+// on an open x face the flux term adds 2 w_F (F_x - F*_x) / N.
 __global__ __launch_bounds__(256) void k_loss_cons_flux(const NTube* __restrict__ tubes,
                                                         const int32_t* __restrict__ tile_tube, int ntubes, int M,
-                                                        Norm nm, const float* __restrict__ gn_in,
+                                                        Norm nm, double inv_n, const float* __restrict__ gn_in,
+                                                        const float* __restrict__ y, const float* __restrict__ fs,
                                                         bf16* __restrict__ dY)
 {
   const int tile = blockIdx.x;
@@ -599,8 +662,11 @@ __global__ __launch_bounds__(256) void k_loss_cons_flux(const NTube* __restrict_
     const bool open = face_open(tb, g, a);
     const int64_t up = open ? shifted(tb, g, a, +1) : gn;
     for (int s = 0; s < M; ++s) {
-      const float v = open ? (gn_in[up * M + s] - gn_in[gn * M + s]) * nm.out_scale[3 * s + a] : 0.f;
-      dY[gn * COUTL + 3 * s + a] = (bf16)v;
+      double v = open ? (double)(gn_in[up * M + s] - gn_in[gn * M + s]) : 0.0;
+      if (a == 0 && open && nm.weight[M + 4] != 0.f)
+        v += 2.0 * nm.weight[M + 4] * ((double)y[gn * COUTL + 3 * s] * nm.out_scale[3 * s] - (double)fs[gn * M + s]) *
+             inv_n;
+      dY[gn * COUTL + 3 * s + a] = (bf16)(float)(v * nm.out_scale[3 * s + a]);
     }
   }
 }
@@ -1159,13 +1225,17 @@ extern "C" int mclbm_nn_loss(mclbm_nn* net, const float* target, const float* ch
   for (int c = 0; c < net->C; ++c) nm.weight[c] = channel_weight ? channel_weight[c] : 1.f;
   const unsigned grid = (unsigned)net->ntiles;
   if (net->Ms > 0) {
-    // dL/dn per node in the first activation-gradient buffer (free until backward)
+    // dL/dn and the target x fluxes per node, [n][M] each, in the first
+    // activation-gradient buffer (free until backward; WIDTH BF16 = 128 bytes per node)
     float* gnode = (float*)net->dy[0];
+    float* fstar = gnode + (size_t)net->n * net->Ms;
+    hipLaunchKernelGGL(k_flux_target, dim3(grid), dim3(256), 0, net->stream, net->dTubes, net->dTileTube,
+                       net->ntubes, net->Ms, net->fin, target, fstar);
     hipLaunchKernelGGL(k_loss_cons, dim3(grid), dim3(256), 0, net->stream, net->dTubes, net->dTileTube,
-                       net->ntubes, net->Ms, nm, 1.0 / (double)net->n, net->fout, target, gnode, net->dyl,
-                       net->dpart);
+                       net->ntubes, net->Ms, nm, 1.0 / (double)net->n, net->fout, target, net->yout, fstar, gnode,
+                       net->dyl, net->dpart);
     hipLaunchKernelGGL(k_loss_cons_flux, dim3(grid), dim3(256), 0, net->stream, net->dTubes, net->dTileTube,
-                       net->ntubes, net->Ms, nm, gnode, net->dyl);
+                       net->ntubes, net->Ms, nm, 1.0 / (double)net->n, gnode, net->yout, fstar, net->dyl);
   } else {
     hipLaunchKernelGGL(k_loss, dim3(grid), dim3(256), 0, net->stream, net->dTubes, net->dTileTube, net->ntubes,
                        net->C, nm, 1.0 / (double)net->n, net->fin, target, net->yout, net->dyl, net->dpart);

@@ -17,7 +17,8 @@ from . import mclbm as mc
 
 DEPTH = 6
 K_DEFAULT = 100
-LR = 5e-4
+LR = 1e-4          # larger rates let one late, heavily weighted pair's gradient spike kill the
+                   # ReLUs (the loss jumps to that of predicting no change and stays there)
 
 
 def channels(M: int) -> int:
@@ -66,10 +67,24 @@ def _tube_views(x, dims, C, stride=256):
         yield x[:, C * off[t]:C * off[t + 1]].reshape(x.shape[0], C, n)[:, :, ::max(1, n // stride)]
 
 
+def x_flux_targets(x: np.ndarray, dims, C: int, M: int) -> np.ndarray:
+    """The x fluxes the snapshot changes imply along the first x row of each tube,
+    F*_s(x) = -sum_{x' <= x} dn_s(x') (the target of the x-flux loss term; exact for
+    fields uniform in y and z, as in these tubes): [pairs][M][sum of nx] (host)."""
+    sizes = [nx * ny * nz for nx, ny, nz in dims]
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    rows = []
+    for t, (nx, ny, nz) in enumerate(dims):
+        seg = x[:, C * off[t]:C * off[t + 1]].reshape(x.shape[0], C, sizes[t])[:, :, :nx]
+        n = molar_densities(seg, M)
+        rows.append(-np.cumsum(n[1:] - n[:-1], axis=-1))
+    return np.concatenate(rows, axis=-1)
+
+
 def channel_stats(snaps, dims, M: int) -> dict:
     """Spreads from the trajectories (host, subsampled nodes): of every field,
-    of its change over one interval, and of the change of each molar density
-    n_s (per interval, for the loss weights)."""
+    of its change over one interval, of the change of each molar density n_s (per
+    interval, for the loss weights) and of the implied x fluxes of n_s."""
     x = snaps.cpu().numpy().astype(np.float64)
     C = channels(M)
     segs = list(_tube_views(x, dims, C))
@@ -77,8 +92,10 @@ def channel_stats(snaps, dims, M: int) -> dict:
     d = allf[1:] - allf[:-1]
     n = np.concatenate([molar_densities(s, M) for s in segs], axis=2)
     dn = n[1:] - n[:-1]
+    F = x_flux_targets(x, dims, C, M)
     return {"mean": allf.mean(axis=(0, 2)), "std": allf.std(axis=(0, 2)), "dstd": d.std(axis=(0, 2)),
-            "dn_std": dn.std(axis=(0, 2)), "dn_ms_pair": (dn ** 2).mean(axis=2)}
+            "dn_std": dn.std(axis=(0, 2)), "dn_ms_pair": (dn ** 2).mean(axis=2),
+            "Fx_std": np.sqrt((F ** 2).mean(axis=(0, 2))), "Fx_ms_pair": (F ** 2).mean(axis=2)}
 
 
 IN_FLOOR = 1e-3      # smallest input spread used for scaling (T and u vary by ~1e-3)
@@ -86,12 +103,13 @@ OUT_FLOOR = 1e-4     # smallest output unit (a channel that never changes, e.g. 
 
 
 def norm_from_stats(st: dict, M: int) -> dict:
-    """Inputs to zero mean and unit spread; outputs (conservative form): the
-    fluxes of n_s in units of the typical change of n_s, T and u in units of
-    their typical change; floors keep channels that (almost) never vary from
-    being blown up to round-off."""
+    """Inputs to zero mean and unit spread; outputs (conservative form): the x
+    fluxes of n_s in units of their typical size, the y and z fluxes in units of
+    the typical change of n_s, T and u in units of their typical change; floors
+    keep channels that (almost) never vary from being blown up to round-off."""
     in_scale = 1.0 / np.maximum(st["std"], IN_FLOOR)
     flux = np.repeat(np.maximum(st["dn_std"], 1e-7), 3)
+    flux[0::3] = np.maximum(st["Fx_std"], 1e-7)
     tu = np.maximum(st["dstd"][M:M + 4], OUT_FLOOR)
     return {"in_shift": st["mean"].astype(np.float32), "in_scale": in_scale.astype(np.float32),
             "out_scale": np.concatenate([flux, tu]).astype(np.float32)}
@@ -124,25 +142,30 @@ def build_net(dims, tubes_params, norm, M: int, depth: int = DEPTH, params=None,
     return net
 
 
-def pair_weights(st: dict, M: int, floor_frac: float = 1e-2) -> np.ndarray:
+def pair_weights(st: dict, M: int, floor_frac: float = 1e-2, flux_weight: float = 0.1) -> np.ndarray:
     """Loss weights per snapshot pair in physical units: the molar densities by
     the pair's own mean squared change (a relative error, so late, slow
     intervals count as much as early ones), T and u by their typical change at
-    weights 0.2 and 0.1, p unused. Returns [nsnap][C]."""
+    weights 0.2 and 0.1, and the x fluxes (the p slot) by flux_weight over the
+    pair's mean squared x flux (also relative). Returns [nsnap][C]."""
     C = channels(M)
     ms = st["dn_ms_pair"]
     floor = floor_frac * ms.mean(axis=0)
     out = np.zeros((ms.shape[0], C), dtype=np.float64)
     out[:, :M] = 1.0 / np.maximum(ms, floor)
+    msF = st["Fx_ms_pair"].mean(axis=1)
+    out[:, M + 4] = flux_weight / np.maximum(msF, floor_frac * msF.mean())
     out[:, M] = 0.2 / np.maximum(st["dstd"][M], OUT_FLOOR) ** 2
     out[:, M + 1:M + 4] = 0.1 / np.maximum(st["dstd"][M + 1:M + 4], OUT_FLOOR) ** 2
     return out.astype(np.float32)
 
 
-def train(net, snaps, iters: int, weights, lr: float = LR, seed: int = 0, log_every: int = 0):
+def train(net, snaps, iters: int, weights, lr: float = LR, seed: int = 0, log_every: int = 0,
+          warmup: int = 500):
     """Adam on random (t, t + K) snapshot pairs of all tubes at once, with a
-    cosine learning-rate decay; weights: per-pair channel weights [nsnap][C].
-    Returns the loss history."""
+    linear learning-rate warm-up over the first `warmup` iterations and a cosine
+    decay after; weights: per-pair channel weights [nsnap][C]. Returns the loss
+    history."""
     rng = np.random.default_rng(seed)
     losses = []
     nsnap = snaps.shape[0] - 1
@@ -152,7 +175,7 @@ def train(net, snaps, iters: int, weights, lr: float = LR, seed: int = 0, log_ev
         net.forward()
         losses.append(net.loss(snaps[j + 1], weights[j]))
         net.backward()
-        lr_it = lr * 0.5 * (1.0 + np.cos(np.pi * it / iters)) + 0.02 * lr
+        lr_it = (lr * 0.5 * (1.0 + np.cos(np.pi * it / iters)) + 0.02 * lr) * min(1.0, (it + 1) / max(warmup, 1))
         net.adam_step(lr_it)
         if log_every and (it + 1) % log_every == 0:
             print(f"  iter {it + 1}: loss {np.mean(losses[-log_every:]):.4g}", flush=True)

@@ -19,9 +19,7 @@ def brute_conv(x, W, b):
                     s = b[o]
                     for tap in range(27):
                         dz, dy, dx = tap // 9 - 1, (tap // 3) % 3 - 1, tap % 3 - 1
-                        xi = xx + dx
-                        if xi < 0 or xi >= nx:
-                            continue              # zero padding at the walls
+                        xi = min(max(xx + dx, 0), nx - 1)   # replicate padding at the walls
                         zi, yi = (z + dz) % nz, (yy + dy) % ny
                         for i in range(Cin):
                             s += W[tap, o, i] * x[i, zi, yi, xi]
@@ -38,15 +36,47 @@ def test_conv_matches_brute_force_loops():
 
 
 def test_conv_single_tap_is_a_shift():
-    """One unit weight on tap (dz, dy, dx) = (0, 0, +1): y(x) = in(x + 1), zero at the last x."""
+    """One unit weight on tap (dz, dy, dx) = (0, 0, +1): y(x) = in(x + 1), the wall
+    value itself at the last x."""
     x = np.arange(2 * 2 * 3 * 4, dtype=float).reshape(2, 2, 3, 4)
     W = np.zeros((27, 2, 2))
     W[9 * 1 + 3 * 1 + 2, 0, 0] = 1.0            # tap (0, 0, +1)
     assert S.tap_offset(14) == (0, 0, 1)
     y = S.conv(x, W, None)
     np.testing.assert_array_equal(y[0, :, :, :-1], x[0, :, :, 1:])
-    np.testing.assert_array_equal(y[0, :, :, -1], 0.0)
+    np.testing.assert_array_equal(y[0, :, :, -1], x[0, :, :, -1])
     np.testing.assert_array_equal(y[1], 0.0)
+
+
+def test_conv_sees_no_wall_in_an_x_uniform_field():
+    """Replicate padding: a field constant along x gives wall outputs equal to the
+    interior ones (zero padding would not)."""
+    rng = np.random.default_rng(7)
+    x = np.repeat(rng.normal(size=(3, 2, 3, 1)), 6, axis=3)
+    W = rng.normal(size=(27, 2, 3))
+    y = S.conv(x, W, rng.normal(size=2))
+    np.testing.assert_allclose(y, np.repeat(y[..., 2:3], 6, axis=3), rtol=1e-12, atol=1e-12)
+
+
+def test_conv_with_mirror_symmetric_weights_is_the_method_of_images():
+    """With weights symmetric under dx -> -dx, the convolution of a tube equals the
+    circular convolution of its mirror image doubled domain (x, then x reversed)
+    restricted to the tube: the half-way wall as a mirror."""
+    rng = np.random.default_rng(8)
+    x = rng.normal(size=(2, 3, 4, 5))
+    W = rng.normal(size=(27, 3, 2))
+    for tap in range(27):
+        dz, dy, dx = S.tap_offset(tap)
+        if dx == 1:
+            W[tap] = W[tap - 2]                      # tap (dz, dy, -1)
+    b = rng.normal(size=3)
+    ext = np.concatenate([x, x[..., ::-1]], axis=3)
+    circ = np.zeros((3,) + ext.shape[1:])
+    for tap in range(27):
+        dz, dy, dx = S.tap_offset(tap)
+        circ += np.tensordot(W[tap], np.roll(ext, (-dz, -dy, -dx), axis=(1, 2, 3)), axes=(1, 0))
+    circ += b[:, None, None, None]
+    np.testing.assert_allclose(S.conv(x, W, b), circ[..., :5], rtol=1e-12, atol=1e-12)
 
 
 def test_conv_input_grad_is_the_adjoint():
@@ -222,16 +252,18 @@ def test_conservative_output_keeps_moles_exactly():
     assert np.count_nonzero(np.abs(d) > 1e-15) == 2
 
 
-def test_conservative_loss_gradient_matches_central_differences():
-    """The adjoint of the divergence and of p = T sum n, X = n / sum n."""
+@pytest.mark.parametrize("wf", [0.0, 3e5])
+def test_conservative_loss_gradient_matches_central_differences(wf):
+    """The adjoint of the divergence and of p = T sum n, X = n / sum n, and of the
+    x-flux term (weight in the p slot)."""
     M = 3
     f, y, scale = _cons_problem(seed=13, M=M)
     tgt, _ = S.conservative_fields(f, 0.3 * np.random.default_rng(14).normal(size=y.shape), scale, M)
-    w = np.array([1e6, 2e6, 5e5, 1e4, 1e5, 1e5, 1e5, 0.0])
+    w = np.array([1e6, 2e6, 5e5, 1e4, 1e5, 1e5, 1e5, wf])
     N = f[0].size
     L, dy = S.conservative_loss(f, y, tgt, w, scale, M, N)
     rng = np.random.default_rng(15)
-    h = 1e-6
+    h = 1e-4                     # loss ~0.2, gradients ~1e-6: a smaller step is round-off
     for _ in range(40):
         idx = tuple(int(rng.integers(0, s)) for s in y.shape)
         yp, ym = y.copy(), y.copy()
@@ -239,6 +271,34 @@ def test_conservative_loss_gradient_matches_central_differences():
         ym[idx] -= h
         fd = (S.conservative_loss(f, yp, tgt, w, scale, M, N)[0] - S.conservative_loss(f, ym, tgt, w, scale, M, N)[0]) / (2 * h)
         assert dy[idx] == pytest.approx(fd, rel=1e-5, abs=1e-12), idx
+
+
+def test_flux_target_reconstructs_the_fluxes_of_a_walled_tube():
+    """Fields uniform in y and z, a target made by known x fluxes (none through the
+    walls) and known T, u changes: the target fluxes, minus the change summed from
+    the left wall, are those fluxes, so predicting them gives zero loss; a uniform
+    offset on every interior face (invisible to the interior divergence) does not."""
+    M = 3
+    rng = np.random.default_rng(21)
+    f, _, scale = _cons_problem(seed=22, M=M, shape=(1, 1, 9))
+    f = np.repeat(np.repeat(f, 2, axis=1), 3, axis=2)          # [C][2][3][9], uniform in y, z
+    y = np.zeros((3 * M + 4,) + f.shape[1:])
+    for s in range(M):
+        y[3 * s] = rng.normal(size=9)[None, None, :]
+    y[3 * M:] = rng.normal(size=(4, 1, 1, 1))
+    for s in range(M):
+        y[3 * s][..., -1] = 0.0                               # the wall face
+    tgt, _ = S.conservative_fields(f, y, scale, M)
+    w = np.array([1e6, 2e6, 5e5, 1e4, 1e5, 1e5, 1e5, 3e5])
+    L, dy = S.conservative_loss(f, y, tgt, w, scale, M, f[0].size)
+    assert L < 1e-18 and np.abs(dy).max() < 1e-9
+    y2 = y.copy()
+    y2[0][..., :-1] += 0.1                                    # uniform offset, species 0
+    _, n2 = S.conservative_fields(f, y2, scale, M)
+    _, n1 = S.conservative_fields(f, y, scale, M)
+    assert np.abs(n2 - n1)[..., 1:-1].max() < 1e-15           # the interior does not see it
+    L2, _ = S.conservative_loss(f, y2, tgt, w * np.r_[np.zeros(7), 1.0], scale, M, f[0].size)
+    assert L2 == pytest.approx(3e5 * (0.1 * 1e-4) ** 2 * 8 / 9, rel=1e-9)   # 8 open faces of 9 per row
 
 
 def test_network_gradient_conservative_form():
@@ -253,7 +313,7 @@ def test_network_gradient_conservative_form():
     norm = {"in_shift": np.full(C, 0.2), "in_scale": np.full(C, 3.0), "out_scale": scale}
     p = S.he_init(C, depth, 17, width=width, gain=3.0, species=M).astype(np.float64)
     p += 0.1 * rng.normal(size=p.size)
-    w = np.array([1e6, 1e6, 1e6, 1e4, 1e5, 1e5, 1e5, 0.0])
+    w = np.array([1e6, 1e6, 1e6, 1e4, 1e5, 1e5, 1e5, 2e5])
     L, g = S.loss_and_grad(p, fs, tg, norm, C, depth, width, weight=w, species=M)
     h = 1e-6
     for k in rng.choice(p.size, 30, replace=False):
