@@ -274,6 +274,14 @@ int validate_one(const mclbm_params* p, std::string& err)
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) { err = "grid sizes must be positive"; return MCLBM_EARG; }
   const int64_t n = (int64_t)p->nx * p->ny * p->nz;
   if (n >= ((int64_t)1 << 31)) { err = "nx*ny*nz must be below 2^31"; return MCLBM_EARG; }
+  // the kernels address one lattice direction (or record field) of a tube with a
+  // 32-bit byte offset: n times the widest element (FP64 storage and records: 8
+  // bytes, otherwise 4) must stay below 2^32
+  const int64_t widest = p->precision == MCLBM_FP64 ? 8 : 4;
+  if (n * widest >= ((int64_t)1 << 32)) {
+    err = "nx*ny*nz times the element size must be below 2^32 bytes";
+    return MCLBM_EARG;
+  }
   if (p->wall_x != 0 && p->wall_x != 1) { err = "wall_x must be 0 or 1"; return MCLBM_EARG; }
   if (p->wall_x && p->nx < 2) { err = "walls need nx >= 2"; return MCLBM_EARG; }
   if (p->precision < MCLBM_FP64 || p->precision > MCLBM_BF16) { err = "unknown precision"; return MCLBM_EARG; }

@@ -366,15 +366,24 @@ __global__ __launch_bounds__(256) void k_bgrad(const NTube* __restrict__ tubes, 
   partial[(size_t)tile * C + c] = s;
 }
 
-// grad[c] += sum_t partial[t][c] for the real channels c < count (row stride C).
-__global__ void k_bgrad_reduce(const float* __restrict__ partial, int ntiles, int C, int count,
-                               float* __restrict__ grad)
+// grad[c] += sum_t partial[t][c] for the real channels c < count (row stride C):
+// block c, thread i sums tiles i, i + 256, ..., then a tree in LDS; a fixed order,
+// so the result is deterministic.
+__global__ __launch_bounds__(256) void k_bgrad_reduce(const float* __restrict__ partial, int ntiles, int C,
+                                                      int count, float* __restrict__ grad)
 {
-  const int c = threadIdx.x;
+  __shared__ float red[256];
+  const int c = blockIdx.x;
   if (c >= count) return;
   float s = 0.f;
-  for (int t = 0; t < ntiles; ++t) s += partial[(size_t)t * C + c];
-  grad[c] += s;
+  for (int t = threadIdx.x; t < ntiles; t += 256) s += partial[(size_t)t * C + c];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) grad[c] += red[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -974,8 +983,8 @@ void bgrad(mclbm_nn* net, const bf16* dY, int C, int layer)
 {
   hipLaunchKernelGGL(k_bgrad, dim3((unsigned)net->ntiles), dim3(256), 0, net->stream, net->dTubes, net->dTileTube,
                      net->ntubes, C, dY, net->bpart);
-  hipLaunchKernelGGL(k_bgrad_reduce, dim3(1), dim3(64), 0, net->stream, net->bpart, (int)net->ntiles, C,
-                     net->out_r[layer], net->grad + net->b_off[layer]);
+  hipLaunchKernelGGL(k_bgrad_reduce, dim3((unsigned)net->out_r[layer]), dim3(256), 0, net->stream, net->bpart,
+                     (int)net->ntiles, C, net->out_r[layer], net->grad + net->b_off[layer]);
 }
 
 }  // namespace

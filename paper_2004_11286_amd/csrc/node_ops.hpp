@@ -121,9 +121,20 @@ __host__ __device__ __forceinline__ R load_dev(const S* __restrict__ p, size_t i
   return R(p[idx]) * inv_scale;
 }
 
+// Element idx of the array that starts at base. The base is the same for every
+// lane of a wavefront (an array of one lattice direction, or of one record field,
+// of one tube) and the byte offset fits in 32 bits (a tube's node count times the
+// widest element is below 2^32, checked at context creation), so the access is a
+// scalar base plus a 32-bit vector offset instead of 64-bit address arithmetic.
+template <typename T>
+__host__ __device__ __forceinline__ T* at32(T* base, uint32_t idx)
+{
+  return (T*)((char*)base + idx * (uint32_t)sizeof(T));
+}
+
 // Neighbour offsets of a node: x positions, y and z strides, wrapped periodically.
 struct Nbr {
-  int64_t x[3], y[3], z[3];   // index contributions for c = -1, 0, +1
+  uint32_t x[3], y[3], z[3];  // index contributions for c = -1, 0, +1
   bool lo, hi;                // node touches the x = 0 / x = nx-1 wall
 };
 
@@ -138,16 +149,16 @@ __host__ __device__ __forceinline__ Nbr neighbours(const Params<R>& P, int64_t n
   const uint32_t t = nd / nx;
   const uint32_t y = t % ny;
   const uint32_t z = t / ny;
-  const int64_t sy = nx, sz = (int64_t)nx * ny;
+  const uint32_t sy = nx, sz = nx * ny;
   b.x[0] = x == 0 ? nx - 1 : x - 1;
   b.x[1] = x;
   b.x[2] = x == nx - 1 ? 0 : x + 1;
-  b.y[0] = (int64_t)(y == 0 ? ny - 1 : y - 1) * sy;
-  b.y[1] = (int64_t)y * sy;
-  b.y[2] = (int64_t)(y == ny - 1 ? 0 : y + 1) * sy;
-  b.z[0] = (int64_t)(z == 0 ? nz - 1 : z - 1) * sz;
-  b.z[1] = (int64_t)z * sz;
-  b.z[2] = (int64_t)(z == nz - 1 ? 0 : z + 1) * sz;
+  b.y[0] = (y == 0 ? ny - 1 : y - 1) * sy;
+  b.y[1] = y * sy;
+  b.y[2] = (y == ny - 1 ? 0 : y + 1) * sy;
+  b.z[0] = (z == 0 ? nz - 1 : z - 1) * sz;
+  b.z[1] = z * sz;
+  b.z[2] = (z == nz - 1 ? 0 : z + 1) * sz;
   b.lo = x == 0;
   b.hi = x == nx - 1;
   return b;
@@ -155,9 +166,9 @@ __host__ __device__ __forceinline__ Nbr neighbours(const Params<R>& P, int64_t n
 
 // Stencil neighbour index: at an x wall the ghost node mirrors the boundary node.
 template <bool WALLS>
-__host__ __device__ __forceinline__ int64_t stencil_index(const Nbr& b, int ci, int cj, int ck)
+__host__ __device__ __forceinline__ uint32_t stencil_index(const Nbr& b, int ci, int cj, int ck)
 {
-  int64_t xi = b.x[ci + 1];
+  uint32_t xi = b.x[ci + 1];
   if (WALLS) {
     if (ci < 0 && b.lo) xi = b.x[1];
     if (ci > 0 && b.hi) xi = b.x[1];
@@ -254,6 +265,7 @@ __host__ __device__ __forceinline__ void state_node(const Params<double>& P, con
 {
   using D = double;
   const size_t n = (size_t)P.n;
+  const uint32_t nd = (uint32_t)node;
   constexpr int LF = M - 1, LG = M;
   D rho_s[M], js[M][3];
 #pragma unroll
@@ -261,7 +273,7 @@ __host__ __device__ __forceinline__ void state_node(const Params<double>& P, con
     D r = 0.0, ja[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const D d = load_dev<S, D>(pop, (size_t)(a * Q + i) * n + node, P.inv_scale[a]);
+      const D d = load_dev<S, D>(at32(pop + (size_t)(a * Q + i) * n, nd), 0, P.inv_scale[a]);
       r += d;
       acc_c(ja[0], cx(i), d);
       acc_c(ja[1], cy(i), d);
@@ -277,7 +289,7 @@ __host__ __device__ __forceinline__ void state_node(const Params<double>& P, con
   D rhoE = 0.0, q[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const D d = load_dev<S, D>(pop, (size_t)(LF * Q + i) * n + node, P.inv_scale[LF]);
+    const D d = load_dev<S, D>(at32(pop + (size_t)(LF * Q + i) * n, nd), 0, P.inv_scale[LF]);
     rho += d;
     acc_c(j[0], cx(i), d);
     acc_c(j[1], cy(i), d);
@@ -288,7 +300,7 @@ __host__ __device__ __forceinline__ void state_node(const Params<double>& P, con
     acc_c(Pxy, cx(i) * cy(i), d);
     acc_c(Pxz, cx(i) * cz(i), d);
     acc_c(Pyz, cy(i) * cz(i), d);
-    const D e = load_dev<S, D>(pop, (size_t)(LG * Q + i) * n + node, P.inv_scale[LG]);
+    const D e = load_dev<S, D>(at32(pop + (size_t)(LG * Q + i) * n, nd), 0, P.inv_scale[LG]);
     rhoE += e;
     acc_c(q[0], cx(i), e);
     acc_c(q[1], cy(i), e);
@@ -326,7 +338,7 @@ __host__ __device__ __forceinline__ void state_node(const Params<double>& P, con
     for (int c = 0; c < 3; ++c) up += s.u[c] * (Pn[c][k] - (c == k ? s.P : 0.0) - rho * s.u[c] * s.u[k]);
     qn[k] = q[k] - hyd * rho * s.u[k] - up;
   }
-  auto put = [&](int f, D v) { stream_store(&rec[(size_t)f * n + node], Rec(v)); };
+  auto put = [&](int f, D v) { stream_store(at32(rec + (size_t)f * n, nd), Rec(v)); };
 #pragma unroll
   for (int k = 0; k < 3; ++k) put(REC_PHIX + k, j[k] * (1.0 - 3.0 * theta) - j[k] * s.u[k] * s.u[k]);
   put(REC_OMEGA, omega);
@@ -354,31 +366,32 @@ __host__ __device__ __forceinline__ void gfield_node(const Params<double>& P, co
                                             R* __restrict__ G, int64_t node)
 {
   const size_t n = (size_t)P.n;
+  const uint32_t nd = (uint32_t)node;
   Nbr b = neighbours(P, node);
   R dphi[3] = {R(0), R(0), R(0)};
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     if (csq(i) == 0) continue;
-    int64_t nb = stencil_index<WALLS>(b, cx(i), cy(i), cz(i));
+    const uint32_t nb = stencil_index<WALLS>(b, cx(i), cy(i), cz(i));
     const R w3 = R(3.0 * w13(i));
     if (cx(i)) {
-      R v = rec[(size_t)REC_PHIX * n + nb];
+      R v = *at32(rec + (size_t)REC_PHIX * n, nb);
       if (is_ghost<WALLS>(b, cx(i))) v = -v;        // Phi_x is odd under the wall mirror
       dphi[0] += cx(i) > 0 ? w3 * v : -(w3 * v);
     }
     if (cy(i)) {
-      R v = rec[(size_t)REC_PHIY * n + nb];
+      R v = *at32(rec + (size_t)REC_PHIY * n, nb);
       dphi[1] += cy(i) > 0 ? w3 * v : -(w3 * v);
     }
     if (cz(i)) {
-      R v = rec[(size_t)REC_PHIZ * n + nb];
+      R v = *at32(rec + (size_t)REC_PHIZ * n, nb);
       dphi[2] += cz(i) > 0 ? w3 * v : -(w3 * v);
     }
   }
-  R om = rec[(size_t)REC_OMEGA * n + node];
+  R om = *at32(rec + (size_t)REC_OMEGA * n, nd);
   R f = R(1) / om - R(0.5);
 #pragma unroll
-  for (int k = 0; k < 3; ++k) stream_store(&G[(size_t)k * n + node], R(f * dphi[k]));
+  for (int k = 0; k < 3; ++k) stream_store(at32(G + (size_t)k * n, nd), R(f * dphi[k]));
 }
 
 // --------------------------------------------------------------------------
@@ -449,10 +462,24 @@ __host__ __device__ __forceinline__ void push(const Params<R>& P, S* __restrict_
   if (WALLS && ((cx(i) < 0 && b.lo) || (cx(i) > 0 && b.hi))) {
     dst[(size_t)(l * Q + opp(i)) * n + node] = v;    // half-way bounce-back
   } else {
-    const int64_t d = b.x[cx(i) + 1] + b.y[cy(i) + 1] + b.z[cz(i) + 1];
+    const int64_t d = (int64_t)b.x[cx(i) + 1] + b.y[cy(i) + 1] + b.z[cz(i) + 1];
     dst[(size_t)(l * Q + i) * n + d] = v;    // plain store: the shifted pushes of a wavefront
                                               // merge into whole lines in the cache
   }
+}
+
+// Load the Q stored values of one lattice of a node into v (lat: the lattice's
+// first direction array), all issued before any is used: the compiler barrier
+// after the loads keeps the scheduler from interleaving each load with its use
+// (one load in flight at a time), which it otherwise may do to save registers.
+// Where this matters is decided per kernel (GROUP_LOADS in collide_node): holding
+// a lattice's values costs registers, which other kernels need more.
+template <typename S>
+__host__ __device__ __forceinline__ void load_lattice(const S* __restrict__ lat, size_t n, uint32_t node, S v[Q])
+{
+#pragma unroll
+  for (int i = 0; i < Q; ++i) v[i] = stream_load(at32(lat + (size_t)i * n, node));
+  lattice_barrier();
 }
 
 // PART selects the lattices: 0 all, 1 the stored species lattices, 2 the momentum
@@ -464,8 +491,13 @@ __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const 
 {
   const size_t n = (size_t)P.n;
   constexpr int LF = M - 1, LG = M;
+  // issue a lattice's loads together (load_lattice) where the scheduler otherwise
+  // serialises them: 16-bit storage, and the unsplit collision of three or more
+  // species (one wave per SIMD, registers to spare); elsewhere each load is
+  // followed by its use
+  constexpr bool GROUP_LOADS = sizeof(S) == 2 || (PART == 0 && M >= 3);
   const Nbr b = neighbours(P, node);
-  auto get = [&](int f) -> R { return R(rec[(size_t)f * n + node]); };
+  auto get = [&](int f) -> R { return R(*at32(rec + (size_t)f * n, (uint32_t)node)); };
 
   // ---- node state from the record
   const R rho = get(REC_RHO);
@@ -515,15 +547,15 @@ __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const 
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     if (csq(i) == 0) continue;
-    const int64_t nb = stencil_index<WALLS>(b, cx(i), cy(i), cz(i));
+    const uint32_t nb = stencil_index<WALLS>(b, cx(i), cy(i), cz(i));
     const R w3 = R(3.0 * w13(i));
-    const R cpn = w3 * R(rec[(size_t)REC_CP * n + nb]);
+    const R cpn = w3 * R(*at32(rec + (size_t)REC_CP * n, nb));
     acc_c(gcp[0], cx(i), cpn);
     acc_c(gcp[1], cy(i), cpn);
     acc_c(gcp[2], cz(i), cpn);
-    if (cx(i)) acc_c(dG[0], cx(i), w3 * R(G[nb]));
-    if (cy(i)) acc_c(dG[1], cy(i), w3 * R(G[n + nb]));
-    if (cz(i)) acc_c(dG[2], cz(i), w3 * R(G[2 * n + nb]));
+    if (cx(i)) acc_c(dG[0], cx(i), w3 * R(*at32(G, nb)));
+    if (cy(i)) acc_c(dG[1], cy(i), w3 * R(*at32(G + n, nb)));
+    if (cz(i)) acc_c(dG[2], cz(i), w3 * R(*at32(G + 2 * n, nb)));
   }
   }
   const R Xc[3] = {-dG[0], -dG[1], -dG[2]};
@@ -562,10 +594,16 @@ __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const 
       S v[Q];
       R t0 = R(0), s0 = R(0);
       Rng rng(node, a, step);
+      if constexpr (GROUP_LOADS) {
+        load_lattice(src + (size_t)a * Q * n, n, (uint32_t)node, v);
 #pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        v[i] = stream_load(&src[(size_t)(a * Q + i) * n + node]);
-        t0 += from_store<S, R>(P, a, v[i]);
+        for (int i = 0; i < Q; ++i) t0 += from_store<S, R>(P, a, v[i]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          v[i] = stream_load(at32(src + (size_t)(a * Q + i) * n, (uint32_t)node));
+          t0 += from_store<S, R>(P, a, v[i]);
+        }
       }
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
@@ -602,9 +640,10 @@ __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const 
     S v[Q];
     R t0 = R(0), t1[3] = {R(0), R(0), R(0)}, s0 = R(0), s1[3] = {R(0), R(0), R(0)};
     Rng rng(node, LF, step);
+    if constexpr (GROUP_LOADS) load_lattice(src + (size_t)LF * Q * n, n, (uint32_t)node, v);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      v[i] = stream_load(&src[(size_t)(LF * Q + i) * n + node]);
+      if constexpr (!GROUP_LOADS) v[i] = stream_load(at32(src + (size_t)(LF * Q + i) * n, (uint32_t)node));
       const R d = from_store<S, R>(P, LF, v[i]);
       t0 += d;
       acc_c(t1[0], cx(i), d);
@@ -683,9 +722,10 @@ __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const 
     S v[Q];
     R t0 = R(0), s0 = R(0);
     Rng rng(node, LG, step);
+    if constexpr (GROUP_LOADS) load_lattice(src + (size_t)LG * Q * n, n, (uint32_t)node, v);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      v[i] = stream_load(&src[(size_t)(LG * Q + i) * n + node]);
+      if constexpr (!GROUP_LOADS) v[i] = stream_load(at32(src + (size_t)(LG * Q + i) * n, (uint32_t)node));
       t0 += from_store<S, R>(P, LG, v[i]);
     }
 #pragma unroll
