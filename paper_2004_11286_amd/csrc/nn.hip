@@ -48,7 +48,18 @@ struct NTube {
   int32_t nx, ny, nz;
   int32_t first_tile, ntiles;
   int32_t pad;
+  int64_t ntot;   // nodes of all tubes (the stride of the activation layout)
 };
+
+// Activations and activation gradients (BF16) are chunk-major: [C / 16][n][16]
+// over the n nodes of all tubes, so the 16 channels one MFMA step takes from a
+// node are 32 contiguous bytes and a wavefront's gather of consecutive nodes
+// covers whole cache lines (node-major rows of 64 channels would use 32 bytes of
+// each 128-byte line per load). Channel counts are multiples of 16.
+__device__ __forceinline__ size_t aidx(const NTube& tb, int64_t gnode, int c)
+{
+  return (size_t)(c >> 4) * (size_t)tb.ntot * 16 + (size_t)gnode * 16 + (size_t)(c & 15);
+}
 
 // The tube and tube-local node of lane-independent tile `tile`.
 __device__ inline NTube tube_of(const NTube* tubes, const int32_t* tile_tube, int ntubes, int tile)
@@ -160,13 +171,13 @@ __global__ __launch_bounds__(256) void k_conv(const NTube* __restrict__ tubes, c
       for (int kc = 0; kc < KC; ++kc) {
         bf16x8 v;
         if (ok) {
-          v = *(const bf16x8*)(in + nb * CIN + kc * 16 + khalf);
+          v = *(const bf16x8*)(in + aidx(tb, nb, kc * 16 + khalf));
         } else {
 #pragma unroll
           for (int j = 0; j < 8; ++j) v[j] = (bf16)0.f;
         }
         if (extra) {
-          const bf16x8 e = *(const bf16x8*)(in + ne * CIN + kc * 16 + khalf);
+          const bf16x8 e = *(const bf16x8*)(in + aidx(tb, ne, kc * 16 + khalf));
 #pragma unroll
           for (int j = 0; j < 8; ++j) v[j] = (bf16)((float)v[j] + (float)e[j]);
         }
@@ -206,18 +217,18 @@ __global__ __launch_bounds__(256) void k_conv(const NTube* __restrict__ tubes, c
           bf16x4 o;
 #pragma unroll
           for (int j = 0; j < 4; ++j) o[j] = (bf16)fmaxf(v[j], 0.f);
-          *(bf16x4*)((bf16*)out + gn * COUT + co0) = o;
+          *(bf16x4*)((bf16*)out + aidx(tb, gn, co0)) = o;
         } else if (EPI == 1) {
           f32x4 o;
 #pragma unroll
           for (int j = 0; j < 4; ++j) o[j] = v[j];
           *(f32x4*)((float*)out + gn * COUT + co0) = o;
         } else {
-          const bf16x4 mk = *(const bf16x4*)(mask + gn * COUT + co0);
+          const bf16x4 mk = *(const bf16x4*)(mask + aidx(tb, gn, co0));
           bf16x4 o;
 #pragma unroll
           for (int j = 0; j < 4; ++j) o[j] = (bf16)((float)mk[j] > 0.f ? v[j] : 0.f);
-          *(bf16x4*)((bf16*)out + gn * COUT + co0) = o;
+          *(bf16x4*)((bf16*)out + aidx(tb, gn, co0)) = o;
         }
       }
   }
@@ -267,7 +278,7 @@ __global__ __launch_bounds__(256) void k_wgrad(const NTube* __restrict__ tubes, 
       for (int c8 = 0; c8 < COUT / 8; ++c8) {
         bf16x8 v;
         if (valid) {
-          v = *(const bf16x8*)(dY + (tb.base + node) * COUT + c8 * 8);
+          v = *(const bf16x8*)(dY + aidx(tb, tb.base + node, c8 * 8));
         } else {
 #pragma unroll
           for (int j = 0; j < 8; ++j) v[j] = (bf16)0.f;
@@ -290,7 +301,7 @@ __global__ __launch_bounds__(256) void k_wgrad(const NTube* __restrict__ tubes, 
       for (int c8 = 0; c8 < CIN / 8; ++c8) {
         bf16x8 v;
         if (ok) {
-          v = *(const bf16x8*)(X + nb * CIN + c8 * 8);
+          v = *(const bf16x8*)(X + aidx(tb, nb, c8 * 8));
         } else {
 #pragma unroll
           for (int j = 0; j < 8; ++j) v[j] = (bf16)0.f;
@@ -362,7 +373,7 @@ __global__ __launch_bounds__(256) void k_bgrad(const NTube* __restrict__ tubes, 
   if (c >= C) return;
   float s = 0.f;
   const int n0 = (tile - tb.first_tile) * TILE;
-  for (int i = 0; i < TILE && n0 + i < n_t; ++i) s += (float)dY[(tb.base + n0 + i) * C + c];
+  for (int i = 0; i < TILE && n0 + i < n_t; ++i) s += (float)dY[aidx(tb, tb.base + n0 + i, c)];
   partial[(size_t)tile * C + c] = s;
 }
 
@@ -418,13 +429,12 @@ __global__ __launch_bounds__(256) void k_pack_in(const NTube* __restrict__ tubes
     if (c < C + P + S) return cond[(size_t)t * S + (c - C - P)];
     return 0.f;
   };
-  bf16* dst = act0 + (tb.base + node) * CIN0;
 #pragma unroll
   for (int c8 = 0; c8 < CIN0 / 8; ++c8) {
     bf16x8 v;
 #pragma unroll
     for (int j = 0; j < 8; ++j) v[j] = (bf16)value(c8 * 8 + j);
-    *(bf16x8*)(dst + c8 * 8) = v;
+    *(bf16x8*)(act0 + aidx(tb, tb.base + node, c8 * 8)) = v;
   }
 }
 
@@ -474,7 +484,7 @@ __global__ __launch_bounds__(256) void k_loss(const NTube* __restrict__ tubes, c
       bf16x8 v;
 #pragma unroll
       for (int j = 0; j < 8; ++j) v[j] = d[c8 * 8 + j];
-      *(bf16x8*)(dY + gn * COUTL + c8 * 8) = v;
+      *(bf16x8*)(dY + aidx(tb, gn, c8 * 8)) = v;
     }
   }
   red[threadIdx.x] = l;
@@ -639,7 +649,7 @@ __global__ __launch_bounds__(256) void k_loss_cons(const NTube* __restrict__ tub
       bf16x8 v;
 #pragma unroll
       for (int j = 0; j < 8; ++j) v[j] = d[c8 * 8 + j];
-      *(bf16x8*)(dY + gn * COUTL + c8 * 8) = v;
+      *(bf16x8*)(dY + aidx(tb, gn, c8 * 8)) = v;
     }
   }
   red[threadIdx.x] = l;
@@ -675,7 +685,7 @@ __global__ __launch_bounds__(256) void k_loss_cons_flux(const NTube* __restrict_
       if (a == 0 && open && nm.weight[M + 4] != 0.f)
         v += 2.0 * nm.weight[M + 4] * ((double)y[gn * COUTL + 3 * s] * nm.out_scale[3 * s] - (double)fs[gn * M + s]) *
              inv_n;
-      dY[gn * COUTL + 3 * s + a] = (bf16)(float)(v * nm.out_scale[3 * s + a]);
+      dY[aidx(tb, gn, 3 * s + a)] = (bf16)(float)(v * nm.out_scale[3 * s + a]);
     }
   }
 }
@@ -1087,6 +1097,7 @@ extern "C" int mclbm_nn_create(int32_t channels, int32_t two_term, int32_t condi
     tb.first_tile = tile;
     tb.ntiles = (int32_t)((n + TILE - 1) / TILE);
     tb.pad = 0;
+    tb.ntot = lay.n;
     for (int k = 0; k < tb.ntiles; ++k) net->hTileTube[tile + k] = t;
     tile += tb.ntiles;
     base += n;
