@@ -80,20 +80,18 @@ __device__ inline int64_t wrap_index(const NTube& tb, int x, int y, int z)
 // Convolution (forward, and backward with respect to the input)
 // ---------------------------------------------------------------------------
 // EPI 0: + bias, ReLU, BF16 out; EPI 1: + bias, FP32 out; EPI 2: times the
-// ReLU mask (mask > 0), BF16 out. sign = +1 is the forward gather, in(x + d)
-// with x clamped to the tube (replicate padding at the walls) and y, z wrapped;
-// sign = -1 its adjoint, in(x - d) with nothing from outside the tube, plus, at
-// a wall node, the ghost's share: the forward took the ghost value of tap
-// dx = -1 at x = 0 (dx = +1 at x = nx - 1) from the wall node itself, so that
-// node's gradient also collects in(wall node) under the same tap. The two
-// operands of that tap are added in FP32 and rounded to BF16 once.
+// ReLU mask (mask > 0), BF16 out. EPI 0 and 1 gather forward, in(x + d) with x
+// clamped to the tube (replicate padding at the walls) and y, z wrapped; EPI 2
+// is the adjoint, in(x - d) with nothing from outside the tube, plus, at a wall
+// node, the ghost's share (ghost() below).
 template <int CIN, int COUT, int EPI>
 __global__ __launch_bounds__(256) void k_conv(const NTube* __restrict__ tubes, const int32_t* __restrict__ tile_tube,
                                               int ntubes, const bf16* __restrict__ W, const float* __restrict__ bias,
                                               const bf16* __restrict__ in, const bf16* __restrict__ mask,
-                                              void* __restrict__ out, int sign)
+                                              void* __restrict__ out)
 {
   static_assert(CIN % 16 == 0 && COUT % 32 == 0, "channel counts must fit the 32x32x16 MFMA");
+  constexpr int SIGN = EPI == 2 ? -1 : 1;  // the forward gathers in(x + d), its adjoint (EPI 2) in(x - d)
   constexpr int LS = CIN + 8;              // LDS row stride (bf16): staggers the banks of the rows
   constexpr int MB = COUT / 32;
   constexpr int KC = CIN / 16;
@@ -147,43 +145,64 @@ __global__ __launch_bounds__(256) void k_conv(const NTube* __restrict__ tubes, c
   store_w(0);
   __syncthreads();
   const int khalf = 8 * (lane >> 5);
-  for (int tap = 0; tap < NTAP; ++tap) {
-    const int buf = tap & 1;
-    if (tap + 1 < NTAP) load_w(tap + 1);
-    const int dx = sign * (tap % 3 - 1), dy = sign * ((tap / 3) % 3 - 1), dz = sign * (tap / 9 - 1);
-    bf16x8 bop[2][KC];
+  // the activations of one tap (B operands), gathered one tap ahead of the
+  // multiplications that use them so that their latency hides behind the
+  // previous tap's MFMAs
+  auto gather = [&](int tap, bf16x8 (&bop)[2][KC]) {
+    const int dx = SIGN * (tap % 3 - 1), dy = SIGN * ((tap / 3) % 3 - 1), dz = SIGN * (tap / 9 - 1);
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
       const int x = xs[b] + dx;
-      bool ok, extra = false;
+      bool ok;
       int xr;
-      if (sign > 0) {
+      if constexpr (SIGN > 0) {
         xr = x < 0 ? 0 : (x >= tb.nx ? tb.nx - 1 : x);
         ok = valid[b];
       } else {
         ok = valid[b] && x >= 0 && x < tb.nx;
         xr = ok ? x : 0;
-        extra = valid[b] && ((xs[b] == 0 && dx == 1) || (xs[b] == tb.nx - 1 && dx == -1));
       }
       const int64_t nb = wrap_index(tb, xr, ys[b] + dy, zs[b] + dz);
-      const int64_t ne = wrap_index(tb, xs[b], ys[b] + dy, zs[b] + dz);
 #pragma unroll
       for (int kc = 0; kc < KC; ++kc) {
-        bf16x8 v;
         if (ok) {
-          v = *(const bf16x8*)(in + aidx(tb, nb, kc * 16 + khalf));
+          bop[b][kc] = *(const bf16x8*)(in + aidx(tb, nb, kc * 16 + khalf));
         } else {
 #pragma unroll
-          for (int j = 0; j < 8; ++j) v[j] = (bf16)0.f;
+          for (int j = 0; j < 8; ++j) bop[b][kc][j] = (bf16)0.f;
         }
-        if (extra) {
-          const bf16x8 e = *(const bf16x8*)(in + aidx(tb, ne, kc * 16 + khalf));
-#pragma unroll
-          for (int j = 0; j < 8; ++j) v[j] = (bf16)((float)v[j] + (float)e[j]);
-        }
-        bop[b][kc] = v;
       }
     }
+  };
+  // the adjoint's share of a ghost: at a wall node the forward took the ghost of
+  // tap dx = -1 at x = 0 (dx = +1 at x = nx - 1) from the wall node itself, so the
+  // wall node also collects in(wall node) under that tap; the two operands are
+  // added in FP32 and rounded once (wall lanes only, loaded when used)
+  auto ghost = [&](int tap, bf16x8 (&bop)[2][KC]) {
+    const int dx = SIGN * (tap % 3 - 1), dy = SIGN * ((tap / 3) % 3 - 1), dz = SIGN * (tap / 9 - 1);
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const bool extra = valid[b] && ((xs[b] == 0 && dx == 1) || (xs[b] == tb.nx - 1 && dx == -1));
+      if (extra) {
+        const int64_t ne = wrap_index(tb, xs[b], ys[b] + dy, zs[b] + dz);
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) {
+          const bf16x8 e = *(const bf16x8*)(in + aidx(tb, ne, kc * 16 + khalf));
+#pragma unroll
+          for (int j = 0; j < 8; ++j) bop[b][kc][j] = (bf16)((float)bop[b][kc][j] + (float)e[j]);
+        }
+      }
+    }
+  };
+  bf16x8 bcur[2][KC], bnxt[2][KC];
+  gather(0, bcur);
+  for (int tap = 0; tap < NTAP; ++tap) {
+    const int buf = tap & 1;
+    if (tap + 1 < NTAP) {
+      load_w(tap + 1);
+      gather(tap + 1, bnxt);
+    }
+    if constexpr (SIGN < 0) ghost(tap, bcur);
 #pragma unroll
     for (int kc = 0; kc < KC; ++kc)
 #pragma unroll
@@ -191,10 +210,14 @@ __global__ __launch_bounds__(256) void k_conv(const NTube* __restrict__ tubes, c
         const bf16x8 a = *(const bf16x8*)(&wl[buf][(mb * 32 + (lane & 31)) * LS + kc * 16 + khalf]);
 #pragma unroll
         for (int b = 0; b < 2; ++b)
-          acc[mb][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bop[b][kc], acc[mb][b], 0, 0, 0);
+          acc[mb][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bcur[b][kc], acc[mb][b], 0, 0, 0);
       }
     if (tap + 1 < NTAP) store_w(buf ^ 1);
     __syncthreads();
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) bcur[b][kc] = bnxt[b][kc];
   }
   // epilogue: lane holds channels co0 .. co0+3 of its node for each group g
 #pragma unroll
@@ -968,10 +991,10 @@ int repack(mclbm_nn* net)
 }
 
 template <int CIN, int COUT, int EPI>
-void conv(mclbm_nn* net, const bf16* W, const float* b, const bf16* in, const bf16* mask, void* out, int sign)
+void conv(mclbm_nn* net, const bf16* W, const float* b, const bf16* in, const bf16* mask, void* out)
 {
   hipLaunchKernelGGL((k_conv<CIN, COUT, EPI>), dim3((unsigned)net->ntiles), dim3(256), 0, net->stream, net->dTubes,
-                     net->dTileTube, net->ntubes, W, b, in, mask, out, sign);
+                     net->dTileTube, net->ntubes, W, b, in, mask, out);
 }
 
 template <int CIN, int COUT>
@@ -1225,9 +1248,9 @@ extern "C" int mclbm_nn_forward(mclbm_nn* net)
   hipLaunchKernelGGL(k_pack_in, dim3(grid), dim3(256), 0, net->stream, net->dTubes, net->dTileTube, net->ntubes,
                      net->C, net->P, net->S, net->norm, net->fin, net->cond, net->act[0]);
   const int D = net->depth;
-  conv<CIN0, WIDTH, 0>(net, net->wf[0], net->bp[0], net->act[0], nullptr, net->act[1], 1);
-  for (int k = 1; k + 1 < D; ++k) conv<WIDTH, WIDTH, 0>(net, net->wf[k], net->bp[k], net->act[k], nullptr, net->act[k + 1], 1);
-  conv<WIDTH, COUTL, 1>(net, net->wf[D - 1], net->bp[D - 1], net->act[D - 1], nullptr, net->yout, 1);
+  conv<CIN0, WIDTH, 0>(net, net->wf[0], net->bp[0], net->act[0], nullptr, net->act[1]);
+  for (int k = 1; k + 1 < D; ++k) conv<WIDTH, WIDTH, 0>(net, net->wf[k], net->bp[k], net->act[k], nullptr, net->act[k + 1]);
+  conv<WIDTH, COUTL, 1>(net, net->wf[D - 1], net->bp[D - 1], net->act[D - 1], nullptr, net->yout);
   if (net->Ms > 0)
     hipLaunchKernelGGL(k_unpack_cons, dim3(grid), dim3(256), 0, net->stream, net->dTubes, net->dTileTube,
                        net->ntubes, net->Ms, net->norm, net->fin, net->yout, net->fout);
@@ -1279,12 +1302,12 @@ extern "C" int mclbm_nn_backward(mclbm_nn* net)
   // last layer: dW from dyl and act[D-1]; then the gradient of act[D-1]
   wgrad<WIDTH, COUTL>(net, net->dyl, net->act[D - 1], D - 1);
   bgrad(net, net->dyl, COUTL, D - 1);
-  conv<COUTL, WIDTH, 2>(net, net->wb[D - 1], nullptr, net->dyl, net->act[D - 1], net->dy[0], -1);
+  conv<COUTL, WIDTH, 2>(net, net->wb[D - 1], nullptr, net->dyl, net->act[D - 1], net->dy[0]);
   int cur = 0;
   for (int k = D - 2; k >= 1; --k) {
     wgrad<WIDTH, WIDTH>(net, net->dy[cur], net->act[k], k);
     bgrad(net, net->dy[cur], WIDTH, k);
-    conv<WIDTH, WIDTH, 2>(net, net->wb[k], nullptr, net->dy[cur], net->act[k], net->dy[cur ^ 1], -1);
+    conv<WIDTH, WIDTH, 2>(net, net->wb[k], nullptr, net->dy[cur], net->act[k], net->dy[cur ^ 1]);
     cur ^= 1;
   }
   wgrad<CIN0, WIDTH>(net, net->dy[cur], net->act[0], 0);
