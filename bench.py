@@ -208,7 +208,7 @@ def ensemble_bench(mc, steps: int = 50, seq_steps: int = 10, trial_steps: int = 
 BF16_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix-core peak
 
 
-def surrogate_bench(train_iters: int = 12000):
+def surrogate_bench(train_iters: int = 24000):
     """The learned surrogate: trained by the library's BF16 MFMA kernels on
     trajectories of a 2048-tube ensemble (every 100 steps up to 5000; the tubes
     are one-dimensional, uniform in y and z, so a one-node cross-section carries
@@ -279,7 +279,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
-    ap.add_argument("--surrogate-iters", type=int, default=12000)
+    ap.add_argument("--surrogate-iters", type=int, default=24000)
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes five times (to scale HBM counters)")
     args = ap.parse_args()
