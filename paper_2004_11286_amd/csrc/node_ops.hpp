@@ -115,10 +115,11 @@ __host__ __device__ __forceinline__ R mixture_conductivity(const Params<R>& P, c
   return R(0.5) * (lin + R(1) / harm);
 }
 
+// A stored population (read once per pass: a nontemporal load) as a scaled deviation.
 template <typename S, typename R>
 __host__ __device__ __forceinline__ R load_dev(const S* __restrict__ p, size_t idx, R inv_scale)
 {
-  return R(p[idx]) * inv_scale;
+  return R(stream_load(p + idx)) * inv_scale;
 }
 
 // Element idx of the array that starts at base. The base is the same for every
