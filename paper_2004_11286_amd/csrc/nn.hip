@@ -262,8 +262,9 @@ __global__ __launch_bounds__(256) void k_conv(const NTube* __restrict__ tubes, c
 // (the forward's gather: x clamped to the tube, y and z wrapped)
 // ---------------------------------------------------------------------------
 // The reduction runs over nodes, so both operands are staged transposed in LDS
-// (channel rows, node columns) for 128-node chunks; workgroup (g, tap) sums the
-// chunks g, g + G, ... and writes its partial [g][tap][COUT][CINP].
+// (channel rows, node columns) for 128-node chunks; workgroup (g, (dy, dz)) sums
+// the chunks g, g + G, ... for the taps dx = -1, 0, +1 and writes its partials
+// [g][tap][COUT][CINP].
 constexpr int WCH = 128;   // nodes per staged chunk
 
 template <int CIN, int COUT>
@@ -275,92 +276,134 @@ __global__ __launch_bounds__(256) void k_wgrad(const NTube* __restrict__ tubes, 
   constexpr int S = WCH + 8;
   constexpr int NB = (COUT / 32) * (CINP / 32);
   constexpr int PW = (NB + 3) / 4;
+  // one workgroup takes the three taps dx = -1, 0, +1 of one (dy, dz): the output
+  // gradient chunk is staged once for all three, and the three shifted input
+  // windows overlap (two of them come from the cache)
   __shared__ __attribute__((aligned(16))) bf16 dyt[COUT * S];
-  __shared__ __attribute__((aligned(16))) bf16 xt[CINP * S];
-  const int tap = blockIdx.y, g = blockIdx.x, G = gridDim.x;
+  __shared__ __attribute__((aligned(16))) bf16 xt[3][CINP * S];
+  const int yz = blockIdx.y, g = blockIdx.x, G = gridDim.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
-  f32x16 acc[PW];
+  const int dy = yz % 3 - 1, dz = yz / 3 - 1;
+  const int tap0 = 9 * (dz + 1) + 3 * (dy + 1);   // taps tap0 + k, dx = k - 1
+  f32x16 acc[3][PW];
 #pragma unroll
-  for (int q = 0; q < PW; ++q)
+  for (int k = 0; k < 3; ++k)
 #pragma unroll
-    for (int v = 0; v < 16; ++v) acc[q][v] = 0.f;
+    for (int q = 0; q < PW; ++q)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[k][q][v] = 0.f;
   if (CIN < CINP) {
-    for (int k = threadIdx.x; k < (CINP - CIN) * S; k += 256) xt[CIN * S + k] = (bf16)0.f;
+    for (int e = threadIdx.x; e < 3 * (CINP - CIN) * S; e += 256) {
+      const int k = e / ((CINP - CIN) * S);
+      xt[k][CIN * S + e % ((CINP - CIN) * S)] = (bf16)0.f;
+    }
   }
   const int khalf = 8 * (lane >> 5);
-  for (int ch = g; ch < nchunks; ch += G) {
+  // 4 * WCH staging items over 256 threads, two each: item < WCH stages dY of node
+  // item, item WCH + k WCH + i stages X of node i shifted by dx = k - 1. A chunk's
+  // items are loaded into registers while the previous chunk's MFMAs run.
+  constexpr int C8 = (COUT > CIN ? COUT : CIN) / 8;
+  bf16x8 st[2][C8];
+  auto load_items = [&](int ch) {
     const int tile = ch >> 1;
     const NTube tb = tube_of(tubes, tile_tube, ntubes, tile);
     const int n_t = tb.nx * tb.ny * tb.nz;
-    const int i = threadIdx.x & (WCH - 1);
-    const int node = (tile - tb.first_tile) * TILE + (ch & 1) * WCH + i;
-    const bool valid = node < n_t;
-    if (threadIdx.x < WCH) {
+    const int node0 = (tile - tb.first_tile) * TILE + (ch & 1) * WCH;
 #pragma unroll
-      for (int c8 = 0; c8 < COUT / 8; ++c8) {
-        bf16x8 v;
+    for (int r = 0; r < 2; ++r) {
+      const int item = threadIdx.x + 256 * r;
+      const int node = node0 + (item & (WCH - 1));
+      const bool valid = node < n_t;
+      if (item < WCH) {
+#pragma unroll
+        for (int c8 = 0; c8 < COUT / 8; ++c8) {
+          if (valid) {
+            st[r][c8] = *(const bf16x8*)(dY + aidx(tb, tb.base + node, c8 * 8));
+          } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) st[r][c8][j] = (bf16)0.f;
+          }
+        }
+      } else {
+        const int dx = item / WCH - 2;
+        int x = 0, y = 0, z = 0;
         if (valid) {
-          v = *(const bf16x8*)(dY + aidx(tb, tb.base + node, c8 * 8));
-        } else {
-#pragma unroll
-          for (int j = 0; j < 8; ++j) v[j] = (bf16)0.f;
+          x = node % tb.nx;
+          const int rr = node / tb.nx;
+          y = rr % tb.ny;
+          z = rr / tb.ny;
         }
+        // replicate padding: x clamped to the tube; y, z wrapped
+        const int xx = x + dx < 0 ? 0 : (x + dx >= tb.nx ? tb.nx - 1 : x + dx);
+        const int64_t nb = wrap_index(tb, xx, y + dy, z + dz);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) dyt[(c8 * 8 + j) * S + i] = v[j];
-      }
-    } else {
-      int x = 0, y = 0, z = 0;
-      if (valid) {
-        x = node % tb.nx;
-        const int r = node / tb.nx;
-        y = r % tb.ny;
-        z = r / tb.ny;
-      }
-      const bool ok = valid;                 // replicate padding: x clamped to the tube
-      const int xx = x + dx < 0 ? 0 : (x + dx >= tb.nx ? tb.nx - 1 : x + dx);
-      const int64_t nb = wrap_index(tb, xx, y + dy, z + dz);
+        for (int c8 = 0; c8 < CIN / 8; ++c8) {
+          if (valid) {
+            st[r][c8] = *(const bf16x8*)(X + aidx(tb, nb, c8 * 8));
+          } else {
 #pragma unroll
-      for (int c8 = 0; c8 < CIN / 8; ++c8) {
-        bf16x8 v;
-        if (ok) {
-          v = *(const bf16x8*)(X + aidx(tb, nb, c8 * 8));
-        } else {
-#pragma unroll
-          for (int j = 0; j < 8; ++j) v[j] = (bf16)0.f;
+            for (int j = 0; j < 8; ++j) st[r][c8][j] = (bf16)0.f;
+          }
         }
-#pragma unroll
-        for (int j = 0; j < 8; ++j) xt[(c8 * 8 + j) * S + i] = v[j];
       }
     }
+  };
+  auto store_items = [&]() {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int item = threadIdx.x + 256 * r;
+      const int i = item & (WCH - 1);
+      if (item < WCH) {
+#pragma unroll
+        for (int c8 = 0; c8 < COUT / 8; ++c8)
+#pragma unroll
+          for (int j = 0; j < 8; ++j) dyt[(c8 * 8 + j) * S + i] = st[r][c8][j];
+      } else {
+        const int k = item / WCH - 1;
+#pragma unroll
+        for (int c8 = 0; c8 < CIN / 8; ++c8)
+#pragma unroll
+          for (int j = 0; j < 8; ++j) xt[k][(c8 * 8 + j) * S + i] = st[r][c8][j];
+      }
+    }
+  };
+  if (g < nchunks) load_items(g);
+  for (int ch = g; ch < nchunks; ch += G) {
+    store_items();
     __syncthreads();
+    if (ch + G < nchunks) load_items(ch + G);
 #pragma unroll
     for (int q = 0; q < PW; ++q) {
       const int blk = wave + 4 * q;
       if (blk < NB) {
         const int mb = blk / (CINP / 32), cb = blk % (CINP / 32);
-#pragma unroll 4
+#pragma unroll 2
         for (int k0 = 0; k0 < WCH; k0 += 16) {
           const bf16x8 a = *(const bf16x8*)(&dyt[(mb * 32 + (lane & 31)) * S + k0 + khalf]);
-          const bf16x8 b = *(const bf16x8*)(&xt[(cb * 32 + (lane & 31)) * S + k0 + khalf]);
-          acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[q], 0, 0, 0);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            const bf16x8 b = *(const bf16x8*)(&xt[k][(cb * 32 + (lane & 31)) * S + k0 + khalf]);
+            acc[k][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[k][q], 0, 0, 0);
+          }
         }
       }
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int q = 0; q < PW; ++q) {
-    const int blk = wave + 4 * q;
-    if (blk >= NB) continue;
-    const int mb = blk / (CINP / 32), cb = blk % (CINP / 32);
+  for (int k = 0; k < 3; ++k)
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int row = mb * 32 + 8 * (v / 4) + 4 * (lane >> 5) + (v % 4);
-      const int col = cb * 32 + (lane & 31);
-      partial[(((size_t)g * NTAP + tap) * COUT + row) * CINP + col] = acc[q][v];
+    for (int q = 0; q < PW; ++q) {
+      const int blk = wave + 4 * q;
+      if (blk >= NB) continue;
+      const int mb = blk / (CINP / 32), cb = blk % (CINP / 32);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int row = mb * 32 + 8 * (v / 4) + 4 * (lane >> 5) + (v % 4);
+        const int col = cb * 32 + (lane & 31);
+        partial[(((size_t)g * NTAP + tap0 + k) * COUT + row) * CINP + col] = acc[k][q][v];
+      }
     }
-  }
 }
 
 // grad[tap][co][j] += sum_g partial[g][tap][co][col] over the parameters of a
@@ -931,7 +974,9 @@ NNLayout nn_layout(int C, int P, int S, int Ms, int depth, const int32_t* dims, 
     wfb += align_up(sizeof(bf16) * NTAP * out_p[k] * in_p[k]);
     bpb += align_up(sizeof(float) * out_p[k]);
   }
-  l.wG = (int)std::min<int64_t>(2 * l.ntiles, 64);
+  // weight-gradient groups: 56 x 9 (dy, dz) workgroups fill the 256 compute units
+  // two deep (the 64 -> 64 kernel stages 68 KB of LDS: two workgroups per unit)
+  l.wG = (int)std::min<int64_t>(2 * l.ntiles, 56);
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += align_up(bytes); return o; };
   l.tubes = take(sizeof(NTube) * ntubes);
@@ -1002,7 +1047,7 @@ void wgrad(mclbm_nn* net, const bf16* dY, const bf16* X, int layer)
 {
   constexpr int CINP = CIN < 32 ? 32 : CIN;
   const int nchunks = (int)(2 * net->ntiles);
-  hipLaunchKernelGGL((k_wgrad<CIN, COUT>), dim3(net->wG, NTAP), dim3(256), 0, net->stream, net->dTubes,
+  hipLaunchKernelGGL((k_wgrad<CIN, COUT>), dim3(net->wG, NTAP / 3), dim3(256), 0, net->stream, net->dTubes,
                      net->dTileTube, net->ntubes, nchunks, dY, X, net->wpart);
   // only the real channels have parameters (the padded ones stay zero)
   const int co_r = net->out_r[layer], ci_r = net->in_r[layer];
