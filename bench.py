@@ -260,6 +260,9 @@ def surrogate_bench(train_iters: int = 24000):
                   "loss_last100": float(np.mean(losses[-100:])), "ms_per_step": ms_train_step,
                   "TFLOPs_per_step_approx": train_flops / (ms_train_step * 1e-3) / 1e12},
         "eval": res,
+        "hops_within_1e-3_linf": [{"t0": r["t0"], "X_linf": r["X_linf"],
+                                   "speedup_advance_vs_lattice": r["ms_lattice"] / r["ms_advance"]}
+                                  for r in res if r["X_linf"] <= 1e-3],
         "speedup_forward_vs_lattice": float(np.median([r["ms_lattice"] / r["ms_forward"] for r in res])),
         "speedup_advance_vs_lattice": float(np.median([r["ms_lattice"] / r["ms_advance"] for r in res])),
         "roofline_conv_forward": {"bound": "mfma", "achieved": achieved, "peak": BF16_PEAK_TFLOPS,
