@@ -117,6 +117,14 @@ int mclbm_nn_loss(mclbm_nn *net, const float *target, const float *channel_weigh
 int mclbm_nn_backward(mclbm_nn *net);
 int mclbm_nn_zero_grad(mclbm_nn *net);
 
+/* Global 2-norm of the accumulated gradients (FP64 sum of squares over all
+ * parameters), written to *norm (may be NULL). If max_norm > 0 and the norm exceeds
+ * it, every gradient is scaled by max_norm / norm (clipping by global norm, before
+ * the optimiser step); max_norm = 0 only measures. A non-finite norm is returned
+ * and nothing is scaled. MCLBM_EARG for a negative or NaN max_norm. Synchronises
+ * the stream. */
+int mclbm_nn_clip_grad_norm(mclbm_nn *net, double max_norm, double *norm);
+
 /* One Adam step (Kingma and Ba) on the accumulated gradients, then clears them. */
 int mclbm_nn_adam_step(mclbm_nn *net, float lr, float beta1, float beta2, float eps);
 

@@ -21,7 +21,8 @@ Plain numpy, written from the definitions, not from the GPU kernels:
   conservative form also the error of the fluxes through the x faces against
   those the target change implies on a walled tube with fields uniform in y and
   z, which fixes the uniform flux offset that the divergence cannot see;
-- Adam as published by Kingma and Ba (bias-corrected first and second moments);
+- Adam as published by Kingma and Ba (bias-corrected first and second moments),
+  optionally after clipping the gradient by its global Euclidean norm;
 - the mole residual: with R_U = 1 the molar density of species s is
   rho_s / m_s = p X_s / T, so a tube's moles are sum_x p X_s / T.
 
@@ -308,6 +309,17 @@ def loss_and_grad(params, tubes_f, tubes_target, norm, C, depth, width=64, weigh
             if k > 0:
                 d = rnd(conv_input_grad(d, rnd(W)) * (acts[k] > 0))
     return total / N, flatten(grads)
+
+
+def clip_grad_norm(grad, max_norm):
+    """Clipping by global norm: (grad scaled by max_norm / |grad| when |grad| >
+    max_norm > 0, else grad unchanged; |grad|), |.| the Euclidean norm over all
+    parameters."""
+    g = np.asarray(grad, dtype=np.float64)
+    norm = float(np.sqrt(np.sum(g * g)))
+    if max_norm > 0.0 and np.isfinite(norm) and norm > max_norm:
+        return g * (max_norm / norm), norm
+    return g.copy(), norm
 
 
 def adam(params, grad, m, v, step, lr, b1, b2, eps):

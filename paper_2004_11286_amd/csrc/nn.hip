@@ -840,6 +840,30 @@ __global__ void k_pack_b(const float* __restrict__ b, int OUT, int OUTP, float* 
   if (k < OUTP) bp[k] = k < OUT ? b[k] : 0.f;
 }
 
+// Sum of squares of g[0..n) in FP64, one partial per block (grid-stride, fixed order).
+__global__ __launch_bounds__(256) void k_sumsq(const float* __restrict__ g, int64_t n, double* __restrict__ partial)
+{
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const double v = g[i];
+    s += v * v;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void k_scale(float* __restrict__ g, int64_t n, float f)
+{
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) g[i] *= f;
+}
+
 __global__ void k_zero(float* __restrict__ p, int64_t n)
 {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1358,6 +1382,30 @@ extern "C" int mclbm_nn_backward(mclbm_nn* net)
   wgrad<CIN0, WIDTH>(net, net->dy[cur], net->act[0], 0);
   bgrad(net, net->dy[cur], WIDTH, 0);
   return nn_check(net, "mclbm_nn_backward");
+}
+
+extern "C" int mclbm_nn_clip_grad_norm(mclbm_nn* net, double max_norm, double* norm)
+{
+  if (!net) return MCLBM_EARG;
+  if (!(max_norm >= 0.0)) return nn_fail(net, MCLBM_EARG, "max_norm must be >= 0");
+  // partials in the loss buffer (ntiles * MAXC doubles, at least 16)
+  const unsigned nb = (unsigned)std::min<int64_t>(256, (int64_t)net->ntiles * MAXC);
+  hipLaunchKernelGGL(k_sumsq, dim3(nb), dim3(256), 0, net->stream, net->grad, net->nparam, net->dpart);
+  int rc = nn_check(net, "k_sumsq");
+  if (rc) return rc;
+  std::vector<double> part(nb);
+  NN_TRY(net, hipMemcpyAsync(part.data(), net->dpart, sizeof(double) * nb, hipMemcpyDeviceToHost, net->stream));
+  NN_TRY(net, hipStreamSynchronize(net->stream));
+  double s = 0.0;
+  for (double v : part) s += v;
+  const double nrm = std::sqrt(s);
+  if (norm) *norm = nrm;
+  if (max_norm > 0.0 && std::isfinite(nrm) && nrm > max_norm) {
+    hipLaunchKernelGGL(k_scale, dim3(blocks_for(net->nparam, 256)), dim3(256), 0, net->stream, net->grad, net->nparam,
+                       (float)(max_norm / nrm));
+    return nn_check(net, "k_scale");
+  }
+  return MCLBM_OK;
 }
 
 extern "C" int mclbm_nn_zero_grad(mclbm_nn* net)

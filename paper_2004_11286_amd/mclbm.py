@@ -46,7 +46,8 @@ EXPORTS = ["mclbm_workspace_bytes", "mclbm_batch_workspace_bytes", "mclbm_create
 NN_EXPORTS = ["mclbm_nn_workspace_bytes", "mclbm_nn_create", "mclbm_nn_destroy", "mclbm_nn_last_error",
               "mclbm_nn_param_count", "mclbm_nn_set_params", "mclbm_nn_get_params", "mclbm_nn_get_grads",
               "mclbm_nn_set_norm", "mclbm_nn_set_conditioning", "mclbm_nn_io", "mclbm_nn_forward", "mclbm_nn_loss", "mclbm_nn_backward",
-              "mclbm_nn_zero_grad", "mclbm_nn_adam_step", "mclbm_nn_mole_residual", "mclbm_nn_advance"]
+              "mclbm_nn_zero_grad", "mclbm_nn_clip_grad_norm", "mclbm_nn_adam_step", "mclbm_nn_mole_residual",
+              "mclbm_nn_advance"]
 
 
 class mclbm_params(C.Structure):
@@ -125,6 +126,7 @@ def _load():
     L.mclbm_nn_backward.argtypes = [vp]
     L.mclbm_nn_zero_grad.argtypes = [vp]
     L.mclbm_nn_adam_step.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float]
+    L.mclbm_nn_clip_grad_norm.argtypes = [vp, C.c_double, dp]
     L.mclbm_nn_mole_residual.argtypes = [vp, C.c_int32, vp, vp, dp]
     L.mclbm_nn_advance.argtypes = [vp, vp, C.c_int32, C.c_double, ip, dp]
     L.mclbm_destroy.argtypes = [vp]
@@ -627,6 +629,12 @@ def mclbm_nn_zero_grad(net) -> None:
     _nn_check(net, lib.mclbm_nn_zero_grad(net))
 
 
+def mclbm_nn_clip_grad_norm(net, max_norm: float) -> float:
+    out = C.c_double()
+    _nn_check(net, lib.mclbm_nn_clip_grad_norm(net, float(max_norm), C.byref(out)))
+    return out.value
+
+
 def mclbm_nn_adam_step(net, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8) -> None:
     _nn_check(net, lib.mclbm_nn_adam_step(net, float(lr), float(beta1), float(beta2), float(eps)))
 
@@ -726,6 +734,10 @@ class Net:
 
     def zero_grad(self):
         mclbm_nn_zero_grad(self.net)
+
+    def clip_grad_norm(self, max_norm: float = 0.0) -> float:
+        """Global gradient norm; gradients scaled down to max_norm when above it (> 0)."""
+        return mclbm_nn_clip_grad_norm(self.net, max_norm)
 
     def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
         mclbm_nn_adam_step(self.net, lr, beta1, beta2, eps)

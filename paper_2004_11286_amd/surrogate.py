@@ -161,20 +161,29 @@ def pair_weights(st: dict, M: int, floor_frac: float = 1e-2, flux_weight: float 
 
 
 def train(net, snaps, iters: int, weights, lr: float = LR, seed: int = 0, log_every: int = 0,
-          warmup: int = 500):
+          warmup: int = 500, clip: float = 0.0):
     """Adam on random (t, t + K) snapshot pairs of all tubes at once, with a
     linear learning-rate warm-up over the first `warmup` iterations and a cosine
-    decay after; weights: per-pair channel weights [nsnap][C]. Returns the loss
-    history."""
+    decay after; weights: per-pair channel weights [nsnap][C]. clip > 0 clips
+    the gradient by its global norm at clip times a running mean of the recent
+    (clipped) norms, so that a single outlying pair cannot throw the weights far.
+    Returns the loss history."""
     rng = np.random.default_rng(seed)
     losses = []
     nsnap = snaps.shape[0] - 1
+    norm_mean = None
     for it in range(iters):
         j = int(rng.integers(0, nsnap))
         net.fields_in.copy_(snaps[j])
         net.forward()
         losses.append(net.loss(snaps[j + 1], weights[j]))
         net.backward()
+        if clip > 0.0:
+            limit = 0.0 if norm_mean is None or it < 50 else clip * norm_mean
+            nrm = net.clip_grad_norm(limit)
+            if np.isfinite(nrm):
+                kept = min(nrm, limit) if limit > 0.0 else nrm
+                norm_mean = kept if norm_mean is None else 0.98 * norm_mean + 0.02 * kept
         lr_it = (lr * 0.5 * (1.0 + np.cos(np.pi * it / iters)) + 0.02 * lr) * min(1.0, (it + 1) / max(warmup, 1))
         net.adam_step(lr_it)
         if log_every and (it + 1) % log_every == 0:

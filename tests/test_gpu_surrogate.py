@@ -360,6 +360,35 @@ def test_conservative_gradients_match_oracle(env, wf):
             assert rel < 2e-2, (li, name, rel)
 
 
+def test_clip_grad_norm_matches_reference(env):
+    """The norm of the accumulated gradients and their clipping, against the
+    reference definition on the gradients read back before the call."""
+    mc, torch = env
+    depth = 3
+    p = S.he_init(C, depth, seed=41, species=3)
+    net, nm = cons_net(env, depth, p)
+    fs = [f.astype(np.float32).astype(np.float64) for f in cons_fields(42)]
+    rng = np.random.default_rng(43)
+    tg = [S.conservative_fields(f, rng.normal(size=(13,) + f.shape[1:]), nm["out_scale"], 3)[0] for f in fs]
+    net.zero_grad()
+    net.forward(flat(env, fs))
+    net.loss(flat(env, [t.astype(np.float32) for t in tg]), np.array([1e6] * 3 + [1e4, 1e5, 1e5, 1e5, 1e5], np.float32))
+    net.backward()
+    g0 = net.get_grads().astype(np.float64)
+    want, n_ref = S.clip_grad_norm(g0, 0.0)
+    n = net.clip_grad_norm(0.0)                          # measure only
+    assert n == pytest.approx(n_ref, rel=1e-6)
+    np.testing.assert_array_equal(net.get_grads(), g0.astype(np.float32))
+    want, _ = S.clip_grad_norm(g0, 0.25 * n_ref)
+    n2 = net.clip_grad_norm(0.25 * n_ref)
+    assert n2 == pytest.approx(n_ref, rel=1e-6)
+    got = net.get_grads().astype(np.float64)
+    assert np.abs(got - want).max() <= 1e-6 * np.abs(want).max()
+    with pytest.raises(mc.MclbmError):
+        net.clip_grad_norm(-1.0)
+    net.close()
+
+
 def test_network_arguments_are_checked(env):
     mc, torch = env
     net = mc.Net(C, 3, DIMS, species=3)

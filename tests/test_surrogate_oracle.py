@@ -323,3 +323,19 @@ def test_network_gradient_conservative_form():
         Lp, _ = S.loss_and_grad(pp, fs, tg, norm, C, depth, width, weight=w, species=M)
         Lm, _ = S.loss_and_grad(pm, fs, tg, norm, C, depth, width, weight=w, species=M)
         assert g[k] == pytest.approx((Lp - Lm) / (2 * h), rel=2e-5, abs=1e-10), k
+
+
+def test_clip_grad_norm_definition():
+    """Clipping by global norm: the clipped gradient has the limit as its norm and
+    the direction of the original; below the limit, or with limit 0, nothing
+    changes and the norm is reported."""
+    g = np.array([3.0, -4.0, 12.0])                      # norm 13
+    c, n = S.clip_grad_norm(g, 6.5)
+    assert n == 13.0
+    np.testing.assert_allclose(c, g / 2.0, rtol=1e-15)
+    assert np.sqrt(np.sum(c * c)) == pytest.approx(6.5, rel=1e-15)
+    c2, n2 = S.clip_grad_norm(g, 20.0)
+    np.testing.assert_array_equal(c2, g)
+    c3, n3 = S.clip_grad_norm(g, 0.0)
+    np.testing.assert_array_equal(c3, g)
+    assert n2 == n3 == 13.0
