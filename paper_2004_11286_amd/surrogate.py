@@ -51,6 +51,16 @@ def trajectories(tubes: list, K: int = K_DEFAULT, nsnap: int = 50, precision: in
     torch.cuda.synchronize()
     dims = [(s[2], s[1], s[0]) for s in b.shapes]
     b.close()
+    # a tube whose state left the lattice's stable range shows as non-finite fields
+    last = snaps[-1].cpu().numpy()
+    off, bad = 0, []
+    for t, (nx, ny, nz) in enumerate(dims):
+        n = nx * ny * nz
+        if not np.all(np.isfinite(last[C * off:C * (off + n)])):
+            bad.append(t)
+        off += n
+    if bad:
+        raise ValueError(f"tubes {bad} became non-finite within {K * nsnap} steps; leave them out of the ensemble")
     return snaps, dims
 
 
