@@ -144,14 +144,18 @@ def test_ternary_tube_16bit_storage(mc, ternary_1000, prec, bound):
         assert errs[k] < (5 * bound if k == "u" else bound), (k, errs[k])
 
 
-def test_full_size_shear_layer_windows(mc, oracle_mod):
-    """The 256^3 shear layer in the benchmark's configuration (FP32 storage): the
-    GPU state after 20 steps, cut into 9^3 periodic windows around sampled nodes,
-    advanced one step by the oracle, matches the GPU's step 21 at the window
-    centres (one step depends on neighbours up to distance 3). Conservation of
-    the masses and the energy holds at full size."""
+@pytest.mark.parametrize("prec, tol, ctol", [("fp32", 1e-6, 1e-6), ("fp16", 4e-3, 1e-4), ("bf16", 3e-2, 1e-3)])
+def test_full_size_shear_layer_windows(mc, oracle_mod, prec, tol, ctol):
+    """The 256^3 shear layer in the benchmark's configuration: the GPU state after
+    20 steps, cut into 9^3 periodic windows around sampled nodes, advanced one step
+    by the oracle, matches the GPU's step 21 at the window centres (one step
+    depends on neighbours up to distance 3). With 16-bit storage the stored result
+    of the step carries the stochastic rounding of the deviations, up to one unit
+    in the last place (2^-10 relative for FP16, 2^-7 for BF16), which sets the
+    bounds (measured: 1.7e-3 and 1.3e-2 at worst). Conservation of the masses and
+    the energy holds at full size (to the storage rounding)."""
     params, f = W.shear_layer()
-    s = mc.Sim(params, mc.MCLBM_FP32)
+    s = mc.Sim(params, mc.PRECISIONS[prec])
     s.init_fields(**f)
     c0 = s.conservation()
     s.step(20)
@@ -162,8 +166,10 @@ def test_full_size_shear_layer_windows(mc, oracle_mod):
     c1 = s.conservation()
     s.close()
     M = params["M"]
-    np.testing.assert_allclose(c1[:M + 1], c0[:M + 1], rtol=1e-6)
-    np.testing.assert_allclose(c1[M + 4], c0[M + 4], rtol=1e-6)
+    print(prec, "conservation drift", np.abs(c1[:M + 1] / c0[:M + 1] - 1).max(), abs(c1[M + 4] / c0[M + 4] - 1))
+    np.testing.assert_allclose(c1[:M + 1], c0[:M + 1], rtol=ctol)
+    np.testing.assert_allclose(c1[M + 4], c0[M + 4], rtol=ctol)
+    worst = {k: 0.0 for k in FIELDS}
     rng = np.random.default_rng(4)
     centers = [(0, 0, 0), (255, 64, 128), (17, 63, 200), (100, 192, 5), (200, 130, 255)]
     centers += [tuple(int(v) for v in rng.integers(0, 256, 3)) for _ in range(5)]
@@ -180,7 +186,9 @@ def test_full_size_shear_layer_windows(mc, oracle_mod):
             ov = om[k][..., r, r, r]
             gv = g[k][..., z, y, x]
             scale = max(np.abs(f[k]).max(), 1e-3) if k == "u" else np.abs(ov).max()
-            assert np.abs(gv - ov).max() <= 1e-6 * scale, (k, (x, y, z), gv, ov)
+            worst[k] = max(worst[k], float(np.abs(gv - ov).max() / scale))
+            assert np.abs(gv - ov).max() <= tol * scale, (k, (x, y, z), gv, ov)
+    print(prec, "worst window error", worst)
 
 
 def test_checkpoint_resume_is_bitwise(mc):
