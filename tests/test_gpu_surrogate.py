@@ -326,6 +326,42 @@ def test_conservative_forward_matches_oracle_and_keeps_moles(env):
             assert err <= 1e-2 * change + 1e-6 * np.abs(pred[lo:hi]).max(), (t, name, err, change)
 
 
+def test_full_size_forward_on_uniform_cross_sections(env):
+    """The benchmark's evaluation geometry (eight tubes of 128 x 32 x 32, 1 M nodes)
+    and network (depth 6, three second terms, six tube constants, conservative
+    output): with fields uniform in y and z, every (y, z) row of the GPU output is
+    the same, and matches the FP64 reference run on the tube's single row
+    (128 x 1 x 1), which the periodic wrap in y and z makes an exact stand-in."""
+    mc, torch = env
+    depth, Sn, ny, nz, nx = 6, 6, 32, 32, 128
+    dims = [(nx, ny, nz)] * 8
+    p = S.he_init(C, depth, seed=51, S=Sn, species=3)
+    p += np.random.default_rng(52).normal(0, 0.01, p.size).astype(np.float32)
+    cond = np.random.default_rng(53).uniform(-1, 1, (len(dims), Sn)).astype(np.float32)
+    nm = {"in_shift": np.array([0.33] * 3 + [0.33, 0, 0, 0, 0.025], np.float32),
+          "in_scale": np.array([3.0] * 3 + [30.0, 300, 300, 300, 100], np.float32), "out_scale": CONS_SCALE}
+    net = mc.Net(C, depth, dims, conditioning=Sn, two_term=3, species=3)
+    net.set_conditioning(cond)
+    net.set_norm(nm["in_shift"], nm["in_scale"], nm["out_scale"])
+    net.set_params(p)
+    rows = [r.astype(np.float32).astype(np.float64) for r in cons_fields(54, dims=[(nx, 1, 1)] * len(dims))]
+    full = [np.broadcast_to(r, (C, nz, ny, nx)) for r in rows]
+    out = net.forward(flat(env, full)).cpu().numpy()
+    net.close()
+    nm64 = {k: np.asarray(v, np.float32).astype(np.float64) for k, v in nm.items()}
+    n = nx * ny * nz
+    for t, r in enumerate(rows):
+        g = out[C * t * n:C * (t + 1) * n].reshape(C, nz, ny, nx)
+        spread = np.abs(g - g[:, :1, :1, :]).max()
+        print("full size tube", t, "largest difference between rows", spread)
+        assert spread <= 1e-6 * np.abs(g).max()
+        _, pred, _ = S.forward(p, r, nm64, C, depth, round_bf16=True, cond=cond[t].astype(np.float64), P=3, species=3)
+        for lo, hi, name in ((0, 3, "X"), (3, 4, "T"), (4, 7, "u"), (7, 8, "p")):
+            change = np.abs(pred[lo:hi] - r[lo:hi]).max()
+            err = np.abs(g[lo:hi, 0, 0, :] - pred[lo:hi, 0, 0, :]).max()
+            assert err <= 1e-2 * change + 1e-6 * np.abs(pred[lo:hi]).max(), (t, name, err, change)
+
+
 @pytest.mark.parametrize("wf", [0.0, 1e5])
 def test_conservative_gradients_match_oracle(env, wf):
     """Loss and gradients of the conservative form, without and with the x-flux term."""
