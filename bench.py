@@ -208,7 +208,7 @@ def ensemble_bench(mc, steps: int = 50, seq_steps: int = 10, trial_steps: int = 
 BF16_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix-core peak
 
 
-def surrogate_bench(train_iters: int = 24000):
+def surrogate_bench(train_iters: int = 36000):
     """The learned surrogate: trained by the library's BF16 MFMA kernels on
     trajectories of a 2048-tube ensemble (every 100 steps up to 5000; the tubes
     are one-dimensional, uniform in y and z, so a one-node cross-section carries
@@ -233,7 +233,7 @@ def surrogate_bench(train_iters: int = 24000):
     net = SG.build_net(dims, [p for p, _ in train_tubes], norm, M)
     ms_train_step, _ = SG.timed_train_step(net, snaps, pw)
     net.set_params(SG.he_init(C, 6, SG.DEPTH, 0, 3 * M + 4))
-    losses = SG.train(net, snaps, train_iters, pw)
+    losses = SG.train(net, snaps, train_iters, pw, lr=2e-4, clip=2.0)
     params = net.get_params()
     n_train = sum(a * b * c for a, b, c in dims)
     net.close()
@@ -256,7 +256,7 @@ def surrogate_bench(train_iters: int = 24000):
                     "padding": "replicate at the x walls, periodic in y and z",
                     "loss": "molar densities, T, u, and the x fluxes the target change implies (weight 0.1)",
                     "dtype": "bf16 weights/activations, fp32 accumulate"},
-        "train": {"iters": train_iters, "seconds": train_s, "loss_first100": float(np.mean(losses[:100])),
+        "train": {"iters": train_iters, "lr": 2e-4, "clip_times_mean_norm": 2.0, "seconds": train_s, "loss_first100": float(np.mean(losses[:100])),
                   "loss_last100": float(np.mean(losses[-100:])), "ms_per_step": ms_train_step,
                   "TFLOPs_per_step_approx": train_flops / (ms_train_step * 1e-3) / 1e12},
         "eval": res,
@@ -282,7 +282,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
-    ap.add_argument("--surrogate-iters", type=int, default=24000)
+    ap.add_argument("--surrogate-iters", type=int, default=36000)
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes five times (to scale HBM counters)")
     args = ap.parse_args()
