@@ -185,6 +185,14 @@ int mclbm_set_launch(mclbm_ctx *c, const mclbm_launch *in);
  * 2 trial_steps. Synchronises the stream. */
 int mclbm_autotune(mclbm_ctx *c, int32_t trial_steps, char *report, size_t report_len);
 
+/* Moles of every species in each x half of every tube, FP64 (the diagnostic of
+ * the Loschmidt tube, Sec. 4.2: half-tube mean mole fractions are the ratios of
+ * these): out[t][h][a] = sum over the nodes of tube t with x < nx / 2 (h = 0) or
+ * x >= nx / 2 (h = 1) of rho_a / m_a (R_U = 1, the slaved species' density from
+ * the deficit of eq rhoMATCH). out: host [ntubes][2][M]. Synchronises the stream.
+ * MCLBM_EARG before the first initialisation. */
+int mclbm_half_tube_moles(mclbm_ctx *c, double *out);
+
 /* Streaming copy of `bytes` bytes (a multiple of 16; both pointers 16-byte
  * aligned device memory, not overlapping) from src to dst, ordered on hip_stream
  * (NULL: the default stream): 16-byte nontemporal loads and stores, the access

@@ -179,6 +179,21 @@ __global__ __launch_bounds__(RED_BLOCK) void k_conserved(const Params<double>* _
   block_sum<NV>(v, partial, w.block);
 }
 
+// Moles of every species in each x half of every tube (block partials [2 M]).
+template <typename S, int M>
+__global__ __launch_bounds__(RED_BLOCK) void k_half_moles(const Params<double>* __restrict__ P, Launch Ln,
+                                                          const S* __restrict__ pop, double* __restrict__ partial)
+{
+  constexpr int NV = 2 * M;
+  double v[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = 0.0;
+  const Where w = locate(Ln);
+  const Params<double>& Pt = P[w.t];
+  if (w.node < Pt.n) half_moles_node<S, M>(Pt, pop + pop_stride<M>() * w.base, w.node, v);
+  block_sum<NV>(v, partial, w.block);
+}
+
 // Sums of the initial fields (X_a, p, T) per tube, for the reference states
 // (the parameter blocks are not filled yet: tube sizes come from tube_n).
 template <int M>
@@ -240,6 +255,8 @@ struct Ops {
                double* T, unsigned grid, hipStream_t st);
   void (*conserved)(const void* Pd, const Launch& ln, const void* pop, double* partial, unsigned grid,
                     hipStream_t st);
+  void (*half_moles)(const void* Pd, const Launch& ln, const void* pop, double* partial, unsigned grid,
+                     hipStream_t st);
   void (*init)(const void* Pd, const Launch& ln, const double* X, const double* p, const double* T,
                const double* u, void* pop, int* bad, unsigned grid, hipStream_t st);
   void (*field_sums)(const int64_t* tube_n, const Launch& ln, const double* X, const double* p, const double* T,
@@ -287,6 +304,11 @@ Ops make_ops()
   o.conserved = [](const void* Pd, const Launch& ln, const void* pop, double* partial, unsigned grid,
                    hipStream_t st) {
     hipLaunchKernelGGL((k_conserved<S, M>), dim3(grid), dim3(RED_BLOCK), 0, st, (const Params<double>*)Pd, ln,
+                       (const S*)pop, partial);
+  };
+  o.half_moles = [](const void* Pd, const Launch& ln, const void* pop, double* partial, unsigned grid,
+                     hipStream_t st) {
+    hipLaunchKernelGGL((k_half_moles<S, M>), dim3(grid), dim3(RED_BLOCK), 0, st, (const Params<double>*)Pd, ln,
                        (const S*)pop, partial);
   };
   o.init = [](const void* Pd, const Launch& ln, const double* X, const double* p, const double* T,

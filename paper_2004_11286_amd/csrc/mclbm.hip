@@ -942,6 +942,17 @@ extern "C" int mclbm_conservation(mclbm_ctx* c, double* out)
   return MCLBM_OK;
 }
 
+extern "C" int mclbm_half_tube_moles(mclbm_ctx* c, double* out)
+{
+  if (!c || !out) return c ? fail(c, MCLBM_EARG, "out is NULL") : MCLBM_EARG;
+  if (!c->initialised) return fail(c, MCLBM_EARG, "no state yet");
+  const int nv = 2 * c->M;
+  c->ops.half_moles(c->dPd, launch_all(c), c->pop[c->cur], c->partial, (unsigned)c->nblocks, c->stream);
+  int rc = check_launch(c, "k_half_moles");
+  if (rc) return rc;
+  return reduce_to_host(c, nv, out);
+}
+
 extern "C" int64_t mclbm_step_count(const mclbm_ctx* c) { return c ? c->steps : -1; }
 
 namespace {

@@ -917,4 +917,36 @@ __host__ __device__ __forceinline__ void conserved_node(const Params<double>& P,
   out[M + 5] = ok ? 0.0 : 1.0;
 }
 
+// Moles of every species at a node, rho_a / m_a (R_U = 1; the slaved species from
+// the deficit, eq rhoMATCH), in slot [h][a] of out[2 M], h = 0 for x < nx / 2 and
+// h = 1 otherwise (the other half's slots zero): summed over a tube, the moles in
+// each half of a Loschmidt tube, whose ratios are the half-tube mean mole
+// fractions of Sec. 4.2.
+template <typename S, int M>
+__host__ __device__ __forceinline__ void half_moles_node(const Params<double>& P, const S* __restrict__ pop,
+                                                int64_t node, double* out /*[2 M]*/)
+{
+  const size_t n = (size_t)P.n;
+  constexpr int LF = M - 1;
+  double rho_a[M], rest = 0.0;
+#pragma unroll
+  for (int a = 0; a < M - 1; ++a) {
+    double sum = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) sum += (double)pop[(size_t)(a * Q + i) * n + node] * P.inv_scale[a];
+    rho_a[a] = P.ref0[a] + sum;
+    rest += rho_a[a];
+  }
+  double rho = 0.0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) rho += (double)pop[(size_t)(LF * Q + i) * n + node] * P.inv_scale[LF];
+  rho_a[M - 1] = rho + P.ref0[LF] - rest;
+  const int h = (int)(node % P.nx) >= P.nx / 2 ? 1 : 0;
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    out[h * M + a] = rho_a[a] * P.inv_m[a];
+    out[(1 - h) * M + a] = 0.0;
+  }
+}
+
 }  // namespace mclbm

@@ -42,7 +42,7 @@ EXPORTS = ["mclbm_workspace_bytes", "mclbm_batch_workspace_bytes", "mclbm_create
            "mclbm_init_fields", "mclbm_step", "mclbm_read_moments", "mclbm_read_fields_f32",
            "mclbm_conservation", "mclbm_step_count", "mclbm_state_bytes", "mclbm_save", "mclbm_load",
            "mclbm_set_timing", "mclbm_kernel_stats", "mclbm_get_launch", "mclbm_set_launch",
-           "mclbm_autotune", "mclbm_stream_copy"]
+           "mclbm_autotune", "mclbm_stream_copy", "mclbm_half_tube_moles"]
 NN_EXPORTS = ["mclbm_nn_workspace_bytes", "mclbm_nn_create", "mclbm_nn_destroy", "mclbm_nn_last_error",
               "mclbm_nn_param_count", "mclbm_nn_set_params", "mclbm_nn_get_params", "mclbm_nn_get_grads",
               "mclbm_nn_set_norm", "mclbm_nn_set_conditioning", "mclbm_nn_io", "mclbm_nn_forward", "mclbm_nn_loss", "mclbm_nn_backward",
@@ -146,6 +146,7 @@ def _load():
     L.mclbm_set_timing.argtypes = [vp, C.c_int]
     L.mclbm_kernel_stats.argtypes = [vp, C.c_int32, dp, C.POINTER(C.c_int64), C.POINTER(C.c_char_p)]
     L.mclbm_stream_copy.argtypes = [vp, vp, C.c_size_t, vp]
+    L.mclbm_half_tube_moles.argtypes = [vp, dp]
     return L
 
 
@@ -292,6 +293,13 @@ def mclbm_conservation(ctx, M: int) -> np.ndarray:
     return out
 
 
+def mclbm_half_tube_moles(ctx, M: int) -> np.ndarray:
+    """Per-tube moles of every species in each x half, shape [ntubes][2][M]."""
+    out = np.zeros((mclbm_tube_count(ctx), 2, M))
+    _check(ctx, lib.mclbm_half_tube_moles(ctx, out.ctypes.data_as(C.POINTER(C.c_double))))
+    return out
+
+
 def mclbm_step_count(ctx) -> int:
     return int(lib.mclbm_step_count(ctx))
 
@@ -393,6 +401,10 @@ class Sim:
 
     def conservation(self) -> np.ndarray:
         return mclbm_conservation(self.ctx, self.M)[0]
+
+    def half_tube_moles(self) -> np.ndarray:
+        """[2][M]: moles of every species in the x < nx/2 and x >= nx/2 halves."""
+        return mclbm_half_tube_moles(self.ctx, self.M)[0]
 
     @property
     def step_count(self) -> int:
@@ -500,6 +512,10 @@ class Batch:
 
     def conservation(self) -> np.ndarray:
         return mclbm_conservation(self.ctx, self.M)
+
+    def half_tube_moles(self) -> np.ndarray:
+        """[ntubes][2][M]: moles of every species in each x half of every tube."""
+        return mclbm_half_tube_moles(self.ctx, self.M)
 
     @property
     def step_count(self) -> int:

@@ -191,6 +191,34 @@ def test_full_size_shear_layer_windows(mc, oracle_mod, prec, tol, ctol):
     print(prec, "worst window error", worst)
 
 
+@pytest.mark.parametrize("prec, tol", [("fp64", 1e-12), ("fp32", 1e-6)])
+def test_half_tube_moles(mc, oracle_mod, prec, tol):
+    """The diagnostic of the Loschmidt tube (Sec. 4.2): moles of every species in
+    each x half of a walled ternary tube after 200 steps, against the oracle's
+    fields (molar density p X_a / T with R_U = 1, summed over the half); their sum
+    over both halves keeps its initial value (species mass), while moles cross
+    the middle."""
+    params, f = W.ternary_tube(nx=64, ny=2, nz=2)
+    assert params["wall_x"] == 1
+    s = mc.Sim(params, mc.PRECISIONS[prec])
+    s.init_fields(**f)
+    h0 = s.half_tube_moles()
+    s.step(200)
+    h1 = s.half_tube_moles()
+    s.close()
+    o = oracle_mod.OracleSim(params)
+    o.init_fields(**f)
+    o.step(200)
+    m = o.read_moments()
+    n_a = m["p"][None] * m["X"] / m["T"][None]
+    half = params["nx"] // 2
+    want = np.stack([n_a[..., :half].sum(axis=(1, 2, 3)), n_a[..., half:].sum(axis=(1, 2, 3))])
+    print(prec, "half-tube moles", h1.tolist(), "oracle", want.tolist())
+    assert np.abs(h1 - want).max() <= tol * np.abs(want).max()
+    np.testing.assert_allclose(h1.sum(axis=0), h0.sum(axis=0), rtol=tol)
+    assert np.abs(h1 - h0).max() > 1e3 * tol * np.abs(h0).max()
+
+
 def test_checkpoint_resume_is_bitwise(mc):
     params, f = W.ternary_tube(nx=64)
     s = mc.Sim(params, mc.MCLBM_FP32)
