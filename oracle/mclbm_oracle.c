@@ -9,8 +9,10 @@
  *
  * One time step, in the paper's order:
  *   1. moments of every lattice; strong coupling slaves species M to the
- *      momentum lattice (Sec. 3.6.2, eqs rhoMATCH, uMATCH); temperature from
- *      the energy lattice with constant specific heats (eq temperature2, T_0=0);
+ *      momentum lattice (Sec. 3.6.2, eqs rhoMATCH, uMATCH); weak coupling
+ *      (Sec. 3.6.1) evolves every species lattice with its own conservation law;
+ *      temperature from the energy lattice with constant specific heats
+ *      (eq temperature2, T_0=0);
  *   2. mixture viscosity (Wilke, eq viscosityMixture) and conductivity (Mathur,
  *      eq conductivityMixture), relaxation rates omega, omega_1 (eqs omega, omega1);
  *   3. the non-local terms at the same time level: the isotropy correction X
@@ -36,7 +38,12 @@
  *     nodes; the x component of the momentum-like field Phi changes sign;
  *   - a species with rho_a == 0 exactly has an identically zero row in
  *     eq transform12; its diffusion velocity is set to zero;
- *   - initial populations are the local equilibria of the given fields.
+ *   - initial populations are the local equilibria of the given fields;
+ *   - weak coupling: the species see the species-barycentric velocity
+ *     u_s = sum_a j_a / sum_a rho_a (in J_a = j_a - rho_a u_s of eq transform12
+ *     and in the species equilibria), and the composition is Y_a = rho_a /
+ *     sum_b rho_b; the mixture density, velocity, temperature and pressure come
+ *     from the momentum and energy lattices as under strong coupling.
  *
  * Pins (tests run on the CPU): moment identities of the equilibria and of the
  * energy ansatz, the correction vectors, the derivative operator's symbol,
@@ -164,7 +171,7 @@ void oracle_gansatz(double theta, double M0, const double m[3], const double Mt[
 /* Simulation state                                                           */
 /* ------------------------------------------------------------------------- */
 struct oracle_sim {
-  int M, nx, ny, nz, wall_x, keep_slaved, flags;
+  int M, nx, ny, nz, wall_x, keep_slaved, weak, flags;
   long n;
   double m[MAXM], cv[MAXM], D[MAXM][MAXM], mu[MAXM], lam[MAXM];
   double *pop;   /* [(M+2)][Q][n] pre-collision populations */
@@ -221,7 +228,8 @@ int oracle_create(const oracle_params *p, oracle_sim **out)
   s->M = p->M;
   s->nx = p->nx; s->ny = p->ny; s->nz = p->nz;
   s->wall_x = p->wall_x ? 1 : 0;
-  s->keep_slaved = p->keep_slaved ? 1 : 0;
+  s->weak = p->weak ? 1 : 0;
+  s->keep_slaved = (p->keep_slaved || s->weak) ? 1 : 0;   /* weak coupling evolves every species */
   s->flags = p->debug_flags;
   s->n = (long)p->nx * p->ny * p->nz;
   for (int a = 0; a < s->M; ++a) {
@@ -273,7 +281,7 @@ void oracle_destroy(oracle_sim *s)
 typedef struct {
   double rho_a[MAXM], j_a[MAXM][3];
   double rho, j[3], rhoE;
-  double u[3], Y[MAXM], X[MAXM], mmix, R, Cv, Cp, T, P;
+  double u[3], us[3], Y[MAXM], X[MAXM], mmix, R, Cv, Cp, T, P, Ps;
   double Ha[MAXM], H;
   double mu, lam, omega, omega1;
 } state_t;
@@ -296,25 +304,43 @@ static void node_state(const oracle_sim *s, const double *pop, long node, state_
     for (int a = 0; a < 3; ++a) st->j[a] += fi * cvel(i, a);
     st->rhoE += POP(s, pop, LAT_G(s), i, node);
   }
-  /* species 1..M-1: eqs densitya, auxua */
-  for (int a = 0; a < M - 1; ++a)
+  /* species 1..M-1 (all M under weak coupling): eqs densitya, auxua */
+  const int nown = s->weak ? M : M - 1;
+  for (int a = 0; a < nown; ++a)
     for (int i = 0; i < Q; ++i) {
       double fai = POP(s, pop, a, i, node);
       st->rho_a[a] += fai;
       for (int k = 0; k < 3; ++k) st->j_a[a][k] += fai * cvel(i, k);
     }
-  /* strong coupling: the slaved species takes the deficits, eqs rhoMATCH, uMATCH */
-  st->rho_a[M - 1] = st->rho;
-  for (int k = 0; k < 3; ++k) st->j_a[M - 1][k] = st->j[k];
-  for (int a = 0; a < M - 1; ++a) {
-    st->rho_a[M - 1] -= st->rho_a[a];
-    for (int k = 0; k < 3; ++k) st->j_a[M - 1][k] -= st->j_a[a][k];
+  if (!s->weak) {
+    /* strong coupling: the slaved species takes the deficits, eqs rhoMATCH, uMATCH */
+    st->rho_a[M - 1] = st->rho;
+    for (int k = 0; k < 3; ++k) st->j_a[M - 1][k] = st->j[k];
+    for (int a = 0; a < M - 1; ++a) {
+      st->rho_a[M - 1] -= st->rho_a[a];
+      for (int k = 0; k < 3; ++k) st->j_a[M - 1][k] -= st->j_a[a][k];
+    }
   }
   for (int k = 0; k < 3; ++k) st->u[k] = st->j[k] / st->rho;
+  /* the species' own density: rho under strong coupling, sum_a rho_a under weak */
+  double rho_sp = st->rho;
+  if (s->weak) {
+    rho_sp = 0.0;
+    for (int a = 0; a < M; ++a) rho_sp += st->rho_a[a];
+  }
+  /* velocity the species relax towards: u, or the species-barycentric one */
+  for (int k = 0; k < 3; ++k) {
+    st->us[k] = st->u[k];
+    if (s->weak && !(s->flags & ORACLE_WEAK_MIXTURE_U)) {
+      double js = 0.0;
+      for (int a = 0; a < M; ++a) js += st->j_a[a][k];
+      st->us[k] = js / rho_sp;
+    }
+  }
   /* composition, Sec. 2.1 */
   double inv_m = 0.0;
   for (int a = 0; a < M; ++a) {
-    st->Y[a] = st->rho_a[a] / st->rho;
+    st->Y[a] = st->rho_a[a] / rho_sp;
     inv_m += st->Y[a] / s->m[a];
   }
   st->mmix = 1.0 / inv_m;
@@ -328,6 +354,9 @@ static void node_state(const oracle_sim *s, const double *pop, long node, state_
   double usq = st->u[0] * st->u[0] + st->u[1] * st->u[1] + st->u[2] * st->u[2];
   st->T = (st->rhoE / st->rho - usq / 2.0) / st->Cv;     /* eq temperature2, T_0 = 0 */
   st->P = st->rho * st->R * st->T;                       /* eq eosIdealGas */
+  /* pressure of the species subsystem in its friction terms: P under strong
+   * coupling, sum_a rho_a R_a T of the species' own densities under weak */
+  st->Ps = (s->weak && !(s->flags & ORACLE_WEAK_MIXTURE_P)) ? rho_sp * st->R * st->T : st->P;
   for (int a = 0; a < M; ++a) {
     st->Ha[a] = (s->cv[a] + 1.0 / s->m[a]) * st->T;      /* eq specHa */
     st->H += st->Y[a] * st->Ha[a];                       /* eq specH */
@@ -483,10 +512,11 @@ static void compute_nonlocal(oracle_sim *s)
 /* ------------------------------------------------------------------------- */
 /* Diffusion velocities, eq transform12                                       */
 /* ------------------------------------------------------------------------- */
-/* Solve rho_a V_a - 1/2 sum_b K_ab (V_b - V_a) = j_a - rho_a u for the three
- * components, by Gaussian elimination with partial pivoting on the species
- * present (rho_a != 0). An absent species has an identically zero row and
- * column; its V_a is set to zero. */
+/* Solve rho_a V_a - 1/2 sum_b K_ab (V_b - V_a) = j_a - rho_a u_s for the three
+ * components, u_s being the velocity the species relax towards (the mixture
+ * velocity under strong coupling), by Gaussian elimination with partial
+ * pivoting on the species present (rho_a != 0). An absent species has an
+ * identically zero row and column; its V_a is set to zero. */
 static void diffusion_velocities(int M, const state_t *st, double K[MAXM][MAXM],
                                  double V[MAXM][3])
 {
@@ -505,7 +535,7 @@ static void diffusion_velocities(int M, const state_t *st, double K[MAXM][MAXM],
       A[r][c] -= 0.5 * K[a][b];   /* - 1/2 K_ab V_b */
       A[r][r] += 0.5 * K[a][b];   /* + 1/2 K_ab V_a */
     }
-    for (int k = 0; k < 3; ++k) rhs[r][k] = st->j_a[a][k] - st->rho_a[a] * st->u[k];
+    for (int k = 0; k < 3; ++k) rhs[r][k] = st->j_a[a][k] - st->rho_a[a] * st->us[k];
   }
   for (int col = 0; col < np; ++col) {
     int piv = col;
@@ -543,7 +573,7 @@ static void species_rates(const oracle_sim *s, const state_t *st, double inv_tau
     for (int b = 0; b < M; ++b) {
       inv_tau[a][b] = (st->T / s->D[a][b]) * (st->mmix / (s->m[a] * s->m[b]));
       inv_tau_a += st->Y[b] * inv_tau[a][b];             /* eq tau */
-      K[a][b] = st->P * st->X[a] * st->X[b] / s->D[a][b];
+      K[a][b] = st->Ps * st->X[a] * st->X[b] / s->D[a][b];
     }
     double tau_a = 1.0 / inv_tau_a;
     beta[a] = 1.0 / (2.0 * tau_a + 1.0);
@@ -568,9 +598,9 @@ static int collide_node(oracle_sim *s, long node)
   double feq[MAXM][Q], fstar[MAXM][Q];
   for (int b = 0; b < M; ++b) {
     double RbT = st.T / s->m[b];
-    double ub[3] = {st.u[0] + V[b][0], st.u[1] + V[b][1], st.u[2] + V[b][2]};
+    double ub[3] = {st.us[0] + V[b][0], st.us[1] + V[b][1], st.us[2] + V[b][2]};
     double psi_eq[Q], psi_st[Q];
-    oracle_psi(st.u, RbT, psi_eq);                          /* eq 27eq  */
+    oracle_psi(st.us, RbT, psi_eq);                         /* eq 27eq  */
     oracle_psi(ub, RbT, psi_st);                            /* eq 27qeq */
     for (int i = 0; i < Q; ++i) {
       feq[b][i] = st.rho_a[b] * psi_eq[i];

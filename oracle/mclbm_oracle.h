@@ -30,7 +30,9 @@ enum {
   ORACLE_DROP_QCORR = 2,      /* omit the correction flux (eq corrFourier)               */
   ORACLE_DROP_XCORR = 4,      /* omit the A_i . X isotropy correction (eq fwithcorrection) */
   ORACLE_DROP_UPNEQ = 8,      /* omit -u.(P - P^eq) in the quasi-equilibrium flux         */
-  ORACLE_DROP_FSOURCE = 16    /* omit the (beta_a - 1) F_ai term (eq SMlbm)               */
+  ORACLE_DROP_FSOURCE = 16,   /* omit the (beta_a - 1) F_ai term (eq SMlbm)               */
+  ORACLE_WEAK_MIXTURE_U = 32, /* weak coupling: species relax towards the momentum lattice's u */
+  ORACLE_WEAK_MIXTURE_P = 64  /* weak coupling: friction K_ab with the momentum lattice's P  */
 };
 
 typedef struct {
@@ -39,7 +41,8 @@ typedef struct {
   int32_t wall_x;       /* 0 periodic in x; 1 half-way bounce-back walls at both x ends */
   int32_t keep_slaved;  /* 1: store and evolve the slaved species' lattice literally    */
   int32_t debug_flags;  /* ORACLE_DROP_* planted mistakes (tests only), else 0          */
-  int32_t reserved;
+  int32_t weak;         /* 1: weak coupling (Sec. 3.6.1): all M species lattices evolve
+                           with their own conservation laws (implies keep_slaved)     */
   const double *molar_mass; /* [M] molar masses m_a                                     */
   const double *cv;         /* [M] mass-based constant specific heats C_{a,v}           */
   const double *D;          /* [M*M] symmetric binary diffusivities, diagonal included  */

@@ -25,13 +25,15 @@ DROP_QCORR = 2
 DROP_XCORR = 4
 DROP_UPNEQ = 8
 DROP_FSOURCE = 16
+WEAK_MIXTURE_U = 32
+WEAK_MIXTURE_P = 64
 
 
 class _Params(C.Structure):
     _fields_ = [
         ("M", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
         ("wall_x", C.c_int32), ("keep_slaved", C.c_int32), ("debug_flags", C.c_int32),
-        ("reserved", C.c_int32),
+        ("weak", C.c_int32),
         ("molar_mass", C.POINTER(C.c_double)), ("cv", C.POINTER(C.c_double)),
         ("D", C.POINTER(C.c_double)), ("mu", C.POINTER(C.c_double)),
         ("lam", C.POINTER(C.c_double)),
@@ -173,7 +175,7 @@ class OracleSim:
                         _f64(params["D"]).reshape(-1), _f64(params["mu"]),
                         _f64(params["lambda"])]
         p = _Params(self.M, self.nx, self.ny, self.nz, int(params.get("wall_x", 0)),
-                    int(keep_slaved), int(debug_flags), 0,
+                    int(keep_slaved), int(debug_flags), int(params.get("weak", 0)),
                     *[_dp(a) for a in self._arrays])
         h = C.c_void_p()
         rc = lib().oracle_create(C.byref(p), C.byref(h))
