@@ -71,7 +71,14 @@ typedef struct {
   int32_t wall_x;      /* 0: periodic in x; 1: half-way bounce-back walls at both x ends
                           (Sec. 4.2); y and z are always periodic                      */
   int32_t precision;   /* MCLBM_FP64 .. MCLBM_BF16                                    */
-  int32_t reserved0, reserved1;   /* must be 0                                        */
+  int32_t weak;        /* 0: strong coupling (Sec. 3.6.2): species M is slaved to the
+                          momentum lattice (eqs rhoMATCH, uMATCH) and not stored.
+                          1: weak coupling (Sec. 3.6.1): all M species lattices are
+                          stored and evolved; the species keep their own density and
+                          velocity (eqs rhoSPEC, uSPEC) and Dalton pressure, and take
+                          T from the energy lattice. MCLBM_FP64 and MCLBM_FP32 only
+                          (else MCLBM_EUNSUPPORTED); all tubes of a batch agree     */
+  int32_t reserved1;   /* must be 0                                                  */
   const double *molar_mass;  /* [M] molar masses m_a > 0                              */
   const double *cv;          /* [M] mass-based specific heats C_{a,v} > 0             */
   const double *D;           /* [M*M] symmetric binary diffusivities D_ab > 0, row major,

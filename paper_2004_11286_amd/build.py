@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmclbm.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["mclbm.hip", "nn.hip", "inst_fp64.hip", "inst_fp32_fp64.hip", "inst_fp32.hip", "inst_fp16.hip",
+SOURCES = ["mclbm.hip", "nn.hip", "inst_fp64.hip", "inst_fp32_fp64.hip", "inst_weak.hip", "inst_fp32.hip", "inst_fp16.hip",
            "inst_bf16.hip"]
 
 ARCH = os.environ.get("MCLBM_OFFLOAD_ARCH", "gfx950")

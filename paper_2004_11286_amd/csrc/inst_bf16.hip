@@ -2,5 +2,9 @@
 #include "kernels.hpp"
 
 namespace mclbm {
-bool pick_bf16(int M, int walls, kern::Ops& o) { return kern::pick_m<__bf16, float, float>(M, walls, o); }
+// weak coupling is compiled for FP64 arithmetic only
+bool pick_bf16(int M, int walls, int weak, kern::Ops& o)
+{
+  return !weak && kern::pick_m<__bf16, float, float, false>(M, walls, o);
+}
 }  // namespace mclbm

@@ -2,5 +2,10 @@
 #include "kernels.hpp"
 
 namespace mclbm {
-bool pick_fp64(int M, int walls, kern::Ops& o) { return kern::pick_m<double, double, double>(M, walls, o); }
+bool pick_fp64_weak(int M, int walls, kern::Ops& o);   // inst_weak.hip
+
+bool pick_fp64(int M, int walls, int weak, kern::Ops& o)
+{
+  return weak ? pick_fp64_weak(M, walls, o) : kern::pick_m<double, double, double, false>(M, walls, o);
+}
 }  // namespace mclbm

@@ -1,0 +1,12 @@
+// inst_weak.hip -- weak coupling (all M species lattices stored): double storage
+// and arithmetic with a double record, and float storage with double arithmetic
+// and a float record.
+#include "kernels.hpp"
+
+namespace mclbm {
+bool pick_fp64_weak(int M, int walls, kern::Ops& o) { return kern::pick_m<double, double, double, true>(M, walls, o); }
+bool pick_fp32_fp64_weak(int M, int walls, kern::Ops& o)
+{
+  return kern::pick_m<float, double, float, true>(M, walls, o);
+}
+}  // namespace mclbm

@@ -86,17 +86,18 @@ constexpr int collide_waves() { return ((M == 2 && sizeof(S) < 8) ? 2 : 1) == 2 
 template <int M, int V>
 constexpr int moment_waves() { return (M == 2 ? 2 : 1) == 2 ? 2 - V : 1 + V; }
 
-template <int M>
-constexpr size_t pop_stride() { return (size_t)(M + 1) * Q; }   // populations per node (stored lattices)
+template <int M, bool WEAK>
+constexpr size_t pop_stride() { return (size_t)Lat<M, WEAK>::L * Q; }   // populations per node (stored lattices)
 
-template <typename S, typename Rec, int M, int V>
+template <typename S, typename Rec, int M, int V, bool WEAK>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(moment_waves<M, V>()))) void k_moments(const Params<double>* __restrict__ P, Launch Ln, const S* __restrict__ pop,
                                                    Rec* __restrict__ rec)
 {
   const Where w = locate(Ln);
   const Params<double>& Pt = P[w.t];
   if (w.node < Pt.n)
-    state_node<S, Rec, M>(Pt, pop + pop_stride<M>() * w.base, rec + (size_t)RecLayout<M>::FIELDS * w.base, w.node);
+    state_node<S, Rec, M, WEAK>(Pt, pop + pop_stride<M, WEAK>() * w.base,
+                                rec + (size_t)RecLayout<M, WEAK>::FIELDS * w.base, w.node);
 }
 
 template <typename Rec, bool W>
@@ -113,7 +114,7 @@ __global__ __launch_bounds__(BLOCK) void k_gfield(const Params<double>* __restri
 template <typename S, int M, int V, int PART>
 constexpr int collide_part_waves() { return PART == 0 ? collide_waves<S, M, V>() : 2; }
 
-template <typename S, typename R, typename Rec, int M, bool W, int V, int PART>
+template <typename S, typename R, typename Rec, int M, bool W, int V, int PART, bool WEAK>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(collide_part_waves<S, M, V, PART>()))) void k_collide(const Params<R>* __restrict__ P, Launch Ln, const S* __restrict__ src,
                                                    S* __restrict__ dst, const Rec* __restrict__ rec,
                                                    const Rec* __restrict__ G, StepNo sn)
@@ -121,24 +122,25 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(collide_p
   const Where w = locate(Ln);
   const Params<R>& Pt = P[w.t];
   if (w.node < Pt.n) {
-    const size_t po = pop_stride<M>() * w.base;
-    collide_node<S, R, Rec, M, W, PART>(Pt, src + po, dst + po, rec + (size_t)RecLayout<M>::FIELDS * w.base,
-                                        G + 3 * w.base, w.node, step_of(sn));
+    const size_t po = pop_stride<M, WEAK>() * w.base;
+    collide_node<S, R, Rec, M, W, PART, WEAK>(Pt, src + po, dst + po,
+                                              rec + (size_t)RecLayout<M, WEAK>::FIELDS * w.base, G + 3 * w.base,
+                                              w.node, step_of(sn));
   }
 }
 
 template <typename T>
 __device__ inline T* seg(T* p, int64_t off) { return p ? p + off : p; }
 
-template <typename S, typename R, int M>
+template <typename S, typename R, int M, bool WEAK>
 __global__ __launch_bounds__(BLOCK) void k_read(const Params<R>* __restrict__ P, Launch Ln, const S* __restrict__ pop,
                                                 double* X, double* rho, double* u, double* p, double* T)
 {
   const Where w = locate(Ln);
   const Params<R>& Pt = P[w.t];
   if (w.node < Pt.n)
-    read_node<S, R, M>(Pt, pop + pop_stride<M>() * w.base, w.node, seg(X, M * w.base), seg(rho, w.base),
-                       seg(u, 3 * w.base), seg(p, w.base), seg(T, w.base));
+    read_node<S, R, M, WEAK>(Pt, pop + pop_stride<M, WEAK>() * w.base, w.node, seg(X, M * w.base),
+                             seg(rho, w.base), seg(u, 3 * w.base), seg(p, w.base), seg(T, w.base));
 }
 
 // Block sum of NV doubles per thread into out[slot * NV + k] (fixed order).
@@ -165,7 +167,7 @@ __device__ inline void block_sum(const double (&v)[NV], double* out, uint32_t sl
 
 static_assert(RED_BLOCK == BLOCK, "reductions use the launch blocks of the tubes");
 
-template <typename S, int M>
+template <typename S, int M, bool WEAK>
 __global__ __launch_bounds__(RED_BLOCK) void k_conserved(const Params<double>* __restrict__ P, Launch Ln,
                                                          const S* __restrict__ pop, double* __restrict__ partial)
 {
@@ -175,12 +177,12 @@ __global__ __launch_bounds__(RED_BLOCK) void k_conserved(const Params<double>* _
   for (int k = 0; k < NV; ++k) v[k] = 0.0;
   const Where w = locate(Ln);
   const Params<double>& Pt = P[w.t];
-  if (w.node < Pt.n) conserved_node<S, M>(Pt, pop + pop_stride<M>() * w.base, w.node, v);
+  if (w.node < Pt.n) conserved_node<S, M, WEAK>(Pt, pop + pop_stride<M, WEAK>() * w.base, w.node, v);
   block_sum<NV>(v, partial, w.block);
 }
 
 // Moles of every species in each x half of every tube (block partials [2 M]).
-template <typename S, int M>
+template <typename S, int M, bool WEAK>
 __global__ __launch_bounds__(RED_BLOCK) void k_half_moles(const Params<double>* __restrict__ P, Launch Ln,
                                                           const S* __restrict__ pop, double* __restrict__ partial)
 {
@@ -190,7 +192,7 @@ __global__ __launch_bounds__(RED_BLOCK) void k_half_moles(const Params<double>* 
   for (int k = 0; k < NV; ++k) v[k] = 0.0;
   const Where w = locate(Ln);
   const Params<double>& Pt = P[w.t];
-  if (w.node < Pt.n) half_moles_node<S, M>(Pt, pop + pop_stride<M>() * w.base, w.node, v);
+  if (w.node < Pt.n) half_moles_node<S, M, WEAK>(Pt, pop + pop_stride<M, WEAK>() * w.base, w.node, v);
   block_sum<NV>(v, partial, w.block);
 }
 
@@ -217,7 +219,7 @@ __global__ __launch_bounds__(RED_BLOCK) void k_field_sums(const int64_t* __restr
   block_sum<NV>(v, partial, w.block);
 }
 
-template <typename S, int M>
+template <typename S, int M, bool WEAK>
 __global__ __launch_bounds__(BLOCK) void k_init(const Params<double>* __restrict__ P, Launch Ln,
                                                 const double* __restrict__ X, const double* __restrict__ p,
                                                 const double* __restrict__ T, const double* __restrict__ u,
@@ -227,14 +229,14 @@ __global__ __launch_bounds__(BLOCK) void k_init(const Params<double>* __restrict
   const Params<double>& Pt = P[w.t];
   int bad = 0;
   if (w.node < Pt.n)
-    bad = init_node<S, M>(Pt, X + (size_t)M * w.base, p + w.base, T + w.base, u + 3 * w.base,
-                          pop + pop_stride<M>() * w.base, w.node);
+    bad = init_node<S, M, WEAK>(Pt, X + (size_t)M * w.base, p + w.base, T + w.base, u + 3 * w.base,
+                                pop + pop_stride<M, WEAK>() * w.base, w.node);
   bad = __syncthreads_or(bad);
   if (threadIdx.x == 0) block_bad[w.block] = bad;
 }
 
 // ---------------------------------------------------------------------------
-// Dispatch over (storage, arithmetic, species count, walls, occupancy variant)
+// Dispatch over (storage, arithmetic, species count, walls, coupling, occupancy variant)
 // ---------------------------------------------------------------------------
 constexpr int NVARIANT = 2;
 
@@ -263,34 +265,34 @@ struct Ops {
                      double* partial, unsigned grid, hipStream_t st);
 };
 
-template <typename S, typename Rec, int M, int V>
+template <typename S, typename Rec, int M, int V, bool WEAK>
 void launch_moments(const void* Pd, const Launch& ln, const void* pop, void* rec, unsigned grid, hipStream_t st)
 {
-  hipLaunchKernelGGL((k_moments<S, Rec, M, V>), dim3(grid), dim3(BLOCK), 0, st, (const Params<double>*)Pd, ln,
+  hipLaunchKernelGGL((k_moments<S, Rec, M, V, WEAK>), dim3(grid), dim3(BLOCK), 0, st, (const Params<double>*)Pd, ln,
                      (const S*)pop, (Rec*)rec);
 }
 
-template <typename S, typename R, typename Rec, int M, bool W, int V, int PART>
+template <typename S, typename R, typename Rec, int M, bool W, int V, int PART, bool WEAK>
 void launch_collide(const void* P, const Launch& ln, const void* src, void* dst, const void* rec, const void* G,
                     StepNo sn, unsigned grid, hipStream_t st)
 {
-  hipLaunchKernelGGL((k_collide<S, R, Rec, M, W, V, PART>), dim3(grid), dim3(BLOCK), 0, st, (const Params<R>*)P,
-                     ln, (const S*)src, (S*)dst, (const Rec*)rec, (const Rec*)G, sn);
+  hipLaunchKernelGGL((k_collide<S, R, Rec, M, W, V, PART, WEAK>), dim3(grid), dim3(BLOCK), 0, st,
+                     (const Params<R>*)P, ln, (const S*)src, (S*)dst, (const Rec*)rec, (const Rec*)G, sn);
 }
 
-template <typename S, typename R, typename Rec, int M, bool W>
+template <typename S, typename R, typename Rec, int M, bool W, bool WEAK>
 Ops make_ops()
 {
   Ops o;
   o.s_bytes = sizeof(S);
   o.r_bytes = sizeof(Rec);
-  o.rec_fields = RecLayout<M>::FIELDS;
-  o.moments[0] = launch_moments<S, Rec, M, 0>;
-  o.moments[1] = launch_moments<S, Rec, M, 1>;
-  o.collide[0] = launch_collide<S, R, Rec, M, W, 0, 0>;
-  o.collide[1] = launch_collide<S, R, Rec, M, W, 1, 0>;
-  o.collide_split[0] = launch_collide<S, R, Rec, M, W, 0, 1>;
-  o.collide_split[1] = launch_collide<S, R, Rec, M, W, 0, 2>;
+  o.rec_fields = RecLayout<M, WEAK>::FIELDS;
+  o.moments[0] = launch_moments<S, Rec, M, 0, WEAK>;
+  o.moments[1] = launch_moments<S, Rec, M, 1, WEAK>;
+  o.collide[0] = launch_collide<S, R, Rec, M, W, 0, 0, WEAK>;
+  o.collide[1] = launch_collide<S, R, Rec, M, W, 1, 0, WEAK>;
+  o.collide_split[0] = launch_collide<S, R, Rec, M, W, 0, 1, WEAK>;
+  o.collide_split[1] = launch_collide<S, R, Rec, M, W, 0, 2, WEAK>;
   o.gfield = [](const void* Pd, const Launch& ln, const void* rec, void* G, int rec_fields, unsigned grid,
                 hipStream_t st) {
     hipLaunchKernelGGL((k_gfield<Rec, W>), dim3(grid), dim3(BLOCK), 0, st, (const Params<double>*)Pd, ln,
@@ -298,22 +300,22 @@ Ops make_ops()
   };
   o.read = [](const void* P, const Launch& ln, const void* pop, double* X, double* rho, double* u, double* p,
               double* T, unsigned grid, hipStream_t st) {
-    hipLaunchKernelGGL((k_read<S, R, M>), dim3(grid), dim3(BLOCK), 0, st, (const Params<R>*)P, ln, (const S*)pop,
+    hipLaunchKernelGGL((k_read<S, R, M, WEAK>), dim3(grid), dim3(BLOCK), 0, st, (const Params<R>*)P, ln, (const S*)pop,
                        X, rho, u, p, T);
   };
   o.conserved = [](const void* Pd, const Launch& ln, const void* pop, double* partial, unsigned grid,
                    hipStream_t st) {
-    hipLaunchKernelGGL((k_conserved<S, M>), dim3(grid), dim3(RED_BLOCK), 0, st, (const Params<double>*)Pd, ln,
+    hipLaunchKernelGGL((k_conserved<S, M, WEAK>), dim3(grid), dim3(RED_BLOCK), 0, st, (const Params<double>*)Pd, ln,
                        (const S*)pop, partial);
   };
   o.half_moles = [](const void* Pd, const Launch& ln, const void* pop, double* partial, unsigned grid,
                      hipStream_t st) {
-    hipLaunchKernelGGL((k_half_moles<S, M>), dim3(grid), dim3(RED_BLOCK), 0, st, (const Params<double>*)Pd, ln,
+    hipLaunchKernelGGL((k_half_moles<S, M, WEAK>), dim3(grid), dim3(RED_BLOCK), 0, st, (const Params<double>*)Pd, ln,
                        (const S*)pop, partial);
   };
   o.init = [](const void* Pd, const Launch& ln, const double* X, const double* p, const double* T,
               const double* u, void* pop, int* bad, unsigned grid, hipStream_t st) {
-    hipLaunchKernelGGL((k_init<S, M>), dim3(grid), dim3(BLOCK), 0, st, (const Params<double>*)Pd, ln, X, p, T, u,
+    hipLaunchKernelGGL((k_init<S, M, WEAK>), dim3(grid), dim3(BLOCK), 0, st, (const Params<double>*)Pd, ln, X, p, T, u,
                        (S*)pop, bad);
   };
   o.field_sums = [](const int64_t* tube_n, const Launch& ln, const double* X, const double* p, const double* T,
@@ -323,24 +325,25 @@ Ops make_ops()
   return o;
 }
 
-template <typename S, typename R, typename Rec>
+template <typename S, typename R, typename Rec, bool WEAK>
 bool pick_m(int M, int walls, Ops& o)
 {
   switch (M) {
-    case 2: o = walls ? make_ops<S, R, Rec, 2, true>() : make_ops<S, R, Rec, 2, false>(); return true;
-    case 3: o = walls ? make_ops<S, R, Rec, 3, true>() : make_ops<S, R, Rec, 3, false>(); return true;
-    case 4: o = walls ? make_ops<S, R, Rec, 4, true>() : make_ops<S, R, Rec, 4, false>(); return true;
+    case 2: o = walls ? make_ops<S, R, Rec, 2, true, WEAK>() : make_ops<S, R, Rec, 2, false, WEAK>(); return true;
+    case 3: o = walls ? make_ops<S, R, Rec, 3, true, WEAK>() : make_ops<S, R, Rec, 3, false, WEAK>(); return true;
+    case 4: o = walls ? make_ops<S, R, Rec, 4, true, WEAK>() : make_ops<S, R, Rec, 4, false, WEAK>(); return true;
     default: return false;
   }
 }
 
 }  // namespace kern
 
-// One entry point per instantiated (storage, arithmetic) pair.
-bool pick_fp64(int M, int walls, kern::Ops& o);
-bool pick_fp32_fp64(int M, int walls, kern::Ops& o);
-bool pick_fp32(int M, int walls, kern::Ops& o);
-bool pick_fp16(int M, int walls, kern::Ops& o);
-bool pick_bf16(int M, int walls, kern::Ops& o);
+// One entry point per instantiated (storage, arithmetic) pair. weak: 1 for weak
+// coupling (compiled for FP64 and FP32 storage with FP64 arithmetic only).
+bool pick_fp64(int M, int walls, int weak, kern::Ops& o);
+bool pick_fp32_fp64(int M, int walls, int weak, kern::Ops& o);
+bool pick_fp32(int M, int walls, int weak, kern::Ops& o);
+bool pick_fp16(int M, int walls, int weak, kern::Ops& o);
+bool pick_bf16(int M, int walls, int weak, kern::Ops& o);
 
 }  // namespace mclbm

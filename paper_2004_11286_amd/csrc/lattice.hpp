@@ -13,7 +13,17 @@ namespace mclbm {
 
 constexpr int Q = 27;
 constexpr int MAXM = 8;           // species per context
-constexpr int MAXL = MAXM + 1;    // stored lattices: M-1 species, momentum f, energy g
+constexpr int MAXL = MAXM + 2;    // stored lattices: up to M species, momentum f, energy g
+
+// Stored lattices of an M-species context. Strong coupling (Sec. 3.6.2) stores
+// species 1..M-1 (the slaved species' populations are never read); weak
+// coupling (Sec. 3.6.1) stores all M species. Then the momentum lattice f (LF)
+// and the energy lattice g (LG).
+template <int M, bool WEAK>
+struct Lat {
+  static constexpr int NS = WEAK ? M : M - 1;
+  static constexpr int LF = NS, LG = NS + 1, L = NS + 2;
+};
 
 __host__ __device__ constexpr int cx(int i) { return i / 9 - 1; }
 __host__ __device__ constexpr int cy(int i) { return (i / 3) % 3 - 1; }

@@ -135,14 +135,14 @@ __global__ __launch_bounds__(BLOCK) void k_pred_to_state(const Params<double>* _
   if (threadIdx.x == 0) block_bad[w.block] = bad;
 }
 
-bool pick_ops(int precision, int M, int walls, Ops& o)
+bool pick_ops(int precision, int M, int walls, int weak, Ops& o)
 {
   switch (precision) {
-    case MCLBM_FP64: return pick_fp64(M, walls, o);
-    case MCLBM_FP32: return pick_fp32_fp64(M, walls, o);
-    case MCLBM_FP32_FP32: return pick_fp32(M, walls, o);
-    case MCLBM_FP16: return pick_fp16(M, walls, o);
-    case MCLBM_BF16: return pick_bf16(M, walls, o);
+    case MCLBM_FP64: return pick_fp64(M, walls, weak, o);
+    case MCLBM_FP32: return pick_fp32_fp64(M, walls, weak, o);
+    case MCLBM_FP32_FP32: return pick_fp32(M, walls, weak, o);
+    case MCLBM_FP16: return pick_fp16(M, walls, weak, o);
+    case MCLBM_BF16: return pick_bf16(M, walls, weak, o);
     default: return false;
   }
 }
@@ -167,7 +167,7 @@ struct TubeHost {
 // Context
 // ---------------------------------------------------------------------------
 struct mclbm_ctx {
-  int M = 0, wall_x = 0, precision = 0, L = 0, ntubes = 0;
+  int M = 0, wall_x = 0, precision = 0, weak = 0, L = 0, ntubes = 0;
   int64_t n = 0;            // nodes over all tubes
   int64_t nblocks = 0;      // launch blocks over all tubes
   std::vector<TubeHost> tubes;
@@ -234,7 +234,7 @@ size_t record_bytes(int precision) { return precision == MCLBM_FP64 ? 8 : 4; }
 
 Layout layout_for(const mclbm_params* tp, int ntubes)
 {
-  const int M = tp[0].M, precision = tp[0].precision;
+  const int M = tp[0].M, precision = tp[0].precision, weak = tp[0].weak;
   Layout l{};
   l.n = 0;
   l.nblocks = 0;
@@ -244,8 +244,11 @@ Layout layout_for(const mclbm_params* tp, int ntubes)
     l.nblocks += (n + BLOCK - 1) / BLOCK;
   }
   const size_t s_bytes = storage_bytes(precision), r_bytes = record_bytes(precision);
-  const int L = M + 1;
-  const int rec_fields = REC_RHOA + (M - 1) + 3 * M;
+  // stored lattices and record fields (RecLayout): M-1 stored species under
+  // strong coupling, M under weak coupling (which also records u_s)
+  const int ns = weak ? M : M - 1;
+  const int L = ns + 2;
+  const int rec_fields = REC_RHOA + ns + 3 * M + (weak ? 3 : 0);
   size_t off = 0;
   l.pd = off; off += align_up(sizeof(Params<double>) * ntubes);
   l.pr = off; off += align_up(sizeof(Params<float>) * ntubes);
@@ -285,7 +288,12 @@ int validate_one(const mclbm_params* p, std::string& err)
   if (p->wall_x != 0 && p->wall_x != 1) { err = "wall_x must be 0 or 1"; return MCLBM_EARG; }
   if (p->wall_x && p->nx < 2) { err = "walls need nx >= 2"; return MCLBM_EARG; }
   if (p->precision < MCLBM_FP64 || p->precision > MCLBM_BF16) { err = "unknown precision"; return MCLBM_EARG; }
-  if (p->reserved0 || p->reserved1) { err = "reserved fields must be 0"; return MCLBM_EARG; }
+  if (p->weak != 0 && p->weak != 1) { err = "weak must be 0 or 1"; return MCLBM_EARG; }
+  if (p->reserved1) { err = "reserved fields must be 0"; return MCLBM_EARG; }
+  if (p->weak && p->precision != MCLBM_FP64 && p->precision != MCLBM_FP32) {
+    err = "weak coupling is compiled for MCLBM_FP64 and MCLBM_FP32 only";
+    return MCLBM_EUNSUPPORTED;
+  }
   if (!p->molar_mass || !p->cv || !p->D || !p->mu || !p->lambda) { err = "species arrays must be given"; return MCLBM_EARG; }
   for (int a = 0; a < p->M; ++a) {
     if (!(p->molar_mass[a] > 0) || !(p->cv[a] > 0) || !(p->mu[a] > 0) || !(p->lambda[a] > 0)) {
@@ -311,8 +319,9 @@ int validate(const mclbm_params* tp, int ntubes, std::string& err)
       if (ntubes > 1) err = "tube " + std::to_string(t) + ": " + err;
       return rc;
     }
-    if (tp[t].M != tp[0].M || tp[t].wall_x != tp[0].wall_x || tp[t].precision != tp[0].precision) {
-      err = "all tubes of a batch must share M, wall_x and precision";
+    if (tp[t].M != tp[0].M || tp[t].wall_x != tp[0].wall_x || tp[t].precision != tp[0].precision ||
+        tp[t].weak != tp[0].weak) {
+      err = "all tubes of a batch must share M, wall_x, precision and weak";
       return MCLBM_EARG;
     }
     const int64_t n = (int64_t)tp[t].nx * tp[t].ny * tp[t].nz;
@@ -356,8 +365,10 @@ int push_params(mclbm_ctx* c)
   const double tol = absent_tol_for(c->precision);
   for (int t = 0; t < c->ntubes; ++t) {
     const TubeHost& th = c->tubes[t];
-    fill_params<double>(c->hPd[t], th.hs, th.nx, th.ny, th.nz, c->wall_x, th.ref, th.ref0, th.ref2, th.scale, tol);
-    fill_params<float>(c->hPf[t], th.hs, th.nx, th.ny, th.nz, c->wall_x, th.ref, th.ref0, th.ref2, th.scale, tol);
+    fill_params<double>(c->hPd[t], th.hs, th.nx, th.ny, th.nz, c->wall_x, c->L, th.ref, th.ref0, th.ref2, th.scale,
+                        tol);
+    fill_params<float>(c->hPf[t], th.hs, th.nx, th.ny, th.nz, c->wall_x, c->L, th.ref, th.ref0, th.ref2, th.scale,
+                       tol);
   }
   HIP_TRY(c, hipMemcpyAsync(c->dPd, c->hPd.data(), sizeof(Params<double>) * c->ntubes, hipMemcpyHostToDevice,
                             c->stream));
@@ -449,7 +460,7 @@ int upload_params(mclbm_ctx* c, const std::vector<RefState>& rs)
 {
   for (int t = 0; t < c->ntubes; ++t) {
     TubeHost& th = c->tubes[t];
-    reference_tables(th.hs, rs[t], th.ref, th.ref0, th.ref2);
+    reference_tables(th.hs, c->L - 2, rs[t], th.ref, th.ref0, th.ref2);
     for (int l = 0; l < MAXL; ++l) th.scale[l] = 1.0;
     for (int l = 0; l < c->L; ++l) {
       th.scale[l] = scale_for(c->precision, th.ref[l]);
@@ -650,7 +661,8 @@ extern "C" int mclbm_batch_create(const mclbm_params* tp, int32_t ntubes, void* 
   c->M = tp[0].M;
   c->wall_x = tp[0].wall_x;
   c->precision = tp[0].precision;
-  c->L = c->M + 1;
+  c->weak = tp[0].weak;
+  c->L = (c->weak ? c->M : c->M - 1) + 2;
   c->ntubes = ntubes;
   c->n = lay.n;
   c->nblocks = lay.nblocks;
@@ -672,7 +684,7 @@ extern "C" int mclbm_batch_create(const mclbm_params* tp, int32_t ntubes, void* 
       for (int b = 0; b < p->M; ++b) th.hs.D[a][b] = p->D[a * p->M + b];
     }
   }
-  if (!pick_ops(c->precision, c->M, c->wall_x, c->ops)) {
+  if (!pick_ops(c->precision, c->M, c->wall_x, c->weak, c->ops)) {
     delete c;
     return fail(nullptr, MCLBM_EUNSUPPORTED, "no kernels compiled for this configuration");
   }
@@ -959,13 +971,14 @@ namespace {
 struct CkptHeader {
   char magic[8];
   int32_t M, wall_x, precision, ntubes;
+  int32_t weak, pad;
   int64_t steps;
 };
 struct CkptTube {
   int32_t nx, ny, nz, pad;
   double ref[MAXL][Q], ref0[MAXL], ref2[MAXL], scale[MAXL];
 };
-const char kMagic[8] = "MCLBMv2";
+const char kMagic[8] = "MCLBMv3";
 
 size_t header_bytes(const mclbm_ctx* c) { return sizeof(CkptHeader) + sizeof(CkptTube) * c->ntubes; }
 }  // namespace
@@ -983,7 +996,7 @@ extern "C" int mclbm_save(mclbm_ctx* c, void* host_buf, size_t bytes)
   if (bytes < mclbm_state_bytes(c)) return fail(c, MCLBM_EARG, "buffer too small");
   CkptHeader h{};
   std::memcpy(h.magic, kMagic, 8);
-  h.M = c->M; h.wall_x = c->wall_x; h.precision = c->precision; h.ntubes = c->ntubes;
+  h.M = c->M; h.wall_x = c->wall_x; h.precision = c->precision; h.ntubes = c->ntubes; h.weak = c->weak;
   h.steps = c->steps;
   char* dst = (char*)host_buf;
   std::memcpy(dst, &h, sizeof(h));
@@ -1011,7 +1024,7 @@ extern "C" int mclbm_load(mclbm_ctx* c, const void* host_buf, size_t bytes)
   CkptHeader h;
   std::memcpy(&h, src, sizeof(h));
   if (std::memcmp(h.magic, kMagic, 8) != 0 || h.M != c->M || h.wall_x != c->wall_x || h.precision != c->precision ||
-      h.ntubes != c->ntubes)
+      h.ntubes != c->ntubes || h.weak != c->weak)
     return fail(c, MCLBM_EARG, "checkpoint does not match this context");
   std::vector<CkptTube> ct(c->ntubes);
   for (int t = 0; t < c->ntubes; ++t) {

@@ -2,10 +2,13 @@
 // lattice Boltzmann model (Sawant, Dorschner, Karlin, arXiv 2004.11286),
 // written as inlined functions that the HIP kernels call once per lattice node.
 //
-// Storage: pop[l][i][n] with l = 0..M-2 the stored species (species M is slaved
-// to the momentum lattice under strong coupling, Sec. 3.6.2, and no quantity
-// ever reads its populations), l = M-1 the momentum lattice f, l = M the energy
-// lattice g; n = x + nx (y + ny z). Stored values are d = s_l (f - f_ref,l,i).
+// Storage: pop[l][i][n] with l = 0..NS-1 the stored species, l = NS the
+// momentum lattice f, l = NS+1 the energy lattice g; n = x + nx (y + ny z).
+// Under strong coupling (Sec. 3.6.2) NS = M-1: species M is slaved to the
+// momentum lattice and no quantity ever reads its populations. Under weak
+// coupling (Sec. 3.6.1) NS = M: the species subsystem of Sec. 2 keeps its own
+// density and velocity (eqs rhoSPEC, uSPEC) and takes T from the energy lattice.
+// Stored values are d = s_l (f - f_ref,l,i).
 //
 // A step is three passes:
 //   state_node    reads every population of a node, forms the moments in FP64,
@@ -33,12 +36,13 @@ enum {
   REC_OMEGA = 3, REC_CP = 4,                   // omega (eq omega), mixture C_p
   REC_RHO = 5, REC_UX = 6, REC_UY = 7, REC_UZ = 8, REC_T = 9, REC_OMEGA1 = 10,
   REC_QNX = 11, REC_QNY = 12, REC_QNZ = 13,    // q - q^eq - u.(P - P^eq)
-  REC_RHOA = 14                                // then rho_a (M-1 stored species), V_a (3 M)
-};
-template <int M>
+  REC_RHOA = 14                                // then rho_a (stored species), V_a (3 M),
+};                                             // and under weak coupling u_s (3)
+template <int M, bool WEAK = false>
 struct RecLayout {
-  static constexpr int V = REC_RHOA + (M - 1);
-  static constexpr int FIELDS = V + 3 * M;
+  static constexpr int V = REC_RHOA + Lat<M, WEAK>::NS;
+  static constexpr int US = V + 3 * M;
+  static constexpr int FIELDS = US + (WEAK ? 3 : 0);
 };
 
 // Macroscopic state of a node (Secs. 2.1, 3.1, 3.2; strong coupling Sec. 3.6.2).
@@ -49,8 +53,10 @@ struct Mix {
   R mmix, Rg, Cv, Cp, T, P;
 };
 
-// rho_s[0..M-2]: stored species densities; the slaved species takes the deficit.
-template <typename R, int M>
+// rho_s: species densities. Strong coupling: rho_s[0..M-2] stored, the slaved
+// species takes the deficit and Y_a = rho_a / rho. Weak coupling: all M stored,
+// Y_a = rho_a / sum_b rho_b (the species subsystem's own density, eq rhoSPEC).
+template <typename R, int M, bool WEAK = false>
 __host__ __device__ __forceinline__ void mixture_state(const Params<R>& P, R rho, const R j[3], R rhoE,
                                               const R rho_s[M], Mix<R, M>& s)
 {
@@ -63,17 +69,28 @@ __host__ __device__ __forceinline__ void mixture_state(const Params<R>& P, R rho
     s.u[k] = j[k] * s.inv_rho;
     s.usq += s.u[k] * s.u[k];
   }
-  R deficit = rho;
+  R inv_rs = s.inv_rho;
+  if constexpr (WEAK) {
+    R rs = R(0);
 #pragma unroll
-  for (int a = 0; a < M - 1; ++a) {
-    s.rho_a[a] = rho_s[a];
-    deficit -= rho_s[a];
+    for (int a = 0; a < M; ++a) {
+      s.rho_a[a] = rho_s[a];
+      rs += rho_s[a];
+    }
+    inv_rs = R(1) / rs;
+  } else {
+    R deficit = rho;
+#pragma unroll
+    for (int a = 0; a < M - 1; ++a) {
+      s.rho_a[a] = rho_s[a];
+      deficit -= rho_s[a];
+    }
+    s.rho_a[M - 1] = deficit;
   }
-  s.rho_a[M - 1] = deficit;
   R inv_m = R(0), Cv = R(0), Cp = R(0);
 #pragma unroll
   for (int a = 0; a < M; ++a) {
-    s.Y[a] = s.rho_a[a] * s.inv_rho;
+    s.Y[a] = s.rho_a[a] * inv_rs;
     inv_m += s.Y[a] * P.inv_m[a];
     Cv += s.Y[a] * P.cv[a];
     Cp += s.Y[a] * P.cp[a];
@@ -185,8 +202,11 @@ __host__ __device__ __forceinline__ bool is_ghost(const Nbr& b, int ci)
 
 // --------------------------------------------------------------------------
 // Diffusion velocities: rho_a V_a + 1/2 sum_b K_ab (V_a - V_b) = j_a - rho_a u
-// (eq transform12), with K_ab = P X_a X_b / D_ab. A species whose density is at
-// or below the detection threshold has a zero row and column: V_a = 0.
+// (eq transform12), with K_ab = P X_a X_b / D_ab; u and P are those of the
+// species subsystem (the mixture's under strong coupling; under weak coupling
+// u_s = sum_a j_a / sum_a rho_a and the Dalton pressure sum_a rho_a R_a T). A
+// species whose density is at or below the detection threshold has a zero row
+// and column: V_a = 0.
 // --------------------------------------------------------------------------
 template <typename R, int M>
 __host__ __device__ __forceinline__ void species_present(const Params<R>& P, const R rho_a[M], R rho, bool present[M])
@@ -196,19 +216,19 @@ __host__ __device__ __forceinline__ void species_present(const Params<R>& P, con
 }
 
 template <typename R, int M>
-__host__ __device__ __forceinline__ void friction_matrix(const Params<R>& P, const Mix<R, M>& s, const bool present[M],
-                                                R K[M][M])
+__host__ __device__ __forceinline__ void friction_matrix(const Params<R>& P, const Mix<R, M>& s, R Pk,
+                                                const bool present[M], R K[M][M])
 {
 #pragma unroll
   for (int a = 0; a < M; ++a)
 #pragma unroll
     for (int c = 0; c < M; ++c)
-      K[a][c] = (present[a] && present[c]) ? s.P * s.X[a] * s.X[c] * P.invD[a][c] : R(0);
+      K[a][c] = (present[a] && present[c]) ? Pk * s.X[a] * s.X[c] * P.invD[a][c] : R(0);
 }
 
 template <typename R, int M>
 __host__ __device__ __forceinline__ void diffusion_velocities(const Mix<R, M>& s, const bool present[M], const R K[M][M],
-                                                     const R js[M][3], R V[M][3])
+                                                     const R js[M][3], const R uref[3], R V[M][3])
 {
   R A[M][M], rhs[M][3];
 #pragma unroll
@@ -222,7 +242,7 @@ __host__ __device__ __forceinline__ void diffusion_velocities(const Mix<R, M>& s
     }
     A[a][a] = diag;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) rhs[a][k] = present[a] ? js[a][k] - s.rho_a[a] * s.u[k] : R(0);
+    for (int k = 0; k < 3; ++k) rhs[a][k] = present[a] ? js[a][k] - s.rho_a[a] * uref[k] : R(0);
   }
   // Gaussian elimination without pivoting: the matrix is column diagonally dominant
 #pragma unroll
@@ -260,17 +280,17 @@ __host__ __device__ __forceinline__ void acc_c(R& acc, int c, R v)
 // --------------------------------------------------------------------------
 // Pass 1: node state -> record (FP64 arithmetic, record stored as Rec)
 // --------------------------------------------------------------------------
-template <typename S, typename Rec, int M>
+template <typename S, typename Rec, int M, bool WEAK = false>
 __host__ __device__ __forceinline__ void state_node(const Params<double>& P, const S* __restrict__ pop,
                                            Rec* __restrict__ rec, int64_t node)
 {
   using D = double;
   const size_t n = (size_t)P.n;
   const uint32_t nd = (uint32_t)node;
-  constexpr int LF = M - 1, LG = M;
+  constexpr int NS = Lat<M, WEAK>::NS, LF = Lat<M, WEAK>::LF, LG = Lat<M, WEAK>::LG;
   D rho_s[M], js[M][3];
 #pragma unroll
-  for (int a = 0; a < M - 1; ++a) {
+  for (int a = 0; a < NS; ++a) {
     D r = 0.0, ja[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -285,7 +305,7 @@ __host__ __device__ __forceinline__ void state_node(const Params<double>& P, con
     for (int k = 0; k < 3; ++k) js[a][k] = ja[k];
     lattice_barrier();
   }
-  rho_s[M - 1] = 0.0;
+  if constexpr (!WEAK) rho_s[M - 1] = 0.0;
   D rho = 0.0, j[3] = {0.0, 0.0, 0.0}, Pd[3] = {0.0, 0.0, 0.0}, Pxy = 0.0, Pxz = 0.0, Pyz = 0.0;
   D rhoE = 0.0, q[3] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -312,19 +332,35 @@ __host__ __device__ __forceinline__ void state_node(const Params<double>& P, con
 #pragma unroll
   for (int k = 0; k < 3; ++k) Pd[k] += P.ref2[LF];
   Mix<D, M> s;
-  mixture_state<D, M>(P, rho, j, rhoE, rho_s, s);
+  mixture_state<D, M, WEAK>(P, rho, j, rhoE, rho_s, s);
+  D us[3], Pk = s.P;                     // velocity and pressure of the species subsystem
+  if constexpr (WEAK) {
+    D rs = 0.0;
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {          // slaved species momentum: the deficit (eq uMATCH)
-    D jm = j[k];
+    for (int a = 0; a < M; ++a) rs += s.rho_a[a];
 #pragma unroll
-    for (int a = 0; a < M - 1; ++a) jm -= js[a][k];
-    js[M - 1][k] = jm;
+    for (int k = 0; k < 3; ++k) {
+      D jt = 0.0;
+#pragma unroll
+      for (int a = 0; a < M; ++a) jt += js[a][k];
+      us[k] = jt / rs;                   // eq uSPEC
+    }
+    Pk = rs * s.Rg * s.T;                // Dalton: sum_a rho_a R_a T
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {        // slaved species momentum: the deficit (eq uMATCH)
+      D jm = j[k];
+#pragma unroll
+      for (int a = 0; a < M - 1; ++a) jm -= js[a][k];
+      js[M - 1][k] = jm;
+      us[k] = s.u[k];
+    }
   }
   bool present[M];
   species_present<D, M>(P, s.rho_a, s.rho, present);
   D K[M][M], V[M][3];
-  friction_matrix<D, M>(P, s, present, K);
-  diffusion_velocities<D, M>(s, present, K, js, V);
+  friction_matrix<D, M>(P, s, Pk, present, K);
+  diffusion_velocities<D, M>(s, present, K, js, us, V);
   const D theta = s.Rg * s.T;
   const D omega = 2.0 * s.P / (s.P + 2.0 * mixture_viscosity<D, M>(P, s.X));
   const D omega1 = 2.0 * s.P * s.Cp / (s.P * s.Cp + 2.0 * mixture_conductivity<D, M>(P, s.X));
@@ -352,11 +388,15 @@ __host__ __device__ __forceinline__ void state_node(const Params<double>& P, con
 #pragma unroll
   for (int k = 0; k < 3; ++k) put(REC_QNX + k, qn[k]);
 #pragma unroll
-  for (int a = 0; a < M - 1; ++a) put(REC_RHOA + a, s.rho_a[a]);
+  for (int a = 0; a < NS; ++a) put(REC_RHOA + a, s.rho_a[a]);
 #pragma unroll
   for (int a = 0; a < M; ++a)
 #pragma unroll
-    for (int k = 0; k < 3; ++k) put(RecLayout<M>::V + 3 * a + k, V[a][k]);
+    for (int k = 0; k < 3; ++k) put(RecLayout<M, WEAK>::V + 3 * a + k, V[a][k]);
+  if constexpr (WEAK) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) put(RecLayout<M, WEAK>::US + k, us[k]);
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -485,13 +525,14 @@ __host__ __device__ __forceinline__ void load_lattice(const S* __restrict__ lat,
 
 // PART selects the lattices: 0 all, 1 the stored species lattices, 2 the momentum
 // and energy lattices (a split collision in two launches computes the same step).
-template <typename S, typename R, typename Rec, int M, bool WALLS, int PART = 0>
+template <typename S, typename R, typename Rec, int M, bool WALLS, int PART = 0, bool WEAK = false>
 __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const S* __restrict__ src,
                                              S* __restrict__ dst, const Rec* __restrict__ rec,
                                              const Rec* __restrict__ G, int64_t node, uint32_t step)
 {
   const size_t n = (size_t)P.n;
-  constexpr int LF = M - 1, LG = M;
+  constexpr int NS = Lat<M, WEAK>::NS, LF = Lat<M, WEAK>::LF, LG = Lat<M, WEAK>::LG;
+  using RL = RecLayout<M, WEAK>;
   // issue a lattice's loads together (load_lattice) where the scheduler otherwise
   // serialises them: 16-bit storage, and the unsplit collision of three or more
   // species (one wave per SIMD, registers to spare); elsewhere each load is
@@ -504,9 +545,10 @@ __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const 
   const R rho = get(REC_RHO);
   R rho_s[M];
 #pragma unroll
-  for (int a = 0; a < M - 1; ++a) rho_s[a] = get(REC_RHOA + a);
-  rho_s[M - 1] = R(0);
+  for (int a = 0; a < NS; ++a) rho_s[a] = get(REC_RHOA + a);
+  if constexpr (!WEAK) rho_s[M - 1] = R(0);
   Mix<R, M> s;
+  R rs = rho;                     // the species subsystem's density
   {
     s.rho = rho;
     s.inv_rho = R(1) / rho;
@@ -516,17 +558,28 @@ __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const 
       s.u[k] = get(REC_UX + k);
       s.usq += s.u[k] * s.u[k];
     }
-    R deficit = rho;
+    R inv_rs = s.inv_rho;
+    if constexpr (WEAK) {
+      rs = R(0);
 #pragma unroll
-    for (int a = 0; a < M - 1; ++a) {
-      s.rho_a[a] = rho_s[a];
-      deficit -= rho_s[a];
+      for (int a = 0; a < M; ++a) {
+        s.rho_a[a] = rho_s[a];
+        rs += rho_s[a];
+      }
+      inv_rs = R(1) / rs;
+    } else {
+      R deficit = rho;
+#pragma unroll
+      for (int a = 0; a < M - 1; ++a) {
+        s.rho_a[a] = rho_s[a];
+        deficit -= rho_s[a];
+      }
+      s.rho_a[M - 1] = deficit;
     }
-    s.rho_a[M - 1] = deficit;
     R inv_m = R(0), Cp = R(0);
 #pragma unroll
     for (int a = 0; a < M; ++a) {
-      s.Y[a] = s.rho_a[a] * s.inv_rho;
+      s.Y[a] = s.rho_a[a] * inv_rs;
       inv_m += s.Y[a] * P.inv_m[a];
       Cp += s.Y[a] * P.cp[a];
     }
@@ -565,10 +618,19 @@ __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const 
   // F_ai = sum_b K_ab [Psi_i(u, R_b T) - Psi_i(u + V_b, R_b T)] (eq fstar1), with
   // K_ab = P X_a X_b / D_ab, 1/tau_a = sum_b Y_b / tau_ab (eqs tauab, tau).
   if constexpr (PART != 2) {
+    // velocity and pressure of the species subsystem: the mixture's under strong
+    // coupling; u_s (eq uSPEC) and the Dalton pressure under weak coupling
+    R us[3] = {s.u[0], s.u[1], s.u[2]};
+    R Pk = s.P;
+    if constexpr (WEAK) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) us[k] = get(RL::US + k);
+      Pk = rs * s.Rg * s.T;
+    }
     bool present[M];
     species_present<R, M>(P, s.rho_a, s.rho, present);
     R K[M][M];
-    friction_matrix<R, M>(P, s, present, K);
+    friction_matrix<R, M>(P, s, Pk, present, K);
     // F_ai is a small correction: with 32- or 16-bit storage its triplets are kept
     // in FP32 (pe32: Psi(u), pd32: Psi(u) - Psi(u + V)); with FP64 storage in FP64.
     using F32 = typename std::conditional<sizeof(S) == 8, double, float>::type;
@@ -578,12 +640,12 @@ __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const 
       const F32 zeta = F32(s.T * P.inv_m[c]);
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        pe32[c][k] = psi_trip<F32>(F32(s.u[k]), zeta);
-        pd32[c][k] = psi_diff_trip<F32>(F32(s.u[k]), F32(get(RecLayout<M>::V + 3 * c + k)));
+        pe32[c][k] = psi_trip<F32>(F32(us[k]), zeta);
+        pd32[c][k] = psi_diff_trip<F32>(F32(us[k]), F32(get(RL::V + 3 * c + k)));
       }
     }
 #pragma unroll
-    for (int a = 0; a < M - 1; ++a) {
+    for (int a = 0; a < NS; ++a) {
       R acc = R(0);
 #pragma unroll
       for (int c = 0; c < M; ++c) acc += s.Y[c] * P.invD[a][c] * P.inv_m[c];
@@ -591,7 +653,7 @@ __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const 
       const R beta = inv_tau / (R(2) + inv_tau);            // dt / (2 tau_a + dt)
       Trip<R> pa[3];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) pa[k] = psi_trip<R>(s.u[k], s.T * P.inv_m[a]);
+      for (int k = 0; k < 3; ++k) pa[k] = psi_trip<R>(us[k], s.T * P.inv_m[a]);
       S v[Q];
       R t0 = R(0), s0 = R(0);
       Rng rng(node, a, step);
@@ -704,7 +766,7 @@ __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const 
     for (int a = 0; a < M; ++a) {
       const R ca = P.cp[a] * s.Y[a];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) hyv[k] += ca * get(RecLayout<M>::V + 3 * a + k);
+      for (int k = 0; k < 3; ++k) hyv[k] += ca * get(RL::V + 3 * a + k);
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -755,21 +817,21 @@ __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const 
 // --------------------------------------------------------------------------
 // Read-back of the macroscopic fields
 // --------------------------------------------------------------------------
-template <typename S, typename R, int M>
+template <typename S, typename R, int M, bool WEAK = false>
 __host__ __device__ __forceinline__ void read_node(const Params<R>& P, const S* __restrict__ pop, int64_t node,
                                           double* X, double* rho_o, double* u, double* p, double* T)
 {
   const size_t n = (size_t)P.n;
-  constexpr int LF = M - 1, LG = M;
+  constexpr int NS = Lat<M, WEAK>::NS, LF = Lat<M, WEAK>::LF, LG = Lat<M, WEAK>::LG;
   R rho_s[M];
 #pragma unroll
-  for (int a = 0; a < M - 1; ++a) {
+  for (int a = 0; a < NS; ++a) {
     R sum = R(0);
 #pragma unroll
     for (int i = 0; i < Q; ++i) sum += load_dev<S, R>(pop, (size_t)(a * Q + i) * n + node, P.inv_scale[a]);
     rho_s[a] = P.ref0[a] + sum;
   }
-  rho_s[M - 1] = R(0);
+  if constexpr (!WEAK) rho_s[M - 1] = R(0);
   R rho = R(0), j[3] = {R(0), R(0), R(0)}, rhoE = R(0);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
@@ -783,7 +845,7 @@ __host__ __device__ __forceinline__ void read_node(const Params<R>& P, const S* 
   rho += P.ref0[LF];
   rhoE += P.ref0[LG];
   Mix<R, M> s;
-  mixture_state<R, M>(P, rho, j, rhoE, rho_s, s);
+  mixture_state<R, M, WEAK>(P, rho, j, rhoE, rho_s, s);
   if (X)
 #pragma unroll
     for (int a = 0; a < M; ++a) X[(size_t)a * n + node] = (double)s.X[a];
@@ -798,13 +860,13 @@ __host__ __device__ __forceinline__ void read_node(const Params<R>& P, const S* 
 // --------------------------------------------------------------------------
 // Initialisation at the local equilibrium of (X_a, p, T, u), computed in FP64
 // --------------------------------------------------------------------------
-template <typename S, int M>
+template <typename S, int M, bool WEAK = false>
 __host__ __device__ __forceinline__ int init_node(const Params<double>& P, const double* X,
                                          const double* p, const double* T, const double* u, S* __restrict__ pop,
                                          int64_t node)
 {
   const size_t n = (size_t)P.n;
-  constexpr int LF = M - 1, LG = M;
+  constexpr int NS = Lat<M, WEAK>::NS, LF = Lat<M, WEAK>::LF, LG = Lat<M, WEAK>::LG;
   double Xa[M], mmix = 0.0;
 #pragma unroll
   for (int a = 0; a < M; ++a) {
@@ -825,7 +887,7 @@ __host__ __device__ __forceinline__ int init_node(const Params<double>& P, const
   }
   int bad = (Tn > 0.0 && pn > 0.0) ? 0 : 1;
 #pragma unroll
-  for (int a = 0; a < M - 1; ++a) {
+  for (int a = 0; a < NS; ++a) {
     const double zeta = Tn * P.inv_m[a];
     if (!(zeta + usq < 1.0)) bad = 1;
     Trip<double> t[3];
@@ -875,18 +937,19 @@ __host__ __device__ __forceinline__ int init_node(const Params<double>& P, const
 }
 
 // --------------------------------------------------------------------------
-// Conserved sums of a node in FP64: rho_1..rho_M (rho_M slaved), rho, rho u, rho E,
-// plus a flag for non-finite values or a negative slaved density.
+// Conserved sums of a node in FP64: rho_1..rho_M (rho_M slaved under strong
+// coupling, from its own lattice under weak), rho, rho u, rho E, plus a flag for
+// non-finite values or a negative density of species M.
 // --------------------------------------------------------------------------
-template <typename S, int M>
+template <typename S, int M, bool WEAK = false>
 __host__ __device__ __forceinline__ void conserved_node(const Params<double>& P, const S* __restrict__ pop,
                                                int64_t node, double* out /*[M+6]*/)
 {
   const size_t n = (size_t)P.n;
-  constexpr int LF = M - 1, LG = M;
+  constexpr int NS = Lat<M, WEAK>::NS, LF = Lat<M, WEAK>::LF, LG = Lat<M, WEAK>::LG;
   double rest = 0.0;
 #pragma unroll
-  for (int a = 0; a < M - 1; ++a) {
+  for (int a = 0; a < NS; ++a) {
     double sum = 0.0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) sum += (double)pop[(size_t)(a * Q + i) * n + node] * P.inv_scale[a];
@@ -905,7 +968,7 @@ __host__ __device__ __forceinline__ void conserved_node(const Params<double>& P,
   }
   rho += P.ref0[LF];
   rhoE += P.ref0[LG];
-  out[M - 1] = rho - rest;
+  if constexpr (!WEAK) out[M - 1] = rho - rest;
   out[M] = rho;
   out[M + 1] = j[0];
   out[M + 2] = j[1];
@@ -917,30 +980,32 @@ __host__ __device__ __forceinline__ void conserved_node(const Params<double>& P,
   out[M + 5] = ok ? 0.0 : 1.0;
 }
 
-// Moles of every species at a node, rho_a / m_a (R_U = 1; the slaved species from
-// the deficit, eq rhoMATCH), in slot [h][a] of out[2 M], h = 0 for x < nx / 2 and
+// Moles of every species at a node, rho_a / m_a (R_U = 1; under strong coupling
+// the slaved species from the deficit, eq rhoMATCH), in slot [h][a] of out[2 M], h = 0 for x < nx / 2 and
 // h = 1 otherwise (the other half's slots zero): summed over a tube, the moles in
 // each half of a Loschmidt tube, whose ratios are the half-tube mean mole
 // fractions of Sec. 4.2.
-template <typename S, int M>
+template <typename S, int M, bool WEAK = false>
 __host__ __device__ __forceinline__ void half_moles_node(const Params<double>& P, const S* __restrict__ pop,
                                                 int64_t node, double* out /*[2 M]*/)
 {
   const size_t n = (size_t)P.n;
-  constexpr int LF = M - 1;
+  constexpr int NS = Lat<M, WEAK>::NS, LF = Lat<M, WEAK>::LF;
   double rho_a[M], rest = 0.0;
 #pragma unroll
-  for (int a = 0; a < M - 1; ++a) {
+  for (int a = 0; a < NS; ++a) {
     double sum = 0.0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) sum += (double)pop[(size_t)(a * Q + i) * n + node] * P.inv_scale[a];
     rho_a[a] = P.ref0[a] + sum;
     rest += rho_a[a];
   }
-  double rho = 0.0;
+  if constexpr (!WEAK) {
+    double rho = 0.0;
 #pragma unroll
-  for (int i = 0; i < Q; ++i) rho += (double)pop[(size_t)(LF * Q + i) * n + node] * P.inv_scale[LF];
-  rho_a[M - 1] = rho + P.ref0[LF] - rest;
+    for (int i = 0; i < Q; ++i) rho += (double)pop[(size_t)(LF * Q + i) * n + node] * P.inv_scale[LF];
+    rho_a[M - 1] = rho + P.ref0[LF] - rest;
+  }
   const int h = (int)(node % P.nx) >= P.nx / 2 ? 1 : 0;
 #pragma unroll
   for (int a = 0; a < M; ++a) {

@@ -30,10 +30,12 @@ inline double wilke_phi(const HostSpecies& h, int a, int b)
 }
 
 // Reference populations of every stored lattice at the mean state, zero
-// velocity: species rho_a Psi(0, R_a T), momentum rho Psi(0, R T), energy the
-// energy-lattice equilibrium with zero flux. All are symmetric under c -> -c.
-inline void reference_tables(const HostSpecies& h, const RefState& rs, double ref[MAXL][Q], double ref0[MAXL],
-                             double ref2[MAXL])
+// velocity: species rho_a Psi(0, R_a T) for the ns stored species (M-1 under
+// strong coupling, M under weak), momentum rho Psi(0, R T) at lattice ns, energy
+// the energy-lattice equilibrium with zero flux at ns + 1. All are symmetric
+// under c -> -c.
+inline void reference_tables(const HostSpecies& h, int ns, const RefState& rs, double ref[MAXL][Q],
+                             double ref0[MAXL], double ref2[MAXL])
 {
   const int M = h.M;
   double mmix = 0.0;
@@ -47,8 +49,8 @@ inline void reference_tables(const HostSpecies& h, const RefState& rs, double re
     Trip<double> t = psi_trip<double>(0.0, zeta);
     for (int i = 0; i < Q; ++i) ref[l][i] = dens * t(cx(i)) * t(cy(i)) * t(cz(i));
   };
-  for (int a = 0; a < M - 1; ++a) fill_psi(a, rho * rs.X[a] * h.m[a] / mmix, rs.T / h.m[a]);
-  fill_psi(M - 1, rho, Rg * rs.T);
+  for (int a = 0; a < ns; ++a) fill_psi(a, rho * rs.X[a] * h.m[a] / mmix, rs.T / h.m[a]);
+  fill_psi(ns, rho, Rg * rs.T);
   {
     const double theta = Rg * rs.T;
     const double rhoE = rho * Cv * rs.T;
@@ -60,10 +62,10 @@ inline void reference_tables(const HostSpecies& h, const RefState& rs, double re
       double bz = 0.0;
       if (csq(i) == 0) bz = 3.0 * zf * rt2;
       if (csq(i) == 1) bz = -0.5 * zf * rt2;
-      ref[M][i] = w * (rhoE + rt2 * (csq(i) - 3.0 * theta) * 0.5 / (theta * theta)) + bz;
+      ref[ns + 1][i] = w * (rhoE + rt2 * (csq(i) - 3.0 * theta) * 0.5 / (theta * theta)) + bz;
     }
   }
-  for (int l = 0; l <= M; ++l) {
+  for (int l = 0; l <= ns + 1; ++l) {
     ref0[l] = 0.0;
     ref2[l] = 0.0;
     for (int i = 0; i < Q; ++i) {
@@ -76,7 +78,7 @@ inline void reference_tables(const HostSpecies& h, const RefState& rs, double re
 // Fill a parameter block. scale[l] multiplies stored deviations (1 for FP64 and
 // FP32 storage; a range-fitting factor for 16-bit storage).
 template <typename R>
-inline void fill_params(Params<R>& P, const HostSpecies& h, int nx, int ny, int nz, int wall_x,
+inline void fill_params(Params<R>& P, const HostSpecies& h, int nx, int ny, int nz, int wall_x, int L,
                         const double ref[MAXL][Q], const double ref0[MAXL], const double ref2[MAXL],
                         const double scale[MAXL], double absent_tol)
 {
@@ -100,7 +102,7 @@ inline void fill_params(Params<R>& P, const HostSpecies& h, int nx, int ny, int 
       P.phi[a][b] = R(wilke_phi(h, a, b));
     }
   }
-  for (int l = 0; l <= h.M; ++l) {
+  for (int l = 0; l < L; ++l) {
     for (int i = 0; i < Q; ++i) P.ref[l][i] = R(ref[l][i]);
     P.ref0[l] = R(ref0[l]);
     P.ref2[l] = R(ref2[l]);

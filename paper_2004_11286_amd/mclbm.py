@@ -53,7 +53,7 @@ NN_EXPORTS = ["mclbm_nn_workspace_bytes", "mclbm_nn_create", "mclbm_nn_destroy",
 class mclbm_params(C.Structure):
     _fields_ = [
         ("M", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
-        ("wall_x", C.c_int32), ("precision", C.c_int32), ("reserved0", C.c_int32),
+        ("wall_x", C.c_int32), ("precision", C.c_int32), ("weak", C.c_int32),
         ("reserved1", C.c_int32),
         ("molar_mass", C.POINTER(C.c_double)), ("cv", C.POINTER(C.c_double)),
         ("D", C.POINTER(C.c_double)), ("mu", C.POINTER(C.c_double)),
@@ -158,13 +158,14 @@ def _f64(a) -> np.ndarray:
 
 
 def make_params(params: dict, precision: int):
-    """mclbm_params from a workload dict; returns (struct, arrays kept alive)."""
+    """mclbm_params from a workload dict (``weak``: 1 for weak coupling, default 0);
+    returns (struct, arrays kept alive)."""
     M = int(params["M"])
     arrs = [_f64(params["molar_mass"]), _f64(params["cv"]), _f64(params["D"]).reshape(M * M),
             _f64(params["mu"]), _f64(params["lambda"])]
     dp = C.POINTER(C.c_double)
     p = mclbm_params(M, int(params["nx"]), int(params["ny"]), int(params["nz"]),
-                     int(params.get("wall_x", 0)), int(precision), 0, 0,
+                     int(params.get("wall_x", 0)), int(precision), int(params.get("weak", 0)), 0,
                      *[a.ctypes.data_as(dp) for a in arrs])
     return p, arrs
 

@@ -6,13 +6,16 @@ import numpy as np
 FIELDS = ("X", "rho", "u", "p", "T")
 
 # Checkpoint written by mclbm_save (see mclbm.hip): a header (magic[8], M,
-# wall_x, precision, ntubes as int32, int64 step count), then per tube its size
-# and reference tables, then the stored populations of all tubes.
+# wall_x, precision, ntubes, weak, pad as int32, int64 step count), then per tube
+# its size and reference tables (10 lattices: up to 8 species, f, g), then the
+# stored populations of all tubes (M-1 species lattices under strong coupling,
+# M under weak coupling, then f and g).
+_MAXL = 10
 _HDR = np.dtype([("magic", "S8"), ("M", "<i4"), ("wall_x", "<i4"), ("precision", "<i4"),
-                 ("ntubes", "<i4"), ("steps", "<i8")])
+                 ("ntubes", "<i4"), ("weak", "<i4"), ("pad", "<i4"), ("steps", "<i8")])
 _TUBE = np.dtype([("nx", "<i4"), ("ny", "<i4"), ("nz", "<i4"), ("pad", "<i4"),
-                  ("ref", "<f8", (9, 27)), ("ref0", "<f8", (9,)), ("ref2", "<f8", (9,)),
-                  ("scale", "<f8", (9,))])
+                  ("ref", "<f8", (_MAXL, 27)), ("ref0", "<f8", (_MAXL,)), ("ref2", "<f8", (_MAXL,)),
+                  ("scale", "<f8", (_MAXL,))])
 _STORE = {0: np.float64, 1: np.float32, 2: np.float32, 3: np.float16}
 
 
@@ -30,10 +33,11 @@ def decode_checkpoint(buf, tube: int = 0) -> tuple[dict, np.ndarray]:
     """Header dict of one tube and its stored values as an array [L][27][nz][ny][nx]."""
     h = np.frombuffer(buf, dtype=_HDR, count=1)[0]
     M, prec, ntubes = int(h["M"]), int(h["precision"]), int(h["ntubes"])
+    L = M + 2 if int(h["weak"]) else M + 1
     tubes = np.frombuffer(buf, dtype=_TUBE, count=ntubes, offset=_HDR.itemsize)
     sizes = [int(t["nx"]) * int(t["ny"]) * int(t["nz"]) for t in tubes]
-    start = (M + 1) * 27 * sum(sizes[:tube])
-    count = (M + 1) * 27 * sizes[tube]
+    start = L * 27 * sum(sizes[:tube])
+    count = L * 27 * sizes[tube]
     off = _HDR.itemsize + _TUBE.itemsize * ntubes
     if prec == 4:
         raw = np.frombuffer(buf, dtype=np.uint16, offset=off, count=start + count)[start:]
@@ -43,7 +47,7 @@ def decode_checkpoint(buf, tube: int = 0) -> tuple[dict, np.ndarray]:
     t = tubes[tube]
     hdr = {k: h[k] for k in _HDR.names}
     hdr.update({k: t[k] for k in _TUBE.names})
-    return hdr, vals.reshape(M + 1, 27, int(t["nz"]), int(t["ny"]), int(t["nx"]))
+    return hdr, vals.reshape(L, 27, int(t["nz"]), int(t["ny"]), int(t["nx"]))
 
 
 def oracle_window(hdr: dict, vals: np.ndarray, center, radius: int) -> np.ndarray:
@@ -51,6 +55,7 @@ def oracle_window(hdr: dict, vals: np.ndarray, center, radius: int) -> np.ndarra
     in the oracle's layout [(M+2)][27][w][w][w]; the slaved species' lattice
     (never read under strong coupling) is left at zero."""
     M = int(hdr["M"])
+    L = vals.shape[0]
     nz, ny, nx = vals.shape[2:]
     x0, y0, z0 = center
     ix = np.arange(x0 - radius, x0 + radius + 1) % nx
@@ -58,9 +63,10 @@ def oracle_window(hdr: dict, vals: np.ndarray, center, radius: int) -> np.ndarra
     iz = np.arange(z0 - radius, z0 + radius + 1) % nz
     w = 2 * radius + 1
     out = np.zeros((M + 2, 27, w, w, w))
-    sub = vals[np.ix_(np.arange(M + 1), np.arange(27), iz, iy, ix)].astype(np.float64)
-    for l in range(M + 1):
+    sub = vals[np.ix_(np.arange(L), np.arange(27), iz, iy, ix)].astype(np.float64)
+    for l in range(L):
         f = hdr["ref"][l][:, None, None, None] + sub[l] / hdr["scale"][l]
-        dst = l if l < M - 1 else l + 1          # GPU lattices: species 1..M-1, f, g
+        # GPU lattices: species 1..M-1 (1..M under weak coupling), f, g
+        dst = l if (L == M + 2 or l < M - 1) else l + 1
         out[dst] = f
     return out

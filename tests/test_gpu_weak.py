@@ -1,0 +1,216 @@
+"""GPU parity of weak coupling (Sec. 3.6.1) against the oracle, through the C ABI.
+
+Weak coupling stores and evolves all M species lattices; the species subsystem
+keeps its own density and velocity (eqs rhoSPEC, uSPEC) and Dalton pressure and
+takes T from the energy lattice. The oracle's weak mode is pinned on the CPU
+(tests/test_oracle_weak.py). Here the GPU path is compared with it: fields and
+every stored population (FP64, ragged grids, all M, with and without walls), the
+conservation sums, FP32 storage over 1000 steps, and windows of the full-size
+shear layer.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import FIELDS, decode_checkpoint, field_errors, oracle_window
+from paper_2004_11286_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mc():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2004_11286_amd import mclbm
+
+    return mclbm
+
+
+def _case(M, nx, ny, nz, walls, seed):
+    if M == 2:
+        params, _ = W.binary_interdiffusion(nx=nx, ny=ny, nz=nz)
+        X0 = [0.4, 0.6]
+    elif M == 3:
+        params, _ = W.ternary_tube(nx=nx, ny=ny, nz=nz)
+        X0 = [0.3, 0.3, 0.4]
+    else:
+        params, _ = W.ternary_tube(nx=nx, ny=ny, nz=nz, masses=(2.0, 16.0, 28.0, 40.0),
+                                   x_left=(0.2, 0.2, 0.1, 0.5), x_right=(0.1, 0.2, 0.2, 0.5),
+                                   Doff={(0, 1): 0.08, (0, 2): 0.07, (0, 3): 0.06, (1, 2): 0.03,
+                                         (1, 3): 0.02, (2, 3): 0.04})
+        X0 = [0.2, 0.2, 0.15, 0.45]
+    params = dict(params, wall_x=int(walls), weak=1)
+    f = W.random_near_equilibrium(params, nx, ny, nz, seed=seed, X0=X0, p0=params["P0"], T0=0.3,
+                                  amp=0.05, uamp=0.03)
+    return params, f
+
+
+def _populations(hdr, vals):
+    """Absolute populations [(M+2)][27][nz][ny][nx] of a weakly coupled checkpoint."""
+    L = vals.shape[0]
+    return np.stack([hdr["ref"][l][:, None, None, None] + vals[l].astype(np.float64) / hdr["scale"][l]
+                     for l in range(L)])
+
+
+@pytest.mark.parametrize("M", [2, 3, 4])
+@pytest.mark.parametrize("walls", [0, 1])
+def test_weak_ragged_grid_fp64(mc, oracle_mod, M, walls):
+    """13 x 7 x 5 nodes (not a multiple of the 256-thread block), 20 steps in FP64:
+    fields, conservation sums and every stored population (species M's own lattice
+    included) against the oracle; the result differs from strong coupling's."""
+    params, f = _case(M, 13, 7, 5, walls, seed=31 + 2 * M + walls)
+    s = mc.Sim(params, mc.MCLBM_FP64)
+    s.init_fields(**f)
+    s.step(20)
+    g, gc = s.read_moments(), s.conservation()
+    hdr, vals = decode_checkpoint(s.save())
+    s.close()
+    assert int(hdr["weak"]) == 1 and vals.shape[0] == M + 2
+    o = oracle_mod.OracleSim(params)
+    o.init_fields(**f)
+    o.step(20)
+    om, oc, op = o.read_moments(), o.conservation(), o.populations()
+    errs = field_errors(g, om)
+    pop_err = float(np.abs(_populations(hdr, vals) - op).max() / np.abs(op).max())
+    print("weak fp64", M, walls, errs, "populations", pop_err)
+    for k in FIELDS:
+        assert errs[k] < 1e-12, (k, errs[k])
+    assert pop_err < 1e-12
+    np.testing.assert_allclose(gc[:M + 1], oc[:M + 1], rtol=1e-12)
+    np.testing.assert_allclose(gc[M + 4], oc[M + 4], rtol=1e-12)
+    strong = mc.Sim(dict(params, weak=0), mc.MCLBM_FP64)
+    strong.init_fields(**f)
+    strong.step(20)
+    gs = strong.read_moments()
+    strong.close()
+    assert np.abs(gs["X"] - g["X"]).max() > 1e-9
+
+
+def test_weak_species_momentum_conserved_fp64(mc, oracle_mod):
+    """Periodic ternary, 200 steps: the species' total momentum sum_a j_a (from
+    the GPU's stored species populations) is conserved, as the weakly coupled
+    system requires, and equals the momentum lattice's from the consistent start."""
+    params, f = _case(3, 12, 6, 5, 0, seed=5)
+    s = mc.Sim(params, mc.MCLBM_FP64)
+    s.init_fields(**f)
+    c = oracle_mod.velocities()
+
+    def species_momentum():
+        hdr, vals = decode_checkpoint(s.save())
+        P = _populations(hdr, vals)
+        return np.array([np.sum(P[:3] * c[None, :, k, None, None, None]) for k in range(3)])
+
+    j0 = species_momentum()
+    c0 = s.conservation()
+    s.step(200)
+    j1 = species_momentum()
+    c1 = s.conservation()
+    s.close()
+    scale = c0[3]
+    print("species momentum", j0, j1, "momentum lattice", c1[4:7])
+    np.testing.assert_allclose(j1, j0, atol=1e-13 * scale)
+    np.testing.assert_allclose(j1, c1[4:7], atol=1e-12 * scale)
+
+
+@pytest.fixture(scope="module")
+def weak_tube_1000(oracle_mod):
+    params, f = W.ternary_tube()
+    params = dict(params, weak=1)
+    o = oracle_mod.OracleSim(params)
+    o.init_fields(**f)
+    o.step(1000)
+    return params, f, o.read_moments()
+
+
+def test_weak_ternary_tube_fp32_1000_steps(mc, weak_tube_1000):
+    """256 x 4 x 4 tube with walls, FP32 storage, FP64 collision, 1000 steps."""
+    params, f, o = weak_tube_1000
+    s = mc.Sim(params, mc.MCLBM_FP32)
+    s.init_fields(**f)
+    s.step(1000)
+    g = s.read_moments()
+    s.close()
+    errs = field_errors(g, o)
+    print("weak C2 fp32 1000", errs)
+    for k in FIELDS:
+        assert errs[k] < 1e-5, (k, errs[k])
+
+
+def test_weak_full_size_shear_layer_windows(mc, oracle_mod):
+    """The 256^3 shear layer under weak coupling, FP32 storage: the GPU state after
+    20 steps, cut into 9^3 periodic windows around sampled nodes (all four stored
+    lattices), advanced one step by the oracle, matches the GPU's step 21 at the
+    window centres; the masses and the energy are conserved at full size."""
+    params, f = W.shear_layer()
+    params = dict(params, weak=1)
+    s = mc.Sim(params, mc.MCLBM_FP32)
+    s.init_fields(**f)
+    c0 = s.conservation()
+    s.step(20)
+    hdr, vals = decode_checkpoint(s.save())
+    s.step(1)
+    g = s.read_moments()
+    c1 = s.conservation()
+    s.close()
+    M = params["M"]
+    np.testing.assert_allclose(c1[:M + 1], c0[:M + 1], rtol=1e-6)
+    np.testing.assert_allclose(c1[M + 4], c0[M + 4], rtol=1e-6)
+    worst = {k: 0.0 for k in FIELDS}
+    rng = np.random.default_rng(9)
+    centers = [(0, 0, 0), (255, 64, 128), (17, 63, 200)]
+    centers += [tuple(int(v) for v in rng.integers(0, 256, 3)) for _ in range(4)]
+    r = 4
+    for (x, y, z) in centers:
+        win = oracle_window(hdr, vals, (x, y, z), r)
+        wp = dict(params, nx=2 * r + 1, ny=2 * r + 1, nz=2 * r + 1, wall_x=0)
+        o = oracle_mod.OracleSim(wp)
+        o.set_populations(win)
+        o.step(1)
+        om = o.read_moments()
+        for k in FIELDS:
+            ov = om[k][..., r, r, r]
+            gv = g[k][..., z, y, x]
+            scale = max(np.abs(f[k]).max(), 1e-3) if k == "u" else np.abs(ov).max()
+            worst[k] = max(worst[k], float(np.abs(gv - ov).max() / scale))
+            assert np.abs(gv - ov).max() <= 1e-6 * scale, (k, (x, y, z), gv, ov)
+    print("weak fp32 worst window error", worst)
+
+
+def test_weak_half_tube_moles_fp64(mc, oracle_mod):
+    """Half-tube moles of a walled ternary tube under weak coupling (every species
+    from its own lattice) against the oracle's species densities."""
+    params, f = W.ternary_tube(nx=64, ny=2, nz=2)
+    params = dict(params, weak=1)
+    s = mc.Sim(params, mc.MCLBM_FP64)
+    s.init_fields(**f)
+    s.step(200)
+    h = s.half_tube_moles()
+    s.close()
+    o = oracle_mod.OracleSim(params)
+    o.init_fields(**f)
+    o.step(200)
+    rho_a = o.populations()[:3].sum(axis=1)
+    n_a = rho_a / np.asarray(params["molar_mass"])[:, None, None, None]
+    half = params["nx"] // 2
+    want = np.stack([n_a[..., :half].sum(axis=(1, 2, 3)), n_a[..., half:].sum(axis=(1, 2, 3))])
+    print("weak half-tube moles", h.tolist(), want.tolist())
+    assert np.abs(h - want).max() <= 1e-12 * np.abs(want).max()
+
+
+def test_weak_checkpoint_resume_is_bitwise(mc):
+    params, f = W.ternary_tube(nx=64)
+    params = dict(params, weak=1)
+    s = mc.Sim(params, mc.MCLBM_FP32)
+    s.init_fields(**f)
+    s.step(15)
+    buf = s.save()
+    s.step(10)
+    a = s.read_moments()
+    s.load(buf)
+    s.step(10)
+    b = s.read_moments()
+    s.close()
+    for k in FIELDS:
+        np.testing.assert_array_equal(a[k], b[k])
