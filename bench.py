@@ -28,22 +28,24 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
 PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = ["lattice.hpp", "node_ops.hpp", "device_ops.hpp", "kernels.hpp", "inst_fp64.hip",
-                  "inst_fp32_fp64.hip", "inst_fp32.hip", "inst_fp16.hip", "inst_bf16.hip"]
+                  "inst_fp32_fp64.hip", "inst_weak.hip", "inst_fp32.hip", "inst_fp16.hip", "inst_bf16.hip"]
 
 
-def record_fields(M: int) -> int:
-    """Node record: Phi (3), omega, C_p, rho, u (3), T, omega_1, q_neq (3), rho_a (M-1), V_a (3 M)."""
-    return 14 + (M - 1) + 3 * M
+def record_fields(M: int, weak: bool = False) -> int:
+    """Node record: Phi (3), omega, C_p, rho, u (3), T, omega_1, q_neq (3), rho_a (M-1;
+    M under weak coupling), V_a (3 M), and under weak coupling u_s (3)."""
+    return 14 + (M if weak else M - 1) + 3 * M + (3 if weak else 0)
 
 
-def algorithmic_bytes(M: int, s_bytes: int, r_bytes: int) -> dict:
+def algorithmic_bytes(M: int, s_bytes: int, r_bytes: int, weak: bool = False) -> dict:
     """Bytes each kernel must move per node, every value read or written once:
     k_moments reads the populations and writes the record; k_gfield reads Phi and
     omega and writes G; k_collide reads the populations, the record except Phi,
-    and G, and writes the populations."""
-    L = M + 1
+    and G, and writes the populations. Stored lattices: M + 1 (strong coupling),
+    M + 2 (weak)."""
+    L = M + 2 if weak else M + 1
     pops = L * 27 * s_bytes
-    rec = record_fields(M) * r_bytes
+    rec = record_fields(M, weak) * r_bytes
     return {
         "k_moments": pops + rec,
         "k_gfield": 4 * r_bytes + 3 * r_bytes,
@@ -350,6 +352,24 @@ def main():
             del v
             torch.cuda.empty_cache()
 
+    weak = None
+    if not args.no_variants:
+        # weak coupling (all M species lattices evolved) on the same workload: a
+        # different model from strong coupling, so its fields are not compared
+        wp = dict(params, weak=1)
+        v, el, st = time_run(mc, wp, fields, prec, args.steps, args.warmup)
+        wab = algorithmic_bytes(M, sb, rb, weak=True)
+        wcol = st["k_collide"]["avg_ms"]
+        wgbs = wab["k_collide"] * n / (wcol * 1e-3) / 1e9
+        weak = {"MLUPS": n * args.steps / el / 1e6, "ms_per_step": el / args.steps * 1e3,
+                "stored_lattices": M + 2, "launch": v.launch(), "collide_avg_ms": wcol,
+                "collide_algorithmic_bytes_per_node": wab["k_collide"], "collide_GBs": wgbs,
+                "collide_frac_of_hbm_peak": wgbs / HBM_PEAK_GBS,
+                "kernels_avg_ms": {k: x["avg_ms"] for k, x in st.items()}}
+        v.close()
+        del v
+        torch.cuda.empty_cache()
+
     ensemble = None if args.no_ensemble else ensemble_bench(mc)
     surrogate = None if args.no_surrogate else surrogate_bench(args.surrogate_iters)
     cpu = None if args.no_cpu else cpu_baseline()
@@ -382,6 +402,7 @@ def main():
                                "method_min_bytes_per_node": ab["method_min"],
                                "method_min_frac": ab["method_min"] * mlups * 1e6 / 1e9 / HBM_PEAK_GBS},
         "variants": variants,
+        "weak_coupling": weak,
         "ensemble": ensemble,
         "surrogate": surrogate,
         "cpu_baseline": cpu,

@@ -169,18 +169,21 @@ int mclbm_kernel_stats(mclbm_ctx *c, int32_t kernel, double *total_ms, int64_t *
  * storage, to the stochastic rounding that such a last-bit difference can flip).
  * Only the time differs. */
 typedef struct {
-  int32_t variant;      /* occupancy variant of the moments and collide kernels, 0 or 1 */
+  int32_t variant;      /* occupancy variant of the moments kernel, and of the fused
+                           collide kernel (split = 0), 0 or 1                           */
   int32_t swizzle;      /* 1: each XCD takes a contiguous run of blocks                  */
   int32_t order;        /* 0: tubes in the given order; 1: longest tube first            */
   int32_t graph_steps;  /* 0: launch each kernel of each step; K > 0 (even): replay a
                            HIP graph of K captured steps (not while timing is enabled)   */
   int32_t sequential;   /* 1: launch every tube on its own (the unbatched reference)     */
   int32_t split;        /* 1: collide the species lattices, then the momentum and energy
-                           lattices, in two launches with fewer registers each
-                           (occupancy variant 0)                                        */
+                           lattices, in two launches with fewer registers each (one
+                           occupancy form)                                              */
   int32_t reserved[2];  /* must be 0                                                     */
 } mclbm_launch;
 
+/* A new context starts with every field 0, except under weak coupling, which
+ * starts with variant = 1 and split = 1 (faster with the extra stored lattice). */
 int mclbm_get_launch(const mclbm_ctx *c, mclbm_launch *out);
 int mclbm_set_launch(mclbm_ctx *c, const mclbm_launch *in);
 

@@ -135,7 +135,7 @@ def test_autotune_picks_a_choice_and_keeps_the_trajectory(mc):
     print(rep)
     lines = rep.strip().splitlines()
     assert lines[-1].startswith("chosen")
-    assert len(lines) == 1 + 24 + 1                          # header, 3 x 2 x 2 x 2 candidates, choice
+    assert len(lines) == 1 + 32 + 1                          # header, 4 x 2 x 2 x 2 candidates, choice
     chosen = [int(v) for v in lines[-1].split()[1:6]]
     lc = b.launch()
     assert [lc["variant"], lc["split"], lc["swizzle"], lc["order"], lc["graph_steps"]] == chosen
@@ -240,9 +240,10 @@ def test_batch_checkpoint_resume_is_bitwise(mc):
 def test_launch_arguments_are_checked(mc):
     tubes = small_ensemble(n=2, seed=14)
     b = mc.Batch([p for p, _ in tubes], mc.MCLBM_FP32)
-    for bad in (dict(variant=2), dict(graph_steps=3), dict(swizzle=2), dict(split=1, variant=1), dict(order=2)):
+    for bad in (dict(variant=2), dict(graph_steps=3), dict(swizzle=2), dict(split=2), dict(order=2)):
         with pytest.raises(mc.MclbmError):
             b.set_launch(**bad)
+    b.set_launch(variant=1, split=1)
     b.set_launch(variant=0, split=0)
     b.close()
 

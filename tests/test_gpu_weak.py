@@ -214,3 +214,28 @@ def test_weak_checkpoint_resume_is_bitwise(mc):
     s.close()
     for k in FIELDS:
         np.testing.assert_array_equal(a[k], b[k])
+
+
+def test_weak_launch_choices_agree(mc):
+    """A weakly coupled context starts with the split collision and the
+    higher-occupancy moments kernel; every launch choice computes the same step
+    (the split to rounding: its kernels are compiled separately)."""
+    params, f = _case(3, 13, 7, 5, 1, seed=3)
+    out = []
+    for launch in (None, dict(variant=0, split=0), dict(variant=1, split=0), dict(variant=0, split=1)):
+        s = mc.Sim(params, mc.MCLBM_FP64)
+        if launch is None:
+            lc = s.launch()
+            assert lc["variant"] == 1 and lc["split"] == 1
+        else:
+            s.set_launch(**launch)
+        s.init_fields(**f)
+        s.step(20)
+        out.append(s.read_moments())
+        s.close()
+    for got in out[1:]:
+        for k in FIELDS:
+            scale = max(np.abs(out[0][k]).max(), 1e-3 if k == "u" else 0.0)
+            assert np.abs(got[k] - out[0][k]).max() <= 1e-13 * scale, k
+    for k in FIELDS:
+        np.testing.assert_array_equal(out[1][k], out[2][k])      # fused forms: bitwise
