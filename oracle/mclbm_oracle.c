@@ -11,8 +11,9 @@
  *   1. moments of every lattice; strong coupling slaves species M to the
  *      momentum lattice (Sec. 3.6.2, eqs rhoMATCH, uMATCH); weak coupling
  *      (Sec. 3.6.1) evolves every species lattice with its own conservation law;
- *      temperature from the energy lattice with constant specific heats
- *      (eq temperature2, T_0=0);
+ *      temperature from the energy lattice: with constant specific heats in
+ *      closed form (eq temperature2, T_0=0), with specific heats polynomial in T
+ *      by Newton's method on eq temperature;
  *   2. mixture viscosity (Wilke, eq viscosityMixture) and conductivity (Mathur,
  *      eq conductivityMixture), relaxation rates omega, omega_1 (eqs omega, omega1);
  *   3. the non-local terms at the same time level: the isotropy correction X
@@ -174,6 +175,8 @@ struct oracle_sim {
   int M, nx, ny, nz, wall_x, keep_slaved, weak, flags;
   long n;
   double m[MAXM], cv[MAXM], D[MAXM][MAXM], mu[MAXM], lam[MAXM];
+  int cvt;                 /* 1: C_{a,v}(T) = sum_k cvc[a][k] T^k, else the constant cv[a] */
+  double cvc[MAXM][4];
   double *pop;   /* [(M+2)][Q][n] pre-collision populations */
   double *post;  /* [(M+2)][Q][n] post-collision populations */
   /* node fields used by the non-local terms */
@@ -232,9 +235,19 @@ int oracle_create(const oracle_params *p, oracle_sim **out)
   s->keep_slaved = (p->keep_slaved || s->weak) ? 1 : 0;   /* weak coupling evolves every species */
   s->flags = p->debug_flags;
   s->n = (long)p->nx * p->ny * p->nz;
+  s->cvt = p->cv_coef ? 1 : 0;
   for (int a = 0; a < s->M; ++a) {
     s->m[a] = p->molar_mass[a];
     s->cv[a] = p->cv[a];
+    if (s->cvt) {
+      for (int k = 0; k < 4; ++k) {
+        s->cvc[a][k] = p->cv_coef[a * 4 + k];
+        if (!(k == 0 ? s->cvc[a][k] > 0 : s->cvc[a][k] >= 0)) {
+          free(s);
+          return -1;
+        }
+      }
+    }
     s->mu[a] = p->mu[a];
     s->lam[a] = p->lambda[a];
     if (!(s->m[a] > 0) || !(s->cv[a] > 0) || !(s->mu[a] > 0) || !(s->lam[a] > 0)) {
@@ -293,6 +306,41 @@ static double wilke_phi(const oracle_sim *s, int a, int b)
   return num * num / (sqrt(8.0) * sqrt(1.0 + s->m[a] / s->m[b]));
 }
 
+/* Specific heat of species a at temperature T (polynomial case), and its
+ * internal energy U_a(T), the integral of C_{a,v} from T_0 = 0 (eq specUa). */
+static double species_cv(const oracle_sim *s, int a, double T)
+{
+  const double *c = s->cvc[a];
+  return c[0] + c[1] * T + c[2] * T * T + c[3] * T * T * T;
+}
+
+static double species_U(const oracle_sim *s, int a, double T)
+{
+  const double *c = s->cvc[a];
+  return c[0] * T + c[1] * T * T / 2.0 + c[2] * T * T * T / 3.0 + c[3] * T * T * T * T / 4.0;
+}
+
+/* Temperature from eq temperature, sum_a Y_a U_a(T) = e, by Newton's method:
+ * U is increasing and convex for c_0 > 0, c_k >= 0, so the iteration started at
+ * e / sum_a Y_a c_a0 (an upper bound) decreases monotonically to the root. */
+static double solve_temperature(const oracle_sim *s, const double *Y, double e)
+{
+  double c0 = 0.0;
+  for (int a = 0; a < s->M; ++a) c0 += Y[a] * s->cvc[a][0];
+  double T = e / c0;
+  for (int it = 0; it < 100; ++it) {
+    double U = 0.0, Cv = 0.0;
+    for (int a = 0; a < s->M; ++a) {
+      U += Y[a] * species_U(s, a, T);
+      Cv += Y[a] * species_cv(s, a, T);
+    }
+    double dT = (U - e) / Cv;
+    T -= dT;
+    if (fabs(dT) <= 1e-15 * fabs(T)) break;
+  }
+  return T;
+}
+
 static void node_state(const oracle_sim *s, const double *pop, long node, state_t *st)
 {
   const int M = s->M;
@@ -346,19 +394,30 @@ static void node_state(const oracle_sim *s, const double *pop, long node, state_
   st->mmix = 1.0 / inv_m;
   for (int a = 0; a < M; ++a) st->X[a] = (st->mmix / s->m[a]) * st->Y[a];
   st->R = 1.0 / st->mmix;                                /* eq defineSpecificGasContant */
-  /* caloric properties, Sec. 3.1 with constant C_{a,v} and C_{a,p} = C_{a,v} + R_a */
-  for (int a = 0; a < M; ++a) {
-    st->Cv += st->Y[a] * s->cv[a];
-    st->Cp += st->Y[a] * (s->cv[a] + 1.0 / s->m[a]);
-  }
   double usq = st->u[0] * st->u[0] + st->u[1] * st->u[1] + st->u[2] * st->u[2];
-  st->T = (st->rhoE / st->rho - usq / 2.0) / st->Cv;     /* eq temperature2, T_0 = 0 */
+  if (s->cvt) {
+    /* specific heats polynomial in T: eq temperature, then eq Cvmix at that T */
+    st->T = solve_temperature(s, st->Y, st->rhoE / st->rho - usq / 2.0);
+    for (int a = 0; a < M; ++a) st->Cv += st->Y[a] * species_cv(s, a, st->T);
+    st->Cp = st->Cv + st->R;                             /* Mayer */
+  } else {
+    /* caloric properties, Sec. 3.1 with constant C_{a,v} and C_{a,p} = C_{a,v} + R_a */
+    for (int a = 0; a < M; ++a) {
+      st->Cv += st->Y[a] * s->cv[a];
+      st->Cp += st->Y[a] * (s->cv[a] + 1.0 / s->m[a]);
+    }
+    st->T = (st->rhoE / st->rho - usq / 2.0) / st->Cv;   /* eq temperature2, T_0 = 0 */
+  }
   st->P = st->rho * st->R * st->T;                       /* eq eosIdealGas */
   /* pressure of the species subsystem in its friction terms: P under strong
    * coupling, sum_a rho_a R_a T of the species' own densities under weak */
   st->Ps = (s->weak && !(s->flags & ORACLE_WEAK_MIXTURE_P)) ? rho_sp * st->R * st->T : st->P;
   for (int a = 0; a < M; ++a) {
-    st->Ha[a] = (s->cv[a] + 1.0 / s->m[a]) * st->T;      /* eq specHa */
+    if (s->cvt && (s->flags & ORACLE_CVT_HA_CPT))
+      st->Ha[a] = (species_cv(s, a, st->T) + 1.0 / s->m[a]) * st->T;
+    else if (s->cvt)
+      st->Ha[a] = species_U(s, a, st->T) + st->T / s->m[a];            /* eq specHa */
+    else st->Ha[a] = (s->cv[a] + 1.0 / s->m[a]) * st->T;
     st->H += st->Y[a] * st->Ha[a];                       /* eq specH */
   }
   /* transport, eqs viscosityMixture and conductivityMixture */
@@ -785,6 +844,12 @@ int oracle_init_fields(oracle_sim *s, const double *X, const double *p, const do
     }
     double rhoE = rho * (Cv * Tn + usq / 2.0);
     double H = Cp * Tn;
+    if (s->cvt) {                              /* eqs Umix, specH with U_a(T) */
+      double U = 0.0;
+      for (int a = 0; a < M; ++a) U += Y[a] * species_U(s, a, Tn);
+      rhoE = rho * (U + usq / 2.0);
+      H = U + R * Tn;
+    }
     double psi[Q];
     for (int a = 0; a < M; ++a) {
       if (a == M - 1 && !s->keep_slaved) continue;

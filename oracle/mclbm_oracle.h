@@ -32,7 +32,8 @@ enum {
   ORACLE_DROP_UPNEQ = 8,      /* omit -u.(P - P^eq) in the quasi-equilibrium flux         */
   ORACLE_DROP_FSOURCE = 16,   /* omit the (beta_a - 1) F_ai term (eq SMlbm)               */
   ORACLE_WEAK_MIXTURE_U = 32, /* weak coupling: species relax towards the momentum lattice's u */
-  ORACLE_WEAK_MIXTURE_P = 64  /* weak coupling: friction K_ab with the momentum lattice's P  */
+  ORACLE_WEAK_MIXTURE_P = 64, /* weak coupling: friction K_ab with the momentum lattice's P  */
+  ORACLE_CVT_HA_CPT = 128     /* polynomial C_v: H_a = C_{a,p}(T) T, not the integral of eq specHa */
 };
 
 typedef struct {
@@ -48,6 +49,8 @@ typedef struct {
   const double *D;          /* [M*M] symmetric binary diffusivities, diagonal included  */
   const double *mu;         /* [M] species dynamic viscosities                          */
   const double *lambda;     /* [M] species thermal conductivities                       */
+  const double *cv_coef;    /* NULL: constant cv; else [M][4]: C_{a,v}(T) = sum_k c_k T^k,
+                               c_0 > 0, c_k >= 0 (cv is then not used)                  */
 } oracle_params;
 
 typedef struct oracle_sim oracle_sim;

@@ -27,6 +27,7 @@ DROP_UPNEQ = 8
 DROP_FSOURCE = 16
 WEAK_MIXTURE_U = 32
 WEAK_MIXTURE_P = 64
+CVT_HA_CPT = 128
 
 
 class _Params(C.Structure):
@@ -36,7 +37,7 @@ class _Params(C.Structure):
         ("weak", C.c_int32),
         ("molar_mass", C.POINTER(C.c_double)), ("cv", C.POINTER(C.c_double)),
         ("D", C.POINTER(C.c_double)), ("mu", C.POINTER(C.c_double)),
-        ("lam", C.POINTER(C.c_double)),
+        ("lam", C.POINTER(C.c_double)), ("cv_coef", C.POINTER(C.c_double)),
     ]
 
 
@@ -174,9 +175,13 @@ class OracleSim:
         self._arrays = [_f64(params["molar_mass"]), _f64(params["cv"]),
                         _f64(params["D"]).reshape(-1), _f64(params["mu"]),
                         _f64(params["lambda"])]
+        cvc = params.get("cv_coef")
+        if cvc is not None:
+            self._arrays.append(_f64(cvc).reshape(self.M * 4))
         p = _Params(self.M, self.nx, self.ny, self.nz, int(params.get("wall_x", 0)),
                     int(keep_slaved), int(debug_flags), int(params.get("weak", 0)),
-                    *[_dp(a) for a in self._arrays])
+                    *[_dp(a) for a in self._arrays[:5]],
+                    _dp(self._arrays[5]) if cvc is not None else None)
         h = C.c_void_p()
         rc = lib().oracle_create(C.byref(p), C.byref(h))
         if rc != 0:
