@@ -28,16 +28,17 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
 PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = ["lattice.hpp", "node_ops.hpp", "device_ops.hpp", "kernels.hpp", "inst_fp64.hip",
-                  "inst_fp32_fp64.hip", "inst_weak.hip", "inst_fp32.hip", "inst_fp16.hip", "inst_bf16.hip"]
+                  "inst_fp32_fp64.hip", "inst_weak.hip", "inst_cvt.hip", "inst_fp32.hip", "inst_fp16.hip", "inst_bf16.hip"]
 
 
-def record_fields(M: int, weak: bool = False) -> int:
+def record_fields(M: int, weak: bool = False, cvt: bool = False) -> int:
     """Node record: Phi (3), omega, C_p, rho, u (3), T, omega_1, q_neq (3), rho_a (M-1;
-    M under weak coupling), V_a (3 M), and under weak coupling u_s (3)."""
-    return 14 + (M if weak else M - 1) + 3 * M + (3 if weak else 0)
+    M under weak coupling), V_a (3 M), under weak coupling u_s (3), and with
+    temperature-dependent heat capacities Y_a (M-1)."""
+    return 14 + (M if weak else M - 1) + 3 * M + (3 if weak else 0) + (M - 1 if cvt else 0)
 
 
-def algorithmic_bytes(M: int, s_bytes: int, r_bytes: int, weak: bool = False) -> dict:
+def algorithmic_bytes(M: int, s_bytes: int, r_bytes: int, weak: bool = False, cvt: bool = False) -> dict:
     """Bytes each kernel must move per node, every value read or written once:
     k_moments reads the populations and writes the record; k_gfield reads Phi and
     omega and writes G; k_collide reads the populations, the record except Phi,
@@ -45,7 +46,7 @@ def algorithmic_bytes(M: int, s_bytes: int, r_bytes: int, weak: bool = False) ->
     M + 2 (weak)."""
     L = M + 2 if weak else M + 1
     pops = L * 27 * s_bytes
-    rec = record_fields(M, weak) * r_bytes
+    rec = record_fields(M, weak, cvt) * r_bytes
     return {
         "k_moments": pops + rec,
         "k_gfield": 4 * r_bytes + 3 * r_bytes,
@@ -370,6 +371,26 @@ def main():
         del v
         torch.cuda.empty_cache()
 
+    cv_of_T = None
+    if not args.no_variants:
+        # temperature-dependent heat capacities (cubic C_{a,v}(T), about twice the
+        # constant part at the shear layer's T = 1) on the same workload
+        cv = np.asarray(params["cv"], dtype=np.float64)
+        shapes = [[1.0, 0.6, 0.1, 0.3], [1.0, 0.0, 0.4, 0.0]]
+        cp_ = dict(params, cv_coef=np.stack([cv[a] * np.asarray(shapes[a]) for a in range(M)]))
+        v, el, st = time_run(mc, cp_, fields, prec, args.steps, args.warmup)
+        cab = algorithmic_bytes(M, sb, rb, cvt=True)
+        ccol = st["k_collide"]["avg_ms"]
+        cgbs = cab["k_collide"] * n / (ccol * 1e-3) / 1e9
+        cv_of_T = {"MLUPS": n * args.steps / el / 1e6, "ms_per_step": el / args.steps * 1e3,
+                   "cv_coef_shape": shapes, "collide_avg_ms": ccol,
+                   "collide_algorithmic_bytes_per_node": cab["k_collide"], "collide_GBs": cgbs,
+                   "collide_frac_of_hbm_peak": cgbs / HBM_PEAK_GBS,
+                   "kernels_avg_ms": {k: x["avg_ms"] for k, x in st.items()}}
+        v.close()
+        del v
+        torch.cuda.empty_cache()
+
     ensemble = None if args.no_ensemble else ensemble_bench(mc)
     surrogate = None if args.no_surrogate else surrogate_bench(args.surrogate_iters)
     cpu = None if args.no_cpu else cpu_baseline()
@@ -403,6 +424,7 @@ def main():
                                "method_min_frac": ab["method_min"] * mlups * 1e6 / 1e9 / HBM_PEAK_GBS},
         "variants": variants,
         "weak_coupling": weak,
+        "cv_of_T": cv_of_T,
         "ensemble": ensemble,
         "surrogate": surrogate,
         "cpu_baseline": cpu,

@@ -86,6 +86,13 @@ typedef struct {
                                 b = a)                                                 */
   const double *mu;          /* [M] species dynamic viscosities (Wilke mixing, Sec. 3.4) */
   const double *lambda;      /* [M] species thermal conductivities (Mathur mixing)    */
+  const double *cv_coef;     /* NULL: constant specific heats cv (eq temperature2). Else
+                                [M][4]: C_{a,v}(T) = sum_k c_ak T^k with c_a0 > 0 and
+                                c_ak >= 0 (k >= 1), cv unused; U_a = int_0^T C_{a,v},
+                                H_a = U_a + R_a T (eqs specUa, specHa) and T from
+                                eq temperature by Newton's method (Sec. 3.1). Strong
+                                coupling with MCLBM_FP64 or MCLBM_FP32 only (else
+                                MCLBM_EUNSUPPORTED); all tubes of a batch agree on NULL */
 } mclbm_params;
 
 /* Device workspace bytes a context with these parameters needs (0 on bad input). */

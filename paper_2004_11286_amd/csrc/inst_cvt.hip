@@ -1,0 +1,12 @@
+// inst_cvt.hip -- temperature-dependent specific heats (strong coupling): double
+// storage and arithmetic with a double record, and float storage with double
+// arithmetic and a float record.
+#include "kernels.hpp"
+
+namespace mclbm {
+bool pick_fp64_cvt(int M, int walls, kern::Ops& o) { return kern::pick_m<double, double, double, false, true>(M, walls, o); }
+bool pick_fp32_fp64_cvt(int M, int walls, kern::Ops& o)
+{
+  return kern::pick_m<float, double, float, false, true>(M, walls, o);
+}
+}  // namespace mclbm

@@ -3,9 +3,13 @@
 
 namespace mclbm {
 bool pick_fp64_weak(int M, int walls, kern::Ops& o);   // inst_weak.hip
+bool pick_fp64_cvt(int M, int walls, kern::Ops& o);    // inst_cvt.hip
 
-bool pick_fp64(int M, int walls, int weak, kern::Ops& o)
+bool pick_fp64(int M, int walls, int weak, int cvt, kern::Ops& o)
 {
-  return weak ? pick_fp64_weak(M, walls, o) : kern::pick_m<double, double, double, false>(M, walls, o);
+  if (weak && cvt) return false;
+  if (weak) return pick_fp64_weak(M, walls, o);
+  if (cvt) return pick_fp64_cvt(M, walls, o);
+  return kern::pick_m<double, double, double, false>(M, walls, o);
 }
 }  // namespace mclbm

@@ -89,15 +89,15 @@ constexpr int moment_waves() { return (M == 2 ? 2 : 1) == 2 ? 2 - V : 1 + V; }
 template <int M, bool WEAK>
 constexpr size_t pop_stride() { return (size_t)Lat<M, WEAK>::L * Q; }   // populations per node (stored lattices)
 
-template <typename S, typename Rec, int M, int V, bool WEAK>
+template <typename S, typename Rec, int M, int V, bool WEAK, bool CVT>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(moment_waves<M, V>()))) void k_moments(const Params<double>* __restrict__ P, Launch Ln, const S* __restrict__ pop,
                                                    Rec* __restrict__ rec)
 {
   const Where w = locate(Ln);
   const Params<double>& Pt = P[w.t];
   if (w.node < Pt.n)
-    state_node<S, Rec, M, WEAK>(Pt, pop + pop_stride<M, WEAK>() * w.base,
-                                rec + (size_t)RecLayout<M, WEAK>::FIELDS * w.base, w.node);
+    state_node<S, Rec, M, WEAK, CVT>(Pt, pop + pop_stride<M, WEAK>() * w.base,
+                                     rec + (size_t)RecLayout<M, WEAK, CVT>::FIELDS * w.base, w.node);
 }
 
 template <typename Rec, bool W>
@@ -114,7 +114,7 @@ __global__ __launch_bounds__(BLOCK) void k_gfield(const Params<double>* __restri
 template <typename S, int M, int V, int PART>
 constexpr int collide_part_waves() { return PART == 0 ? collide_waves<S, M, V>() : 2; }
 
-template <typename S, typename R, typename Rec, int M, bool W, int V, int PART, bool WEAK>
+template <typename S, typename R, typename Rec, int M, bool W, int V, int PART, bool WEAK, bool CVT>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(collide_part_waves<S, M, V, PART>()))) void k_collide(const Params<R>* __restrict__ P, Launch Ln, const S* __restrict__ src,
                                                    S* __restrict__ dst, const Rec* __restrict__ rec,
                                                    const Rec* __restrict__ G, StepNo sn)
@@ -123,23 +123,23 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(collide_p
   const Params<R>& Pt = P[w.t];
   if (w.node < Pt.n) {
     const size_t po = pop_stride<M, WEAK>() * w.base;
-    collide_node<S, R, Rec, M, W, PART, WEAK>(Pt, src + po, dst + po,
-                                              rec + (size_t)RecLayout<M, WEAK>::FIELDS * w.base, G + 3 * w.base,
-                                              w.node, step_of(sn));
+    collide_node<S, R, Rec, M, W, PART, WEAK, CVT>(Pt, src + po, dst + po,
+                                                   rec + (size_t)RecLayout<M, WEAK, CVT>::FIELDS * w.base,
+                                                   G + 3 * w.base, w.node, step_of(sn));
   }
 }
 
 template <typename T>
 __device__ inline T* seg(T* p, int64_t off) { return p ? p + off : p; }
 
-template <typename S, typename R, int M, bool WEAK>
+template <typename S, typename R, int M, bool WEAK, bool CVT>
 __global__ __launch_bounds__(BLOCK) void k_read(const Params<R>* __restrict__ P, Launch Ln, const S* __restrict__ pop,
                                                 double* X, double* rho, double* u, double* p, double* T)
 {
   const Where w = locate(Ln);
   const Params<R>& Pt = P[w.t];
   if (w.node < Pt.n)
-    read_node<S, R, M, WEAK>(Pt, pop + pop_stride<M, WEAK>() * w.base, w.node, seg(X, M * w.base),
+    read_node<S, R, M, WEAK, CVT>(Pt, pop + pop_stride<M, WEAK>() * w.base, w.node, seg(X, M * w.base),
                              seg(rho, w.base), seg(u, 3 * w.base), seg(p, w.base), seg(T, w.base));
 }
 
@@ -219,7 +219,7 @@ __global__ __launch_bounds__(RED_BLOCK) void k_field_sums(const int64_t* __restr
   block_sum<NV>(v, partial, w.block);
 }
 
-template <typename S, int M, bool WEAK>
+template <typename S, int M, bool WEAK, bool CVT>
 __global__ __launch_bounds__(BLOCK) void k_init(const Params<double>* __restrict__ P, Launch Ln,
                                                 const double* __restrict__ X, const double* __restrict__ p,
                                                 const double* __restrict__ T, const double* __restrict__ u,
@@ -229,7 +229,7 @@ __global__ __launch_bounds__(BLOCK) void k_init(const Params<double>* __restrict
   const Params<double>& Pt = P[w.t];
   int bad = 0;
   if (w.node < Pt.n)
-    bad = init_node<S, M, WEAK>(Pt, X + (size_t)M * w.base, p + w.base, T + w.base, u + 3 * w.base,
+    bad = init_node<S, M, WEAK, CVT>(Pt, X + (size_t)M * w.base, p + w.base, T + w.base, u + 3 * w.base,
                                 pop + pop_stride<M, WEAK>() * w.base, w.node);
   bad = __syncthreads_or(bad);
   if (threadIdx.x == 0) block_bad[w.block] = bad;
@@ -265,34 +265,34 @@ struct Ops {
                      double* partial, unsigned grid, hipStream_t st);
 };
 
-template <typename S, typename Rec, int M, int V, bool WEAK>
+template <typename S, typename Rec, int M, int V, bool WEAK, bool CVT>
 void launch_moments(const void* Pd, const Launch& ln, const void* pop, void* rec, unsigned grid, hipStream_t st)
 {
-  hipLaunchKernelGGL((k_moments<S, Rec, M, V, WEAK>), dim3(grid), dim3(BLOCK), 0, st, (const Params<double>*)Pd, ln,
+  hipLaunchKernelGGL((k_moments<S, Rec, M, V, WEAK, CVT>), dim3(grid), dim3(BLOCK), 0, st, (const Params<double>*)Pd, ln,
                      (const S*)pop, (Rec*)rec);
 }
 
-template <typename S, typename R, typename Rec, int M, bool W, int V, int PART, bool WEAK>
+template <typename S, typename R, typename Rec, int M, bool W, int V, int PART, bool WEAK, bool CVT>
 void launch_collide(const void* P, const Launch& ln, const void* src, void* dst, const void* rec, const void* G,
                     StepNo sn, unsigned grid, hipStream_t st)
 {
-  hipLaunchKernelGGL((k_collide<S, R, Rec, M, W, V, PART, WEAK>), dim3(grid), dim3(BLOCK), 0, st,
+  hipLaunchKernelGGL((k_collide<S, R, Rec, M, W, V, PART, WEAK, CVT>), dim3(grid), dim3(BLOCK), 0, st,
                      (const Params<R>*)P, ln, (const S*)src, (S*)dst, (const Rec*)rec, (const Rec*)G, sn);
 }
 
-template <typename S, typename R, typename Rec, int M, bool W, bool WEAK>
+template <typename S, typename R, typename Rec, int M, bool W, bool WEAK, bool CVT>
 Ops make_ops()
 {
   Ops o;
   o.s_bytes = sizeof(S);
   o.r_bytes = sizeof(Rec);
-  o.rec_fields = RecLayout<M, WEAK>::FIELDS;
-  o.moments[0] = launch_moments<S, Rec, M, 0, WEAK>;
-  o.moments[1] = launch_moments<S, Rec, M, 1, WEAK>;
-  o.collide[0] = launch_collide<S, R, Rec, M, W, 0, 0, WEAK>;
-  o.collide[1] = launch_collide<S, R, Rec, M, W, 1, 0, WEAK>;
-  o.collide_split[0] = launch_collide<S, R, Rec, M, W, 0, 1, WEAK>;
-  o.collide_split[1] = launch_collide<S, R, Rec, M, W, 0, 2, WEAK>;
+  o.rec_fields = RecLayout<M, WEAK, CVT>::FIELDS;
+  o.moments[0] = launch_moments<S, Rec, M, 0, WEAK, CVT>;
+  o.moments[1] = launch_moments<S, Rec, M, 1, WEAK, CVT>;
+  o.collide[0] = launch_collide<S, R, Rec, M, W, 0, 0, WEAK, CVT>;
+  o.collide[1] = launch_collide<S, R, Rec, M, W, 1, 0, WEAK, CVT>;
+  o.collide_split[0] = launch_collide<S, R, Rec, M, W, 0, 1, WEAK, CVT>;
+  o.collide_split[1] = launch_collide<S, R, Rec, M, W, 0, 2, WEAK, CVT>;
   o.gfield = [](const void* Pd, const Launch& ln, const void* rec, void* G, int rec_fields, unsigned grid,
                 hipStream_t st) {
     hipLaunchKernelGGL((k_gfield<Rec, W>), dim3(grid), dim3(BLOCK), 0, st, (const Params<double>*)Pd, ln,
@@ -300,7 +300,7 @@ Ops make_ops()
   };
   o.read = [](const void* P, const Launch& ln, const void* pop, double* X, double* rho, double* u, double* p,
               double* T, unsigned grid, hipStream_t st) {
-    hipLaunchKernelGGL((k_read<S, R, M, WEAK>), dim3(grid), dim3(BLOCK), 0, st, (const Params<R>*)P, ln, (const S*)pop,
+    hipLaunchKernelGGL((k_read<S, R, M, WEAK, CVT>), dim3(grid), dim3(BLOCK), 0, st, (const Params<R>*)P, ln, (const S*)pop,
                        X, rho, u, p, T);
   };
   o.conserved = [](const void* Pd, const Launch& ln, const void* pop, double* partial, unsigned grid,
@@ -315,7 +315,7 @@ Ops make_ops()
   };
   o.init = [](const void* Pd, const Launch& ln, const double* X, const double* p, const double* T,
               const double* u, void* pop, int* bad, unsigned grid, hipStream_t st) {
-    hipLaunchKernelGGL((k_init<S, M, WEAK>), dim3(grid), dim3(BLOCK), 0, st, (const Params<double>*)Pd, ln, X, p, T, u,
+    hipLaunchKernelGGL((k_init<S, M, WEAK, CVT>), dim3(grid), dim3(BLOCK), 0, st, (const Params<double>*)Pd, ln, X, p, T, u,
                        (S*)pop, bad);
   };
   o.field_sums = [](const int64_t* tube_n, const Launch& ln, const double* X, const double* p, const double* T,
@@ -325,13 +325,13 @@ Ops make_ops()
   return o;
 }
 
-template <typename S, typename R, typename Rec, bool WEAK>
+template <typename S, typename R, typename Rec, bool WEAK, bool CVT = false>
 bool pick_m(int M, int walls, Ops& o)
 {
   switch (M) {
-    case 2: o = walls ? make_ops<S, R, Rec, 2, true, WEAK>() : make_ops<S, R, Rec, 2, false, WEAK>(); return true;
-    case 3: o = walls ? make_ops<S, R, Rec, 3, true, WEAK>() : make_ops<S, R, Rec, 3, false, WEAK>(); return true;
-    case 4: o = walls ? make_ops<S, R, Rec, 4, true, WEAK>() : make_ops<S, R, Rec, 4, false, WEAK>(); return true;
+    case 2: o = walls ? make_ops<S, R, Rec, 2, true, WEAK, CVT>() : make_ops<S, R, Rec, 2, false, WEAK, CVT>(); return true;
+    case 3: o = walls ? make_ops<S, R, Rec, 3, true, WEAK, CVT>() : make_ops<S, R, Rec, 3, false, WEAK, CVT>(); return true;
+    case 4: o = walls ? make_ops<S, R, Rec, 4, true, WEAK, CVT>() : make_ops<S, R, Rec, 4, false, WEAK, CVT>(); return true;
     default: return false;
   }
 }
@@ -339,11 +339,12 @@ bool pick_m(int M, int walls, Ops& o)
 }  // namespace kern
 
 // One entry point per instantiated (storage, arithmetic) pair. weak: 1 for weak
-// coupling (compiled for FP64 and FP32 storage with FP64 arithmetic only).
-bool pick_fp64(int M, int walls, int weak, kern::Ops& o);
-bool pick_fp32_fp64(int M, int walls, int weak, kern::Ops& o);
-bool pick_fp32(int M, int walls, int weak, kern::Ops& o);
-bool pick_fp16(int M, int walls, int weak, kern::Ops& o);
-bool pick_bf16(int M, int walls, int weak, kern::Ops& o);
+// coupling; cvt: 1 for temperature-dependent specific heats (each compiled for
+// FP64 and FP32 storage with FP64 arithmetic only, and not together).
+bool pick_fp64(int M, int walls, int weak, int cvt, kern::Ops& o);
+bool pick_fp32_fp64(int M, int walls, int weak, int cvt, kern::Ops& o);
+bool pick_fp32(int M, int walls, int weak, int cvt, kern::Ops& o);
+bool pick_fp16(int M, int walls, int weak, int cvt, kern::Ops& o);
+bool pick_bf16(int M, int walls, int weak, int cvt, kern::Ops& o);
 
 }  // namespace mclbm

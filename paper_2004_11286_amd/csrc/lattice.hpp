@@ -77,6 +77,7 @@ struct Params {
   int64_t n;
   R m[MAXM], inv_m[MAXM], cv[MAXM], cp[MAXM];
   R mu[MAXM], lam[MAXM], inv_lam[MAXM];
+  R cvc[MAXM][4];         // C_{a,v}(T) = sum_k cvc[a][k] T^k (temperature-dependent kernels only)
   R invD[MAXM][MAXM];     // 1 / D_ab
   R phi[MAXM][MAXM];      // Wilke's phi_ab
   R ref[MAXL][Q];         // reference populations f_ref

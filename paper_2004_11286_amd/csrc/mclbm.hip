@@ -135,14 +135,14 @@ __global__ __launch_bounds__(BLOCK) void k_pred_to_state(const Params<double>* _
   if (threadIdx.x == 0) block_bad[w.block] = bad;
 }
 
-bool pick_ops(int precision, int M, int walls, int weak, Ops& o)
+bool pick_ops(int precision, int M, int walls, int weak, int cvt, Ops& o)
 {
   switch (precision) {
-    case MCLBM_FP64: return pick_fp64(M, walls, weak, o);
-    case MCLBM_FP32: return pick_fp32_fp64(M, walls, weak, o);
-    case MCLBM_FP32_FP32: return pick_fp32(M, walls, weak, o);
-    case MCLBM_FP16: return pick_fp16(M, walls, weak, o);
-    case MCLBM_BF16: return pick_bf16(M, walls, weak, o);
+    case MCLBM_FP64: return pick_fp64(M, walls, weak, cvt, o);
+    case MCLBM_FP32: return pick_fp32_fp64(M, walls, weak, cvt, o);
+    case MCLBM_FP32_FP32: return pick_fp32(M, walls, weak, cvt, o);
+    case MCLBM_FP16: return pick_fp16(M, walls, weak, cvt, o);
+    case MCLBM_BF16: return pick_bf16(M, walls, weak, cvt, o);
     default: return false;
   }
 }
@@ -167,7 +167,7 @@ struct TubeHost {
 // Context
 // ---------------------------------------------------------------------------
 struct mclbm_ctx {
-  int M = 0, wall_x = 0, precision = 0, weak = 0, L = 0, ntubes = 0;
+  int M = 0, wall_x = 0, precision = 0, weak = 0, cvt = 0, L = 0, ntubes = 0;
   int64_t n = 0;            // nodes over all tubes
   int64_t nblocks = 0;      // launch blocks over all tubes
   std::vector<TubeHost> tubes;
@@ -234,7 +234,7 @@ size_t record_bytes(int precision) { return precision == MCLBM_FP64 ? 8 : 4; }
 
 Layout layout_for(const mclbm_params* tp, int ntubes)
 {
-  const int M = tp[0].M, precision = tp[0].precision, weak = tp[0].weak;
+  const int M = tp[0].M, precision = tp[0].precision, weak = tp[0].weak, cvt = tp[0].cv_coef != nullptr;
   Layout l{};
   l.n = 0;
   l.nblocks = 0;
@@ -248,7 +248,7 @@ Layout layout_for(const mclbm_params* tp, int ntubes)
   // strong coupling, M under weak coupling (which also records u_s)
   const int ns = weak ? M : M - 1;
   const int L = ns + 2;
-  const int rec_fields = REC_RHOA + ns + 3 * M + (weak ? 3 : 0);
+  const int rec_fields = REC_RHOA + ns + 3 * M + (weak ? 3 : 0) + (cvt ? M - 1 : 0);
   size_t off = 0;
   l.pd = off; off += align_up(sizeof(Params<double>) * ntubes);
   l.pr = off; off += align_up(sizeof(Params<float>) * ntubes);
@@ -294,6 +294,21 @@ int validate_one(const mclbm_params* p, std::string& err)
     err = "weak coupling is compiled for MCLBM_FP64 and MCLBM_FP32 only";
     return MCLBM_EUNSUPPORTED;
   }
+  if (p->cv_coef) {
+    for (int a = 0; a < p->M; ++a)
+      for (int k = 0; k < 4; ++k) {
+        const double c = p->cv_coef[a * 4 + k];
+        if (!(k == 0 ? c > 0 : c >= 0) || !std::isfinite(c)) {
+          err = "cv_coef: c_a0 must be positive and c_ak (k >= 1) non-negative";
+          return MCLBM_EARG;
+        }
+      }
+    if (p->weak || (p->precision != MCLBM_FP64 && p->precision != MCLBM_FP32)) {
+      err = "temperature-dependent specific heats are compiled for strong coupling with MCLBM_FP64 and "
+            "MCLBM_FP32 only";
+      return MCLBM_EUNSUPPORTED;
+    }
+  }
   if (!p->molar_mass || !p->cv || !p->D || !p->mu || !p->lambda) { err = "species arrays must be given"; return MCLBM_EARG; }
   for (int a = 0; a < p->M; ++a) {
     if (!(p->molar_mass[a] > 0) || !(p->cv[a] > 0) || !(p->mu[a] > 0) || !(p->lambda[a] > 0)) {
@@ -320,8 +335,8 @@ int validate(const mclbm_params* tp, int ntubes, std::string& err)
       return rc;
     }
     if (tp[t].M != tp[0].M || tp[t].wall_x != tp[0].wall_x || tp[t].precision != tp[0].precision ||
-        tp[t].weak != tp[0].weak) {
-      err = "all tubes of a batch must share M, wall_x, precision and weak";
+        tp[t].weak != tp[0].weak || (tp[t].cv_coef == nullptr) != (tp[0].cv_coef == nullptr)) {
+      err = "all tubes of a batch must share M, wall_x, precision, weak and whether cv_coef is given";
       return MCLBM_EARG;
     }
     const int64_t n = (int64_t)tp[t].nx * tp[t].ny * tp[t].nz;
@@ -662,6 +677,7 @@ extern "C" int mclbm_batch_create(const mclbm_params* tp, int32_t ntubes, void* 
   c->wall_x = tp[0].wall_x;
   c->precision = tp[0].precision;
   c->weak = tp[0].weak;
+  c->cvt = tp[0].cv_coef != nullptr;
   c->L = (c->weak ? c->M : c->M - 1) + 2;
   if (c->weak) {
     // four or more stored lattices: the split collision (two launches with fewer
@@ -689,9 +705,11 @@ extern "C" int mclbm_batch_create(const mclbm_params* tp, int32_t ntubes, void* 
       th.hs.mu[a] = p->mu[a];
       th.hs.lam[a] = p->lambda[a];
       for (int b = 0; b < p->M; ++b) th.hs.D[a][b] = p->D[a * p->M + b];
+      for (int k = 0; k < 4; ++k) th.hs.cvc[a][k] = p->cv_coef ? p->cv_coef[a * 4 + k] : (k == 0 ? p->cv[a] : 0.0);
     }
+    th.hs.cvt = p->cv_coef != nullptr;
   }
-  if (!pick_ops(c->precision, c->M, c->wall_x, c->weak, c->ops)) {
+  if (!pick_ops(c->precision, c->M, c->wall_x, c->weak, c->cvt, c->ops)) {
     delete c;
     return fail(nullptr, MCLBM_EUNSUPPORTED, "no kernels compiled for this configuration");
   }
@@ -978,7 +996,7 @@ namespace {
 struct CkptHeader {
   char magic[8];
   int32_t M, wall_x, precision, ntubes;
-  int32_t weak, pad;
+  int32_t weak, cvt;
   int64_t steps;
 };
 struct CkptTube {
@@ -1003,7 +1021,7 @@ extern "C" int mclbm_save(mclbm_ctx* c, void* host_buf, size_t bytes)
   if (bytes < mclbm_state_bytes(c)) return fail(c, MCLBM_EARG, "buffer too small");
   CkptHeader h{};
   std::memcpy(h.magic, kMagic, 8);
-  h.M = c->M; h.wall_x = c->wall_x; h.precision = c->precision; h.ntubes = c->ntubes; h.weak = c->weak;
+  h.M = c->M; h.wall_x = c->wall_x; h.precision = c->precision; h.ntubes = c->ntubes; h.weak = c->weak; h.cvt = c->cvt;
   h.steps = c->steps;
   char* dst = (char*)host_buf;
   std::memcpy(dst, &h, sizeof(h));
@@ -1031,7 +1049,7 @@ extern "C" int mclbm_load(mclbm_ctx* c, const void* host_buf, size_t bytes)
   CkptHeader h;
   std::memcpy(&h, src, sizeof(h));
   if (std::memcmp(h.magic, kMagic, 8) != 0 || h.M != c->M || h.wall_x != c->wall_x || h.precision != c->precision ||
-      h.ntubes != c->ntubes || h.weak != c->weak)
+      h.ntubes != c->ntubes || h.weak != c->weak || h.cvt != c->cvt)
     return fail(c, MCLBM_EARG, "checkpoint does not match this context");
   std::vector<CkptTube> ct(c->ntubes);
   for (int t = 0; t < c->ntubes; ++t) {

@@ -38,12 +38,55 @@ enum {
   REC_QNX = 11, REC_QNY = 12, REC_QNZ = 13,    // q - q^eq - u.(P - P^eq)
   REC_RHOA = 14                                // then rho_a (stored species), V_a (3 M),
 };                                             // and under weak coupling u_s (3)
-template <int M, bool WEAK = false>
+template <int M, bool WEAK = false, bool CVT = false>
 struct RecLayout {
   static constexpr int V = REC_RHOA + Lat<M, WEAK>::NS;
   static constexpr int US = V + 3 * M;
-  static constexpr int FIELDS = US + (WEAK ? 3 : 0);
+  static constexpr int YF = US + (WEAK ? 3 : 0);         // with C_v(T): Y_a, a < M-1
+  static constexpr int FIELDS = YF + (CVT ? M - 1 : 0);
 };
+
+// Temperature-dependent specific heats (Sec. 3.1): the mixture's C_v(T) =
+// sum_k c_k T^k with c_k = sum_a Y_a c_ak (eq Cvmix), and its integral from
+// T_0 = 0, U(T) = sum_a Y_a U_a(T) (eqs specUa, Umix).
+template <typename R, int M>
+__host__ __device__ __forceinline__ void mix_cv_poly(const Params<R>& P, const R Y[M], R c[4])
+{
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    c[k] = R(0);
+#pragma unroll
+    for (int a = 0; a < M; ++a) c[k] += Y[a] * P.cvc[a][k];
+  }
+}
+
+template <typename R>
+__host__ __device__ __forceinline__ R poly_cv(const R c[4], R T)
+{
+  return c[0] + T * (c[1] + T * (c[2] + T * c[3]));
+}
+
+template <typename R>
+__host__ __device__ __forceinline__ R poly_U(const R c[4], R T)
+{
+  return T * (c[0] + T * (c[1] * R(0.5) + T * (c[2] * R(1.0 / 3.0) + T * (c[3] * R(0.25)))));
+}
+
+// T from U(T) = e (eq temperature) by Newton's method. With c_0 > 0 and c_k >= 0,
+// U is increasing and convex and e / c_0 bounds the root from above, so the
+// iterates fall monotonically; the loop ends when the step is below 1e-15 T
+// (a few iterations), or after 40.
+template <typename R>
+__host__ __device__ __forceinline__ R solve_temperature(const R c[4], R e)
+{
+  R T = e / c[0];
+  for (int it = 0; it < 40; ++it) {
+    const R dT = (poly_U(c, T) - e) / poly_cv(c, T);
+    T -= dT;
+    if (!(dT > R(1e-15) * T || dT < -R(1e-15) * T)) break;
+  }
+  return T;
+}
 
 // Macroscopic state of a node (Secs. 2.1, 3.1, 3.2; strong coupling Sec. 3.6.2).
 template <typename R, int M>
@@ -56,7 +99,7 @@ struct Mix {
 // rho_s: species densities. Strong coupling: rho_s[0..M-2] stored, the slaved
 // species takes the deficit and Y_a = rho_a / rho. Weak coupling: all M stored,
 // Y_a = rho_a / sum_b rho_b (the species subsystem's own density, eq rhoSPEC).
-template <typename R, int M, bool WEAK = false>
+template <typename R, int M, bool WEAK = false, bool CVT = false>
 __host__ __device__ __forceinline__ void mixture_state(const Params<R>& P, R rho, const R j[3], R rhoE,
                                               const R rho_s[M], Mix<R, M>& s)
 {
@@ -99,9 +142,17 @@ __host__ __device__ __forceinline__ void mixture_state(const Params<R>& P, R rho
   s.mmix = R(1) / inv_m;
 #pragma unroll
   for (int a = 0; a < M; ++a) s.X[a] = s.Y[a] * s.mmix * P.inv_m[a];
-  s.Cv = Cv;
-  s.Cp = Cp;
-  s.T = (rhoE * s.inv_rho - R(0.5) * s.usq) / Cv;   // constant specific heats, T_0 = 0
+  if constexpr (CVT) {
+    R c[4];
+    mix_cv_poly<R, M>(P, s.Y, c);
+    s.T = solve_temperature<R>(c, rhoE * s.inv_rho - R(0.5) * s.usq);
+    s.Cv = poly_cv<R>(c, s.T);
+    s.Cp = s.Cv + s.Rg;                                // Mayer
+  } else {
+    s.Cv = Cv;
+    s.Cp = Cp;
+    s.T = (rhoE * s.inv_rho - R(0.5) * s.usq) / Cv;  // constant specific heats, T_0 = 0
+  }
   s.P = rho * s.Rg * s.T;
 }
 
@@ -280,7 +331,7 @@ __host__ __device__ __forceinline__ void acc_c(R& acc, int c, R v)
 // --------------------------------------------------------------------------
 // Pass 1: node state -> record (FP64 arithmetic, record stored as Rec)
 // --------------------------------------------------------------------------
-template <typename S, typename Rec, int M, bool WEAK = false>
+template <typename S, typename Rec, int M, bool WEAK = false, bool CVT = false>
 __host__ __device__ __forceinline__ void state_node(const Params<double>& P, const S* __restrict__ pop,
                                            Rec* __restrict__ rec, int64_t node)
 {
@@ -332,7 +383,7 @@ __host__ __device__ __forceinline__ void state_node(const Params<double>& P, con
 #pragma unroll
   for (int k = 0; k < 3; ++k) Pd[k] += P.ref2[LF];
   Mix<D, M> s;
-  mixture_state<D, M, WEAK>(P, rho, j, rhoE, rho_s, s);
+  mixture_state<D, M, WEAK, CVT>(P, rho, j, rhoE, rho_s, s);
   D us[3], Pk = s.P;                     // velocity and pressure of the species subsystem
   if constexpr (WEAK) {
     D rs = 0.0;
@@ -365,7 +416,13 @@ __host__ __device__ __forceinline__ void state_node(const Params<double>& P, con
   const D omega = 2.0 * s.P / (s.P + 2.0 * mixture_viscosity<D, M>(P, s.X));
   const D omega1 = 2.0 * s.P * s.Cp / (s.P * s.Cp + 2.0 * mixture_conductivity<D, M>(P, s.X));
   // non-equilibrium energy flux q - q^eq - u.(P - P^eq), used by the energy collision
-  const D hyd = s.Cp * s.T + 0.5 * s.usq;
+  D H = s.Cp * s.T;                      // mixture enthalpy (eq specH)
+  if constexpr (CVT) {
+    D c[4];
+    mix_cv_poly<D, M>(P, s.Y, c);
+    H = poly_U<D>(c, s.T) + s.Rg * s.T;
+  }
+  const D hyd = H + 0.5 * s.usq;
   const D Pn[3][3] = {{Pd[0], Pxy, Pxz}, {Pxy, Pd[1], Pyz}, {Pxz, Pyz, Pd[2]}};
   D qn[3];
 #pragma unroll
@@ -396,6 +453,10 @@ __host__ __device__ __forceinline__ void state_node(const Params<double>& P, con
   if constexpr (WEAK) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) put(RecLayout<M, WEAK>::US + k, us[k]);
+  }
+  if constexpr (CVT) {
+#pragma unroll
+    for (int a = 0; a < M - 1; ++a) put(RecLayout<M, WEAK, CVT>::YF + a, s.Y[a]);
   }
 }
 
@@ -525,14 +586,14 @@ __host__ __device__ __forceinline__ void load_lattice(const S* __restrict__ lat,
 
 // PART selects the lattices: 0 all, 1 the stored species lattices, 2 the momentum
 // and energy lattices (a split collision in two launches computes the same step).
-template <typename S, typename R, typename Rec, int M, bool WALLS, int PART = 0, bool WEAK = false>
+template <typename S, typename R, typename Rec, int M, bool WALLS, int PART = 0, bool WEAK = false, bool CVT = false>
 __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const S* __restrict__ src,
                                              S* __restrict__ dst, const Rec* __restrict__ rec,
                                              const Rec* __restrict__ G, int64_t node, uint32_t step)
 {
   const size_t n = (size_t)P.n;
   constexpr int NS = Lat<M, WEAK>::NS, LF = Lat<M, WEAK>::LF, LG = Lat<M, WEAK>::LG;
-  using RL = RecLayout<M, WEAK>;
+  using RL = RecLayout<M, WEAK, CVT>;
   // issue a lattice's loads together (load_lattice) where the scheduler otherwise
   // serialises them: 16-bit storage, and the unsplit collision of three or more
   // species (one wave per SIMD, registers to spare); elsewhere each load is
@@ -595,18 +656,30 @@ __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const 
   const R omega = get(REC_OMEGA);
   const R omega1 = get(REC_OMEGA1);
 
-  // ---- non-local terms: X_a = -d_a G_a (eq Xalpha) and d_a C_p (sum_a H_a d Y_a = T d C_p)
+  // ---- non-local terms: X_a = -d_a G_a (eq Xalpha) and d_a C_p (sum_a H_a d Y_a = T d C_p);
+  // with C_v(T), the gradients of Y_a, a < M-1 (sum_a d Y_a = 0 gives the last)
   R dG[3] = {R(0), R(0), R(0)}, gcp[3] = {R(0), R(0), R(0)};
+  R gY[CVT ? M - 1 : 1][3] = {};
   if constexpr (PART != 1) {
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     if (csq(i) == 0) continue;
     const uint32_t nb = stencil_index<WALLS>(b, cx(i), cy(i), cz(i));
     const R w3 = R(3.0 * w13(i));
-    const R cpn = w3 * R(*at32(rec + (size_t)REC_CP * n, nb));
-    acc_c(gcp[0], cx(i), cpn);
-    acc_c(gcp[1], cy(i), cpn);
-    acc_c(gcp[2], cz(i), cpn);
+    if constexpr (CVT) {
+#pragma unroll
+      for (int a = 0; a < M - 1; ++a) {
+        const R yn = w3 * R(*at32(rec + (size_t)(RL::YF + a) * n, nb));
+        acc_c(gY[a][0], cx(i), yn);
+        acc_c(gY[a][1], cy(i), yn);
+        acc_c(gY[a][2], cz(i), yn);
+      }
+    } else {
+      const R cpn = w3 * R(*at32(rec + (size_t)REC_CP * n, nb));
+      acc_c(gcp[0], cx(i), cpn);
+      acc_c(gcp[1], cy(i), cpn);
+      acc_c(gcp[2], cz(i), cpn);
+    }
     if (cx(i)) acc_c(dG[0], cx(i), w3 * R(*at32(G, nb)));
     if (cy(i)) acc_c(dG[1], cy(i), w3 * R(*at32(G + n, nb)));
     if (cz(i)) acc_c(dG[2], cz(i), w3 * R(*at32(G + 2 * n, nb)));
@@ -756,23 +829,43 @@ __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const 
   //      + (2 - omega_1)/2 P sum_a H_a d Y_a     (the exact rewrite of eqs g, gistar,
   // gstareq1mom, interdiffusion and corrFourier that has no pole at omega = omega_1)
   if constexpr (PART != 1) {
-    const R H = s.Cp * s.T;
+    R H = s.Cp * s.T;
+    R ha[CVT ? M : 1];                 // with C_v(T): H_a(T) = U_a(T) + R_a T (eq specHa)
+    if constexpr (CVT) {
+      H = R(0);
+#pragma unroll
+      for (int a = 0; a < M; ++a) {
+        ha[a] = poly_U<R>(P.cvc[a], s.T) + s.T * P.inv_m[a];
+        H += s.Y[a] * ha[a];
+      }
+    }
     const R hyd = H + R(0.5) * s.usq;
     const R inv_theta = R(1) / theta;
-    const R rhoE = rho * (H - s.Rg * s.T + R(0.5) * s.usq);   // rho (C_v T + u^2/2), C_v = C_p - R
+    const R rhoE = rho * (H - s.Rg * s.T + R(0.5) * s.usq);   // rho (U + u^2/2), U = H - R T
     R qeq[3], dq[3];
     R hyv[3] = {R(0), R(0), R(0)};
 #pragma unroll
     for (int a = 0; a < M; ++a) {
-      const R ca = P.cp[a] * s.Y[a];
+      R ca;
+      if constexpr (CVT) ca = ha[a] * s.Y[a];
+      else ca = P.cp[a] * s.Y[a];
 #pragma unroll
       for (int k = 0; k < 3; ++k) hyv[k] += ca * get(RL::V + 3 * a + k);
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       qeq[k] = hyd * rho * s.u[k];
-      dq[k] = (omega - omega1) * get(REC_QNX + k) + omega1 * rho * s.T * hyv[k] +
-              R(0.5) * (R(2) - omega1) * s.P * s.T * gcp[k];
+      if constexpr (CVT) {
+        // sum_a H_a d Y_a = sum_{a < M-1} (H_a - H_M) d Y_a
+        R hgy = R(0);
+#pragma unroll
+        for (int a = 0; a < M - 1; ++a) hgy += (ha[a] - ha[M - 1]) * gY[a][k];
+        dq[k] = (omega - omega1) * get(REC_QNX + k) + omega1 * rho * hyv[k] +
+                R(0.5) * (R(2) - omega1) * s.P * hgy;
+      } else {
+        dq[k] = (omega - omega1) * get(REC_QNX + k) + omega1 * rho * s.T * hyv[k] +
+                R(0.5) * (R(2) - omega1) * s.P * s.T * gcp[k];
+      }
     }
     // closed form of R^eq - rho E theta I for T_0 = 0: rho theta^2 I + kappa u u
     const R kappa = rho * (hyd + theta);
@@ -817,7 +910,7 @@ __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const 
 // --------------------------------------------------------------------------
 // Read-back of the macroscopic fields
 // --------------------------------------------------------------------------
-template <typename S, typename R, int M, bool WEAK = false>
+template <typename S, typename R, int M, bool WEAK = false, bool CVT = false>
 __host__ __device__ __forceinline__ void read_node(const Params<R>& P, const S* __restrict__ pop, int64_t node,
                                           double* X, double* rho_o, double* u, double* p, double* T)
 {
@@ -845,7 +938,7 @@ __host__ __device__ __forceinline__ void read_node(const Params<R>& P, const S* 
   rho += P.ref0[LF];
   rhoE += P.ref0[LG];
   Mix<R, M> s;
-  mixture_state<R, M, WEAK>(P, rho, j, rhoE, rho_s, s);
+  mixture_state<R, M, WEAK, CVT>(P, rho, j, rhoE, rho_s, s);
   if (X)
 #pragma unroll
     for (int a = 0; a < M; ++a) X[(size_t)a * n + node] = (double)s.X[a];
@@ -860,7 +953,7 @@ __host__ __device__ __forceinline__ void read_node(const Params<R>& P, const S* 
 // --------------------------------------------------------------------------
 // Initialisation at the local equilibrium of (X_a, p, T, u), computed in FP64
 // --------------------------------------------------------------------------
-template <typename S, int M, bool WEAK = false>
+template <typename S, int M, bool WEAK = false, bool CVT = false>
 __host__ __device__ __forceinline__ int init_node(const Params<double>& P, const double* X,
                                          const double* p, const double* T, const double* u, S* __restrict__ pop,
                                          int64_t node)
@@ -912,8 +1005,15 @@ __host__ __device__ __forceinline__ int init_node(const Params<double>& P, const
     }
   }
   {
-    const double rhoE = rho * (Cv * Tn + 0.5 * usq);
-    const double hyd = Cp * Tn + 0.5 * usq;
+    double U = Cv * Tn, H = Cp * Tn;        // specific internal energy and enthalpy
+    if constexpr (CVT) {                     // eqs Umix, specH with C_v(T)
+      double c[4];
+      mix_cv_poly<double, M>(P, Y, c);
+      U = poly_U<double>(c, Tn);
+      H = U + Rg * Tn;
+    }
+    const double rhoE = rho * (U + 0.5 * usq);
+    const double hyd = H + 0.5 * usq;
     const double kappa = rho * (hyd + theta);
     const double rt2 = rho * theta * theta;
     const double zf = (1.0 - 3.0 * theta) * 0.5 / theta;

@@ -14,6 +14,8 @@ struct HostSpecies {
   int M;
   double m[MAXM], cv[MAXM], mu[MAXM], lam[MAXM];
   double D[MAXM][MAXM];
+  int cvt;                  // 1: C_{a,v}(T) = sum_k cvc[a][k] T^k, else the constant cv
+  double cvc[MAXM][4];      // (the constant case holds cv[a], 0, 0, 0)
 };
 
 // Mean state used for the reference equilibria (zero velocity).
@@ -44,6 +46,14 @@ inline void reference_tables(const HostSpecies& h, int ns, const RefState& rs, d
   const double rho = rs.p / (Rg * rs.T);
   double Cv = 0.0;
   for (int a = 0; a < M; ++a) Cv += rs.X[a] * h.m[a] / mmix * h.cv[a];
+  double U = 0.0;           // with C_v(T): specific internal energy at the mean state (eq Umix)
+  if (h.cvt) {
+    for (int a = 0; a < M; ++a) {
+      const double* c = h.cvc[a];
+      const double T = rs.T;
+      U += rs.X[a] * h.m[a] / mmix * T * (c[0] + T * (c[1] / 2 + T * (c[2] / 3 + T * c[3] / 4)));
+    }
+  }
   std::memset(ref, 0, sizeof(double) * MAXL * Q);
   auto fill_psi = [&](int l, double dens, double zeta) {
     Trip<double> t = psi_trip<double>(0.0, zeta);
@@ -53,7 +63,7 @@ inline void reference_tables(const HostSpecies& h, int ns, const RefState& rs, d
   fill_psi(ns, rho, Rg * rs.T);
   {
     const double theta = Rg * rs.T;
-    const double rhoE = rho * Cv * rs.T;
+    const double rhoE = h.cvt ? rho * U : rho * Cv * rs.T;
     const double rt2 = rho * theta * theta;
     const double zf = (1.0 - 3.0 * theta) * 0.5 / theta;
     const Trip<double> wt = w_trip<double>(theta);
@@ -96,6 +106,7 @@ inline void fill_params(Params<R>& P, const HostSpecies& h, int nx, int ny, int 
     P.cp[a] = R(h.cv[a] + 1.0 / h.m[a]);       // Mayer: C_{a,p} - C_{a,v} = R_a
     P.mu[a] = R(h.mu[a]);
     P.lam[a] = R(h.lam[a]);
+    for (int k = 0; k < 4; ++k) P.cvc[a][k] = R(h.cvc[a][k]);
     P.inv_lam[a] = R(1.0 / h.lam[a]);
     for (int b = 0; b < h.M; ++b) {
       P.invD[a][b] = R(1.0 / h.D[a][b]);

@@ -57,7 +57,7 @@ class mclbm_params(C.Structure):
         ("reserved1", C.c_int32),
         ("molar_mass", C.POINTER(C.c_double)), ("cv", C.POINTER(C.c_double)),
         ("D", C.POINTER(C.c_double)), ("mu", C.POINTER(C.c_double)),
-        ("lam", C.POINTER(C.c_double)),
+        ("lam", C.POINTER(C.c_double)), ("cv_coef", C.POINTER(C.c_double)),
     ]
 
 
@@ -164,9 +164,13 @@ def make_params(params: dict, precision: int):
     arrs = [_f64(params["molar_mass"]), _f64(params["cv"]), _f64(params["D"]).reshape(M * M),
             _f64(params["mu"]), _f64(params["lambda"])]
     dp = C.POINTER(C.c_double)
+    cvc = params.get("cv_coef")
+    if cvc is not None:
+        arrs.append(_f64(cvc).reshape(M * 4))
     p = mclbm_params(M, int(params["nx"]), int(params["ny"]), int(params["nz"]),
                      int(params.get("wall_x", 0)), int(precision), int(params.get("weak", 0)), 0,
-                     *[a.ctypes.data_as(dp) for a in arrs])
+                     *[a.ctypes.data_as(dp) for a in arrs[:5]],
+                     arrs[5].ctypes.data_as(dp) if cvc is not None else None)
     return p, arrs
 
 
