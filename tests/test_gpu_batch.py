@@ -258,3 +258,33 @@ def test_stream_copy_is_exact(mc):
         mc.stream_copy(b, a)
         torch.cuda.synchronize()
         assert torch.equal(a, b), n
+
+
+@pytest.mark.parametrize("model", ["weak", "cv_of_T"])
+def test_batch_models_match_oracle_and_single_contexts(mc, oracle_mod, model):
+    """Weak coupling and temperature-dependent heat capacities in a batch of ragged
+    tubes (each with its own species data): every tube bit for bit equal to its
+    own single-tube context, and within 1e-12 of the oracle (FP64, 30 steps)."""
+    tubes = []
+    for p, f in small_ensemble(n=4, seed=21):
+        if model == "weak":
+            p = dict(p, weak=1)
+        else:
+            cv = np.asarray(p["cv"], dtype=np.float64)
+            p = dict(p, cv_coef=np.stack([cv[a] * np.array([1.0, 0.5 * 3, 0.0, 0.2 * 27]) for a in range(p["M"])]))
+        tubes.append((p, f))
+    g, _ = run_batch(mc, tubes, mc.MCLBM_FP64, 30)
+    for t, (params, f) in enumerate(tubes):
+        s = mc.Sim(params, mc.MCLBM_FP64)
+        s.init_fields(**f)
+        s.step(30)
+        r = s.read_moments()
+        s.close()
+        o = oracle_mod.OracleSim(params)
+        o.init_fields(**f)
+        o.step(30)
+        om = o.read_moments()
+        for k in FIELDS:
+            np.testing.assert_array_equal(g[t][k], r[k], err_msg=f"{model} tube {t} {k}")
+            scale = max(np.abs(om[k]).max(), 1e-3 if k == "u" else 0.0)
+            assert np.abs(g[t][k] - om[k]).max() <= 1e-12 * scale, (model, t, k)
