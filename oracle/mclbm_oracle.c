@@ -177,6 +177,7 @@ struct oracle_sim {
   double m[MAXM], cv[MAXM], D[MAXM][MAXM], mu[MAXM], lam[MAXM];
   int cvt;                 /* 1: C_{a,v}(T) = sum_k cvc[a][k] T^k, else the constant cv[a] */
   double cvc[MAXM][4];
+  double fin[MAXM + 2][Q]; /* open x ends: populations of the inlet equilibrium */
   double *pop;   /* [(M+2)][Q][n] pre-collision populations */
   double *post;  /* [(M+2)][Q][n] post-collision populations */
   /* node fields used by the non-local terms */
@@ -219,18 +220,22 @@ int oracle_threads(void)
 #endif
 }
 
+static int local_equilibrium(const oracle_sim *s, const double *Xa, double Pn, double Tn, const double uu[3],
+                             double out[][Q]);
+
 int oracle_create(const oracle_params *p, oracle_sim **out)
 {
   if (!p || !out) return -1;
   *out = NULL;
   if (p->M < 2 || p->M > MAXM || p->nx < 1 || p->ny < 1 || p->nz < 1) return -1;
   if (p->wall_x && p->nx < 2) return -1;
+  if (p->wall_x < 0 || p->wall_x > 2 || (p->wall_x == 2 && !p->inlet)) return -1;
   if (!p->molar_mass || !p->cv || !p->D || !p->mu || !p->lambda) return -1;
   oracle_sim *s = (oracle_sim *)calloc(1, sizeof(oracle_sim));
   if (!s) return -1;
   s->M = p->M;
   s->nx = p->nx; s->ny = p->ny; s->nz = p->nz;
-  s->wall_x = p->wall_x ? 1 : 0;
+  s->wall_x = p->wall_x;
   s->weak = p->weak ? 1 : 0;
   s->keep_slaved = (p->keep_slaved || s->weak) ? 1 : 0;   /* weak coupling evolves every species */
   s->flags = p->debug_flags;
@@ -275,6 +280,15 @@ int oracle_create(const oracle_params *p, oracle_sim **out)
   if (!s->pop || !s->post || !s->Phi || !s->om || !s->Yf || !s->G || !s->Xc || !s->gY) {
     oracle_destroy(s);
     return -1;
+  }
+  if (s->wall_x == 2) {
+    /* inlet fields: X (M), p, T, u (3) */
+    const double *in = p->inlet;
+    const double uin[3] = {in[s->M + 2], in[s->M + 3], in[s->M + 4]};
+    if (local_equilibrium(s, in, in[s->M], in[s->M + 1], uin, s->fin) != 0) {
+      oracle_destroy(s);
+      return -1;
+    }
   }
   *out = s;
   return 0;
@@ -441,15 +455,19 @@ static void node_state(const oracle_sim *s, const double *pop, long node, state_
 /* ------------------------------------------------------------------------- */
 /* Value of a node field at integer position (x, y, z): periodic in y and z; in
  * x periodic, or mirrored about the walls at x = -1/2 and x = nx - 1/2, in which
- * case odd_x = 1 flips the sign (x component of a vector field). */
+ * case odd_x = 1 flips the sign (x component of a vector field), or, at open x
+ * ends, the boundary node's value (zero gradient). */
 static double field_at(const oracle_sim *s, const double *fld, int x, int y, int z, int odd_x)
 {
   double sign = 1.0;
   y = wrap(y, s->ny);
   z = wrap(z, s->nz);
-  if (s->wall_x) {
+  if (s->wall_x == 1) {
     if (x < 0) { x = -1 - x; sign = odd_x ? -1.0 : 1.0; }
     else if (x >= s->nx) { x = 2 * s->nx - 1 - x; sign = odd_x ? -1.0 : 1.0; }
+  } else if (s->wall_x == 2) {
+    if (x < 0) x = 0;
+    else if (x >= s->nx) x = s->nx - 1;
   } else {
     x = wrap(x, s->nx);
   }
@@ -549,6 +567,14 @@ static void compute_nonlocal(oracle_sim *s)
           node_field_ctx phi = {s, s->Phi + (long)k * n, k == 0};
           double omega = field_at(s, s->om, x, y, z, 0);
           s->G[gidx(s, k, x, y, z)] = (1.0 / omega - 0.5) * iso_deriv(node_field_get, &phi, x, y, z, k);
+        }
+  /* open x ends: G beyond the boundary is the boundary node's (zero gradient) */
+  if (s->wall_x == 2)
+    for (int k = 0; k < 3; ++k)
+      for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y) {
+          s->G[gidx(s, k, -1, y, z)] = s->G[gidx(s, k, 0, y, z)];
+          s->G[gidx(s, k, nx, y, z)] = s->G[gidx(s, k, nx - 1, y, z)];
         }
   /* X_k = - d_k G_k (eq Xalpha, dt = 1) and the mass-fraction gradients */
 #pragma omp parallel for schedule(static) if (n >= 512)
@@ -754,7 +780,9 @@ static void stream(oracle_sim *s)
             long src = node_index(s, x, y, z);
             double v = POP(s, s->post, l, i, src);
             int xd = x + cvel(i, 0);
-            if (s->wall_x && (xd < 0 || xd >= nx)) {
+            if (s->wall_x == 2 && (xd < 0 || xd >= nx)) {
+              /* open x ends: leaves the domain */
+            } else if (s->wall_x && (xd < 0 || xd >= nx)) {
               POP(s, s->pop, l, opposite(i), src) = v;      /* half-way bounce-back */
             } else {
               long dst = node_index(s, wrap(xd, nx), wrap(y + cvel(i, 1), ny),
@@ -763,6 +791,22 @@ static void stream(oracle_sim *s)
             }
           }
     }
+  if (s->wall_x == 2) {
+    /* open x ends: what enters node 0 from outside is the inlet equilibrium; what
+     * enters node nx-1 from outside comes from a ghost beyond it that holds the
+     * boundary node's post-collision state (zero gradient) */
+    for (int z = 0; z < nz; ++z)
+      for (int l = 0; l < L; ++l) {
+        if (l == s->M - 1 && !s->keep_slaved) continue;
+        for (int i = 0; i < Q; ++i)
+          for (int y = 0; y < ny; ++y) {
+            if (cvel(i, 0) > 0) POP(s, s->pop, l, i, node_index(s, 0, y, z)) = s->fin[l][i];
+            if (cvel(i, 0) < 0)
+              POP(s, s->pop, l, i, node_index(s, nx - 1, y, z)) =
+                  POP(s, s->post, l, i, node_index(s, nx - 1, wrap(y - cvel(i, 1), ny), wrap(z - cvel(i, 2), nz)));
+          }
+      }
+  }
 }
 
 static int one_step(oracle_sim *s)
@@ -813,6 +857,61 @@ int oracle_step(oracle_sim *s, int64_t nsteps)
 /* ------------------------------------------------------------------------- */
 /* Initialisation and read-back                                               */
 /* ------------------------------------------------------------------------- */
+/* Populations of every lattice at the local equilibrium of (X, p, T, u) at one
+ * node, written through put(l, i, value). Returns 0, 1 for invalid fields, 2 for
+ * an infeasible state (R_a T + u^2 >= 1). */
+static int local_equilibrium(const oracle_sim *s, const double *Xa, double Pn, double Tn, const double uu[3],
+                             double out[][Q])
+{
+  const int M = s->M;
+  int bad = 0;
+  double mmix = 0.0, xsum = 0.0;
+  for (int a = 0; a < M; ++a) {
+    mmix += Xa[a] * s->m[a];                 /* m = sum X_a m_a, equivalent to eq meanMolecularWeight */
+    xsum += Xa[a];
+    if (Xa[a] < 0.0) bad = 1;
+  }
+  if (fabs(xsum - 1.0) > 1e-12) bad = 1;
+  if (!(Tn > 0.0) || !(Pn > 0.0)) return 1;
+  double usq = uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2];
+  double R = 1.0 / mmix;
+  double rho = Pn / (R * Tn);                /* eq eosIdealGas */
+  double Y[MAXM], Cv = 0.0, Cp = 0.0;
+  for (int a = 0; a < M; ++a) {
+    Y[a] = Xa[a] * s->m[a] / mmix;           /* eq moleFractionDefinition */
+    Cv += Y[a] * s->cv[a];
+    Cp += Y[a] * (s->cv[a] + 1.0 / s->m[a]);
+  }
+  double rhoE = rho * (Cv * Tn + usq / 2.0);
+  double H = Cp * Tn;
+  if (s->cvt) {                              /* eqs Umix, specH with U_a(T) */
+    double U = 0.0;
+    for (int a = 0; a < M; ++a) U += Y[a] * species_U(s, a, Tn);
+    rhoE = rho * (U + usq / 2.0);
+    H = U + R * Tn;
+  }
+  double psi[Q];
+  for (int a = 0; a < M; ++a) {
+    if (a == M - 1 && !s->keep_slaved) continue;
+    double RaT = Tn / s->m[a];
+    if (!(RaT + usq < 1.0)) bad = 2;
+    oracle_psi(uu, RaT, psi);
+    for (int i = 0; i < Q; ++i) out[a][i] = rho * Y[a] * psi[i];
+  }
+  oracle_psi(uu, R * Tn, psi);
+  for (int i = 0; i < Q; ++i) out[LAT_F(s)][i] = rho * psi[i];
+  double qeq[3], Req[9];
+  for (int a = 0; a < 3; ++a) {
+    qeq[a] = (H + usq / 2.0) * rho * uu[a];
+    for (int b = 0; b < 3; ++b) {
+      double Peq = (a == b ? Pn : 0.0) + rho * uu[a] * uu[b];
+      Req[3 * a + b] = (H + usq / 2.0) * Peq + Pn * uu[a] * uu[b];
+    }
+  }
+  oracle_gansatz(R * Tn, rhoE, qeq, Req, out[LAT_G(s)]);
+  return bad;
+}
+
 int oracle_init_fields(oracle_sim *s, const double *X, const double *p, const double *T,
                        const double *u)
 {
@@ -822,55 +921,15 @@ int oracle_init_fields(oracle_sim *s, const double *X, const double *p, const do
   int bad = 0;
   memset(s->pop, 0, sizeof(double) * (size_t)(M + 2) * Q * n);
   for (long node = 0; node < n; ++node) {
-    double Xa[MAXM], mmix = 0.0, xsum = 0.0;
-    for (int a = 0; a < M; ++a) {
-      Xa[a] = X[(long)a * n + node];
-      mmix += Xa[a] * s->m[a];                 /* m = sum X_a m_a, equivalent to eq meanMolecularWeight */
-      xsum += Xa[a];
-      if (Xa[a] < 0.0) bad = 1;
-    }
-    if (fabs(xsum - 1.0) > 1e-12) bad = 1;
-    double Tn = T[node], Pn = p[node];
-    if (!(Tn > 0.0) || !(Pn > 0.0)) { bad = 1; continue; }
+    double Xa[MAXM], eq[MAXM + 2][Q];
+    memset(eq, 0, sizeof(eq));
+    for (int a = 0; a < M; ++a) Xa[a] = X[(long)a * n + node];
     double uu[3] = {u[node], u[n + node], u[2 * n + node]};
-    double usq = uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2];
-    double R = 1.0 / mmix;
-    double rho = Pn / (R * Tn);                /* eq eosIdealGas */
-    double Y[MAXM], Cv = 0.0, Cp = 0.0;
-    for (int a = 0; a < M; ++a) {
-      Y[a] = Xa[a] * s->m[a] / mmix;           /* eq moleFractionDefinition */
-      Cv += Y[a] * s->cv[a];
-      Cp += Y[a] * (s->cv[a] + 1.0 / s->m[a]);
-    }
-    double rhoE = rho * (Cv * Tn + usq / 2.0);
-    double H = Cp * Tn;
-    if (s->cvt) {                              /* eqs Umix, specH with U_a(T) */
-      double U = 0.0;
-      for (int a = 0; a < M; ++a) U += Y[a] * species_U(s, a, Tn);
-      rhoE = rho * (U + usq / 2.0);
-      H = U + R * Tn;
-    }
-    double psi[Q];
-    for (int a = 0; a < M; ++a) {
-      if (a == M - 1 && !s->keep_slaved) continue;
-      double RaT = Tn / s->m[a];
-      if (!(RaT + usq < 1.0)) bad = 2;
-      oracle_psi(uu, RaT, psi);
-      for (int i = 0; i < Q; ++i) POP(s, s->pop, a, i, node) = rho * Y[a] * psi[i];
-    }
-    oracle_psi(uu, R * Tn, psi);
-    for (int i = 0; i < Q; ++i) POP(s, s->pop, LAT_F(s), i, node) = rho * psi[i];
-    double qeq[3], Req[9];
-    for (int a = 0; a < 3; ++a) {
-      qeq[a] = (H + usq / 2.0) * rho * uu[a];
-      for (int b = 0; b < 3; ++b) {
-        double Peq = (a == b ? Pn : 0.0) + rho * uu[a] * uu[b];
-        Req[3 * a + b] = (H + usq / 2.0) * Peq + Pn * uu[a] * uu[b];
-      }
-    }
-    double g[Q];
-    oracle_gansatz(R * Tn, rhoE, qeq, Req, g);
-    for (int i = 0; i < Q; ++i) POP(s, s->pop, LAT_G(s), i, node) = g[i];
+    int b = local_equilibrium(s, Xa, p[node], T[node], uu, eq);
+    if (b > bad) bad = b;
+    if (b == 1) continue;
+    for (int l = 0; l < M + 2; ++l)
+      for (int i = 0; i < Q; ++i) POP(s, s->pop, l, i, node) = eq[l][i];
   }
   if (bad == 2) return -2;
   return bad ? -1 : 0;

@@ -39,7 +39,9 @@ enum {
 typedef struct {
   int32_t M;            /* number of species, 2..8                                      */
   int32_t nx, ny, nz;   /* lattice size                                                 */
-  int32_t wall_x;       /* 0 periodic in x; 1 half-way bounce-back walls at both x ends */
+  int32_t wall_x;       /* 0 periodic in x; 1 half-way bounce-back walls at both x ends;
+                           2 open x ends: equilibrium inlet at x = 0 (fields `inlet`),
+                           zero-gradient outlet at x = nx - 1                          */
   int32_t keep_slaved;  /* 1: store and evolve the slaved species' lattice literally    */
   int32_t debug_flags;  /* ORACLE_DROP_* planted mistakes (tests only), else 0          */
   int32_t weak;         /* 1: weak coupling (Sec. 3.6.1): all M species lattices evolve
@@ -51,6 +53,7 @@ typedef struct {
   const double *lambda;     /* [M] species thermal conductivities                       */
   const double *cv_coef;    /* NULL: constant cv; else [M][4]: C_{a,v}(T) = sum_k c_k T^k,
                                c_0 > 0, c_k >= 0 (cv is then not used)                  */
+  const double *inlet;      /* wall_x = 2: [M+5] inlet fields X (M), p, T, u (3)        */
 } oracle_params;
 
 typedef struct oracle_sim oracle_sim;

@@ -38,6 +38,7 @@ class _Params(C.Structure):
         ("molar_mass", C.POINTER(C.c_double)), ("cv", C.POINTER(C.c_double)),
         ("D", C.POINTER(C.c_double)), ("mu", C.POINTER(C.c_double)),
         ("lam", C.POINTER(C.c_double)), ("cv_coef", C.POINTER(C.c_double)),
+        ("inlet", C.POINTER(C.c_double)),
     ]
 
 
@@ -176,12 +177,14 @@ class OracleSim:
                         _f64(params["D"]).reshape(-1), _f64(params["mu"]),
                         _f64(params["lambda"])]
         cvc = params.get("cv_coef")
-        if cvc is not None:
-            self._arrays.append(_f64(cvc).reshape(self.M * 4))
+        cvc = None if cvc is None else _f64(cvc).reshape(self.M * 4)
+        inl = params.get("inlet")
+        inl = None if inl is None else _f64(inl).reshape(self.M + 5)
+        self._arrays += [a for a in (cvc, inl) if a is not None]
         p = _Params(self.M, self.nx, self.ny, self.nz, int(params.get("wall_x", 0)),
                     int(keep_slaved), int(debug_flags), int(params.get("weak", 0)),
                     *[_dp(a) for a in self._arrays[:5]],
-                    _dp(self._arrays[5]) if cvc is not None else None)
+                    _dp(cvc) if cvc is not None else None, _dp(inl) if inl is not None else None)
         h = C.c_void_p()
         rc = lib().oracle_create(C.byref(p), C.byref(h))
         if rc != 0:

@@ -1,0 +1,86 @@
+"""Pins of the oracle's open x ends (wall_x = 2): an equilibrium inlet at x = 0,
+whose incoming populations are the local equilibrium of given inlet fields, and
+a zero-gradient outlet at x = nx - 1, whose incoming populations come from a
+ghost holding the boundary node's post-collision state. Populations that leave
+through either end are dropped; the stencils see the boundary node's values
+beyond both ends.
+
+What fixes the results, other than the oracle itself:
+  - a uniform equilibrium flowing through the domain, fed with itself, is a
+    fixed point;
+  - in a binary of equal molar masses at uniform p, T and u (uniform density,
+    so the mole fraction obeys advection-diffusion with D_12), an inflow front
+    converges at second order to the closed-form semi-infinite solution with a
+    flux (third-type) inlet condition, u C_in = u C - D dC/dx: an equilibrium
+    inlet fixes the incoming populations, not the composition at a point. The
+    Dirichlet solution (Ogata-Banks) is five times further off;
+  - fed long enough, the domain holds the inlet state everywhere.
+"""
+import numpy as np
+import pytest
+from scipy.special import erfc
+
+import physics_cases as pc
+from paper_2004_11286_amd import workloads as W
+
+T0 = 1.0 / 3.0
+
+
+def test_uniform_through_flow_is_fixed_point(oracle_mod):
+    params, _ = W.ternary_tube(nx=16, ny=3, nz=2)
+    X, P0, u = [0.3, 0.3, 0.4], params["P0"], (0.05, 0.01, -0.02)
+    params = dict(params, wall_x=2, inlet=np.array(X + [P0, T0] + list(u)))
+    s = oracle_mod.OracleSim(params)
+    s.init_fields(**W.uniform_state(params, 16, 3, 2, X=X, p=P0, T=T0, u=u))
+    p0 = s.populations()
+    s.step(200)
+    p1 = s.populations()
+    stored = [0, 1, 3, 4]                      # the slaved species' lattice is not evolved
+    assert np.abs(p1[stored] - p0[stored]).max() <= 1e-13 * np.abs(p0[stored]).max()
+
+
+def _front(oracle_mod, nx, t, u, D=0.05, c0=0.2, cin=0.8):
+    P = T0 / 20.0
+    params = {"nx": nx, "ny": 1, "nz": 1, "wall_x": 2,
+              **pc.species_block([20.0, 20.0], [1.5, 1.5], [0.5, 0.5], P, D),
+              "inlet": np.array([cin, 1 - cin, P, T0, u, 0.0, 0.0])}
+    s = oracle_mod.OracleSim(params)
+    s.init_fields(**pc.line_fields(2, nx, [c0, 1 - c0], P, T0, (u, 0, 0)))
+    s.step(t)
+    X1 = s.read_moments()["X"][0, 0, 0]
+    x = np.arange(nx, dtype=np.float64) + 0.5          # inlet face half-way before node 0
+    a = 2 * np.sqrt(D * t)
+    flux = (0.5 * erfc((x - u * t) / a) + np.sqrt(u * u * t / (np.pi * D)) * np.exp(-(x - u * t) ** 2 / (4 * D * t))
+            - 0.5 * (1 + u * x / D + u * u * t / D) * np.exp(u * x / D) * erfc((x + u * t) / a))
+    dirichlet = 0.5 * (erfc((x - u * t) / a) + np.exp(u * x / D) * erfc((x + u * t) / a))
+    return (np.abs(X1 - (c0 + (cin - c0) * flux)).max(), np.abs(X1 - (c0 + (cin - c0) * dirichlet)).max())
+
+
+def test_inflow_front_converges_to_flux_inlet_solution(oracle_mod):
+    """Diffusive refinement (nx doubled, u halved, t x 4; the Peclet number u nx / D
+    stays 64): the L-infinity error against the third-type solution falls from
+    0.050 to 0.0079; the Dirichlet solution stays 0.039 off."""
+    e256, _ = _front(oracle_mod, 256, 1600, 0.025)
+    e512, d512 = _front(oracle_mod, 512, 6400, 0.0125)
+    print("flux-inlet error", e256, e512, "Dirichlet", d512)
+    assert e512 < 0.012
+    assert e512 < 0.3 * e256
+    assert d512 > 3 * e512
+
+
+def test_domain_flushes_to_inlet_state(oracle_mod):
+    """Fed with X_1 = 0.8 through the inlet for several flow-through times, the
+    domain holds the inlet composition, velocity and density everywhere."""
+    nx, u = 64, 0.05
+    P = T0 / 20.0
+    params = {"nx": nx, "ny": 1, "nz": 1, "wall_x": 2,
+              **pc.species_block([20.0, 20.0], [1.5, 1.5], [0.5, 0.5], P, 0.05),
+              "inlet": np.array([0.8, 0.2, P, T0, u, 0.0, 0.0])}
+    s = oracle_mod.OracleSim(params)
+    s.init_fields(**pc.line_fields(2, nx, [0.2, 0.8], P, T0, (u, 0, 0)))
+    s.step(6000)
+    m = s.read_moments()
+    print("flushed", np.abs(m["X"][0] - 0.8).max(), np.abs(m["u"][0] - u).max())
+    assert np.abs(m["X"][0] - 0.8).max() < 1e-6
+    assert np.abs(m["u"][0] - u).max() < 1e-6 * u
+    assert np.abs(m["p"] / P - 1).max() < 1e-6
