@@ -69,7 +69,14 @@ typedef struct {
   int32_t M;           /* species count (2, 3 or 4 in this build)                     */
   int32_t nx, ny, nz;  /* lattice size; nx*ny*nz < 2^31                               */
   int32_t wall_x;      /* 0: periodic in x; 1: half-way bounce-back walls at both x ends
-                          (Sec. 4.2); y and z are always periodic                      */
+                          (Sec. 4.2); 2: open x ends, an equilibrium inlet at x = 0 (the
+                          populations entering node 0 are the local equilibrium of the
+                          fields `inlet`) and a zero-gradient outlet at x = nx - 1 (the
+                          populations entering it are the boundary node's post-collision
+                          values), both as in the opposed jets of Sec. 4.5; open ends
+                          are compiled for strong coupling, constant cv, MCLBM_FP64 and
+                          MCLBM_FP32 (else MCLBM_EUNSUPPORTED). y and z are always
+                          periodic                                                     */
   int32_t precision;   /* MCLBM_FP64 .. MCLBM_BF16                                    */
   int32_t weak;        /* 0: strong coupling (Sec. 3.6.2): species M is slaved to the
                           momentum lattice (eqs rhoMATCH, uMATCH) and not stored.
@@ -93,6 +100,8 @@ typedef struct {
                                 eq temperature by Newton's method (Sec. 3.1). Strong
                                 coupling with MCLBM_FP64 or MCLBM_FP32 only (else
                                 MCLBM_EUNSUPPORTED); all tubes of a batch agree on NULL */
+  const double *inlet;       /* wall_x = 2: [M + 5] inlet fields X_1..X_M (sum 1), p, T,
+                                u_x, u_y, u_z (each tube its own); else ignored         */
 } mclbm_params;
 
 /* Device workspace bytes a context with these parameters needs (0 on bad input). */

@@ -100,7 +100,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(moment_wa
                                      rec + (size_t)RecLayout<M, WEAK, CVT>::FIELDS * w.base, w.node);
 }
 
-template <typename Rec, bool W>
+template <typename Rec, int W>
 __global__ __launch_bounds__(BLOCK) void k_gfield(const Params<double>* __restrict__ P, Launch Ln,
                                                   const Rec* __restrict__ rec, Rec* __restrict__ G, int rec_fields)
 {
@@ -114,7 +114,7 @@ __global__ __launch_bounds__(BLOCK) void k_gfield(const Params<double>* __restri
 template <typename S, int M, int V, int PART>
 constexpr int collide_part_waves() { return PART == 0 ? collide_waves<S, M, V>() : 2; }
 
-template <typename S, typename R, typename Rec, int M, bool W, int V, int PART, bool WEAK, bool CVT>
+template <typename S, typename R, typename Rec, int M, int W, int V, int PART, bool WEAK, bool CVT>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(collide_part_waves<S, M, V, PART>()))) void k_collide(const Params<R>* __restrict__ P, Launch Ln, const S* __restrict__ src,
                                                    S* __restrict__ dst, const Rec* __restrict__ rec,
                                                    const Rec* __restrict__ G, StepNo sn)
@@ -272,7 +272,7 @@ void launch_moments(const void* Pd, const Launch& ln, const void* pop, void* rec
                      (const S*)pop, (Rec*)rec);
 }
 
-template <typename S, typename R, typename Rec, int M, bool W, int V, int PART, bool WEAK, bool CVT>
+template <typename S, typename R, typename Rec, int M, int W, int V, int PART, bool WEAK, bool CVT>
 void launch_collide(const void* P, const Launch& ln, const void* src, void* dst, const void* rec, const void* G,
                     StepNo sn, unsigned grid, hipStream_t st)
 {
@@ -280,7 +280,7 @@ void launch_collide(const void* P, const Launch& ln, const void* src, void* dst,
                      (const Params<R>*)P, ln, (const S*)src, (S*)dst, (const Rec*)rec, (const Rec*)G, sn);
 }
 
-template <typename S, typename R, typename Rec, int M, bool W, bool WEAK, bool CVT>
+template <typename S, typename R, typename Rec, int M, int W, bool WEAK, bool CVT>
 Ops make_ops()
 {
   Ops o;
@@ -325,22 +325,36 @@ Ops make_ops()
   return o;
 }
 
+// walls: 0 periodic x, 1 walls at both x ends (BC_PERIODIC, BC_WALLS)
 template <typename S, typename R, typename Rec, bool WEAK, bool CVT = false>
 bool pick_m(int M, int walls, Ops& o)
 {
   switch (M) {
-    case 2: o = walls ? make_ops<S, R, Rec, 2, true, WEAK, CVT>() : make_ops<S, R, Rec, 2, false, WEAK, CVT>(); return true;
-    case 3: o = walls ? make_ops<S, R, Rec, 3, true, WEAK, CVT>() : make_ops<S, R, Rec, 3, false, WEAK, CVT>(); return true;
-    case 4: o = walls ? make_ops<S, R, Rec, 4, true, WEAK, CVT>() : make_ops<S, R, Rec, 4, false, WEAK, CVT>(); return true;
+    case 2: o = walls ? make_ops<S, R, Rec, 2, BC_WALLS, WEAK, CVT>() : make_ops<S, R, Rec, 2, BC_PERIODIC, WEAK, CVT>(); return true;
+    case 3: o = walls ? make_ops<S, R, Rec, 3, BC_WALLS, WEAK, CVT>() : make_ops<S, R, Rec, 3, BC_PERIODIC, WEAK, CVT>(); return true;
+    case 4: o = walls ? make_ops<S, R, Rec, 4, BC_WALLS, WEAK, CVT>() : make_ops<S, R, Rec, 4, BC_PERIODIC, WEAK, CVT>(); return true;
+    default: return false;
+  }
+}
+
+// open x ends (strong coupling, constant heat capacities)
+template <typename S, typename R, typename Rec>
+bool pick_m_open(int M, Ops& o)
+{
+  switch (M) {
+    case 2: o = make_ops<S, R, Rec, 2, BC_OPEN, false, false>(); return true;
+    case 3: o = make_ops<S, R, Rec, 3, BC_OPEN, false, false>(); return true;
+    case 4: o = make_ops<S, R, Rec, 4, BC_OPEN, false, false>(); return true;
     default: return false;
   }
 }
 
 }  // namespace kern
 
-// One entry point per instantiated (storage, arithmetic) pair. weak: 1 for weak
-// coupling; cvt: 1 for temperature-dependent specific heats (each compiled for
-// FP64 and FP32 storage with FP64 arithmetic only, and not together).
+// One entry point per instantiated (storage, arithmetic) pair. walls: the x
+// boundary (0 periodic, 1 walls, 2 open); weak: 1 for weak coupling; cvt: 1 for
+// temperature-dependent specific heats. Open ends, weak coupling and C_v(T) are
+// compiled for FP64 and FP32 storage with FP64 arithmetic only, one at a time.
 bool pick_fp64(int M, int walls, int weak, int cvt, kern::Ops& o);
 bool pick_fp32_fp64(int M, int walls, int weak, int cvt, kern::Ops& o);
 bool pick_fp32(int M, int walls, int weak, int cvt, kern::Ops& o);

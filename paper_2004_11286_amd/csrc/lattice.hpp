@@ -84,6 +84,7 @@ struct Params {
   R ref0[MAXL];           // sum_i f_ref (zeroth moment)
   R ref2[MAXL];           // sum_i f_ref c_ia^2 (diagonal second moment, isotropic)
   R scale[MAXL], inv_scale[MAXL];
+  R inl[MAXL][Q];         // open x ends: inlet equilibrium minus f_ref, per stored lattice
   R absent_tol;           // |rho_a| <= absent_tol * rho: species absent, V_a = 0
 };
 

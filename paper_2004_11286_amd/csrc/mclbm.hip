@@ -159,6 +159,7 @@ struct TubeHost {
   HostSpecies hs{};
   double ref[MAXL][Q] = {};
   double ref0[MAXL] = {}, ref2[MAXL] = {}, scale[MAXL] = {};
+  double inlet[MAXM + 5] = {};   // open x ends: X (M), p, T, u (3)
 };
 
 }  // namespace
@@ -285,7 +286,25 @@ int validate_one(const mclbm_params* p, std::string& err)
     err = "nx*ny*nz times the element size must be below 2^32 bytes";
     return MCLBM_EARG;
   }
-  if (p->wall_x != 0 && p->wall_x != 1) { err = "wall_x must be 0 or 1"; return MCLBM_EARG; }
+  if (p->wall_x < 0 || p->wall_x > 2) { err = "wall_x must be 0, 1 or 2"; return MCLBM_EARG; }
+  if (p->wall_x == 2) {
+    if (!p->inlet) { err = "open x ends need the inlet fields"; return MCLBM_EARG; }
+    double xs = 0.0;
+    bool ok = p->inlet[p->M] > 0 && p->inlet[p->M + 1] > 0;
+    for (int k = 0; k < p->M + 5; ++k) ok = ok && std::isfinite(p->inlet[k]);
+    for (int a = 0; a < p->M; ++a) {
+      ok = ok && p->inlet[a] >= 0;
+      xs += p->inlet[a];
+    }
+    if (!ok || std::fabs(xs - 1.0) > 1e-12) {
+      err = "inlet: mole fractions must be non-negative and sum to 1, p and T positive";
+      return MCLBM_EARG;
+    }
+    if (p->weak || p->cv_coef || (p->precision != MCLBM_FP64 && p->precision != MCLBM_FP32)) {
+      err = "open x ends are compiled for strong coupling with constant cv, MCLBM_FP64 and MCLBM_FP32 only";
+      return MCLBM_EUNSUPPORTED;
+    }
+  }
   if (p->wall_x && p->nx < 2) { err = "walls need nx >= 2"; return MCLBM_EARG; }
   if (p->precision < MCLBM_FP64 || p->precision > MCLBM_BF16) { err = "unknown precision"; return MCLBM_EARG; }
   if (p->weak != 0 && p->weak != 1) { err = "weak must be 0 or 1"; return MCLBM_EARG; }
@@ -384,6 +403,29 @@ int push_params(mclbm_ctx* c)
                         tol);
     fill_params<float>(c->hPf[t], th.hs, th.nx, th.ny, th.nz, c->wall_x, c->L, th.ref, th.ref0, th.ref2, th.scale,
                        tol);
+    if (c->wall_x == 2) {
+      // the inlet equilibrium of every stored lattice, as a deviation from f_ref:
+      // the initialisation of one node (n = 1, unit scale) at the inlet fields
+      Params<double> P1 = c->hPd[t];
+      P1.n = 1;
+      for (int l = 0; l < MAXL; ++l) P1.scale[l] = 1.0;
+      double dev[MAXL * Q] = {};
+      const int M = c->M;
+      const double* in = th.inlet;
+      int bad = 1;
+      switch (M) {
+        case 2: bad = init_node<double, 2>(P1, in, in + M, in + M + 1, in + M + 2, dev, 0); break;
+        case 3: bad = init_node<double, 3>(P1, in, in + M, in + M + 1, in + M + 2, dev, 0); break;
+        case 4: bad = init_node<double, 4>(P1, in, in + M, in + M + 1, in + M + 2, dev, 0); break;
+        default: break;
+      }
+      if (bad) return fail(c, MCLBM_ESTATE, "infeasible inlet state (R_a T + u^2 >= 1)");
+      for (int l = 0; l < c->L; ++l)
+        for (int i = 0; i < Q; ++i) {
+          c->hPd[t].inl[l][i] = dev[l * Q + i];
+          c->hPf[t].inl[l][i] = (float)dev[l * Q + i];
+        }
+    }
   }
   HIP_TRY(c, hipMemcpyAsync(c->dPd, c->hPd.data(), sizeof(Params<double>) * c->ntubes, hipMemcpyHostToDevice,
                             c->stream));
@@ -708,6 +750,8 @@ extern "C" int mclbm_batch_create(const mclbm_params* tp, int32_t ntubes, void* 
       for (int k = 0; k < 4; ++k) th.hs.cvc[a][k] = p->cv_coef ? p->cv_coef[a * 4 + k] : (k == 0 ? p->cv[a] : 0.0);
     }
     th.hs.cvt = p->cv_coef != nullptr;
+    if (p->wall_x == 2)
+      for (int k = 0; k < p->M + 5; ++k) th.inlet[k] = p->inlet[k];
   }
   if (!pick_ops(c->precision, c->M, c->wall_x, c->weak, c->cvt, c->ops)) {
     delete c;

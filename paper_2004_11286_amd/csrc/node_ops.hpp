@@ -233,22 +233,28 @@ __host__ __device__ __forceinline__ Nbr neighbours(const Params<R>& P, int64_t n
   return b;
 }
 
-// Stencil neighbour index: at an x wall the ghost node mirrors the boundary node.
-template <bool WALLS>
+// x boundary kinds: periodic, half-way bounce-back walls (Sec. 4.2), or open ends
+// (equilibrium inlet at x = 0, zero-gradient outlet at x = nx - 1).
+enum { BC_PERIODIC = 0, BC_WALLS = 1, BC_OPEN = 2 };
+
+// Stencil neighbour index: beyond an x wall the ghost node mirrors the boundary
+// node; beyond an open end it holds the boundary node's values (zero gradient).
+template <int BC>
 __host__ __device__ __forceinline__ uint32_t stencil_index(const Nbr& b, int ci, int cj, int ck)
 {
   uint32_t xi = b.x[ci + 1];
-  if (WALLS) {
+  if (BC != BC_PERIODIC) {
     if (ci < 0 && b.lo) xi = b.x[1];
     if (ci > 0 && b.hi) xi = b.x[1];
   }
   return xi + b.y[cj + 1] + b.z[ck + 1];
 }
 
-template <bool WALLS>
+// A mirrored wall ghost (odd fields change sign there; not at open ends).
+template <int BC>
 __host__ __device__ __forceinline__ bool is_ghost(const Nbr& b, int ci)
 {
-  return WALLS && ((ci < 0 && b.lo) || (ci > 0 && b.hi));
+  return BC == BC_WALLS && ((ci < 0 && b.lo) || (ci > 0 && b.hi));
 }
 
 // --------------------------------------------------------------------------
@@ -463,7 +469,7 @@ __host__ __device__ __forceinline__ void state_node(const Params<double>& P, con
 // --------------------------------------------------------------------------
 // Pass 2: G_a = (1/omega - 1/2) d_a Phi_a, with d_a = 3 sum_i w_i c_ia (.)(x + c_i)
 // --------------------------------------------------------------------------
-template <typename R, bool WALLS>
+template <typename R, int BC>
 __host__ __device__ __forceinline__ void gfield_node(const Params<double>& P, const R* __restrict__ rec,
                                             R* __restrict__ G, int64_t node)
 {
@@ -474,11 +480,11 @@ __host__ __device__ __forceinline__ void gfield_node(const Params<double>& P, co
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     if (csq(i) == 0) continue;
-    const uint32_t nb = stencil_index<WALLS>(b, cx(i), cy(i), cz(i));
+    const uint32_t nb = stencil_index<BC>(b, cx(i), cy(i), cz(i));
     const R w3 = R(3.0 * w13(i));
     if (cx(i)) {
       R v = *at32(rec + (size_t)REC_PHIX * n, nb);
-      if (is_ghost<WALLS>(b, cx(i))) v = -v;        // Phi_x is odd under the wall mirror
+      if (is_ghost<BC>(b, cx(i))) v = -v;           // Phi_x is odd under the wall mirror
       dphi[0] += cx(i) > 0 ? w3 * v : -(w3 * v);
     }
     if (cy(i)) {
@@ -555,13 +561,20 @@ __host__ __device__ __forceinline__ R from_store(const Params<R>& P, int l, S v)
 }
 
 // Streaming: write the post-collision value of direction i to the neighbour
-// x + c_i of the other buffer, or bounce it back at an x wall.
-template <typename S, typename R, bool WALLS>
+// x + c_i of the other buffer, or bounce it back at an x wall. At open ends a
+// value leaving the domain is dropped, and the outlet's ghost (beyond x = nx - 1,
+// holding the boundary node's post-collision state) sends the values with
+// c_x < 0 into the boundary node's neighbours in y and z.
+template <typename S, typename R, int BC>
 __host__ __device__ __forceinline__ void push(const Params<R>& P, S* __restrict__ dst, const Nbr& b, int l, int i,
                                      int64_t node, S v)
 {
   const size_t n = (size_t)P.n;
-  if (WALLS && ((cx(i) < 0 && b.lo) || (cx(i) > 0 && b.hi))) {
+  if (BC == BC_OPEN && cx(i) < 0 && b.hi)
+    dst[(size_t)(l * Q + i) * n + (b.x[1] + b.y[cy(i) + 1] + b.z[cz(i) + 1])] = v;
+  if (BC == BC_OPEN && ((cx(i) < 0 && b.lo) || (cx(i) > 0 && b.hi))) {
+    // leaves through an open end
+  } else if (BC == BC_WALLS && ((cx(i) < 0 && b.lo) || (cx(i) > 0 && b.hi))) {
     dst[(size_t)(l * Q + opp(i)) * n + node] = v;    // half-way bounce-back
   } else {
     const int64_t d = (int64_t)b.x[cx(i) + 1] + b.y[cy(i) + 1] + b.z[cz(i) + 1];
@@ -586,7 +599,22 @@ __host__ __device__ __forceinline__ void load_lattice(const S* __restrict__ lat,
 
 // PART selects the lattices: 0 all, 1 the stored species lattices, 2 the momentum
 // and energy lattices (a split collision in two launches computes the same step).
-template <typename S, typename R, typename Rec, int M, bool WALLS, int PART = 0, bool WEAK = false, bool CVT = false>
+// The populations entering an equilibrium inlet (node x = 0, c_x > 0) of lattice l:
+// the stored inlet equilibrium.
+template <typename S, typename R, int BC>
+__host__ __device__ __forceinline__ void inlet(const Params<R>& P, S* __restrict__ dst, const Nbr& b, int l,
+                                      int64_t node, Rng& rng)
+{
+  if constexpr (BC == BC_OPEN) {
+    if (b.lo) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+        if (cx(i) > 0) dst[(size_t)(l * Q + i) * (size_t)P.n + node] = to_store<S, R>(P, l, P.inl[l][i], rng);
+    }
+  }
+}
+
+template <typename S, typename R, typename Rec, int M, int BC, int PART = 0, bool WEAK = false, bool CVT = false>
 __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const S* __restrict__ src,
                                              S* __restrict__ dst, const Rec* __restrict__ rec,
                                              const Rec* __restrict__ G, int64_t node, uint32_t step)
@@ -664,7 +692,7 @@ __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const 
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     if (csq(i) == 0) continue;
-    const uint32_t nb = stencil_index<WALLS>(b, cx(i), cy(i), cz(i));
+    const uint32_t nb = stencil_index<BC>(b, cx(i), cy(i), cz(i));
     const R w3 = R(3.0 * w13(i));
     if constexpr (CVT) {
 #pragma unroll
@@ -761,7 +789,8 @@ __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const 
       // the arithmetic and of the other 26 values' rounding to storage
       v[13] = to_store<S, R>(P, a, t0 - s0, rng);
 #pragma unroll
-      for (int i = 0; i < Q; ++i) push<S, R, WALLS>(P, dst, b, a, i, node, v[i]);
+      for (int i = 0; i < Q; ++i) push<S, R, BC>(P, dst, b, a, i, node, v[i]);
+      inlet<S, R, BC>(P, dst, b, a, node, rng);
       lattice_barrier();
     }
   }
@@ -820,7 +849,8 @@ __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const 
     }
     v[13] = to_store<S, R>(P, LF, t0 - s0, rng);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) push<S, R, WALLS>(P, dst, b, LF, i, node, v[i]);
+    for (int i = 0; i < Q; ++i) push<S, R, BC>(P, dst, b, LF, i, node, v[i]);
+    inlet<S, R, BC>(P, dst, b, LF, node, rng);
     lattice_barrier();
   }
 
@@ -903,7 +933,8 @@ __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const 
     // the collision conserves rho E: the rest population takes the defect
     v[13] = to_store<S, R>(P, LG, t0 - s0, rng);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) push<S, R, WALLS>(P, dst, b, LG, i, node, v[i]);
+    for (int i = 0; i < Q; ++i) push<S, R, BC>(P, dst, b, LG, i, node, v[i]);
+    inlet<S, R, BC>(P, dst, b, LG, node, rng);
   }
 }
 

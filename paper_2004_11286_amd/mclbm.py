@@ -58,6 +58,7 @@ class mclbm_params(C.Structure):
         ("molar_mass", C.POINTER(C.c_double)), ("cv", C.POINTER(C.c_double)),
         ("D", C.POINTER(C.c_double)), ("mu", C.POINTER(C.c_double)),
         ("lam", C.POINTER(C.c_double)), ("cv_coef", C.POINTER(C.c_double)),
+        ("inlet", C.POINTER(C.c_double)),
     ]
 
 
@@ -165,12 +166,15 @@ def make_params(params: dict, precision: int):
             _f64(params["mu"]), _f64(params["lambda"])]
     dp = C.POINTER(C.c_double)
     cvc = params.get("cv_coef")
-    if cvc is not None:
-        arrs.append(_f64(cvc).reshape(M * 4))
+    cvc = None if cvc is None else _f64(cvc).reshape(M * 4)
+    inl = params.get("inlet")
+    inl = None if inl is None else _f64(inl).reshape(M + 5)
+    arrs += [a for a in (cvc, inl) if a is not None]
     p = mclbm_params(M, int(params["nx"]), int(params["ny"]), int(params["nz"]),
                      int(params.get("wall_x", 0)), int(precision), int(params.get("weak", 0)), 0,
                      *[a.ctypes.data_as(dp) for a in arrs[:5]],
-                     arrs[5].ctypes.data_as(dp) if cvc is not None else None)
+                     cvc.ctypes.data_as(dp) if cvc is not None else None,
+                     inl.ctypes.data_as(dp) if inl is not None else None)
     return p, arrs
 
 
