@@ -391,6 +391,24 @@ def main():
         del v
         torch.cuda.empty_cache()
 
+    open_x = None
+    if not args.no_variants:
+        # open x ends: the same 256^3 binary fields carried through the domain by a
+        # mean flow u_x = 0.05, fed at x = 0 with the mean composition and state
+        Xm = [float(fields["X"][a].mean()) for a in range(M)]
+        Xm[-1] = 1.0 - sum(Xm[:-1])
+        op_ = dict(params, wall_x=2,
+                   inlet=np.array(Xm + [float(fields["p"].mean()), float(fields["T"].mean()), 0.05, 0.0, 0.0]))
+        of = dict(fields, u=fields["u"] + np.array([0.05, 0.0, 0.0])[:, None, None, None])
+        v, el, st = time_run(mc, op_, of, prec, args.steps, args.warmup)
+        oc = st["k_collide"]["avg_ms"]
+        open_x = {"MLUPS": n * args.steps / el / 1e6, "ms_per_step": el / args.steps * 1e3, "collide_avg_ms": oc,
+                  "collide_GBs": ab["k_collide"] * n / (oc * 1e-3) / 1e9,
+                  "kernels_avg_ms": {k: x["avg_ms"] for k, x in st.items()}}
+        v.close()
+        del v
+        torch.cuda.empty_cache()
+
     ensemble = None if args.no_ensemble else ensemble_bench(mc)
     surrogate = None if args.no_surrogate else surrogate_bench(args.surrogate_iters)
     cpu = None if args.no_cpu else cpu_baseline()
@@ -425,6 +443,7 @@ def main():
         "variants": variants,
         "weak_coupling": weak,
         "cv_of_T": cv_of_T,
+        "open_x": open_x,
         "ensemble": ensemble,
         "surrogate": surrogate,
         "cpu_baseline": cpu,
