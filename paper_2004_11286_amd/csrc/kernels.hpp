@@ -129,6 +129,17 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(collide_p
   }
 }
 
+// Open x ends: rewrite the populations entering the two boundary planes after
+// the collision (a launch over all nodes; only x = 0 and x = nx - 1 write).
+template <typename S, typename R, int M>
+__global__ __launch_bounds__(BLOCK) void k_open_fix(const Params<R>* __restrict__ P, Launch Ln, S* __restrict__ dst,
+                                                    StepNo sn)
+{
+  const Where w = locate(Ln);
+  const Params<R>& Pt = P[w.t];
+  if (w.node < Pt.n) open_fix_node<S, R, Lat<M, false>::L>(Pt, dst + pop_stride<M, false>() * w.base, w.node, step_of(sn));
+}
+
 template <typename T>
 __device__ inline T* seg(T* p, int64_t off) { return p ? p + off : p; }
 
@@ -261,6 +272,8 @@ struct Ops {
                      hipStream_t st);
   void (*init)(const void* Pd, const Launch& ln, const double* X, const double* p, const double* T,
                const double* u, void* pop, int* bad, unsigned grid, hipStream_t st);
+  // open x ends only (else null): after each collision, on its destination buffer
+  void (*open_fix)(const void* P, const Launch& ln, void* dst, StepNo sn, unsigned grid, hipStream_t st);
   void (*field_sums)(const int64_t* tube_n, const Launch& ln, const double* X, const double* p, const double* T,
                      double* partial, unsigned grid, hipStream_t st);
 };
@@ -322,6 +335,12 @@ Ops make_ops()
                     double* partial, unsigned grid, hipStream_t st) {
     hipLaunchKernelGGL((k_field_sums<M>), dim3(grid), dim3(RED_BLOCK), 0, st, tube_n, ln, X, p, T, partial);
   };
+  o.open_fix = nullptr;
+  if constexpr (W == BC_OPEN) {
+    o.open_fix = [](const void* P, const Launch& ln, void* dst, StepNo sn, unsigned grid, hipStream_t st) {
+      hipLaunchKernelGGL((k_open_fix<S, R, M>), dim3(grid), dim3(BLOCK), 0, st, (const Params<R>*)P, ln, (S*)dst, sn);
+    };
+  }
   return o;
 }
 

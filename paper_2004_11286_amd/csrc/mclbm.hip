@@ -587,6 +587,7 @@ void collide(mclbm_ctx* c, const Launch& ln, int from, StepNo sn, unsigned grid,
   } else {
     c->ops.collide[c->lc.variant](c->dPr, ln, c->pop[from], c->pop[1 - from], c->rec, c->G, sn, grid, st);
   }
+  if (c->ops.open_fix) c->ops.open_fix(c->dPr, ln, c->pop[1 - from], sn, grid, st);
 }
 
 // The launches of one step from buffer `from` on stream st.

@@ -561,20 +561,15 @@ __host__ __device__ __forceinline__ R from_store(const Params<R>& P, int l, S v)
 }
 
 // Streaming: write the post-collision value of direction i to the neighbour
-// x + c_i of the other buffer, or bounce it back at an x wall. At open ends a
-// value leaving the domain is dropped, and the outlet's ghost (beyond x = nx - 1,
-// holding the boundary node's post-collision state) sends the values with
-// c_x < 0 into the boundary node's neighbours in y and z.
+// x + c_i of the other buffer, or bounce it back at an x wall. Open ends stream
+// as periodic here; open_fix_node then rewrites what enters the two boundary
+// planes (the wrapped values are exactly the ones an open end drops).
 template <typename S, typename R, int BC>
 __host__ __device__ __forceinline__ void push(const Params<R>& P, S* __restrict__ dst, const Nbr& b, int l, int i,
                                      int64_t node, S v)
 {
   const size_t n = (size_t)P.n;
-  if (BC == BC_OPEN && cx(i) < 0 && b.hi)
-    dst[(size_t)(l * Q + i) * n + (b.x[1] + b.y[cy(i) + 1] + b.z[cz(i) + 1])] = v;
-  if (BC == BC_OPEN && ((cx(i) < 0 && b.lo) || (cx(i) > 0 && b.hi))) {
-    // leaves through an open end
-  } else if (BC == BC_WALLS && ((cx(i) < 0 && b.lo) || (cx(i) > 0 && b.hi))) {
+  if (BC == BC_WALLS && ((cx(i) < 0 && b.lo) || (cx(i) > 0 && b.hi))) {
     dst[(size_t)(l * Q + opp(i)) * n + node] = v;    // half-way bounce-back
   } else {
     const int64_t d = (int64_t)b.x[cx(i) + 1] + b.y[cy(i) + 1] + b.z[cz(i) + 1];
@@ -599,18 +594,33 @@ __host__ __device__ __forceinline__ void load_lattice(const S* __restrict__ lat,
 
 // PART selects the lattices: 0 all, 1 the stored species lattices, 2 the momentum
 // and energy lattices (a split collision in two launches computes the same step).
-// The populations entering an equilibrium inlet (node x = 0, c_x > 0) of lattice l:
-// the stored inlet equilibrium.
-template <typename S, typename R, int BC>
-__host__ __device__ __forceinline__ void inlet(const Params<R>& P, S* __restrict__ dst, const Nbr& b, int l,
-                                      int64_t node, Rng& rng)
+// Open x ends, after the collision has streamed periodically into dst: what
+// enters node x = 0 (c_x > 0) is the stored inlet equilibrium; what enters node
+// x = nx - 1 (c_x < 0) comes from a ghost beyond it holding the boundary node's
+// post-collision state, i.e. the value that node pushed into x = nx - 2 at the
+// same (y, z). Reads x = nx - 2 and writes x = 0 and x = nx - 1 in disjoint
+// directions (nx >= 2), so the nodes of a launch do not interfere.
+template <typename S, typename R, int L>
+__host__ __device__ __forceinline__ void open_fix_node(const Params<R>& P, S* __restrict__ dst, int64_t node,
+                                              uint32_t step)
 {
-  if constexpr (BC == BC_OPEN) {
-    if (b.lo) {
+  const size_t n = (size_t)P.n;
+  const uint32_t x = (uint32_t)node % (uint32_t)P.nx;
+  if (x == 0) {
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+      Rng rng(node, l + 16, step);
 #pragma unroll
       for (int i = 0; i < Q; ++i)
-        if (cx(i) > 0) dst[(size_t)(l * Q + i) * (size_t)P.n + node] = to_store<S, R>(P, l, P.inl[l][i], rng);
+        if (cx(i) > 0) dst[(size_t)(l * Q + i) * n + node] = to_store<S, R>(P, l, P.inl[l][i], rng);
     }
+  }
+  if (x == (uint32_t)P.nx - 1) {
+#pragma unroll
+    for (int l = 0; l < L; ++l)
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+        if (cx(i) < 0) dst[(size_t)(l * Q + i) * n + node] = dst[(size_t)(l * Q + i) * n + node - 1];
   }
 }
 
@@ -790,7 +800,6 @@ __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const 
       v[13] = to_store<S, R>(P, a, t0 - s0, rng);
 #pragma unroll
       for (int i = 0; i < Q; ++i) push<S, R, BC>(P, dst, b, a, i, node, v[i]);
-      inlet<S, R, BC>(P, dst, b, a, node, rng);
       lattice_barrier();
     }
   }
@@ -850,7 +859,6 @@ __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const 
     v[13] = to_store<S, R>(P, LF, t0 - s0, rng);
 #pragma unroll
     for (int i = 0; i < Q; ++i) push<S, R, BC>(P, dst, b, LF, i, node, v[i]);
-    inlet<S, R, BC>(P, dst, b, LF, node, rng);
     lattice_barrier();
   }
 
@@ -934,7 +942,6 @@ __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const 
     v[13] = to_store<S, R>(P, LG, t0 - s0, rng);
 #pragma unroll
     for (int i = 0; i < Q; ++i) push<S, R, BC>(P, dst, b, LG, i, node, v[i]);
-    inlet<S, R, BC>(P, dst, b, LG, node, rng);
   }
 }
 
