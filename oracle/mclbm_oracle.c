@@ -178,6 +178,8 @@ struct oracle_sim {
   int cvt;                 /* 1: C_{a,v}(T) = sum_k cvc[a][k] T^k, else the constant cv[a] */
   double cvc[MAXM][4];
   double fin[MAXM + 2][Q]; /* open x ends: populations of the inlet equilibrium */
+  int trn;                 /* 1: transport coefficients as powers of T / T_ref */
+  double s_mu[MAXM], s_lam[MAXM], s_D, T_ref;
   double *pop;   /* [(M+2)][Q][n] pre-collision populations */
   double *post;  /* [(M+2)][Q][n] post-collision populations */
   /* node fields used by the non-local terms */
@@ -241,6 +243,19 @@ int oracle_create(const oracle_params *p, oracle_sim **out)
   s->flags = p->debug_flags;
   s->n = (long)p->nx * p->ny * p->nz;
   s->cvt = p->cv_coef ? 1 : 0;
+  s->trn = p->transport_exp ? 1 : 0;
+  if (s->trn) {
+    for (int a = 0; a < s->M; ++a) {
+      s->s_mu[a] = p->transport_exp[a];
+      s->s_lam[a] = p->transport_exp[s->M + a];
+    }
+    s->s_D = p->transport_exp[2 * s->M];
+    s->T_ref = p->transport_exp[2 * s->M + 1];
+    if (!(s->T_ref > 0)) {
+      free(s);
+      return -1;
+    }
+  }
   for (int a = 0; a < s->M; ++a) {
     s->m[a] = p->molar_mass[a];
     s->cv[a] = p->cv[a];
@@ -313,11 +328,29 @@ typedef struct {
   double mu, lam, omega, omega1;
 } state_t;
 
-/* Wilke's factor phi_ab, eq wilkePhi. */
-static double wilke_phi(const oracle_sim *s, int a, int b)
+/* Wilke's factor phi_ab, eq wilkePhi, for species viscosities mu_a, mu_b. */
+static double wilke_phi(const oracle_sim *s, int a, int b, double mu_a, double mu_b)
 {
-  double num = 1.0 + sqrt((s->mu[a] / s->mu[b]) * sqrt(s->m[b] / s->m[a]));
+  double num = 1.0 + sqrt((mu_a / mu_b) * sqrt(s->m[b] / s->m[a]));
   return num * num / (sqrt(8.0) * sqrt(1.0 + s->m[a] / s->m[b]));
+}
+
+/* Species transport coefficients at temperature T: the given constants, or, with
+ * temperature exponents, mu_a (T / T_ref)^s_mu,a, lambda_a (T / T_ref)^s_lam,a and
+ * D_ab (T / T_ref)^s_D. */
+static double species_mu(const oracle_sim *s, int a, double T)
+{
+  return s->trn ? s->mu[a] * pow(T / s->T_ref, s->s_mu[a]) : s->mu[a];
+}
+
+static double species_lam(const oracle_sim *s, int a, double T)
+{
+  return s->trn ? s->lam[a] * pow(T / s->T_ref, s->s_lam[a]) : s->lam[a];
+}
+
+static double diffusivity(const oracle_sim *s, int a, int b, double T)
+{
+  return s->trn ? s->D[a][b] * pow(T / s->T_ref, s->s_D) : s->D[a][b];
 }
 
 /* Specific heat of species a at temperature T (polynomial case), and its
@@ -435,15 +468,20 @@ static void node_state(const oracle_sim *s, const double *pop, long node, state_
     st->H += st->Y[a] * st->Ha[a];                       /* eq specH */
   }
   /* transport, eqs viscosityMixture and conductivityMixture */
+  double mu_a[MAXM], lam_a[MAXM];
+  for (int a = 0; a < M; ++a) {
+    mu_a[a] = species_mu(s, a, st->T);
+    lam_a[a] = species_lam(s, a, st->T);
+  }
   for (int a = 0; a < M; ++a) {
     double den = 0.0;
-    for (int b = 0; b < M; ++b) den += wilke_phi(s, a, b) * st->X[b];
-    st->mu += s->mu[a] * st->X[a] / den;
+    for (int b = 0; b < M; ++b) den += wilke_phi(s, a, b, mu_a[a], mu_a[b]) * st->X[b];
+    st->mu += mu_a[a] * st->X[a] / den;
   }
   double lin = 0.0, harm = 0.0;
   for (int a = 0; a < M; ++a) {
-    lin += st->X[a] * s->lam[a];
-    harm += st->X[a] / s->lam[a];
+    lin += st->X[a] * lam_a[a];
+    harm += st->X[a] / lam_a[a];
   }
   st->lam = 0.5 * (lin + 1.0 / harm);
   st->omega = 2.0 * st->P / (st->P + 2.0 * st->mu);                     /* eq omega  */
@@ -656,9 +694,10 @@ static void species_rates(const oracle_sim *s, const state_t *st, double inv_tau
   for (int a = 0; a < M; ++a) {
     double inv_tau_a = 0.0;
     for (int b = 0; b < M; ++b) {
-      inv_tau[a][b] = (st->T / s->D[a][b]) * (st->mmix / (s->m[a] * s->m[b]));
+      const double Dab = diffusivity(s, a, b, st->T);
+      inv_tau[a][b] = (st->T / Dab) * (st->mmix / (s->m[a] * s->m[b]));
       inv_tau_a += st->Y[b] * inv_tau[a][b];             /* eq tau */
-      K[a][b] = st->Ps * st->X[a] * st->X[b] / s->D[a][b];
+      K[a][b] = st->Ps * st->X[a] * st->X[b] / Dab;
     }
     double tau_a = 1.0 / inv_tau_a;
     beta[a] = 1.0 / (2.0 * tau_a + 1.0);

@@ -54,6 +54,9 @@ typedef struct {
   const double *cv_coef;    /* NULL: constant cv; else [M][4]: C_{a,v}(T) = sum_k c_k T^k,
                                c_0 > 0, c_k >= 0 (cv is then not used)                  */
   const double *inlet;      /* wall_x = 2: [M+5] inlet fields X (M), p, T, u (3)        */
+  const double *transport_exp; /* NULL: constant transport coefficients; else [2M+2]:
+                               s_mu (M), s_lam (M), s_D, T_ref: mu_a (T/T_ref)^s_mu,a,
+                               lambda_a (T/T_ref)^s_lam,a, D_ab (T/T_ref)^s_D          */
 } oracle_params;
 
 typedef struct oracle_sim oracle_sim;

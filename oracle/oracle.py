@@ -38,7 +38,7 @@ class _Params(C.Structure):
         ("molar_mass", C.POINTER(C.c_double)), ("cv", C.POINTER(C.c_double)),
         ("D", C.POINTER(C.c_double)), ("mu", C.POINTER(C.c_double)),
         ("lam", C.POINTER(C.c_double)), ("cv_coef", C.POINTER(C.c_double)),
-        ("inlet", C.POINTER(C.c_double)),
+        ("inlet", C.POINTER(C.c_double)), ("transport_exp", C.POINTER(C.c_double)),
     ]
 
 
@@ -180,11 +180,13 @@ class OracleSim:
         cvc = None if cvc is None else _f64(cvc).reshape(self.M * 4)
         inl = params.get("inlet")
         inl = None if inl is None else _f64(inl).reshape(self.M + 5)
-        self._arrays += [a for a in (cvc, inl) if a is not None]
+        tex = params.get("transport_exp")
+        tex = None if tex is None else _f64(tex).reshape(2 * self.M + 2)
+        self._arrays += [a for a in (cvc, inl, tex) if a is not None]
         p = _Params(self.M, self.nx, self.ny, self.nz, int(params.get("wall_x", 0)),
                     int(keep_slaved), int(debug_flags), int(params.get("weak", 0)),
                     *[_dp(a) for a in self._arrays[:5]],
-                    _dp(cvc) if cvc is not None else None, _dp(inl) if inl is not None else None)
+                    *[_dp(a) if a is not None else None for a in (cvc, inl, tex)])
         h = C.c_void_p()
         rc = lib().oracle_create(C.byref(p), C.byref(h))
         if rc != 0:
