@@ -102,6 +102,12 @@ typedef struct {
                                 MCLBM_EUNSUPPORTED); all tubes of a batch agree on NULL */
   const double *inlet;       /* wall_x = 2: [M + 5] inlet fields X_1..X_M (sum 1), p, T,
                                 u_x, u_y, u_z (each tube its own); else ignored         */
+  const double *transport_exp; /* NULL: constant mu, lambda, D. Else [2M + 2]: s_mu (M),
+                                s_lam (M), s_D, T_ref > 0, giving mu_a (T/T_ref)^s_mu,a,
+                                lambda_a (T/T_ref)^s_lam,a, D_ab (T/T_ref)^s_D at the
+                                local T (the given mu, lambda, D are the values at
+                                T_ref); Wilke's phi from the viscosities at T. Same
+                                support and batch rule as cv_coef                      */
 } mclbm_params;
 
 /* Device workspace bytes a context with these parameters needs (0 on bad input). */

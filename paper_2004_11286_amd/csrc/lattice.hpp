@@ -78,6 +78,7 @@ struct Params {
   R m[MAXM], inv_m[MAXM], cv[MAXM], cp[MAXM];
   R mu[MAXM], lam[MAXM], inv_lam[MAXM];
   R cvc[MAXM][4];         // C_{a,v}(T) = sum_k cvc[a][k] T^k (temperature-dependent kernels only)
+  R s_mu[MAXM], s_lam[MAXM], s_D, T_ref;   // transport exponents about T_ref (same kernels)
   R invD[MAXM][MAXM];     // 1 / D_ab
   R phi[MAXM][MAXM];      // Wilke's phi_ab
   R ref[MAXL][Q];         // reference populations f_ref

@@ -235,7 +235,8 @@ size_t record_bytes(int precision) { return precision == MCLBM_FP64 ? 8 : 4; }
 
 Layout layout_for(const mclbm_params* tp, int ntubes)
 {
-  const int M = tp[0].M, precision = tp[0].precision, weak = tp[0].weak, cvt = tp[0].cv_coef != nullptr;
+  const int M = tp[0].M, precision = tp[0].precision, weak = tp[0].weak;
+  const int cvt = tp[0].cv_coef != nullptr || tp[0].transport_exp != nullptr;
   Layout l{};
   l.n = 0;
   l.nblocks = 0;
@@ -300,8 +301,9 @@ int validate_one(const mclbm_params* p, std::string& err)
       err = "inlet: mole fractions must be non-negative and sum to 1, p and T positive";
       return MCLBM_EARG;
     }
-    if (p->weak || p->cv_coef || (p->precision != MCLBM_FP64 && p->precision != MCLBM_FP32)) {
-      err = "open x ends are compiled for strong coupling with constant cv, MCLBM_FP64 and MCLBM_FP32 only";
+    if (p->weak || p->cv_coef || p->transport_exp || (p->precision != MCLBM_FP64 && p->precision != MCLBM_FP32)) {
+      err = "open x ends are compiled for strong coupling with constant cv and transport, MCLBM_FP64 and "
+            "MCLBM_FP32 only";
       return MCLBM_EUNSUPPORTED;
     }
   }
@@ -312,6 +314,19 @@ int validate_one(const mclbm_params* p, std::string& err)
   if (p->weak && p->precision != MCLBM_FP64 && p->precision != MCLBM_FP32) {
     err = "weak coupling is compiled for MCLBM_FP64 and MCLBM_FP32 only";
     return MCLBM_EUNSUPPORTED;
+  }
+  if (p->transport_exp) {
+    bool ok = p->transport_exp[2 * p->M + 1] > 0;
+    for (int k = 0; k < 2 * p->M + 2; ++k) ok = ok && std::isfinite(p->transport_exp[k]);
+    if (!ok) {
+      err = "transport_exp: exponents must be finite and T_ref positive";
+      return MCLBM_EARG;
+    }
+    if (p->weak || (p->precision != MCLBM_FP64 && p->precision != MCLBM_FP32)) {
+      err = "temperature-dependent transport is compiled for strong coupling with MCLBM_FP64 and MCLBM_FP32 "
+            "only";
+      return MCLBM_EUNSUPPORTED;
+    }
   }
   if (p->cv_coef) {
     for (int a = 0; a < p->M; ++a)
@@ -354,8 +369,10 @@ int validate(const mclbm_params* tp, int ntubes, std::string& err)
       return rc;
     }
     if (tp[t].M != tp[0].M || tp[t].wall_x != tp[0].wall_x || tp[t].precision != tp[0].precision ||
-        tp[t].weak != tp[0].weak || (tp[t].cv_coef == nullptr) != (tp[0].cv_coef == nullptr)) {
-      err = "all tubes of a batch must share M, wall_x, precision, weak and whether cv_coef is given";
+        tp[t].weak != tp[0].weak || (tp[t].cv_coef == nullptr) != (tp[0].cv_coef == nullptr) ||
+        (tp[t].transport_exp == nullptr) != (tp[0].transport_exp == nullptr)) {
+      err = "all tubes of a batch must share M, wall_x, precision, weak and whether cv_coef and transport_exp are "
+            "given";
       return MCLBM_EARG;
     }
     const int64_t n = (int64_t)tp[t].nx * tp[t].ny * tp[t].nz;
@@ -720,7 +737,7 @@ extern "C" int mclbm_batch_create(const mclbm_params* tp, int32_t ntubes, void* 
   c->wall_x = tp[0].wall_x;
   c->precision = tp[0].precision;
   c->weak = tp[0].weak;
-  c->cvt = tp[0].cv_coef != nullptr;
+  c->cvt = tp[0].cv_coef != nullptr || tp[0].transport_exp != nullptr;
   c->L = (c->weak ? c->M : c->M - 1) + 2;
   if (c->weak) {
     // four or more stored lattices: the split collision (two launches with fewer
@@ -751,6 +768,12 @@ extern "C" int mclbm_batch_create(const mclbm_params* tp, int32_t ntubes, void* 
       for (int k = 0; k < 4; ++k) th.hs.cvc[a][k] = p->cv_coef ? p->cv_coef[a * 4 + k] : (k == 0 ? p->cv[a] : 0.0);
     }
     th.hs.cvt = p->cv_coef != nullptr;
+    for (int a = 0; a < p->M; ++a) {
+      th.hs.s_mu[a] = p->transport_exp ? p->transport_exp[a] : 0.0;
+      th.hs.s_lam[a] = p->transport_exp ? p->transport_exp[p->M + a] : 0.0;
+    }
+    th.hs.s_D = p->transport_exp ? p->transport_exp[2 * p->M] : 0.0;
+    th.hs.T_ref = p->transport_exp ? p->transport_exp[2 * p->M + 1] : 1.0;
     if (p->wall_x == 2)
       for (int k = 0; k < p->M + 5; ++k) th.inlet[k] = p->inlet[k];
   }

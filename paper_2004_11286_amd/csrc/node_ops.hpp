@@ -171,6 +171,42 @@ __host__ __device__ __forceinline__ R mixture_viscosity(const Params<R>& P, cons
   return mu;
 }
 
+// The same at temperature T with temperature-dependent transport (R19):
+// mu_a (T/T_ref)^s_mu,a in Wilke's rule, with phi_ab (eq wilkePhi) from those
+// viscosities, and lambda_a (T/T_ref)^s_lam,a in Mathur's rule.
+template <typename R, int M>
+__host__ __device__ __forceinline__ void mixture_transport_T(const Params<R>& P, const R X[M], R T, R& mu, R& lam)
+{
+  const R lt = log(T / P.T_ref);
+  R mua[M], lin = R(0), harm = R(0);
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    mua[a] = P.mu[a] * exp(P.s_mu[a] * lt);
+    const R la = P.lam[a] * exp(P.s_lam[a] * lt);
+    lin += X[a] * la;
+    harm += X[a] / la;
+  }
+  mu = R(0);
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    R den = R(0);
+#pragma unroll
+    for (int b = 0; b < M; ++b) {
+      const R num = R(1) + sqrt((mua[a] / mua[b]) * sqrt(P.m[b] / P.m[a]));
+      den += num * num / (sqrt(R(8)) * sqrt(R(1) + P.m[a] / P.m[b])) * X[b];
+    }
+    mu += mua[a] * X[a] / den;
+  }
+  lam = R(0.5) * (lin + R(1) / harm);
+}
+
+// 1 / D_ab(T) = (1 / D_ab) (T_ref / T)^s_D: the factor (T_ref / T)^s_D.
+template <typename R>
+__host__ __device__ __forceinline__ R inv_diffusivity_factor(const Params<R>& P, R T)
+{
+  return exp(-P.s_D * log(T / P.T_ref));
+}
+
 template <typename R, int M>
 __host__ __device__ __forceinline__ R mixture_conductivity(const Params<R>& P, const R X[M])
 {
@@ -416,11 +452,19 @@ __host__ __device__ __forceinline__ void state_node(const Params<double>& P, con
   bool present[M];
   species_present<D, M>(P, s.rho_a, s.rho, present);
   D K[M][M], V[M][3];
+  if constexpr (CVT) Pk *= inv_diffusivity_factor<D>(P, s.T);   // K_ab = P X_a X_b / D_ab(T)
   friction_matrix<D, M>(P, s, Pk, present, K);
   diffusion_velocities<D, M>(s, present, K, js, us, V);
   const D theta = s.Rg * s.T;
-  const D omega = 2.0 * s.P / (s.P + 2.0 * mixture_viscosity<D, M>(P, s.X));
-  const D omega1 = 2.0 * s.P * s.Cp / (s.P * s.Cp + 2.0 * mixture_conductivity<D, M>(P, s.X));
+  D mu_mix, lam_mix;
+  if constexpr (CVT) {
+    mixture_transport_T<D, M>(P, s.X, s.T, mu_mix, lam_mix);
+  } else {
+    mu_mix = mixture_viscosity<D, M>(P, s.X);
+    lam_mix = mixture_conductivity<D, M>(P, s.X);
+  }
+  const D omega = 2.0 * s.P / (s.P + 2.0 * mu_mix);
+  const D omega1 = 2.0 * s.P * s.Cp / (s.P * s.Cp + 2.0 * lam_mix);
   // non-equilibrium energy flux q - q^eq - u.(P - P^eq), used by the energy collision
   D H = s.Cp * s.T;                      // mixture enthalpy (eq specH)
   if constexpr (CVT) {
@@ -741,6 +785,11 @@ __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const 
     bool present[M];
     species_present<R, M>(P, s.rho_a, s.rho, present);
     R K[M][M];
+    R gD = R(1);                       // (T_ref / T)^s_D with temperature-dependent transport
+    if constexpr (CVT) {
+      gD = inv_diffusivity_factor<R>(P, s.T);
+      Pk *= gD;
+    }
     friction_matrix<R, M>(P, s, Pk, present, K);
     // F_ai is a small correction: with 32- or 16-bit storage its triplets are kept
     // in FP32 (pe32: Psi(u), pd32: Psi(u) - Psi(u + V)); with FP64 storage in FP64.
@@ -760,7 +809,8 @@ __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const 
       R acc = R(0);
 #pragma unroll
       for (int c = 0; c < M; ++c) acc += s.Y[c] * P.invD[a][c] * P.inv_m[c];
-      const R inv_tau = s.T * s.mmix * P.inv_m[a] * acc;
+      R inv_tau = s.T * s.mmix * P.inv_m[a] * acc;
+      if constexpr (CVT) inv_tau *= gD;
       const R beta = inv_tau / (R(2) + inv_tau);            // dt / (2 tau_a + dt)
       Trip<R> pa[3];
 #pragma unroll

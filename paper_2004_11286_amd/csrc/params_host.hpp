@@ -16,6 +16,7 @@ struct HostSpecies {
   double D[MAXM][MAXM];
   int cvt;                  // 1: C_{a,v}(T) = sum_k cvc[a][k] T^k, else the constant cv
   double cvc[MAXM][4];      // (the constant case holds cv[a], 0, 0, 0)
+  double s_mu[MAXM], s_lam[MAXM], s_D, T_ref;   // transport exponents (0 and 1: constant)
 };
 
 // Mean state used for the reference equilibria (zero velocity).
@@ -107,6 +108,8 @@ inline void fill_params(Params<R>& P, const HostSpecies& h, int nx, int ny, int 
     P.mu[a] = R(h.mu[a]);
     P.lam[a] = R(h.lam[a]);
     for (int k = 0; k < 4; ++k) P.cvc[a][k] = R(h.cvc[a][k]);
+    P.s_mu[a] = R(h.s_mu[a]);
+    P.s_lam[a] = R(h.s_lam[a]);
     P.inv_lam[a] = R(1.0 / h.lam[a]);
     for (int b = 0; b < h.M; ++b) {
       P.invD[a][b] = R(1.0 / h.D[a][b]);
@@ -121,6 +124,8 @@ inline void fill_params(Params<R>& P, const HostSpecies& h, int nx, int ny, int 
     P.inv_scale[l] = R(1.0 / scale[l]);
   }
   P.absent_tol = R(absent_tol);
+  P.s_D = R(h.s_D);
+  P.T_ref = R(h.T_ref);
 }
 
 }  // namespace mclbm

@@ -58,7 +58,7 @@ class mclbm_params(C.Structure):
         ("molar_mass", C.POINTER(C.c_double)), ("cv", C.POINTER(C.c_double)),
         ("D", C.POINTER(C.c_double)), ("mu", C.POINTER(C.c_double)),
         ("lam", C.POINTER(C.c_double)), ("cv_coef", C.POINTER(C.c_double)),
-        ("inlet", C.POINTER(C.c_double)),
+        ("inlet", C.POINTER(C.c_double)), ("transport_exp", C.POINTER(C.c_double)),
     ]
 
 
@@ -169,12 +169,13 @@ def make_params(params: dict, precision: int):
     cvc = None if cvc is None else _f64(cvc).reshape(M * 4)
     inl = params.get("inlet")
     inl = None if inl is None else _f64(inl).reshape(M + 5)
-    arrs += [a for a in (cvc, inl) if a is not None]
+    tex = params.get("transport_exp")
+    tex = None if tex is None else _f64(tex).reshape(2 * M + 2)
+    arrs += [a for a in (cvc, inl, tex) if a is not None]
     p = mclbm_params(M, int(params["nx"]), int(params["ny"]), int(params["nz"]),
                      int(params.get("wall_x", 0)), int(precision), int(params.get("weak", 0)), 0,
                      *[a.ctypes.data_as(dp) for a in arrs[:5]],
-                     cvc.ctypes.data_as(dp) if cvc is not None else None,
-                     inl.ctypes.data_as(dp) if inl is not None else None)
+                     *[a.ctypes.data_as(dp) if a is not None else None for a in (cvc, inl, tex)])
     return p, arrs
 
 

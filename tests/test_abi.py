@@ -108,6 +108,16 @@ def test_cv_of_T_workspace_and_validation():
     with pytest.raises(m.MclbmError) as e:
         m.mclbm_batch_workspace_bytes([p, dict(p, cv_coef=cvc)], m.MCLBM_FP32)
     assert "cv_coef" in str(e.value)
+    tex = np.array([0.7, 0.7, 0.7, 0.8, 0.8, 0.8, 1.75, 0.25])
+    assert m.mclbm_workspace_bytes(dict(p, transport_exp=tex), m.MCLBM_FP64) == \
+        m.mclbm_workspace_bytes(dict(p, cv_coef=cvc), m.MCLBM_FP64)
+    for bad in (np.concatenate([tex[:-1], [0.0]]), np.concatenate([[np.inf], tex[1:]])):
+        with pytest.raises(m.MclbmError) as e:
+            m.mclbm_workspace_bytes(dict(p, transport_exp=bad), m.MCLBM_FP64)
+        assert "transport_exp" in str(e.value)
+    with pytest.raises(m.MclbmError) as e:
+        m.mclbm_workspace_bytes(dict(p, transport_exp=tex), m.MCLBM_FP16)
+    assert "temperature-dependent transport" in str(e.value)
 
 
 def test_open_ends_validation():

@@ -164,3 +164,62 @@ def test_cvt_full_size_shear_layer_windows(mc, oracle_mod):
             worst[k] = max(worst[k], float(np.abs(gv - ov).max() / scale))
             assert np.abs(gv - ov).max() <= 1e-6 * scale, (k, (x, y, z), gv, ov)
     print("cvt fp32 worst window error", worst)
+
+
+def with_transport(params, T_ref):
+    """Transport coefficients as powers of T / T_ref (viscosity 0.7, 0.8, ...;
+    conductivity 0.75, 0.85, ...; diffusivity 1.75)."""
+    M = params["M"]
+    tex = np.concatenate([0.7 + 0.1 * np.arange(M), 0.75 + 0.1 * np.arange(M), [1.75, T_ref]])
+    return dict(params, transport_exp=tex)
+
+
+@pytest.mark.parametrize("M,walls,cvt", [(2, 0, False), (3, 1, False), (3, 1, True), (4, 0, True)])
+def test_transport_of_T_ragged_grid_fp64(mc, oracle_mod, M, walls, cvt):
+    """Temperature-dependent transport (T about 1.4 T_ref), alone and with C_v(T):
+    13 x 7 x 5 nodes, 20 steps in FP64, fields against the oracle; the result
+    differs from constant transport."""
+    params, f = _case(M, 13, 7, 5, walls, seed=91 + M)
+    if not cvt:
+        params = {k: v for k, v in params.items() if k != "cv_coef"}
+    params = with_transport(params, 0.3 / 1.4)
+    s = mc.Sim(params, mc.MCLBM_FP64)
+    s.init_fields(**f)
+    s.step(20)
+    g, gc = s.read_moments(), s.conservation()
+    s.close()
+    o = oracle_mod.OracleSim(params)
+    o.init_fields(**f)
+    o.step(20)
+    om, oc = o.read_moments(), o.conservation()
+    errs = field_errors(g, om)
+    print("transport fp64", M, walls, cvt, errs)
+    for k in FIELDS:
+        assert errs[k] < 1e-12, (k, errs[k])
+    np.testing.assert_allclose(gc[:M + 1], oc[:M + 1], rtol=1e-12)
+    const = mc.Sim({k: v for k, v in params.items() if k != "transport_exp"}, mc.MCLBM_FP64)
+    const.init_fields(**f)
+    const.step(20)
+    gk = const.read_moments()
+    const.close()
+    assert np.abs(gk["X"] - g["X"]).max() > 1e-9
+
+
+def test_transport_of_T_ternary_tube_fp32_1000_steps(mc, oracle_mod):
+    """256 x 4 x 4 walled tube with C_v(T) and temperature-dependent transport,
+    FP32 storage, FP64 collision, 1000 steps."""
+    params, f = W.ternary_tube()
+    params = with_transport(with_cv_of_T(params, 1 / 3), 0.25)
+    o = oracle_mod.OracleSim(params)
+    o.init_fields(**f)
+    o.step(1000)
+    om = o.read_moments()
+    s = mc.Sim(params, mc.MCLBM_FP32)
+    s.init_fields(**f)
+    s.step(1000)
+    g = s.read_moments()
+    s.close()
+    errs = field_errors(g, om)
+    print("transport C2 fp32 1000", errs)
+    for k in FIELDS:
+        assert errs[k] < 1e-5, (k, errs[k])
