@@ -4,14 +4,17 @@
  * Dorschner and Karlin (arXiv 2004.11286): M species population sets relaxing
  * under the Stefan--Maxwell kinetic model (Sec. 2), a compressible mixture
  * momentum lattice and an energy lattice (Sec. 3), all on D3Q27, strongly
- * coupled (Sec. 3.6.2), fused stream-and-collide over every node.
+ * coupled (Sec. 3.6.2) or weakly coupled (Sec. 3.6.1), fused stream-and-collide
+ * over every node; x ends periodic, walled or open; constant or
+ * temperature-dependent specific heats and transport coefficients.
  *
  * Conventions for every call:
  *   - Return value: MCLBM_OK (0) on success, a negative MCLBM_E* code on error;
  *     mclbm_last_error() then describes the failure. No exception crosses the ABI.
  *   - Units: lattice units, dt = dx = 1, universal gas constant R_U = 1 (a species
- *     of molar mass m_a has gas constant 1/m_a), constant specific heats with
- *     T_0 = 0 (Sec. 4.1).
+ *     of molar mass m_a has gas constant 1/m_a), T_0 = 0 (Sec. 4.1); specific
+ *     heats constant unless mclbm_params.cv_coef is given. Physical data are
+ *     converted by acoustic scaling in the Python package (units.py).
  *   - Field layout: structure of arrays, x fastest: node n = x + nx (y + ny z).
  *     A field with C components is C consecutive planes of nx*ny*nz doubles.
  *   - Ownership: the caller owns every buffer it passes, including the device
@@ -20,13 +23,14 @@
  *   - Streams: every call is ordered on the HIP stream given at creation; calls
  *     that return data to the host synchronise that stream. Calls on one context
  *     are not thread safe.
- *   - Species M (the last) is slaved to the mixture (strong coupling, Sec. 3.6.2):
- *     its density and momentum are the deficits of the mixture's. Order species so
- *     that the last one carries most of the mass everywhere.
+ *   - Under strong coupling (the default) species M (the last) is slaved to the
+ *     mixture (Sec. 3.6.2): its density and momentum are the deficits of the
+ *     mixture's. Order species so that the last one carries most of the mass
+ *     everywhere. Under weak coupling (mclbm_params.weak) it has its own lattice.
  *   - Batches: a context holds one or more independent lattices ("tubes", the
  *     Loschmidt-tube setting of Sec. 4.2 repeated with different mixtures). All
- *     tubes of a context share M, wall_x and precision; sizes and species data
- *     differ per tube. Every per-node array of the calls below is the
+ *     tubes of a context share M, wall_x, precision, the coupling and which
+ *     optional data are given; sizes, species data and inlets differ per tube. Every per-node array of the calls below is the
  *     concatenation over the tubes, in creation order, of that tube's own array
  *     in the single-tube layout: a field with C components holds, for tube t,
  *     C * n_t values at offset C * (n_0 + ... + n_{t-1}). A context made with
@@ -157,7 +161,8 @@ int mclbm_step(mclbm_ctx *c, int64_t nsteps);
 int mclbm_read_moments(mclbm_ctx *c, double *X, double *rho, double *u, double *p, double *T,
                        int on_device);
 
-/* Domain sums in FP64 per tube, out [ntubes][M+5]: rho_1 .. rho_M (rho_M slaved),
+/* Domain sums in FP64 per tube, out [ntubes][M+5]: rho_1 .. rho_M (rho_M slaved
+ * under strong coupling, from its own lattice under weak),
  * rho, rho u_x, rho u_y, rho u_z, rho E. Returns MCLBM_ENAN if any node holds a
  * non-finite value or a negative slaved density. Synchronises the stream. */
 int mclbm_conservation(mclbm_ctx *c, double *out);
