@@ -52,10 +52,11 @@
  * species collision, binary erf interdiffusion, ternary half-tube means against
  * an independent Maxwell--Stefan solver, the printed gas constants and sound
  * speeds of S1-S4, Kirchhoff sound attenuation, shear and thermal decay with
- * the Wilke and Mathur mixing rules, and temperature uniformity under
- * interdiffusion. The -u.(P - P^eq) term of eq gstareq1mom has no pin of its
- * own (parity unpinned for that term): its effect on every tested quantity is
- * below the tests' resolution.
+ * the Wilke and Mathur mixing rules, temperature uniformity under
+ * interdiffusion, and the viscous heating pattern of a decaying shear wave
+ * against linearised Navier--Stokes (which pins the -u.(P - P^eq) term of
+ * eq gstareq1mom). Weak coupling, temperature-dependent heat capacities and
+ * transport, and open x ends have pins of their own.
  */
 #include "mclbm_oracle.h"
 
