@@ -153,9 +153,15 @@ def cpu_baseline(seconds_target: float = 15.0):
         o.step(1)
         elapsed += time.perf_counter() - t0
         steps += 1
+    cpu_model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu_model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), cpu_model)
+    except OSError:
+        pass
     return {"value": n * steps / elapsed / 1e6, "unit": "MLUPS", "cores": O.threads(), "kind": "oracle",
             "sample": f"FP64 oracle, {steps} steps of a 32x256x8 box of the shear-layer recipe "
-                      f"({elapsed:.1f} s)"}
+                      f"({elapsed:.1f} s)", "cpu_model": cpu_model}
 
 
 def ensemble_bench(mc, steps: int = 50, seq_steps: int = 10, trial_steps: int = 10):
