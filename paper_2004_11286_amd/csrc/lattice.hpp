@@ -73,7 +73,7 @@ __host__ __device__ constexpr double w13(int i) { return w13_1d(cx(i)) * w13_1d(
 template <typename R>
 struct Params {
   int32_t M, nx, ny, nz;
-  int32_t wall_x, pad0, pad1, pad2;
+  int32_t wall_x, trn, pad1, pad2;   // trn: transport exponents given (R19)
   int64_t n;
   R m[MAXM], inv_m[MAXM], cv[MAXM], cp[MAXM];
   R mu[MAXM], lam[MAXM], inv_lam[MAXM];

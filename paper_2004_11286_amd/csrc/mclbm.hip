@@ -1,12 +1,16 @@
 // mclbm.hip -- context management and the C ABI of libmclbm (include/mclbm.h).
 //
 // One time step = three launches over all nodes of all tubes, one thread per node:
-//   k_moments  read 27 (M+1) populations -> node record (FP64 state, Sec. 2.5.3,
-//              3.2, 3.4: Phi, omega, C_p, rho, u, T, omega_1, q_neq, rho_a, V_a)
+//   k_moments  read the 27 L populations (L = M + 1 stored lattices under strong
+//              coupling, M + 2 under weak) -> node record (FP64 state, Sec. 2.5.3,
+//              3.2, 3.4: Phi, omega, C_p, rho, u, T, omega_1, q_neq, rho_a, V_a;
+//              u_s under weak coupling, Y_a with temperature-dependent heat
+//              capacities)
 //   k_gfield   G_a = (1/omega - 1/2) d_a Phi_a from the records of the neighbours
-//   k_collide  read the populations again, X_a = -d_a G_a and d C_p from the
-//              neighbours, collide every lattice, push to the neighbours of the
-//              other buffer (bounce-back at x walls)
+//   k_collide  read the populations again, X_a = -d_a G_a and d C_p (or d Y_a)
+//              from the neighbours, collide every lattice, push to the neighbours
+//              of the other buffer (bounce-back at x walls); with open x ends a
+//              fourth launch, k_open_fix, rewrites what enters the end planes
 // The two reads of the populations are forced by the non-local terms of the
 // momentum and energy collisions, which need the neighbours' moments at the same
 // time level (eqs Xalpha and corrFourier). Populations are laid out as
@@ -774,6 +778,7 @@ extern "C" int mclbm_batch_create(const mclbm_params* tp, int32_t ntubes, void* 
     }
     th.hs.s_D = p->transport_exp ? p->transport_exp[2 * p->M] : 0.0;
     th.hs.T_ref = p->transport_exp ? p->transport_exp[2 * p->M + 1] : 1.0;
+    th.hs.trn = p->transport_exp != nullptr;
     if (p->wall_x == 2)
       for (int k = 0; k < p->M + 5; ++k) th.inlet[k] = p->inlet[k];
   }

@@ -171,12 +171,29 @@ __host__ __device__ __forceinline__ R mixture_viscosity(const Params<R>& P, cons
   return mu;
 }
 
+template <typename R, int M>
+__host__ __device__ __forceinline__ R mixture_conductivity(const Params<R>& P, const R X[M])
+{
+  R lin = R(0), harm = R(0);
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    lin += X[a] * P.lam[a];
+    harm += X[a] * P.inv_lam[a];
+  }
+  return R(0.5) * (lin + R(1) / harm);
+}
+
 // The same at temperature T with temperature-dependent transport (R19):
 // mu_a (T/T_ref)^s_mu,a in Wilke's rule, with phi_ab (eq wilkePhi) from those
 // viscosities, and lambda_a (T/T_ref)^s_lam,a in Mathur's rule.
 template <typename R, int M>
 __host__ __device__ __forceinline__ void mixture_transport_T(const Params<R>& P, const R X[M], R T, R& mu, R& lam)
 {
+  if (!P.trn) {                        // constant transport: the precomputed Wilke factors
+    mu = mixture_viscosity<R, M>(P, X);
+    lam = mixture_conductivity<R, M>(P, X);
+    return;
+  }
   const R lt = log(T / P.T_ref);
   R mua[M], lin = R(0), harm = R(0);
 #pragma unroll
@@ -204,19 +221,7 @@ __host__ __device__ __forceinline__ void mixture_transport_T(const Params<R>& P,
 template <typename R>
 __host__ __device__ __forceinline__ R inv_diffusivity_factor(const Params<R>& P, R T)
 {
-  return exp(-P.s_D * log(T / P.T_ref));
-}
-
-template <typename R, int M>
-__host__ __device__ __forceinline__ R mixture_conductivity(const Params<R>& P, const R X[M])
-{
-  R lin = R(0), harm = R(0);
-#pragma unroll
-  for (int a = 0; a < M; ++a) {
-    lin += X[a] * P.lam[a];
-    harm += X[a] * P.inv_lam[a];
-  }
-  return R(0.5) * (lin + R(1) / harm);
+  return P.trn ? exp(-P.s_D * log(T / P.T_ref)) : R(1);
 }
 
 // A stored population (read once per pass: a nontemporal load) as a scaled deviation.

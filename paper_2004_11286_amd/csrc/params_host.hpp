@@ -17,6 +17,7 @@ struct HostSpecies {
   int cvt;                  // 1: C_{a,v}(T) = sum_k cvc[a][k] T^k, else the constant cv
   double cvc[MAXM][4];      // (the constant case holds cv[a], 0, 0, 0)
   double s_mu[MAXM], s_lam[MAXM], s_D, T_ref;   // transport exponents (0 and 1: constant)
+  int trn;                  // 1: transport exponents given
 };
 
 // Mean state used for the reference equilibria (zero velocity).
@@ -125,6 +126,7 @@ inline void fill_params(Params<R>& P, const HostSpecies& h, int nx, int ny, int 
   }
   P.absent_tol = R(absent_tol);
   P.s_D = R(h.s_D);
+  P.trn = h.trn;
   P.T_ref = R(h.T_ref);
 }
 
