@@ -173,7 +173,7 @@ void oracle_gansatz(double theta, double M0, const double m[3], const double Mt[
 /* Simulation state                                                           */
 /* ------------------------------------------------------------------------- */
 struct oracle_sim {
-  int M, nx, ny, nz, wall_x, keep_slaved, weak, flags;
+  int M, nx, ny, nz, wall_x, wall_y, keep_slaved, weak, flags;
   long n;
   double m[MAXM], cv[MAXM], D[MAXM][MAXM], mu[MAXM], lam[MAXM];
   int cvt;                 /* 1: C_{a,v}(T) = sum_k cvc[a][k] T^k, else the constant cv[a] */
@@ -239,6 +239,11 @@ int oracle_create(const oracle_params *p, oracle_sim **out)
   s->M = p->M;
   s->nx = p->nx; s->ny = p->ny; s->nz = p->nz;
   s->wall_x = p->wall_x;
+  s->wall_y = p->wall_y ? 1 : 0;
+  if (s->wall_y && (p->ny < 2 || s->wall_x == 2)) {
+    free(s);
+    return -1;
+  }
   s->weak = p->weak ? 1 : 0;
   s->keep_slaved = (p->keep_slaved || s->weak) ? 1 : 0;   /* weak coupling evolves every species */
   s->flags = p->debug_flags;
@@ -492,18 +497,25 @@ static void node_state(const oracle_sim *s, const double *pop, long node, state_
 /* ------------------------------------------------------------------------- */
 /* Non-local terms                                                           */
 /* ------------------------------------------------------------------------- */
-/* Value of a node field at integer position (x, y, z): periodic in y and z; in
- * x periodic, or mirrored about the walls at x = -1/2 and x = nx - 1/2, in which
- * case odd_x = 1 flips the sign (x component of a vector field), or, at open x
- * ends, the boundary node's value (zero gradient). */
-static double field_at(const oracle_sim *s, const double *fld, int x, int y, int z, int odd_x)
+/* Value of a node field at integer position (x, y, z): periodic in z; in x
+ * periodic, or mirrored about the walls at x = -1/2 and x = nx - 1/2, or, at open
+ * x ends, the boundary node's value (zero gradient); in y periodic, or mirrored
+ * about free-slip walls at y = -1/2 and y = ny - 1/2. comp is the vector
+ * component the field is (-1 for a scalar): a mirror flips the sign of the
+ * component normal to it. */
+static double field_at(const oracle_sim *s, const double *fld, int x, int y, int z, int comp)
 {
   double sign = 1.0;
-  y = wrap(y, s->ny);
   z = wrap(z, s->nz);
+  if (s->wall_y) {
+    if (y < 0) { y = -1 - y; if (comp == 1) sign = -sign; }
+    else if (y >= s->ny) { y = 2 * s->ny - 1 - y; if (comp == 1) sign = -sign; }
+  } else {
+    y = wrap(y, s->ny);
+  }
   if (s->wall_x == 1) {
-    if (x < 0) { x = -1 - x; sign = odd_x ? -1.0 : 1.0; }
-    else if (x >= s->nx) { x = 2 * s->nx - 1 - x; sign = odd_x ? -1.0 : 1.0; }
+    if (x < 0) { x = -1 - x; if (comp == 0) sign = -sign; }
+    else if (x >= s->nx) { x = 2 * s->nx - 1 - x; if (comp == 0) sign = -sign; }
   } else if (s->wall_x == 2) {
     if (x < 0) x = 0;
     else if (x >= s->nx) x = s->nx - 1;
@@ -541,12 +553,12 @@ static double iso_deriv(accessor_fn get, const void *ctx, int x, int y, int z, i
 }
 
 /* accessor: node field with the simulation's boundary rule */
-typedef struct { const oracle_sim *s; const double *fld; int odd_x; } node_field_ctx;
+typedef struct { const oracle_sim *s; const double *fld; int comp; } node_field_ctx;
 
 static double node_field_get(const void *ctx, int x, int y, int z)
 {
   const node_field_ctx *c = (const node_field_ctx *)ctx;
-  return field_at(c->s, c->fld, x, y, z, c->odd_x);
+  return field_at(c->s, c->fld, x, y, z, c->comp);
 }
 
 /* accessor: plain periodic field on an nx*ny*nz grid */
@@ -588,6 +600,8 @@ static double g_get(const void *ctx, int x, int y, int z)
   const g_ctx *c = (const g_ctx *)ctx;
   const oracle_sim *s = c->s;
   if (!s->wall_x) x = wrap(x, s->nx);
+  /* free-slip y walls: every G_k is even under the y mirror (d_y Phi_y is) */
+  if (s->wall_y) y = y < 0 ? -1 - y : (y >= s->ny ? 2 * s->ny - 1 - y : y);
   return s->G[gidx(s, c->k, x, wrap(y, s->ny), wrap(z, s->nz))];
 }
 
@@ -603,8 +617,8 @@ static void compute_nonlocal(oracle_sim *s)
     for (int y = 0; y < ny; ++y)
       for (int x = -1; x <= nx; ++x)
         for (int k = 0; k < 3; ++k) {
-          node_field_ctx phi = {s, s->Phi + (long)k * n, k == 0};
-          double omega = field_at(s, s->om, x, y, z, 0);
+          node_field_ctx phi = {s, s->Phi + (long)k * n, k};
+          double omega = field_at(s, s->om, x, y, z, -1);
           s->G[gidx(s, k, x, y, z)] = (1.0 / omega - 0.5) * iso_deriv(node_field_get, &phi, x, y, z, k);
         }
   /* open x ends: G beyond the boundary is the boundary node's (zero gradient) */
@@ -626,7 +640,7 @@ static void compute_nonlocal(oracle_sim *s)
           s->Xc[(long)k * n + node] = -iso_deriv(g_get, &gc, x, y, z, k);
         }
         for (int a = 0; a < M; ++a) {
-          node_field_ctx yc = {s, s->Yf + (long)a * n, 0};
+          node_field_ctx yc = {s, s->Yf + (long)a * n, -1};
           for (int k = 0; k < 3; ++k)
             s->gY[((long)a * 3 + k) * n + node] = iso_deriv(node_field_get, &yc, x, y, z, k);
         }
@@ -820,10 +834,16 @@ static void stream(oracle_sim *s)
             long src = node_index(s, x, y, z);
             double v = POP(s, s->post, l, i, src);
             int xd = x + cvel(i, 0);
+            int yd = y + cvel(i, 1);
             if (s->wall_x == 2 && (xd < 0 || xd >= nx)) {
               /* open x ends: leaves the domain */
             } else if (s->wall_x && (xd < 0 || xd >= nx)) {
               POP(s, s->pop, l, opposite(i), src) = v;      /* half-way bounce-back */
+            } else if (s->wall_y && (yd < 0 || yd >= ny)) {
+              /* free-slip y wall: specular reflection, c_y reversed, at the same y */
+              int iy = i + 3 * (-2 * cvel(i, 1));
+              long dst = node_index(s, wrap(xd, nx), y, wrap(z + cvel(i, 2), nz));
+              POP(s, s->pop, l, iy, dst) = v;
             } else {
               long dst = node_index(s, wrap(xd, nx), wrap(y + cvel(i, 1), ny),
                                     wrap(z + cvel(i, 2), nz));

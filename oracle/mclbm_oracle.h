@@ -57,6 +57,9 @@ typedef struct {
   const double *transport_exp; /* NULL: constant transport coefficients; else [2M+2]:
                                s_mu (M), s_lam (M), s_D, T_ref: mu_a (T/T_ref)^s_mu,a,
                                lambda_a (T/T_ref)^s_lam,a, D_ab (T/T_ref)^s_D          */
+  int32_t wall_y;           /* 1: free-slip walls at both y ends (specular reflection);
+                               needs ny >= 2 and wall_x 0 or 1                           */
+  int32_t reserved2;
 } oracle_params;
 
 typedef struct oracle_sim oracle_sim;

@@ -39,6 +39,7 @@ class _Params(C.Structure):
         ("D", C.POINTER(C.c_double)), ("mu", C.POINTER(C.c_double)),
         ("lam", C.POINTER(C.c_double)), ("cv_coef", C.POINTER(C.c_double)),
         ("inlet", C.POINTER(C.c_double)), ("transport_exp", C.POINTER(C.c_double)),
+        ("wall_y", C.c_int32), ("reserved2", C.c_int32),
     ]
 
 
@@ -186,7 +187,8 @@ class OracleSim:
         p = _Params(self.M, self.nx, self.ny, self.nz, int(params.get("wall_x", 0)),
                     int(keep_slaved), int(debug_flags), int(params.get("weak", 0)),
                     *[_dp(a) for a in self._arrays[:5]],
-                    *[_dp(a) if a is not None else None for a in (cvc, inl, tex)])
+                    *[_dp(a) if a is not None else None for a in (cvc, inl, tex)],
+                    int(params.get("wall_y", 0)), 0)
         h = C.c_void_p()
         rc = lib().oracle_create(C.byref(p), C.byref(h))
         if rc != 0:
