@@ -2,9 +2,9 @@
 #include "kernels.hpp"
 
 namespace mclbm {
-// open ends, weak coupling and C_v(T) are compiled for FP64 arithmetic only
+// open ends, free-slip walls, weak coupling and C_v(T) are compiled for FP64 arithmetic only
 bool pick_bf16(int M, int walls, int weak, int cvt, kern::Ops& o)
 {
-  return !weak && !cvt && walls != 2 && kern::pick_m<__bf16, float, float, false>(M, walls, o);
+  return !weak && !cvt && walls <= 1 && kern::pick_m<__bf16, float, float, false>(M, walls, o);
 }
 }  // namespace mclbm

@@ -336,7 +336,7 @@ Ops make_ops()
     hipLaunchKernelGGL((k_field_sums<M>), dim3(grid), dim3(RED_BLOCK), 0, st, tube_n, ln, X, p, T, partial);
   };
   o.open_fix = nullptr;
-  if constexpr (W == BC_OPEN) {
+  if constexpr (xbc(W) == BC_OPEN) {
     o.open_fix = [](const void* P, const Launch& ln, void* dst, StepNo sn, unsigned grid, hipStream_t st) {
       hipLaunchKernelGGL((k_open_fix<S, R, M>), dim3(grid), dim3(BLOCK), 0, st, (const Params<R>*)P, ln, (S*)dst, sn);
     };
@@ -356,6 +356,20 @@ bool pick_m(int M, int walls, Ops& o)
   }
 }
 
+// free-slip y walls with periodic (walls_x = 0) or walled (1) x ends (strong
+// coupling, constant heat capacities and transport)
+template <typename S, typename R, typename Rec>
+bool pick_m_yslip(int M, int walls_x, Ops& o)
+{
+  constexpr int P = BC_YSLIP | BC_PERIODIC, Wl = BC_YSLIP | BC_WALLS;
+  switch (M) {
+    case 2: o = walls_x ? make_ops<S, R, Rec, 2, Wl, false, false>() : make_ops<S, R, Rec, 2, P, false, false>(); return true;
+    case 3: o = walls_x ? make_ops<S, R, Rec, 3, Wl, false, false>() : make_ops<S, R, Rec, 3, P, false, false>(); return true;
+    case 4: o = walls_x ? make_ops<S, R, Rec, 4, Wl, false, false>() : make_ops<S, R, Rec, 4, P, false, false>(); return true;
+    default: return false;
+  }
+}
+
 // open x ends (strong coupling, constant heat capacities)
 template <typename S, typename R, typename Rec>
 bool pick_m_open(int M, Ops& o)
@@ -371,9 +385,11 @@ bool pick_m_open(int M, Ops& o)
 }  // namespace kern
 
 // One entry point per instantiated (storage, arithmetic) pair. walls: the x
-// boundary (0 periodic, 1 walls, 2 open); weak: 1 for weak coupling; cvt: 1 for
-// temperature-dependent specific heats. Open ends, weak coupling and C_v(T) are
-// compiled for FP64 and FP32 storage with FP64 arithmetic only, one at a time.
+// boundary (0 periodic, 1 walls, 2 open) plus 4 for free-slip y walls; weak: 1
+// for weak coupling; cvt: 1 for temperature-dependent specific heats and
+// transport. Open ends, free-slip walls, weak coupling and the temperature-
+// dependent kernels are compiled for FP64 and FP32 storage with FP64
+// arithmetic only, one at a time.
 bool pick_fp64(int M, int walls, int weak, int cvt, kern::Ops& o);
 bool pick_fp32_fp64(int M, int walls, int weak, int cvt, kern::Ops& o);
 bool pick_fp32(int M, int walls, int weak, int cvt, kern::Ops& o);

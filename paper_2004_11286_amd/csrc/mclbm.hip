@@ -172,7 +172,7 @@ struct TubeHost {
 // Context
 // ---------------------------------------------------------------------------
 struct mclbm_ctx {
-  int M = 0, wall_x = 0, precision = 0, weak = 0, cvt = 0, L = 0, ntubes = 0;
+  int M = 0, wall_x = 0, wall_y = 0, precision = 0, weak = 0, cvt = 0, L = 0, ntubes = 0;
   int64_t n = 0;            // nodes over all tubes
   int64_t nblocks = 0;      // launch blocks over all tubes
   std::vector<TubeHost> tubes;
@@ -314,7 +314,16 @@ int validate_one(const mclbm_params* p, std::string& err)
   if (p->wall_x && p->nx < 2) { err = "walls need nx >= 2"; return MCLBM_EARG; }
   if (p->precision < MCLBM_FP64 || p->precision > MCLBM_BF16) { err = "unknown precision"; return MCLBM_EARG; }
   if (p->weak != 0 && p->weak != 1) { err = "weak must be 0 or 1"; return MCLBM_EARG; }
-  if (p->reserved1) { err = "reserved fields must be 0"; return MCLBM_EARG; }
+  if (p->wall_y != 0 && p->wall_y != 1) { err = "wall_y must be 0 or 1"; return MCLBM_EARG; }
+  if (p->wall_y) {
+    if (p->ny < 2) { err = "free-slip y walls need ny >= 2"; return MCLBM_EARG; }
+    if (p->weak || p->cv_coef || p->transport_exp || p->wall_x == 2 ||
+        (p->precision != MCLBM_FP64 && p->precision != MCLBM_FP32)) {
+      err = "free-slip y walls are compiled for strong coupling with constant cv and transport, periodic or "
+            "walled x ends, MCLBM_FP64 and MCLBM_FP32 only";
+      return MCLBM_EUNSUPPORTED;
+    }
+  }
   if (p->weak && p->precision != MCLBM_FP64 && p->precision != MCLBM_FP32) {
     err = "weak coupling is compiled for MCLBM_FP64 and MCLBM_FP32 only";
     return MCLBM_EUNSUPPORTED;
@@ -373,7 +382,8 @@ int validate(const mclbm_params* tp, int ntubes, std::string& err)
       return rc;
     }
     if (tp[t].M != tp[0].M || tp[t].wall_x != tp[0].wall_x || tp[t].precision != tp[0].precision ||
-        tp[t].weak != tp[0].weak || (tp[t].cv_coef == nullptr) != (tp[0].cv_coef == nullptr) ||
+        tp[t].weak != tp[0].weak || tp[t].wall_y != tp[0].wall_y ||
+        (tp[t].cv_coef == nullptr) != (tp[0].cv_coef == nullptr) ||
         (tp[t].transport_exp == nullptr) != (tp[0].transport_exp == nullptr)) {
       err = "all tubes of a batch must share M, wall_x, precision, weak and whether cv_coef and transport_exp are "
             "given";
@@ -742,6 +752,7 @@ extern "C" int mclbm_batch_create(const mclbm_params* tp, int32_t ntubes, void* 
   c->precision = tp[0].precision;
   c->weak = tp[0].weak;
   c->cvt = tp[0].cv_coef != nullptr || tp[0].transport_exp != nullptr;
+  c->wall_y = tp[0].wall_y;
   c->L = (c->weak ? c->M : c->M - 1) + 2;
   if (c->weak) {
     // four or more stored lattices: the split collision (two launches with fewer
@@ -782,7 +793,7 @@ extern "C" int mclbm_batch_create(const mclbm_params* tp, int32_t ntubes, void* 
     if (p->wall_x == 2)
       for (int k = 0; k < p->M + 5; ++k) th.inlet[k] = p->inlet[k];
   }
-  if (!pick_ops(c->precision, c->M, c->wall_x, c->weak, c->cvt, c->ops)) {
+  if (!pick_ops(c->precision, c->M, c->wall_x | (c->wall_y << 2), c->weak, c->cvt, c->ops)) {
     delete c;
     return fail(nullptr, MCLBM_EUNSUPPORTED, "no kernels compiled for this configuration");
   }

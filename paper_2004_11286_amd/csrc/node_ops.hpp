@@ -246,6 +246,7 @@ __host__ __device__ __forceinline__ T* at32(T* base, uint32_t idx)
 struct Nbr {
   uint32_t x[3], y[3], z[3];  // index contributions for c = -1, 0, +1
   bool lo, hi;                // node touches the x = 0 / x = nx-1 wall
+  bool ylo, yhi;              // node touches the y = 0 / y = ny-1 wall
 };
 
 template <typename R>
@@ -271,31 +272,49 @@ __host__ __device__ __forceinline__ Nbr neighbours(const Params<R>& P, int64_t n
   b.z[2] = (z == nz - 1 ? 0 : z + 1) * sz;
   b.lo = x == 0;
   b.hi = x == nx - 1;
+  b.ylo = y == 0;
+  b.yhi = y == ny - 1;
   return b;
 }
 
-// x boundary kinds: periodic, half-way bounce-back walls (Sec. 4.2), or open ends
-// (equilibrium inlet at x = 0, zero-gradient outlet at x = nx - 1).
-enum { BC_PERIODIC = 0, BC_WALLS = 1, BC_OPEN = 2 };
+// Boundary kinds, one integer: the x ends (BC & 3) are periodic, half-way
+// bounce-back walls (Sec. 4.2) or open (equilibrium inlet at x = 0, zero-gradient
+// outlet at x = nx - 1); BC_YSLIP adds free-slip walls at both y ends (specular
+// reflection; otherwise y is periodic).
+enum { BC_PERIODIC = 0, BC_WALLS = 1, BC_OPEN = 2, BC_YSLIP = 4 };
+__host__ __device__ constexpr int xbc(int BC) { return BC & 3; }
 
 // Stencil neighbour index: beyond an x wall the ghost node mirrors the boundary
-// node; beyond an open end it holds the boundary node's values (zero gradient).
+// node; beyond an open end it holds the boundary node's values (zero gradient);
+// beyond a free-slip y wall it mirrors the boundary node.
 template <int BC>
 __host__ __device__ __forceinline__ uint32_t stencil_index(const Nbr& b, int ci, int cj, int ck)
 {
   uint32_t xi = b.x[ci + 1];
-  if (BC != BC_PERIODIC) {
+  if (xbc(BC) != BC_PERIODIC) {
     if (ci < 0 && b.lo) xi = b.x[1];
     if (ci > 0 && b.hi) xi = b.x[1];
   }
-  return xi + b.y[cj + 1] + b.z[ck + 1];
+  uint32_t yi = b.y[cj + 1];
+  if (BC & BC_YSLIP) {
+    if (cj < 0 && b.ylo) yi = b.y[1];
+    if (cj > 0 && b.yhi) yi = b.y[1];
+  }
+  return xi + yi + b.z[ck + 1];
 }
 
-// A mirrored wall ghost (odd fields change sign there; not at open ends).
+// A mirrored wall ghost in x (odd fields change sign there; not at open ends).
 template <int BC>
 __host__ __device__ __forceinline__ bool is_ghost(const Nbr& b, int ci)
 {
-  return BC == BC_WALLS && ((ci < 0 && b.lo) || (ci > 0 && b.hi));
+  return xbc(BC) == BC_WALLS && ((ci < 0 && b.lo) || (ci > 0 && b.hi));
+}
+
+// A mirrored free-slip ghost in y (Phi_y changes sign there).
+template <int BC>
+__host__ __device__ __forceinline__ bool is_ghost_y(const Nbr& b, int cj)
+{
+  return (BC & BC_YSLIP) && ((cj < 0 && b.ylo) || (cj > 0 && b.yhi));
 }
 
 // --------------------------------------------------------------------------
@@ -538,6 +557,7 @@ __host__ __device__ __forceinline__ void gfield_node(const Params<double>& P, co
     }
     if (cy(i)) {
       R v = *at32(rec + (size_t)REC_PHIY * n, nb);
+      if (is_ghost_y<BC>(b, cy(i))) v = -v;         // Phi_y is odd under the y mirror
       dphi[1] += cy(i) > 0 ? w3 * v : -(w3 * v);
     }
     if (cz(i)) {
@@ -618,8 +638,12 @@ __host__ __device__ __forceinline__ void push(const Params<R>& P, S* __restrict_
                                      int64_t node, S v)
 {
   const size_t n = (size_t)P.n;
-  if (BC == BC_WALLS && ((cx(i) < 0 && b.lo) || (cx(i) > 0 && b.hi))) {
+  if (xbc(BC) == BC_WALLS && ((cx(i) < 0 && b.lo) || (cx(i) > 0 && b.hi))) {
     dst[(size_t)(l * Q + opp(i)) * n + node] = v;    // half-way bounce-back
+  } else if ((BC & BC_YSLIP) && ((cy(i) < 0 && b.ylo) || (cy(i) > 0 && b.yhi))) {
+    // free-slip y wall: specular reflection (c_y reversed) at the node's own y
+    const int64_t d = (int64_t)b.x[cx(i) + 1] + b.y[1] + b.z[cz(i) + 1];
+    dst[(size_t)(l * Q + i - 6 * cy(i)) * n + d] = v;
   } else {
     const int64_t d = (int64_t)b.x[cx(i) + 1] + b.y[cy(i) + 1] + b.z[cz(i) + 1];
     dst[(size_t)(l * Q + i) * n + d] = v;    // plain store: the shifted pushes of a wavefront

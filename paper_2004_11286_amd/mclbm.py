@@ -54,7 +54,7 @@ class mclbm_params(C.Structure):
     _fields_ = [
         ("M", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
         ("wall_x", C.c_int32), ("precision", C.c_int32), ("weak", C.c_int32),
-        ("reserved1", C.c_int32),
+        ("wall_y", C.c_int32),
         ("molar_mass", C.POINTER(C.c_double)), ("cv", C.POINTER(C.c_double)),
         ("D", C.POINTER(C.c_double)), ("mu", C.POINTER(C.c_double)),
         ("lam", C.POINTER(C.c_double)), ("cv_coef", C.POINTER(C.c_double)),
@@ -173,7 +173,8 @@ def make_params(params: dict, precision: int):
     tex = None if tex is None else _f64(tex).reshape(2 * M + 2)
     arrs += [a for a in (cvc, inl, tex) if a is not None]
     p = mclbm_params(M, int(params["nx"]), int(params["ny"]), int(params["nz"]),
-                     int(params.get("wall_x", 0)), int(precision), int(params.get("weak", 0)), 0,
+                     int(params.get("wall_x", 0)), int(precision), int(params.get("weak", 0)),
+                     int(params.get("wall_y", 0)),
                      *[a.ctypes.data_as(dp) for a in arrs[:5]],
                      *[a.ctypes.data_as(dp) if a is not None else None for a in (cvc, inl, tex)])
     return p, arrs

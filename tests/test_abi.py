@@ -145,6 +145,23 @@ def test_open_ends_validation():
         m.mclbm_workspace_bytes(dict(p, wall_x=3), m.MCLBM_FP32)
 
 
+def test_free_slip_validation():
+    """Free-slip y walls need ny >= 2 and are compiled for strong coupling with
+    constant properties, periodic or walled x ends and FP64 arithmetic."""
+    m = pytest.importorskip("paper_2004_11286_amd.mclbm")
+    p, _ = W.ternary_tube(nx=16, ny=4, nz=2)
+    assert m.mclbm_workspace_bytes(dict(p, wall_y=1), m.MCLBM_FP32) == m.mclbm_workspace_bytes(p, m.MCLBM_FP32)
+    for bad in (dict(p, wall_y=2), dict(p, ny=1, wall_y=1)):
+        with pytest.raises(m.MclbmError):
+            m.mclbm_workspace_bytes(bad, m.MCLBM_FP32)
+    inlet = np.array([0.3, 0.3, 0.4, p["P0"], 1 / 3, 0.05, 0.0, 0.0])
+    for q, prec in ((dict(p, wall_y=1, weak=1), m.MCLBM_FP64), (dict(p, wall_y=1), m.MCLBM_BF16),
+                    (dict(p, wall_y=1, wall_x=2, inlet=inlet), m.MCLBM_FP64)):
+        with pytest.raises(m.MclbmError) as e:
+            m.mclbm_workspace_bytes(q, prec)
+        assert "free-slip" in str(e.value)
+
+
 def test_create_rejects_bad_workspace():
     m = pytest.importorskip("paper_2004_11286_amd.mclbm")
     p, _ = W.binary_interdiffusion()
