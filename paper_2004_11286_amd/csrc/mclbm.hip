@@ -1105,7 +1105,8 @@ extern "C" int mclbm_save(mclbm_ctx* c, void* host_buf, size_t bytes)
   if (bytes < mclbm_state_bytes(c)) return fail(c, MCLBM_EARG, "buffer too small");
   CkptHeader h{};
   std::memcpy(h.magic, kMagic, 8);
-  h.M = c->M; h.wall_x = c->wall_x; h.precision = c->precision; h.ntubes = c->ntubes; h.weak = c->weak; h.cvt = c->cvt;
+  h.M = c->M; h.wall_x = c->wall_x | (c->wall_y << 2);   // the x and y boundary kinds
+  h.precision = c->precision; h.ntubes = c->ntubes; h.weak = c->weak; h.cvt = c->cvt;
   h.steps = c->steps;
   char* dst = (char*)host_buf;
   std::memcpy(dst, &h, sizeof(h));
@@ -1132,7 +1133,8 @@ extern "C" int mclbm_load(mclbm_ctx* c, const void* host_buf, size_t bytes)
   const char* src = (const char*)host_buf;
   CkptHeader h;
   std::memcpy(&h, src, sizeof(h));
-  if (std::memcmp(h.magic, kMagic, 8) != 0 || h.M != c->M || h.wall_x != c->wall_x || h.precision != c->precision ||
+  if (std::memcmp(h.magic, kMagic, 8) != 0 || h.M != c->M || h.wall_x != (c->wall_x | (c->wall_y << 2)) ||
+      h.precision != c->precision ||
       h.ntubes != c->ntubes || h.weak != c->weak || h.cvt != c->cvt)
     return fail(c, MCLBM_EARG, "checkpoint does not match this context");
   std::vector<CkptTube> ct(c->ntubes);

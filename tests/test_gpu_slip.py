@@ -107,3 +107,25 @@ def test_slip_ternary_fp32_1000_steps(mc, oracle_mod):
     print("slip fp32 1000", errs)
     for k in FIELDS:
         assert errs[k] < 1e-5, (k, errs[k])
+
+
+def test_slip_checkpoint_resume_and_mismatch(mc):
+    """A free-slip checkpoint resumes bit for bit, and a context with periodic y
+    refuses it."""
+    params, f = _case(3, 16, 8, 4, 1, seed=5)
+    s = mc.Sim(params, mc.MCLBM_FP32)
+    s.init_fields(**f)
+    s.step(7)
+    buf = s.save()
+    s.step(5)
+    a = s.read_moments()
+    s.load(buf)
+    s.step(5)
+    b = s.read_moments()
+    s.close()
+    for k in FIELDS:
+        np.testing.assert_array_equal(a[k], b[k])
+    other = mc.Sim(dict(params, wall_y=0), mc.MCLBM_FP32)
+    with pytest.raises(mc.MclbmError):
+        other.load(buf)
+    other.close()
