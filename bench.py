@@ -296,7 +296,7 @@ def main():
                     help="only run a plain device copy of MIB mebibytes five times (to scale HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU slab decomposition is a design, not an implementation)", file=sys.stderr)
         sys.exit(2)
 

@@ -70,7 +70,7 @@ typedef struct mclbm_ctx mclbm_ctx;
 
 /* Problem description. Arrays are read during mclbm_create only. */
 typedef struct {
-  int32_t M;           /* species count (2, 3 or 4 in this build)                     */
+  int32_t M;           /* species count (the kernels are compiled for 2, 3 and 4)      */
   int32_t nx, ny, nz;  /* lattice size; nx*ny*nz < 2^31                               */
   int32_t wall_x;      /* 0: periodic in x; 1: half-way bounce-back walls at both x ends
                           (Sec. 4.2); 2: open x ends, an equilibrium inlet at x = 0 (the

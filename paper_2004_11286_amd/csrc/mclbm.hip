@@ -279,7 +279,7 @@ int validate_one(const mclbm_params* p, std::string& err)
 {
   if (!p) { err = "params is NULL"; return MCLBM_EARG; }
   if (p->M < 2 || p->M > MAXM) { err = "M must be in 2..8"; return MCLBM_EARG; }
-  if (p->M > 4) { err = "this build compiles M = 2, 3, 4"; return MCLBM_EUNSUPPORTED; }
+  if (p->M > 4) { err = "the kernels are compiled for M = 2, 3, 4"; return MCLBM_EUNSUPPORTED; }
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) { err = "grid sizes must be positive"; return MCLBM_EARG; }
   const int64_t n = (int64_t)p->nx * p->ny * p->nz;
   if (n >= ((int64_t)1 << 31)) { err = "nx*ny*nz must be below 2^31"; return MCLBM_EARG; }
