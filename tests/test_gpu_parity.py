@@ -295,3 +295,33 @@ def test_non_finite_state_is_detected(mc):
         s.conservation()
     assert e.value.code == mc.MCLBM_ENAN
     s.close()
+
+
+def test_physical_units_front_end_fp64(mc, oracle_mod):
+    """An H2/CH4/Ar mixture at 300 K and 1 atm converted to lattice units by the
+    acoustic-scaling front end (units.py), with a physical temperature and
+    velocity perturbation converted the same way, through the library for 50
+    steps in FP64 against the oracle, and read back in SI units."""
+    from paper_2004_11286_amd import units as U
+
+    species = {"molar_mass": np.array([2.016, 16.043, 39.948]), "cv_molar": np.array([2.5, 3.3, 1.5]),
+               "D": np.array([[1.5e-4, 7.7e-5, 8.3e-5], [7.7e-5, 2.2e-5, 2.2e-5], [8.3e-5, 2.2e-5, 1.8e-5]]),
+               "mu": np.array([8.9e-6, 1.1e-5, 2.27e-5]), "lambda": np.array([0.18, 0.034, 0.0177])}
+    X_ref = np.array([0.3, 0.4, 0.3])
+    params, s = U.to_lattice(species, X_ref, 300.0, 101325.0, dx=7e-7, T_lat=0.3)
+    nx, ny, nz = 24, 8, 4
+    params = dict(params, nx=nx, ny=ny, nz=nz, wall_x=1)
+    rng = np.random.default_rng(3)
+    shape = (nz, ny, nx)
+    X = np.stack([np.full(shape, x) for x in X_ref])
+    T_si = 300.0 * (1 + 0.05 * np.sin(2 * np.pi * np.arange(nx) / nx))[None, None, :] * np.ones(shape)
+    u_si = rng.uniform(-10, 10, (3,) + shape)
+    fields = U.fields_to_lattice(s, X, np.full(shape, 101325.0), T_si, u_si)
+    g, _ = run_gpu(mc, params, fields, 50, mc.MCLBM_FP64)
+    o, _ = run_oracle(oracle_mod, params, fields, 50)
+    errs = field_errors(g, o)
+    print("front end fp64", errs)
+    for k in FIELDS:
+        assert errs[k] < 1e-12, (k, errs[k])
+    si = U.fields_to_physical(s, g)
+    assert 250 < si["T"].min() and si["T"].max() < 350
