@@ -28,7 +28,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
 PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = ["lattice.hpp", "node_ops.hpp", "device_ops.hpp", "kernels.hpp", "inst_fp64.hip",
-                  "inst_fp32_fp64.hip", "inst_weak.hip", "inst_cvt.hip", "inst_fp32.hip", "inst_fp16.hip", "inst_bf16.hip"]
+                  "inst_fp32_fp64.hip", "inst_weak.hip", "inst_cvt.hip", "inst_weak_cvt.hip", "inst_fp32.hip",
+                  "inst_fp16.hip", "inst_bf16.hip"]
 
 
 def record_fields(M: int, weak: bool = False, cvt: bool = False) -> int:
@@ -397,6 +398,22 @@ def main():
         del v
         torch.cuda.empty_cache()
 
+    weak_cv_of_T = None
+    if not args.no_variants:
+        # weak coupling with the same temperature-dependent heat capacities
+        v, el, st = time_run(mc, dict(cp_, weak=1), fields, prec, args.steps, args.warmup)
+        wcab = algorithmic_bytes(M, sb, rb, weak=True, cvt=True)
+        wccol = st["k_collide"]["avg_ms"]
+        wcgbs = wcab["k_collide"] * n / (wccol * 1e-3) / 1e9
+        weak_cv_of_T = {"MLUPS": n * args.steps / el / 1e6, "ms_per_step": el / args.steps * 1e3,
+                        "launch": v.launch(), "collide_avg_ms": wccol,
+                        "collide_algorithmic_bytes_per_node": wcab["k_collide"], "collide_GBs": wcgbs,
+                        "collide_frac_of_hbm_peak": wcgbs / HBM_PEAK_GBS,
+                        "kernels_avg_ms": {k: x["avg_ms"] for k, x in st.items()}}
+        v.close()
+        del v
+        torch.cuda.empty_cache()
+
     open_x = None
     if not args.no_variants:
         # open x ends: the same 256^3 binary fields carried through the domain by a
@@ -449,6 +466,7 @@ def main():
         "variants": variants,
         "weak_coupling": weak,
         "cv_of_T": cv_of_T,
+        "weak_cv_of_T": weak_cv_of_T,
         "open_x": open_x,
         "ensemble": ensemble,
         "surrogate": surrogate,

@@ -105,9 +105,10 @@ typedef struct {
                                 [M][4]: C_{a,v}(T) = sum_k c_ak T^k with c_a0 > 0 and
                                 c_ak >= 0 (k >= 1), cv unused; U_a = int_0^T C_{a,v},
                                 H_a = U_a + R_a T (eqs specUa, specHa) and T from
-                                eq temperature by Newton's method (Sec. 3.1). Strong
-                                coupling with MCLBM_FP64 or MCLBM_FP32 only (else
-                                MCLBM_EUNSUPPORTED); all tubes of a batch agree on NULL */
+                                eq temperature by Newton's method (Sec. 3.1), with Y_a
+                                the species subsystem's under weak coupling. MCLBM_FP64
+                                or MCLBM_FP32 only (else MCLBM_EUNSUPPORTED); all tubes
+                                of a batch agree on NULL                                */
   const double *inlet;       /* wall_x = 2: [M + 5] inlet fields X_1..X_M (sum 1), p, T,
                                 u_x, u_y, u_z (each tube its own); else ignored         */
   const double *transport_exp; /* NULL: constant mu, lambda, D. Else [2M + 2]: s_mu (M),

@@ -335,9 +335,8 @@ int validate_one(const mclbm_params* p, std::string& err)
       err = "transport_exp: exponents must be finite and T_ref positive";
       return MCLBM_EARG;
     }
-    if (p->weak || (p->precision != MCLBM_FP64 && p->precision != MCLBM_FP32)) {
-      err = "temperature-dependent transport is compiled for strong coupling with MCLBM_FP64 and MCLBM_FP32 "
-            "only";
+    if (p->precision != MCLBM_FP64 && p->precision != MCLBM_FP32) {
+      err = "temperature-dependent transport is compiled for MCLBM_FP64 and MCLBM_FP32 only";
       return MCLBM_EUNSUPPORTED;
     }
   }
@@ -350,9 +349,8 @@ int validate_one(const mclbm_params* p, std::string& err)
           return MCLBM_EARG;
         }
       }
-    if (p->weak || (p->precision != MCLBM_FP64 && p->precision != MCLBM_FP32)) {
-      err = "temperature-dependent specific heats are compiled for strong coupling with MCLBM_FP64 and "
-            "MCLBM_FP32 only";
+    if (p->precision != MCLBM_FP64 && p->precision != MCLBM_FP32) {
+      err = "temperature-dependent specific heats are compiled for MCLBM_FP64 and MCLBM_FP32 only";
       return MCLBM_EUNSUPPORTED;
     }
   }

@@ -6,13 +6,13 @@ import numpy as np
 FIELDS = ("X", "rho", "u", "p", "T")
 
 # Checkpoint written by mclbm_save (see mclbm.hip): a header (magic[8], M,
-# wall_x, precision, ntubes, weak, pad as int32, int64 step count), then per tube
+# wall_x, precision, ntubes, weak, cvt as int32, int64 step count), then per tube
 # its size and reference tables (10 lattices: up to 8 species, f, g), then the
 # stored populations of all tubes (M-1 species lattices under strong coupling,
 # M under weak coupling, then f and g).
 _MAXL = 10
 _HDR = np.dtype([("magic", "S8"), ("M", "<i4"), ("wall_x", "<i4"), ("precision", "<i4"),
-                 ("ntubes", "<i4"), ("weak", "<i4"), ("pad", "<i4"), ("steps", "<i8")])
+                 ("ntubes", "<i4"), ("weak", "<i4"), ("cvt", "<i4"), ("steps", "<i8")])
 _TUBE = np.dtype([("nx", "<i4"), ("ny", "<i4"), ("nz", "<i4"), ("pad", "<i4"),
                   ("ref", "<f8", (_MAXL, 27)), ("ref0", "<f8", (_MAXL,)), ("ref2", "<f8", (_MAXL,)),
                   ("scale", "<f8", (_MAXL,))])

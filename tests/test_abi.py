@@ -100,11 +100,14 @@ def test_cv_of_T_workspace_and_validation():
         with pytest.raises(m.MclbmError) as e:
             m.mclbm_workspace_bytes(dict(p, cv_coef=bad), m.MCLBM_FP64)
         assert "cv_coef" in str(e.value)
-    for q, prec in ((dict(p, cv_coef=cvc, weak=1), m.MCLBM_FP64), (dict(p, cv_coef=cvc), m.MCLBM_FP16),
+    for prec, r_bytes in ((m.MCLBM_FP64, 8), (m.MCLBM_FP32, 4)):      # with weak coupling too
+        assert (m.mclbm_workspace_bytes(dict(p, cv_coef=cvc, weak=1), prec)
+                - m.mclbm_workspace_bytes(dict(p, weak=1), prec) == 2 * n * r_bytes)
+    for q, prec in ((dict(p, cv_coef=cvc, weak=1), m.MCLBM_FP16), (dict(p, cv_coef=cvc), m.MCLBM_FP16),
                     (dict(p, cv_coef=cvc), m.MCLBM_FP32_FP32)):
         with pytest.raises(m.MclbmError) as e:
             m.mclbm_workspace_bytes(q, prec)
-        assert "temperature-dependent" in str(e.value)
+        assert "compiled for MCLBM_FP64 and MCLBM_FP32 only" in str(e.value)
     with pytest.raises(m.MclbmError) as e:
         m.mclbm_batch_workspace_bytes([p, dict(p, cv_coef=cvc)], m.MCLBM_FP32)
     assert "cv_coef" in str(e.value)

@@ -6,7 +6,8 @@ takes T from the energy lattice. The oracle's weak mode is pinned on the CPU
 (tests/test_oracle_weak.py). Here the GPU path is compared with it: fields and
 every stored population (FP64, ragged grids, all M, with and without walls), the
 conservation sums, FP32 storage over 1000 steps, and windows of the full-size
-shear layer.
+shear layer; and weak coupling with temperature-dependent heat capacities and
+transport (Sec. 3.1) on ragged grids and the walled tube.
 """
 import numpy as np
 import pytest
@@ -239,3 +240,69 @@ def test_weak_launch_choices_agree(mc):
             assert np.abs(got[k] - out[0][k]).max() <= 1e-13 * scale, k
     for k in FIELDS:
         np.testing.assert_array_equal(out[1][k], out[2][k])      # fused forms: bitwise
+
+
+def _cv_and_transport(params, T0=0.3):
+    """C_{a,v}(T) rising with T differently per species, and transport
+    coefficients as powers of T / T_ref with T_ref = T0 / 1.3."""
+    cv = np.asarray(params["cv"], dtype=np.float64)
+    shapes = [[1.0, 0.6 / T0, 0.1 / T0 ** 2, 0.3 / T0 ** 3], [1.0, 0.0, 0.4 / T0 ** 2, 0.0],
+              [1.0, 0.2 / T0, 0.0, 0.1 / T0 ** 3], [1.0, 0.3 / T0, 0.3 / T0 ** 2, 0.0]]
+    M = params["M"]
+    tex = np.concatenate([0.7 + 0.1 * np.arange(M), 0.75 + 0.1 * np.arange(M), [1.75, T0 / 1.3]])
+    return dict(params, cv_coef=np.stack([cv[a] * np.asarray(shapes[a]) for a in range(M)]), transport_exp=tex)
+
+
+@pytest.mark.parametrize("M", [2, 3, 4])
+@pytest.mark.parametrize("walls", [0, 1])
+def test_weak_cv_of_T_ragged_grid_fp64(mc, oracle_mod, M, walls):
+    """Weak coupling with C_v(T) and T-dependent transport: 13 x 7 x 5 nodes, 20
+    steps in FP64, fields, conservation sums and every stored population against
+    the oracle; the result differs from constant properties."""
+    params, f = _case(M, 13, 7, 5, walls, seed=71 + 2 * M + walls)
+    params = _cv_and_transport(params)
+    s = mc.Sim(params, mc.MCLBM_FP64)
+    s.init_fields(**f)
+    s.step(20)
+    g, gc = s.read_moments(), s.conservation()
+    hdr, vals = decode_checkpoint(s.save())
+    s.close()
+    assert int(hdr["weak"]) == 1 and int(hdr["cvt"]) == 1 and vals.shape[0] == M + 2
+    o = oracle_mod.OracleSim(params)
+    o.init_fields(**f)
+    o.step(20)
+    om, oc, op = o.read_moments(), o.conservation(), o.populations()
+    errs = field_errors(g, om)
+    pop_err = float(np.abs(_populations(hdr, vals) - op).max() / np.abs(op).max())
+    print("weak cvt fp64", M, walls, errs, "populations", pop_err)
+    for k in FIELDS:
+        assert errs[k] < 1e-12, (k, errs[k])
+    assert pop_err < 1e-12
+    np.testing.assert_allclose(gc[:M + 1], oc[:M + 1], rtol=1e-12)
+    np.testing.assert_allclose(gc[M + 4], oc[M + 4], rtol=1e-12)
+    const = mc.Sim({k: v for k, v in params.items() if k not in ("cv_coef", "transport_exp")}, mc.MCLBM_FP64)
+    const.init_fields(**f)
+    const.step(20)
+    gk = const.read_moments()
+    const.close()
+    assert np.abs(gk["T"] - g["T"]).max() > 1e-6 * np.abs(g["T"]).max()
+
+
+def test_weak_cv_of_T_ternary_tube_fp32_1000_steps(mc, oracle_mod):
+    """256 x 4 x 4 walled tube, weak coupling with C_v(T) and T-dependent
+    transport, FP32 storage, FP64 collision, 1000 steps."""
+    params, f = W.ternary_tube()
+    params = _cv_and_transport(dict(params, weak=1), T0=1 / 3)
+    o = oracle_mod.OracleSim(params)
+    o.init_fields(**f)
+    o.step(1000)
+    om = o.read_moments()
+    s = mc.Sim(params, mc.MCLBM_FP32)
+    s.init_fields(**f)
+    s.step(1000)
+    g = s.read_moments()
+    s.close()
+    errs = field_errors(g, om)
+    print("weak cvt C2 fp32 1000", errs)
+    for k in FIELDS:
+        assert errs[k] < 1e-5, (k, errs[k])
