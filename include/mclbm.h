@@ -78,9 +78,9 @@ typedef struct {
                           fields `inlet`) and a zero-gradient outlet at x = nx - 1 (the
                           populations entering it are the boundary node's post-collision
                           values), both as in the opposed jets of Sec. 4.5; open ends
-                          are compiled for strong coupling, constant cv, MCLBM_FP64 and
-                          MCLBM_FP32 (else MCLBM_EUNSUPPORTED). z is always periodic;
-                          y is periodic unless wall_y                                  */
+                          are compiled for MCLBM_FP64 and MCLBM_FP32 (else
+                          MCLBM_EUNSUPPORTED), with either coupling and either kind of
+                          properties. z is always periodic; y is periodic unless wall_y */
   int32_t precision;   /* MCLBM_FP64 .. MCLBM_BF16                                    */
   int32_t weak;        /* 0: strong coupling (Sec. 3.6.2): species M is slaved to the
                           momentum lattice (eqs rhoMATCH, uMATCH) and not stored.
@@ -91,8 +91,8 @@ typedef struct {
                           (else MCLBM_EUNSUPPORTED); all tubes of a batch agree     */
   int32_t wall_y;      /* 0: periodic in y; 1: free-slip walls at both y ends (half-way,
                           specular reflection: the lateral walls of the opposed jets,
-                          Sec. 4.5), with periodic or walled x ends; strong coupling,
-                          constant cv and transport, MCLBM_FP64 and MCLBM_FP32 (else
+                          Sec. 4.5), with periodic or walled x ends, either coupling and
+                          either kind of properties; MCLBM_FP64 and MCLBM_FP32 (else
                           MCLBM_EUNSUPPORTED); all tubes of a batch agree           */
   const double *molar_mass;  /* [M] molar masses m_a > 0                              */
   const double *cv;          /* [M] mass-based specific heats C_{a,v} > 0             */

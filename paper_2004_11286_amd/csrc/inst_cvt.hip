@@ -4,9 +4,9 @@
 #include "kernels.hpp"
 
 namespace mclbm {
-bool pick_fp64_cvt(int M, int walls, kern::Ops& o) { return kern::pick_m<double, double, double, false, true>(M, walls, o); }
+bool pick_fp64_cvt(int M, int walls, kern::Ops& o) { return kern::pick_m_any<double, double, double, false, true>(M, walls, o); }
 bool pick_fp32_fp64_cvt(int M, int walls, kern::Ops& o)
 {
-  return kern::pick_m<float, double, float, false, true>(M, walls, o);
+  return kern::pick_m_any<float, double, float, false, true>(M, walls, o);
 }
 }  // namespace mclbm

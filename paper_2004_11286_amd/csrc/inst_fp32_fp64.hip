@@ -8,13 +8,9 @@ bool pick_fp32_fp64_weak_cvt(int M, int walls, kern::Ops& o);   // inst_weak_cvt
 
 bool pick_fp32_fp64(int M, int walls, int weak, int cvt, kern::Ops& o)
 {
-  const int wx = walls & 3;
-  if (walls & 4) return !weak && !cvt && wx != 2 && kern::pick_m_yslip<float, double, float>(M, wx, o);
-  if (wx == 2 && (weak || cvt)) return false;
-  if (wx == 2) return kern::pick_m_open<float, double, float>(M, o);
   if (weak && cvt) return pick_fp32_fp64_weak_cvt(M, walls, o);
   if (weak) return pick_fp32_fp64_weak(M, walls, o);
   if (cvt) return pick_fp32_fp64_cvt(M, walls, o);
-  return kern::pick_m<float, double, float, false>(M, walls, o);
+  return kern::pick_m_any<float, double, float, false, false>(M, walls, o);
 }
 }  // namespace mclbm

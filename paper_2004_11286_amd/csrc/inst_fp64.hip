@@ -8,13 +8,9 @@ bool pick_fp64_weak_cvt(int M, int walls, kern::Ops& o);   // inst_weak_cvt.hip
 
 bool pick_fp64(int M, int walls, int weak, int cvt, kern::Ops& o)
 {
-  const int wx = walls & 3;
-  if (walls & 4) return !weak && !cvt && wx != 2 && kern::pick_m_yslip<double, double, double>(M, wx, o);
-  if (wx == 2 && (weak || cvt)) return false;
-  if (wx == 2) return kern::pick_m_open<double, double, double>(M, o);
   if (weak && cvt) return pick_fp64_weak_cvt(M, walls, o);
   if (weak) return pick_fp64_weak(M, walls, o);
   if (cvt) return pick_fp64_cvt(M, walls, o);
-  return kern::pick_m<double, double, double, false>(M, walls, o);
+  return kern::pick_m_any<double, double, double, false, false>(M, walls, o);
 }
 }  // namespace mclbm

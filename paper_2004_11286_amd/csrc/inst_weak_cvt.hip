@@ -6,10 +6,10 @@
 namespace mclbm {
 bool pick_fp64_weak_cvt(int M, int walls, kern::Ops& o)
 {
-  return kern::pick_m<double, double, double, true, true>(M, walls, o);
+  return kern::pick_m_any<double, double, double, true, true>(M, walls, o);
 }
 bool pick_fp32_fp64_weak_cvt(int M, int walls, kern::Ops& o)
 {
-  return kern::pick_m<float, double, float, true, true>(M, walls, o);
+  return kern::pick_m_any<float, double, float, true, true>(M, walls, o);
 }
 }  // namespace mclbm

@@ -131,13 +131,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(collide_p
 
 // Open x ends: rewrite the populations entering the two boundary planes after
 // the collision (a launch over all nodes; only x = 0 and x = nx - 1 write).
-template <typename S, typename R, int M>
+template <typename S, typename R, int M, bool WEAK>
 __global__ __launch_bounds__(BLOCK) void k_open_fix(const Params<R>* __restrict__ P, Launch Ln, S* __restrict__ dst,
                                                     StepNo sn)
 {
   const Where w = locate(Ln);
   const Params<R>& Pt = P[w.t];
-  if (w.node < Pt.n) open_fix_node<S, R, Lat<M, false>::L>(Pt, dst + pop_stride<M, false>() * w.base, w.node, step_of(sn));
+  if (w.node < Pt.n) open_fix_node<S, R, Lat<M, WEAK>::L>(Pt, dst + pop_stride<M, WEAK>() * w.base, w.node, step_of(sn));
 }
 
 template <typename T>
@@ -338,7 +338,7 @@ Ops make_ops()
   o.open_fix = nullptr;
   if constexpr (xbc(W) == BC_OPEN) {
     o.open_fix = [](const void* P, const Launch& ln, void* dst, StepNo sn, unsigned grid, hipStream_t st) {
-      hipLaunchKernelGGL((k_open_fix<S, R, M>), dim3(grid), dim3(BLOCK), 0, st, (const Params<R>*)P, ln, (S*)dst, sn);
+      hipLaunchKernelGGL((k_open_fix<S, R, M, WEAK>), dim3(grid), dim3(BLOCK), 0, st, (const Params<R>*)P, ln, (S*)dst, sn);
     };
   }
   return o;
@@ -356,30 +356,40 @@ bool pick_m(int M, int walls, Ops& o)
   }
 }
 
-// free-slip y walls with periodic (walls_x = 0) or walled (1) x ends (strong
-// coupling, constant heat capacities and transport)
-template <typename S, typename R, typename Rec>
+// free-slip y walls with periodic (walls_x = 0) or walled (1) x ends
+template <typename S, typename R, typename Rec, bool WEAK = false, bool CVT = false>
 bool pick_m_yslip(int M, int walls_x, Ops& o)
 {
   constexpr int P = BC_YSLIP | BC_PERIODIC, Wl = BC_YSLIP | BC_WALLS;
   switch (M) {
-    case 2: o = walls_x ? make_ops<S, R, Rec, 2, Wl, false, false>() : make_ops<S, R, Rec, 2, P, false, false>(); return true;
-    case 3: o = walls_x ? make_ops<S, R, Rec, 3, Wl, false, false>() : make_ops<S, R, Rec, 3, P, false, false>(); return true;
-    case 4: o = walls_x ? make_ops<S, R, Rec, 4, Wl, false, false>() : make_ops<S, R, Rec, 4, P, false, false>(); return true;
+    case 2: o = walls_x ? make_ops<S, R, Rec, 2, Wl, WEAK, CVT>() : make_ops<S, R, Rec, 2, P, WEAK, CVT>(); return true;
+    case 3: o = walls_x ? make_ops<S, R, Rec, 3, Wl, WEAK, CVT>() : make_ops<S, R, Rec, 3, P, WEAK, CVT>(); return true;
+    case 4: o = walls_x ? make_ops<S, R, Rec, 4, Wl, WEAK, CVT>() : make_ops<S, R, Rec, 4, P, WEAK, CVT>(); return true;
     default: return false;
   }
 }
 
-// open x ends (strong coupling, constant heat capacities)
-template <typename S, typename R, typename Rec>
+// open x ends (periodic y)
+template <typename S, typename R, typename Rec, bool WEAK = false, bool CVT = false>
 bool pick_m_open(int M, Ops& o)
 {
   switch (M) {
-    case 2: o = make_ops<S, R, Rec, 2, BC_OPEN, false, false>(); return true;
-    case 3: o = make_ops<S, R, Rec, 3, BC_OPEN, false, false>(); return true;
-    case 4: o = make_ops<S, R, Rec, 4, BC_OPEN, false, false>(); return true;
+    case 2: o = make_ops<S, R, Rec, 2, BC_OPEN, WEAK, CVT>(); return true;
+    case 3: o = make_ops<S, R, Rec, 3, BC_OPEN, WEAK, CVT>(); return true;
+    case 4: o = make_ops<S, R, Rec, 4, BC_OPEN, WEAK, CVT>(); return true;
     default: return false;
   }
+}
+
+// every boundary set: walls = the x mode (0 periodic, 1 walls, 2 open) plus 4
+// for free-slip y walls (not with open x ends)
+template <typename S, typename R, typename Rec, bool WEAK, bool CVT>
+bool pick_m_any(int M, int walls, Ops& o)
+{
+  const int wx = walls & 3;
+  if (walls & 4) return wx != 2 && pick_m_yslip<S, R, Rec, WEAK, CVT>(M, wx, o);
+  if (wx == 2) return pick_m_open<S, R, Rec, WEAK, CVT>(M, o);
+  return pick_m<S, R, Rec, WEAK, CVT>(M, wx, o);
 }
 
 }  // namespace kern
@@ -389,7 +399,7 @@ bool pick_m_open(int M, Ops& o)
 // for weak coupling; cvt: 1 for temperature-dependent specific heats and
 // transport. Open ends, free-slip walls, weak coupling and the temperature-
 // dependent kernels are compiled for FP64 and FP32 storage with FP64
-// arithmetic only, one at a time.
+// arithmetic only, in every combination (free-slip y walls not with open x ends).
 bool pick_fp64(int M, int walls, int weak, int cvt, kern::Ops& o);
 bool pick_fp32_fp64(int M, int walls, int weak, int cvt, kern::Ops& o);
 bool pick_fp32(int M, int walls, int weak, int cvt, kern::Ops& o);

@@ -305,9 +305,8 @@ int validate_one(const mclbm_params* p, std::string& err)
       err = "inlet: mole fractions must be non-negative and sum to 1, p and T positive";
       return MCLBM_EARG;
     }
-    if (p->weak || p->cv_coef || p->transport_exp || (p->precision != MCLBM_FP64 && p->precision != MCLBM_FP32)) {
-      err = "open x ends are compiled for strong coupling with constant cv and transport, MCLBM_FP64 and "
-            "MCLBM_FP32 only";
+    if (p->precision != MCLBM_FP64 && p->precision != MCLBM_FP32) {
+      err = "open x ends are compiled for MCLBM_FP64 and MCLBM_FP32 only";
       return MCLBM_EUNSUPPORTED;
     }
   }
@@ -317,10 +316,8 @@ int validate_one(const mclbm_params* p, std::string& err)
   if (p->wall_y != 0 && p->wall_y != 1) { err = "wall_y must be 0 or 1"; return MCLBM_EARG; }
   if (p->wall_y) {
     if (p->ny < 2) { err = "free-slip y walls need ny >= 2"; return MCLBM_EARG; }
-    if (p->weak || p->cv_coef || p->transport_exp || p->wall_x == 2 ||
-        (p->precision != MCLBM_FP64 && p->precision != MCLBM_FP32)) {
-      err = "free-slip y walls are compiled for strong coupling with constant cv and transport, periodic or "
-            "walled x ends, MCLBM_FP64 and MCLBM_FP32 only";
+    if (p->wall_x == 2 || (p->precision != MCLBM_FP64 && p->precision != MCLBM_FP32)) {
+      err = "free-slip y walls are compiled for periodic or walled x ends, MCLBM_FP64 and MCLBM_FP32 only";
       return MCLBM_EUNSUPPORTED;
     }
   }
@@ -422,6 +419,18 @@ Launch launch_one(const mclbm_ctx* c, int t)
   return Launch{c->dTubes, c->dBlkTube, c->ntubes, c->hTubes[t].first_block, c->lc.swizzle, 0};
 }
 
+// The equilibrium of the inlet fields in every stored lattice of a context's
+// coupling and heat-capacity mode (one node, n = 1).
+template <int M>
+int inlet_node(int weak, int cvt, const Params<double>& P1, const double* in, double* dev)
+{
+  const double *X = in, *p = in + M, *T = in + M + 1, *u = in + M + 2;
+  if (weak && cvt) return init_node<double, M, true, true>(P1, X, p, T, u, dev, 0);
+  if (weak) return init_node<double, M, true, false>(P1, X, p, T, u, dev, 0);
+  if (cvt) return init_node<double, M, false, true>(P1, X, p, T, u, dev, 0);
+  return init_node<double, M>(P1, X, p, T, u, dev, 0);
+}
+
 int push_params(mclbm_ctx* c)
 {
   HIP_TRY(c, hipStreamSynchronize(c->stream));   // previous uploads from the host blocks are done
@@ -443,9 +452,9 @@ int push_params(mclbm_ctx* c)
       const double* in = th.inlet;
       int bad = 1;
       switch (M) {
-        case 2: bad = init_node<double, 2>(P1, in, in + M, in + M + 1, in + M + 2, dev, 0); break;
-        case 3: bad = init_node<double, 3>(P1, in, in + M, in + M + 1, in + M + 2, dev, 0); break;
-        case 4: bad = init_node<double, 4>(P1, in, in + M, in + M + 1, in + M + 2, dev, 0); break;
+        case 2: bad = inlet_node<2>(c->weak, c->cvt, P1, in, dev); break;
+        case 3: bad = inlet_node<3>(c->weak, c->cvt, P1, in, dev); break;
+        case 4: bad = inlet_node<4>(c->weak, c->cvt, P1, in, dev); break;
         default: break;
       }
       if (bad) return fail(c, MCLBM_ESTATE, "infeasible inlet state (R_a T + u^2 >= 1)");

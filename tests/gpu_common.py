@@ -70,3 +70,33 @@ def oracle_window(hdr: dict, vals: np.ndarray, center, radius: int) -> np.ndarra
         dst = l if (L == M + 2 or l < M - 1) else l + 1
         out[dst] = f
     return out
+
+
+# The coupling and property modes beyond strong coupling with constant
+# properties: (weak, temperature-dependent heat capacities and transport).
+OTHER_MODES = [(1, False), (0, True), (1, True)]
+
+
+def with_mode(params, weak, props, T=0.3):
+    """params with weak coupling and/or cubic C_{a,v}(T) (different per species)
+    and transport coefficients as powers of T / T_ref, T_ref = T / 1.2."""
+    params = dict(params, weak=int(weak))
+    if props:
+        M = params["M"]
+        cv = np.asarray(params["cv"], dtype=np.float64)
+        params["cv_coef"] = np.stack([cv[a] * np.array([1.0, 0.4 / T, 0.1 / T ** 2, 0.05 * (a + 1) / T ** 3])
+                                      for a in range(M)])
+        params["transport_exp"] = np.concatenate([0.7 + 0.1 * np.arange(M), 0.8 + 0.05 * np.arange(M),
+                                                  [1.75, T / 1.2]])
+    return params
+
+
+def stored_population_error(hdr, vals, oracle_pops, M, weak):
+    """Relative L-inf error of every stored lattice of a checkpoint against the
+    oracle's populations (all M + 2 under weak coupling; the slaved species'
+    lattice is not stored under strong coupling)."""
+    L = vals.shape[0]
+    gp = np.stack([hdr["ref"][l][:, None, None, None] + vals[l].astype(np.float64) / hdr["scale"][l]
+                   for l in range(L)])
+    ref = oracle_pops if weak else np.concatenate([oracle_pops[:M - 1], oracle_pops[M:M + 2]])
+    return float(np.abs(gp - ref).max() / np.abs(ref).max())

@@ -139,18 +139,21 @@ def test_open_ends_validation():
         with pytest.raises(m.MclbmError) as e:
             m.mclbm_workspace_bytes(dict(q, inlet=bad), m.MCLBM_FP32)
         assert "inlet" in str(e.value)
-    for r, prec in ((dict(q, weak=1), m.MCLBM_FP64), (dict(q, cv_coef=np.ones((3, 4))), m.MCLBM_FP64),
-                    (q, m.MCLBM_FP16)):
-        with pytest.raises(m.MclbmError) as e:
-            m.mclbm_workspace_bytes(r, prec)
-        assert "open x ends" in str(e.value)
+    # with either coupling and either kind of properties: the workspace of the walled tube
+    for r in (dict(q, weak=1), dict(q, cv_coef=np.ones((3, 4))), dict(q, weak=1, cv_coef=np.ones((3, 4)))):
+        w = dict(r, wall_x=1)
+        del w["inlet"]
+        assert m.mclbm_workspace_bytes(r, m.MCLBM_FP64) == m.mclbm_workspace_bytes(w, m.MCLBM_FP64)
+    with pytest.raises(m.MclbmError) as e:
+        m.mclbm_workspace_bytes(q, m.MCLBM_FP16)
+    assert "open x ends" in str(e.value)
     with pytest.raises(m.MclbmError):
         m.mclbm_workspace_bytes(dict(p, wall_x=3), m.MCLBM_FP32)
 
 
 def test_free_slip_validation():
-    """Free-slip y walls need ny >= 2 and are compiled for strong coupling with
-    constant properties, periodic or walled x ends and FP64 arithmetic."""
+    """Free-slip y walls need ny >= 2 and are compiled for periodic or walled x
+    ends and FP64 arithmetic, with either coupling and either kind of properties."""
     m = pytest.importorskip("paper_2004_11286_amd.mclbm")
     p, _ = W.ternary_tube(nx=16, ny=4, nz=2)
     assert m.mclbm_workspace_bytes(dict(p, wall_y=1), m.MCLBM_FP32) == m.mclbm_workspace_bytes(p, m.MCLBM_FP32)
@@ -158,7 +161,9 @@ def test_free_slip_validation():
         with pytest.raises(m.MclbmError):
             m.mclbm_workspace_bytes(bad, m.MCLBM_FP32)
     inlet = np.array([0.3, 0.3, 0.4, p["P0"], 1 / 3, 0.05, 0.0, 0.0])
-    for q, prec in ((dict(p, wall_y=1, weak=1), m.MCLBM_FP64), (dict(p, wall_y=1), m.MCLBM_BF16),
+    for q in (dict(p, weak=1), dict(p, cv_coef=np.ones((3, 4))), dict(p, weak=1, wall_x=1)):
+        assert m.mclbm_workspace_bytes(dict(q, wall_y=1), m.MCLBM_FP64) == m.mclbm_workspace_bytes(q, m.MCLBM_FP64)
+    for q, prec in ((dict(p, wall_y=1, weak=1), m.MCLBM_FP32_FP32), (dict(p, wall_y=1), m.MCLBM_BF16),
                     (dict(p, wall_y=1, wall_x=2, inlet=inlet), m.MCLBM_FP64)):
         with pytest.raises(m.MclbmError) as e:
             m.mclbm_workspace_bytes(q, prec)

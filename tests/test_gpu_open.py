@@ -4,12 +4,14 @@ ends are pinned on the CPU (tests/test_oracle_open.py). Compared here: fields
 and stored populations on ragged grids with an inlet state different from the
 interior (FP64), the uniform through-flow fixed point, the inflow front of the
 advection-diffusion pin (FP64 and FP32), and a walled-tube-sized ternary
-through-flow over 1000 steps (FP32).
+through-flow over 1000 steps (FP32); the same ragged grids under weak coupling
+and with temperature-dependent heat capacities and transport, and the
+through-flow with both (FP32).
 """
 import numpy as np
 import pytest
 
-from gpu_common import FIELDS, decode_checkpoint, field_errors
+from gpu_common import FIELDS, OTHER_MODES, decode_checkpoint, field_errors, stored_population_error, with_mode
 import physics_cases as pc
 from paper_2004_11286_amd import workloads as W
 
@@ -137,5 +139,58 @@ def test_open_ternary_through_flow_fp32_1000_steps(mc, oracle_mod):
     s.close()
     errs = field_errors(g, om)
     print("open C2 fp32 1000", errs)
+    for k in FIELDS:
+        assert errs[k] < 1e-5, (k, errs[k])
+
+
+@pytest.mark.parametrize("weak,props", OTHER_MODES)
+@pytest.mark.parametrize("M", [2, 3, 4])
+def test_open_other_modes_ragged_grid_fp64(mc, oracle_mod, M, weak, props):
+    """Weak coupling and/or C_v(T) with T-dependent transport: 13 x 7 x 5 nodes,
+    20 steps in FP64, fields, mass and energy sums and every stored population
+    against the oracle."""
+    params, f = _case(M, 13, 7, 5, seed=131 + M + 5 * weak + 10 * props)
+    params = with_mode(params, weak, props)
+    s = mc.Sim(params, mc.MCLBM_FP64)
+    s.init_fields(**f)
+    s.step(20)
+    g, gc = s.read_moments(), s.conservation()
+    hdr, vals = decode_checkpoint(s.save())
+    s.close()
+    o = oracle_mod.OracleSim(params)
+    o.init_fields(**f)
+    o.step(20)
+    om, oc, op = o.read_moments(), o.conservation(), o.populations()
+    errs = field_errors(g, om)
+    pop_err = stored_population_error(hdr, vals, op, M, weak)
+    print("open modes fp64", M, weak, props, errs, "populations", pop_err)
+    for k in FIELDS:
+        assert errs[k] < 1e-12, (k, errs[k])
+    assert pop_err < 1e-12
+    np.testing.assert_allclose(gc[:M + 1], oc[:M + 1], rtol=1e-12)
+    np.testing.assert_allclose(gc[M + 4], oc[M + 4], rtol=1e-12)
+
+
+def test_open_weak_cv_of_T_through_flow_fp32_1000_steps(mc, oracle_mod):
+    """The ternary tube's interface carried through open ends by a mean flow of
+    0.02, weak coupling with C_v(T) and T-dependent transport, FP32 storage,
+    1000 steps."""
+    params, f = W.ternary_tube()
+    Xl = [float(v) for v in f["X"][:, 0, 0, 0]]
+    params = with_mode(dict(params, wall_x=2, inlet=np.array(Xl + [params["P0"], T0, 0.02, 0.0, 0.0])), 1, True,
+                       T=T0)
+    f = dict(f, u=f["u"].copy())
+    f["u"][0] += 0.02
+    o = oracle_mod.OracleSim(params)
+    o.init_fields(**f)
+    o.step(1000)
+    om = o.read_moments()
+    s = mc.Sim(params, mc.MCLBM_FP32)
+    s.init_fields(**f)
+    s.step(1000)
+    g = s.read_moments()
+    s.close()
+    errs = field_errors(g, om)
+    print("open weak cvt fp32 1000", errs)
     for k in FIELDS:
         assert errs[k] < 1e-5, (k, errs[k])

@@ -1,11 +1,13 @@
 """GPU parity of free-slip y walls (wall_y = 1: specular reflection at the y ends,
 mirrored stencil ghosts with Phi_y odd) against the oracle, through the C ABI.
 The oracle's free-slip walls are pinned on the CPU (tests/test_oracle_slip.py).
+Compared here with strong coupling and constant properties, and under weak
+coupling and/or temperature-dependent heat capacities and transport.
 """
 import numpy as np
 import pytest
 
-from gpu_common import FIELDS, decode_checkpoint, field_errors
+from gpu_common import FIELDS, OTHER_MODES, decode_checkpoint, field_errors, stored_population_error, with_mode
 from paper_2004_11286_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -129,3 +131,55 @@ def test_slip_checkpoint_resume_and_mismatch(mc):
     with pytest.raises(mc.MclbmError):
         other.load(buf)
     other.close()
+
+
+@pytest.mark.parametrize("weak,props", OTHER_MODES)
+@pytest.mark.parametrize("M", [2, 3, 4])
+@pytest.mark.parametrize("walls", [0, 1])
+def test_slip_other_modes_ragged_grid_fp64(mc, oracle_mod, M, walls, weak, props):
+    """Weak coupling and/or C_v(T) with T-dependent transport: 13 x 7 x 5 nodes,
+    20 steps in FP64, fields, mass and energy sums and every stored population
+    against the oracle."""
+    params, f = _case(M, 13, 7, 5, walls, seed=151 + 2 * M + walls + 10 * weak + 20 * props)
+    params = with_mode(params, weak, props)
+    s = mc.Sim(params, mc.MCLBM_FP64)
+    s.init_fields(**f)
+    s.step(20)
+    g, gc = s.read_moments(), s.conservation()
+    hdr, vals = decode_checkpoint(s.save())
+    s.close()
+    o = oracle_mod.OracleSim(params)
+    o.init_fields(**f)
+    o.step(20)
+    om, oc, op = o.read_moments(), o.conservation(), o.populations()
+    errs = field_errors(g, om)
+    pop_err = stored_population_error(hdr, vals, op, M, weak)
+    print("slip modes fp64", M, walls, weak, props, errs, "populations", pop_err)
+    for k in FIELDS:
+        assert errs[k] < 1e-12, (k, errs[k])
+    assert pop_err < 1e-12
+    np.testing.assert_allclose(gc[:M + 1], oc[:M + 1], rtol=1e-12)
+    np.testing.assert_allclose(gc[M + 4], oc[M + 4], rtol=1e-12)
+
+
+def test_slip_weak_cv_of_T_fp32_1000_steps(mc, oracle_mod):
+    """The 64 x 16 x 4 walled interface with free-slip y walls and a shear flow,
+    weak coupling with C_v(T) and T-dependent transport, FP32 storage, 1000 steps."""
+    params, f = W.ternary_tube(nx=64, ny=16, nz=4)
+    params = with_mode(dict(params, wall_y=1), 1, True, T=1 / 3)
+    f = dict(f, u=f["u"].copy())
+    y = np.arange(16, dtype=np.float64) + 0.5
+    f["u"][2] += 0.02 * np.cos(np.pi * y / 16)[None, :, None]
+    o = oracle_mod.OracleSim(params)
+    o.init_fields(**f)
+    o.step(1000)
+    om = o.read_moments()
+    s = mc.Sim(params, mc.MCLBM_FP32)
+    s.init_fields(**f)
+    s.step(1000)
+    g = s.read_moments()
+    s.close()
+    errs = field_errors(g, om)
+    print("slip weak cvt fp32 1000", errs)
+    for k in FIELDS:
+        assert errs[k] < 1e-5, (k, errs[k])

@@ -7,7 +7,9 @@ What fixes the results: a plug flow parallel to the walls is a fixed point; the
 walls exchange no tangential momentum, so mass, energy and the x and z momenta
 are conserved exactly while the y momentum is not; and a shear mode whose
 profile has zero slope at both walls, u_x = A cos(pi (y + 1/2) / ny), decays at
-nu (pi / ny)^2, the free-slip (Neumann) eigenvalue.
+nu (pi / ny)^2, the free-slip (Neumann) eigenvalue. The fixed point and the
+conservation laws hold under weak coupling and with temperature-dependent heat
+capacities and transport as well.
 """
 import numpy as np
 import pytest
@@ -78,3 +80,56 @@ def test_neumann_shear_mode_decays_at_free_slip_rate(oracle_mod):
     nu = wilke_mu(params["mu"], params["molar_mass"], X) / rho
     print("decay", G, "free-slip", nu * k * k)
     assert G / (nu * k * k) == pytest.approx(1.0, abs=0.01)
+
+
+def _with_mode(params, weak, props, T=1 / 3):
+    params = dict(params, weak=weak)
+    if props:
+        M = params["M"]
+        cv = np.asarray(params["cv"], dtype=np.float64)
+        params["cv_coef"] = np.stack([cv[a] * np.array([1.0, 0.4 / T, 0.1 / T ** 2, 0.05 * (a + 1) / T ** 3])
+                                      for a in range(M)])
+        params["transport_exp"] = np.concatenate([0.7 + 0.1 * np.arange(M), 0.8 + 0.05 * np.arange(M),
+                                                  [1.75, T / 1.2]])
+    return params
+
+
+MODES = [(1, False), (0, True), (1, True)]
+
+
+@pytest.mark.parametrize("weak,props", MODES)
+def test_plug_flow_fixed_point_other_modes(oracle_mod, weak, props):
+    """The plug flow between free-slip walls stays put under weak coupling (every
+    lattice, species M's included, reflected) and with C_v(T) and T-dependent
+    transport."""
+    params, _ = W.ternary_tube(nx=6, ny=8, nz=3)
+    X, P0, T0, u = [0.3, 0.3, 0.4], params["P0"], 1 / 3, (0.05, 0.0, 0.02)
+    params = _with_mode(dict(params, wall_x=0, wall_y=1), weak, props)
+    s = oracle_mod.OracleSim(params)
+    s.init_fields(**W.uniform_state(params, 6, 8, 3, X=X, p=P0, T=T0, u=u))
+    p0 = s.populations()
+    s.step(200)
+    p1 = s.populations()
+    stored = list(range(5)) if weak else [0, 1, 3, 4]
+    assert np.abs(p1[stored] - p0[stored]).max() <= 1e-13 * np.abs(p0[stored]).max()
+
+
+@pytest.mark.parametrize("weak,props", MODES)
+def test_free_slip_conservation_other_modes(oracle_mod, weak, props):
+    """Periodic x, free-slip y walls: every species' mass, the mixture's mass and
+    energy, and the x and z momenta are conserved in every mode; the walls take
+    y momentum."""
+    params, _ = W.ternary_tube(nx=10, ny=8, nz=4)
+    params = _with_mode(dict(params, wall_x=0, wall_y=1), weak, props)
+    f = W.random_near_equilibrium(params, 10, 8, 4, seed=23, X0=[0.3, 0.3, 0.4], p0=params["P0"], T0=1 / 3,
+                                  amp=0.05, uamp=0.03)
+    s = oracle_mod.OracleSim(params)
+    s.init_fields(**f)
+    c0 = s.conservation()
+    s.step(200)
+    c1 = s.conservation()
+    M = params["M"]
+    mass_like = list(range(M + 1)) + [M + 4]
+    np.testing.assert_allclose(c1[mass_like], c0[mass_like], rtol=1e-12)
+    np.testing.assert_allclose(c1[[M + 1, M + 3]], c0[[M + 1, M + 3]], atol=1e-12 * c0[M])
+    assert abs(c1[M + 2] - c0[M + 2]) > 1e-6 * c0[M]
