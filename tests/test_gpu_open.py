@@ -194,3 +194,28 @@ def test_open_weak_cv_of_T_through_flow_fp32_1000_steps(mc, oracle_mod):
     print("open weak cvt fp32 1000", errs)
     for k in FIELDS:
         assert errs[k] < 1e-5, (k, errs[k])
+
+
+def test_open_weak_cv_of_T_checkpoint_resume_and_mismatch(mc):
+    """A weakly coupled context with C_v(T) and open x ends resumes bit for bit
+    from its checkpoint (all M + 2 lattices); contexts that differ in coupling or
+    in the kind of heat capacities refuse it."""
+    params, f = _case(3, 16, 6, 4, seed=9)
+    params = with_mode(params, 1, True)
+    s = mc.Sim(params, mc.MCLBM_FP32)
+    s.init_fields(**f)
+    s.step(7)
+    buf = s.save()
+    s.step(5)
+    a = s.read_moments()
+    s.load(buf)
+    s.step(5)
+    b = s.read_moments()
+    s.close()
+    for k in FIELDS:
+        np.testing.assert_array_equal(a[k], b[k])
+    for other_params in (dict(params, weak=0), {k: v for k, v in params.items() if k not in ("cv_coef", "transport_exp")}):
+        other = mc.Sim(other_params, mc.MCLBM_FP32)
+        with pytest.raises(mc.MclbmError):
+            other.load(buf)
+        other.close()
