@@ -260,18 +260,26 @@ def test_stream_copy_is_exact(mc):
         assert torch.equal(a, b), n
 
 
-@pytest.mark.parametrize("model", ["weak", "cv_of_T"])
+@pytest.mark.parametrize("model", ["weak", "cv_of_T", "weak_cv_of_T_open", "weak_cv_of_T_slip"])
 def test_batch_models_match_oracle_and_single_contexts(mc, oracle_mod, model):
-    """Weak coupling and temperature-dependent heat capacities in a batch of ragged
-    tubes (each with its own species data): every tube bit for bit equal to its
-    own single-tube context, and within 1e-12 of the oracle (FP64, 30 steps)."""
+    """Weak coupling and temperature-dependent heat capacities, apart and together
+    (between open x ends, each tube fed at its own left-end state, or between
+    free-slip y walls), in a batch of ragged tubes (each with its own species
+    data): every tube bit for bit equal to its own single-tube context, and
+    within 1e-12 of the oracle (FP64, 30 steps)."""
     tubes = []
     for p, f in small_ensemble(n=4, seed=21):
-        if model == "weak":
+        if model.startswith("weak"):
             p = dict(p, weak=1)
-        else:
+        if "cv_of_T" in model:
             cv = np.asarray(p["cv"], dtype=np.float64)
             p = dict(p, cv_coef=np.stack([cv[a] * np.array([1.0, 0.5 * 3, 0.0, 0.2 * 27]) for a in range(p["M"])]))
+        if model.endswith("open"):
+            Xl = [float(v) for v in f["X"][:, 0, 0, 0]]
+            p = dict(p, wall_x=2, inlet=np.array(Xl + [float(f["p"][0, 0, 0]), float(f["T"][0, 0, 0]), 0.02, 0.0, 0.0]))
+            f = dict(f, u=f["u"] + np.array([0.02, 0.0, 0.0])[:, None, None, None])
+        if model.endswith("slip"):
+            p = dict(p, wall_y=1)
         tubes.append((p, f))
     g, _ = run_batch(mc, tubes, mc.MCLBM_FP64, 30)
     for t, (params, f) in enumerate(tubes):
