@@ -378,6 +378,21 @@ def main():
         del v
         torch.cuda.empty_cache()
 
+    weak_fp16 = None
+    if not args.no_variants:
+        # weak coupling with FP16 deviation storage and FP32 arithmetic
+        v, el, st = time_run(mc, dict(params, weak=1), fields, mc.MCLBM_FP16, args.steps, args.warmup)
+        hab = algorithmic_bytes(M, 2, 4, weak=True)
+        hcol = st["k_collide"]["avg_ms"]
+        weak_fp16 = {"MLUPS": n * args.steps / el / 1e6, "ms_per_step": el / args.steps * 1e3,
+                     "launch": v.launch(), "collide_avg_ms": hcol,
+                     "collide_algorithmic_bytes_per_node": hab["k_collide"],
+                     "collide_GBs": hab["k_collide"] * n / (hcol * 1e-3) / 1e9,
+                     "kernels_avg_ms": {k: x["avg_ms"] for k, x in st.items()}}
+        v.close()
+        del v
+        torch.cuda.empty_cache()
+
     cv_of_T = None
     if not args.no_variants:
         # temperature-dependent heat capacities (cubic C_{a,v}(T), about twice the
@@ -465,6 +480,7 @@ def main():
                                "method_min_frac": ab["method_min"] * mlups * 1e6 / 1e9 / HBM_PEAK_GBS},
         "variants": variants,
         "weak_coupling": weak,
+        "weak_fp16": weak_fp16,
         "cv_of_T": cv_of_T,
         "weak_cv_of_T": weak_cv_of_T,
         "open_x": open_x,

@@ -87,8 +87,9 @@ typedef struct {
                           1: weak coupling (Sec. 3.6.1): all M species lattices are
                           stored and evolved; the species keep their own density and
                           velocity (eqs rhoSPEC, uSPEC) and Dalton pressure, and take
-                          T from the energy lattice. MCLBM_FP64 and MCLBM_FP32 only
-                          (else MCLBM_EUNSUPPORTED); all tubes of a batch agree     */
+                          T from the energy lattice. MCLBM_FP64, MCLBM_FP32 and
+                          MCLBM_FP16 (else MCLBM_EUNSUPPORTED); all tubes of a batch
+                          agree                                                     */
   int32_t wall_y;      /* 0: periodic in y; 1: free-slip walls at both y ends (half-way,
                           specular reflection: the lateral walls of the opposed jets,
                           Sec. 4.5), with periodic or walled x ends, either coupling and

@@ -2,9 +2,12 @@
 #include "kernels.hpp"
 
 namespace mclbm {
-// open ends, free-slip walls, weak coupling and C_v(T) are compiled for FP64 arithmetic only
+// strong and weak coupling with constant properties, periodic or walled x ends;
+// open ends, free-slip walls and C_v(T) are compiled for FP64 arithmetic only
 bool pick_fp16(int M, int walls, int weak, int cvt, kern::Ops& o)
 {
-  return !weak && !cvt && walls <= 1 && kern::pick_m<_Float16, float, float, false>(M, walls, o);
+  if (cvt || walls > 1) return false;
+  if (weak) return kern::pick_m<_Float16, float, float, true>(M, walls, o);
+  return kern::pick_m<_Float16, float, float, false>(M, walls, o);
 }
 }  // namespace mclbm

@@ -321,8 +321,8 @@ int validate_one(const mclbm_params* p, std::string& err)
       return MCLBM_EUNSUPPORTED;
     }
   }
-  if (p->weak && p->precision != MCLBM_FP64 && p->precision != MCLBM_FP32) {
-    err = "weak coupling is compiled for MCLBM_FP64 and MCLBM_FP32 only";
+  if (p->weak && p->precision != MCLBM_FP64 && p->precision != MCLBM_FP32 && p->precision != MCLBM_FP16) {
+    err = "weak coupling is compiled for MCLBM_FP64, MCLBM_FP32 and MCLBM_FP16 only";
     return MCLBM_EUNSUPPORTED;
   }
   if (p->transport_exp) {

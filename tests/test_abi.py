@@ -64,15 +64,16 @@ def test_workspace_bytes_and_validation():
 def test_weak_coupling_workspace_and_validation():
     """Weak coupling stores one more lattice (species M) in both population
     buffers and four more record fields (rho_M and the species velocity u_s); it
-    is compiled for FP64 arithmetic only, and a batch cannot mix couplings."""
+    is compiled for FP64 arithmetic and for FP16 storage, and a batch cannot mix
+    couplings."""
     m = pytest.importorskip("paper_2004_11286_amd.mclbm")
     p, _ = W.binary_interdiffusion()
     n = 64 * 8 * 8
-    for prec, s_bytes, r_bytes in ((m.MCLBM_FP64, 8, 8), (m.MCLBM_FP32, 4, 4)):
+    for prec, s_bytes, r_bytes in ((m.MCLBM_FP64, 8, 8), (m.MCLBM_FP32, 4, 4), (m.MCLBM_FP16, 2, 4)):
         strong = m.mclbm_workspace_bytes(p, prec)
         weak = m.mclbm_workspace_bytes(dict(p, weak=1), prec)
         assert weak - strong == 2 * 27 * n * s_bytes + 4 * n * r_bytes
-    for prec in (m.MCLBM_FP32_FP32, m.MCLBM_FP16, m.MCLBM_BF16):
+    for prec in (m.MCLBM_FP32_FP32, m.MCLBM_BF16):
         with pytest.raises(m.MclbmError) as e:
             m.mclbm_workspace_bytes(dict(p, weak=1), prec)
         assert "weak coupling" in str(e.value)

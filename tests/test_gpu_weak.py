@@ -139,6 +139,26 @@ def test_weak_ternary_tube_fp32_1000_steps(mc, weak_tube_1000):
         assert errs[k] < 1e-5, (k, errs[k])
 
 
+def test_weak_ternary_tube_fp16_1000_steps(mc, weak_tube_1000):
+    """The same tube with FP16 deviation storage (stochastic rounding) and FP32
+    collision: bounded like strong coupling's FP16 run (1e-2, five times that
+    for the velocity, whose maximum is only 1e-3); the stochastically rounded
+    stores keep every species' mass to 1e-4 (unbiased rounding errors)."""
+    params, f, o = weak_tube_1000
+    s = mc.Sim(params, mc.MCLBM_FP16)
+    s.init_fields(**f)
+    c0 = s.conservation()
+    s.step(1000)
+    g = s.read_moments()
+    c1 = s.conservation()
+    s.close()
+    errs = field_errors(g, o)
+    print("weak C2 fp16 1000", errs, "mass drift", np.abs(c1[:3] / c0[:3] - 1).max())
+    for k in FIELDS:
+        assert errs[k] < (5e-2 if k == "u" else 1e-2), (k, errs[k])
+    np.testing.assert_allclose(c1[:4], c0[:4], rtol=1e-4)
+
+
 def test_weak_full_size_shear_layer_windows(mc, oracle_mod):
     """The 256^3 shear layer under weak coupling, FP32 storage: the GPU state after
     20 steps, cut into 9^3 periodic windows around sampled nodes (all four stored
