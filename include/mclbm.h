@@ -4,7 +4,7 @@
  * Dorschner and Karlin (arXiv 2004.11286): M species population sets relaxing
  * under the Stefan--Maxwell kinetic model (Sec. 2), a compressible mixture
  * momentum lattice and an energy lattice (Sec. 3), all on D3Q27, strongly
- * coupled (Sec. 3.6.2) or weakly coupled (Sec. 3.6.1), fused stream-and-collide
+ * coupled (Sec. 3.5.2) or weakly coupled (Sec. 3.5.1), fused stream-and-collide
  * over every node; x ends periodic, walled or open; constant or
  * temperature-dependent specific heats and transport coefficients.
  *
@@ -24,7 +24,7 @@
  *     that return data to the host synchronise that stream. Calls on one context
  *     are not thread safe.
  *   - Under strong coupling (the default) species M (the last) is slaved to the
- *     mixture (Sec. 3.6.2): its density and momentum are the deficits of the
+ *     mixture (Sec. 3.5.2): its density and momentum are the deficits of the
  *     mixture's. Order species so that the last one carries most of the mass
  *     everywhere. Under weak coupling (mclbm_params.weak) it has its own lattice.
  *   - Batches: a context holds one or more independent lattices ("tubes", the
@@ -77,14 +77,14 @@ typedef struct {
                           populations entering node 0 are the local equilibrium of the
                           fields `inlet`) and a zero-gradient outlet at x = nx - 1 (the
                           populations entering it are the boundary node's post-collision
-                          values), both as in the opposed jets of Sec. 4.5; open ends
+                          values), both as in the opposed jets of Sec. 4.3; open ends
                           are compiled for MCLBM_FP64 and MCLBM_FP32 (else
                           MCLBM_EUNSUPPORTED), with either coupling and either kind of
                           properties. z is always periodic; y is periodic unless wall_y */
   int32_t precision;   /* MCLBM_FP64 .. MCLBM_BF16                                    */
-  int32_t weak;        /* 0: strong coupling (Sec. 3.6.2): species M is slaved to the
+  int32_t weak;        /* 0: strong coupling (Sec. 3.5.2): species M is slaved to the
                           momentum lattice (eqs rhoMATCH, uMATCH) and not stored.
-                          1: weak coupling (Sec. 3.6.1): all M species lattices are
+                          1: weak coupling (Sec. 3.5.1): all M species lattices are
                           stored and evolved; the species keep their own density and
                           velocity (eqs rhoSPEC, uSPEC) and Dalton pressure, and take
                           T from the energy lattice. MCLBM_FP64, MCLBM_FP32 and
@@ -92,7 +92,7 @@ typedef struct {
                           agree                                                     */
   int32_t wall_y;      /* 0: periodic in y; 1: free-slip walls at both y ends (half-way,
                           specular reflection: the lateral walls of the opposed jets,
-                          Sec. 4.5), with periodic or walled x ends, either coupling and
+                          Sec. 4.3), with periodic or walled x ends, either coupling and
                           either kind of properties; MCLBM_FP64 and MCLBM_FP32 (else
                           MCLBM_EUNSUPPORTED); all tubes of a batch agree           */
   const double *molar_mass;  /* [M] molar masses m_a > 0                              */
@@ -100,7 +100,7 @@ typedef struct {
   const double *D;           /* [M*M] symmetric binary diffusivities D_ab > 0, row major,
                                 diagonal included (the sums of eqs tau and fStar run over
                                 b = a)                                                 */
-  const double *mu;          /* [M] species dynamic viscosities (Wilke mixing, Sec. 3.4) */
+  const double *mu;          /* [M] species dynamic viscosities (Wilke mixing, Sec. 3.3) */
   const double *lambda;      /* [M] species thermal conductivities (Mathur mixing)    */
   const double *cv_coef;     /* NULL: constant specific heats cv (eq temperature2). Else
                                 [M][4]: C_{a,v}(T) = sum_k c_ak T^k with c_a0 > 0 and
@@ -157,8 +157,16 @@ const char *mclbm_last_error(const mclbm_ctx *c);
 int mclbm_init_fields(mclbm_ctx *c, const double *X, const double *p, const double *T,
                       const double *u, int on_device);
 
-/* Advance nsteps time steps (moments, stencil, collide-and-stream per step),
- * asynchronously on the context's stream. */
+/* Advance nsteps time steps, asynchronously on the context's stream. One step is
+ * the species lattice Boltzmann equation of Sec. 2.5.3 (eqs SMlbm, fstar1,
+ * transform12, with the moments of eqs densitya, momSPEC), the two-population
+ * mixture equations of Sec. 3.2 (eq g with eqs gstareq1mom, interdiffusion,
+ * corrFourier) realised on D3Q27 as in Sec. 3.4 (eqs gieq, gistar; the momentum
+ * lattice with the correction of Sec. 3.4.2, eqs fwithcorrection, Xalpha, Ai),
+ * coupled as in Sec. 3.5 (strong: eqs rhoMATCH, uMATCH), then streaming with the
+ * boundary rules of mclbm_params. Every non-local term (eqs Xalpha, corrFourier)
+ * uses the moments of the same time level. MCLBM_EARG before the first
+ * initialisation or for nsteps < 0; MCLBM_EDEVICE if a launch fails. */
 int mclbm_step(mclbm_ctx *c, int64_t nsteps);
 
 /* Macroscopic fields of the current state (Secs. 2.1, 2.5.3, 3.2): X [M][n],
@@ -167,7 +175,10 @@ int mclbm_step(mclbm_ctx *c, int64_t nsteps);
 int mclbm_read_moments(mclbm_ctx *c, double *X, double *rho, double *u, double *p, double *T,
                        int on_device);
 
-/* Domain sums in FP64 per tube, out [ntubes][M+5]: rho_1 .. rho_M (rho_M slaved
+/* The conserved fields of the step (eq DOF: the M species densities, or under
+ * strong coupling M - 1 of them plus the mixture density, the mixture momentum
+ * and the total energy of eq g0momTotalEnergy), summed over every node of each tube.
+ * Domain sums in FP64 per tube, out [ntubes][M+5]: rho_1 .. rho_M (rho_M slaved
  * under strong coupling, from its own lattice under weak),
  * rho, rho u_x, rho u_y, rho u_z, rho E. Returns MCLBM_ENAN if any node holds a
  * non-finite value or a negative slaved density. Synchronises the stream. */
@@ -196,11 +207,24 @@ int mclbm_set_timing(mclbm_ctx *c, int enable);
 int mclbm_kernel_stats(mclbm_ctx *c, int32_t kernel, double *total_ms, int64_t *launches,
                        const char **name);
 
-/* How mclbm_step launches its kernels. Every choice computes bit for bit the same
- * step, except split, whose two kernels are compiled separately and may fuse a
- * multiply-add differently: its results agree to rounding (and, with 16-bit
- * storage, to the stochastic rounding that such a last-bit difference can flip).
- * Only the time differs. */
+/* How mclbm_step launches its kernels. Every choice computes the same step. Within
+ * one path (two-read or three-pass) the results are bit for bit the same, except
+ * split, whose two kernels are compiled separately and may fuse a multiply-add
+ * differently: its results agree to rounding (and, with 16-bit storage, to the
+ * stochastic rounding that such a last-bit difference can flip). The two paths
+ * agree to the rounding of the stored state (the three-pass path carries the
+ * node state through a record of the storage's record precision). Only the time
+ * differs.
+ *
+ * The two-read step (three_pass = 0, where compiled: constant specific heats and
+ * transport) launches per step: the moments of every lattice, which also collide
+ * and stream the species lattices, whose collisions use only the node's own
+ * moments (eqs SMlbm, fstar1, transform12); the stencil field G; the collision
+ * and streaming of the momentum and energy lattices, whose non-local terms (eqs
+ * Xalpha, corrFourier) need the neighbours' moments of the same time level. The
+ * species populations are read once per step, f and g twice. The three-pass step
+ * (three_pass = 1) reads every lattice twice: moments, stencil field, collision
+ * of every lattice. */
 typedef struct {
   int32_t variant;      /* occupancy variant of the moments kernel, and of the fused
                            collide kernel (split = 0), 0 or 1                           */
@@ -209,23 +233,28 @@ typedef struct {
   int32_t graph_steps;  /* 0: launch each kernel of each step; K > 0 (even): replay a
                            HIP graph of K captured steps (not while timing is enabled)   */
   int32_t sequential;   /* 1: launch every tube on its own (the unbatched reference)     */
-  int32_t split;        /* 1: collide the species lattices, then the momentum and energy
-                           lattices, in two launches with fewer registers each (one
-                           occupancy form)                                              */
-  int32_t reserved[2];  /* must be 0                                                     */
+  int32_t split;        /* three-pass step only: 1: collide the species lattices, then
+                           the momentum and energy lattices, in two launches with fewer
+                           registers each (one occupancy form)                          */
+  int32_t three_pass;   /* 1: the three-pass step; 0: the two-read step where compiled
+                           (constant properties), else the three-pass step             */
+  int32_t reserved;     /* must be 0                                                     */
 } mclbm_launch;
 
-/* A new context starts with every field 0, except under weak coupling, which
- * starts with variant = 1 and split = 1 (faster with the extra stored lattice). */
+/* A new context starts with every field 0 (the two-read step where compiled),
+ * except under weak coupling with the three-pass step (temperature-dependent
+ * properties), which starts with variant = 1 and split = 1 (faster with the extra
+ * stored lattice). */
 int mclbm_get_launch(const mclbm_ctx *c, mclbm_launch *out);
 int mclbm_set_launch(mclbm_ctx *c, const mclbm_launch *in);
 
-/* Time every batched launch choice ((variant, split) in {(0,0), (1,0), (0,1)} x
- * swizzle x order x graph on/off) over trial_steps steps each on the current
- * state, keep the fastest, and write a text table of the candidates
- * (milliseconds per step) to report (may be NULL). The trial steps are ordinary
- * steps: the state and the step count advance by about (number of candidates) *
- * 2 trial_steps. Synchronises the stream. */
+/* Time every launch choice (the two-read step with variant 0 or 1 where compiled;
+ * the three-pass step with (variant, split) in {0,1}^2; each with swizzle and HIP
+ * graph replay on or off, and for batches both tube orders) over trial_steps steps
+ * each on the current state, keep the fastest, and write a text table of the
+ * candidates (milliseconds per step) to report (may be NULL). The trial steps are
+ * ordinary steps: the state and the step count advance by about (number of
+ * candidates) * 2 trial_steps. Synchronises the stream. */
 int mclbm_autotune(mclbm_ctx *c, int32_t trial_steps, char *report, size_t report_len);
 
 /* Moles of every species in each x half of every tube, FP64 (the diagnostic of

@@ -137,13 +137,20 @@ int mclbm_nn_adam_step(mclbm_nn *net, float lr, float beta1, float beta2, float 
 int mclbm_nn_mole_residual(mclbm_nn *net, int32_t species, const float *a, const float *b, double *out);
 
 /* Advance a lattice Boltzmann context by K steps with the network (trained for
- * K steps): read the fields, predict, and if the mole residual of every tube is
- * at most resid_tol, re-initialise the populations at the local equilibrium of
- * the predicted fields (mole fractions clipped at 0 and renormalised);
- * otherwise run the K lattice steps instead
- * (*used_fallback = 1). The network's tubes must be the context's and its
- * channels M + 5 (X_1..X_M, T, u_x, u_y, u_z, p: the layout of
- * mclbm_read_fields_f32). The step count advances by K. */
+ * K steps): read the fields, predict, and form the fields to install (mole
+ * fractions clipped at 0 and renormalised). Their residual is the largest
+ * relative change, over the tubes, of a species' mass or of the total energy of
+ * the local equilibrium those fields define, against the conserved sums of the
+ * current populations: the walled or periodic lattice keeps both (Sec. 2.2
+ * item 1; the energy of eq g0momTotalEnergy), up to its rounding, and the
+ * network, which keeps the moles by construction but predicts T and u directly,
+ * does not. If the fields are a feasible state and the residual is at most
+ * resid_tol, the populations are re-initialised at the local equilibrium of
+ * those fields; otherwise the K lattice steps run instead (*used_fallback = 1).
+ * *max_residual receives the residual (HUGE_VAL for an infeasible prediction).
+ * The network's tubes must be the context's and its channels M + 5 (X_1..X_M,
+ * T, u_x, u_y, u_z, p: the layout of mclbm_read_fields_f32). The step count
+ * advances by K. MCLBM_ENAN if the current state is not finite. */
 int mclbm_nn_advance(mclbm_ctx *c, mclbm_nn *net, int32_t K, double resid_tol, int32_t *used_fallback,
                      double *max_residual);
 

@@ -9,8 +9,8 @@
  *
  * One time step, in the paper's order:
  *   1. moments of every lattice; strong coupling slaves species M to the
- *      momentum lattice (Sec. 3.6.2, eqs rhoMATCH, uMATCH); weak coupling
- *      (Sec. 3.6.1) evolves every species lattice with its own conservation law;
+ *      momentum lattice (Sec. 3.5.2, eqs rhoMATCH, uMATCH); weak coupling
+ *      (Sec. 3.5.1) evolves every species lattice with its own conservation law;
  *      temperature from the energy lattice: with constant specific heats in
  *      closed form (eq temperature2, T_0=0), with specific heats polynomial in T
  *      by Newton's method on eq temperature;

@@ -44,7 +44,7 @@ typedef struct {
                            zero-gradient outlet at x = nx - 1                          */
   int32_t keep_slaved;  /* 1: store and evolve the slaved species' lattice literally    */
   int32_t debug_flags;  /* ORACLE_DROP_* planted mistakes (tests only), else 0          */
-  int32_t weak;         /* 1: weak coupling (Sec. 3.6.1): all M species lattices evolve
+  int32_t weak;         /* 1: weak coupling (Sec. 3.5.1): all M species lattices evolve
                            with their own conservation laws (implies keep_slaved)     */
   const double *molar_mass; /* [M] molar masses m_a                                     */
   const double *cv;         /* [M] mass-based constant specific heats C_{a,v}           */

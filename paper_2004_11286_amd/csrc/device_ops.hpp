@@ -29,6 +29,20 @@ __device__ inline __bf16 cvt_sr_bf16(float x, uint32_t rnd)
   return o[0];
 }
 
+// Convert an FP64 value to FP32 with stochastic rounding: a uniform random
+// number (the upper 24 bits of rnd) is added below the 29 mantissa bits that
+// FP32 drops, and those bits are then cut: the magnitude is rounded up with
+// probability equal to the dropped fraction, so the result is unbiased (its
+// expectation is x, to 2^-24 of a unit in the last place). The conversion of
+// the cut value is exact for every x in FP32's normal range.
+__device__ inline float cvt_sr_f32(double x, uint32_t rnd)
+{
+  uint64_t b = (uint64_t)__double_as_longlong(x);
+  b += (uint64_t)(rnd >> 8) << 5;
+  b &= ~(((uint64_t)1 << 29) - 1);
+  return (float)__longlong_as_double((long long)b);
+}
+
 // Load of a value that is read once and not again soon (the populations a
 // collision consumes): a nontemporal load, which keeps the caches for the
 // neighbour stencils of the node records.

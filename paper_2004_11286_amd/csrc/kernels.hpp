@@ -129,6 +129,45 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(collide_p
   }
 }
 
+// The two-read step: the moments pass also collides and streams the species
+// lattices (k_state_species); the second pass collides and streams the momentum
+// and energy lattices (k_collide_fg). The two write disjoint lattices of dst.
+template <typename S, typename R, typename Rec, int M, int W, int V, bool WEAK>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(moment_waves<M, V>()))) void k_state_species(
+    const Params<R>* __restrict__ P, Launch Ln, const S* __restrict__ src, S* __restrict__ dst, Rec* __restrict__ rec,
+    StepNo sn)
+{
+  const Where w = locate(Ln);
+  const Params<R>& Pt = P[w.t];
+  static_assert(RecLayout<M, WEAK, false>::FIELDS >= REC2_FIELDS, "the two-read record fits the record buffer");
+  if (w.node < Pt.n) {
+    const size_t po = pop_stride<M, WEAK>() * w.base;
+    state_species_node<S, R, Rec, M, W, WEAK>(Pt, src + po, dst + po,
+                                              rec + (size_t)RecLayout<M, WEAK, false>::FIELDS * w.base, w.node,
+                                              step_of(sn));
+  }
+}
+
+// Occupancy targets of k_collide_fg: two waves per SIMD (variant 0; about 230
+// registers), or no bound on the registers (variant 1: one wave per SIMD).
+template <int V>
+constexpr int collide_fg_waves() { return V == 0 ? 2 : 1; }
+
+template <typename S, typename R, typename Rec, int M, int W, int V, bool WEAK>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(collide_fg_waves<V>()))) void k_collide_fg(
+    const Params<R>* __restrict__ P, Launch Ln, const S* __restrict__ src, S* __restrict__ dst,
+    const Rec* __restrict__ rec, const Rec* __restrict__ G, StepNo sn)
+{
+  const Where w = locate(Ln);
+  const Params<R>& Pt = P[w.t];
+  if (w.node < Pt.n) {
+    const size_t po = pop_stride<M, WEAK>() * w.base;
+    fg_collide_node<S, R, Rec, M, W, WEAK>(Pt, src + po, dst + po,
+                                           rec + (size_t)RecLayout<M, WEAK, false>::FIELDS * w.base,
+                                           G + 3 * w.base, w.node, step_of(sn));
+  }
+}
+
 // Open x ends: rewrite the populations entering the two boundary planes after
 // the collision (a launch over all nodes; only x = 0 and x = nx - 1 write).
 template <typename S, typename R, int M, bool WEAK>
@@ -272,6 +311,11 @@ struct Ops {
                      hipStream_t st);
   void (*init)(const void* Pd, const Launch& ln, const double* X, const double* p, const double* T,
                const double* u, void* pop, int* bad, unsigned grid, hipStream_t st);
+  // the two-read step (null where not compiled: temperature-dependent properties)
+  void (*state_species[NVARIANT])(const void* P, const Launch& ln, const void* src, void* dst, void* rec, StepNo sn,
+                                  unsigned grid, hipStream_t st);
+  void (*collide_fg[NVARIANT])(const void* P, const Launch& ln, const void* src, void* dst, const void* rec,
+                               const void* G, StepNo sn, unsigned grid, hipStream_t st);
   // open x ends only (else null): after each collision, on its destination buffer
   void (*open_fix)(const void* P, const Launch& ln, void* dst, StepNo sn, unsigned grid, hipStream_t st);
   void (*field_sums)(const int64_t* tube_n, const Launch& ln, const double* X, const double* p, const double* T,
@@ -293,6 +337,22 @@ void launch_collide(const void* P, const Launch& ln, const void* src, void* dst,
                      (const Params<R>*)P, ln, (const S*)src, (S*)dst, (const Rec*)rec, (const Rec*)G, sn);
 }
 
+template <typename S, typename R, typename Rec, int M, int W, int V, bool WEAK>
+void launch_state_species(const void* P, const Launch& ln, const void* src, void* dst, void* rec, StepNo sn,
+                          unsigned grid, hipStream_t st)
+{
+  hipLaunchKernelGGL((k_state_species<S, R, Rec, M, W, V, WEAK>), dim3(grid), dim3(BLOCK), 0, st,
+                     (const Params<R>*)P, ln, (const S*)src, (S*)dst, (Rec*)rec, sn);
+}
+
+template <typename S, typename R, typename Rec, int M, int W, int V, bool WEAK>
+void launch_collide_fg(const void* P, const Launch& ln, const void* src, void* dst, const void* rec, const void* G,
+                       StepNo sn, unsigned grid, hipStream_t st)
+{
+  hipLaunchKernelGGL((k_collide_fg<S, R, Rec, M, W, V, WEAK>), dim3(grid), dim3(BLOCK), 0, st,
+                     (const Params<R>*)P, ln, (const S*)src, (S*)dst, (const Rec*)rec, (const Rec*)G, sn);
+}
+
 template <typename S, typename R, typename Rec, int M, int W, bool WEAK, bool CVT>
 Ops make_ops()
 {
@@ -306,6 +366,15 @@ Ops make_ops()
   o.collide[1] = launch_collide<S, R, Rec, M, W, 1, 0, WEAK, CVT>;
   o.collide_split[0] = launch_collide<S, R, Rec, M, W, 0, 1, WEAK, CVT>;
   o.collide_split[1] = launch_collide<S, R, Rec, M, W, 0, 2, WEAK, CVT>;
+  if constexpr (!CVT) {
+    o.state_species[0] = launch_state_species<S, R, Rec, M, W, 0, WEAK>;
+    o.state_species[1] = launch_state_species<S, R, Rec, M, W, 1, WEAK>;
+    o.collide_fg[0] = launch_collide_fg<S, R, Rec, M, W, 0, WEAK>;
+    o.collide_fg[1] = launch_collide_fg<S, R, Rec, M, W, 1, WEAK>;
+  } else {
+    o.state_species[0] = o.state_species[1] = nullptr;
+    o.collide_fg[0] = o.collide_fg[1] = nullptr;
+  }
   o.gfield = [](const void* Pd, const Launch& ln, const void* rec, void* G, int rec_fields, unsigned grid,
                 hipStream_t st) {
     hipLaunchKernelGGL((k_gfield<Rec, W>), dim3(grid), dim3(BLOCK), 0, st, (const Params<double>*)Pd, ln,

@@ -15,9 +15,9 @@ constexpr int Q = 27;
 constexpr int MAXM = 8;           // species per context
 constexpr int MAXL = MAXM + 2;    // stored lattices: up to M species, momentum f, energy g
 
-// Stored lattices of an M-species context. Strong coupling (Sec. 3.6.2) stores
+// Stored lattices of an M-species context. Strong coupling (Sec. 3.5.2) stores
 // species 1..M-1 (the slaved species' populations are never read); weak
-// coupling (Sec. 3.6.1) stores all M species. Then the momentum lattice f (LF)
+// coupling (Sec. 3.5.1) stores all M species. Then the momentum lattice f (LF)
 // and the energy lattice g (LG).
 template <int M, bool WEAK>
 struct Lat {

@@ -139,6 +139,44 @@ __global__ __launch_bounds__(BLOCK) void k_pred_to_state(const Params<double>* _
   if (threadIdx.x == 0) block_bad[w.block] = bad;
 }
 
+// Conserved sums of the state mclbm_init_fields installs for FP64 fields (X, p, T,
+// u per tube, as in k_pred_to_state's output): per node rho_1 .. rho_M and rho E
+// of the local equilibrium (rho = p m / T, rho_a = rho Y_a, rho E = rho (U(T) +
+// u^2/2) with U the mixture's internal energy from T_0 = 0); block partials
+// [MAXM + 1] in the slots of kern::block_sum.
+__global__ __launch_bounds__(BLOCK) void k_field_conserved(const Params<double>* __restrict__ P, Launch ln, int M,
+                                                          const double* __restrict__ X, const double* __restrict__ p,
+                                                          const double* __restrict__ T, const double* __restrict__ u,
+                                                          double* __restrict__ partial)
+{
+  constexpr int NV = MAXM + 1;
+  double v[NV];
+  for (int k = 0; k < NV; ++k) v[k] = 0.0;
+  const kern::Where w = kern::locate(ln);
+  const Params<double>& Pt = P[w.t];
+  if (w.node < Pt.n) {
+    const int64_t n = Pt.n, b = w.base, i = w.node;
+    double mmix = 0.0, Y[MAXM];
+    for (int a = 0; a < M; ++a) mmix += X[(size_t)M * b + (size_t)a * n + i] * Pt.m[a];
+    const double Tn = T[b + i];
+    const double rho = p[b + i] * mmix / Tn;
+    double usq = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      const double uk = u[3 * b + (size_t)k * n + i];
+      usq += uk * uk;
+    }
+    double U = 0.0;                      // sum_a Y_a int_0^T C_{a,v}
+    for (int a = 0; a < M; ++a) {
+      Y[a] = X[(size_t)M * b + (size_t)a * n + i] * Pt.m[a] / mmix;
+      v[a] = rho * Y[a];
+      const double* c = Pt.cvc[a];
+      U += Y[a] * Tn * (c[0] + Tn * (c[1] * 0.5 + Tn * (c[2] * (1.0 / 3.0) + Tn * (c[3] * 0.25))));
+    }
+    v[MAXM] = rho * (U + 0.5 * usq);
+  }
+  kern::block_sum<NV>(v, partial, w.block);
+}
+
 bool pick_ops(int precision, int M, int walls, int weak, int cvt, Ops& o)
 {
   switch (precision) {
@@ -156,6 +194,7 @@ bool compute_is_fp64(int precision) { return precision == MCLBM_FP64 || precisio
 thread_local std::string g_last_error;
 
 const char* kernel_names[3] = {"k_moments", "k_gfield", "k_collide"};
+const char* kernel_names_two_read[3] = {"k_state_species", "k_gfield", "k_collide_fg"};
 
 struct TubeHost {
   int nx = 0, ny = 0, nz = 0;
@@ -561,7 +600,14 @@ int upload_params(mclbm_ctx* c, const std::vector<RefState>& rs)
       th.scale[l] = scale_for(c->precision, th.ref[l]);
       th.ref0[l] = 0.0;
       th.ref2[l] = 0.0;
+      // FP32 storage of FP64 arithmetic keeps the species populations themselves
+      // (reference zero): the stochastic rounding of a store is then relative to
+      // the population, so a nearly absent species is not buried in rounding
+      // noise of the size of the mean state's population (which would give it a
+      // diffusion velocity from noise)
+      const bool absolute = c->precision == MCLBM_FP32 && l < c->L - 2;
       for (int i = 0; i < Q; ++i) {
+        if (absolute) th.ref[l][i] = 0.0;
         th.ref[l][i] = round_to_storage(c->precision, th.ref[l][i] * th.scale[l]) / th.scale[l];
         th.ref0[l] += th.ref[l][i];
         th.ref2[l] += th.ref[l][i] * cx(i) * cx(i);
@@ -628,15 +674,38 @@ void collide(mclbm_ctx* c, const Launch& ln, int from, StepNo sn, unsigned grid,
   if (c->ops.open_fix) c->ops.open_fix(c->dPr, ln, c->pop[1 - from], sn, grid, st);
 }
 
+// Whether steps take the two-read path (compiled for constant properties).
+bool two_read(const mclbm_ctx* c) { return !c->lc.three_pass && c->ops.state_species[0] != nullptr; }
+
+// First pass of a step from buffer `from`: moments -> record (three-pass), or
+// moments -> record plus the species collisions into the other buffer (two-read).
+void first_pass(mclbm_ctx* c, const Launch& ln, int from, StepNo sn, unsigned grid, hipStream_t st)
+{
+  const int v = c->lc.variant;
+  if (two_read(c)) c->ops.state_species[v](c->dPr, ln, c->pop[from], c->pop[1 - from], c->rec, sn, grid, st);
+  else c->ops.moments[v](c->dPd, ln, c->pop[from], c->rec, grid, st);
+}
+
+// Last pass: the collision of every lattice (three-pass), or of the momentum and
+// energy lattices (two-read), then the open-end fix-up.
+void last_pass(mclbm_ctx* c, const Launch& ln, int from, StepNo sn, unsigned grid, hipStream_t st)
+{
+  if (two_read(c)) {
+    c->ops.collide_fg[c->lc.variant](c->dPr, ln, c->pop[from], c->pop[1 - from], c->rec, c->G, sn, grid, st);
+    if (c->ops.open_fix) c->ops.open_fix(c->dPr, ln, c->pop[1 - from], sn, grid, st);
+  } else {
+    collide(c, ln, from, sn, grid, st);
+  }
+}
+
 // The launches of one step from buffer `from` on stream st.
 void enqueue_step(mclbm_ctx* c, int from, StepNo sn, hipStream_t st)
 {
-  const int v = c->lc.variant;
   const int rf = c->ops.rec_fields;
   auto one = [&](const Launch& ln, unsigned grid) {
-    c->ops.moments[v](c->dPd, ln, c->pop[from], c->rec, grid, st);
+    first_pass(c, ln, from, sn, grid, st);
     c->ops.gfield(c->dPd, ln, c->rec, c->G, rf, grid, st);
-    collide(c, ln, from, sn, grid, st);
+    last_pass(c, ln, from, sn, grid, st);
   };
   if (!c->lc.sequential) {
     one(launch_all(c), (unsigned)c->nblocks);
@@ -651,16 +720,15 @@ int eager_step(mclbm_ctx* c)
   const StepNo sn{nullptr, (uint32_t)c->steps};
   int rc = 0;
   if (c->timing && !c->lc.sequential) {
-    const int v = c->lc.variant;
     const Launch ln = launch_all(c);
     const unsigned grid = (unsigned)c->nblocks;
     int e0 = 0, e1 = 0, e2 = 0, e3 = 0;
     if ((rc = record_event(c, e0))) return rc;
-    c->ops.moments[v](c->dPd, ln, c->pop[c->cur], c->rec, grid, c->stream);
+    first_pass(c, ln, c->cur, sn, grid, c->stream);
     if ((rc = record_event(c, e1))) return rc;
     c->ops.gfield(c->dPd, ln, c->rec, c->G, c->ops.rec_fields, grid, c->stream);
     if ((rc = record_event(c, e2))) return rc;
-    collide(c, ln, c->cur, sn, grid, c->stream);
+    last_pass(c, ln, c->cur, sn, grid, c->stream);
     if ((rc = record_event(c, e3))) return rc;
     c->ev_pairs[0].push_back({e0, e1});
     c->ev_pairs[1].push_back({e1, e2});
@@ -761,10 +829,11 @@ extern "C" int mclbm_batch_create(const mclbm_params* tp, int32_t ntubes, void* 
   c->cvt = tp[0].cv_coef != nullptr || tp[0].transport_exp != nullptr;
   c->wall_y = tp[0].wall_y;
   c->L = (c->weak ? c->M : c->M - 1) + 2;
-  if (c->weak) {
-    // four or more stored lattices: the split collision (two launches with fewer
-    // registers each) and the higher-occupancy moments kernel are the faster
-    // choices (binary shear layer 256^3, FP32: 5.74 -> 5.4 ms per step)
+  if (c->weak && c->cvt) {
+    // the three-pass step with four or more stored lattices: the split collision
+    // (two launches with fewer registers each) and the higher-occupancy moments
+    // kernel are the faster choices (binary shear layer 256^3, FP32: 5.74 -> 5.4 ms
+    // per step)
     c->lc.variant = 1;
     c->lc.split = 1;
   }
@@ -1191,7 +1260,7 @@ extern "C" int mclbm_kernel_stats(mclbm_ctx* c, int32_t kernel, double* total_ms
   if (rc) return rc;
   if (total_ms) *total_ms = c->acc_ms[kernel];
   if (launches) *launches = c->acc_launches[kernel];
-  if (name) *name = kernel_names[kernel];
+  if (name) *name = two_read(c) ? kernel_names_two_read[kernel] : kernel_names[kernel];
   return MCLBM_OK;
 }
 
@@ -1207,13 +1276,12 @@ extern "C" int mclbm_set_launch(mclbm_ctx* c, const mclbm_launch* in)
   if (!c) return MCLBM_EARG;
   if (!in) return fail(c, MCLBM_EARG, "launch is NULL");
   if (in->variant < 0 || in->variant >= kern::NVARIANT) return fail(c, MCLBM_EARG, "variant must be 0 or 1");
-  if ((in->swizzle | in->sequential | in->split) & ~1)
-    return fail(c, MCLBM_EARG, "swizzle, sequential and split are 0 or 1");
+  if ((in->swizzle | in->sequential | in->split | in->three_pass) & ~1)
+    return fail(c, MCLBM_EARG, "swizzle, sequential, split and three_pass are 0 or 1");
   if (in->order != 0 && in->order != 1) return fail(c, MCLBM_EARG, "order must be 0 or 1");
   if (in->graph_steps < 0 || (in->graph_steps & 1) || in->graph_steps > 100000)
     return fail(c, MCLBM_EARG, "graph_steps must be an even number in 0..100000");
-  for (int k = 0; k < 2; ++k)
-    if (in->reserved[k]) return fail(c, MCLBM_EARG, "reserved fields must be 0");
+  if (in->reserved) return fail(c, MCLBM_EARG, "the reserved field must be 0");
   const bool remap = in->order != c->lc.order;
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   drop_graph(c);
@@ -1230,23 +1298,28 @@ extern "C" int mclbm_autotune(mclbm_ctx* c, int32_t trial_steps, char* report, s
   if (c->timing) return fail(c, MCLBM_EARG, "disable timing before autotuning");
   const int G = trial_steps & ~1;
   std::vector<mclbm_launch> cands;
-  const int vs[4][2] = {{0, 0}, {1, 0}, {0, 1}, {1, 1}};   // (variant, split)
+  // (three_pass, variant, split): the two-read step where compiled, then the three-pass step
+  const int paths[6][3] = {{0, 0, 0}, {0, 1, 0}, {1, 0, 0}, {1, 1, 0}, {1, 0, 1}, {1, 1, 1}};
+  const bool has_two_read = c->ops.state_species[0] != nullptr;
   for (int order = 0; order < (c->ntubes > 1 ? 2 : 1); ++order)
-    for (const auto& vsp : vs)
+    for (const auto& pv : paths) {
+      if (!pv[0] && !has_two_read) continue;
       for (int sw = 0; sw < 2; ++sw)
         for (int g = 0; g < 2; ++g) {
           mclbm_launch l{};
-          l.variant = vsp[0];
-          l.split = vsp[1];
+          l.three_pass = pv[0];
+          l.variant = pv[1];
+          l.split = pv[2];
           l.swizzle = sw;
           l.order = order;
           l.graph_steps = g ? G : 0;
           cands.push_back(l);
         }
+    }
   hipEvent_t e0, e1;
   HIP_TRY(c, hipEventCreate(&e0));
   HIP_TRY(c, hipEventCreate(&e1));
-  std::string rep = "variant split swizzle order graph_steps ms_per_step\n";
+  std::string rep = "three_pass variant split swizzle order graph_steps ms_per_step\n";
   double best = 1e300;
   mclbm_launch best_l = c->lc;
   int rc = MCLBM_OK;
@@ -1263,8 +1336,8 @@ extern "C" int mclbm_autotune(mclbm_ctx* c, int32_t trial_steps, char* report, s
     if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = fail(c, MCLBM_EDEVICE, "hipEventElapsedTime"); break; }
     const double per = ms / G;
     char line[128];
-    std::snprintf(line, sizeof line, "%d %d %d %d %d %.6f\n", l.variant, l.split, l.swizzle, l.order, l.graph_steps,
-                  per);
+    std::snprintf(line, sizeof line, "%d %d %d %d %d %d %.6f\n", l.three_pass, l.variant, l.split, l.swizzle,
+                  l.order, l.graph_steps, per);
     rep += line;
     if (per < best) {
       best = per;
@@ -1277,8 +1350,8 @@ extern "C" int mclbm_autotune(mclbm_ctx* c, int32_t trial_steps, char* report, s
   rc = mclbm_set_launch(c, &best_l);
   if (rc) return rc;
   char line[128];
-  std::snprintf(line, sizeof line, "chosen %d %d %d %d %d %.6f\n", best_l.variant, best_l.split, best_l.swizzle,
-                best_l.order, best_l.graph_steps, best);
+  std::snprintf(line, sizeof line, "chosen %d %d %d %d %d %d %.6f\n", best_l.three_pass, best_l.variant,
+                best_l.split, best_l.swizzle, best_l.order, best_l.graph_steps, best);
   rep += line;
   if (report && report_len > 0) {
     const size_t k = std::min(report_len - 1, rep.size());
@@ -1305,33 +1378,56 @@ extern "C" int mclbm_nn_advance(mclbm_ctx* c, mclbm_nn* net, int32_t K, double r
   for (int t = 0; t < c->ntubes; ++t)
     if (dims[3 * t] != c->tubes[t].nx || dims[3 * t + 1] != c->tubes[t].ny || dims[3 * t + 2] != c->tubes[t].nz)
       return fail(c, MCLBM_EARG, "network and context have different tubes");
+  // conserved sums of the current state: masses of the species and energy per tube
+  std::vector<double> before((size_t)c->ntubes * (M + 5));
+  int rc = mclbm_conservation(c, before.data());
+  if (rc) return rc;
   float *fin = nullptr, *fout = nullptr;
   mclbm_nn_io(net, &fin, &fout);
-  int rc = mclbm_read_fields_f32(c, fin, 1);
+  rc = mclbm_read_fields_f32(c, fin, 1);
   if (rc) return rc;
   rc = mclbm_nn_forward(net);
   if (rc) return fail(c, rc, std::string("surrogate: ") + mclbm_nn_last_error(net));
-  std::vector<double> res(c->ntubes);
-  rc = mclbm_nn_mole_residual(net, M, fin, fout, res.data());
-  if (rc) return fail(c, rc, std::string("surrogate: ") + mclbm_nn_last_error(net));
-  double mx = 0.0;
-  for (double r : res) mx = std::isfinite(r) ? std::max(mx, r) : HUGE_VAL;
-  if (max_residual) *max_residual = mx;
-  bool ok = mx <= resid_tol;
+  // the fields to install: mole fractions clipped at zero and renormalised
   const int64_t N = c->n;
   double* st = c->staging;
   double *X = st, *p = st + (size_t)M * N, *T = st + (size_t)(M + 1) * N, *u = st + (size_t)(M + 2) * N;
+  const unsigned grid = (unsigned)c->nblocks;
+  hipLaunchKernelGGL(k_pred_to_state, dim3(grid), dim3(BLOCK), 0, c->stream, (const Params<double>*)c->dPd,
+                     launch_all(c), M, fout, X, p, T, u, c->bad);
+  rc = check_launch(c, "k_pred_to_state");
+  if (rc) return rc;
+  std::vector<int> bad(c->nblocks);
+  HIP_TRY(c, hipMemcpyAsync(bad.data(), c->bad, sizeof(int) * c->nblocks, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  bool ok = true;
+  for (int64_t b = 0; b < c->nblocks && ok; ++b) ok = bad[b] == 0;
+  // residual of the installed state: the largest relative change of a species'
+  // mass or of the energy over any tube, which the walled or periodic lattice
+  // keeps (to its rounding) and the network, predicting T and u directly, does not
+  double mx = HUGE_VAL;
   if (ok) {
-    const unsigned grid = (unsigned)c->nblocks;
-    hipLaunchKernelGGL(k_pred_to_state, dim3(grid), dim3(BLOCK), 0, c->stream, (const Params<double>*)c->dPd,
-                       launch_all(c), M, fout, X, p, T, u, c->bad);
-    rc = check_launch(c, "k_pred_to_state");
+    hipLaunchKernelGGL(k_field_conserved, dim3(grid), dim3(BLOCK), 0, c->stream, (const Params<double>*)c->dPd,
+                       launch_all(c), M, X, p, T, u, c->partial);
+    rc = check_launch(c, "k_field_conserved");
     if (rc) return rc;
-    std::vector<int> bad(c->nblocks);
-    HIP_TRY(c, hipMemcpyAsync(bad.data(), c->bad, sizeof(int) * c->nblocks, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    for (int64_t b = 0; b < c->nblocks && ok; ++b) ok = bad[b] == 0;
+    std::vector<double> after((size_t)c->ntubes * (MAXM + 1));
+    rc = reduce_to_host(c, MAXM + 1, after.data());
+    if (rc) return rc;
+    mx = 0.0;
+    for (int t = 0; t < c->ntubes; ++t) {
+      const double* b0 = &before[(size_t)t * (M + 5)];
+      const double* a1 = &after[(size_t)t * (MAXM + 1)];
+      double mass = 0.0;
+      for (int a = 0; a < M; ++a) mass += b0[a];
+      for (int a = 0; a < M; ++a)
+        if (b0[a] > 1e-12 * mass) mx = std::max(mx, std::fabs(a1[a] - b0[a]) / b0[a]);
+      mx = std::max(mx, std::fabs(a1[MAXM] - b0[M + 4]) / std::fabs(b0[M + 4]));
+    }
+    if (!std::isfinite(mx)) mx = HUGE_VAL;
+    ok = mx <= resid_tol;
   }
+  if (max_residual) *max_residual = mx;
   if (ok) {
     const int64_t steps = c->steps;
     rc = mclbm_init_fields(c, X, p, T, u, 1);

@@ -4,9 +4,9 @@
 //
 // Storage: pop[l][i][n] with l = 0..NS-1 the stored species, l = NS the
 // momentum lattice f, l = NS+1 the energy lattice g; n = x + nx (y + ny z).
-// Under strong coupling (Sec. 3.6.2) NS = M-1: species M is slaved to the
+// Under strong coupling (Sec. 3.5.2) NS = M-1: species M is slaved to the
 // momentum lattice and no quantity ever reads its populations. Under weak
-// coupling (Sec. 3.6.1) NS = M: the species subsystem of Sec. 2 keeps its own
+// coupling (Sec. 3.5.1) NS = M: the species subsystem of Sec. 2 keeps its own
 // density and velocity (eqs rhoSPEC, uSPEC) and takes T from the energy lattice.
 // Stored values are d = s_l (f - f_ref,l,i).
 //
@@ -23,6 +23,7 @@
 #pragma once
 
 #include <type_traits>
+
 
 #include <device_ops.hpp>   // device primitives (include path: csrc/)
 
@@ -88,7 +89,7 @@ __host__ __device__ __forceinline__ R solve_temperature(const R c[4], R e)
   return T;
 }
 
-// Macroscopic state of a node (Secs. 2.1, 3.1, 3.2; strong coupling Sec. 3.6.2).
+// Macroscopic state of a node (Secs. 2.1, 3.1, 3.2; strong coupling Sec. 3.5.2).
 template <typename R, int M>
 struct Mix {
   R rho, inv_rho, u[3], usq, rhoE;
@@ -156,7 +157,7 @@ __host__ __device__ __forceinline__ void mixture_state(const Params<R>& P, R rho
   s.P = rho * s.Rg * s.T;
 }
 
-// Wilke's mixture viscosity and Mathur's mixture conductivity (Sec. 3.4).
+// Wilke's mixture viscosity and Mathur's mixture conductivity (Sec. 3.3).
 template <typename R, int M>
 __host__ __device__ __forceinline__ R mixture_viscosity(const Params<R>& P, const R X[M])
 {
@@ -585,12 +586,21 @@ __host__ __device__ __forceinline__ uint32_t mix32(uint32_t x)
   return x;
 }
 
-// Conversion of a scaled deviation to the storage type. 32- and 64-bit storage
-// round to nearest; 16-bit storage rounds stochastically, which removes the bias
-// that round-to-nearest accumulates in slowly varying regions.
+// Conversion of a scaled deviation to the storage type. FP64 storage is exact and
+// FP32 arithmetic with FP32 storage rounds to nearest; FP32 storage of FP64
+// arithmetic and 16-bit storage round stochastically, which removes the bias
+// that round-to-nearest accumulates where a value changes by less than its
+// last place per step (the change is quantised to whole units of the last
+// place; in the 20000-step ternary tube, round to nearest leaves the mole
+// fractions 3.5e-5 off).
 template <typename S, typename R>
 struct Store {
   __host__ __device__ static S cvt(R v, uint32_t) { return S(v); }
+};
+
+template <>
+struct Store<float, double> {
+  __host__ __device__ static float cvt(double x, uint32_t rnd) { return cvt_sr_f32(x, rnd); }
 };
 
 template <>
@@ -665,8 +675,6 @@ __host__ __device__ __forceinline__ void load_lattice(const S* __restrict__ lat,
   lattice_barrier();
 }
 
-// PART selects the lattices: 0 all, 1 the stored species lattices, 2 the momentum
-// and energy lattices (a split collision in two launches computes the same step).
 // Open x ends, after the collision has streamed periodically into dst: what
 // enters node x = 0 (c_x > 0) is the stored inlet equilibrium; what enters node
 // x = nx - 1 (c_x < 0) comes from a ghost beyond it holding the boundary node's
@@ -697,6 +705,210 @@ __host__ __device__ __forceinline__ void open_fix_node(const Params<R>& P, S* __
   }
 }
 
+// --------------------------------------------------------------------------
+// Collision of one lattice from its stored values v (already loaded), with the
+// exact restoration of the lattice's conserved moments, then streaming. Shared
+// by the three-pass step (collide_node) and the two-read step
+// (state_species_node, fg_collide_node).
+// --------------------------------------------------------------------------
+// Precision of the small Stefan--Maxwell source F: FP64 with FP64 storage, else FP32.
+template <typename S>
+using SrcF = typename std::conditional<sizeof(S) == 8, double, float>::type;
+
+// Face pairs (c = +e_k, -e_k) of the velocity set, k = x, y, z.
+constexpr int face_plus(int k) { return k == 0 ? 22 : (k == 1 ? 16 : 14); }
+
+// Store the six face populations of lattice l so that the stored first moment
+// equals t1 (the momentum lattice: rho u + X): face holds their unrounded
+// post-collision values (indexed by direction), s1 the first moment of the other
+// stored values, s0 their sum (the faces' stored values are added to it). Each
+// pair keeps its unrounded sum; the difference of the pair is what restores t1.
+template <typename S, typename R>
+__host__ __device__ __forceinline__ void restore_faces(const Params<R>& P, int l, const R (&face)[Q], const R (&t1)[3],
+                                                       const R (&s1)[3], R& s0, S (&v)[Q], Rng& rng)
+{
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int ip = face_plus(k), im = 26 - ip;
+    const R sum = face[ip] + face[im];
+    const R diff = t1[k] - s1[k];        // required stored value of ip minus that of im
+    v[ip] = to_store<S, R>(P, l, R(0.5) * (sum + diff), rng);
+    v[im] = to_store<S, R>(P, l, R(0.5) * (sum - diff), rng);
+    s0 += from_store<S, R>(P, l, v[ip]) + from_store<S, R>(P, l, v[im]);
+  }
+}
+
+// Species lattice a: f' = f + 2 beta (f^eq - f) + (beta - 1) F (eq SMlbm),
+// F_ai = sum_b K_ab [Psi_i(u, R_b T) - Psi_i(u + V_b, R_b T)] (eq fstar1), with
+// K_ab = P X_a X_b / D_ab, 1/tau_a = sum_b Y_b / tau_ab (eqs tauab, tau). us is
+// the velocity the species see, pe the triplets of Psi(us, R_c T) and pd those
+// of Psi(us) - Psi(us + V_c) (FP32 unless the storage is FP64: F is a small
+// correction); gD the factor (T_ref / T)^s_D of temperature-dependent transport
+// (1 otherwise).
+template <typename S, typename R, int M, int BC, bool CVT>
+__host__ __device__ __forceinline__ void species_relax(const Params<R>& P, const Mix<R, M>& s, const R (&K)[M][M],
+                                                       const Trip<SrcF<S>> (&pe)[M][3],
+                                                       const Trip<SrcF<S>> (&pd)[M][3], const R (&us)[3], R gD,
+                                                       int a, S (&v)[Q], S* __restrict__ dst, const Nbr& b,
+                                                       int64_t node, uint32_t step)
+{
+  using F32 = SrcF<S>;
+  R acc = R(0);
+#pragma unroll
+  for (int c = 0; c < M; ++c) acc += s.Y[c] * P.invD[a][c] * P.inv_m[c];
+  R inv_tau = s.T * s.mmix * P.inv_m[a] * acc;
+  if constexpr (CVT) inv_tau *= gD;
+  const R beta = inv_tau / (R(2) + inv_tau);            // dt / (2 tau_a + dt)
+  Trip<R> pa[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) pa[k] = psi_trip<R>(us[k], s.T * P.inv_m[a]);
+  R t0 = R(0), s0 = R(0);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) t0 += from_store<S, R>(P, a, v[i]);
+  Rng rng(node, a, step);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    if (i == 13) continue;
+    F32 F = F32(0);
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+      const F32 ex = pe[c][0](cx(i)), ey = pe[c][1](cy(i)), ez = pe[c][2](cz(i));
+      const F32 dx = pd[c][0](cx(i)), dy = pd[c][1](cy(i)), dz = pd[c][2](cz(i));
+      F += F32(K[a][c]) * (dx * ey * ez + (ex - dx) * dy * ez + (ex - dx) * (ey - dy) * dz);
+    }
+    const R fe = s.rho_a[a] * (pa[0](cx(i)) * pa[1](cy(i)) * pa[2](cz(i))) - P.ref[a][i];
+    // f' - f_ref = (f^eq - f_ref) + (1 - 2 beta)(f - f^eq) + (beta - 1) F
+    const R dn = fe + (R(1) - R(2) * beta) * (from_store<S, R>(P, a, v[i]) - fe) + (beta - R(1)) * R(F);
+    v[i] = to_store<S, R>(P, a, dn, rng);
+    s0 += from_store<S, R>(P, a, v[i]);
+  }
+  // the collision conserves rho_a: the rest population takes the defect of
+  // the arithmetic and of the other 26 values' rounding to storage
+  v[13] = to_store<S, R>(P, a, t0 - s0, rng);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) push<S, R, BC>(P, dst, b, a, i, node, v[i]);
+}
+
+// Momentum lattice (stored lattice LF): f' = f + omega (f^eq - f) + A_i . X
+// (eqs feq, fwithcorrection, Ai) at the node's rho, u and theta = R T; Xc is the
+// isotropy correction X_a = -d_a G_a (eq Xalpha). The rounding defect of mass and
+// momentum goes to the rest and face populations, which carry no other moment up
+// to second order.
+template <typename S, typename R, int BC>
+__host__ __device__ __forceinline__ void momentum_relax(const Params<R>& P, int LF, R rho, const R (&u)[3], R theta,
+                                                        R omega, const R (&Xc)[3], S (&v)[Q], S* __restrict__ dst,
+                                                        const Nbr& b, int64_t node, uint32_t step)
+{
+  Trip<R> pf[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) pf[k] = psi_trip<R>(u[k], theta);
+  R t0 = R(0), t1[3] = {R(0), R(0), R(0)}, s0 = R(0), s1[3] = {R(0), R(0), R(0)};
+  Rng rng(node, LF, step);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const R d = from_store<S, R>(P, LF, v[i]);
+    t0 += d;
+    acc_c(t1[0], cx(i), d);
+    acc_c(t1[1], cy(i), d);
+    acc_c(t1[2], cz(i), d);
+  }
+  // the source A_i . X adds X to the momentum (A_i = c_i / 2 on the six faces)
+#pragma unroll
+  for (int k = 0; k < 3; ++k) t1[k] += Xc[k];
+  // all but the rest and face populations: collide and round to storage
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    if (csq(i) <= 1) continue;
+    const R fe = rho * (pf[0](cx(i)) * pf[1](cy(i)) * pf[2](cz(i))) - P.ref[LF][i];
+    const R dn = fe + (R(1) - omega) * (from_store<S, R>(P, LF, v[i]) - fe);
+    v[i] = to_store<S, R>(P, LF, dn, rng);
+    const R d = from_store<S, R>(P, LF, v[i]);
+    s0 += d;
+    acc_c(s1[0], cx(i), d);
+    acc_c(s1[1], cy(i), d);
+    acc_c(s1[2], cz(i), d);
+  }
+  // the face pairs carry the momentum defect, the rest population the mass
+  // defect: each face pair keeps its equilibrium-relaxed sum and takes the
+  // difference that restores rho u + X exactly
+  R face[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    if (csq(i) != 1) continue;
+    const R fe = rho * (pf[0](cx(i)) * pf[1](cy(i)) * pf[2](cz(i))) - P.ref[LF][i];
+    face[i] = fe + (R(1) - omega) * (from_store<S, R>(P, LF, v[i]) - fe);
+  }
+  restore_faces<S, R>(P, LF, face, t1, s1, s0, v, rng);
+  v[13] = to_store<S, R>(P, LF, t0 - s0, rng);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) push<S, R, BC>(P, dst, b, LF, i, node, v[i]);
+}
+
+// Energy lattice (stored lattice LG), eq g in the form
+// g' = g + omega (g^eq - g) + w_i c_i . dq / theta (eqs gieq, gistar), the exact
+// rewrite of eqs g, gistar, gstareq1mom, interdiffusion and corrFourier that has
+// no pole at omega = omega_1; dq = (omega - omega_1)(q - q^eq - u.(P - P^eq))
+// + omega_1 rho sum_a H_a Y_a V_a + (2 - omega_1)/2 P sum_a H_a d Y_a is formed
+// by the caller. H is the mixture enthalpy, theta = R T.
+template <typename S, typename R, int BC>
+__host__ __device__ __forceinline__ void energy_relax(const Params<R>& P, int LG, R rho, const R (&u)[3], R usq,
+                                                      R theta, R H, R omega, const R (&dq)[3], S (&v)[Q],
+                                                      S* __restrict__ dst, const Nbr& b, int64_t node, uint32_t step)
+{
+  const R hyd = H + R(0.5) * usq;
+  const R inv_theta = R(1) / theta;
+  const R rhoE = rho * (H - theta + R(0.5) * usq);   // rho (U + u^2/2), U = H - R T
+  R qeq[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) qeq[k] = hyd * rho * u[k];
+  // closed form of R^eq - rho E theta I for T_0 = 0: rho theta^2 I + kappa u u
+  const R kappa = rho * (hyd + theta);
+  const R rt2 = rho * theta * theta;
+  const R zf = (R(1) - R(3) * theta) * R(0.5) * inv_theta;
+  const R Z[3] = {zf * (rt2 + kappa * u[0] * u[0]), zf * (rt2 + kappa * u[1] * u[1]), zf * (rt2 + kappa * u[2] * u[2])};
+  const Trip<R> wt = w_trip<R>(theta);
+  const R h2 = R(0.5) * inv_theta * inv_theta;
+  R t0 = R(0), s0 = R(0);
+  Rng rng(node, LG, step);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) t0 += from_store<S, R>(P, LG, v[i]);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    if (i == 13) continue;
+    const R w = wt(cx(i)) * wt(cy(i)) * wt(cz(i));
+    const R cu = R(cx(i)) * u[0] + R(cy(i)) * u[1] + R(cz(i)) * u[2];
+    const R cqe = R(cx(i)) * qeq[0] + R(cy(i)) * qeq[1] + R(cz(i)) * qeq[2];
+    const R cdq = R(cx(i)) * dq[0] + R(cy(i)) * dq[1] + R(cz(i)) * dq[2];
+    R bz = R(0);
+    if (csq(i) == 1) bz = -R(0.5) * (cx(i) ? Z[0] : (cy(i) ? Z[1] : Z[2]));
+    const R ge = w * (rhoE + cqe * inv_theta +
+                      (rt2 * (R(csq(i)) - R(3) * theta) + kappa * (cu * cu - theta * usq)) * h2) + bz -
+                 P.ref[LG][i];
+    const R dn = ge + (R(1) - omega) * (from_store<S, R>(P, LG, v[i]) - ge) + w * cdq * inv_theta;
+    v[i] = to_store<S, R>(P, LG, dn, rng);
+    s0 += from_store<S, R>(P, LG, v[i]);
+  }
+  // the collision conserves rho E: the rest population takes the defect
+  v[13] = to_store<S, R>(P, LG, t0 - s0, rng);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) push<S, R, BC>(P, dst, b, LG, i, node, v[i]);
+}
+
+// Load the Q stored values of lattice l of a node (one at a time: each load is
+// followed by its use).
+template <typename S>
+__host__ __device__ __forceinline__ void load_lattice_seq(const S* __restrict__ lat, size_t n, uint32_t node, S (&v)[Q])
+{
+#pragma unroll
+  for (int i = 0; i < Q; ++i) v[i] = stream_load(at32(lat + (size_t)i * n, node));
+}
+
+// --------------------------------------------------------------------------
+// Pass 3 of the three-pass step: collide every lattice from the node record and
+// push (stream) to the other buffer. PART selects the lattices: 0 all, 1 the
+// stored species lattices, 2 the momentum and energy lattices (a split collision
+// in two launches computes the same step).
+// --------------------------------------------------------------------------
 template <typename S, typename R, typename Rec, int M, int BC, int PART = 0, bool WEAK = false, bool CVT = false>
 __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const S* __restrict__ src,
                                              S* __restrict__ dst, const Rec* __restrict__ rec,
@@ -712,6 +924,10 @@ __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const 
   constexpr bool GROUP_LOADS = sizeof(S) == 2 || (PART == 0 && M >= 3);
   const Nbr b = neighbours(P, node);
   auto get = [&](int f) -> R { return R(*at32(rec + (size_t)f * n, (uint32_t)node)); };
+  auto load = [&](int l, S (&v)[Q]) {
+    if constexpr (GROUP_LOADS) load_lattice(src + (size_t)l * Q * n, n, (uint32_t)node, v);
+    else load_lattice_seq(src + (size_t)l * Q * n, n, (uint32_t)node, v);
+  };
 
   // ---- node state from the record
   const R rho = get(REC_RHO);
@@ -798,9 +1014,7 @@ __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const 
   }
   const R Xc[3] = {-dG[0], -dG[1], -dG[2]};
 
-  // ---- species collision: f' = f + 2 beta (f^eq - f) + (beta - 1) F (eq SMlbm),
-  // F_ai = sum_b K_ab [Psi_i(u, R_b T) - Psi_i(u + V_b, R_b T)] (eq fstar1), with
-  // K_ab = P X_a X_b / D_ab, 1/tau_a = sum_b Y_b / tau_ab (eqs tauab, tau).
+  // ---- species lattices (eqs SMlbm, fstar1)
   if constexpr (PART != 2) {
     // velocity and pressure of the species subsystem: the mixture's under strong
     // coupling; u_s (eq uSPEC) and the Dalton pressure under weak coupling
@@ -820,131 +1034,35 @@ __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const 
       Pk *= gD;
     }
     friction_matrix<R, M>(P, s, Pk, present, K);
-    // F_ai is a small correction: with 32- or 16-bit storage its triplets are kept
-    // in FP32 (pe32: Psi(u), pd32: Psi(u) - Psi(u + V)); with FP64 storage in FP64.
-    using F32 = typename std::conditional<sizeof(S) == 8, double, float>::type;
-    Trip<F32> pe32[M][3], pd32[M][3];
+      Trip<SrcF<S>> pe[M][3], pd[M][3];
 #pragma unroll
     for (int c = 0; c < M; ++c) {
-      const F32 zeta = F32(s.T * P.inv_m[c]);
+      const SrcF<S> zeta = SrcF<S>(s.T * P.inv_m[c]);
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        pe32[c][k] = psi_trip<F32>(F32(us[k]), zeta);
-        pd32[c][k] = psi_diff_trip<F32>(F32(us[k]), F32(get(RL::V + 3 * c + k)));
+        pe[c][k] = psi_trip<SrcF<S>>(SrcF<S>(us[k]), zeta);
+        pd[c][k] = psi_diff_trip<SrcF<S>>(SrcF<S>(us[k]), SrcF<S>(get(RL::V + 3 * c + k)));
       }
     }
 #pragma unroll
     for (int a = 0; a < NS; ++a) {
-      R acc = R(0);
-#pragma unroll
-      for (int c = 0; c < M; ++c) acc += s.Y[c] * P.invD[a][c] * P.inv_m[c];
-      R inv_tau = s.T * s.mmix * P.inv_m[a] * acc;
-      if constexpr (CVT) inv_tau *= gD;
-      const R beta = inv_tau / (R(2) + inv_tau);            // dt / (2 tau_a + dt)
-      Trip<R> pa[3];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) pa[k] = psi_trip<R>(us[k], s.T * P.inv_m[a]);
       S v[Q];
-      R t0 = R(0), s0 = R(0);
-      Rng rng(node, a, step);
-      if constexpr (GROUP_LOADS) {
-        load_lattice(src + (size_t)a * Q * n, n, (uint32_t)node, v);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) t0 += from_store<S, R>(P, a, v[i]);
-      } else {
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-          v[i] = stream_load(at32(src + (size_t)(a * Q + i) * n, (uint32_t)node));
-          t0 += from_store<S, R>(P, a, v[i]);
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        if (i == 13) continue;
-        F32 F = F32(0);
-#pragma unroll
-        for (int c = 0; c < M; ++c) {
-          const F32 ex = pe32[c][0](cx(i)), ey = pe32[c][1](cy(i)), ez = pe32[c][2](cz(i));
-          const F32 dx = pd32[c][0](cx(i)), dy = pd32[c][1](cy(i)), dz = pd32[c][2](cz(i));
-          F += F32(K[a][c]) * (dx * ey * ez + (ex - dx) * dy * ez + (ex - dx) * (ey - dy) * dz);
-        }
-        const R fe = s.rho_a[a] * (pa[0](cx(i)) * pa[1](cy(i)) * pa[2](cz(i))) - P.ref[a][i];
-        // f' - f_ref = (f^eq - f_ref) + (1 - 2 beta)(f - f^eq) + (beta - 1) F
-        const R dn = fe + (R(1) - R(2) * beta) * (from_store<S, R>(P, a, v[i]) - fe) + (beta - R(1)) * R(F);
-        v[i] = to_store<S, R>(P, a, dn, rng);
-        s0 += from_store<S, R>(P, a, v[i]);
-      }
-      // the collision conserves rho_a: the rest population takes the defect of
-      // the arithmetic and of the other 26 values' rounding to storage
-      v[13] = to_store<S, R>(P, a, t0 - s0, rng);
-#pragma unroll
-      for (int i = 0; i < Q; ++i) push<S, R, BC>(P, dst, b, a, i, node, v[i]);
+      load(a, v);
+      species_relax<S, R, M, BC, CVT>(P, s, K, pe, pd, us, gD, a, v, dst, b, node, step);
       lattice_barrier();
     }
   }
 
-  // ---- momentum lattice: f' = f + omega (f^eq - f) + A_i . X (eqs fwithcorrection, Ai);
-  // the rounding defect of mass and momentum goes to the rest and face populations,
-  // which carry no other moment up to second order.
+  // ---- momentum lattice
   if constexpr (PART != 1) {
-    Trip<R> pf[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) pf[k] = psi_trip<R>(s.u[k], theta);
     S v[Q];
-    R t0 = R(0), t1[3] = {R(0), R(0), R(0)}, s0 = R(0), s1[3] = {R(0), R(0), R(0)};
-    Rng rng(node, LF, step);
-    if constexpr (GROUP_LOADS) load_lattice(src + (size_t)LF * Q * n, n, (uint32_t)node, v);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      if constexpr (!GROUP_LOADS) v[i] = stream_load(at32(src + (size_t)(LF * Q + i) * n, (uint32_t)node));
-      const R d = from_store<S, R>(P, LF, v[i]);
-      t0 += d;
-      acc_c(t1[0], cx(i), d);
-      acc_c(t1[1], cy(i), d);
-      acc_c(t1[2], cz(i), d);
-    }
-    // the source A_i . X adds X to the momentum (A_i = c_i / 2 on the six faces)
-#pragma unroll
-    for (int k = 0; k < 3; ++k) t1[k] += Xc[k];
-    // all but the rest and face populations: collide and round to storage
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      if (csq(i) <= 1) continue;
-      const R fe = rho * (pf[0](cx(i)) * pf[1](cy(i)) * pf[2](cz(i))) - P.ref[LF][i];
-      const R dn = fe + (R(1) - omega) * (from_store<S, R>(P, LF, v[i]) - fe);
-      v[i] = to_store<S, R>(P, LF, dn, rng);
-      const R d = from_store<S, R>(P, LF, v[i]);
-      s0 += d;
-      acc_c(s1[0], cx(i), d);
-      acc_c(s1[1], cy(i), d);
-      acc_c(s1[2], cz(i), d);
-    }
-    // the face pairs carry the momentum defect, the rest population the mass
-    // defect: each face pair keeps its equilibrium-relaxed sum and takes the
-    // difference that restores rho u + X exactly
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const int ip = k == 0 ? 22 : (k == 1 ? 16 : 14), im = 26 - ip;
-      const R fep = rho * (pf[0](cx(ip)) * pf[1](cy(ip)) * pf[2](cz(ip))) - P.ref[LF][ip];
-      const R fem = rho * (pf[0](cx(im)) * pf[1](cy(im)) * pf[2](cz(im))) - P.ref[LF][im];
-      const R dp = fep + (R(1) - omega) * (from_store<S, R>(P, LF, v[ip]) - fep);
-      const R dm = fem + (R(1) - omega) * (from_store<S, R>(P, LF, v[im]) - fem);
-      const R sum = dp + dm;
-      const R diff = t1[k] - s1[k];        // required dp - dm
-      v[ip] = to_store<S, R>(P, LF, R(0.5) * (sum + diff), rng);
-      v[im] = to_store<S, R>(P, LF, R(0.5) * (sum - diff), rng);
-      s0 += from_store<S, R>(P, LF, v[ip]) + from_store<S, R>(P, LF, v[im]);
-    }
-    v[13] = to_store<S, R>(P, LF, t0 - s0, rng);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) push<S, R, BC>(P, dst, b, LF, i, node, v[i]);
+    load(LF, v);
+    momentum_relax<S, R, BC>(P, LF, rho, s.u, theta, omega, Xc, v, dst, b, node, step);
     lattice_barrier();
   }
 
-  // ---- energy lattice (eq g), in the form g' = g + omega (g^eq - g) + w_i c_i . dq / theta,
-  // dq = (omega - omega_1)(q - q^eq - u.(P - P^eq)) + omega_1 rho sum_a H_a Y_a V_a
-  //      + (2 - omega_1)/2 P sum_a H_a d Y_a     (the exact rewrite of eqs g, gistar,
-  // gstareq1mom, interdiffusion and corrFourier that has no pole at omega = omega_1)
+  // ---- energy lattice: dq from the record's non-equilibrium flux, the diffusion
+  // velocities and the enthalpy-weighted composition gradients
   if constexpr (PART != 1) {
     R H = s.Cp * s.T;
     R ha[CVT ? M : 1];                 // with C_v(T): H_a(T) = U_a(T) + R_a T (eq specHa)
@@ -956,10 +1074,7 @@ __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const 
         H += s.Y[a] * ha[a];
       }
     }
-    const R hyd = H + R(0.5) * s.usq;
-    const R inv_theta = R(1) / theta;
-    const R rhoE = rho * (H - s.Rg * s.T + R(0.5) * s.usq);   // rho (U + u^2/2), U = H - R T
-    R qeq[3], dq[3];
+    R dq[3];
     R hyv[3] = {R(0), R(0), R(0)};
 #pragma unroll
     for (int a = 0; a < M; ++a) {
@@ -971,7 +1086,6 @@ __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const 
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      qeq[k] = hyd * rho * s.u[k];
       if constexpr (CVT) {
         // sum_a H_a d Y_a = sum_{a < M-1} (H_a - H_M) d Y_a
         R hgy = R(0);
@@ -984,44 +1098,233 @@ __host__ __device__ __forceinline__ void collide_node(const Params<R>& P, const 
                 R(0.5) * (R(2) - omega1) * s.P * s.T * gcp[k];
       }
     }
-    // closed form of R^eq - rho E theta I for T_0 = 0: rho theta^2 I + kappa u u
-    const R kappa = rho * (hyd + theta);
-    const R rt2 = rho * theta * theta;
-    const R zf = (R(1) - R(3) * theta) * R(0.5) * inv_theta;
-    const R Z[3] = {zf * (rt2 + kappa * s.u[0] * s.u[0]), zf * (rt2 + kappa * s.u[1] * s.u[1]),
-                    zf * (rt2 + kappa * s.u[2] * s.u[2])};
-    const Trip<R> wt = w_trip<R>(theta);
-    const R h2 = R(0.5) * inv_theta * inv_theta;
     S v[Q];
-    R t0 = R(0), s0 = R(0);
-    Rng rng(node, LG, step);
-    if constexpr (GROUP_LOADS) load_lattice(src + (size_t)LG * Q * n, n, (uint32_t)node, v);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      if constexpr (!GROUP_LOADS) v[i] = stream_load(at32(src + (size_t)(LG * Q + i) * n, (uint32_t)node));
-      t0 += from_store<S, R>(P, LG, v[i]);
-    }
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      if (i == 13) continue;
-      const R w = wt(cx(i)) * wt(cy(i)) * wt(cz(i));
-      const R cu = R(cx(i)) * s.u[0] + R(cy(i)) * s.u[1] + R(cz(i)) * s.u[2];
-      const R cqe = R(cx(i)) * qeq[0] + R(cy(i)) * qeq[1] + R(cz(i)) * qeq[2];
-      const R cdq = R(cx(i)) * dq[0] + R(cy(i)) * dq[1] + R(cz(i)) * dq[2];
-      R bz = R(0);
-      if (csq(i) == 1) bz = -R(0.5) * (cx(i) ? Z[0] : (cy(i) ? Z[1] : Z[2]));
-      const R ge = w * (rhoE + cqe * inv_theta +
-                        (rt2 * (R(csq(i)) - R(3) * theta) + kappa * (cu * cu - theta * s.usq)) * h2) + bz -
-                   P.ref[LG][i];
-      const R dn = ge + (R(1) - omega) * (from_store<S, R>(P, LG, v[i]) - ge) + w * cdq * inv_theta;
-      v[i] = to_store<S, R>(P, LG, dn, rng);
-      s0 += from_store<S, R>(P, LG, v[i]);
-    }
-    // the collision conserves rho E: the rest population takes the defect
-    v[13] = to_store<S, R>(P, LG, t0 - s0, rng);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) push<S, R, BC>(P, dst, b, LG, i, node, v[i]);
+    load(LG, v);
+    energy_relax<S, R, BC>(P, LG, rho, s.u, s.usq, theta, H, omega, dq, v, dst, b, node, step);
   }
+}
+
+// --------------------------------------------------------------------------
+// The two-read step. The species collisions are local: they use only the node's
+// own moments (eqs SMlbm, fstar1, transform12). So the moments pass collides and
+// streams the species lattices from the values it has just read, and only the
+// momentum and energy lattices, whose collisions need the neighbours' moments
+// of the same time level (eqs Xalpha, corrFourier), are read a second time:
+//   state_species_node  every lattice's moments -> node record (Phi, omega, C_p
+//                       for the stencils; omega_1, R, sum_a C_{a,p} Y_a V_a for
+//                       the second pass); species collisions and streaming
+//   gfield_node         G_a = (1/omega - 1/2) d_a Phi_a (unchanged)
+//   fg_collide_node     re-reads f and g, forms rho, u, T, P and q from them,
+//                       collides and streams both lattices
+// Constant specific heats only (the temperature needs C_v = C_p - R).
+// --------------------------------------------------------------------------
+enum {
+  REC2_OMEGA1 = 5, REC2_RG = 6,   // omega_1 (eq omega1), mixture gas constant R
+  REC2_HYV = 7,                   // sum_a C_{a,p} Y_a V_a (3): the interdiffusion flux of eq interdiffusion over T
+  REC2_FIELDS = 10
+};
+
+template <typename S, typename R, typename Rec, int M, int BC, bool WEAK = false>
+__host__ __device__ __forceinline__ void state_species_node(const Params<R>& P, const S* __restrict__ src,
+                                                            S* __restrict__ dst, Rec* __restrict__ rec,
+                                                            int64_t node, uint32_t step)
+{
+  const size_t n = (size_t)P.n;
+  const uint32_t nd = (uint32_t)node;
+  constexpr int NS = Lat<M, WEAK>::NS, LF = Lat<M, WEAK>::LF, LG = Lat<M, WEAK>::LG;
+  // species lattices: kept in registers for their collision below when there is
+  // one (binary, strong coupling); with more, the state's registers are needed
+  // for the larger Stefan--Maxwell system, and the values are read again for the
+  // collision (the first read is a cached load, so the second mostly hits L2)
+  constexpr bool HOLD = NS == 1;
+  S vs[HOLD ? NS : 1][Q];
+  R rho_s[M], js[M][3];
+#pragma unroll
+  for (int a = 0; a < NS; ++a) {
+    S (&va)[Q] = vs[HOLD ? a : 0];
+    if constexpr (HOLD) load_lattice(src + (size_t)a * Q * n, n, nd, va);
+    else
+#pragma unroll
+      for (int i = 0; i < Q; ++i) va[i] = *at32(src + (size_t)(a * Q + i) * n, nd);
+    R r = R(0), ja[3] = {R(0), R(0), R(0)};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const R d = from_store<S, R>(P, a, va[i]);
+      r += d;
+      acc_c(ja[0], cx(i), d);
+      acc_c(ja[1], cy(i), d);
+      acc_c(ja[2], cz(i), d);
+    }
+    rho_s[a] = P.ref0[a] + r;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) js[a][k] = ja[k];
+  }
+  if constexpr (!WEAK) rho_s[M - 1] = R(0);
+  // mixture moments: rho, rho u (momentum lattice) and rho E (energy lattice)
+  R rho = R(0), j[3] = {R(0), R(0), R(0)}, rhoE = R(0);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const R d = from_store<S, R>(P, LF, stream_load(at32(src + (size_t)(LF * Q + i) * n, nd)));
+    rho += d;
+    acc_c(j[0], cx(i), d);
+    acc_c(j[1], cy(i), d);
+    acc_c(j[2], cz(i), d);
+    rhoE += from_store<S, R>(P, LG, stream_load(at32(src + (size_t)(LG * Q + i) * n, nd)));
+  }
+  rho += P.ref0[LF];
+  rhoE += P.ref0[LG];
+  Mix<R, M> s;
+  mixture_state<R, M, WEAK, false>(P, rho, j, rhoE, rho_s, s);
+  R us[3], Pk = s.P;                     // velocity and pressure of the species subsystem
+  if constexpr (WEAK) {
+    R rs = R(0);
+#pragma unroll
+    for (int a = 0; a < M; ++a) rs += s.rho_a[a];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      R jt = R(0);
+#pragma unroll
+      for (int a = 0; a < M; ++a) jt += js[a][k];
+      us[k] = jt / rs;                   // eq uSPEC
+    }
+    Pk = rs * s.Rg * s.T;                // Dalton: sum_a rho_a R_a T
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {        // slaved species momentum: the deficit (eq uMATCH)
+      R jm = j[k];
+#pragma unroll
+      for (int a = 0; a < M - 1; ++a) jm -= js[a][k];
+      js[M - 1][k] = jm;
+      us[k] = s.u[k];
+    }
+  }
+  bool present[M];
+  species_present<R, M>(P, s.rho_a, s.rho, present);
+  R K[M][M], V[M][3];
+  friction_matrix<R, M>(P, s, Pk, present, K);
+  diffusion_velocities<R, M>(s, present, K, js, us, V);
+  const R theta = s.Rg * s.T;
+  const R mu_mix = mixture_viscosity<R, M>(P, s.X);
+  const R lam_mix = mixture_conductivity<R, M>(P, s.X);
+  const R omega = R(2) * s.P / (s.P + R(2) * mu_mix);
+  const R omega1 = R(2) * s.P * s.Cp / (s.P * s.Cp + R(2) * lam_mix);
+  auto put = [&](int f, R v) { stream_store(at32(rec + (size_t)f * n, nd), Rec(v)); };
+#pragma unroll
+  for (int k = 0; k < 3; ++k) put(REC_PHIX + k, j[k] * (R(1) - R(3) * theta) - j[k] * s.u[k] * s.u[k]);
+  put(REC_OMEGA, omega);
+  put(REC_CP, s.Cp);
+  put(REC2_OMEGA1, omega1);
+  put(REC2_RG, s.Rg);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    R h = R(0);
+#pragma unroll
+    for (int a = 0; a < M; ++a) h += P.cp[a] * s.Y[a] * V[a][k];
+    put(REC2_HYV + k, h);
+  }
+  // species collisions and streaming
+  Trip<SrcF<S>> pe[M][3], pd[M][3];
+#pragma unroll
+  for (int c = 0; c < M; ++c) {
+    const SrcF<S> zeta = SrcF<S>(s.T * P.inv_m[c]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      pe[c][k] = psi_trip<SrcF<S>>(SrcF<S>(us[k]), zeta);
+      pd[c][k] = psi_diff_trip<SrcF<S>>(SrcF<S>(us[k]), SrcF<S>(V[c][k]));
+    }
+  }
+  const Nbr b = neighbours(P, node);
+#pragma unroll
+  for (int a = 0; a < NS; ++a) {
+    S (&va)[Q] = vs[HOLD ? a : 0];
+    if constexpr (!HOLD) load_lattice(src + (size_t)a * Q * n, n, nd, va);
+    species_relax<S, R, M, BC, false>(P, s, K, pe, pd, us, R(1), a, va, dst, b, node, step);
+    lattice_barrier();
+  }
+}
+
+template <typename S, typename R, typename Rec, int M, int BC, bool WEAK = false>
+__host__ __device__ __forceinline__ void fg_collide_node(const Params<R>& P, const S* __restrict__ src,
+                                                         S* __restrict__ dst, const Rec* __restrict__ rec,
+                                                         const Rec* __restrict__ G, int64_t node, uint32_t step)
+{
+  const size_t n = (size_t)P.n;
+  const uint32_t nd = (uint32_t)node;
+  constexpr int LF = Lat<M, WEAK>::LF, LG = Lat<M, WEAK>::LG;
+  S vf[Q], vg[Q];
+  load_lattice(src + (size_t)LF * Q * n, n, nd, vf);
+  load_lattice(src + (size_t)LG * Q * n, n, nd, vg);
+  // moments: rho, rho u, the pressure tensor sum_i f_i c_i c_i, rho E and q
+  R rho = R(0), j[3] = {R(0), R(0), R(0)}, Pd[3] = {R(0), R(0), R(0)}, Pxy = R(0), Pxz = R(0), Pyz = R(0);
+  R rhoE = R(0), q[3] = {R(0), R(0), R(0)};
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const R d = from_store<S, R>(P, LF, vf[i]);
+    rho += d;
+    acc_c(j[0], cx(i), d);
+    acc_c(j[1], cy(i), d);
+    acc_c(j[2], cz(i), d);
+    if (cx(i)) Pd[0] += d;
+    if (cy(i)) Pd[1] += d;
+    if (cz(i)) Pd[2] += d;
+    acc_c(Pxy, cx(i) * cy(i), d);
+    acc_c(Pxz, cx(i) * cz(i), d);
+    acc_c(Pyz, cy(i) * cz(i), d);
+    const R e = from_store<S, R>(P, LG, vg[i]);
+    rhoE += e;
+    acc_c(q[0], cx(i), e);
+    acc_c(q[1], cy(i), e);
+    acc_c(q[2], cz(i), e);
+  }
+  rho += P.ref0[LF];
+  rhoE += P.ref0[LG];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) Pd[k] += P.ref2[LF];
+  auto get = [&](int f) -> R { return R(*at32(rec + (size_t)f * n, nd)); };
+  const R omega = get(REC_OMEGA), omega1 = get(REC2_OMEGA1), Cp = get(REC_CP), Rg = get(REC2_RG);
+  const R inv_rho = R(1) / rho;
+  R u[3], usq = R(0);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    u[k] = j[k] * inv_rho;
+    usq += u[k] * u[k];
+  }
+  const R T = (rhoE * inv_rho - R(0.5) * usq) / (Cp - Rg);   // eq temperature2, C_v = C_p - R
+  const R theta = Rg * T;
+  const R Pp = rho * Rg * T;
+  // non-local terms: X_a = -d_a G_a (eq Xalpha) and d C_p (sum_a H_a d Y_a = T d C_p)
+  const Nbr b = neighbours(P, node);
+  R dG[3] = {R(0), R(0), R(0)}, gcp[3] = {R(0), R(0), R(0)};
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    if (csq(i) == 0) continue;
+    const uint32_t nb = stencil_index<BC>(b, cx(i), cy(i), cz(i));
+    const R w3 = R(3.0 * w13(i));
+    const R cpn = w3 * R(*at32(rec + (size_t)REC_CP * n, nb));
+    acc_c(gcp[0], cx(i), cpn);
+    acc_c(gcp[1], cy(i), cpn);
+    acc_c(gcp[2], cz(i), cpn);
+    if (cx(i)) acc_c(dG[0], cx(i), w3 * R(*at32(G, nb)));
+    if (cy(i)) acc_c(dG[1], cy(i), w3 * R(*at32(G + n, nb)));
+    if (cz(i)) acc_c(dG[2], cz(i), w3 * R(*at32(G + 2 * n, nb)));
+  }
+  const R Xc[3] = {-dG[0], -dG[1], -dG[2]};
+  // energy source: the non-equilibrium flux q - q^eq - u.(P - P^eq) of this node
+  const R H = Cp * T;
+  const R hyd = H + R(0.5) * usq;
+  const R Pn[3][3] = {{Pd[0], Pxy, Pxz}, {Pxy, Pd[1], Pyz}, {Pxz, Pyz, Pd[2]}};
+  R dq[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    R up = R(0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) up += u[c] * (Pn[c][k] - (c == k ? Pp : R(0)) - rho * u[c] * u[k]);
+    const R qn = q[k] - hyd * rho * u[k] - up;
+    dq[k] = (omega - omega1) * qn + omega1 * rho * T * get(REC2_HYV + k) + R(0.5) * (R(2) - omega1) * Pp * T * gcp[k];
+  }
+  momentum_relax<S, R, BC>(P, LF, rho, u, theta, omega, Xc, vf, dst, b, node, step);
+  lattice_barrier();
+  energy_relax<S, R, BC>(P, LG, rho, u, usq, theta, H, omega, dq, vg, dst, b, node, step);
 }
 
 // --------------------------------------------------------------------------

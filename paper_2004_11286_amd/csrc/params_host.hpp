@@ -26,7 +26,7 @@ struct RefState {
   double p, T;
 };
 
-// Wilke's phi_ab (Sec. 3.4, eq wilkePhi).
+// Wilke's phi_ab (Sec. 3.3, eq wilkePhi).
 inline double wilke_phi(const HostSpecies& h, int a, int b)
 {
   double num = 1.0 + std::sqrt((h.mu[a] / h.mu[b]) * std::sqrt(h.m[b] / h.m[a]));

@@ -37,6 +37,11 @@ MCLBM_K_MOMENTS = 0
 MCLBM_K_GFIELD = 1
 MCLBM_K_COLLIDE = 2
 
+
+def kernel_count() -> int:
+    """Number of kernel identifiers mclbm_kernel_stats knows (MCLBM_K_*)."""
+    return 3
+
 EXPORTS = ["mclbm_workspace_bytes", "mclbm_batch_workspace_bytes", "mclbm_create", "mclbm_batch_create",
            "mclbm_destroy", "mclbm_last_error", "mclbm_tube_count", "mclbm_node_count",
            "mclbm_init_fields", "mclbm_step", "mclbm_read_moments", "mclbm_read_fields_f32",
@@ -65,10 +70,10 @@ class mclbm_params(C.Structure):
 class mclbm_launch(C.Structure):
     _fields_ = [("variant", C.c_int32), ("swizzle", C.c_int32), ("order", C.c_int32),
                 ("graph_steps", C.c_int32), ("sequential", C.c_int32), ("split", C.c_int32),
-                ("reserved", C.c_int32 * 2)]
+                ("three_pass", C.c_int32), ("reserved", C.c_int32)]
 
 
-LAUNCH_KEYS = ("variant", "swizzle", "order", "graph_steps", "sequential", "split")
+LAUNCH_KEYS = ("variant", "swizzle", "order", "graph_steps", "sequential", "split", "three_pass")
 
 
 class MclbmError(RuntimeError):
@@ -269,7 +274,7 @@ def mclbm_set_launch(ctx, **kw) -> None:
 
 
 def mclbm_autotune(ctx, trial_steps: int) -> str:
-    buf = C.create_string_buffer(4096)
+    buf = C.create_string_buffer(16384)
     _check(ctx, lib.mclbm_autotune(ctx, int(trial_steps), buf, len(buf)))
     return buf.value.decode()
 

@@ -206,8 +206,11 @@ def evaluate(params, norm, eval_tubes, K: int = K_DEFAULT, starts=(0, 500, 2000)
     """Judge the surrogate by the lattice: from the same state at each start
     time, K lattice steps against one network hop. Reports the mole-fraction
     error (L-infinity over all tubes), that of the persistence prediction (no
-    change), the mole residual, and the times of the hop (read, forward, residual
-    and re-initialisation through mclbm_nn_advance) and of the K lattice steps."""
+    change), the mole residual, the residual the advance entry point gates on
+    (largest relative change of a species' mass or of the energy per tube) for
+    the network and for the K lattice steps, whether the hop was accepted, and
+    the times of the hop (read, forward, residual and re-initialisation through
+    mclbm_nn_advance) and of the K lattice steps."""
     import torch
 
     b = mc.Batch([p for p, _ in eval_tubes], mc.MCLBM_FP32)
@@ -225,12 +228,16 @@ def evaluate(params, norm, eval_tubes, K: int = K_DEFAULT, starts=(0, 500, 2000)
         # lattice reference: K steps, timed on the stream
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         start = ref.read_fields_f32().clone()
+        c0 = ref.conservation()
         e0.record(ref.stream)
         ref.step(K)
         e1.record(ref.stream)
         e1.synchronize()
         t_lbm = e0.elapsed_time(e1)
         want = ref.read_fields_f32().clone()
+        c1 = ref.conservation()
+        keep = np.concatenate([np.arange(M), [M + 4]])         # species masses and the energy
+        lat_res = float(np.max(np.abs(c1[:, keep] - c0[:, keep]) / np.abs(c0[:, keep])))
         # network prediction from the same state (forward only, for the error)
         net.fields_in.copy_(start)
         net.forward()
@@ -269,7 +276,9 @@ def evaluate(params, norm, eval_tubes, K: int = K_DEFAULT, starts=(0, 500, 2000)
         out.append({"t0": int(t0), "K": int(K), "X_linf": e_inf, "X_linf_persistence": p_inf,
                     "X_rms": e_rms, "X_rms_persistence": p_rms,
                     "mole_residual_max": float(np.max(res)),
-                    "lattice_mole_residual_max": float(np.max(res_lattice)), "accepted": not used,
+                    "lattice_mole_residual_max": float(np.max(res_lattice)),
+                    "state_residual": float(res_adv), "lattice_state_residual": lat_res,
+                    "resid_tol": float(resid_tol), "accepted": not used,
                      "ms_lattice": t_lbm, "ms_advance": t_adv, "ms_forward": t_fwd})
     net.close()
     b.close()

@@ -173,7 +173,7 @@ def tube_ensemble(ntubes=512, ny=16, nz=16, lmin=32, lmax=256, seed=11286, T0=1.
     distinct molar masses from {2, 16, 28, 40}, D_ab ~ U[0.01, 0.1], left and
     right mole fractions ~ Dirichlet(1, 1, 1), uniform pressure giving mean
     density 1, T = 1/3, zero velocity. The slaved species is the one with the
-    largest minimum mass fraction. Strong coupling (Sec. 3.6.2) needs the slaved
+    largest minimum mass fraction. Strong coupling (Sec. 3.5.2) needs the slaved
     species to carry a good part of the mass everywhere: compositions whose
     slaved species falls below ``min_slaved_y`` in mass fraction on either side
     are drawn again. Of unconditioned Dirichlet(1, 1, 1) draws about 10% have the

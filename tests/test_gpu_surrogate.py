@@ -5,8 +5,9 @@ the mole residual, and the advance entry point with and without fallback.
 
 Bounds: the depth-2 forward to 1e-3 of the output's maximum (only FP32-versus-
 FP64 sums differ, plus rare BF16 ties of the hidden layer); the depth-6 forward
-to 1e-2 (rounding differences of BF16 activations compound over layers); the
-gradients per layer to 1e-2 in the 2-norm; Adam to FP32 rounding.
+to 5e-3 (rounding differences of BF16 activations compound over layers); every
+element of each layer's gradients to a bound about ten times the measured
+max |gpu - ref| / max |ref| of that comparison; Adam to FP32 rounding.
 """
 import numpy as np
 import pytest
@@ -18,6 +19,9 @@ pytestmark = pytest.mark.gpu
 
 DIMS = [(13, 4, 3), (40, 2, 5), (7, 8, 8)]       # ragged tubes: 156, 400 and 448 nodes
 C = 8                                            # X_1..X_3, T, u (3), p
+# element-wise gradient bounds per layer, max |gpu - ref| / max |ref|
+GRAD_BOUND = 1e-2
+GRAD_BOUND_CONS = 2e-2
 
 
 @pytest.fixture(scope="module")
@@ -73,7 +77,7 @@ def split(vec, dims=DIMS):
     return out
 
 
-@pytest.mark.parametrize("depth,bound", [(2, 1e-3), (6, 1e-2)])
+@pytest.mark.parametrize("depth,bound", [(2, 1e-3), (6, 5e-3)])
 def test_forward_matches_oracle(env, depth, bound):
     p = S.he_init(C, depth, seed=depth, gain=1.0)
     p += np.random.default_rng(1).normal(0, 0.01, p.size).astype(np.float32)
@@ -147,9 +151,9 @@ def test_loss_and_gradients_match_oracle(env, Pn, Sn):
         for name, size in (("W", 27 * o * i), ("b", o)):
             a, b = g_gpu[k:k + size], g_ref[k:k + size]
             k += size
-            rel = np.linalg.norm(a - b) / np.linalg.norm(b)
-            print("grad layer", li, name, "rel 2-norm", rel)
-            assert rel < 1e-2, (li, name, rel)
+            rel = np.abs(a - b).max() / np.abs(b).max()
+            print("grad layer", li, name, "elementwise rel linf", rel, "2-norm", np.linalg.norm(a - b) / np.linalg.norm(b))
+            assert rel < GRAD_BOUND, (li, name, rel)
 
 
 def test_adam_step_matches_oracle(env):
@@ -236,13 +240,57 @@ def test_advance_with_a_null_network_keeps_the_fields(env):
     net = mc.Net(C, 3, [(32, 4, 4)])
     net.set_params(np.zeros(net.param_count, np.float32))
     used, res = net.advance(s, 100, 1e-4)
-    assert not used and res == 0.0 and s.step_count == 150
+    # the residual of the installed state: the FP32 read-back of the fields only
+    print("null network: residual of the installed state", res)
+    assert not used and res <= 1e-6 and s.step_count == 150
     after = s.read_moments()
     for k in ("X", "T", "p"):
         np.testing.assert_allclose(after[k], before[k], rtol=2e-6, atol=1e-7)
     np.testing.assert_allclose(after["u"], before["u"], atol=1e-7)
     net.close()
     s.close()
+
+
+@pytest.mark.parametrize("dT_rel,falls_back", [(1e-2, True), (1e-6, False)])
+def test_advance_rejects_a_hop_that_keeps_the_moles_but_not_the_energy(env, dT_rel, falls_back):
+    """A conservative network whose only nonzero parameter is the bias of its
+    temperature output raises T by dT_rel everywhere and keeps every species'
+    moles exactly: the mole residual of the prediction is zero, but the state it
+    would install holds dT_rel more energy (and proportionally more pressure).
+    With dT_rel = 1e-2 the advance falls back to the lattice (bitwise its K
+    steps); with 1e-6 the hop is accepted and T is raised by that fraction."""
+    mc, _ = env
+    s, params = _tube_sim(mc)
+    ref, _ = _tube_sim(mc)
+    before = s.read_moments()
+    T0 = float(np.mean(before["T"]))
+    depth = 3
+    net = mc.Net(C, depth, [(32, 4, 4)], species=3)
+    out_scale = np.array([3e-4] * 9 + [1e-3, 3e-4, 3e-4, 3e-4], np.float32)
+    net.set_norm(np.full(C, 0.3, np.float32), np.ones(C, np.float32), out_scale)
+    p = np.zeros(net.param_count, np.float32)
+    p[-13 + 9] = dT_rel * T0 / out_scale[9]             # last layer's bias of the T channel
+    net.set_params(p)
+    fin = s.read_fields_f32()
+    net.fields_in.copy_(fin)
+    net.forward()
+    moles = net.mole_residual(3, fin, net.fields_out)
+    used, res = net.advance(s, 20, 1e-4)
+    print("dT/T", dT_rel, "mole residual", moles, "state residual", res, "fallback", used)
+    assert np.all(moles <= 1e-6)
+    assert abs(res - dT_rel) <= 0.05 * dT_rel + 2e-7      # plus the FP32 read-back of the fields
+    assert bool(used) == falls_back and s.step_count == 70
+    got = s.read_moments()
+    if falls_back:
+        ref.step(20)
+        want = ref.read_moments()
+        for k in got:
+            np.testing.assert_array_equal(got[k], want[k])
+    else:
+        np.testing.assert_allclose(got["T"], before["T"] * (1 + dT_rel), rtol=1e-6)
+    net.close()
+    s.close()
+    ref.close()
 
 
 def test_trained_on_lattice_trajectories(env):
@@ -274,7 +322,7 @@ def test_trained_on_lattice_trajectories(env):
         assert res["X_rms"] < 0.9 * res["X_rms_persistence"]
         assert res["ms_forward"] < res["ms_lattice"]
         assert res["mole_residual_max"] <= 1e-5
-        assert res["accepted"] == (res["mole_residual_max"] <= 1e-4)
+        assert res["accepted"] == (res["state_residual"] <= 1e-4)
 
 
 def cons_fields(seed, dims=DIMS, M=3):
@@ -391,9 +439,10 @@ def test_conservative_gradients_match_oracle(env, wf):
         for name, size in (("W", 27 * o * i), ("b", o)):
             a, b = g_gpu[k:k + size], g_ref[k:k + size]
             k += size
-            rel = np.linalg.norm(a - b) / np.linalg.norm(b)
-            print("conservative grad layer", li, name, "rel 2-norm", rel)
-            assert rel < 2e-2, (li, name, rel)
+            rel = np.abs(a - b).max() / np.abs(b).max()
+            print("conservative grad layer", li, name, "elementwise rel linf", rel, "2-norm",
+                  np.linalg.norm(a - b) / np.linalg.norm(b))
+            assert rel < GRAD_BOUND_CONS, (li, name, rel)
 
 
 def test_clip_grad_norm_matches_reference(env):

@@ -1,4 +1,4 @@
-"""GPU parity of weak coupling (Sec. 3.6.1) against the oracle, through the C ABI.
+"""GPU parity of weak coupling (Sec. 3.5.1) against the oracle, through the C ABI.
 
 Weak coupling stores and evolves all M species lattices; the species subsystem
 keeps its own density and velocity (eqs rhoSPEC, uSPEC) and Dalton pressure and
@@ -141,8 +141,8 @@ def test_weak_ternary_tube_fp32_1000_steps(mc, weak_tube_1000):
 
 def test_weak_ternary_tube_fp16_1000_steps(mc, weak_tube_1000):
     """The same tube with FP16 deviation storage (stochastic rounding) and FP32
-    collision: bounded like strong coupling's FP16 run (1e-2, five times that
-    for the velocity, whose maximum is only 1e-3); the stochastically rounded
+    collision: each field bounded just above its measured error (velocity against
+    max(max |u|, 1e-3)); X and u miss the 1e-3 bar. The stochastically rounded
     stores keep every species' mass to 1e-4 (unbiased rounding errors)."""
     params, f, o = weak_tube_1000
     s = mc.Sim(params, mc.MCLBM_FP16)
@@ -152,10 +152,11 @@ def test_weak_ternary_tube_fp16_1000_steps(mc, weak_tube_1000):
     g = s.read_moments()
     c1 = s.conservation()
     s.close()
-    errs = field_errors(g, o)
+    errs = field_errors(g, o, u_floor=1e-3)
     print("weak C2 fp16 1000", errs, "mass drift", np.abs(c1[:3] / c0[:3] - 1).max())
+    bounds = {"X": 3e-3, "rho": 1.4e-3, "u": 2e-2, "p": 5e-4, "T": 1.5e-3}   # measured 2.4e-3, 1.1e-3, 1.5e-2, 3.8e-4, 1.2e-3
     for k in FIELDS:
-        assert errs[k] < (5e-2 if k == "u" else 1e-2), (k, errs[k])
+        assert errs[k] < bounds[k], (k, errs[k])
     np.testing.assert_allclose(c1[:4], c0[:4], rtol=1e-4)
 
 
@@ -238,16 +239,18 @@ def test_weak_checkpoint_resume_is_bitwise(mc):
 
 
 def test_weak_launch_choices_agree(mc):
-    """A weakly coupled context starts with the split collision and the
-    higher-occupancy moments kernel; every launch choice computes the same step
-    (the split to rounding: its kernels are compiled separately)."""
+    """A weakly coupled context starts with the two-read step; every launch choice
+    computes the same step: the two-read variants bit for bit, the three-pass
+    forms (fused, or split into two launches whose kernels are compiled
+    separately) to rounding."""
     params, f = _case(3, 13, 7, 5, 1, seed=3)
     out = []
-    for launch in (None, dict(variant=0, split=0), dict(variant=1, split=0), dict(variant=0, split=1)):
+    for launch in (None, dict(variant=1), dict(three_pass=1, variant=0, split=0),
+                   dict(three_pass=1, variant=1, split=0), dict(three_pass=1, variant=0, split=1)):
         s = mc.Sim(params, mc.MCLBM_FP64)
         if launch is None:
             lc = s.launch()
-            assert lc["variant"] == 1 and lc["split"] == 1
+            assert lc["three_pass"] == 0 and lc["variant"] == 0 and lc["split"] == 0
         else:
             s.set_launch(**launch)
         s.init_fields(**f)
@@ -259,7 +262,8 @@ def test_weak_launch_choices_agree(mc):
             scale = max(np.abs(out[0][k]).max(), 1e-3 if k == "u" else 0.0)
             assert np.abs(got[k] - out[0][k]).max() <= 1e-13 * scale, k
     for k in FIELDS:
-        np.testing.assert_array_equal(out[1][k], out[2][k])      # fused forms: bitwise
+        np.testing.assert_array_equal(out[0][k], out[1][k])      # two-read variants: bitwise
+        np.testing.assert_array_equal(out[2][k], out[3][k])      # fused three-pass forms: bitwise
 
 
 def _cv_and_transport(params, T0=0.3):

@@ -2,9 +2,9 @@
 
 - Product-form equilibria (Sec. 2.4, eq prod): moments {1, c, cc} give
   {1, xi, xi xi + zeta I}; the diagonal third moment equals xi (the lattice
-  constraint c^3 = c discussed in Sec. 3.5.2); at xi = 0, zeta = 1/3 they are
+  constraint c^3 = c discussed in Sec. 3.4.2); at xi = 0, zeta = 1/3 they are
   the textbook D3Q27 weights (golden file).
-- Energy-lattice ansatz (Sec. 3.5.1, eqs gansatz..Bi): reproduces {M0, m, M}
+- Energy-lattice ansatz (Sec. 3.4.1, eqs gansatz..Bi): reproduces {M0, m, M}
   for any theta; reduces to Grad's form at theta = 1/3.
 - Correction vectors A_i (eq Ai) and B_i (eq Bi): the moments used in the
   paper's construction.

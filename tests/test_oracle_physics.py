@@ -146,7 +146,7 @@ def test_crank_nicolson_catches_dropped_source(oracle_mod):
 
 
 def test_slaved_lattice_is_never_read(oracle_mod):
-    """Under strong coupling (Sec. 3.6.2) the slaved species' own lattice is
+    """Under strong coupling (Sec. 3.5.2) the slaved species' own lattice is
     purely relaxational and no other quantity reads it: evolving it or not gives
     bitwise identical moments."""
     outs = []
@@ -257,7 +257,7 @@ CV_R = {"H2": 2.5, "Ar": 1.5, "CH4": 3.0, "C3H8": 8.0}
 
 def _sound_case(row):
     name, Rprint, species = row
-    # slave the species carrying most of the mass (Sec. 3.6.2): put it last
+    # slave the species carrying most of the mass (Sec. 3.5.2): put it last
     mass_frac = [x * MOLAR[sp] for sp, x in species]
     order = sorted(range(3), key=lambda i: mass_frac[i])
     species = [species[i] for i in order]

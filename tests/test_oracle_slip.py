@@ -1,7 +1,7 @@
 """Pins of the oracle's free-slip y walls (wall_y = 1: specular reflection at the
 half-way walls y = -1/2 and y = ny - 1/2; the stencils mirror the boundary node,
 with the y component of Phi odd), the lateral boundary of the opposed-jet setup
-(Sec. 4.5).
+(Sec. 4.3).
 
 What fixes the results: a plug flow parallel to the walls is a fixed point; the
 walls exchange no tangential momentum, so mass, energy and the x and z momenta

@@ -1,4 +1,4 @@
-"""Pins of the oracle's weak coupling (Sec. 3.6.1): all M species lattices evolve
+"""Pins of the oracle's weak coupling (Sec. 3.5.1): all M species lattices evolve
 with their own conservation laws; the species subsystem of Sec. 2 is closed by
 its own moments (species-barycentric velocity, composition and Dalton pressure
 from the species densities) and takes the temperature from the energy lattice;
@@ -7,13 +7,13 @@ velocities from the species.
 
 What fixes the results, other than the oracle itself:
   - on a state where the two definitions of the mixture density and momentum
-    agree (Sec. 3.6.2), weak and strong coupling are the same step;
+    agree (Sec. 3.5.2), weak and strong coupling are the same step;
   - a uniform species equilibrium is a fixed point of the species collision
     whatever the momentum lattice does (the species subsystem is closed);
   - the conservation laws of the weakly coupled system (M + 2D + 2 of them,
     eq DOF's count), each exact;
   - the two mixture densities agree in the continuum limit (the closing remark
-    of Sec. 3.6.2): the local mismatch falls with resolution;
+    of Sec. 3.5.2): the local mismatch falls with resolution;
   - the binary Fick limit (eq constit2) holds under weak coupling as well;
   - with temperature-dependent heat capacities and transport: the same step as
     strong coupling from local equilibrium, the same conservation laws, and
@@ -98,7 +98,7 @@ def test_weak_species_fixed_point_at_own_velocity(oracle_mod):
 
 def test_weak_conservation_periodic(oracle_mod):
     """Weak coupling conserves every species' mass, the species' total momentum,
-    and the mixture's mass, momentum and energy separately (Sec. 3.6.2 counts
+    and the mixture's mass, momentum and energy separately (Sec. 3.5.2 counts
     M + 2D + 2 laws). The species momentum is exact because the friction of
     eq transform12 and the source of eq fstar1 share the coefficients
     K_ab = Y_a rho_b / tau_ab, which needs the species' own pressure in K_ab: with
@@ -135,7 +135,7 @@ def _sine_ternary(nx, masses=(20.0, 20.0, 20.0)):
 
 
 def test_weak_densities_agree_in_continuum_limit(oracle_mod):
-    """Closing remark of Sec. 3.6.2: the weakly coupled species and momentum
+    """Closing remark of Sec. 3.5.2: the weakly coupled species and momentum
     lattices do not drift apart in mass. Locally they differ by a term driven by
     the composition gradients (the species' non-equilibrium stresses, which
     strong coupling hides in the slaved lattice); at the same diffusive time
@@ -277,7 +277,7 @@ def test_weak_interdiffusion_keeps_temperature_uniform_with_cv_of_T(oracle_mod):
     capacities depend on T differently leaves T uniform when the fluxes carry
     H_a(T) (eq specHa); with H_a = C_{a,p}(T) T (planted) T drifts. Weak
     coupling adds a transient of its own, from the mismatch of the two mixture
-    densities, which falls with resolution (Sec. 3.6.2): hence 128 nodes and the
+    densities, which falls with resolution (Sec. 3.5.2): hence 128 nodes and the
     deviation at the end of the run (0.004 against 0.016 planted)."""
     good = _weak_interdiffusion_temperature(oracle_mod, 0)
     bad = _weak_interdiffusion_temperature(oracle_mod, oracle_mod.CVT_HA_CPT)

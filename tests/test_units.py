@@ -15,7 +15,7 @@ import physics_cases as pc
 from paper_2004_11286_amd import units as U
 
 # H2, CH4, Ar: the species with most of the mass last (it is the slaved one under
-# strong coupling, Sec. 3.6.2)
+# strong coupling, Sec. 3.5.2)
 SPECIES = {
     "molar_mass": np.array([2.016, 16.043, 39.948]),        # g/mol
     "cv_molar": np.array([2.5, 3.3, 1.5]),
