@@ -139,6 +139,23 @@ int mclbm_create(const mclbm_params *p, void *dev_workspace, size_t bytes, void 
 int mclbm_batch_create(const mclbm_params *tubes, int32_t ntubes, void *dev_workspace, size_t bytes,
                        void *hip_stream, mclbm_ctx **out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same context as
+ * mclbm_create, whose workspace is instead an array of
+ * MCLBM_STATIC_WORKSPACE_BYTES bytes inside the library, one per device, that
+ * the device keeps until the process ends. No device memory is allocated (no
+ * hipMalloc, no allocating library routine). Every call of the context works as
+ * with mclbm_create. Limits: MCLBM_EARG (with a message naming the sizes) when
+ * mclbm_workspace_bytes(p) exceeds the array; one context per device at a time
+ * (MCLBM_EARG while another holds it; mclbm_destroy releases it). The array
+ * keeps the last context's contents; a new context initialises whatever it
+ * reads (mclbm_init_fields or mclbm_load), as with any workspace. The calls of
+ * a static context race with those of any other context on the same device
+ * only through this array, which no other context can hold; calls on one
+ * context are not thread safe (as for every context). */
+#define MCLBM_STATIC_WORKSPACE_BYTES (64u << 20)
+int mclbm_create_static(const mclbm_params *p, void *hip_stream, mclbm_ctx **out);
+
 void mclbm_destroy(mclbm_ctx *c);
 
 /* Number of tubes, and total number of nodes over all tubes. */

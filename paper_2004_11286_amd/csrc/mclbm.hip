@@ -22,6 +22,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
@@ -924,10 +925,66 @@ extern "C" int mclbm_create(const mclbm_params* p, void* dev_workspace, size_t b
   return mclbm_batch_create(p, 1, dev_workspace, bytes, hip_stream, out);
 }
 
+// ---------------------------------------------------------------------------
+// Static workspace: mclbm_create_static. For callers that cannot allocate device
+// memory, a context whose workspace is an array in the library's code object,
+// one copy per device, of MCLBM_STATIC_WORKSPACE_BYTES. Its device address is
+// looked up once per device (hipGetSymbolAddress) with that device current; the
+// array's name is never used as a device address in host code. One context per
+// device may hold the array at a time.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) char scratch[MCLBM_STATIC_WORKSPACE_BYTES];
+
+namespace {
+constexpr int STATIC_MAX_DEVICES = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[STATIC_MAX_DEVICES] = {};
+const mclbm_ctx* g_static_owner[STATIC_MAX_DEVICES] = {};
+
+// Release the device's static workspace if c holds it (called by mclbm_destroy).
+void release_static(const mclbm_ctx* c)
+{
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  for (int d = 0; d < STATIC_MAX_DEVICES; ++d)
+    if (g_static_owner[d] == c) g_static_owner[d] = nullptr;
+}
+}  // namespace
+
+extern "C" int mclbm_create_static(const mclbm_params* p, void* hip_stream, mclbm_ctx** out)
+{
+  if (!out) return fail(nullptr, MCLBM_EARG, "out is NULL");
+  *out = nullptr;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(nullptr, MCLBM_EDEVICE, "hipGetDevice failed");
+  if (dev < 0 || dev >= STATIC_MAX_DEVICES) return fail(nullptr, MCLBM_EARG, "device index beyond the static table");
+  std::string err;
+  const int vrc = validate(p, 1, err);
+  if (vrc != MCLBM_OK) return fail(nullptr, vrc, err);
+  const size_t need = layout_for(p, 1).total;
+  if (need > (size_t)MCLBM_STATIC_WORKSPACE_BYTES)
+    return fail(nullptr, MCLBM_EARG,
+                "the context needs " + std::to_string(need) + " workspace bytes; the static workspace holds " +
+                    std::to_string((size_t)MCLBM_STATIC_WORKSPACE_BYTES) + " (use mclbm_create)");
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if (!g_static_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(nullptr, MCLBM_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_static_ptr[dev] = ptr;
+  }
+  if (g_static_owner[dev])
+    return fail(nullptr, MCLBM_EARG, "the static workspace of this device is held by another context");
+  const int rc = mclbm_batch_create(p, 1, g_static_ptr[dev], (size_t)MCLBM_STATIC_WORKSPACE_BYTES, hip_stream, out);
+  if (rc == MCLBM_OK) g_static_owner[dev] = *out;
+  return rc;
+}
+
 extern "C" void mclbm_destroy(mclbm_ctx* c)
 {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  release_static(c);
   drop_graph(c);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);

@@ -47,7 +47,7 @@ EXPORTS = ["mclbm_workspace_bytes", "mclbm_batch_workspace_bytes", "mclbm_create
            "mclbm_init_fields", "mclbm_step", "mclbm_read_moments", "mclbm_read_fields_f32",
            "mclbm_conservation", "mclbm_step_count", "mclbm_state_bytes", "mclbm_save", "mclbm_load",
            "mclbm_set_timing", "mclbm_kernel_stats", "mclbm_get_launch", "mclbm_set_launch",
-           "mclbm_autotune", "mclbm_stream_copy", "mclbm_half_tube_moles"]
+           "mclbm_autotune", "mclbm_stream_copy", "mclbm_half_tube_moles", "mclbm_create_static"]
 NN_EXPORTS = ["mclbm_nn_workspace_bytes", "mclbm_nn_create", "mclbm_nn_destroy", "mclbm_nn_last_error",
               "mclbm_nn_param_count", "mclbm_nn_set_params", "mclbm_nn_get_params", "mclbm_nn_get_grads",
               "mclbm_nn_set_norm", "mclbm_nn_set_conditioning", "mclbm_nn_io", "mclbm_nn_forward", "mclbm_nn_loss", "mclbm_nn_backward",
@@ -99,6 +99,7 @@ def _load():
     L.mclbm_workspace_bytes.argtypes = [P]
     L.mclbm_workspace_bytes.restype = C.c_size_t
     L.mclbm_create.argtypes = [P, vp, C.c_size_t, vp, C.POINTER(vp)]
+    L.mclbm_create_static.argtypes = [P, vp, C.POINTER(vp)]
     L.mclbm_batch_workspace_bytes.argtypes = [P, C.c_int32]
     L.mclbm_batch_workspace_bytes.restype = C.c_size_t
     L.mclbm_batch_create.argtypes = [P, C.c_int32, vp, C.c_size_t, vp, C.POINTER(vp)]
@@ -232,6 +233,18 @@ def mclbm_create(params: dict, precision: int, workspace_ptr: int, nbytes: int, 
     return h
 
 
+def mclbm_create_static(params: dict, precision: int, stream: int) -> C.c_void_p:
+    """A context over the library's static workspace (no device allocation)."""
+    p, _keep = make_params(params, precision)
+    h = C.c_void_p()
+    _check(None, lib.mclbm_create_static(C.byref(p), C.c_void_p(stream), C.byref(h)))
+    return h
+
+
+# Bytes of the library's static workspace (MCLBM_STATIC_WORKSPACE_BYTES in include/mclbm.h).
+MCLBM_STATIC_WORKSPACE_BYTES = 64 << 20
+
+
 def mclbm_batch_workspace_bytes(tubes: list, precision: int) -> int:
     arr, _keep = make_param_array(tubes, precision)
     n = lib.mclbm_batch_workspace_bytes(arr, len(tubes))
@@ -352,7 +365,10 @@ def mclbm_kernel_stats(ctx, kernel: int):
 class Sim:
     """A context plus its torch-owned device workspace on ``device``."""
 
-    def __init__(self, params: dict, precision: int | str = MCLBM_FP32, device: str = "cuda:0", stream=None):
+    def __init__(self, params: dict, precision: int | str = MCLBM_FP32, device: str = "cuda:0", stream=None,
+                 static_workspace: bool = False):
+        """static_workspace: use the library's static workspace (mclbm_create_static)
+        instead of a torch-allocated one."""
         import torch
 
         if isinstance(precision, str):
@@ -363,9 +379,14 @@ class Sim:
         self.nx, self.ny, self.nz = int(params["nx"]), int(params["ny"]), int(params["nz"])
         self.n = self.nx * self.ny * self.nz
         self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        if static_workspace:
+            self.workspace = None
+            with torch.cuda.device(self.device):
+                self.ctx = mclbm_create_static(params, self.precision, self.stream.cuda_stream)
+            return
         nbytes = mclbm_workspace_bytes(params, self.precision)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         with torch.cuda.device(self.device):
             self.ctx = mclbm_create(params, self.precision, self.workspace.data_ptr(), nbytes,
                                     self.stream.cuda_stream)
