@@ -259,9 +259,9 @@ typedef struct {
 } mclbm_launch;
 
 /* A new context starts with every field 0 (the two-read step where compiled),
- * except under weak coupling with the three-pass step (temperature-dependent
- * properties), which starts with variant = 1 and split = 1 (faster with the extra
- * stored lattice). */
+ * except with temperature-dependent properties (the three-pass step), which starts
+ * with split = 1, and under weak coupling also variant = 1 (the faster choices
+ * there). */
 int mclbm_get_launch(const mclbm_ctx *c, mclbm_launch *out);
 int mclbm_set_launch(mclbm_ctx *c, const mclbm_launch *in);
 

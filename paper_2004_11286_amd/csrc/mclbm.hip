@@ -830,13 +830,14 @@ extern "C" int mclbm_batch_create(const mclbm_params* tp, int32_t ntubes, void* 
   c->cvt = tp[0].cv_coef != nullptr || tp[0].transport_exp != nullptr;
   c->wall_y = tp[0].wall_y;
   c->L = (c->weak ? c->M : c->M - 1) + 2;
-  if (c->weak && c->cvt) {
-    // the three-pass step with four or more stored lattices: the split collision
-    // (two launches with fewer registers each) and the higher-occupancy moments
-    // kernel are the faster choices (binary shear layer 256^3, FP32: 5.74 -> 5.4 ms
-    // per step)
-    c->lc.variant = 1;
+  if (c->cvt) {
+    // the three-pass step (temperature-dependent properties): the fused collision
+    // spills at two waves per SIMD (binary shear layer 256^3, FP32: collide 4.06
+    // ms); the split collision, two launches with fewer registers each, does not.
+    // With four or more stored lattices (weak coupling) the higher-occupancy
+    // moments kernel is the faster choice too (5.74 -> 5.4 ms per step)
     c->lc.split = 1;
+    if (c->weak) c->lc.variant = 1;
   }
   c->ntubes = ntubes;
   c->n = lay.n;

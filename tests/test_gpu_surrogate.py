@@ -271,8 +271,8 @@ def test_advance_rejects_a_hop_that_keeps_the_moles_but_not_the_energy(env, dT_r
     p = np.zeros(net.param_count, np.float32)
     p[-13 + 9] = dT_rel * T0 / out_scale[9]             # last layer's bias of the T channel
     net.set_params(p)
-    fin = s.read_fields_f32()
-    net.fields_in.copy_(fin)
+    mc.mclbm_read_fields_f32(s.ctx, net.fields_in.data_ptr(), 1)
+    fin = net.fields_in.clone()
     net.forward()
     moles = net.mole_residual(3, fin, net.fields_out)
     used, res = net.advance(s, 20, 1e-4)
