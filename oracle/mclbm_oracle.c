@@ -178,7 +178,9 @@ struct oracle_sim {
   double m[MAXM], cv[MAXM], D[MAXM][MAXM], mu[MAXM], lam[MAXM];
   int cvt;                 /* 1: C_{a,v}(T) = sum_k cvc[a][k] T^k, else the constant cv[a] */
   double cvc[MAXM][4];
-  double fin[MAXM + 2][Q]; /* open x ends: populations of the inlet equilibrium */
+  double fin[MAXM + 2][Q]; /* open x ends and jets: populations of the inlet equilibrium at x = 0 */
+  double fin2[MAXM + 2][Q];/* jets: populations of the inlet equilibrium at x = nx - 1 */
+  int ny0, ny1;            /* jets: nozzle rows ny0 <= y < ny1 */
   int trn;                 /* 1: transport coefficients as powers of T / T_ref */
   double s_mu[MAXM], s_lam[MAXM], s_D, T_ref;
   double *pop;   /* [(M+2)][Q][n] pre-collision populations */
@@ -232,18 +234,25 @@ int oracle_create(const oracle_params *p, oracle_sim **out)
   *out = NULL;
   if (p->M < 2 || p->M > MAXM || p->nx < 1 || p->ny < 1 || p->nz < 1) return -1;
   if (p->wall_x && p->nx < 2) return -1;
-  if (p->wall_x < 0 || p->wall_x > 2 || (p->wall_x == 2 && !p->inlet)) return -1;
+  if (p->wall_x < 0 || p->wall_x > 3 || (p->wall_x >= 2 && !p->inlet)) return -1;
+  /* opposed jets: two nozzles, free-slip walls beside them, outlets at the y ends */
+  if ((p->wall_x == 3) != (p->wall_y == 2)) return -1;
+  if (p->wall_x == 3 && (!p->inlet_right || p->nozzle_y0 < 1 || p->nozzle_y1 > p->ny - 1 ||
+                         p->nozzle_y0 >= p->nozzle_y1))
+    return -1;
   if (!p->molar_mass || !p->cv || !p->D || !p->mu || !p->lambda) return -1;
   oracle_sim *s = (oracle_sim *)calloc(1, sizeof(oracle_sim));
   if (!s) return -1;
   s->M = p->M;
   s->nx = p->nx; s->ny = p->ny; s->nz = p->nz;
   s->wall_x = p->wall_x;
-  s->wall_y = p->wall_y ? 1 : 0;
-  if (s->wall_y && (p->ny < 2 || s->wall_x == 2)) {
+  s->wall_y = p->wall_y == 2 ? 2 : (p->wall_y ? 1 : 0);
+  if (s->wall_y == 1 && (p->ny < 2 || s->wall_x >= 2)) {
     free(s);
     return -1;
   }
+  s->ny0 = p->nozzle_y0;
+  s->ny1 = p->nozzle_y1;
   s->weak = p->weak ? 1 : 0;
   s->keep_slaved = (p->keep_slaved || s->weak) ? 1 : 0;   /* weak coupling evolves every species */
   s->flags = p->debug_flags;
@@ -302,11 +311,19 @@ int oracle_create(const oracle_params *p, oracle_sim **out)
     oracle_destroy(s);
     return -1;
   }
-  if (s->wall_x == 2) {
+  if (s->wall_x >= 2) {
     /* inlet fields: X (M), p, T, u (3) */
     const double *in = p->inlet;
     const double uin[3] = {in[s->M + 2], in[s->M + 3], in[s->M + 4]};
     if (local_equilibrium(s, in, in[s->M], in[s->M + 1], uin, s->fin) != 0) {
+      oracle_destroy(s);
+      return -1;
+    }
+  }
+  if (s->wall_x == 3) {
+    const double *in = p->inlet_right;
+    const double uin[3] = {in[s->M + 2], in[s->M + 3], in[s->M + 4]};
+    if (local_equilibrium(s, in, in[s->M], in[s->M + 1], uin, s->fin2) != 0) {
       oracle_destroy(s);
       return -1;
     }
@@ -503,17 +520,31 @@ static void node_state(const oracle_sim *s, const double *pop, long node, state_
  * about free-slip walls at y = -1/2 and y = ny - 1/2. comp is the vector
  * component the field is (-1 for a scalar): a mirror flips the sign of the
  * component normal to it. */
+static int nozzle_row(const oracle_sim *s, int y) { return y >= s->ny0 && y < s->ny1; }
+
 static double field_at(const oracle_sim *s, const double *fld, int x, int y, int z, int comp)
 {
   double sign = 1.0;
   z = wrap(z, s->nz);
-  if (s->wall_y) {
+  if (s->wall_y == 2) {
+    if (y < 0) y = 0;                 /* outlets: zero gradient */
+    else if (y >= s->ny) y = s->ny - 1;
+  } else if (s->wall_y) {
     if (y < 0) { y = -1 - y; if (comp == 1) sign = -sign; }
     else if (y >= s->ny) { y = 2 * s->ny - 1 - y; if (comp == 1) sign = -sign; }
   } else {
     y = wrap(y, s->ny);
   }
-  if (s->wall_x == 1) {
+  if (s->wall_x == 3) {
+    /* jets: zero gradient beyond a nozzle, the mirror beyond a free-slip wall */
+    if (x < 0) {
+      if (nozzle_row(s, y)) x = 0;
+      else { x = -1 - x; if (comp == 0) sign = -sign; }
+    } else if (x >= s->nx) {
+      if (nozzle_row(s, y)) x = s->nx - 1;
+      else { x = 2 * s->nx - 1 - x; if (comp == 0) sign = -sign; }
+    }
+  } else if (s->wall_x == 1) {
     if (x < 0) { x = -1 - x; if (comp == 0) sign = -sign; }
     else if (x >= s->nx) { x = 2 * s->nx - 1 - x; if (comp == 0) sign = -sign; }
   } else if (s->wall_x == 2) {
@@ -600,8 +631,10 @@ static double g_get(const void *ctx, int x, int y, int z)
   const g_ctx *c = (const g_ctx *)ctx;
   const oracle_sim *s = c->s;
   if (!s->wall_x) x = wrap(x, s->nx);
-  /* free-slip y walls: every G_k is even under the y mirror (d_y Phi_y is) */
-  if (s->wall_y) y = y < 0 ? -1 - y : (y >= s->ny ? 2 * s->ny - 1 - y : y);
+  /* free-slip y walls: every G_k is even under the y mirror (d_y Phi_y is);
+   * outlets: the boundary node's G (zero gradient) */
+  if (s->wall_y == 2) y = y < 0 ? 0 : (y >= s->ny ? s->ny - 1 : y);
+  else if (s->wall_y) y = y < 0 ? -1 - y : (y >= s->ny ? 2 * s->ny - 1 - y : y);
   return s->G[gidx(s, c->k, x, wrap(y, s->ny), wrap(z, s->nz))];
 }
 
@@ -621,11 +654,12 @@ static void compute_nonlocal(oracle_sim *s)
           double omega = field_at(s, s->om, x, y, z, -1);
           s->G[gidx(s, k, x, y, z)] = (1.0 / omega - 0.5) * iso_deriv(node_field_get, &phi, x, y, z, k);
         }
-  /* open x ends: G beyond the boundary is the boundary node's (zero gradient) */
-  if (s->wall_x == 2)
+  /* open x ends and nozzles: G beyond the boundary is the boundary node's (zero gradient) */
+  if (s->wall_x >= 2)
     for (int k = 0; k < 3; ++k)
       for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y) {
+          if (s->wall_x == 3 && !nozzle_row(s, y)) continue;
           s->G[gidx(s, k, -1, y, z)] = s->G[gidx(s, k, 0, y, z)];
           s->G[gidx(s, k, nx, y, z)] = s->G[gidx(s, k, nx - 1, y, z)];
         }
@@ -824,7 +858,9 @@ static void stream(oracle_sim *s)
 {
   const int nx = s->nx, ny = s->ny, nz = s->nz;
   const int L = s->M + 2;
-#pragma omp parallel for schedule(static) if (s->n >= 512)
+  /* every destination slot is written by exactly one source: any split of the
+   * loops over threads is free of races */
+#pragma omp parallel for collapse(2) schedule(static) if (s->n >= 512)
   for (int z = 0; z < nz; ++z)
     for (int l = 0; l < L; ++l) {
       if (l == s->M - 1 && !s->keep_slaved) continue;
@@ -835,7 +871,18 @@ static void stream(oracle_sim *s)
             double v = POP(s, s->post, l, i, src);
             int xd = x + cvel(i, 0);
             int yd = y + cvel(i, 1);
-            if (s->wall_x == 2 && (xd < 0 || xd >= nx)) {
+            if (s->wall_y == 2 && (yd < 0 || yd >= ny)) {
+              /* outlets: leaves the domain */
+            } else if (s->wall_x == 3 && (xd < 0 || xd >= nx)) {
+              /* jets: reflected specularly (c_x reversed, at the same x) into a
+               * row beside the nozzles (a free-slip wall); into a nozzle row it
+               * leaves the domain (the inlet supplies what enters there) */
+              if (!nozzle_row(s, yd)) {
+                int ix = i - 9 * 2 * cvel(i, 0);
+                long dst = node_index(s, x, yd, wrap(z + cvel(i, 2), nz));
+                POP(s, s->pop, l, ix, dst) = v;
+              }
+            } else if (s->wall_x == 2 && (xd < 0 || xd >= nx)) {
               /* open x ends: leaves the domain */
             } else if (s->wall_x && (xd < 0 || xd >= nx)) {
               POP(s, s->pop, l, opposite(i), src) = v;      /* half-way bounce-back */
@@ -851,6 +898,36 @@ static void stream(oracle_sim *s)
             }
           }
     }
+  if (s->wall_x == 3) {
+    /* outlets at the y ends: what enters a boundary row from beyond comes from a
+     * ghost row holding the boundary row's post-collision state (zero gradient;
+     * beyond an x face too, the nearest boundary node's) */
+    for (int z = 0; z < nz; ++z)
+      for (int l = 0; l < L; ++l) {
+        if (l == s->M - 1 && !s->keep_slaved) continue;
+        for (int i = 0; i < Q; ++i) {
+          const int cy = cvel(i, 1);
+          if (!cy) continue;
+          const int yb = cy > 0 ? 0 : ny - 1;
+          for (int x = 0; x < nx; ++x) {
+            int xs = x - cvel(i, 0);
+            xs = xs < 0 ? 0 : (xs >= nx ? nx - 1 : xs);
+            POP(s, s->pop, l, i, node_index(s, x, yb, z)) =
+                POP(s, s->post, l, i, node_index(s, xs, yb, wrap(z - cvel(i, 2), nz)));
+          }
+        }
+      }
+    /* nozzles: what enters from beyond is the inlet equilibrium of that jet */
+    for (int z = 0; z < nz; ++z)
+      for (int l = 0; l < L; ++l) {
+        if (l == s->M - 1 && !s->keep_slaved) continue;
+        for (int i = 0; i < Q; ++i)
+          for (int y = s->ny0; y < s->ny1; ++y) {
+            if (cvel(i, 0) > 0) POP(s, s->pop, l, i, node_index(s, 0, y, z)) = s->fin[l][i];
+            if (cvel(i, 0) < 0) POP(s, s->pop, l, i, node_index(s, nx - 1, y, z)) = s->fin2[l][i];
+          }
+      }
+  }
   if (s->wall_x == 2) {
     /* open x ends: what enters node 0 from outside is the inlet equilibrium; what
      * enters node nx-1 from outside comes from a ghost beyond it that holds the

@@ -41,7 +41,11 @@ typedef struct {
   int32_t nx, ny, nz;   /* lattice size                                                 */
   int32_t wall_x;       /* 0 periodic in x; 1 half-way bounce-back walls at both x ends;
                            2 open x ends: equilibrium inlet at x = 0 (fields `inlet`),
-                           zero-gradient outlet at x = nx - 1                          */
+                           zero-gradient outlet at x = nx - 1;
+                           3 opposed jets (Sec. 4.3): on both x faces the rows
+                           nozzle_y0 <= y < nozzle_y1 are equilibrium inlets (`inlet`
+                           at x = 0, `inlet_right` at x = nx - 1), the other rows
+                           free-slip walls (specular reflection); needs wall_y = 2 */
   int32_t keep_slaved;  /* 1: store and evolve the slaved species' lattice literally    */
   int32_t debug_flags;  /* ORACLE_DROP_* planted mistakes (tests only), else 0          */
   int32_t weak;         /* 1: weak coupling (Sec. 3.5.1): all M species lattices evolve
@@ -58,8 +62,12 @@ typedef struct {
                                s_mu (M), s_lam (M), s_D, T_ref: mu_a (T/T_ref)^s_mu,a,
                                lambda_a (T/T_ref)^s_lam,a, D_ab (T/T_ref)^s_D          */
   int32_t wall_y;           /* 1: free-slip walls at both y ends (specular reflection);
-                               needs ny >= 2 and wall_x 0 or 1                           */
+                               needs ny >= 2 and wall_x 0 or 1. 2: zero-gradient outlets
+                               at both y ends (what enters from beyond is the boundary
+                               node's post-collision state); only with wall_x = 3       */
   int32_t reserved2;
+  const double *inlet_right; /* wall_x = 3: [M+5] fields of the jet entering at x = nx - 1 */
+  int32_t nozzle_y0, nozzle_y1; /* wall_x = 3: nozzle rows, 1 <= y0 < y1 <= ny - 1          */
 } oracle_params;
 
 typedef struct oracle_sim oracle_sim;

@@ -40,6 +40,7 @@ class _Params(C.Structure):
         ("lam", C.POINTER(C.c_double)), ("cv_coef", C.POINTER(C.c_double)),
         ("inlet", C.POINTER(C.c_double)), ("transport_exp", C.POINTER(C.c_double)),
         ("wall_y", C.c_int32), ("reserved2", C.c_int32),
+        ("inlet_right", C.POINTER(C.c_double)), ("nozzle_y0", C.c_int32), ("nozzle_y1", C.c_int32),
     ]
 
 
@@ -183,12 +184,16 @@ class OracleSim:
         inl = None if inl is None else _f64(inl).reshape(self.M + 5)
         tex = params.get("transport_exp")
         tex = None if tex is None else _f64(tex).reshape(2 * self.M + 2)
-        self._arrays += [a for a in (cvc, inl, tex) if a is not None]
+        inr = params.get("inlet_right")
+        inr = None if inr is None else _f64(inr).reshape(self.M + 5)
+        self._arrays += [a for a in (cvc, inl, tex, inr) if a is not None]
+        noz = params.get("nozzle", (0, 0))
         p = _Params(self.M, self.nx, self.ny, self.nz, int(params.get("wall_x", 0)),
                     int(keep_slaved), int(debug_flags), int(params.get("weak", 0)),
                     *[_dp(a) for a in self._arrays[:5]],
                     *[_dp(a) if a is not None else None for a in (cvc, inl, tex)],
-                    int(params.get("wall_y", 0)), 0)
+                    int(params.get("wall_y", 0)), 0, _dp(inr) if inr is not None else None,
+                    int(noz[0]), int(noz[1]))
         h = C.c_void_p()
         rc = lib().oracle_create(C.byref(p), C.byref(h))
         if rc != 0:
