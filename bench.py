@@ -37,7 +37,7 @@ RECIPE_DEPARTURES = ("velocity perturbation band-limited (8 random-phase Fourier
 PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = ["lattice.hpp", "node_ops.hpp", "device_ops.hpp", "kernels.hpp", "inst_fp64.hip",
                   "inst_fp32_fp64.hip", "inst_weak.hip", "inst_cvt.hip", "inst_weak_cvt.hip", "inst_fp32.hip",
-                  "inst_fp16.hip", "inst_bf16.hip"]
+                  "inst_fp16.hip", "inst_bf16.hip", "inst_jets.hip"]
 
 
 def record_fields(M: int, weak: bool = False, cvt: bool = False) -> int:

@@ -80,7 +80,13 @@ typedef struct {
                           values), both as in the opposed jets of Sec. 4.3; open ends
                           are compiled for MCLBM_FP64 and MCLBM_FP32 (else
                           MCLBM_EUNSUPPORTED), with either coupling and either kind of
-                          properties. z is always periodic; y is periodic unless wall_y */
+                          properties. 3: the opposed jets of Sec. 4.3: on both x faces
+                          the rows nozzle_y0 <= y < nozzle_y1 are equilibrium inlets
+                          (`inlet` at x = 0, `inlet_right` at x = nx - 1) and the other
+                          rows free-slip walls (specular reflection); needs wall_y = 2,
+                          strong coupling, constant properties, MCLBM_FP64 or MCLBM_FP32
+                          (else MCLBM_EUNSUPPORTED). z is always periodic; y is
+                          periodic unless wall_y */
   int32_t precision;   /* MCLBM_FP64 .. MCLBM_BF16                                    */
   int32_t weak;        /* 0: strong coupling (Sec. 3.5.2): species M is slaved to the
                           momentum lattice (eqs rhoMATCH, uMATCH) and not stored.
@@ -91,10 +97,13 @@ typedef struct {
                           MCLBM_FP16 (else MCLBM_EUNSUPPORTED); all tubes of a batch
                           agree                                                     */
   int32_t wall_y;      /* 0: periodic in y; 1: free-slip walls at both y ends (half-way,
-                          specular reflection: the lateral walls of the opposed jets,
-                          Sec. 4.3), with periodic or walled x ends, either coupling and
-                          either kind of properties; MCLBM_FP64 and MCLBM_FP32 (else
-                          MCLBM_EUNSUPPORTED); all tubes of a batch agree           */
+                          specular reflection), with periodic or walled x ends, either
+                          coupling and either kind of properties; MCLBM_FP64 and
+                          MCLBM_FP32 (else MCLBM_EUNSUPPORTED). 2: zero-gradient outlets
+                          at both y ends (what enters comes from a ghost row holding
+                          the boundary row's post-collision state: the outlets of the
+                          opposed jets, Sec. 4.3), only with wall_x = 3. All tubes of
+                          a batch agree                                              */
   const double *molar_mass;  /* [M] molar masses m_a > 0                              */
   const double *cv;          /* [M] mass-based specific heats C_{a,v} > 0             */
   const double *D;           /* [M*M] symmetric binary diffusivities D_ab > 0, row major,
@@ -118,6 +127,10 @@ typedef struct {
                                 local T (the given mu, lambda, D are the values at
                                 T_ref); Wilke's phi from the viscosities at T. Same
                                 support and batch rule as cv_coef                      */
+  const double *inlet_right; /* wall_x = 3: [M + 5] fields of the jet entering at x = nx - 1
+                                (X_1..X_M, p, T, u_x, u_y, u_z); else ignored           */
+  int32_t nozzle_y0, nozzle_y1; /* wall_x = 3: the nozzle rows, 1 <= nozzle_y0 < nozzle_y1
+                                <= ny - 1; else ignored                                 */
 } mclbm_params;
 
 /* Device workspace bytes a context with these parameters needs (0 on bad input). */

@@ -654,12 +654,13 @@ static void compute_nonlocal(oracle_sim *s)
           double omega = field_at(s, s->om, x, y, z, -1);
           s->G[gidx(s, k, x, y, z)] = (1.0 / omega - 0.5) * iso_deriv(node_field_get, &phi, x, y, z, k);
         }
-  /* open x ends and nozzles: G beyond the boundary is the boundary node's (zero gradient) */
+  /* open x ends and the jets' x faces: G beyond the boundary is the boundary
+   * node's (zero gradient at a nozzle; beside it, the even mirror image that a
+   * free-slip wall gives away from the nozzle's edge, taken on every wall row) */
   if (s->wall_x >= 2)
     for (int k = 0; k < 3; ++k)
       for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y) {
-          if (s->wall_x == 3 && !nozzle_row(s, y)) continue;
           s->G[gidx(s, k, -1, y, z)] = s->G[gidx(s, k, 0, y, z)];
           s->G[gidx(s, k, nx, y, z)] = s->G[gidx(s, k, nx - 1, y, z)];
         }

@@ -179,6 +179,17 @@ __global__ __launch_bounds__(BLOCK) void k_open_fix(const Params<R>* __restrict_
   if (w.node < Pt.n) open_fix_node<S, R, Lat<M, WEAK>::L>(Pt, dst + pop_stride<M, WEAK>() * w.base, w.node, step_of(sn));
 }
 
+// Opposed jets: rewrite what enters the outlet rows and the nozzles after the
+// collision (a launch over all nodes; only boundary rows and faces write).
+template <typename S, typename R, int M, bool WEAK>
+__global__ __launch_bounds__(BLOCK) void k_jets_fix(const Params<R>* __restrict__ P, Launch Ln, S* __restrict__ dst,
+                                                    StepNo sn)
+{
+  const Where w = locate(Ln);
+  const Params<R>& Pt = P[w.t];
+  if (w.node < Pt.n) jets_fix_node<S, R, Lat<M, WEAK>::L>(Pt, dst + pop_stride<M, WEAK>() * w.base, w.node, step_of(sn));
+}
+
 template <typename T>
 __device__ inline T* seg(T* p, int64_t off) { return p ? p + off : p; }
 
@@ -409,6 +420,10 @@ Ops make_ops()
     o.open_fix = [](const void* P, const Launch& ln, void* dst, StepNo sn, unsigned grid, hipStream_t st) {
       hipLaunchKernelGGL((k_open_fix<S, R, M, WEAK>), dim3(grid), dim3(BLOCK), 0, st, (const Params<R>*)P, ln, (S*)dst, sn);
     };
+  } else if constexpr (xbc(W) == BC_JETS) {
+    o.open_fix = [](const void* P, const Launch& ln, void* dst, StepNo sn, unsigned grid, hipStream_t st) {
+      hipLaunchKernelGGL((k_jets_fix<S, R, M, WEAK>), dim3(grid), dim3(BLOCK), 0, st, (const Params<R>*)P, ln, (S*)dst, sn);
+    };
   }
   return o;
 }
@@ -450,6 +465,19 @@ bool pick_m_open(int M, Ops& o)
   }
 }
 
+// the opposed jets (nozzle faces in x, outlets in y)
+template <typename S, typename R, typename Rec, bool WEAK = false, bool CVT = false>
+bool pick_m_jets(int M, Ops& o)
+{
+  constexpr int J = BC_JETS | BC_YOUT;
+  switch (M) {
+    case 2: o = make_ops<S, R, Rec, 2, J, WEAK, CVT>(); return true;
+    case 3: o = make_ops<S, R, Rec, 3, J, WEAK, CVT>(); return true;
+    case 4: o = make_ops<S, R, Rec, 4, J, WEAK, CVT>(); return true;
+    default: return false;
+  }
+}
+
 // every boundary set: walls = the x mode (0 periodic, 1 walls, 2 open) plus 4
 // for free-slip y walls (not with open x ends)
 template <typename S, typename R, typename Rec, bool WEAK, bool CVT>
@@ -464,7 +492,8 @@ bool pick_m_any(int M, int walls, Ops& o)
 }  // namespace kern
 
 // One entry point per instantiated (storage, arithmetic) pair. walls: the x
-// boundary (0 periodic, 1 walls, 2 open) plus 4 for free-slip y walls; weak: 1
+// boundary (0 periodic, 1 walls, 2 open, 3 opposed jets) plus 4 for free-slip y
+// walls or 8 for outlets at the y ends (with the jets only); weak: 1
 // for weak coupling; cvt: 1 for temperature-dependent specific heats and
 // transport. Open ends, free-slip walls, weak coupling and the temperature-
 // dependent kernels are compiled for FP64 and FP32 storage with FP64

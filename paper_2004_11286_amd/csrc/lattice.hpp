@@ -73,7 +73,8 @@ __host__ __device__ constexpr double w13(int i) { return w13_1d(cx(i)) * w13_1d(
 template <typename R>
 struct Params {
   int32_t M, nx, ny, nz;
-  int32_t wall_x, trn, pad1, pad2;   // trn: transport exponents given (R19)
+  int32_t wall_x, trn, noz0, noz1;   // trn: transport exponents given (R19); opposed jets:
+                                     // nozzle rows noz0 <= y < noz1 of both x faces
   int64_t n;
   R m[MAXM], inv_m[MAXM], cv[MAXM], cp[MAXM];
   R mu[MAXM], lam[MAXM], inv_lam[MAXM];
@@ -85,7 +86,8 @@ struct Params {
   R ref0[MAXL];           // sum_i f_ref (zeroth moment)
   R ref2[MAXL];           // sum_i f_ref c_ia^2 (diagonal second moment, isotropic)
   R scale[MAXL], inv_scale[MAXL];
-  R inl[MAXL][Q];         // open x ends: inlet equilibrium minus f_ref, per stored lattice
+  R inl[MAXL][Q];         // open x ends and the jet at x = 0: inlet equilibrium minus f_ref, per stored lattice
+  R inl2[MAXL][Q];        // opposed jets: the jet at x = nx - 1
   R absent_tol;           // |rho_a| <= absent_tol * rho: species absent, V_a = 0
 };
 

@@ -203,7 +203,9 @@ struct TubeHost {
   HostSpecies hs{};
   double ref[MAXL][Q] = {};
   double ref0[MAXL] = {}, ref2[MAXL] = {}, scale[MAXL] = {};
-  double inlet[MAXM + 5] = {};   // open x ends: X (M), p, T, u (3)
+  double inlet[MAXM + 5] = {};   // open x ends and the jet at x = 0: X (M), p, T, u (3)
+  double inlet2[MAXM + 5] = {};  // opposed jets: the jet at x = nx - 1
+  int noz0 = 0, noz1 = 0;        // opposed jets: nozzle rows
 };
 
 }  // namespace
@@ -331,30 +333,50 @@ int validate_one(const mclbm_params* p, std::string& err)
     err = "nx*ny*nz times the element size must be below 2^32 bytes";
     return MCLBM_EARG;
   }
-  if (p->wall_x < 0 || p->wall_x > 2) { err = "wall_x must be 0, 1 or 2"; return MCLBM_EARG; }
-  if (p->wall_x == 2) {
-    if (!p->inlet) { err = "open x ends need the inlet fields"; return MCLBM_EARG; }
+  if (p->wall_x < 0 || p->wall_x > 3) { err = "wall_x must be 0, 1, 2 or 3"; return MCLBM_EARG; }
+  auto inlet_ok = [&](const double* in) {
     double xs = 0.0;
-    bool ok = p->inlet[p->M] > 0 && p->inlet[p->M + 1] > 0;
-    for (int k = 0; k < p->M + 5; ++k) ok = ok && std::isfinite(p->inlet[k]);
+    bool ok = in[p->M] > 0 && in[p->M + 1] > 0;
+    for (int k = 0; k < p->M + 5; ++k) ok = ok && std::isfinite(in[k]);
     for (int a = 0; a < p->M; ++a) {
-      ok = ok && p->inlet[a] >= 0;
-      xs += p->inlet[a];
+      ok = ok && in[a] >= 0;
+      xs += in[a];
     }
-    if (!ok || std::fabs(xs - 1.0) > 1e-12) {
+    return ok && std::fabs(xs - 1.0) <= 1e-12;
+  };
+  if (p->wall_x >= 2) {
+    if (!p->inlet || (p->wall_x == 3 && !p->inlet_right)) {
+      err = "open x ends need the inlet fields, the opposed jets both inlets";
+      return MCLBM_EARG;
+    }
+    if (!inlet_ok(p->inlet) || (p->wall_x == 3 && !inlet_ok(p->inlet_right))) {
       err = "inlet: mole fractions must be non-negative and sum to 1, p and T positive";
       return MCLBM_EARG;
     }
     if (p->precision != MCLBM_FP64 && p->precision != MCLBM_FP32) {
-      err = "open x ends are compiled for MCLBM_FP64 and MCLBM_FP32 only";
+      err = "open x ends and the opposed jets are compiled for MCLBM_FP64 and MCLBM_FP32 only";
+      return MCLBM_EUNSUPPORTED;
+    }
+  }
+  if ((p->wall_x == 3) != (p->wall_y == 2)) {
+    err = "the opposed jets (wall_x = 3) and the y outlets (wall_y = 2) go together";
+    return MCLBM_EARG;
+  }
+  if (p->wall_x == 3) {
+    if (!(p->nozzle_y0 >= 1 && p->nozzle_y0 < p->nozzle_y1 && p->nozzle_y1 <= p->ny - 1)) {
+      err = "the nozzle rows must satisfy 1 <= nozzle_y0 < nozzle_y1 <= ny - 1";
+      return MCLBM_EARG;
+    }
+    if (p->weak || p->cv_coef || p->transport_exp) {
+      err = "the opposed jets are compiled for strong coupling with constant properties";
       return MCLBM_EUNSUPPORTED;
     }
   }
   if (p->wall_x && p->nx < 2) { err = "walls need nx >= 2"; return MCLBM_EARG; }
   if (p->precision < MCLBM_FP64 || p->precision > MCLBM_BF16) { err = "unknown precision"; return MCLBM_EARG; }
   if (p->weak != 0 && p->weak != 1) { err = "weak must be 0 or 1"; return MCLBM_EARG; }
-  if (p->wall_y != 0 && p->wall_y != 1) { err = "wall_y must be 0 or 1"; return MCLBM_EARG; }
-  if (p->wall_y) {
+  if (p->wall_y < 0 || p->wall_y > 2) { err = "wall_y must be 0, 1 or 2"; return MCLBM_EARG; }
+  if (p->wall_y == 1) {
     if (p->ny < 2) { err = "free-slip y walls need ny >= 2"; return MCLBM_EARG; }
     if (p->wall_x == 2 || (p->precision != MCLBM_FP64 && p->precision != MCLBM_FP32)) {
       err = "free-slip y walls are compiled for periodic or walled x ends, MCLBM_FP64 and MCLBM_FP32 only";
@@ -478,18 +500,20 @@ int push_params(mclbm_ctx* c)
   for (int t = 0; t < c->ntubes; ++t) {
     const TubeHost& th = c->tubes[t];
     fill_params<double>(c->hPd[t], th.hs, th.nx, th.ny, th.nz, c->wall_x, c->L, th.ref, th.ref0, th.ref2, th.scale,
-                        tol);
+                        tol, th.noz0, th.noz1);
     fill_params<float>(c->hPf[t], th.hs, th.nx, th.ny, th.nz, c->wall_x, c->L, th.ref, th.ref0, th.ref2, th.scale,
-                       tol);
-    if (c->wall_x == 2) {
-      // the inlet equilibrium of every stored lattice, as a deviation from f_ref:
-      // the initialisation of one node (n = 1, unit scale) at the inlet fields
+                       tol, th.noz0, th.noz1);
+    // the inlet equilibria of every stored lattice, as deviations from f_ref: the
+    // initialisation of one node (n = 1, unit scale) at the inlet fields (open x
+    // ends: one inlet; opposed jets: one per x face)
+    const int sides = c->wall_x == 3 ? 2 : (c->wall_x == 2 ? 1 : 0);
+    for (int side = 0; side < sides; ++side) {
       Params<double> P1 = c->hPd[t];
       P1.n = 1;
       for (int l = 0; l < MAXL; ++l) P1.scale[l] = 1.0;
       double dev[MAXL * Q] = {};
       const int M = c->M;
-      const double* in = th.inlet;
+      const double* in = side ? th.inlet2 : th.inlet;
       int bad = 1;
       switch (M) {
         case 2: bad = inlet_node<2>(c->weak, c->cvt, P1, in, dev); break;
@@ -500,8 +524,8 @@ int push_params(mclbm_ctx* c)
       if (bad) return fail(c, MCLBM_ESTATE, "infeasible inlet state (R_a T + u^2 >= 1)");
       for (int l = 0; l < c->L; ++l)
         for (int i = 0; i < Q; ++i) {
-          c->hPd[t].inl[l][i] = dev[l * Q + i];
-          c->hPf[t].inl[l][i] = (float)dev[l * Q + i];
+          (side ? c->hPd[t].inl2 : c->hPd[t].inl)[l][i] = dev[l * Q + i];
+          (side ? c->hPf[t].inl2 : c->hPf[t].inl)[l][i] = (float)dev[l * Q + i];
         }
     }
   }
@@ -868,8 +892,13 @@ extern "C" int mclbm_batch_create(const mclbm_params* tp, int32_t ntubes, void* 
     th.hs.s_D = p->transport_exp ? p->transport_exp[2 * p->M] : 0.0;
     th.hs.T_ref = p->transport_exp ? p->transport_exp[2 * p->M + 1] : 1.0;
     th.hs.trn = p->transport_exp != nullptr;
-    if (p->wall_x == 2)
+    if (p->wall_x >= 2)
       for (int k = 0; k < p->M + 5; ++k) th.inlet[k] = p->inlet[k];
+    if (p->wall_x == 3) {
+      for (int k = 0; k < p->M + 5; ++k) th.inlet2[k] = p->inlet_right[k];
+      th.noz0 = p->nozzle_y0;
+      th.noz1 = p->nozzle_y1;
+    }
   }
   if (!pick_ops(c->precision, c->M, c->wall_x | (c->wall_y << 2), c->weak, c->cvt, c->ops)) {
     delete c;

@@ -248,6 +248,7 @@ struct Nbr {
   uint32_t x[3], y[3], z[3];  // index contributions for c = -1, 0, +1
   bool lo, hi;                // node touches the x = 0 / x = nx-1 wall
   bool ylo, yhi;              // node touches the y = 0 / y = ny-1 wall
+  uint32_t yy;                // the node's y
 };
 
 template <typename R>
@@ -275,19 +276,31 @@ __host__ __device__ __forceinline__ Nbr neighbours(const Params<R>& P, int64_t n
   b.hi = x == nx - 1;
   b.ylo = y == 0;
   b.yhi = y == ny - 1;
+  b.yy = y;
   return b;
 }
 
 // Boundary kinds, one integer: the x ends (BC & 3) are periodic, half-way
-// bounce-back walls (Sec. 4.2) or open (equilibrium inlet at x = 0, zero-gradient
-// outlet at x = nx - 1); BC_YSLIP adds free-slip walls at both y ends (specular
-// reflection; otherwise y is periodic).
-enum { BC_PERIODIC = 0, BC_WALLS = 1, BC_OPEN = 2, BC_YSLIP = 4 };
+// bounce-back walls (Sec. 4.2), open (equilibrium inlet at x = 0, zero-gradient
+// outlet at x = nx - 1), or the opposed jets of Sec. 4.3 (on both x faces the
+// nozzle rows are equilibrium inlets and the other rows free-slip walls);
+// BC_YSLIP adds free-slip walls at both y ends (specular reflection) and BC_YOUT
+// zero-gradient outlets at both y ends (the jets' outlets); otherwise y is periodic.
+enum { BC_PERIODIC = 0, BC_WALLS = 1, BC_OPEN = 2, BC_JETS = 3, BC_YSLIP = 4, BC_YOUT = 8 };
 __host__ __device__ constexpr int xbc(int BC) { return BC & 3; }
 
+// A nozzle row of the opposed jets.
+template <typename R>
+__host__ __device__ __forceinline__ bool nozzle_row(const Params<R>& P, int y)
+{
+  return y >= P.noz0 && y < P.noz1;
+}
+
 // Stencil neighbour index: beyond an x wall the ghost node mirrors the boundary
-// node; beyond an open end it holds the boundary node's values (zero gradient);
-// beyond a free-slip y wall it mirrors the boundary node.
+// node; beyond an open end or a nozzle it holds the boundary node's values (zero
+// gradient); beyond a free-slip y wall it mirrors the boundary node, beyond an
+// outlet it holds its values. Mirror and zero gradient read the same node; they
+// differ in the sign of the field's normal component (is_ghost, is_ghost_y).
 template <int BC>
 __host__ __device__ __forceinline__ uint32_t stencil_index(const Nbr& b, int ci, int cj, int ck)
 {
@@ -297,17 +310,26 @@ __host__ __device__ __forceinline__ uint32_t stencil_index(const Nbr& b, int ci,
     if (ci > 0 && b.hi) xi = b.x[1];
   }
   uint32_t yi = b.y[cj + 1];
-  if (BC & BC_YSLIP) {
+  if (BC & (BC_YSLIP | BC_YOUT)) {
     if (cj < 0 && b.ylo) yi = b.y[1];
     if (cj > 0 && b.yhi) yi = b.y[1];
   }
   return xi + yi + b.z[ck + 1];
 }
 
-// A mirrored wall ghost in x (odd fields change sign there; not at open ends).
-template <int BC>
-__host__ __device__ __forceinline__ bool is_ghost(const Nbr& b, int ci)
+// A mirrored wall ghost in x (odd fields change sign there; not at open ends or
+// nozzles). With the jets, the ghost of direction (ci, cj) lies in row y + cj
+// (the boundary row beyond an outlet): a wall row beside the nozzles mirrors.
+template <int BC, typename R>
+__host__ __device__ __forceinline__ bool is_ghost(const Params<R>& P, const Nbr& b, int ci, int cj)
 {
+  if (xbc(BC) == BC_JETS) {
+    if (!((ci < 0 && b.lo) || (ci > 0 && b.hi))) return false;
+    int yg = (int)b.yy + cj;
+    if (yg < 0) yg = 0;
+    if (yg >= P.ny) yg = P.ny - 1;
+    return !nozzle_row(P, yg);
+  }
   return xbc(BC) == BC_WALLS && ((ci < 0 && b.lo) || (ci > 0 && b.hi));
 }
 
@@ -553,7 +575,7 @@ __host__ __device__ __forceinline__ void gfield_node(const Params<double>& P, co
     const R w3 = R(3.0 * w13(i));
     if (cx(i)) {
       R v = *at32(rec + (size_t)REC_PHIX * n, nb);
-      if (is_ghost<BC>(b, cx(i))) v = -v;           // Phi_x is odd under the wall mirror
+      if (is_ghost<BC>(P, b, cx(i), cy(i))) v = -v; // Phi_x is odd under the wall mirror
       dphi[0] += cx(i) > 0 ? w3 * v : -(w3 * v);
     }
     if (cy(i)) {
@@ -648,9 +670,18 @@ __host__ __device__ __forceinline__ void push(const Params<R>& P, S* __restrict_
                                      int64_t node, S v)
 {
   const size_t n = (size_t)P.n;
-  if (xbc(BC) == BC_WALLS && ((cx(i) < 0 && b.lo) || (cx(i) > 0 && b.hi))) {
+  const bool xout = (cx(i) < 0 && b.lo) || (cx(i) > 0 && b.hi);
+  const bool yout = (cy(i) < 0 && b.ylo) || (cy(i) > 0 && b.yhi);
+  if (xbc(BC) == BC_WALLS && xout) {
     dst[(size_t)(l * Q + opp(i)) * n + node] = v;    // half-way bounce-back
-  } else if ((BC & BC_YSLIP) && ((cy(i) < 0 && b.ylo) || (cy(i) > 0 && b.yhi))) {
+  } else if (xbc(BC) == BC_JETS && xout && !((BC & BC_YOUT) && yout) &&
+             !nozzle_row(P, (int)b.yy + cy(i))) {
+    // beside a nozzle: free-slip wall, specular reflection (c_x reversed) at the
+    // node's own x; through a nozzle the value wraps into a slot that
+    // jets_fix_node overwrites with the inlet equilibrium
+    const int64_t d = (int64_t)b.x[1] + b.y[cy(i) + 1] + b.z[cz(i) + 1];
+    dst[(size_t)(l * Q + i - 18 * cx(i)) * n + d] = v;
+  } else if ((BC & BC_YSLIP) && yout) {
     // free-slip y wall: specular reflection (c_y reversed) at the node's own y
     const int64_t d = (int64_t)b.x[cx(i) + 1] + b.y[1] + b.z[cz(i) + 1];
     dst[(size_t)(l * Q + i - 6 * cy(i)) * n + d] = v;
@@ -673,6 +704,51 @@ __host__ __device__ __forceinline__ void load_lattice(const S* __restrict__ lat,
 #pragma unroll
   for (int i = 0; i < Q; ++i) v[i] = stream_load(at32(lat + (size_t)i * n, node));
   lattice_barrier();
+}
+
+// Opposed jets, after the collision has streamed periodically across the x faces'
+// nozzle rows and across the y ends into dst (the wrapped values are exactly the
+// ones that leave the domain there): what enters a boundary row (y = 0: c_y > 0;
+// y = ny - 1: c_y < 0) comes from a ghost row holding the boundary row's
+// post-collision state, shifted like any push (beyond an x face too, the nearest
+// boundary node's), i.e. the value node (clamp(x - c_x), y_b, z - c_z) pushed into
+// row 1 (or ny - 2); what enters a nozzle row's boundary node through its face is
+// the inlet equilibrium of that jet. The slots read (rows 1 and ny - 2, directions
+// entering those rows from the boundary rows) are never written here: the nodes
+// of a launch do not interfere (1 <= noz0 < noz1 <= ny - 1, so ny >= 3).
+template <typename S, typename R, int L>
+__host__ __device__ __forceinline__ void jets_fix_node(const Params<R>& P, S* __restrict__ dst, int64_t node,
+                                                       uint32_t step)
+{
+  const size_t n = (size_t)P.n;
+  const int nx = P.nx, ny = P.ny;
+  const int x = (int)((uint32_t)node % (uint32_t)nx);
+  const int y = (int)(((uint32_t)node / (uint32_t)nx) % (uint32_t)ny);
+  const int64_t row = node - x;                      // node index of (0, y, z)
+  if (y == 0 || y == ny - 1) {
+    const int cin = y == 0 ? 1 : -1;                 // c_y of the directions entering
+    const int64_t inner = row + (int64_t)cin * nx;   // (0, y + cin, z)
+#pragma unroll
+    for (int l = 0; l < L; ++l)
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        if (cy(i) != cin) continue;
+        int xs = x - cx(i);
+        xs = xs < 0 ? 0 : (xs >= nx ? nx - 1 : xs);
+        dst[(size_t)(l * Q + i) * n + node] = dst[(size_t)(l * Q + i) * n + inner + xs + cx(i)];
+      }
+  }
+  if (nozzle_row(P, y) && (x == 0 || x == nx - 1)) {
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+      Rng rng(node, l + 16, step);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        if (x == 0 && cx(i) > 0) dst[(size_t)(l * Q + i) * n + node] = to_store<S, R>(P, l, P.inl[l][i], rng);
+        if (x == nx - 1 && cx(i) < 0) dst[(size_t)(l * Q + i) * n + node] = to_store<S, R>(P, l, P.inl2[l][i], rng);
+      }
+    }
+  }
 }
 
 // Open x ends, after the collision has streamed periodically into dst: what

@@ -92,7 +92,7 @@ inline void reference_tables(const HostSpecies& h, int ns, const RefState& rs, d
 template <typename R>
 inline void fill_params(Params<R>& P, const HostSpecies& h, int nx, int ny, int nz, int wall_x, int L,
                         const double ref[MAXL][Q], const double ref0[MAXL], const double ref2[MAXL],
-                        const double scale[MAXL], double absent_tol)
+                        const double scale[MAXL], double absent_tol, int noz0 = 0, int noz1 = 0)
 {
   std::memset(&P, 0, sizeof(P));
   P.M = h.M;
@@ -100,6 +100,8 @@ inline void fill_params(Params<R>& P, const HostSpecies& h, int nx, int ny, int 
   P.ny = ny;
   P.nz = nz;
   P.wall_x = wall_x;
+  P.noz0 = noz0;
+  P.noz1 = noz1;
   P.n = (int64_t)nx * ny * nz;
   for (int a = 0; a < h.M; ++a) {
     P.m[a] = R(h.m[a]);

@@ -64,6 +64,7 @@ class mclbm_params(C.Structure):
         ("D", C.POINTER(C.c_double)), ("mu", C.POINTER(C.c_double)),
         ("lam", C.POINTER(C.c_double)), ("cv_coef", C.POINTER(C.c_double)),
         ("inlet", C.POINTER(C.c_double)), ("transport_exp", C.POINTER(C.c_double)),
+        ("inlet_right", C.POINTER(C.c_double)), ("nozzle_y0", C.c_int32), ("nozzle_y1", C.c_int32),
     ]
 
 
@@ -165,8 +166,9 @@ def _f64(a) -> np.ndarray:
 
 
 def make_params(params: dict, precision: int):
-    """mclbm_params from a workload dict (``weak``: 1 for weak coupling, default 0);
-    returns (struct, arrays kept alive)."""
+    """mclbm_params from a workload dict (``weak``: 1 for weak coupling, default 0;
+    the opposed jets add ``inlet_right`` and ``nozzle`` = (y0, y1)); returns
+    (struct, arrays kept alive)."""
     M = int(params["M"])
     arrs = [_f64(params["molar_mass"]), _f64(params["cv"]), _f64(params["D"]).reshape(M * M),
             _f64(params["mu"]), _f64(params["lambda"])]
@@ -177,12 +179,16 @@ def make_params(params: dict, precision: int):
     inl = None if inl is None else _f64(inl).reshape(M + 5)
     tex = params.get("transport_exp")
     tex = None if tex is None else _f64(tex).reshape(2 * M + 2)
-    arrs += [a for a in (cvc, inl, tex) if a is not None]
+    inr = params.get("inlet_right")
+    inr = None if inr is None else _f64(inr).reshape(M + 5)
+    noz = params.get("nozzle", (0, 0))
+    arrs += [a for a in (cvc, inl, tex, inr) if a is not None]
     p = mclbm_params(M, int(params["nx"]), int(params["ny"]), int(params["nz"]),
                      int(params.get("wall_x", 0)), int(precision), int(params.get("weak", 0)),
                      int(params.get("wall_y", 0)),
                      *[a.ctypes.data_as(dp) for a in arrs[:5]],
-                     *[a.ctypes.data_as(dp) if a is not None else None for a in (cvc, inl, tex)])
+                     *[a.ctypes.data_as(dp) if a is not None else None for a in (cvc, inl, tex, inr)],
+                     int(noz[0]), int(noz[1]))
     return p, arrs
 
 

@@ -149,7 +149,32 @@ def test_open_ends_validation():
         m.mclbm_workspace_bytes(q, m.MCLBM_FP16)
     assert "open x ends" in str(e.value)
     with pytest.raises(m.MclbmError):
-        m.mclbm_workspace_bytes(dict(p, wall_x=3), m.MCLBM_FP32)
+        m.mclbm_workspace_bytes(dict(p, wall_x=4), m.MCLBM_FP32)
+
+
+def test_opposed_jets_validation():
+    """The opposed jets (wall_x = 3) need both inlets, nozzle rows inside
+    1 <= y0 < y1 <= ny - 1 and outlets at the y ends (wall_y = 2, which goes with
+    them only); they are compiled for strong coupling, constant properties and
+    FP64 arithmetic, and take the workspace of the walled tube."""
+    m = pytest.importorskip("paper_2004_11286_amd.mclbm")
+    p, _ = W.ternary_tube(nx=16, ny=8, nz=2)
+    left = np.array([0.3, 0.3, 0.4, p["P0"], 1 / 3, 0.04, 0.0, 0.0])
+    right = np.array([0.2, 0.3, 0.5, p["P0"], 1 / 3, -0.04, 0.0, 0.0])
+    q = dict(p, wall_x=3, wall_y=2, inlet=left, inlet_right=right, nozzle=(2, 6))
+    for prec in (m.MCLBM_FP64, m.MCLBM_FP32):
+        assert m.mclbm_workspace_bytes(q, prec) == m.mclbm_workspace_bytes(dict(p, wall_x=1), prec)
+    assert m.mclbm_workspace_bytes(dict(q, nozzle=(1, 7)), m.MCLBM_FP32) > 0
+    for bad in (dict(q, inlet_right=None), dict(q, wall_y=0), dict(q, wall_y=1), dict(q, nozzle=(0, 4)),
+                dict(q, nozzle=(3, 8)), dict(q, nozzle=(4, 4)), dict(p, wall_y=2),
+                dict(q, inlet_right=np.array([0.2, 0.3, 0.4, p["P0"], 1 / 3, 0, 0, 0]))):
+        with pytest.raises(m.MclbmError):
+            m.mclbm_workspace_bytes(bad, m.MCLBM_FP32)
+    for bad, prec in ((dict(q, weak=1), m.MCLBM_FP64), (dict(q, cv_coef=np.ones((3, 4))), m.MCLBM_FP64),
+                      (q, m.MCLBM_FP16), (q, m.MCLBM_FP32_FP32)):
+        with pytest.raises(m.MclbmError) as e:
+            m.mclbm_workspace_bytes(bad, prec)
+        assert "jets" in str(e.value)
 
 
 def test_free_slip_validation():

@@ -1,0 +1,154 @@
+"""GPU parity of the opposed jets (Sec. 4.3; wall_x = 3, wall_y = 2: on both x
+faces the nozzle rows are equilibrium inlets and the other rows free-slip walls,
+zero-gradient outlets at both y ends) against the oracle, through the C ABI.
+The oracle's jets are pinned on the CPU (tests/test_oracle_jets.py). Compared
+here: fields and every stored population on ragged grids whose interior and two
+jets all differ (FP64, 20 steps, both step paths, nozzles that reach the rows
+next to the outlets and nozzles a few rows wide), the jets fed with the gas at
+rest, and the counterflow of the oracle pin over 1000 steps (FP32).
+"""
+import numpy as np
+import pytest
+
+from gpu_common import FIELDS, decode_checkpoint, field_errors, stored_population_error
+from paper_2004_11286_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+T0 = 1.0 / 3.0
+
+
+@pytest.fixture(scope="module")
+def mc():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2004_11286_amd import mclbm
+
+    return mclbm
+
+
+def _case(M, nx, ny, nz, nozzle, seed):
+    """Random interior near a mixture unlike either jet; the left jet enters at
+    0.04 with a transverse component, the right one at -0.03, at other states."""
+    if M == 2:
+        params, _ = W.binary_interdiffusion(nx=nx, ny=ny, nz=nz)
+        X0, Xl, Xr = [0.4, 0.6], [0.7, 0.3], [0.2, 0.8]
+    elif M == 3:
+        params, _ = W.ternary_tube(nx=nx, ny=ny, nz=nz)
+        X0, Xl, Xr = [0.3, 0.3, 0.4], [0.1, 0.4, 0.5], [0.45, 0.25, 0.3]
+    else:
+        params, _ = W.ternary_tube(nx=nx, ny=ny, nz=nz, masses=(2.0, 16.0, 28.0, 40.0),
+                                   x_left=(0.2, 0.2, 0.1, 0.5), x_right=(0.1, 0.2, 0.2, 0.5),
+                                   Doff={(0, 1): 0.08, (0, 2): 0.07, (0, 3): 0.06, (1, 2): 0.03,
+                                         (1, 3): 0.02, (2, 3): 0.04})
+        X0, Xl, Xr = [0.2, 0.2, 0.15, 0.45], [0.1, 0.3, 0.1, 0.5], [0.3, 0.1, 0.2, 0.4]
+    P0 = params["P0"]
+    params = dict(params, wall_x=3, wall_y=2, nozzle=nozzle,
+                  inlet=np.array(Xl + [1.02 * P0, 0.31, 0.04, 0.01, -0.02]),
+                  inlet_right=np.array(Xr + [0.99 * P0, 0.35, -0.03, -0.01, 0.01]))
+    f = W.random_near_equilibrium(params, nx, ny, nz, seed=seed, X0=X0, p0=P0, T0=0.3, amp=0.05, uamp=0.03)
+    return params, f
+
+
+def _compare_fp64(mc, oracle_mod, params, f, M, steps, launch=None):
+    s = mc.Sim(params, mc.MCLBM_FP64)
+    if launch:
+        s.set_launch(**launch)
+    s.init_fields(**f)
+    s.step(steps)
+    g = s.read_moments()
+    hdr, vals = decode_checkpoint(s.save())
+    s.close()
+    o = oracle_mod.OracleSim(params)
+    o.init_fields(**f)
+    o.step(steps)
+    errs = field_errors(g, o.read_moments())
+    pop_err = stored_population_error(hdr, vals, o.populations(), M, 0)
+    return errs, pop_err
+
+
+@pytest.mark.parametrize("three_pass", [0, 1])
+@pytest.mark.parametrize("M,shape,nozzle", [(2, (13, 11, 3), (1, 10)), (3, (13, 11, 3), (3, 7)),
+                                            (4, (9, 7, 2), (2, 5)), (3, (6, 5, 1), (1, 4))])
+def test_jets_ragged_grid_fp64(mc, oracle_mod, M, shape, nozzle, three_pass):
+    """20 steps in FP64 on ragged grids: fields and every stored population
+    against the oracle; the jets' fronts and the outflow through the y ends cross
+    several nodes in that time."""
+    nx, ny, nz = shape
+    params, f = _case(M, nx, ny, nz, nozzle, seed=501 + M + 7 * nozzle[0])
+    errs, pop_err = _compare_fp64(mc, oracle_mod, params, f, M, 20, dict(three_pass=three_pass))
+    print("jets fp64", M, shape, nozzle, three_pass, errs, "populations", pop_err)
+    for k in FIELDS:
+        assert errs[k] < 1e-12, (k, errs[k])
+    assert pop_err < 1e-12
+
+
+def test_jets_at_rest_stay_put_fp64(mc):
+    """Gas at rest fed at its own state through both nozzles stays put."""
+    params, _ = W.ternary_tube(nx=12, ny=20, nz=2)
+    X, P0 = [0.1, 0.4, 0.5], params["P0"]
+    inlet = np.array(X + [P0, T0, 0.0, 0.0, 0.0])
+    params = dict(params, wall_x=3, wall_y=2, nozzle=(2, 18), inlet=inlet, inlet_right=inlet)
+    f = W.uniform_state(params, 12, 20, 2, X=X, p=P0, T=T0, u=(0.0, 0.0, 0.0))
+    s = mc.Sim(params, mc.MCLBM_FP64)
+    s.init_fields(**f)
+    a = s.read_moments()
+    s.step(200)
+    b = s.read_moments()
+    s.close()
+    for k in FIELDS:
+        np.testing.assert_allclose(b[k], a[k], rtol=0, atol=1e-12 * max(np.abs(a[k]).max(), 1e-3), err_msg=k)
+
+
+@pytest.mark.parametrize("three_pass", [0, 1])
+def test_jets_counterflow_fp32_1000_steps(mc, oracle_mod, three_pass):
+    """The counterflow of the oracle pin (32 x 64 nodes, nozzles on 52 rows, jets
+    of 0.04 with different compositions) over 1000 steps with FP32 storage."""
+    nx, ny, U = 32, 64, 0.04
+    params, _ = W.ternary_tube(nx=nx, ny=ny, nz=1, T0=T0)
+    xl, xr = np.array([0.1, 0.4, 0.5]), np.array([0.0, 0.5, 0.5])
+    P0 = params["P0"]
+    params = dict(params, wall_x=3, wall_y=2, nozzle=(ny // 10, ny - ny // 10),
+                  inlet=np.concatenate([xl, [P0, T0, U, 0.0, 0.0]]),
+                  inlet_right=np.concatenate([xr, [P0, T0, -U, 0.0, 0.0]]))
+    X = np.broadcast_to((0.5 * (xl + xr))[:, None, None, None], (3, 1, ny, nx)).copy()
+    f = {"X": X, "p": np.full((1, ny, nx), P0), "T": np.full((1, ny, nx), T0), "u": np.zeros((3, 1, ny, nx))}
+    o = oracle_mod.OracleSim(params)
+    o.init_fields(**f)
+    o.step(1000)
+    om = o.read_moments()
+    s = mc.Sim(params, mc.MCLBM_FP32)
+    s.set_launch(three_pass=three_pass)
+    s.init_fields(**f)
+    s.step(1000)
+    g = s.read_moments()
+    s.close()
+    assert np.abs(om["u"][0]).max() > 0.02                   # the jets flow
+    errs = field_errors(g, om, u_floor=1e-3)
+    print("jets fp32 1000", three_pass, errs)
+    for k in FIELDS:
+        assert errs[k] < 1e-5, (k, errs[k])
+
+
+def test_jets_checkpoint_resume(mc):
+    """A jets context resumes bit for bit from its checkpoint; an open-ended
+    context of the same size refuses it."""
+    params, f = _case(3, 10, 9, 2, (2, 7), seed=77)
+    s = mc.Sim(params, mc.MCLBM_FP32)
+    s.init_fields(**f)
+    s.step(6)
+    buf = s.save()
+    s.step(5)
+    a = s.read_moments()
+    s.load(buf)
+    s.step(5)
+    b = s.read_moments()
+    s.close()
+    for k in FIELDS:
+        np.testing.assert_array_equal(a[k], b[k])
+    other = mc.Sim({k: v for k, v in dict(params, wall_x=2, wall_y=0).items() if k not in ("inlet_right", "nozzle")},
+                   mc.MCLBM_FP32)
+    with pytest.raises(mc.MclbmError):
+        other.load(buf)
+    other.close()
