@@ -1,6 +1,6 @@
 // device_ops.hpp -- gfx950 device primitives used by the node functions:
-// stochastic-rounding conversions to 16-bit storage, streaming loads and stores, and a
-// compiler barrier.
+// stochastic-rounding conversions to 16-bit and FP32 storage, buffer accesses,
+// streaming loads and stores, and a compiler barrier.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -41,6 +41,46 @@ __device__ inline float cvt_sr_f32(double x, uint32_t rnd)
   b += (uint64_t)(rnd >> 8) << 5;
   b &= ~(((uint64_t)1 << 29) - 1);
   return (float)__longlong_as_double((long long)b);
+}
+
+// Buffer accesses to one direction's array of a lattice (n values from base). The
+// resource (base address and byte size, in scalar registers) is the same for the
+// whole wavefront: the blocks of a launch each lie in one tube, and base and n
+// are that tube's. Each lane adds a 32-bit byte offset, so an access costs no
+// per-lane address arithmetic, where a global access through a 64-bit per-lane
+// address costs a 64-bit multiply-add or shift-add each. The hardware's range
+// check returns zero for loads and drops stores past the array's end. Word 3 of
+// the resource is the raw (untyped) buffer format of the gfx9 family.
+enum { BUF_CACHED = 0, BUF_NT = 2 };   // cache policy: default, or the nontemporal hint
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uint32_t bytes)
+{
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+template <typename T, int AUX = BUF_CACHED>
+__device__ __forceinline__ T buf_load(const T* base, uint32_t n, uint32_t idx)
+{
+  const __amdgpu_buffer_rsrc_t r = buf_rsrc(base, n * (uint32_t)sizeof(T));
+  const uint32_t off = idx * (uint32_t)sizeof(T);
+  if constexpr (sizeof(T) == 8) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, AUX));
+  else if constexpr (sizeof(T) == 4) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, AUX));
+  else return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, AUX));
+}
+
+template <typename T, int AUX = BUF_CACHED>
+__device__ __forceinline__ void buf_store(T* base, uint32_t n, uint32_t idx, T v)
+{
+  const __amdgpu_buffer_rsrc_t r = buf_rsrc(base, n * (uint32_t)sizeof(T));
+  const uint32_t off = idx * (uint32_t)sizeof(T);
+  if constexpr (sizeof(T) == 8) {
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, AUX);
+  } else if constexpr (sizeof(T) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, AUX);
+  } else {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, off, 0, AUX);
+  }
 }
 
 // Load of a value that is read once and not again soon (the populations a

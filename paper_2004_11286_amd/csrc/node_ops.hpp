@@ -529,7 +529,7 @@ __host__ __device__ __forceinline__ void state_node(const Params<double>& P, con
     for (int c = 0; c < 3; ++c) up += s.u[c] * (Pn[c][k] - (c == k ? s.P : 0.0) - rho * s.u[c] * s.u[k]);
     qn[k] = q[k] - hyd * rho * s.u[k] - up;
   }
-  auto put = [&](int f, D v) { stream_store(at32(rec + (size_t)f * n, nd), Rec(v)); };
+  auto put = [&](int f, D v) { buf_store<Rec, BUF_NT>(rec + (size_t)f * n, (uint32_t)n, nd, Rec(v)); };
 #pragma unroll
   for (int k = 0; k < 3; ++k) put(REC_PHIX + k, j[k] * (1.0 - 3.0 * theta) - j[k] * s.u[k] * s.u[k]);
   put(REC_OMEGA, omega);
@@ -591,7 +591,7 @@ __host__ __device__ __forceinline__ void gfield_node(const Params<double>& P, co
   R om = *at32(rec + (size_t)REC_OMEGA * n, nd);
   R f = R(1) / om - R(0.5);
 #pragma unroll
-  for (int k = 0; k < 3; ++k) stream_store(at32(G + (size_t)k * n, nd), R(f * dphi[k]));
+  for (int k = 0; k < 3; ++k) buf_store<R, BUF_NT>(G + (size_t)k * n, (uint32_t)n, nd, R(f * dphi[k]));
 }
 
 // --------------------------------------------------------------------------
@@ -636,7 +636,12 @@ struct Store<__bf16, float> {
 };
 
 // Random words for stochastic rounding: one hash per (node, lattice, step), then
-// a linear congruential sequence (only its upper bits are used).
+// a linear congruential sequence (only its upper bits are used). An additive
+// (Weyl) sequence would save the multiply, but its fixed increment correlates the
+// rounding of a node's directions (opposite directions nearly anti-correlated for
+// some pairs), which leaves each rounding unbiased but raises the noise of the
+// first moments: FP16 storage of the ternary tube drifted 1.7 times further from
+// the FP64 result over 1000 steps.
 struct Rng {
   uint32_t s;
   __host__ __device__ Rng(int64_t node, int l, uint32_t step)
@@ -672,24 +677,31 @@ __host__ __device__ __forceinline__ void push(const Params<R>& P, S* __restrict_
   const size_t n = (size_t)P.n;
   const bool xout = (cx(i) < 0 && b.lo) || (cx(i) > 0 && b.hi);
   const bool yout = (cy(i) < 0 && b.ylo) || (cy(i) > 0 && b.yhi);
+  // destination direction j and node d (a 32-bit index, as every node index here)
+  int j = i;
+  uint32_t d = b.x[cx(i) + 1] + b.y[cy(i) + 1] + b.z[cz(i) + 1];
   if (xbc(BC) == BC_WALLS && xout) {
-    dst[(size_t)(l * Q + opp(i)) * n + node] = v;    // half-way bounce-back
+    j = opp(i);                                       // half-way bounce-back
+    d = (uint32_t)node;
   } else if (xbc(BC) == BC_JETS && xout && !((BC & BC_YOUT) && yout) &&
              !nozzle_row(P, (int)b.yy + cy(i))) {
     // beside a nozzle: free-slip wall, specular reflection (c_x reversed) at the
     // node's own x; through a nozzle the value wraps into a slot that
     // jets_fix_node overwrites with the inlet equilibrium
-    const int64_t d = (int64_t)b.x[1] + b.y[cy(i) + 1] + b.z[cz(i) + 1];
-    dst[(size_t)(l * Q + i - 18 * cx(i)) * n + d] = v;
+    j = i - 18 * cx(i);
+    d = b.x[1] + b.y[cy(i) + 1] + b.z[cz(i) + 1];
   } else if ((BC & BC_YSLIP) && yout) {
     // free-slip y wall: specular reflection (c_y reversed) at the node's own y
-    const int64_t d = (int64_t)b.x[cx(i) + 1] + b.y[1] + b.z[cz(i) + 1];
-    dst[(size_t)(l * Q + i - 6 * cy(i)) * n + d] = v;
-  } else {
-    const int64_t d = (int64_t)b.x[cx(i) + 1] + b.y[cy(i) + 1] + b.z[cz(i) + 1];
-    dst[(size_t)(l * Q + i) * n + d] = v;    // plain store: the shifted pushes of a wavefront
-                                              // merge into whole lines in the cache
+    j = i - 6 * cy(i);
+    d = b.x[cx(i) + 1] + b.y[1] + b.z[cz(i) + 1];
   }
+  // cached stores: the shifted pushes of a wavefront merge into whole lines in the
+  // cache. The buffer resource must be the same for every lane of the wavefront,
+  // so the buffer store takes only values that keep their direction; a value
+  // reflected into another direction (which lanes do depends on their position)
+  // takes a global store. A wavefront away from every wall skips that branch.
+  if (j == i) buf_store<S>(dst + (size_t)(l * Q + i) * n, (uint32_t)n, d, v);
+  else dst[(size_t)(l * Q + j) * n + d] = v;
 }
 
 // Load the Q stored values of one lattice of a node into v (lat: the lattice's
@@ -702,7 +714,7 @@ template <typename S>
 __host__ __device__ __forceinline__ void load_lattice(const S* __restrict__ lat, size_t n, uint32_t node, S v[Q])
 {
 #pragma unroll
-  for (int i = 0; i < Q; ++i) v[i] = stream_load(at32(lat + (size_t)i * n, node));
+  for (int i = 0; i < Q; ++i) v[i] = buf_load<S, BUF_NT>(lat + (size_t)i * n, (uint32_t)n, node);
   lattice_barrier();
 }
 
@@ -976,7 +988,7 @@ template <typename S>
 __host__ __device__ __forceinline__ void load_lattice_seq(const S* __restrict__ lat, size_t n, uint32_t node, S (&v)[Q])
 {
 #pragma unroll
-  for (int i = 0; i < Q; ++i) v[i] = stream_load(at32(lat + (size_t)i * n, node));
+  for (int i = 0; i < Q; ++i) v[i] = buf_load<S, BUF_NT>(lat + (size_t)i * n, (uint32_t)n, node);
 }
 
 // --------------------------------------------------------------------------
@@ -1221,7 +1233,7 @@ __host__ __device__ __forceinline__ void state_species_node(const Params<R>& P, 
     if constexpr (HOLD) load_lattice(src + (size_t)a * Q * n, n, nd, va);
     else
 #pragma unroll
-      for (int i = 0; i < Q; ++i) va[i] = *at32(src + (size_t)(a * Q + i) * n, nd);
+      for (int i = 0; i < Q; ++i) va[i] = buf_load<S>(src + (size_t)(a * Q + i) * n, (uint32_t)n, nd);
     R r = R(0), ja[3] = {R(0), R(0), R(0)};
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -1240,12 +1252,12 @@ __host__ __device__ __forceinline__ void state_species_node(const Params<R>& P, 
   R rho = R(0), j[3] = {R(0), R(0), R(0)}, rhoE = R(0);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const R d = from_store<S, R>(P, LF, stream_load(at32(src + (size_t)(LF * Q + i) * n, nd)));
+    const R d = from_store<S, R>(P, LF, buf_load<S, BUF_NT>(src + (size_t)(LF * Q + i) * n, (uint32_t)n, nd));
     rho += d;
     acc_c(j[0], cx(i), d);
     acc_c(j[1], cy(i), d);
     acc_c(j[2], cz(i), d);
-    rhoE += from_store<S, R>(P, LG, stream_load(at32(src + (size_t)(LG * Q + i) * n, nd)));
+    rhoE += from_store<S, R>(P, LG, buf_load<S, BUF_NT>(src + (size_t)(LG * Q + i) * n, (uint32_t)n, nd));
   }
   rho += P.ref0[LF];
   rhoE += P.ref0[LG];
@@ -1284,7 +1296,7 @@ __host__ __device__ __forceinline__ void state_species_node(const Params<R>& P, 
   const R lam_mix = mixture_conductivity<R, M>(P, s.X);
   const R omega = R(2) * s.P / (s.P + R(2) * mu_mix);
   const R omega1 = R(2) * s.P * s.Cp / (s.P * s.Cp + R(2) * lam_mix);
-  auto put = [&](int f, R v) { stream_store(at32(rec + (size_t)f * n, nd), Rec(v)); };
+  auto put = [&](int f, R v) { buf_store<Rec, BUF_NT>(rec + (size_t)f * n, (uint32_t)n, nd, Rec(v)); };
 #pragma unroll
   for (int k = 0; k < 3; ++k) put(REC_PHIX + k, j[k] * (R(1) - R(3) * theta) - j[k] * s.u[k] * s.u[k]);
   put(REC_OMEGA, omega);

@@ -209,6 +209,50 @@ def tube_ensemble(ntubes=512, ny=16, nz=16, lmin=32, lmax=256, seed=11286, T0=1.
     return tubes
 
 
+# ----------------------------------------------------------------------------- opposed jets
+# Species of the opposed jets of Sec. 4.3, ordered so that N2 (the carrier of both
+# jets, slaved under strong coupling) is last: H2, O2, H2O, N2.
+JETS_SPECIES = ("H2", "O2", "H2O", "N2")
+JETS_MASSES = (2.0, 32.0, 18.0, 28.0)
+JETS_LEFT = (0.1, 0.0, 0.05, 0.85)      # the jet at x = 0 (Sec. 4.3)
+JETS_RIGHT = (0.0, 0.1, 0.0, 0.9)       # the jet at x = nx - 1
+# Binary diffusivities near 300 K and 1 atm in cm^2/s, rounded (orders of
+# magnitude from gas-kinetic tables), in the species order above; scaled
+# uniformly into lattice units by the recipe.
+JETS_D_PHYS = {(0, 1): 0.81, (0, 2): 0.95, (0, 3): 0.78, (1, 2): 0.26, (1, 3): 0.21, (2, 3): 0.26}
+
+
+def opposed_jets(nx=200, ny=400, nz=1, U=0.04, T0=1.0, omega0=1.0, d_max=0.05, gamma=1.4, nozzle_frac=0.1):
+    """The planar opposed jets of Sec. 4.3: 200 x 400 x 1 nodes, the nozzles
+    nx - 1 apart on the rows nozzle_frac ny <= y < (1 - nozzle_frac) ny of both x
+    faces, free-slip walls beside them, zero-gradient outlets at both y ends
+    (wall_x = 3, wall_y = 2). The jets carry the paper's compositions with equal
+    momentum (the left one at U, the right one at U sqrt(rho_l / rho_r)) at the
+    common pressure and temperature; the interior starts at rest at the mean
+    composition. Lattice-unit species data: the diffusivities of JETS_D_PHYS
+    scaled so the largest is d_max, one ratio of specific heats for all species,
+    viscosities giving omega = omega0 at the mean state."""
+    M = len(JETS_MASSES)
+    m = np.asarray(JETS_MASSES)
+    xl, xr = np.asarray(JETS_LEFT), np.asarray(JETS_RIGHT)
+    scale = d_max / max(JETS_D_PHYS.values())
+    D = full_D({k: v * scale for k, v in JETS_D_PHYS.items()}, M)
+    x0 = 0.5 * (xl + xr)
+    P0 = T0 / float(np.dot(x0, m))                  # mean density 1
+    mu = (1.0 / omega0 - 0.5) * P0
+    sp = _species(JETS_MASSES, gamma=gamma, D=D, mu=mu)
+    ur = U * np.sqrt(float(np.dot(xl, m)) / float(np.dot(xr, m)))
+    noz = (int(round(nozzle_frac * ny)), int(round((1.0 - nozzle_frac) * ny)))
+    x, y, z = _grid(nx, ny, nz)
+    shape = x.shape
+    X = np.broadcast_to(x0[:, None, None, None], (M,) + shape)
+    return _pack(sp, X, np.full(shape, P0), np.full(shape, T0), np.zeros((3,) + shape),
+                 nx=nx, ny=ny, nz=nz, wall_x=3, wall_y=2, nozzle=noz, slaved=M - 1, P0=P0,
+                 inlet=np.concatenate([xl, [P0, T0, U, 0.0, 0.0]]),
+                 inlet_right=np.concatenate([xr, [P0, T0, -ur, 0.0, 0.0]]),
+                 workload=f"opposed jets {nx}x{ny}x{nz} (H2/O2/H2O/N2)")
+
+
 # ----------------------------------------------------------------------------- helpers
 def uniform_state(params: dict, nx, ny, nz, X, p, T, u=(0.0, 0.0, 0.0)):
     """Uniform fields (used for fixed-point and single-node tests)."""

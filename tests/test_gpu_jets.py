@@ -152,3 +152,70 @@ def test_jets_checkpoint_resume(mc):
     with pytest.raises(mc.MclbmError):
         other.load(buf)
     other.close()
+
+
+def _oracle_populations(hdr, vals, M):
+    """Absolute populations of a strongly coupled checkpoint in the oracle's
+    layout [(M+2)][27][n]; the slaved species' lattice (never read under strong
+    coupling) is left at zero."""
+    L = vals.shape[0]
+    n = vals.shape[2] * vals.shape[3] * vals.shape[4]
+    out = np.zeros((M + 2, 27, n))
+    for l in range(L):
+        dst = l if l < M - 1 else l + 1
+        out[dst] = (hdr["ref"][l][:, None, None, None] + vals[l].astype(np.float64) / hdr["scale"][l]).reshape(27, n)
+    return out
+
+
+def test_paper_opposed_jets_steady_state(mc, oracle_mod):
+    """The opposed jets of Sec. 4.3 at the paper's size (200 x 400 x 1, nozzles on
+    the middle 80% of each face, H2/O2/H2O/N2 jets of equal momentum) run to a
+    steady state in FP64 (30000 steps, six transit times). Its stagnation line
+    follows the planar similarity solution of the independent 1D solver, as the
+    paper's lattice solution follows its 1D reference; one more step from that
+    state matches the oracle's step on every population of the grid; FP32
+    storage reaches the same state."""
+    import counterflow1d as CF
+
+    params, f = W.opposed_jets()
+    nx, ny, M = params["nx"], params["ny"], params["M"]
+    steps = 30000
+    s = mc.Sim(params, mc.MCLBM_FP64)
+    s.init_fields(**f)
+    s.step(steps - 1000)
+    a = s.read_moments()
+    s.step(1000)
+    m = s.read_moments()
+    hdr, vals = decode_checkpoint(s.save())
+    s.step(1)
+    hdr1, vals1 = decode_checkpoint(s.save())
+    s.close()
+    drift = max(float(np.abs(m[k] - a[k]).max() / np.abs(a[k]).max()) for k in ("X", "rho", "u"))
+    yc = ny // 2
+    rho, u, X = m["rho"][0, yc], m["u"][0, 0, yc], m["X"][:, 0, yc]
+    xs, uc, _, Xc, _ = CF.solve(nx - 1, rho[0] * u[0], rho[-1] * u[-1], X[:, 0], X[:, -1], params["molar_mass"],
+                                params["D"], params["mu"], float(m["p"][0, yc].mean()), float(m["T"][0, yc].mean()),
+                                composition="dirichlet")
+    xi = np.arange(nx, dtype=float)
+    du = float(np.abs(np.interp(xi, xs, uc) - u).max() / np.ptp(u))
+    dX = [float(np.abs(np.interp(xi, xs, Xc[k]) - X[k]).max()) for k in range(M)]
+    o = oracle_mod.OracleSim(params)
+    o.set_populations(_oracle_populations(hdr, vals, M))
+    o.step(1)
+    pop_err = stored_population_error(hdr1, vals1, o.populations(), M, 0)
+    s32 = mc.Sim(params, mc.MCLBM_FP32)
+    s32.init_fields(**f)
+    s32.step(steps)
+    errs32 = field_errors(s32.read_moments(), m)
+    s32.close()
+    print("paper jets: drift over the last 1000 steps", drift, "u error / range", du, "X errors", dX,
+          "one-step populations", pop_err, "fp32 vs fp64", errs32)
+    assert drift < 2e-3
+    assert du < 0.03
+    assert max(dX) < 0.01
+    # H2 of the left jet diffuses across the stagnation point, against the flow
+    ks = int(np.argmax(u < 0.0))                          # first node past the stagnation point
+    assert X[0, ks + 3] > 1e-3 and X[0, -1] < 1e-3
+    assert pop_err < 1e-12
+    for k in FIELDS:
+        assert errs32[k] < 1e-4, (k, errs32[k])
