@@ -143,6 +143,11 @@ def copy_ceiling_gbs(gib: int = 4, reps: int = 10) -> dict:
     return out
 
 
+# tiles of the step kernels' block shapes (x * y * z nodes); shape 0 is the linear
+# numbering of 256 consecutive nodes
+SHAPE_TILES = ("linear", "64x4x1", "32x8x1", "16x16x1", "64x2x2", "32x4x2")
+
+
 def progress(msg: str) -> None:
     """A progress line on stderr (stdout carries only the JSON result line)."""
     print(f"bench: {msg}", file=sys.stderr, flush=True)
@@ -448,6 +453,19 @@ def main():
     bmin = ab["method_min"]
     achieved = bmin * n / (dom_ms * 1e-3) / 1e9
     kernel_gbs = {k: ab[k] * n / (v["avg_ms"] * 1e-3) / 1e9 for k, v in stats.items() if k in ab}
+    # the block shapes of the step kernels (the headline runs the linear numbering,
+    # shape 0, the fastest on this grid): 10 timed steps each after 2 untimed
+    progress("block shapes")
+    block_shapes = {}
+    for k, tile in enumerate(SHAPE_TILES):
+        sim.set_launch(shape=k)
+        sim.step(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(10)
+        torch.cuda.synchronize()
+        block_shapes[tile] = {"shape": k, "MLUPS": n / ((time.perf_counter() - t0) / 10) / 1e6}
+    sim.set_launch(shape=0)
     sim.close()
     del sim
     torch.cuda.empty_cache()
@@ -565,6 +583,7 @@ def main():
         "method_min_frac": bmin * mlups * 1e6 / 1e9 / HBM_PEAK_GBS,
         "kernels": {k: {"avg_ms": v["avg_ms"], "launches": v["launches"], "GBs": kernel_gbs.get(k),
                         "algorithmic_bytes_per_node": ab.get(k)} for k, v in stats.items()},
+        "block_shapes": block_shapes,
         "step_effective_GBs": {"step_bytes_per_node": ab["step"], "GBs": step_gbs,
                                "method_min_bytes_per_node": bmin,
                                "method_min_GBs": bmin * mlups * 1e6 / 1e9,

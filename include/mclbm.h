@@ -238,7 +238,8 @@ int mclbm_kernel_stats(mclbm_ctx *c, int32_t kernel, double *total_ms, int64_t *
                        const char **name);
 
 /* How mclbm_step launches its kernels. Every choice computes the same step. Within
- * one path (two-read or three-pass) the results are bit for bit the same, except
+ * one path (two-read or three-pass) the results are bit for bit the same (over
+ * every block shape, tube order, swizzle and graph choice), except
  * split, whose two kernels are compiled separately and may fuse a multiply-add
  * differently: its results agree to rounding (and, with 16-bit storage, to the
  * stochastic rounding that such a last-bit difference can flip). The two paths
@@ -268,7 +269,11 @@ typedef struct {
                            registers each (one occupancy form)                          */
   int32_t three_pass;   /* 1: the three-pass step; 0: the two-read step where compiled
                            (constant properties), else the three-pass step             */
-  int32_t reserved;     /* must be 0                                                     */
+  int32_t shape;        /* block shape of the step kernels' 256-thread blocks: 0 the
+                           linear numbering (256 consecutive nodes, rows wrapping); tiles
+                           of x * y * z nodes: 1 64x4x1, 2 32x8x1, 3 16x16x1, 4 64x2x2,
+                           5 32x4x2 (threads beyond a tube's grid idle). Results are
+                           bit for bit the same for every shape                          */
 } mclbm_launch;
 
 /* A new context starts with every field 0 (the two-read step where compiled),
@@ -278,13 +283,16 @@ typedef struct {
 int mclbm_get_launch(const mclbm_ctx *c, mclbm_launch *out);
 int mclbm_set_launch(mclbm_ctx *c, const mclbm_launch *in);
 
-/* Time every launch choice (the two-read step with variant 0 or 1 where compiled;
- * the three-pass step with (variant, split) in {0,1}^2; each with swizzle and HIP
- * graph replay on or off, and for batches both tube orders) over trial_steps steps
- * each on the current state, keep the fastest, and write a text table of the
- * candidates (milliseconds per step) to report (may be NULL). The trial steps are
- * ordinary steps: the state and the step count advance by about (number of
- * candidates) * 2 trial_steps. Synchronises the stream. */
+/* Time the launch choices over trial_steps steps each on the current state and
+ * keep the fastest: first every path (the two-read step with variant 0 or 1 where
+ * compiled; the three-pass step with (variant, split) in {0,1}^2), each with
+ * swizzle and HIP graph replay on or off, and for batches both tube orders, in
+ * the linear block numbering; then the fastest of those with each tiled block
+ * shape. Writes a text table of the candidates (milliseconds per step; columns
+ * three_pass variant split swizzle order graph_steps shape) to report (may be
+ * NULL), ending with the chosen line. The trial steps are ordinary steps: the
+ * state and the step count advance by about (number of candidates) * 2
+ * trial_steps. Synchronises the stream. */
 int mclbm_autotune(mclbm_ctx *c, int32_t trial_steps, char *report, size_t report_len);
 
 /* Moles of every species in each x half of every tube, FP64 (the diagnostic of

@@ -24,10 +24,28 @@ inline size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 // of that single tube would be (pop[l][i][n_t], rec[k][n_t], ...), and its own
 // parameter block P[t]. Launches are in blocks of BLOCK nodes; a block never
 // straddles two tubes.
+//
+// Block shapes. In the linear numbering a block is BLOCK consecutive nodes of a
+// tube (x fastest, rows wrapping). The step kernels can instead take a block as a
+// tile of 2^sx x 2^sy x 2^sz nodes (sx + sy + sz = log2 BLOCK) at a tile origin of
+// the tube's grid, so that the stencil neighbours in y and z of a block's nodes
+// are mostly the block's own; threads of a tile that fall outside the grid (a
+// ragged edge) do nothing. Every node computes the same values either way.
+// The reductions and field transfers always use the linear numbering.
+constexpr int LOG2_BLOCK = 8;
+constexpr int NSHAPES = 6;
+// (sx, sy) of each shape; shape 0 is the linear numbering
+constexpr int SHAPE_SX[NSHAPES] = {0, 6, 5, 4, 6, 5};
+constexpr int SHAPE_SY[NSHAPES] = {0, 2, 3, 4, 1, 2};
+
 struct Tube {
   int64_t base;          // first node of the tube in the concatenated buffers
-  int32_t first_block;   // first block of the tube in a launch over all tubes
+  int32_t first_block;   // first block of the tube in a linear launch over all tubes
   int32_t nblocks;
+  int32_t nx, ny, nz;    // the tube's grid
+  int32_t tiles_x, tiles_y;   // tiles per row and per plane of the current shape
+  int32_t tfirst, tnblocks;   // first block and block count of the tube in a tiled launch
+  int32_t pad;
 };
 
 struct Launch {
@@ -36,7 +54,7 @@ struct Launch {
   int32_t ntubes;
   int32_t block0;            // added to the block index: a launch over one tube
   int32_t swizzle;           // give each XCD a contiguous run of blocks
-  int32_t pad;
+  int32_t shape;             // 0: linear numbering; else sx | sy << 4 of the tiles
 };
 
 // Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD
@@ -56,6 +74,8 @@ struct Where {
   uint32_t block;        // logical block in a launch over all tubes
 };
 
+// The tube, its first node and this thread's node (outside [0, n) for a tile
+// thread beyond the grid: the kernels skip nodes >= n).
 __device__ inline Where locate(const Launch& Ln)
 {
   uint32_t b = blockIdx.x;
@@ -63,7 +83,20 @@ __device__ inline Where locate(const Launch& Ln)
   b += (uint32_t)Ln.block0;
   const int t = Ln.ntubes > 1 ? Ln.blk_tube[b] : 0;
   const Tube tb = Ln.tubes[t];
-  return {t, tb.base, (int64_t)(b - (uint32_t)tb.first_block) * BLOCK + threadIdx.x, b};
+  if (!Ln.shape) return {t, tb.base, (int64_t)(b - (uint32_t)tb.first_block) * BLOCK + threadIdx.x, b};
+  const uint32_t sx = (uint32_t)Ln.shape & 15u, sy = (uint32_t)Ln.shape >> 4;
+  uint32_t lb = b - (uint32_t)tb.tfirst;
+  const uint32_t ix = lb % (uint32_t)tb.tiles_x;
+  lb /= (uint32_t)tb.tiles_x;
+  const uint32_t iy = lb % (uint32_t)tb.tiles_y, iz = lb / (uint32_t)tb.tiles_y;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t x = (ix << sx) + (tid & ((1u << sx) - 1u));
+  const uint32_t y = (iy << sy) + ((tid >> sx) & ((1u << sy) - 1u));
+  const uint32_t z = (iz << (LOG2_BLOCK - sx - sy)) + (tid >> (sx + sy));
+  const bool inside = x < (uint32_t)tb.nx && y < (uint32_t)tb.ny && z < (uint32_t)tb.nz;
+  const int64_t node = inside ? (int64_t)x + (int64_t)tb.nx * ((int64_t)y + (int64_t)tb.ny * (int64_t)z)
+                              : INT64_MAX;
+  return {t, tb.base, node, b};
 }
 
 // Step number for the stochastic-rounding seeds: a constant in eager launches,

@@ -228,6 +228,8 @@ struct mclbm_ctx {
   void* dPr = nullptr;      // Params<float>[ntubes], or alias of dPd
   kern::Tube* dTubes = nullptr;
   int32_t* dBlkTube = nullptr;
+  int32_t* dBlkTubeT = nullptr;   // tube of every block of a tiled launch (block shape > 0)
+  int64_t nblocks_t = 0;          // blocks of a tiled launch over all tubes (current shape)
   int64_t* dTubeN = nullptr;
   uint32_t* dStepCtr = nullptr;
   void* pop[2] = {nullptr, nullptr};
@@ -245,6 +247,7 @@ struct mclbm_ctx {
   std::vector<Params<float>> hPf;
   std::vector<kern::Tube> hTubes;
   std::vector<int32_t> hBlkTube;
+  std::vector<int32_t> hBlkTubeT;
   std::vector<int64_t> hTubeN;
   // launch configuration
   mclbm_launch lc{};
@@ -264,9 +267,18 @@ struct mclbm_ctx {
 namespace {
 
 struct Layout {
-  size_t pd, pr, tubes, blk, tube_n, ctr, pop, rec, G, staging, partial, reduced, bad, total;
-  int64_t n, nblocks;
+  size_t pd, pr, tubes, blk, blkT, tube_n, ctr, pop, rec, G, staging, partial, reduced, bad, total;
+  int64_t n, nblocks, nblocks_tmax;
 };
+
+// Tiles of block shape k (> 0) over an nx x ny x nz grid: per row, per plane, total.
+void tile_counts(int k, int nx, int ny, int nz, int32_t& tx, int32_t& ty, int64_t& total)
+{
+  const int sx = kern::SHAPE_SX[k], sy = kern::SHAPE_SY[k], sz = kern::LOG2_BLOCK - sx - sy;
+  tx = (int32_t)((nx + (1 << sx) - 1) >> sx);
+  ty = (int32_t)((ny + (1 << sy) - 1) >> sy);
+  total = (int64_t)tx * ty * ((nz + (1 << sz) - 1) >> sz);
+}
 
 size_t storage_bytes(int precision)
 {
@@ -291,6 +303,17 @@ Layout layout_for(const mclbm_params* tp, int ntubes)
     l.n += n;
     l.nblocks += (n + BLOCK - 1) / BLOCK;
   }
+  l.nblocks_tmax = 0;
+  for (int k = 1; k < kern::NSHAPES; ++k) {
+    int64_t tot = 0;
+    for (int t = 0; t < ntubes; ++t) {
+      int32_t tx, ty;
+      int64_t nt;
+      tile_counts(k, tp[t].nx, tp[t].ny, tp[t].nz, tx, ty, nt);
+      tot += nt;
+    }
+    l.nblocks_tmax = std::max(l.nblocks_tmax, tot);
+  }
   const size_t s_bytes = storage_bytes(precision), r_bytes = record_bytes(precision);
   // stored lattices and record fields (RecLayout): M-1 stored species under
   // strong coupling, M under weak coupling (which also records u_s)
@@ -302,6 +325,7 @@ Layout layout_for(const mclbm_params* tp, int ntubes)
   l.pr = off; off += align_up(sizeof(Params<float>) * ntubes);
   l.tubes = off; off += align_up(sizeof(kern::Tube) * ntubes);
   l.blk = off; off += align_up(sizeof(int32_t) * l.nblocks);
+  l.blkT = off; off += align_up(sizeof(int32_t) * l.nblocks_tmax);
   l.tube_n = off; off += align_up(sizeof(int64_t) * ntubes);
   l.ctr = off; off += align_up(sizeof(uint32_t));
   l.pop = off; off += 2 * align_up((size_t)L * Q * l.n * s_bytes);
@@ -469,16 +493,38 @@ int fail(mclbm_ctx* c, int code, const std::string& msg)
 
 double absent_tol_for(int precision);
 
-// Launch over every block of every tube.
+// Launch over every block of every tube (linear numbering).
 Launch launch_all(const mclbm_ctx* c)
 {
   return Launch{c->dTubes, c->dBlkTube, c->ntubes, 0, c->lc.swizzle, 0};
 }
 
-// Launch over the blocks of tube t only.
-Launch launch_one(const mclbm_ctx* c, int t)
+// The step kernels' launches take the block shape of the launch choice.
+int32_t shape_code(const mclbm_ctx* c)
 {
-  return Launch{c->dTubes, c->dBlkTube, c->ntubes, c->hTubes[t].first_block, c->lc.swizzle, 0};
+  const int k = c->lc.shape;
+  return k ? kern::SHAPE_SX[k] | kern::SHAPE_SY[k] << 4 : 0;
+}
+
+Launch step_launch_all(const mclbm_ctx* c)
+{
+  if (!c->lc.shape) return launch_all(c);
+  return Launch{c->dTubes, c->dBlkTubeT, c->ntubes, 0, c->lc.swizzle, shape_code(c)};
+}
+
+unsigned step_grid_all(const mclbm_ctx* c) { return (unsigned)(c->lc.shape ? c->nblocks_t : c->nblocks); }
+
+// Step launch over the blocks of tube t only.
+Launch step_launch_one(const mclbm_ctx* c, int t)
+{
+  if (!c->lc.shape)
+    return Launch{c->dTubes, c->dBlkTube, c->ntubes, c->hTubes[t].first_block, c->lc.swizzle, 0};
+  return Launch{c->dTubes, c->dBlkTubeT, c->ntubes, c->hTubes[t].tfirst, c->lc.swizzle, shape_code(c)};
+}
+
+unsigned step_grid_one(const mclbm_ctx* c, int t)
+{
+  return (unsigned)(c->lc.shape ? c->hTubes[t].tnblocks : c->hTubes[t].nblocks);
 }
 
 // The equilibrium of the inlet fields in every stored lattice of a context's
@@ -546,20 +592,39 @@ int push_block_map(mclbm_ctx* c)
   std::iota(order.begin(), order.end(), 0);
   if (c->lc.order == 1)
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return c->tubes[a].n > c->tubes[b].n; });
-  int32_t blk = 0;
+  int32_t blk = 0, blkT = 0;
+  const int k = c->lc.shape;
   for (int t : order) {
-    const int32_t nb = (int32_t)((c->tubes[t].n + BLOCK - 1) / BLOCK);
-    c->hTubes[t].base = c->tubes[t].base;
-    c->hTubes[t].first_block = blk;
-    c->hTubes[t].nblocks = nb;
+    const TubeHost& th = c->tubes[t];
+    kern::Tube& tb = c->hTubes[t];
+    const int32_t nb = (int32_t)((th.n + BLOCK - 1) / BLOCK);
+    tb.base = th.base;
+    tb.first_block = blk;
+    tb.nblocks = nb;
+    tb.nx = th.nx;
+    tb.ny = th.ny;
+    tb.nz = th.nz;
     for (int32_t b = 0; b < nb; ++b) c->hBlkTube[blk + b] = t;
     blk += nb;
+    tb.tiles_x = tb.tiles_y = tb.tfirst = tb.tnblocks = 0;
+    if (k) {
+      int64_t nt = 0;
+      tile_counts(k, th.nx, th.ny, th.nz, tb.tiles_x, tb.tiles_y, nt);
+      tb.tfirst = blkT;
+      tb.tnblocks = (int32_t)nt;
+      for (int32_t b = 0; b < (int32_t)nt; ++b) c->hBlkTubeT[blkT + b] = t;
+      blkT += (int32_t)nt;
+    }
   }
+  c->nblocks_t = blkT;
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   HIP_TRY(c, hipMemcpyAsync(c->dTubes, c->hTubes.data(), sizeof(kern::Tube) * c->ntubes, hipMemcpyHostToDevice,
                             c->stream));
   HIP_TRY(c, hipMemcpyAsync(c->dBlkTube, c->hBlkTube.data(), sizeof(int32_t) * c->nblocks, hipMemcpyHostToDevice,
                             c->stream));
+  if (blkT)
+    HIP_TRY(c, hipMemcpyAsync(c->dBlkTubeT, c->hBlkTubeT.data(), sizeof(int32_t) * blkT, hipMemcpyHostToDevice,
+                              c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return MCLBM_OK;
 }
@@ -733,10 +798,10 @@ void enqueue_step(mclbm_ctx* c, int from, StepNo sn, hipStream_t st)
     last_pass(c, ln, from, sn, grid, st);
   };
   if (!c->lc.sequential) {
-    one(launch_all(c), (unsigned)c->nblocks);
+    one(step_launch_all(c), step_grid_all(c));
     return;
   }
-  for (int t = 0; t < c->ntubes; ++t) one(launch_one(c, t), (unsigned)c->hTubes[t].nblocks);
+  for (int t = 0; t < c->ntubes; ++t) one(step_launch_one(c, t), step_grid_one(c, t));
 }
 
 // One eager step, with per-kernel events when timing is enabled (batched only).
@@ -745,8 +810,8 @@ int eager_step(mclbm_ctx* c)
   const StepNo sn{nullptr, (uint32_t)c->steps};
   int rc = 0;
   if (c->timing && !c->lc.sequential) {
-    const Launch ln = launch_all(c);
-    const unsigned grid = (unsigned)c->nblocks;
+    const Launch ln = step_launch_all(c);
+    const unsigned grid = step_grid_all(c);
     int e0 = 0, e1 = 0, e2 = 0, e3 = 0;
     if ((rc = record_event(c, e0))) return rc;
     first_pass(c, ln, c->cur, sn, grid, c->stream);
@@ -916,6 +981,7 @@ extern "C" int mclbm_batch_create(const mclbm_params* tp, int32_t ntubes, void* 
   c->dPr = compute_is_fp64(c->precision) ? c->dPd : (void*)(ws + lay.pr);
   c->dTubes = (kern::Tube*)(ws + lay.tubes);
   c->dBlkTube = (int32_t*)(ws + lay.blk);
+  c->dBlkTubeT = (int32_t*)(ws + lay.blkT);
   c->dTubeN = (int64_t*)(ws + lay.tube_n);
   c->dStepCtr = (uint32_t*)(ws + lay.ctr);
   const size_t popb = align_up((size_t)c->L * Q * c->n * c->ops.s_bytes);
@@ -931,6 +997,7 @@ extern "C" int mclbm_batch_create(const mclbm_params* tp, int32_t ntubes, void* 
   c->hPf.resize(ntubes);
   c->hTubes.resize(ntubes);
   c->hBlkTube.resize(c->nblocks);
+  c->hBlkTubeT.resize(lay.nblocks_tmax);
   c->hTubeN.resize(ntubes);
   for (int t = 0; t < ntubes; ++t) c->hTubeN[t] = c->tubes[t].n;
   rc = push_block_map(c);
@@ -1368,8 +1435,8 @@ extern "C" int mclbm_set_launch(mclbm_ctx* c, const mclbm_launch* in)
   if (in->order != 0 && in->order != 1) return fail(c, MCLBM_EARG, "order must be 0 or 1");
   if (in->graph_steps < 0 || (in->graph_steps & 1) || in->graph_steps > 100000)
     return fail(c, MCLBM_EARG, "graph_steps must be an even number in 0..100000");
-  if (in->reserved) return fail(c, MCLBM_EARG, "the reserved field must be 0");
-  const bool remap = in->order != c->lc.order;
+  if (in->shape < 0 || in->shape >= kern::NSHAPES) return fail(c, MCLBM_EARG, "shape must be in 0..5");
+  const bool remap = in->order != c->lc.order || in->shape != c->lc.shape;
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   drop_graph(c);
   c->lc = *in;
@@ -1406,30 +1473,41 @@ extern "C" int mclbm_autotune(mclbm_ctx* c, int32_t trial_steps, char* report, s
   hipEvent_t e0, e1;
   HIP_TRY(c, hipEventCreate(&e0));
   HIP_TRY(c, hipEventCreate(&e1));
-  std::string rep = "three_pass variant split swizzle order graph_steps ms_per_step\n";
+  std::string rep = "three_pass variant split swizzle order graph_steps shape ms_per_step\n";
   double best = 1e300;
   mclbm_launch best_l = c->lc;
   int rc = MCLBM_OK;
-  for (const mclbm_launch& l : cands) {
-    if ((rc = mclbm_set_launch(c, &l))) break;
+  auto trial = [&](const mclbm_launch& l) -> int {
+    int r = mclbm_set_launch(c, &l);
+    if (r) return r;
     // first launches of this choice (graph build, caches), then start from buffer 0
-    if ((rc = mclbm_step(c, l.graph_steps ? G : 2))) break;
-    if (c->cur == 1 && (rc = mclbm_step(c, 1))) break;
-    if (hipEventRecord(e0, c->stream) != hipSuccess) { rc = fail(c, MCLBM_EDEVICE, "hipEventRecord"); break; }
-    if ((rc = mclbm_step(c, G))) break;
-    if (hipEventRecord(e1, c->stream) != hipSuccess) { rc = fail(c, MCLBM_EDEVICE, "hipEventRecord"); break; }
-    if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(c, MCLBM_EDEVICE, "hipEventSynchronize"); break; }
+    if ((r = mclbm_step(c, l.graph_steps ? G : 2))) return r;
+    if (c->cur == 1 && (r = mclbm_step(c, 1))) return r;
+    if (hipEventRecord(e0, c->stream) != hipSuccess) return fail(c, MCLBM_EDEVICE, "hipEventRecord");
+    if ((r = mclbm_step(c, G))) return r;
+    if (hipEventRecord(e1, c->stream) != hipSuccess) return fail(c, MCLBM_EDEVICE, "hipEventRecord");
+    if (hipEventSynchronize(e1) != hipSuccess) return fail(c, MCLBM_EDEVICE, "hipEventSynchronize");
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = fail(c, MCLBM_EDEVICE, "hipEventElapsedTime"); break; }
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return fail(c, MCLBM_EDEVICE, "hipEventElapsedTime");
     const double per = ms / G;
     char line[128];
-    std::snprintf(line, sizeof line, "%d %d %d %d %d %d %.6f\n", l.three_pass, l.variant, l.split, l.swizzle,
-                  l.order, l.graph_steps, per);
+    std::snprintf(line, sizeof line, "%d %d %d %d %d %d %d %.6f\n", l.three_pass, l.variant, l.split, l.swizzle,
+                  l.order, l.graph_steps, l.shape, per);
     rep += line;
     if (per < best) {
       best = per;
       best_l = l;
     }
+    return MCLBM_OK;
+  };
+  for (const mclbm_launch& l : cands)
+    if ((rc = trial(l))) break;
+  // the block shapes, with the fastest path, swizzle, order and graph choice
+  const mclbm_launch base = best_l;
+  for (int k = 1; k < kern::NSHAPES && !rc; ++k) {
+    mclbm_launch l = base;
+    l.shape = k;
+    rc = trial(l);
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -1437,8 +1515,8 @@ extern "C" int mclbm_autotune(mclbm_ctx* c, int32_t trial_steps, char* report, s
   rc = mclbm_set_launch(c, &best_l);
   if (rc) return rc;
   char line[128];
-  std::snprintf(line, sizeof line, "chosen %d %d %d %d %d %d %.6f\n", best_l.three_pass, best_l.variant,
-                best_l.split, best_l.swizzle, best_l.order, best_l.graph_steps, best);
+  std::snprintf(line, sizeof line, "chosen %d %d %d %d %d %d %d %.6f\n", best_l.three_pass, best_l.variant,
+                best_l.split, best_l.swizzle, best_l.order, best_l.graph_steps, best_l.shape, best);
   rep += line;
   if (report && report_len > 0) {
     const size_t k = std::min(report_len - 1, rep.size());

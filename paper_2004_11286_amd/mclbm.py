@@ -71,10 +71,10 @@ class mclbm_params(C.Structure):
 class mclbm_launch(C.Structure):
     _fields_ = [("variant", C.c_int32), ("swizzle", C.c_int32), ("order", C.c_int32),
                 ("graph_steps", C.c_int32), ("sequential", C.c_int32), ("split", C.c_int32),
-                ("three_pass", C.c_int32), ("reserved", C.c_int32)]
+                ("three_pass", C.c_int32), ("shape", C.c_int32)]
 
 
-LAUNCH_KEYS = ("variant", "swizzle", "order", "graph_steps", "sequential", "split", "three_pass")
+LAUNCH_KEYS = ("variant", "swizzle", "order", "graph_steps", "sequential", "split", "three_pass", "shape")
 
 
 class MclbmError(RuntimeError):

@@ -74,7 +74,11 @@ def test_batch_is_bitwise_single_contexts(mc, prec):
 
 
 LAUNCHES = [dict(variant=1), dict(swizzle=1), dict(order=1), dict(sequential=1), dict(graph_steps=4),
-            dict(graph_steps=2, swizzle=1, order=1, variant=1)]
+            dict(graph_steps=2, swizzle=1, order=1, variant=1),
+            # block shapes (tiles of 64x4, 32x8, 16x16, 64x2x2, 32x4x2 nodes), alone and with
+            # the other choices: the ragged tubes leave idle threads in edge tiles
+            dict(shape=1), dict(shape=2, sequential=1), dict(shape=3, swizzle=1), dict(shape=4, order=1),
+            dict(shape=5, graph_steps=2, swizzle=1, variant=1)]
 
 
 @pytest.mark.parametrize("three_pass", [0, 1])
@@ -145,10 +149,13 @@ def test_autotune_picks_a_choice_and_keeps_the_trajectory(mc):
     print(rep)
     lines = rep.strip().splitlines()
     assert lines[-1].startswith("chosen")
-    assert len(lines) == 1 + 48 + 1                          # header, 6 x 2 x 2 x 2 candidates, choice
-    chosen = [int(v) for v in lines[-1].split()[1:7]]
+    # header, 6 paths x 2 x 2 x 2 candidates in the linear numbering, the fastest with 5 tiled shapes, choice
+    assert len(lines) == 1 + 48 + 5 + 1
+    assert sorted(int(r.split()[6]) for r in lines[49:54]) == [1, 2, 3, 4, 5]
+    chosen = [int(v) for v in lines[-1].split()[1:8]]
     lc = b.launch()
-    assert [lc["three_pass"], lc["variant"], lc["split"], lc["swizzle"], lc["order"], lc["graph_steps"]] == chosen
+    assert [lc["three_pass"], lc["variant"], lc["split"], lc["swizzle"], lc["order"], lc["graph_steps"],
+            lc["shape"]] == chosen
     n = b.step_count
     b.step(5)
     got = b.read_moments()
@@ -306,3 +313,29 @@ def test_batch_models_match_oracle_and_single_contexts(mc, oracle_mod, model):
             np.testing.assert_array_equal(g[t][k], r[k], err_msg=f"{model} tube {t} {k}")
             scale = max(np.abs(om[k]).max(), 1e-3 if k == "u" else 0.0)
             assert np.abs(g[t][k] - om[k]).max() <= 1e-12 * scale, (model, t, k)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_block_shapes_are_bitwise_equal_single_contexts(mc, prec):
+    """Every block shape gives the same step bit for bit on single contexts with
+    ragged grids: a walled ternary tube with free-slip y walls and the opposed
+    jets (their edge tiles leave threads idle in x, y and z)."""
+    cases = []
+    params, f = W.ternary_tube(nx=13, ny=7, nz=5)
+    cases.append((dict(params, wall_y=1), f))
+    P0 = params["P0"]
+    jets = dict(params, nx=13, ny=11, nz=3, wall_x=3, wall_y=2, nozzle=(2, 9),
+                inlet=np.array([0.1, 0.4, 0.5, P0, 1.0 / 3.0, 0.04, 0.0, 0.0]),
+                inlet_right=np.array([0.3, 0.2, 0.5, P0, 1.0 / 3.0, -0.04, 0.0, 0.0]))
+    cases.append((jets, W.random_near_equilibrium(jets, 13, 11, 3, seed=5, X0=[0.2, 0.3, 0.5], p0=P0, T0=1.0 / 3.0)))
+    for params, f in cases:
+        outs = []
+        for shape in range(6):
+            s = mc.Sim(params, mc.PRECISIONS[prec])
+            s.set_launch(shape=shape)
+            s.init_fields(**f)
+            s.step(7)
+            outs.append(bytes(s.save()))
+            s.close()
+        for shape in range(1, 6):
+            assert outs[shape] == outs[0], (params["wall_x"], shape)
