@@ -405,6 +405,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-shapes", action="store_true", help="skip the block-shape sweep of the headline context")
     ap.add_argument("--surrogate-iters", type=int, default=36000)
     ap.add_argument("--accuracy-steps", type=int, default=1000,
                     help="steps after which the storage modes are compared with FP32 storage")
@@ -457,7 +458,7 @@ def main():
     # shape 0, the fastest on this grid): 10 timed steps each after 2 untimed
     progress("block shapes")
     block_shapes = {}
-    for k, tile in enumerate(SHAPE_TILES):
+    for k, tile in enumerate(SHAPE_TILES if not args.no_shapes else ()):
         sim.set_launch(shape=k)
         sim.step(2)
         torch.cuda.synchronize()

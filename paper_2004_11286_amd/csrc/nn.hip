@@ -3,16 +3,15 @@
 // cores (v_mfma_f32_32x32x16_bf16), their two backward passes, the loss, Adam
 // and the mole-content residual.
 //
-// Activations are node-major, act[node][channel] in BF16, so one lane's 16-byte
+// Activations are BF16, 16 channels of a node contiguous, so one lane's 16-byte
 // load is 8 consecutive channels of one node. A convolution computes
 // out^T[co][node] = sum_tap W_tap[co][ci] in[node + d_tap][ci]: the weights of a
 // tap (row co, ci contiguous) are the MFMA's A operand, staged in LDS and shared
 // by the four waves of a workgroup; the neighbour activations are the B operand,
-// loaded by each lane straight from global memory (the 27 taps re-read them
-// from the caches); the accumulator holds 4 consecutive output channels of one
-// node per lane group, so results leave as 8- or 16-byte vector stores. A
-// workgroup computes 256 nodes of one tube (64 per wave, two 32-node column
-// blocks) for all output channels.
+// staged in LDS per group of three taps; the accumulator holds 4 consecutive
+// output channels of one node per lane group, so results leave as 8- or 16-byte
+// vector stores. A workgroup computes 256 nodes of one tube (64 per wave, two
+// 32-node column blocks) for all output channels.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -83,38 +82,94 @@ __device__ inline int64_t wrap_index(const NTube& tb, int x, int y, int z)
 // ReLU mask (mask > 0), BF16 out. EPI 0 and 1 gather forward, in(x + d) with x
 // clamped to the tube (replicate padding at the walls) and y, z wrapped; EPI 2
 // is the adjoint, in(x - d) with nothing from outside the tube, plus, at a wall
-// node, the ghost's share (ghost() below).
+// node, the ghost's share.
+//
+// The 27 taps run as 9 groups (dy, dz) of three dx taps. For a group, the
+// activations the tile's nodes need are the nodes t0 - 1 .. t0 + TILE of the
+// tile's range shifted by (dy, dz), with y and z wrapped: TILE + 2 rows of CIN
+// channels, staged in LDS once and read by the group's three taps (gathering
+// every tap from the caches instead moves three times the data through them).
+// Node p of the tile reads row p + 1 + dx while x + dx stays in the tube (the node
+// p + dx of the same x row); beyond a wall the forward reads row p + 1 (replicate
+// padding) and the adjoint zero, plus row p + 1 as the ghost's share at a wall
+// node. The next group's rows are loaded into registers while the
+// current group's products run.
 template <int CIN, int COUT, int EPI>
 __global__ __launch_bounds__(256) void k_conv(const NTube* __restrict__ tubes, const int32_t* __restrict__ tile_tube,
-                                              int ntubes, const bf16* __restrict__ W, const float* __restrict__ bias,
-                                              const bf16* __restrict__ in, const bf16* __restrict__ mask,
-                                              void* __restrict__ out)
+                                                int ntubes, const bf16* __restrict__ W, const float* __restrict__ bias,
+                                                const bf16* __restrict__ in, const bf16* __restrict__ mask,
+                                                void* __restrict__ out)
 {
   static_assert(CIN % 16 == 0 && COUT % 32 == 0, "channel counts must fit the 32x32x16 MFMA");
-  constexpr int SIGN = EPI == 2 ? -1 : 1;  // the forward gathers in(x + d), its adjoint (EPI 2) in(x - d)
-  constexpr int LS = CIN + 8;              // LDS row stride (bf16): staggers the banks of the rows
+  constexpr int SIGN = EPI == 2 ? -1 : 1;
+  constexpr int LS = CIN + 8;              // LDS row stride (bf16) of weights and staged rows
   constexpr int MB = COUT / 32;
   constexpr int KC = CIN / 16;
   constexpr int CHUNKS = COUT * CIN / 8;   // 16-byte pieces of one tap's weights
   constexpr int PT = (CHUNKS + 255) / 256;
+  constexpr int RCH = CIN / 8;             // 16-byte pieces of one staged row
+  static_assert(2 * RCH <= 256, "the two extra rows are spread over the first threads");
   __shared__ __attribute__((aligned(16))) bf16 wl[2][COUT * LS];
+  __shared__ __attribute__((aligned(16))) bf16 sl[(TILE + 2) * LS];
 
   const int tile = blockIdx.x;
   const NTube tb = tube_of(tubes, tile_tube, ntubes, tile);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int n_t = tb.nx * tb.ny * tb.nz;
-  int xs[2], ys[2], zs[2], node[2];
+  const int t0 = (tile - tb.first_tile) * TILE;
+  int pos[2], xs[2];
   bool valid[2];
 #pragma unroll
   for (int b = 0; b < 2; ++b) {
-    node[b] = (tile - tb.first_tile) * TILE + wave * 64 + b * 32 + (lane & 31);
-    valid[b] = node[b] < n_t;
-    const int i = valid[b] ? node[b] : 0;
-    xs[b] = i % tb.nx;
-    const int r = i / tb.nx;
-    ys[b] = r % tb.ny;
-    zs[b] = r / tb.ny;
+    pos[b] = wave * 64 + b * 32 + (lane & 31);
+    valid[b] = t0 + pos[b] < n_t;
+    xs[b] = valid[b] ? (t0 + pos[b]) % tb.nx : 0;
   }
+  // staged rows of this thread: row threadIdx.x (all its pieces), and one piece
+  // of the rows TILE and TILE + 1 on the first 2 RCH threads
+  const int r1 = TILE + (int)threadIdx.x / RCH, c1 = (int)threadIdx.x % RCH;
+  const bool extra = threadIdx.x < 2 * RCH;
+  int jx[2], jy[2], jz[2];
+  bool jin[2];
+  {
+    const int rows[2] = {(int)threadIdx.x, r1};
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int j = t0 + rows[k] - 1;
+      jin[k] = j >= 0 && j < n_t && (k == 0 || extra);
+      const int i = jin[k] ? j : 0;
+      jx[k] = i % tb.nx;
+      const int r = i / tb.nx;
+      jy[k] = r % tb.ny;
+      jz[k] = r / tb.ny;
+    }
+  }
+  bf16x8 sreg[RCH], sx1;
+  auto sload = [&](int g) {
+    const int dy = SIGN * (g % 3 - 1), dz = SIGN * (g / 3 - 1);
+    const int64_t nb0 = wrap_index(tb, jx[0], jy[0] + dy, jz[0] + dz);
+#pragma unroll
+    for (int c = 0; c < RCH; ++c) {
+      if (jin[0]) {
+        sreg[c] = *(const bf16x8*)(in + aidx(tb, nb0, c * 8));
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) sreg[c][e] = (bf16)0.f;
+      }
+    }
+    if (jin[1]) {
+      const int64_t nb1 = wrap_index(tb, jx[1], jy[1] + dy, jz[1] + dz);
+      sx1 = *(const bf16x8*)(in + aidx(tb, nb1, c1 * 8));
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) sx1[e] = (bf16)0.f;
+    }
+  };
+  auto sstore = [&]() {
+#pragma unroll
+    for (int c = 0; c < RCH; ++c) *(bf16x8*)(&sl[threadIdx.x * LS + c * 8]) = sreg[c];
+    if (extra) *(bf16x8*)(&sl[r1 * LS + c1 * 8]) = sx1;
+  };
   f32x16 acc[MB][2];
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb)
@@ -141,89 +196,74 @@ __global__ __launch_bounds__(256) void k_conv(const NTube* __restrict__ tubes, c
       }
     }
   };
+  const int khalf = 8 * (lane >> 5);
+  sload(0);
+  sstore();
   load_w(0);
   store_w(0);
   __syncthreads();
-  const int khalf = 8 * (lane >> 5);
-  // the activations of one tap (B operands), gathered one tap ahead of the
-  // multiplications that use them so that their latency hides behind the
-  // previous tap's MFMAs
-  auto gather = [&](int tap, bf16x8 (&bop)[2][KC]) {
-    const int dx = SIGN * (tap % 3 - 1), dy = SIGN * ((tap / 3) % 3 - 1), dz = SIGN * (tap / 9 - 1);
+  for (int g = 0; g < 9; ++g) {
+    if (g + 1 < 9) sload(g + 1);
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const int x = xs[b] + dx;
-      bool ok;
-      int xr;
-      if constexpr (SIGN > 0) {
-        xr = x < 0 ? 0 : (x >= tb.nx ? tb.nx - 1 : x);
-        ok = valid[b];
-      } else {
-        ok = valid[b] && x >= 0 && x < tb.nx;
-        xr = ok ? x : 0;
-      }
-      const int64_t nb = wrap_index(tb, xr, ys[b] + dy, zs[b] + dz);
+    for (int d = 0; d < 3; ++d) {
+      const int tap = 3 * g + d;
+      const int buf = tap & 1;
+      if (tap + 1 < NTAP) load_w(tap + 1);
+      const int dx = SIGN * (d - 1);
+      bf16x8 bop[2][KC];
 #pragma unroll
-      for (int kc = 0; kc < KC; ++kc) {
-        if (ok) {
-          bop[b][kc] = *(const bf16x8*)(in + aidx(tb, nb, kc * 16 + khalf));
-        } else {
-#pragma unroll
-          for (int j = 0; j < 8; ++j) bop[b][kc][j] = (bf16)0.f;
-        }
-      }
-    }
-  };
-  // the adjoint's share of a ghost: at a wall node the forward took the ghost of
-  // tap dx = -1 at x = 0 (dx = +1 at x = nx - 1) from the wall node itself, so the
-  // wall node also collects in(wall node) under that tap; the two operands are
-  // added in FP32 and rounded once (wall lanes only, loaded when used)
-  auto ghost = [&](int tap, bf16x8 (&bop)[2][KC]) {
-    const int dx = SIGN * (tap % 3 - 1), dy = SIGN * ((tap / 3) % 3 - 1), dz = SIGN * (tap / 9 - 1);
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const bool extra = valid[b] && ((xs[b] == 0 && dx == 1) || (xs[b] == tb.nx - 1 && dx == -1));
-      if (extra) {
-        const int64_t ne = wrap_index(tb, xs[b], ys[b] + dy, zs[b] + dz);
+      for (int b = 0; b < 2; ++b) {
+        const int x = xs[b] + dx;
+        const bool inside = x >= 0 && x < tb.nx;
+        const int row = pos[b] + 1 + (inside ? dx : 0);
+        const bool use = valid[b] && (SIGN > 0 || inside);
 #pragma unroll
         for (int kc = 0; kc < KC; ++kc) {
-          const bf16x8 e = *(const bf16x8*)(in + aidx(tb, ne, kc * 16 + khalf));
+          if (use) {
+            bop[b][kc] = *(const bf16x8*)(&sl[row * LS + kc * 16 + khalf]);
+          } else {
 #pragma unroll
-          for (int j = 0; j < 8; ++j) bop[b][kc][j] = (bf16)((float)bop[b][kc][j] + (float)e[j]);
+            for (int e = 0; e < 8; ++e) bop[b][kc][e] = (bf16)0.f;
+          }
+        }
+        if constexpr (SIGN < 0) {
+          // the ghost's share: at a wall node the forward took the ghost of tap
+          // dx = -1 at x = 0 (dx = +1 at x = nx - 1) from the wall node itself, so
+          // the wall node also collects in(wall node) under that tap; the two
+          // operands are added in FP32 and rounded once
+          const bool wall = valid[b] && ((xs[b] == 0 && dx == 1) || (xs[b] == tb.nx - 1 && dx == -1));
+          if (wall) {
+#pragma unroll
+            for (int kc = 0; kc < KC; ++kc) {
+              const bf16x8 e8 = *(const bf16x8*)(&sl[(pos[b] + 1) * LS + kc * 16 + khalf]);
+#pragma unroll
+              for (int e = 0; e < 8; ++e) bop[b][kc][e] = (bf16)((float)bop[b][kc][e] + (float)e8[e]);
+            }
+          }
         }
       }
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+          const bf16x8 a = *(const bf16x8*)(&wl[buf][(mb * 32 + (lane & 31)) * LS + kc * 16 + khalf]);
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            acc[mb][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bop[b][kc], acc[mb][b], 0, 0, 0);
+        }
+      if (tap + 1 < NTAP) store_w(buf ^ 1);
+      __syncthreads();
     }
-  };
-  bf16x8 bcur[2][KC], bnxt[2][KC];
-  gather(0, bcur);
-  for (int tap = 0; tap < NTAP; ++tap) {
-    const int buf = tap & 1;
-    if (tap + 1 < NTAP) {
-      load_w(tap + 1);
-      gather(tap + 1, bnxt);
+    if (g + 1 < 9) {
+      sstore();
+      __syncthreads();
     }
-    if constexpr (SIGN < 0) ghost(tap, bcur);
-#pragma unroll
-    for (int kc = 0; kc < KC; ++kc)
-#pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        const bf16x8 a = *(const bf16x8*)(&wl[buf][(mb * 32 + (lane & 31)) * LS + kc * 16 + khalf]);
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-          acc[mb][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bcur[b][kc], acc[mb][b], 0, 0, 0);
-      }
-    if (tap + 1 < NTAP) store_w(buf ^ 1);
-    __syncthreads();
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int kc = 0; kc < KC; ++kc) bcur[b][kc] = bnxt[b][kc];
   }
   // epilogue: lane holds channels co0 .. co0+3 of its node for each group g
 #pragma unroll
   for (int b = 0; b < 2; ++b) {
     if (!valid[b]) continue;
-    const int64_t gn = tb.base + node[b];
+    const int64_t gn = tb.base + t0 + pos[b];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
