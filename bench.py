@@ -10,7 +10,7 @@ the dominant kernel (timed with HIP events on the library's stream), the other
 storage precisions measured side by side with their per-field error against the
 FP32 run, and the FP64 CPU oracle timed on a bounded crop of the same workload.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32|fp32_fp32|fp16|bf16|fp64]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32|fp32_fp32|fp16|bf16|i16|fp64]
 """
 from __future__ import annotations
 
@@ -37,7 +37,7 @@ RECIPE_DEPARTURES = ("velocity perturbation band-limited (8 random-phase Fourier
 PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = ["lattice.hpp", "node_ops.hpp", "device_ops.hpp", "kernels.hpp", "inst_fp64.hip",
                   "inst_fp32_fp64.hip", "inst_weak.hip", "inst_cvt.hip", "inst_weak_cvt.hip", "inst_fp32.hip",
-                  "inst_fp16.hip", "inst_bf16.hip", "inst_jets.hip"]
+                  "inst_fp16.hip", "inst_bf16.hip", "inst_i16.hip", "inst_jets.hip"]
 
 
 def record_fields(M: int, weak: bool = False, cvt: bool = False) -> int:
@@ -192,12 +192,15 @@ def time_run(mc, params, fields, precision, steps, warmup):
     return sim, timing, stats
 
 
-def fields_after(mc, params, fields, precision, nsteps):
-    """The moments after nsteps from the initial fields (accuracy runs)."""
+def fields_after(mc, params, fields, precision, nsteps, info=None):
+    """The moments after nsteps from the initial fields (accuracy runs); with info
+    a dict, the number of range refits of fixed-point storage goes into it."""
     sim = mc.Sim(params, precision)
     sim.init_fields(**fields)
     sim.step(nsteps)
     out = sim.read_moments()
+    if info is not None:
+        info["range_refits"] = sim.range_refits()
     sim.close()
     return out
 
@@ -479,20 +482,23 @@ def main():
     progress("storage modes")
     variants = {}
     if not args.no_variants:
-        for name in ("fp32_fp32", "fp16", "bf16"):
+        for name in ("fp32_fp32", "fp16", "bf16", "i16"):
             if mc.PRECISIONS[name] == prec:
                 continue
             v, tv, st = time_run(mc, params, fields, mc.PRECISIONS[name], args.steps, args.warmup)
             v.close()
             del v
             vm = n / tv["median_s_per_step"] / 1e6
-            got = fields_after(mc, params, fields, mc.PRECISIONS[name], acc_steps)
+            info = {}
+            got = fields_after(mc, params, fields, mc.PRECISIONS[name], acc_steps, info)
             errs = rel_errors(got, ref)
             variants[name] = {"MLUPS": vm, "speedup_vs_" + args.precision: vm / mlups,
                               f"rel_linf_vs_{args.precision}_after_{acc_steps}_steps": errs,
                               "worst_field_error": max(errs.values()),
                               "meets_1e-3": bool(max(errs.values()) <= 1e-3),
                               "kernels_avg_ms": {k: x["avg_ms"] for k, x in st.items()}}
+            if name == "i16":
+                variants[name]["range_refits_in_accuracy_run"] = info["range_refits"]
             torch.cuda.empty_cache()
 
     def mode_run(p_, f_, precision, wk=False, cv=False):
@@ -508,7 +514,7 @@ def main():
         return out
 
     progress("coupling, property and boundary modes")
-    weak = weak_fp16 = cv_of_T = weak_cv_of_T = open_x = None
+    weak = weak_fp16 = weak_i16 = cv_of_T = weak_cv_of_T = open_x = None
     if not args.no_variants:
         # weak coupling (all M species lattices evolved) on the same workload: a
         # different model from strong coupling, so it is compared with itself
@@ -525,6 +531,16 @@ def main():
         weak_fp16[f"rel_linf_vs_weak_{args.precision}_after_{acc_steps}_steps"] = werrs
         weak_fp16["worst_field_error"] = max(werrs.values())
         weak_fp16["meets_1e-3"] = bool(max(werrs.values()) <= 1e-3)
+        # the same with 16-bit fixed-point storage
+        weak_i16 = mode_run(wp, fields, mc.MCLBM_I16, wk=True)
+        info = {}
+        wgot = fields_after(mc, wp, fields, mc.MCLBM_I16, acc_steps, info)
+        weak_i16["speedup_vs_weak_" + args.precision] = weak_i16["MLUPS"] / weak["MLUPS"]
+        werrs = rel_errors(wgot, wref)
+        weak_i16[f"rel_linf_vs_weak_{args.precision}_after_{acc_steps}_steps"] = werrs
+        weak_i16["worst_field_error"] = max(werrs.values())
+        weak_i16["meets_1e-3"] = bool(max(werrs.values()) <= 1e-3)
+        weak_i16["range_refits_in_accuracy_run"] = info["range_refits"]
         del wref, wgot
         # temperature-dependent heat capacities (cubic C_{a,v}(T), about twice the
         # constant part at the shear layer's T = 1) on the same workload
@@ -566,7 +582,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"fp32": "f32-store/f64-collide", "fp32_fp32": "f32", "fp64": "f64",
-                  "fp16": "f16-store/f32-collide", "bf16": "bf16-store/f32-collide"}[args.precision],
+                  "fp16": "f16-store/f32-collide", "bf16": "bf16-store/f32-collide",
+                  "i16": "i16-fixed-point-store/f32-collide"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"binary Kelvin-Helmholtz shear layer {args.n}^3 periodic, D3Q27, "
                                f"{M} species + momentum + energy lattices, strong coupling",
@@ -595,6 +612,7 @@ def main():
         "variants": variants,
         "weak_coupling": weak,
         "weak_fp16": weak_fp16,
+        "weak_i16": weak_i16,
         "cv_of_T": cv_of_T,
         "weak_cv_of_T": weak_cv_of_T,
         "open_x": open_x,

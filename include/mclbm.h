@@ -60,6 +60,24 @@ extern "C" {
 #define MCLBM_FP32_FP32 2 /* FP32 storage, FP32 collision                                   */
 #define MCLBM_FP16 3      /* FP16 storage of scaled deviations, FP32 collision               */
 #define MCLBM_BF16 4      /* BF16 storage of scaled deviations, FP32 collision               */
+#define MCLBM_I16 5       /* 16-bit fixed-point storage of deviations, FP32 collision (below) */
+/* MCLBM_I16 stores every population of lattice l, direction i as a 16-bit
+ * integer v with f = f_ref + v h / 32767, where f_ref and the half-width h are
+ * shared by the directions of a class (equal |c_x|, |c_y|, |c_z|), per lattice
+ * and tube; stores round stochastically. mclbm_init_fields measures the range
+ * each class takes in the initial state and in the 4 steps after it (run with
+ * wide tables and discarded: the transient of a sharp initial state), and fits
+ * f_ref to its middle and h to twice its half-spread, at least |f_ref|.
+ * mclbm_step reads a device flag per tube after steps 1, 2, 4 and every multiple
+ * of 8 (the step count alone sets these points, so the trajectory does not
+ * depend on how steps are split into calls or launched, and a tube of a batch
+ * evolves as it would alone; checkpoints keep the flags): when a value of a tube
+ * passed 3/4 of its range, that tube's tables are fitted to its current state
+ * again and its state is re-encoded (mclbm_range_refits counts this); when a
+ * value was clamped at the end of its range or was not finite, mclbm_step
+ * returns MCLBM_ESTATE and the state is lost. Strong and weak coupling, constant
+ * properties, periodic or walled x ends. The paper fixes no storage precision;
+ * this is a storage format of this library. */
 
 /* Kernel identifiers for mclbm_kernel_stats. */
 #define MCLBM_K_MOMENTS 0  /* moments of every lattice -> node record {Phi, omega, C_p} */
@@ -87,15 +105,15 @@ typedef struct {
                           strong coupling, constant properties, MCLBM_FP64 or MCLBM_FP32
                           (else MCLBM_EUNSUPPORTED). z is always periodic; y is
                           periodic unless wall_y */
-  int32_t precision;   /* MCLBM_FP64 .. MCLBM_BF16                                    */
+  int32_t precision;   /* MCLBM_FP64 .. MCLBM_I16                                     */
   int32_t weak;        /* 0: strong coupling (Sec. 3.5.2): species M is slaved to the
                           momentum lattice (eqs rhoMATCH, uMATCH) and not stored.
                           1: weak coupling (Sec. 3.5.1): all M species lattices are
                           stored and evolved; the species keep their own density and
                           velocity (eqs rhoSPEC, uSPEC) and Dalton pressure, and take
-                          T from the energy lattice. MCLBM_FP64, MCLBM_FP32 and
-                          MCLBM_FP16 (else MCLBM_EUNSUPPORTED); all tubes of a batch
-                          agree                                                     */
+                          T from the energy lattice. MCLBM_FP64, MCLBM_FP32,
+                          MCLBM_FP16 and MCLBM_I16 (else MCLBM_EUNSUPPORTED); all
+                          tubes of a batch agree                                    */
   int32_t wall_y;      /* 0: periodic in y; 1: free-slip walls at both y ends (half-way,
                           specular reflection), with periodic or walled x ends, either
                           coupling and either kind of properties; MCLBM_FP64 and
@@ -196,8 +214,15 @@ int mclbm_init_fields(mclbm_ctx *c, const double *X, const double *p, const doub
  * coupled as in Sec. 3.5 (strong: eqs rhoMATCH, uMATCH), then streaming with the
  * boundary rules of mclbm_params. Every non-local term (eqs Xalpha, corrFourier)
  * uses the moments of the same time level. MCLBM_EARG before the first
- * initialisation or for nsteps < 0; MCLBM_EDEVICE if a launch fails. */
+ * initialisation or for nsteps < 0; MCLBM_EDEVICE if a launch fails. With
+ * MCLBM_I16 storage it synchronises at each range check to read the range flags
+ * (see MCLBM_I16) and returns MCLBM_ESTATE if a value left its range. */
 int mclbm_step(mclbm_ctx *c, int64_t nsteps);
+
+/* MCLBM_I16 storage: how many times mclbm_step fitted the tables to the state and
+ * re-encoded it since the last mclbm_init_fields or mclbm_load (0 for other
+ * storage); -1 for a NULL context. */
+int64_t mclbm_range_refits(const mclbm_ctx *c);
 
 /* Macroscopic fields of the current state (Secs. 2.1, 2.5.3, 3.2): X [M][n],
  * rho [n], u [3][n], p [n], T [n] as doubles; any pointer may be NULL. on_device

@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libmclbm.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
 SOURCES = ["mclbm.hip", "nn.hip", "inst_fp64.hip", "inst_fp32_fp64.hip", "inst_weak.hip", "inst_cvt.hip",
-           "inst_weak_cvt.hip", "inst_fp32.hip", "inst_fp16.hip", "inst_bf16.hip", "inst_jets.hip"]
+           "inst_weak_cvt.hip", "inst_fp32.hip", "inst_fp16.hip", "inst_bf16.hip", "inst_i16.hip", "inst_jets.hip"]
 
 ARCH = os.environ.get("MCLBM_OFFLOAD_ARCH", "gfx950")
 # Packed FP32 instructions are switched off for all device code.

@@ -29,6 +29,17 @@ __device__ inline __bf16 cvt_sr_bf16(float x, uint32_t rnd)
   return o[0];
 }
 
+// Round x, a value in units of the storage quantum, to a 16-bit integer
+// stochastically: floor(x + r) with r uniform in [0, 1) from the upper 24 bits of
+// rnd (the sum is formed in FP32, so r is resolved to 2^-9 of a unit at |x| near
+// 2^15), clamped to +-32767.
+__device__ inline int16_t cvt_sr_i16(float x, uint32_t rnd)
+{
+  const float r = (float)(rnd >> 8) * 0x1p-24f;
+  const int v = (int)floorf(x + r);
+  return (int16_t)min(max(v, -32767), 32767);
+}
+
 // Convert an FP64 value to FP32 with stochastic rounding: a uniform random
 // number (the upper 24 bits of rnd) is added below the 29 mantissa bits that
 // FP32 drops, and those bits are then cut: the magnitude is rounded up with

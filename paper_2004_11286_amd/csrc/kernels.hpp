@@ -329,6 +329,84 @@ __global__ __launch_bounds__(BLOCK) void k_init(const Params<double>* __restrict
   if (threadIdx.x == 0) block_bad[w.block] = bad;
 }
 
+// Fixed-point storage: the smallest and largest stored integer of every lattice
+// and direction class of every tube, into out[((t MAXL + l) NCLS + k) 2 + {0, 1}]
+// (the host sets the entries to 32767 and -32767 first). A launch over the
+// linear numbering: every wavefront lies in one tube.
+template <int M, bool WEAK>
+__global__ __launch_bounds__(BLOCK) void k_range16(const Params<double>* __restrict__ P, Launch Ln,
+                                                   const int16_t* __restrict__ pop, int32_t* __restrict__ out)
+{
+  constexpr int L = Lat<M, WEAK>::L;
+  const Where w = locate(Ln);
+  const Params<double>& Pt = P[w.t];
+  int lo[L][NCLS], hi[L][NCLS];
+#pragma unroll
+  for (int l = 0; l < L; ++l)
+#pragma unroll
+    for (int k = 0; k < NCLS; ++k) {
+      lo[l][k] = 32767;
+      hi[l][k] = -32767;
+    }
+  if (w.node < Pt.n) {
+    const int16_t* pb = pop + pop_stride<M, WEAK>() * w.base;
+    const size_t n = (size_t)Pt.n;
+#pragma unroll
+    for (int l = 0; l < L; ++l)
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const int v = pb[(size_t)(l * Q + i) * n + w.node];
+        lo[l][ccls(i)] = min(lo[l][ccls(i)], v);
+        hi[l][ccls(i)] = max(hi[l][ccls(i)], v);
+      }
+  }
+#pragma unroll
+  for (int l = 0; l < L; ++l)
+#pragma unroll
+    for (int k = 0; k < NCLS; ++k) {
+      int a = lo[l][k], b = hi[l][k];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        a = min(a, __shfl_xor(a, off, 64));
+        b = max(b, __shfl_xor(b, off, 64));
+      }
+      if ((threadIdx.x & 63) == 0) {
+        int32_t* o = out + ((size_t)(w.t * MAXL + l) * NCLS + k) * 2;
+        atomicMin(o, a);
+        atomicMax(o + 1, b);
+      }
+    }
+}
+
+// Fixed-point storage: re-encode every stored value with new tables,
+// tab[((t MAXL + l) NCLS + k) 4 + {0, 1, 2, 3}] = old centre, old decoding
+// factor, new centre, new encoding factor of tube t, lattice l, class k; the new
+// integer is rounded stochastically (seeded by node, lattice and seed). A tube
+// whose old decoding factors are zero keeps its values.
+template <int M, bool WEAK>
+__global__ __launch_bounds__(BLOCK) void k_rebase16(const Params<double>* __restrict__ P, Launch Ln,
+                                                    int16_t* __restrict__ pop, const double* __restrict__ tab,
+                                                    uint32_t seed)
+{
+  constexpr int L = Lat<M, WEAK>::L;
+  const Where w = locate(Ln);
+  const Params<double>& Pt = P[w.t];
+  if (w.node >= Pt.n || tab[(size_t)w.t * MAXL * NCLS * 4 + 1] == 0.0) return;
+  int16_t* pb = pop + pop_stride<M, WEAK>() * w.base;
+  const size_t n = (size_t)Pt.n;
+#pragma unroll
+  for (int l = 0; l < L; ++l) {
+    Rng rng(w.node, l + 32, seed);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const double* tb = tab + ((size_t)(w.t * MAXL + l) * NCLS + ccls(i)) * 4;
+      int16_t& v = pb[(size_t)(l * Q + i) * n + w.node];
+      const double f = tb[0] + double(v) * tb[1];
+      v = cvt_sr_i16(float((f - tb[2]) * tb[3]), rng.next());
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Dispatch over (storage, arithmetic, species count, walls, coupling, occupancy variant)
 // ---------------------------------------------------------------------------
@@ -364,6 +442,10 @@ struct Ops {
   void (*open_fix)(const void* P, const Launch& ln, void* dst, StepNo sn, unsigned grid, hipStream_t st);
   void (*field_sums)(const int64_t* tube_n, const Launch& ln, const double* X, const double* p, const double* T,
                      double* partial, unsigned grid, hipStream_t st);
+  // fixed-point storage only (else null): range of the stored integers, re-encoding
+  void (*range16)(const void* Pd, const Launch& ln, const void* pop, int32_t* out, unsigned grid, hipStream_t st);
+  void (*rebase16)(const void* Pd, const Launch& ln, void* pop, const double* tab, uint32_t seed, unsigned grid,
+                   hipStream_t st);
 };
 
 template <typename S, typename Rec, int M, int V, bool WEAK, bool CVT>
@@ -448,6 +530,19 @@ Ops make_ops()
                     double* partial, unsigned grid, hipStream_t st) {
     hipLaunchKernelGGL((k_field_sums<M>), dim3(grid), dim3(RED_BLOCK), 0, st, tube_n, ln, X, p, T, partial);
   };
+  o.range16 = nullptr;
+  o.rebase16 = nullptr;
+  if constexpr (is_fixed16<S>()) {
+    o.range16 = [](const void* Pd, const Launch& ln, const void* pop, int32_t* out, unsigned grid, hipStream_t st) {
+      hipLaunchKernelGGL((k_range16<M, WEAK>), dim3(grid), dim3(BLOCK), 0, st, (const Params<double>*)Pd, ln,
+                         (const int16_t*)pop, out);
+    };
+    o.rebase16 = [](const void* Pd, const Launch& ln, void* pop, const double* tab, uint32_t seed, unsigned grid,
+                    hipStream_t st) {
+      hipLaunchKernelGGL((k_rebase16<M, WEAK>), dim3(grid), dim3(BLOCK), 0, st, (const Params<double>*)Pd, ln,
+                         (int16_t*)pop, tab, seed);
+    };
+  }
   o.open_fix = nullptr;
   if constexpr (xbc(W) == BC_OPEN) {
     o.open_fix = [](const void* P, const Launch& ln, void* dst, StepNo sn, unsigned grid, hipStream_t st) {
@@ -536,5 +631,6 @@ bool pick_fp32_fp64(int M, int walls, int weak, int cvt, kern::Ops& o);
 bool pick_fp32(int M, int walls, int weak, int cvt, kern::Ops& o);
 bool pick_fp16(int M, int walls, int weak, int cvt, kern::Ops& o);
 bool pick_bf16(int M, int walls, int weak, int cvt, kern::Ops& o);
+bool pick_i16(int M, int walls, int weak, int cvt, kern::Ops& o);
 
 }  // namespace mclbm

@@ -31,6 +31,13 @@ __host__ __device__ constexpr int cz(int i) { return i % 3 - 1; }
 __host__ __device__ constexpr int cc(int i, int a) { return a == 0 ? cx(i) : (a == 1 ? cy(i) : cz(i)); }
 __host__ __device__ constexpr int csq(int i) { return cx(i) * cx(i) + cy(i) * cy(i) + cz(i) * cz(i); }
 __host__ __device__ constexpr int opp(int i) { return 26 - i; }
+// Class of a direction under the reflections of the three axes: the directions
+// with the same |c_x|, |c_y|, |c_z| (8 classes; the rest direction is class 0).
+__host__ __device__ constexpr int ccls(int i)
+{
+  return (cx(i) != 0 ? 1 : 0) + (cy(i) != 0 ? 2 : 0) + (cz(i) != 0 ? 4 : 0);
+}
+constexpr int NCLS = 8;
 
 // Values of a one-dimensional triplet at c = -1, 0, +1.
 template <typename R>
@@ -69,7 +76,10 @@ __host__ __device__ constexpr double w13(int i) { return w13_1d(cx(i)) * w13_1d(
 
 // Per-context constants, resident in device memory and read through uniform loads.
 // Populations are stored as scaled deviations d = s_l (f - f_ref,l,i) from a
-// symmetric reference equilibrium (zero velocity), so f_ref,i = f_ref,opp(i).
+// reference that is the same for all directions of a class (ccls), so
+// f_ref,i = f_ref,opp(i), and its first and mixed second moments vanish: the
+// equilibrium at rest of the mean state, or, with 16-bit fixed-point storage, the
+// centre of the range each class of each lattice takes.
 template <typename R>
 struct Params {
   int32_t M, nx, ny, nz;
@@ -84,8 +94,12 @@ struct Params {
   R phi[MAXM][MAXM];      // Wilke's phi_ab
   R ref[MAXL][Q];         // reference populations f_ref
   R ref0[MAXL];           // sum_i f_ref (zeroth moment)
-  R ref2[MAXL];           // sum_i f_ref c_ia^2 (diagonal second moment, isotropic)
+  R ref2[MAXL][3];        // sum_i f_ref c_ia^2 (diagonal second moments)
   R scale[MAXL], inv_scale[MAXL];
+  // 16-bit fixed-point storage: a stored integer v of lattice l, direction i is
+  // f = f_ref,l,i + v inv_qs[l][ccls(i)]; qs is the encoding factor
+  R qs[MAXL][NCLS], inv_qs[MAXL][NCLS];
+  uint32_t* range_flag;   // fixed-point storage: bit 0 a value passed 3/4 of its range, bit 1 one was clamped
   R inl[MAXL][Q];         // open x ends and the jet at x = 0: inlet equilibrium minus f_ref, per stored lattice
   R inl2[MAXL][Q];        // opposed jets: the jet at x = nx - 1
   R absent_tol;           // |rho_a| <= absent_tol * rho: species absent, V_a = 0

@@ -186,6 +186,7 @@ bool pick_ops(int precision, int M, int walls, int weak, int cvt, Ops& o)
     case MCLBM_FP32_FP32: return pick_fp32(M, walls, weak, cvt, o);
     case MCLBM_FP16: return pick_fp16(M, walls, weak, cvt, o);
     case MCLBM_BF16: return pick_bf16(M, walls, weak, cvt, o);
+    case MCLBM_I16: return pick_i16(M, walls, weak, cvt, o);
     default: return false;
   }
 }
@@ -201,8 +202,7 @@ struct TubeHost {
   int nx = 0, ny = 0, nz = 0;
   int64_t n = 0, base = 0;
   HostSpecies hs{};
-  double ref[MAXL][Q] = {};
-  double ref0[MAXL] = {}, ref2[MAXL] = {}, scale[MAXL] = {};
+  RefTables tab{};
   double inlet[MAXM + 5] = {};   // open x ends and the jet at x = 0: X (M), p, T, u (3)
   double inlet2[MAXM + 5] = {};  // opposed jets: the jet at x = nx - 1
   int noz0 = 0, noz1 = 0;        // opposed jets: nozzle rows
@@ -239,6 +239,10 @@ struct mclbm_ctx {
   double* partial = nullptr;
   double* reduced = nullptr;
   int* bad = nullptr;
+  uint32_t* dFlag = nullptr;      // fixed point: range flag per tube (bit 0 re-range, bit 1 a value clamped)
+  int32_t* dRange = nullptr;      // fixed point: k_range16 output [ntubes][MAXL][NCLS][2]
+  double* dTab = nullptr;         // fixed point: k_rebase16 tables [ntubes][MAXL][NCLS][4]
+  int64_t reranges = 0;           // fixed point: re-encodings since mclbm_init_fields or mclbm_load
   int cur = 0;
   int64_t steps = 0;
   bool initialised = false;
@@ -267,7 +271,7 @@ struct mclbm_ctx {
 namespace {
 
 struct Layout {
-  size_t pd, pr, tubes, blk, blkT, tube_n, ctr, pop, rec, G, staging, partial, reduced, bad, total;
+  size_t pd, pr, tubes, blk, blkT, tube_n, ctr, flag, range, tab, pop, rec, G, staging, partial, reduced, bad, total;
   int64_t n, nblocks, nblocks_tmax;
 };
 
@@ -284,7 +288,7 @@ size_t storage_bytes(int precision)
 {
   switch (precision) {
     case MCLBM_FP64: return 8;
-    case MCLBM_FP16: case MCLBM_BF16: return 2;
+    case MCLBM_FP16: case MCLBM_BF16: case MCLBM_I16: return 2;
     default: return 4;
   }
 }
@@ -328,6 +332,9 @@ Layout layout_for(const mclbm_params* tp, int ntubes)
   l.blkT = off; off += align_up(sizeof(int32_t) * l.nblocks_tmax);
   l.tube_n = off; off += align_up(sizeof(int64_t) * ntubes);
   l.ctr = off; off += align_up(sizeof(uint32_t));
+  l.flag = off; off += align_up(sizeof(uint32_t) * ntubes);
+  l.range = off; off += align_up(sizeof(int32_t) * ntubes * MAXL * NCLS * 2);
+  l.tab = off; off += align_up(sizeof(double) * ntubes * MAXL * NCLS * 4);
   l.pop = off; off += 2 * align_up((size_t)L * Q * l.n * s_bytes);
   l.rec = off; off += align_up((size_t)rec_fields * l.n * r_bytes);
   l.G = off; off += align_up((size_t)3 * l.n * r_bytes);
@@ -397,7 +404,7 @@ int validate_one(const mclbm_params* p, std::string& err)
     }
   }
   if (p->wall_x && p->nx < 2) { err = "walls need nx >= 2"; return MCLBM_EARG; }
-  if (p->precision < MCLBM_FP64 || p->precision > MCLBM_BF16) { err = "unknown precision"; return MCLBM_EARG; }
+  if (p->precision < MCLBM_FP64 || p->precision > MCLBM_I16) { err = "unknown precision"; return MCLBM_EARG; }
   if (p->weak != 0 && p->weak != 1) { err = "weak must be 0 or 1"; return MCLBM_EARG; }
   if (p->wall_y < 0 || p->wall_y > 2) { err = "wall_y must be 0, 1 or 2"; return MCLBM_EARG; }
   if (p->wall_y == 1) {
@@ -407,8 +414,9 @@ int validate_one(const mclbm_params* p, std::string& err)
       return MCLBM_EUNSUPPORTED;
     }
   }
-  if (p->weak && p->precision != MCLBM_FP64 && p->precision != MCLBM_FP32 && p->precision != MCLBM_FP16) {
-    err = "weak coupling is compiled for MCLBM_FP64, MCLBM_FP32 and MCLBM_FP16 only";
+  if (p->weak && p->precision != MCLBM_FP64 && p->precision != MCLBM_FP32 && p->precision != MCLBM_FP16 &&
+      p->precision != MCLBM_I16) {
+    err = "weak coupling is compiled for MCLBM_FP64, MCLBM_FP32, MCLBM_FP16 and MCLBM_I16 only";
     return MCLBM_EUNSUPPORTED;
   }
   if (p->transport_exp) {
@@ -545,10 +553,10 @@ int push_params(mclbm_ctx* c)
   const double tol = absent_tol_for(c->precision);
   for (int t = 0; t < c->ntubes; ++t) {
     const TubeHost& th = c->tubes[t];
-    fill_params<double>(c->hPd[t], th.hs, th.nx, th.ny, th.nz, c->wall_x, c->L, th.ref, th.ref0, th.ref2, th.scale,
-                        tol, th.noz0, th.noz1);
-    fill_params<float>(c->hPf[t], th.hs, th.nx, th.ny, th.nz, c->wall_x, c->L, th.ref, th.ref0, th.ref2, th.scale,
-                       tol, th.noz0, th.noz1);
+    fill_params<double>(c->hPd[t], th.hs, th.nx, th.ny, th.nz, c->wall_x, c->L, th.tab, tol, c->dFlag + t, th.noz0,
+                        th.noz1);
+    fill_params<float>(c->hPf[t], th.hs, th.nx, th.ny, th.nz, c->wall_x, c->L, th.tab, tol, c->dFlag + t, th.noz0,
+                       th.noz1);
     // the inlet equilibria of every stored lattice, as deviations from f_ref: the
     // initialisation of one node (n = 1, unit scale) at the inlet fields (open x
     // ends: one inlet; opposed jets: one per x face)
@@ -673,23 +681,96 @@ double round_to_storage(int precision, double v)
 double absent_tol_for(int precision)
 {
   switch (precision) {
-    case MCLBM_FP16: return 1e-4;
+    case MCLBM_FP16: case MCLBM_I16: return 1e-4;
     case MCLBM_BF16: return 1e-3;
     default: return 1e-12;
   }
 }
 
 // Reference tables of every tube from its mean state, rounded to storage.
+// 16-bit fixed-point storage (MCLBM_I16). Each class k of directions (equal
+// |c_x|, |c_y|, |c_z|) of each stored lattice l has a centre f_ref and a
+// half-width h: a population f is stored as the integer nearest (stochastically)
+// to (f - f_ref) 32767 / h. The first tables of mclbm_init_fields centre every
+// class on the mean state's equilibrium at rest with a half-width of
+// FIX_FIRST_RANGE times that value; k_range16 then measures what the state takes
+// and fit_class sets the half-width to FIX_MARGIN times the measured one (at
+// least the centre's magnitude). During
+// the steps a value past 3/4 of its range (the margin partly used) makes the
+// host fit the tables again to the state and re-encode it (rerange).
+constexpr double FIX_FIRST_RANGE = 64.0;
+int check_launch(mclbm_ctx* c, const char* what);
+constexpr double FIX_MARGIN = 2.0;
+constexpr int FIX_CHECK_STEPS = 8;    // steps between reads of the range flag
+constexpr double FIX_REL = 1.0;       // least half-width, relative to the class's centre
+// Steps the initialisation takes (and discards) with its first, wide tables to see
+// the range of the transient that follows the initial state. The classes of small
+// weight (edges and corners at a low lattice temperature R_a T) hold equilibrium
+// values far below the non-equilibrium parts that a sharp front adds to them (a
+// diffusion or heat flux enters at a lower power of the weight): in the ternary
+// tube's second step a species' corner populations leave a range fitted to the
+// initial equilibria fifteen times over, and the energy lattice's x faces four
+// times; the excursion is largest in the first steps and decays after.
+constexpr int FIX_PROBE_STEPS = 4;
+int eager_step(mclbm_ctx* c);
+
+// Tables of class k of lattice l: centre and decoding factor rounded to FP32 (the
+// FP32 and FP64 kernels then decode a value alike), encoding factor its inverse.
+void set_class(RefTables& tb, int l, int k, double centre, double half)
+{
+  const double ce = (double)(float)centre;
+  const double inv = (double)(float)(half / 32767.0);
+  for (int i = 0; i < Q; ++i)
+    if (ccls(i) == k) tb.ref[l][i] = ce;
+  tb.inv_qs[l][k] = inv;
+  tb.qs[l][k] = (double)(float)(1.0 / inv);
+}
+
+// Floor of a class's half-width: a millionth of the lattice's largest reference
+// magnitude (a class that holds one value everywhere still gets a range).
+double class_floor(const RefTables& tb, int l)
+{
+  double mx = 0.0;
+  for (int i = 0; i < Q; ++i) mx = std::max(mx, std::fabs(tb.ref[l][i]));
+  return mx > 0.0 ? 1e-6 * mx : 1e-20;
+}
+
+// Fit class k of lattice l to the stored integers lo..hi (current tables): centre
+// the middle of the values, half-width FIX_MARGIN times their half-spread plus
+// one storage unit, and at least FIX_REL times the centre's magnitude (a
+// population may double). The floor matters where the values of a class barely
+// differ over the grid (the moving populations of a gas at rest at uniform
+// pressure): a flow that starts later moves such a population by about
+// (c_i . u / theta) of itself. In the ternary tube the diffusion-driven flow
+// moves the momentum lattice's x faces by up to 56% of themselves within 30
+// steps (up to 30% in one step) and the energy lattice's rest population by 1.4
+// times its initial spread; a floor of an eighth of the centre, or none, lets
+// them reach the end of the range between two checks.
+void fit_class(RefTables& tb, int l, int k, int32_t lo, int32_t hi)
+{
+  int i0 = 0;
+  while (ccls(i0) != k) ++i0;
+  const double c0 = tb.ref[l][i0], inv0 = tb.inv_qs[l][k];
+  const double flo = c0 + lo * inv0, fhi = c0 + hi * inv0;
+  const double centre = 0.5 * (flo + fhi);
+  const double half = FIX_MARGIN * (0.5 * (fhi - flo) + inv0);
+  set_class(tb, l, k, centre, std::max({half, FIX_REL * std::fabs(centre), class_floor(tb, l)}));
+}
+
+// Reference tables of every tube from its mean state, rounded to storage (for
+// fixed point: the first, wide tables).
 int upload_params(mclbm_ctx* c, const std::vector<RefState>& rs)
 {
   for (int t = 0; t < c->ntubes; ++t) {
     TubeHost& th = c->tubes[t];
-    reference_tables(th.hs, c->L - 2, rs[t], th.ref, th.ref0, th.ref2);
-    for (int l = 0; l < MAXL; ++l) th.scale[l] = 1.0;
+    RefTables& tb = th.tab;
+    reference_tables(th.hs, c->L - 2, rs[t], tb);
+    for (int l = 0; l < MAXL; ++l) {
+      tb.scale[l] = 1.0;
+      for (int k = 0; k < NCLS; ++k) tb.qs[l][k] = tb.inv_qs[l][k] = 0.0;
+    }
     for (int l = 0; l < c->L; ++l) {
-      th.scale[l] = scale_for(c->precision, th.ref[l]);
-      th.ref0[l] = 0.0;
-      th.ref2[l] = 0.0;
+      tb.scale[l] = scale_for(c->precision, tb.ref[l]);
       // FP32 storage of FP64 arithmetic keeps the species populations themselves
       // (reference zero): the stochastic rounding of a store is then relative to
       // the population, so a nearly absent species is not buried in rounding
@@ -697,14 +778,87 @@ int upload_params(mclbm_ctx* c, const std::vector<RefState>& rs)
       // diffusion velocity from noise)
       const bool absolute = c->precision == MCLBM_FP32 && l < c->L - 2;
       for (int i = 0; i < Q; ++i) {
-        if (absolute) th.ref[l][i] = 0.0;
-        th.ref[l][i] = round_to_storage(c->precision, th.ref[l][i] * th.scale[l]) / th.scale[l];
-        th.ref0[l] += th.ref[l][i];
-        th.ref2[l] += th.ref[l][i] * cx(i) * cx(i);
+        if (absolute) tb.ref[l][i] = 0.0;
+        tb.ref[l][i] = round_to_storage(c->precision, tb.ref[l][i] * tb.scale[l]) / tb.scale[l];
+      }
+      if (c->precision == MCLBM_I16) {
+        const double fl = class_floor(tb, l);
+        for (int k = 0; k < NCLS; ++k) {
+          int i0 = 0;
+          while (ccls(i0) != k) ++i0;
+          const double r = tb.ref[l][i0];
+          set_class(tb, l, k, r, FIX_FIRST_RANGE * std::max(std::fabs(r), fl));
+        }
       }
     }
+    reference_moments(tb, c->L);
   }
   return push_params(c);
+}
+
+// Fixed point: the smallest and largest stored integer of every tube, lattice and
+// class of the current state, mm[((t MAXL + l) NCLS + k) 2 + {0, 1}].
+int measure_ranges(mclbm_ctx* c, std::vector<int32_t>& mm)
+{
+  const size_t cnt = (size_t)c->ntubes * MAXL * NCLS * 2;
+  mm.assign(cnt, 0);
+  for (size_t j = 0; j < cnt; j += 2) {
+    mm[j] = 32767;
+    mm[j + 1] = -32767;
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->dRange, mm.data(), sizeof(int32_t) * cnt, hipMemcpyHostToDevice, c->stream));
+  c->ops.range16(c->dPd, launch_all(c), c->pop[c->cur], c->dRange, (unsigned)c->nblocks, c->stream);
+  int rc = check_launch(c, "k_range16");
+  if (rc) return rc;
+  HIP_TRY(c, hipMemcpyAsync(mm.data(), c->dRange, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return MCLBM_OK;
+}
+
+int clear_range_flags(mclbm_ctx* c)
+{
+  HIP_TRY(c, hipMemsetAsync(c->dFlag, 0, sizeof(uint32_t) * c->ntubes, c->stream));
+  return MCLBM_OK;
+}
+
+// Fixed point: fit every class of the tubes whose flag asks for it to the current
+// state and re-encode their state with the new tables (k_rebase16; the other
+// tubes keep theirs: a zero old decoding factor marks them), then upload the
+// tables and clear the flags.
+int rerange(mclbm_ctx* c, const std::vector<uint32_t>& flags)
+{
+  std::vector<int32_t> mm;
+  int rc = measure_ranges(c, mm);
+  if (rc) return rc;
+  std::vector<double> tab((size_t)c->ntubes * MAXL * NCLS * 4, 0.0);
+  for (int t = 0; t < c->ntubes; ++t) {
+    if (!(flags[t] & 1u)) continue;
+    c->reranges += 1;
+    RefTables& tb = c->tubes[t].tab;
+    for (int l = 0; l < c->L; ++l)
+      for (int k = 0; k < NCLS; ++k) {
+        const size_t j = ((size_t)t * MAXL + l) * NCLS + k;
+        const int32_t lo = mm[2 * j], hi = mm[2 * j + 1];
+        if (lo <= -32767 || hi >= 32767)
+          return fail(c, MCLBM_ESTATE, "fixed-point storage: a stored value reached the end of its range");
+        int i0 = 0;
+        while (ccls(i0) != k) ++i0;
+        tab[4 * j + 0] = tb.ref[l][i0];
+        tab[4 * j + 1] = tb.inv_qs[l][k];
+        fit_class(tb, l, k, lo, hi);
+        tab[4 * j + 2] = tb.ref[l][i0];
+        tab[4 * j + 3] = tb.qs[l][k];
+      }
+    reference_moments(tb, c->L);
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->dTab, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice, c->stream));
+  c->ops.rebase16(c->dPd, launch_all(c), c->pop[c->cur], c->dTab, (uint32_t)c->steps * 0x9E3779B1u + 0x5bd1e995u,
+                  (unsigned)c->nblocks, c->stream);
+  rc = check_launch(c, "k_rebase16");
+  if (rc) return rc;
+  rc = push_params(c);   // synchronises the stream first: the tables are read by k_rebase16
+  if (rc) return rc;
+  return clear_range_flags(c);
 }
 
 int record_event(mclbm_ctx* c, int& idx)
@@ -984,6 +1138,9 @@ extern "C" int mclbm_batch_create(const mclbm_params* tp, int32_t ntubes, void* 
   c->dBlkTubeT = (int32_t*)(ws + lay.blkT);
   c->dTubeN = (int64_t*)(ws + lay.tube_n);
   c->dStepCtr = (uint32_t*)(ws + lay.ctr);
+  c->dFlag = (uint32_t*)(ws + lay.flag);
+  c->dRange = (int32_t*)(ws + lay.range);
+  c->dTab = (double*)(ws + lay.tab);
   const size_t popb = align_up((size_t)c->L * Q * c->n * c->ops.s_bytes);
   c->pop[0] = ws + lay.pop;
   c->pop[1] = ws + lay.pop + popb;
@@ -1178,25 +1335,88 @@ extern "C" int mclbm_init_fields(mclbm_ctx* c, const double* X, const double* p,
   // the tube sizes of k_init come from the parameter blocks
   int rc = upload_params(c, rs);
   if (rc) return rc;
-  c->ops.init(c->dPd, launch_all(c), dX, dp, dT, du, c->pop[0], c->bad, (unsigned)c->nblocks, c->stream);
-  rc = check_launch(c, "k_init");
-  if (rc) return rc;
-  std::vector<int> bad(c->nblocks);
-  HIP_TRY(c, hipMemcpyAsync(bad.data(), c->bad, sizeof(int) * c->nblocks, hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  for (int64_t b = 0; b < c->nblocks; ++b)
-    if (bad[b]) return fail(c, MCLBM_ESTATE, "infeasible initial state: need T > 0, p > 0, R_a T + u^2 < 1");
   c->cur = 0;
+  // fixed point: initialise with the first (wide) tables, measure the range the
+  // state and the FIX_PROBE_STEPS steps after it take, fit the tables to it and
+  // initialise again; a class found at the end of its range is widened and
+  // measured again. Each tube goes through these passes on its own (a tube's
+  // tables do not depend on the other tubes).
+  std::vector<char> fitted(c->ntubes, 0), done(c->ntubes, 0);
+  for (int pass = 0;; ++pass) {
+    c->cur = 0;
+    c->steps = 0;
+    c->ops.init(c->dPd, launch_all(c), dX, dp, dT, du, c->pop[0], c->bad, (unsigned)c->nblocks, c->stream);
+    rc = check_launch(c, "k_init");
+    if (rc) return rc;
+    std::vector<int> bad(c->nblocks);
+    HIP_TRY(c, hipMemcpyAsync(bad.data(), c->bad, sizeof(int) * c->nblocks, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (int64_t b = 0; b < c->nblocks; ++b)
+      if (bad[b]) return fail(c, MCLBM_ESTATE, "infeasible initial state: need T > 0, p > 0, R_a T + u^2 < 1");
+    if (c->precision != MCLBM_I16) break;
+    if (pass >= 8) return fail(c, MCLBM_ESTATE, "fixed-point storage: no range found that holds the initial state");
+    std::vector<int32_t> m0, mu;
+    if ((rc = measure_ranges(c, m0))) return rc;
+    mu = m0;
+    bool probe = false;
+    for (int t = 0; t < c->ntubes; ++t) probe = probe || !fitted[t];
+    if (probe) {                          // the transient, with the wide tables
+      const bool timing = c->timing;
+      c->timing = false;
+      for (int k = 0; k < FIX_PROBE_STEPS && !rc; ++k) {
+        std::vector<int32_t> mk;
+        if (!(rc = eager_step(c)) && !(rc = measure_ranges(c, mk)))
+          for (size_t j = 0; j < mu.size(); j += 2) {
+            mu[j] = std::min(mu[j], mk[j]);
+            mu[j + 1] = std::max(mu[j + 1], mk[j + 1]);
+          }
+      }
+      c->timing = timing;
+      if (rc) return rc;
+    }
+    bool all_done = true;
+    for (int t = 0; t < c->ntubes; ++t) {
+      if (done[t]) continue;
+      RefTables& tb = c->tubes[t].tab;
+      const std::vector<int32_t>& mm = fitted[t] ? m0 : mu;
+      bool clamped = false;
+      for (int l = 0; l < c->L; ++l)
+        for (int k = 0; k < NCLS; ++k) {
+          const size_t j = ((size_t)t * MAXL + l) * NCLS + k;
+          if (mm[2 * j] > -32767 && mm[2 * j + 1] < 32767) continue;
+          int i0 = 0;
+          while (ccls(i0) != k) ++i0;
+          set_class(tb, l, k, tb.ref[l][i0], FIX_FIRST_RANGE * 32767.0 * tb.inv_qs[l][k]);
+          clamped = true;
+        }
+      if (!clamped && fitted[t]) {
+        done[t] = 1;
+        continue;
+      }
+      all_done = false;
+      fitted[t] = !clamped;
+      if (fitted[t])
+        for (int l = 0; l < c->L; ++l)
+          for (int k = 0; k < NCLS; ++k) {
+            const size_t j = ((size_t)t * MAXL + l) * NCLS + k;
+            fit_class(tb, l, k, mu[2 * j], mu[2 * j + 1]);
+          }
+      reference_moments(tb, c->L);
+    }
+    if (all_done) break;
+    if ((rc = push_params(c))) return rc;
+  }
+  if (c->precision == MCLBM_I16 && (rc = clear_range_flags(c))) return rc;
+  c->reranges = 0;
   c->steps = 0;
   c->initialised = true;
   return MCLBM_OK;
 }
 
-extern "C" int mclbm_step(mclbm_ctx* c, int64_t nsteps)
+namespace {
+// nsteps steps: graph replays where chosen, the rest eager.
+int plain_steps(mclbm_ctx* c, int64_t nsteps)
 {
-  if (!c) return MCLBM_EARG;
-  if (!c->initialised) return fail(c, MCLBM_EARG, "mclbm_init_fields or mclbm_load first");
-  if (nsteps < 0) return fail(c, MCLBM_EARG, "nsteps must be non-negative");
   if (c->lc.graph_steps > 0 && !c->timing) {
     int rc = graph_steps(c, nsteps);
     if (rc) return rc;
@@ -1207,6 +1427,59 @@ extern "C" int mclbm_step(mclbm_ctx* c, int64_t nsteps)
   }
   return MCLBM_OK;
 }
+
+// Fixed point: the step counts after which the host reads the range flags, the
+// powers of two below FIX_CHECK_STEPS (the transient of a sharp initial state)
+// and the multiples of FIX_CHECK_STEPS. They depend on the step count only, not
+// on how the steps are split into calls or launched (a checkpoint keeps the
+// flags), so every split and launch choice gives the same trajectory.
+int64_t next_check(int64_t steps)
+{
+  if (steps < FIX_CHECK_STEPS) {
+    int64_t p = 1;
+    while (p <= steps) p *= 2;
+    return p;
+  }
+  return (steps / FIX_CHECK_STEPS + 1) * FIX_CHECK_STEPS;
+}
+
+// Fixed point: steps up to each check; there a value clamped or not finite is an
+// error, and the tubes with a value past 3/4 of its range are re-ranged.
+int fixed16_steps(mclbm_ctx* c, int64_t nsteps)
+{
+  while (nsteps > 0) {
+    const int64_t m = std::min(nsteps, next_check(c->steps) - c->steps);
+    nsteps -= m;
+    int rc = plain_steps(c, m);
+    if (rc) return rc;
+    if (next_check(c->steps - 1) != c->steps) continue;
+    std::vector<uint32_t> flags(c->ntubes);
+    HIP_TRY(c, hipMemcpyAsync(flags.data(), c->dFlag, sizeof(uint32_t) * c->ntubes, hipMemcpyDeviceToHost,
+                              c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    uint32_t any = 0;
+    for (int t = 0; t < c->ntubes; ++t) {
+      if (flags[t] & 2u)
+        return fail(c, MCLBM_ESTATE, "fixed-point storage: a value of tube " + std::to_string(t) +
+                                         " left its range or was not finite (step " + std::to_string(c->steps) + ")");
+      any |= flags[t];
+    }
+    if (any && (rc = rerange(c, flags))) return rc;
+  }
+  return MCLBM_OK;
+}
+}  // namespace
+
+extern "C" int mclbm_step(mclbm_ctx* c, int64_t nsteps)
+{
+  if (!c) return MCLBM_EARG;
+  if (!c->initialised) return fail(c, MCLBM_EARG, "mclbm_init_fields or mclbm_load first");
+  if (nsteps < 0) return fail(c, MCLBM_EARG, "nsteps must be non-negative");
+  if (c->precision == MCLBM_I16) return fixed16_steps(c, nsteps);
+  return plain_steps(c, nsteps);
+}
+
+extern "C" int64_t mclbm_range_refits(const mclbm_ctx* c) { return c ? c->reranges : -1; }
 
 extern "C" int mclbm_read_moments(mclbm_ctx* c, double* X, double* rho, double* u, double* p, double* T,
                                   int on_device)
@@ -1314,10 +1587,11 @@ struct CkptHeader {
   int64_t steps;
 };
 struct CkptTube {
-  int32_t nx, ny, nz, pad;
-  double ref[MAXL][Q], ref0[MAXL], ref2[MAXL], scale[MAXL];
+  int32_t nx, ny, nz;
+  uint32_t range_flag;   // fixed point: the tube's range flag between two checks
+  RefTables tab;
 };
-const char kMagic[8] = "MCLBMv3";
+const char kMagic[8] = "MCLBMv4";
 
 size_t header_bytes(const mclbm_ctx* c) { return sizeof(CkptHeader) + sizeof(CkptTube) * c->ntubes; }
 }  // namespace
@@ -1338,16 +1612,20 @@ extern "C" int mclbm_save(mclbm_ctx* c, void* host_buf, size_t bytes)
   h.M = c->M; h.wall_x = c->wall_x | (c->wall_y << 2);   // the x and y boundary kinds
   h.precision = c->precision; h.ntubes = c->ntubes; h.weak = c->weak; h.cvt = c->cvt;
   h.steps = c->steps;
+  std::vector<uint32_t> flags(c->ntubes, 0);
+  if (c->precision == MCLBM_I16) {
+    HIP_TRY(c, hipMemcpyAsync(flags.data(), c->dFlag, sizeof(uint32_t) * c->ntubes, hipMemcpyDeviceToHost,
+                              c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
   char* dst = (char*)host_buf;
   std::memcpy(dst, &h, sizeof(h));
   for (int t = 0; t < c->ntubes; ++t) {
     const TubeHost& th = c->tubes[t];
     CkptTube ct{};
     ct.nx = th.nx; ct.ny = th.ny; ct.nz = th.nz;
-    std::memcpy(ct.ref, th.ref, sizeof(ct.ref));
-    std::memcpy(ct.ref0, th.ref0, sizeof(ct.ref0));
-    std::memcpy(ct.ref2, th.ref2, sizeof(ct.ref2));
-    std::memcpy(ct.scale, th.scale, sizeof(ct.scale));
+    ct.range_flag = flags[t];
+    ct.tab = th.tab;
     std::memcpy(dst + sizeof(h) + sizeof(CkptTube) * t, &ct, sizeof(ct));
   }
   HIP_TRY(c, hipMemcpyAsync(dst + header_bytes(c), c->pop[c->cur], (size_t)c->L * Q * c->n * c->ops.s_bytes,
@@ -1376,10 +1654,7 @@ extern "C" int mclbm_load(mclbm_ctx* c, const void* host_buf, size_t bytes)
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   for (int t = 0; t < c->ntubes; ++t) {
     TubeHost& th = c->tubes[t];
-    std::memcpy(th.ref, ct[t].ref, sizeof(th.ref));
-    std::memcpy(th.ref0, ct[t].ref0, sizeof(th.ref0));
-    std::memcpy(th.ref2, ct[t].ref2, sizeof(th.ref2));
-    std::memcpy(th.scale, ct[t].scale, sizeof(th.scale));
+    th.tab = ct[t].tab;
   }
   int rc = push_params(c);
   if (rc) return rc;
@@ -1388,6 +1663,14 @@ extern "C" int mclbm_load(mclbm_ctx* c, const void* host_buf, size_t bytes)
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->cur = 0;
   c->steps = h.steps;
+  c->reranges = 0;
+  if (c->precision == MCLBM_I16) {
+    std::vector<uint32_t> flags(c->ntubes);
+    for (int t = 0; t < c->ntubes; ++t) flags[t] = ct[t].range_flag;
+    HIP_TRY(c, hipMemcpyAsync(c->dFlag, flags.data(), sizeof(uint32_t) * c->ntubes, hipMemcpyHostToDevice,
+                              c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
   c->initialised = true;
   return MCLBM_OK;
 }

@@ -434,7 +434,7 @@ __host__ __device__ __forceinline__ void state_node(const Params<double>& P, con
     D r = 0.0, ja[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const D d = load_dev<S, D>(at32(pop + (size_t)(a * Q + i) * n, nd), 0, P.inv_scale[a]);
+      const D d = load_dev<S, D>(at32(pop + (size_t)(a * Q + i) * n, nd), 0, dec_scale<S>(P, a, i));
       r += d;
       acc_c(ja[0], cx(i), d);
       acc_c(ja[1], cy(i), d);
@@ -450,7 +450,7 @@ __host__ __device__ __forceinline__ void state_node(const Params<double>& P, con
   D rhoE = 0.0, q[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const D d = load_dev<S, D>(at32(pop + (size_t)(LF * Q + i) * n, nd), 0, P.inv_scale[LF]);
+    const D d = load_dev<S, D>(at32(pop + (size_t)(LF * Q + i) * n, nd), 0, dec_scale<S>(P, LF, i));
     rho += d;
     acc_c(j[0], cx(i), d);
     acc_c(j[1], cy(i), d);
@@ -461,7 +461,7 @@ __host__ __device__ __forceinline__ void state_node(const Params<double>& P, con
     acc_c(Pxy, cx(i) * cy(i), d);
     acc_c(Pxz, cx(i) * cz(i), d);
     acc_c(Pyz, cy(i) * cz(i), d);
-    const D e = load_dev<S, D>(at32(pop + (size_t)(LG * Q + i) * n, nd), 0, P.inv_scale[LG]);
+    const D e = load_dev<S, D>(at32(pop + (size_t)(LG * Q + i) * n, nd), 0, dec_scale<S>(P, LG, i));
     rhoE += e;
     acc_c(q[0], cx(i), e);
     acc_c(q[1], cy(i), e);
@@ -470,7 +470,7 @@ __host__ __device__ __forceinline__ void state_node(const Params<double>& P, con
   rho += P.ref0[LF];
   rhoE += P.ref0[LG];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) Pd[k] += P.ref2[LF];
+  for (int k = 0; k < 3; ++k) Pd[k] += P.ref2[LF][k];
   Mix<D, M> s;
   mixture_state<D, M, WEAK, CVT>(P, rho, j, rhoE, rho_s, s);
   D us[3], Pk = s.P;                     // velocity and pressure of the species subsystem
@@ -635,6 +635,46 @@ struct Store<__bf16, float> {
   __host__ __device__ static __bf16 cvt(float x, uint32_t rnd) { return cvt_sr_bf16(x, rnd); }
 };
 
+// 16-bit fixed point: a value in units of the storage quantum of its lattice and
+// direction class, rounded stochastically to an integer in [-32767, 32767].
+template <>
+struct Store<int16_t, float> {
+  __host__ __device__ static int16_t cvt(float x, uint32_t rnd) { return cvt_sr_i16(x, rnd); }
+};
+
+template <typename S>
+constexpr bool is_fixed16() { return std::is_same<S, int16_t>::value; }
+
+// Encoding and decoding factors of lattice l, direction i: one per lattice for
+// the floating-point storage types, one per lattice and direction class for
+// fixed point.
+template <typename S, typename R>
+__host__ __device__ __forceinline__ R enc_scale(const Params<R>& P, int l, int i)
+{
+  if constexpr (is_fixed16<S>()) return P.qs[l][ccls(i)];
+  else return P.scale[l];
+}
+
+template <typename S, typename R>
+__host__ __device__ __forceinline__ R dec_scale(const Params<R>& P, int l, int i)
+{
+  if constexpr (is_fixed16<S>()) return P.inv_qs[l][ccls(i)];
+  else return P.inv_scale[l];
+}
+
+// Storage of an initial deviation (FP64 arithmetic): fixed point rounds to
+// nearest and clamps (the initial range is chosen to hold every value).
+template <typename S>
+__host__ __device__ __forceinline__ S init_store(const Params<double>& P, int l, int i, double dev)
+{
+  if constexpr (is_fixed16<S>()) {
+    const double x = rint(dev * P.qs[l][ccls(i)]);
+    return (int16_t)(x > 32767.0 ? 32767.0 : (x < -32767.0 ? -32767.0 : x));
+  } else {
+    return S(dev * P.scale[l]);
+  }
+}
+
 // Random words for stochastic rounding: one hash per (node, lattice, step), then
 // a linear congruential sequence (only its upper bits are used). An additive
 // (Weyl) sequence would save the multiply, but its fixed increment correlates the
@@ -642,8 +682,11 @@ struct Store<__bf16, float> {
 // some pairs), which leaves each rounding unbiased but raises the noise of the
 // first moments: FP16 storage of the ternary tube drifted 1.7 times further from
 // the FP64 result over 1000 steps.
+// With fixed-point storage it also keeps the largest magnitude (in storage units)
+// that the lattice's stores rounded, for range_check.
 struct Rng {
   uint32_t s;
+  float amax = 0.0f;
   __host__ __device__ Rng(int64_t node, int l, uint32_t step)
       : s(mix32((uint32_t)node ^ mix32((uint32_t)l * 0x632BE5ABu + step * 0x9E3779B1u))) {}
   __host__ __device__ uint32_t next()
@@ -653,17 +696,40 @@ struct Rng {
   }
 };
 
-// Round a post-collision deviation of lattice l to storage.
+// Round a post-collision deviation of lattice l, direction i to storage.
 template <typename S, typename R>
-__host__ __device__ __forceinline__ S to_store(const Params<R>& P, int l, R dev, Rng& rng)
+__host__ __device__ __forceinline__ S to_store(const Params<R>& P, int l, int i, R dev, Rng& rng)
 {
-  return Store<S, R>::cvt(dev * P.scale[l], rng.next());
+  if constexpr (is_fixed16<S>()) {
+    const float x = float(dev * P.qs[l][ccls(i)]);
+    rng.amax = __builtin_elementwise_maximum(rng.amax, fabsf(x));   // NaN propagates
+    return Store<S, R>::cvt(x, rng.next());
+  } else {
+    return Store<S, R>::cvt(dev * P.scale[l], rng.next());
+  }
 }
 
 template <typename S, typename R>
-__host__ __device__ __forceinline__ R from_store(const Params<R>& P, int l, S v)
+__host__ __device__ __forceinline__ R from_store(const Params<R>& P, int l, int i, S v)
 {
-  return R(v) * P.inv_scale[l];
+  return R(v) * dec_scale<S, R>(P, l, i);
+}
+
+// Fixed-point storage: after a lattice's stores, set bit 0 of the context's range
+// flag when a value passed 3/4 of its range (the host then re-ranges the state
+// before the margin is used up), and bits 0 and 1 when one was clamped or not
+// finite (the state is lost). One atomic per wavefront that sets it.
+template <typename S, typename R>
+__host__ __device__ __forceinline__ void range_check(const Params<R>& P, const Rng& rng)
+{
+  if constexpr (is_fixed16<S>()) {
+    const bool hit = !(rng.amax < 24576.0f);
+    const uint64_t any = __ballot(hit);
+    if (any) {
+      const uint64_t bad = __ballot(hit && !(rng.amax <= 32766.0f));
+      if ((int)__lane_id() == __ffsll((unsigned long long)any) - 1) atomicOr(P.range_flag, bad ? 3u : 1u);
+    }
+  }
 }
 
 // Streaming: write the post-collision value of direction i to the neighbour
@@ -756,8 +822,8 @@ __host__ __device__ __forceinline__ void jets_fix_node(const Params<R>& P, S* __
       Rng rng(node, l + 16, step);
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
-        if (x == 0 && cx(i) > 0) dst[(size_t)(l * Q + i) * n + node] = to_store<S, R>(P, l, P.inl[l][i], rng);
-        if (x == nx - 1 && cx(i) < 0) dst[(size_t)(l * Q + i) * n + node] = to_store<S, R>(P, l, P.inl2[l][i], rng);
+        if (x == 0 && cx(i) > 0) dst[(size_t)(l * Q + i) * n + node] = to_store<S, R>(P, l, i, P.inl[l][i], rng);
+        if (x == nx - 1 && cx(i) < 0) dst[(size_t)(l * Q + i) * n + node] = to_store<S, R>(P, l, i, P.inl2[l][i], rng);
       }
     }
   }
@@ -781,7 +847,7 @@ __host__ __device__ __forceinline__ void open_fix_node(const Params<R>& P, S* __
       Rng rng(node, l + 16, step);
 #pragma unroll
       for (int i = 0; i < Q; ++i)
-        if (cx(i) > 0) dst[(size_t)(l * Q + i) * n + node] = to_store<S, R>(P, l, P.inl[l][i], rng);
+        if (cx(i) > 0) dst[(size_t)(l * Q + i) * n + node] = to_store<S, R>(P, l, i, P.inl[l][i], rng);
     }
   }
   if (x == (uint32_t)P.nx - 1) {
@@ -820,9 +886,9 @@ __host__ __device__ __forceinline__ void restore_faces(const Params<R>& P, int l
     const int ip = face_plus(k), im = 26 - ip;
     const R sum = face[ip] + face[im];
     const R diff = t1[k] - s1[k];        // required stored value of ip minus that of im
-    v[ip] = to_store<S, R>(P, l, R(0.5) * (sum + diff), rng);
-    v[im] = to_store<S, R>(P, l, R(0.5) * (sum - diff), rng);
-    s0 += from_store<S, R>(P, l, v[ip]) + from_store<S, R>(P, l, v[im]);
+    v[ip] = to_store<S, R>(P, l, ip, R(0.5) * (sum + diff), rng);
+    v[im] = to_store<S, R>(P, l, im, R(0.5) * (sum - diff), rng);
+    s0 += from_store<S, R>(P, l, ip, v[ip]) + from_store<S, R>(P, l, im, v[im]);
   }
 }
 
@@ -852,7 +918,7 @@ __host__ __device__ __forceinline__ void species_relax(const Params<R>& P, const
   for (int k = 0; k < 3; ++k) pa[k] = psi_trip<R>(us[k], s.T * P.inv_m[a]);
   R t0 = R(0), s0 = R(0);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) t0 += from_store<S, R>(P, a, v[i]);
+  for (int i = 0; i < Q; ++i) t0 += from_store<S, R>(P, a, i, v[i]);
   Rng rng(node, a, step);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
@@ -866,13 +932,14 @@ __host__ __device__ __forceinline__ void species_relax(const Params<R>& P, const
     }
     const R fe = s.rho_a[a] * (pa[0](cx(i)) * pa[1](cy(i)) * pa[2](cz(i))) - P.ref[a][i];
     // f' - f_ref = (f^eq - f_ref) + (1 - 2 beta)(f - f^eq) + (beta - 1) F
-    const R dn = fe + (R(1) - R(2) * beta) * (from_store<S, R>(P, a, v[i]) - fe) + (beta - R(1)) * R(F);
-    v[i] = to_store<S, R>(P, a, dn, rng);
-    s0 += from_store<S, R>(P, a, v[i]);
+    const R dn = fe + (R(1) - R(2) * beta) * (from_store<S, R>(P, a, i, v[i]) - fe) + (beta - R(1)) * R(F);
+    v[i] = to_store<S, R>(P, a, i, dn, rng);
+    s0 += from_store<S, R>(P, a, i, v[i]);
   }
   // the collision conserves rho_a: the rest population takes the defect of
   // the arithmetic and of the other 26 values' rounding to storage
-  v[13] = to_store<S, R>(P, a, t0 - s0, rng);
+  v[13] = to_store<S, R>(P, a, 13, t0 - s0, rng);
+  range_check<S, R>(P, rng);
 #pragma unroll
   for (int i = 0; i < Q; ++i) push<S, R, BC>(P, dst, b, a, i, node, v[i]);
 }
@@ -894,7 +961,7 @@ __host__ __device__ __forceinline__ void momentum_relax(const Params<R>& P, int 
   Rng rng(node, LF, step);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const R d = from_store<S, R>(P, LF, v[i]);
+    const R d = from_store<S, R>(P, LF, i, v[i]);
     t0 += d;
     acc_c(t1[0], cx(i), d);
     acc_c(t1[1], cy(i), d);
@@ -908,9 +975,9 @@ __host__ __device__ __forceinline__ void momentum_relax(const Params<R>& P, int 
   for (int i = 0; i < Q; ++i) {
     if (csq(i) <= 1) continue;
     const R fe = rho * (pf[0](cx(i)) * pf[1](cy(i)) * pf[2](cz(i))) - P.ref[LF][i];
-    const R dn = fe + (R(1) - omega) * (from_store<S, R>(P, LF, v[i]) - fe);
-    v[i] = to_store<S, R>(P, LF, dn, rng);
-    const R d = from_store<S, R>(P, LF, v[i]);
+    const R dn = fe + (R(1) - omega) * (from_store<S, R>(P, LF, i, v[i]) - fe);
+    v[i] = to_store<S, R>(P, LF, i, dn, rng);
+    const R d = from_store<S, R>(P, LF, i, v[i]);
     s0 += d;
     acc_c(s1[0], cx(i), d);
     acc_c(s1[1], cy(i), d);
@@ -924,10 +991,11 @@ __host__ __device__ __forceinline__ void momentum_relax(const Params<R>& P, int 
   for (int i = 0; i < Q; ++i) {
     if (csq(i) != 1) continue;
     const R fe = rho * (pf[0](cx(i)) * pf[1](cy(i)) * pf[2](cz(i))) - P.ref[LF][i];
-    face[i] = fe + (R(1) - omega) * (from_store<S, R>(P, LF, v[i]) - fe);
+    face[i] = fe + (R(1) - omega) * (from_store<S, R>(P, LF, i, v[i]) - fe);
   }
   restore_faces<S, R>(P, LF, face, t1, s1, s0, v, rng);
-  v[13] = to_store<S, R>(P, LF, t0 - s0, rng);
+  v[13] = to_store<S, R>(P, LF, 13, t0 - s0, rng);
+  range_check<S, R>(P, rng);
 #pragma unroll
   for (int i = 0; i < Q; ++i) push<S, R, BC>(P, dst, b, LF, i, node, v[i]);
 }
@@ -959,7 +1027,7 @@ __host__ __device__ __forceinline__ void energy_relax(const Params<R>& P, int LG
   R t0 = R(0), s0 = R(0);
   Rng rng(node, LG, step);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) t0 += from_store<S, R>(P, LG, v[i]);
+  for (int i = 0; i < Q; ++i) t0 += from_store<S, R>(P, LG, i, v[i]);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     if (i == 13) continue;
@@ -972,12 +1040,13 @@ __host__ __device__ __forceinline__ void energy_relax(const Params<R>& P, int LG
     const R ge = w * (rhoE + cqe * inv_theta +
                       (rt2 * (R(csq(i)) - R(3) * theta) + kappa * (cu * cu - theta * usq)) * h2) + bz -
                  P.ref[LG][i];
-    const R dn = ge + (R(1) - omega) * (from_store<S, R>(P, LG, v[i]) - ge) + w * cdq * inv_theta;
-    v[i] = to_store<S, R>(P, LG, dn, rng);
-    s0 += from_store<S, R>(P, LG, v[i]);
+    const R dn = ge + (R(1) - omega) * (from_store<S, R>(P, LG, i, v[i]) - ge) + w * cdq * inv_theta;
+    v[i] = to_store<S, R>(P, LG, i, dn, rng);
+    s0 += from_store<S, R>(P, LG, i, v[i]);
   }
   // the collision conserves rho E: the rest population takes the defect
-  v[13] = to_store<S, R>(P, LG, t0 - s0, rng);
+  v[13] = to_store<S, R>(P, LG, 13, t0 - s0, rng);
+  range_check<S, R>(P, rng);
 #pragma unroll
   for (int i = 0; i < Q; ++i) push<S, R, BC>(P, dst, b, LG, i, node, v[i]);
 }
@@ -1237,7 +1306,7 @@ __host__ __device__ __forceinline__ void state_species_node(const Params<R>& P, 
     R r = R(0), ja[3] = {R(0), R(0), R(0)};
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const R d = from_store<S, R>(P, a, va[i]);
+      const R d = from_store<S, R>(P, a, i, va[i]);
       r += d;
       acc_c(ja[0], cx(i), d);
       acc_c(ja[1], cy(i), d);
@@ -1252,12 +1321,12 @@ __host__ __device__ __forceinline__ void state_species_node(const Params<R>& P, 
   R rho = R(0), j[3] = {R(0), R(0), R(0)}, rhoE = R(0);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const R d = from_store<S, R>(P, LF, buf_load<S, BUF_NT>(src + (size_t)(LF * Q + i) * n, (uint32_t)n, nd));
+    const R d = from_store<S, R>(P, LF, i, buf_load<S, BUF_NT>(src + (size_t)(LF * Q + i) * n, (uint32_t)n, nd));
     rho += d;
     acc_c(j[0], cx(i), d);
     acc_c(j[1], cy(i), d);
     acc_c(j[2], cz(i), d);
-    rhoE += from_store<S, R>(P, LG, buf_load<S, BUF_NT>(src + (size_t)(LG * Q + i) * n, (uint32_t)n, nd));
+    rhoE += from_store<S, R>(P, LG, i, buf_load<S, BUF_NT>(src + (size_t)(LG * Q + i) * n, (uint32_t)n, nd));
   }
   rho += P.ref0[LF];
   rhoE += P.ref0[LG];
@@ -1347,7 +1416,7 @@ __host__ __device__ __forceinline__ void fg_collide_node(const Params<R>& P, con
   R rhoE = R(0), q[3] = {R(0), R(0), R(0)};
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const R d = from_store<S, R>(P, LF, vf[i]);
+    const R d = from_store<S, R>(P, LF, i, vf[i]);
     rho += d;
     acc_c(j[0], cx(i), d);
     acc_c(j[1], cy(i), d);
@@ -1358,7 +1427,7 @@ __host__ __device__ __forceinline__ void fg_collide_node(const Params<R>& P, con
     acc_c(Pxy, cx(i) * cy(i), d);
     acc_c(Pxz, cx(i) * cz(i), d);
     acc_c(Pyz, cy(i) * cz(i), d);
-    const R e = from_store<S, R>(P, LG, vg[i]);
+    const R e = from_store<S, R>(P, LG, i, vg[i]);
     rhoE += e;
     acc_c(q[0], cx(i), e);
     acc_c(q[1], cy(i), e);
@@ -1367,7 +1436,7 @@ __host__ __device__ __forceinline__ void fg_collide_node(const Params<R>& P, con
   rho += P.ref0[LF];
   rhoE += P.ref0[LG];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) Pd[k] += P.ref2[LF];
+  for (int k = 0; k < 3; ++k) Pd[k] += P.ref2[LF][k];
   auto get = [&](int f) -> R { return R(*at32(rec + (size_t)f * n, nd)); };
   const R omega = get(REC_OMEGA), omega1 = get(REC2_OMEGA1), Cp = get(REC_CP), Rg = get(REC2_RG);
   const R inv_rho = R(1) / rho;
@@ -1429,19 +1498,19 @@ __host__ __device__ __forceinline__ void read_node(const Params<R>& P, const S* 
   for (int a = 0; a < NS; ++a) {
     R sum = R(0);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) sum += load_dev<S, R>(pop, (size_t)(a * Q + i) * n + node, P.inv_scale[a]);
+    for (int i = 0; i < Q; ++i) sum += load_dev<S, R>(pop, (size_t)(a * Q + i) * n + node, dec_scale<S>(P, a, i));
     rho_s[a] = P.ref0[a] + sum;
   }
   if constexpr (!WEAK) rho_s[M - 1] = R(0);
   R rho = R(0), j[3] = {R(0), R(0), R(0)}, rhoE = R(0);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const R d = load_dev<S, R>(pop, (size_t)(LF * Q + i) * n + node, P.inv_scale[LF]);
+    const R d = load_dev<S, R>(pop, (size_t)(LF * Q + i) * n + node, dec_scale<S>(P, LF, i));
     rho += d;
     if (cx(i)) j[0] += cx(i) > 0 ? d : -d;
     if (cy(i)) j[1] += cy(i) > 0 ? d : -d;
     if (cz(i)) j[2] += cz(i) > 0 ? d : -d;
-    rhoE += load_dev<S, R>(pop, (size_t)(LG * Q + i) * n + node, P.inv_scale[LG]);
+    rhoE += load_dev<S, R>(pop, (size_t)(LG * Q + i) * n + node, dec_scale<S>(P, LG, i));
   }
   rho += P.ref0[LF];
   rhoE += P.ref0[LG];
@@ -1497,7 +1566,7 @@ __host__ __device__ __forceinline__ int init_node(const Params<double>& P, const
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const double f = rho * Y[a] * (t[0](cx(i)) * t[1](cy(i)) * t[2](cz(i)));
-      pop[(size_t)(a * Q + i) * n + node] = S((f - P.ref[a][i]) * P.scale[a]);
+      pop[(size_t)(a * Q + i) * n + node] = init_store<S>(P, a, i, f - P.ref[a][i]);
     }
   }
   const double theta = Rg * Tn;
@@ -1509,7 +1578,7 @@ __host__ __device__ __forceinline__ int init_node(const Params<double>& P, const
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const double f = rho * (t[0](cx(i)) * t[1](cy(i)) * t[2](cz(i)));
-      pop[(size_t)(LF * Q + i) * n + node] = S((f - P.ref[LF][i]) * P.scale[LF]);
+      pop[(size_t)(LF * Q + i) * n + node] = init_store<S>(P, LF, i, f - P.ref[LF][i]);
     }
   }
   {
@@ -1538,7 +1607,7 @@ __host__ __device__ __forceinline__ int init_node(const Params<double>& P, const
       const double g = w * (rhoE + hyd * rho * cu / theta +
                             (rt2 * (csq(i) - 3.0 * theta) + kappa * (cu * cu - theta * usq)) * 0.5 / (theta * theta)) +
                        bz;
-      pop[(size_t)(LG * Q + i) * n + node] = S((g - P.ref[LG][i]) * P.scale[LG]);
+      pop[(size_t)(LG * Q + i) * n + node] = init_store<S>(P, LG, i, g - P.ref[LG][i]);
     }
   }
   return bad;
@@ -1560,19 +1629,19 @@ __host__ __device__ __forceinline__ void conserved_node(const Params<double>& P,
   for (int a = 0; a < NS; ++a) {
     double sum = 0.0;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) sum += (double)pop[(size_t)(a * Q + i) * n + node] * P.inv_scale[a];
+    for (int i = 0; i < Q; ++i) sum += (double)pop[(size_t)(a * Q + i) * n + node] * dec_scale<S>(P, a, i);
     out[a] = P.ref0[a] + sum;
     rest += out[a];
   }
   double rho = 0.0, j[3] = {0.0, 0.0, 0.0}, rhoE = 0.0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const double d = (double)pop[(size_t)(LF * Q + i) * n + node] * P.inv_scale[LF];
+    const double d = (double)pop[(size_t)(LF * Q + i) * n + node] * dec_scale<S>(P, LF, i);
     rho += d;
     j[0] += cx(i) * d;
     j[1] += cy(i) * d;
     j[2] += cz(i) * d;
-    rhoE += (double)pop[(size_t)(LG * Q + i) * n + node] * P.inv_scale[LG];
+    rhoE += (double)pop[(size_t)(LG * Q + i) * n + node] * dec_scale<S>(P, LG, i);
   }
   rho += P.ref0[LF];
   rhoE += P.ref0[LG];
@@ -1604,14 +1673,14 @@ __host__ __device__ __forceinline__ void half_moles_node(const Params<double>& P
   for (int a = 0; a < NS; ++a) {
     double sum = 0.0;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) sum += (double)pop[(size_t)(a * Q + i) * n + node] * P.inv_scale[a];
+    for (int i = 0; i < Q; ++i) sum += (double)pop[(size_t)(a * Q + i) * n + node] * dec_scale<S>(P, a, i);
     rho_a[a] = P.ref0[a] + sum;
     rest += rho_a[a];
   }
   if constexpr (!WEAK) {
     double rho = 0.0;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) rho += (double)pop[(size_t)(LF * Q + i) * n + node] * P.inv_scale[LF];
+    for (int i = 0; i < Q; ++i) rho += (double)pop[(size_t)(LF * Q + i) * n + node] * dec_scale<S>(P, LF, i);
     rho_a[M - 1] = rho + P.ref0[LF] - rest;
   }
   const int h = (int)(node % P.nx) >= P.nx / 2 ? 1 : 0;

@@ -26,6 +26,32 @@ struct RefState {
   double p, T;
 };
 
+// Reference and scale tables of one tube's stored lattices (also the per-tube
+// part of a checkpoint): ref[l][i] the reference populations, ref0 and ref2 their
+// zeroth and diagonal second moments; scale[l] the factor of floating-point
+// deviations; qs[l][k] and inv_qs[l][k] the encoding and decoding factors of
+// fixed-point storage per direction class k (zero otherwise).
+struct RefTables {
+  double ref[MAXL][Q];
+  double ref0[MAXL];
+  double ref2[MAXL][3];
+  double scale[MAXL];
+  double qs[MAXL][NCLS], inv_qs[MAXL][NCLS];
+};
+
+// Moments ref0 and ref2 of the reference populations of lattices 0..L-1.
+inline void reference_moments(RefTables& t, int L)
+{
+  for (int l = 0; l < L; ++l) {
+    t.ref0[l] = 0.0;
+    for (int k = 0; k < 3; ++k) t.ref2[l][k] = 0.0;
+    for (int i = 0; i < Q; ++i) {
+      t.ref0[l] += t.ref[l][i];
+      for (int k = 0; k < 3; ++k) t.ref2[l][k] += t.ref[l][i] * cc(i, k) * cc(i, k);
+    }
+  }
+}
+
 // Wilke's phi_ab (Sec. 3.3, eq wilkePhi).
 inline double wilke_phi(const HostSpecies& h, int a, int b)
 {
@@ -38,9 +64,9 @@ inline double wilke_phi(const HostSpecies& h, int a, int b)
 // strong coupling, M under weak), momentum rho Psi(0, R T) at lattice ns, energy
 // the energy-lattice equilibrium with zero flux at ns + 1. All are symmetric
 // under c -> -c.
-inline void reference_tables(const HostSpecies& h, int ns, const RefState& rs, double ref[MAXL][Q],
-                             double ref0[MAXL], double ref2[MAXL])
+inline void reference_tables(const HostSpecies& h, int ns, const RefState& rs, RefTables& tab)
 {
+  double (&ref)[MAXL][Q] = tab.ref;
   const int M = h.M;
   double mmix = 0.0;
   for (int a = 0; a < M; ++a) mmix += rs.X[a] * h.m[a];
@@ -77,22 +103,15 @@ inline void reference_tables(const HostSpecies& h, int ns, const RefState& rs, d
       ref[ns + 1][i] = w * (rhoE + rt2 * (csq(i) - 3.0 * theta) * 0.5 / (theta * theta)) + bz;
     }
   }
-  for (int l = 0; l <= ns + 1; ++l) {
-    ref0[l] = 0.0;
-    ref2[l] = 0.0;
-    for (int i = 0; i < Q; ++i) {
-      ref0[l] += ref[l][i];
-      ref2[l] += ref[l][i] * cx(i) * cx(i);
-    }
-  }
+  reference_moments(tab, ns + 2);
 }
 
-// Fill a parameter block. scale[l] multiplies stored deviations (1 for FP64 and
-// FP32 storage; a range-fitting factor for 16-bit storage).
+// Fill a parameter block. scale[l] multiplies stored floating-point deviations (1
+// for FP64 and FP32 storage; a range-fitting factor for 16-bit floating point);
+// range_flag is the context's device word that fixed-point kernels report to.
 template <typename R>
 inline void fill_params(Params<R>& P, const HostSpecies& h, int nx, int ny, int nz, int wall_x, int L,
-                        const double ref[MAXL][Q], const double ref0[MAXL], const double ref2[MAXL],
-                        const double scale[MAXL], double absent_tol, int noz0 = 0, int noz1 = 0)
+                        const RefTables& t, double absent_tol, uint32_t* range_flag, int noz0 = 0, int noz1 = 0)
 {
   std::memset(&P, 0, sizeof(P));
   P.M = h.M;
@@ -120,12 +139,17 @@ inline void fill_params(Params<R>& P, const HostSpecies& h, int nx, int ny, int 
     }
   }
   for (int l = 0; l < L; ++l) {
-    for (int i = 0; i < Q; ++i) P.ref[l][i] = R(ref[l][i]);
-    P.ref0[l] = R(ref0[l]);
-    P.ref2[l] = R(ref2[l]);
-    P.scale[l] = R(scale[l]);
-    P.inv_scale[l] = R(1.0 / scale[l]);
+    for (int i = 0; i < Q; ++i) P.ref[l][i] = R(t.ref[l][i]);
+    P.ref0[l] = R(t.ref0[l]);
+    for (int k = 0; k < 3; ++k) P.ref2[l][k] = R(t.ref2[l][k]);
+    P.scale[l] = R(t.scale[l]);
+    P.inv_scale[l] = R(1.0 / t.scale[l]);
+    for (int k = 0; k < NCLS; ++k) {
+      P.qs[l][k] = R(t.qs[l][k]);
+      P.inv_qs[l][k] = R(t.inv_qs[l][k]);
+    }
   }
+  P.range_flag = range_flag;
   P.absent_tol = R(absent_tol);
   P.s_D = R(h.s_D);
   P.trn = h.trn;

@@ -29,9 +29,10 @@ MCLBM_FP32 = 1
 MCLBM_FP32_FP32 = 2
 MCLBM_FP16 = 3
 MCLBM_BF16 = 4
+MCLBM_I16 = 5
 PRECISIONS = {"fp64": MCLBM_FP64, "fp32": MCLBM_FP32, "fp32_fp32": MCLBM_FP32_FP32,
-              "fp16": MCLBM_FP16, "bf16": MCLBM_BF16}
-STORAGE_BYTES = {MCLBM_FP64: 8, MCLBM_FP32: 4, MCLBM_FP32_FP32: 4, MCLBM_FP16: 2, MCLBM_BF16: 2}
+              "fp16": MCLBM_FP16, "bf16": MCLBM_BF16, "i16": MCLBM_I16}
+STORAGE_BYTES = {MCLBM_FP64: 8, MCLBM_FP32: 4, MCLBM_FP32_FP32: 4, MCLBM_FP16: 2, MCLBM_BF16: 2, MCLBM_I16: 2}
 
 MCLBM_K_MOMENTS = 0
 MCLBM_K_GFIELD = 1
@@ -45,7 +46,7 @@ def kernel_count() -> int:
 EXPORTS = ["mclbm_workspace_bytes", "mclbm_batch_workspace_bytes", "mclbm_create", "mclbm_batch_create",
            "mclbm_destroy", "mclbm_last_error", "mclbm_tube_count", "mclbm_node_count",
            "mclbm_init_fields", "mclbm_step", "mclbm_read_moments", "mclbm_read_fields_f32",
-           "mclbm_conservation", "mclbm_step_count", "mclbm_state_bytes", "mclbm_save", "mclbm_load",
+           "mclbm_conservation", "mclbm_step_count", "mclbm_range_refits", "mclbm_state_bytes", "mclbm_save", "mclbm_load",
            "mclbm_set_timing", "mclbm_kernel_stats", "mclbm_get_launch", "mclbm_set_launch",
            "mclbm_autotune", "mclbm_stream_copy", "mclbm_half_tube_moles", "mclbm_create_static"]
 NN_EXPORTS = ["mclbm_nn_workspace_bytes", "mclbm_nn_create", "mclbm_nn_destroy", "mclbm_nn_last_error",
@@ -147,6 +148,8 @@ def _load():
     L.mclbm_conservation.argtypes = [vp, dp]
     L.mclbm_step_count.argtypes = [vp]
     L.mclbm_step_count.restype = C.c_int64
+    L.mclbm_range_refits.argtypes = [vp]
+    L.mclbm_range_refits.restype = C.c_int64
     L.mclbm_state_bytes.argtypes = [vp]
     L.mclbm_state_bytes.restype = C.c_size_t
     L.mclbm_save.argtypes = [vp, vp, C.c_size_t]
@@ -339,6 +342,10 @@ def mclbm_step_count(ctx) -> int:
     return int(lib.mclbm_step_count(ctx))
 
 
+def mclbm_range_refits(ctx) -> int:
+    return int(lib.mclbm_range_refits(ctx))
+
+
 def mclbm_state_bytes(ctx) -> int:
     return int(lib.mclbm_state_bytes(ctx))
 
@@ -453,6 +460,9 @@ class Sim:
     def step_count(self) -> int:
         return mclbm_step_count(self.ctx)
 
+    def range_refits(self) -> int:
+        return mclbm_range_refits(self.ctx)
+
     def launch(self) -> dict:
         return mclbm_get_launch(self.ctx)
 
@@ -563,6 +573,9 @@ class Batch:
     @property
     def step_count(self) -> int:
         return mclbm_step_count(self.ctx)
+
+    def range_refits(self) -> int:
+        return mclbm_range_refits(self.ctx)
 
     def launch(self) -> dict:
         return mclbm_get_launch(self.ctx)

@@ -7,16 +7,35 @@ FIELDS = ("X", "rho", "u", "p", "T")
 
 # Checkpoint written by mclbm_save (see mclbm.hip): a header (magic[8], M,
 # wall_x, precision, ntubes, weak, cvt as int32, int64 step count), then per tube
-# its size and reference tables (10 lattices: up to 8 species, f, g), then the
-# stored populations of all tubes (M-1 species lattices under strong coupling,
-# M under weak coupling, then f and g).
+# its size, its fixed-point range flag and its reference tables (10 lattices: up
+# to 8 species, f, g; fixed-point factors per lattice and direction class), then
+# the stored populations of all tubes (M-1 species lattices under strong
+# coupling, M under weak coupling, then f and g).
 _MAXL = 10
+_NCLS = 8
 _HDR = np.dtype([("magic", "S8"), ("M", "<i4"), ("wall_x", "<i4"), ("precision", "<i4"),
                  ("ntubes", "<i4"), ("weak", "<i4"), ("cvt", "<i4"), ("steps", "<i8")])
-_TUBE = np.dtype([("nx", "<i4"), ("ny", "<i4"), ("nz", "<i4"), ("pad", "<i4"),
-                  ("ref", "<f8", (_MAXL, 27)), ("ref0", "<f8", (_MAXL,)), ("ref2", "<f8", (_MAXL,)),
-                  ("scale", "<f8", (_MAXL,))])
-_STORE = {0: np.float64, 1: np.float32, 2: np.float32, 3: np.float16}
+_TUBE = np.dtype([("nx", "<i4"), ("ny", "<i4"), ("nz", "<i4"), ("range_flag", "<u4"),
+                  ("ref", "<f8", (_MAXL, 27)), ("ref0", "<f8", (_MAXL,)), ("ref2", "<f8", (_MAXL, 3)),
+                  ("scale", "<f8", (_MAXL,)), ("qs", "<f8", (_MAXL, _NCLS)), ("inv_qs", "<f8", (_MAXL, _NCLS))])
+_STORE = {0: np.float64, 1: np.float32, 2: np.float32, 3: np.float16, 5: np.int16}
+# direction class (equal |c_x|, |c_y|, |c_z|) of the 27 directions, i = 9 (c_x+1) + 3 (c_y+1) + (c_z+1)
+_CLS = np.array([(i // 9 != 1) + 2 * ((i // 3) % 3 != 1) + 4 * (i % 3 != 1) for i in range(27)])
+
+
+def absolute_populations(hdr: dict, vals: np.ndarray) -> np.ndarray:
+    """Stored values [L][27][...] of a decoded checkpoint as absolute populations in
+    FP64, for every storage type."""
+    L = vals.shape[0]
+    out = np.empty(vals.shape, dtype=np.float64)
+    shape = (27,) + (1,) * (vals.ndim - 2)
+    for l in range(L):
+        if int(hdr["precision"]) == 5:
+            dec = hdr["inv_qs"][l][_CLS]
+        else:
+            dec = np.full(27, 1.0 / hdr["scale"][l])
+        out[l] = hdr["ref"][l].reshape(shape) + vals[l].astype(np.float64) * dec.reshape(shape)
+    return out
 
 
 def rel_linf(a: np.ndarray, b: np.ndarray) -> float:
@@ -72,12 +91,11 @@ def oracle_window(hdr: dict, vals: np.ndarray, center, radius: int) -> np.ndarra
     iz = np.arange(z0 - radius, z0 + radius + 1) % nz
     w = 2 * radius + 1
     out = np.zeros((M + 2, 27, w, w, w))
-    sub = vals[np.ix_(np.arange(L), np.arange(27), iz, iy, ix)].astype(np.float64)
+    sub = absolute_populations(hdr, vals[np.ix_(np.arange(L), np.arange(27), iz, iy, ix)])
     for l in range(L):
-        f = hdr["ref"][l][:, None, None, None] + sub[l] / hdr["scale"][l]
         # GPU lattices: species 1..M-1 (1..M under weak coupling), f, g
         dst = l if (L == M + 2 or l < M - 1) else l + 1
-        out[dst] = f
+        out[dst] = sub[l]
     return out
 
 
@@ -105,7 +123,6 @@ def stored_population_error(hdr, vals, oracle_pops, M, weak):
     oracle's populations (all M + 2 under weak coupling; the slaved species'
     lattice is not stored under strong coupling)."""
     L = vals.shape[0]
-    gp = np.stack([hdr["ref"][l][:, None, None, None] + vals[l].astype(np.float64) / hdr["scale"][l]
-                   for l in range(L)])
+    gp = absolute_populations(hdr, vals)
     ref = oracle_pops if weak else np.concatenate([oracle_pops[:M - 1], oracle_pops[M:M + 2]])
     return float(np.abs(gp - ref).max() / np.abs(ref).max())

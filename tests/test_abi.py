@@ -84,6 +84,25 @@ def test_weak_coupling_workspace_and_validation():
     assert "weak" in str(e.value)
 
 
+def test_fixed16_workspace_and_validation():
+    """16-bit fixed-point storage takes the workspace of FP16 storage (two bytes a
+    population, FP32 record); it is compiled for both couplings with constant
+    properties and periodic or walled x ends only."""
+    m = pytest.importorskip("paper_2004_11286_amd.mclbm")
+    p, _ = W.binary_interdiffusion()
+    tube, _ = W.ternary_tube(nx=16, ny=2, nz=2)
+    for q in (p, dict(p, weak=1), tube, dict(tube, weak=1)):
+        assert m.mclbm_workspace_bytes(q, m.MCLBM_I16) == m.mclbm_workspace_bytes(q, m.MCLBM_FP16)
+    inlet = np.array([0.3, 0.3, 0.4, tube["P0"], 1 / 3, 0.05, 0.0, 0.0])
+    for bad, what in ((dict(tube, wall_x=2, inlet=inlet), "open x ends"), (dict(tube, wall_y=1), "free-slip"),
+                      (dict(tube, cv_coef=np.ones((3, 4))), "")):
+        with pytest.raises(m.MclbmError) as e:
+            m.mclbm_workspace_bytes(bad, m.MCLBM_I16)
+        assert what in str(e.value)
+    with pytest.raises(m.MclbmError):
+        m.mclbm_workspace_bytes(p, m.MCLBM_I16 + 1)             # unknown precision
+
+
 def test_cv_of_T_workspace_and_validation():
     """Temperature-dependent specific heats add M - 1 mass-fraction fields to the
     node record; the coefficients must give a positive, non-decreasing C_v; the

@@ -59,7 +59,7 @@ def test_batch_matches_oracle_fp64(mc, oracle_mod):
             assert errs[k] < 1e-12, (t, k, errs[k])
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "i16"])
 def test_batch_is_bitwise_single_contexts(mc, prec):
     tubes = small_ensemble(seed=6)
     g, _ = run_batch(mc, tubes, mc.PRECISIONS[prec], 30)
@@ -82,7 +82,7 @@ LAUNCHES = [dict(variant=1), dict(swizzle=1), dict(order=1), dict(sequential=1),
 
 
 @pytest.mark.parametrize("three_pass", [0, 1])
-@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "i16"])
 def test_launch_choices_are_bitwise_equal(mc, prec, three_pass):
     """Within each step path (two-read, three-pass) every launch choice computes
     the same step bit for bit. The graph runs start from an odd step (one eager
@@ -111,7 +111,7 @@ def test_launch_choices_are_bitwise_equal(mc, prec, three_pass):
             assert a == r, (launch, k)
 
 
-@pytest.mark.parametrize("prec,rtol", [("fp32", 1e-5), ("fp16", 2e-3)])
+@pytest.mark.parametrize("prec,rtol", [("fp32", 1e-5), ("fp16", 2e-3), ("i16", 1e-3)])
 def test_step_paths_agree_to_rounding(mc, prec, rtol):
     """The two-read step, the three-pass step and its split collision (species
     lattices, then momentum and energy lattices, in two launches) compute the

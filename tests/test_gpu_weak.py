@@ -160,6 +160,29 @@ def test_weak_ternary_tube_fp16_1000_steps(mc, weak_tube_1000):
     np.testing.assert_allclose(c1[:4], c0[:4], rtol=1e-4)
 
 
+def test_weak_ternary_tube_i16_1000_steps(mc, weak_tube_1000):
+    """The same tube with 16-bit fixed-point storage (per-class ranges, stochastic
+    rounding, FP32 collision): each field bounded just above its measured error
+    (velocity against max(max |u|, 1e-3)), about FP16's (the ranges of this tube
+    are set by their floor, the centre's magnitude); every species' mass kept to
+    1e-4."""
+    params, f, o = weak_tube_1000
+    s = mc.Sim(params, mc.MCLBM_I16)
+    s.init_fields(**f)
+    c0 = s.conservation()
+    s.step(1000)
+    g = s.read_moments()
+    c1 = s.conservation()
+    refits = s.range_refits()
+    s.close()
+    errs = field_errors(g, o, u_floor=1e-3)
+    print("weak C2 i16 1000", errs, "mass drift", np.abs(c1[:3] / c0[:3] - 1).max(), "refits", refits)
+    bounds = {"X": 2.5e-3, "rho": 1.3e-3, "u": 2e-2, "p": 4e-4, "T": 1.5e-3}   # measured 1.9e-3, 9.9e-4, 1.4e-2, 2.5e-4, 1.1e-3
+    for k in FIELDS:
+        assert errs[k] < bounds[k], (k, errs[k])
+    np.testing.assert_allclose(c1[:4], c0[:4], rtol=1e-4)
+
+
 def test_weak_full_size_shear_layer_windows(mc, oracle_mod):
     """The 256^3 shear layer under weak coupling, FP32 storage: the GPU state after
     20 steps, cut into 9^3 periodic windows around sampled nodes (all four stored
