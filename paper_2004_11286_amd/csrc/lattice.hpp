@@ -38,6 +38,13 @@ __host__ __device__ constexpr int ccls(int i)
   return (cx(i) != 0 ? 1 : 0) + (cy(i) != 0 ? 2 : 0) + (cz(i) != 0 ? 4 : 0);
 }
 constexpr int NCLS = 8;
+// The first direction of i's class: reference tables are the same over a class,
+// so reading them at the representative leaves 8 distinct values per lattice in
+// scalar registers instead of 27.
+__host__ __device__ constexpr int crep(int i)
+{
+  return (cx(i) != 0 ? 0 : 9) + (cy(i) != 0 ? 0 : 3) + (cz(i) != 0 ? 0 : 1);
+}
 
 // Values of a one-dimensional triplet at c = -1, 0, +1.
 template <typename R>

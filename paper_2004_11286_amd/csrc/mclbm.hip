@@ -553,6 +553,11 @@ int push_params(mclbm_ctx* c)
   const double tol = absent_tol_for(c->precision);
   for (int t = 0; t < c->ntubes; ++t) {
     const TubeHost& th = c->tubes[t];
+    // the kernels read the reference of a direction at its class's representative
+    for (int l = 0; l < c->L; ++l)
+      for (int i = 0; i < Q; ++i)
+        if (!(th.tab.ref[l][i] == th.tab.ref[l][crep(i)]))
+          return fail(c, MCLBM_ESTATE, "reference tables differ within a direction class");
     fill_params<double>(c->hPd[t], th.hs, th.nx, th.ny, th.nz, c->wall_x, c->L, th.tab, tol, c->dFlag + t, th.noz0,
                         th.noz1);
     fill_params<float>(c->hPf[t], th.hs, th.nx, th.ny, th.nz, c->wall_x, c->L, th.tab, tol, c->dFlag + t, th.noz0,

@@ -930,7 +930,7 @@ __host__ __device__ __forceinline__ void species_relax(const Params<R>& P, const
       const F32 dx = pd[c][0](cx(i)), dy = pd[c][1](cy(i)), dz = pd[c][2](cz(i));
       F += F32(K[a][c]) * (dx * ey * ez + (ex - dx) * dy * ez + (ex - dx) * (ey - dy) * dz);
     }
-    const R fe = s.rho_a[a] * (pa[0](cx(i)) * pa[1](cy(i)) * pa[2](cz(i))) - P.ref[a][i];
+    const R fe = s.rho_a[a] * (pa[0](cx(i)) * pa[1](cy(i)) * pa[2](cz(i))) - P.ref[a][crep(i)];
     // f' - f_ref = (f^eq - f_ref) + (1 - 2 beta)(f - f^eq) + (beta - 1) F
     const R dn = fe + (R(1) - R(2) * beta) * (from_store<S, R>(P, a, i, v[i]) - fe) + (beta - R(1)) * R(F);
     v[i] = to_store<S, R>(P, a, i, dn, rng);
@@ -974,7 +974,7 @@ __host__ __device__ __forceinline__ void momentum_relax(const Params<R>& P, int 
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     if (csq(i) <= 1) continue;
-    const R fe = rho * (pf[0](cx(i)) * pf[1](cy(i)) * pf[2](cz(i))) - P.ref[LF][i];
+    const R fe = rho * (pf[0](cx(i)) * pf[1](cy(i)) * pf[2](cz(i))) - P.ref[LF][crep(i)];
     const R dn = fe + (R(1) - omega) * (from_store<S, R>(P, LF, i, v[i]) - fe);
     v[i] = to_store<S, R>(P, LF, i, dn, rng);
     const R d = from_store<S, R>(P, LF, i, v[i]);
@@ -990,7 +990,7 @@ __host__ __device__ __forceinline__ void momentum_relax(const Params<R>& P, int 
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     if (csq(i) != 1) continue;
-    const R fe = rho * (pf[0](cx(i)) * pf[1](cy(i)) * pf[2](cz(i))) - P.ref[LF][i];
+    const R fe = rho * (pf[0](cx(i)) * pf[1](cy(i)) * pf[2](cz(i))) - P.ref[LF][crep(i)];
     face[i] = fe + (R(1) - omega) * (from_store<S, R>(P, LF, i, v[i]) - fe);
   }
   restore_faces<S, R>(P, LF, face, t1, s1, s0, v, rng);
@@ -1039,7 +1039,7 @@ __host__ __device__ __forceinline__ void energy_relax(const Params<R>& P, int LG
     if (csq(i) == 1) bz = -R(0.5) * (cx(i) ? Z[0] : (cy(i) ? Z[1] : Z[2]));
     const R ge = w * (rhoE + cqe * inv_theta +
                       (rt2 * (R(csq(i)) - R(3) * theta) + kappa * (cu * cu - theta * usq)) * h2) + bz -
-                 P.ref[LG][i];
+                 P.ref[LG][crep(i)];
     const R dn = ge + (R(1) - omega) * (from_store<S, R>(P, LG, i, v[i]) - ge) + w * cdq * inv_theta;
     v[i] = to_store<S, R>(P, LG, i, dn, rng);
     s0 += from_store<S, R>(P, LG, i, v[i]);

@@ -111,7 +111,7 @@ def test_launch_choices_are_bitwise_equal(mc, prec, three_pass):
             assert a == r, (launch, k)
 
 
-@pytest.mark.parametrize("prec,rtol", [("fp32", 1e-5), ("fp16", 2e-3), ("i16", 1e-3)])
+@pytest.mark.parametrize("prec,rtol", [("fp32", 1e-5), ("fp16", 2e-3), ("i16", 2e-3)])
 def test_step_paths_agree_to_rounding(mc, prec, rtol):
     """The two-read step, the three-pass step and its split collision (species
     lattices, then momentum and energy lattices, in two launches) compute the
