@@ -205,6 +205,18 @@ def fields_after(mc, params, fields, precision, nsteps, info=None):
     return out
 
 
+def sixteen_bit_summary(variants, base):
+    """The fastest 16-bit storage mode whose every field stays within 1e-3 of the
+    base run after the accuracy steps, with its speedup and worst field error (None
+    when none does)."""
+    ok = [(k, v) for k, v in variants.items() if k in ("fp16", "bf16", "i16") and v["meets_1e-3"]]
+    if not ok:
+        return None
+    k, v = max(ok, key=lambda kv: kv[1]["MLUPS"])
+    return {"storage": k, "MLUPS": v["MLUPS"], "speedup_vs_" + base: v["speedup_vs_" + base],
+            "worst_field_error": v["worst_field_error"]}
+
+
 def rel_errors(got, ref, u_floor=0.0):
     errs = {}
     for k in ("X", "rho", "u", "p", "T"):
@@ -610,6 +622,7 @@ def main():
                                "step_counted_GBs": (measured_step_bytes(args.precision, dom) or 0) * mlups * 1e6
                                / 1e9 or None},
         "variants": variants,
+        "sixteen_bit_at_1e-3": sixteen_bit_summary(variants, args.precision),
         "weak_coupling": weak,
         "weak_fp16": weak_fp16,
         "weak_i16": weak_i16,
