@@ -23,10 +23,11 @@
  *   - Streams: every call is ordered on the HIP stream given at creation; calls
  *     that return data to the host synchronise that stream. Calls on one context
  *     are not thread safe.
- *   - Under strong coupling (the default) species M (the last) is slaved to the
- *     mixture (Sec. 3.5.2): its density and momentum are the deficits of the
- *     mixture's. Order species so that the last one carries most of the mass
- *     everywhere. Under weak coupling (mclbm_params.weak) it has its own lattice.
+ *   - Under strong coupling (the default) one species is slaved to the mixture
+ *     (Sec. 3.5.2): its density and momentum are the deficits of the mixture's.
+ *     mclbm_params.slaved names it (default species M); choose one that carries
+ *     most of the mass everywhere. Under weak coupling (mclbm_params.weak) every
+ *     species has its own lattice.
  *   - Batches: a context holds one or more independent lattices ("tubes", the
  *     Loschmidt-tube setting of Sec. 4.2 repeated with different mixtures). All
  *     tubes of a context share M, wall_x, precision, the coupling and which
@@ -149,6 +150,13 @@ typedef struct {
                                 (X_1..X_M, p, T, u_x, u_y, u_z); else ignored           */
   int32_t nozzle_y0, nozzle_y1; /* wall_x = 3: the nozzle rows, 1 <= nozzle_y0 < nozzle_y1
                                 <= ny - 1; else ignored                                 */
+  int32_t slaved;      /* strong coupling: the species whose density and momentum
+                          follow from the mixture's (eqs rhoMATCH, uMATCH; the paper
+                          slaves the one carrying most of the mass), 1-based; 0 means
+                          species M. The library keeps it last internally; every array
+                          and field crossing this interface stays in the caller's
+                          species order. Weak coupling: 0 (or M). All tubes of a batch
+                          agree; mclbm_nn_advance takes only 0 (or M)             */
 } mclbm_params;
 
 /* Device workspace bytes a context with these parameters needs (0 on bad input). */
@@ -249,7 +257,8 @@ int64_t mclbm_step_count(const mclbm_ctx *c);
 
 /* Checkpoint: the population state, the reference tables and the step count,
  * copied to / from a host buffer of mclbm_state_bytes(c) bytes. Restoring into a
- * context created with the same parameters resumes bit for bit. */
+ * context created with the same parameters (M, boundaries, precision, coupling,
+ * slaved species, property kinds and tube sizes are checked) resumes bit for bit. */
 size_t mclbm_state_bytes(const mclbm_ctx *c);
 int mclbm_save(mclbm_ctx *c, void *host_buf, size_t bytes);
 int mclbm_load(mclbm_ctx *c, const void *host_buf, size_t bytes);

@@ -150,7 +150,9 @@ int mclbm_nn_mole_residual(mclbm_nn *net, int32_t species, const float *a, const
  * *max_residual receives the residual (HUGE_VAL for an infeasible prediction).
  * The network's tubes must be the context's and its channels M + 5 (X_1..X_M,
  * T, u_x, u_y, u_z, p: the layout of mclbm_read_fields_f32). The step count
- * advances by K. MCLBM_ENAN if the current state is not finite. */
+ * advances by K. MCLBM_ENAN if the current state is not finite;
+ * MCLBM_EUNSUPPORTED for a context whose slaved species is not the last
+ * (mclbm_params.slaved other than 0 or M). */
 int mclbm_nn_advance(mclbm_ctx *c, mclbm_nn *net, int32_t K, double resid_tol, int32_t *used_fallback,
                      double *max_residual);
 

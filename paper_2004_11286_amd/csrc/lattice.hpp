@@ -110,6 +110,9 @@ struct Params {
   R inl[MAXL][Q];         // open x ends and the jet at x = 0: inlet equilibrium minus f_ref, per stored lattice
   R inl2[MAXL][Q];        // opposed jets: the jet at x = nx - 1
   R absent_tol;           // |rho_a| <= absent_tol * rho: species absent, V_a = 0
+  int32_t xperm[MAXM];    // the caller's index of species a (the slaved species is a = M-1
+                          // here and may be any species to the caller): plane of X read
+                          // by initialisation and written by the read-back
 };
 
 }  // namespace mclbm

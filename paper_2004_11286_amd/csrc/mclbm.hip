@@ -243,6 +243,8 @@ struct mclbm_ctx {
   int32_t* dRange = nullptr;      // fixed point: k_range16 output [ntubes][MAXL][NCLS][2]
   double* dTab = nullptr;         // fixed point: k_rebase16 tables [ntubes][MAXL][NCLS][4]
   int64_t reranges = 0;           // fixed point: re-encodings since mclbm_init_fields or mclbm_load
+  int32_t xperm[MAXM] = {};       // the caller's index of the library's species a (slaved: a = M - 1)
+  bool xperm_identity = true;
   int cur = 0;
   int64_t steps = 0;
   bool initialised = false;
@@ -406,6 +408,11 @@ int validate_one(const mclbm_params* p, std::string& err)
   if (p->wall_x && p->nx < 2) { err = "walls need nx >= 2"; return MCLBM_EARG; }
   if (p->precision < MCLBM_FP64 || p->precision > MCLBM_I16) { err = "unknown precision"; return MCLBM_EARG; }
   if (p->weak != 0 && p->weak != 1) { err = "weak must be 0 or 1"; return MCLBM_EARG; }
+  if (p->slaved < 0 || p->slaved > p->M) { err = "slaved must be 0 (species M) or 1..M"; return MCLBM_EARG; }
+  if (p->weak && p->slaved != 0 && p->slaved != p->M) {
+    err = "weak coupling slaves no species: slaved must be 0";
+    return MCLBM_EARG;
+  }
   if (p->wall_y < 0 || p->wall_y > 2) { err = "wall_y must be 0, 1 or 2"; return MCLBM_EARG; }
   if (p->wall_y == 1) {
     if (p->ny < 2) { err = "free-slip y walls need ny >= 2"; return MCLBM_EARG; }
@@ -459,6 +466,9 @@ int validate_one(const mclbm_params* p, std::string& err)
   return MCLBM_OK;
 }
 
+// The caller's (0-based) index of the slaved species: slaved = 0 means species M.
+int slaved_of(const mclbm_params* p) { return p->slaved == 0 ? p->M - 1 : p->slaved - 1; }
+
 int validate(const mclbm_params* tp, int ntubes, std::string& err)
 {
   if (!tp) { err = "params is NULL"; return MCLBM_EARG; }
@@ -472,10 +482,11 @@ int validate(const mclbm_params* tp, int ntubes, std::string& err)
     }
     if (tp[t].M != tp[0].M || tp[t].wall_x != tp[0].wall_x || tp[t].precision != tp[0].precision ||
         tp[t].weak != tp[0].weak || tp[t].wall_y != tp[0].wall_y ||
+        slaved_of(&tp[t]) != slaved_of(&tp[0]) ||
         (tp[t].cv_coef == nullptr) != (tp[0].cv_coef == nullptr) ||
         (tp[t].transport_exp == nullptr) != (tp[0].transport_exp == nullptr)) {
-      err = "all tubes of a batch must share M, wall_x, precision, weak and whether cv_coef and transport_exp are "
-            "given";
+      err = "all tubes of a batch must share M, wall_x, precision, weak, the slaved species and whether cv_coef "
+            "and transport_exp are given";
       return MCLBM_EARG;
     }
     const int64_t n = (int64_t)tp[t].nx * tp[t].ny * tp[t].nz;
@@ -558,10 +569,10 @@ int push_params(mclbm_ctx* c)
       for (int i = 0; i < Q; ++i)
         if (!(th.tab.ref[l][i] == th.tab.ref[l][crep(i)]))
           return fail(c, MCLBM_ESTATE, "reference tables differ within a direction class");
-    fill_params<double>(c->hPd[t], th.hs, th.nx, th.ny, th.nz, c->wall_x, c->L, th.tab, tol, c->dFlag + t, th.noz0,
-                        th.noz1);
-    fill_params<float>(c->hPf[t], th.hs, th.nx, th.ny, th.nz, c->wall_x, c->L, th.tab, tol, c->dFlag + t, th.noz0,
-                       th.noz1);
+    fill_params<double>(c->hPd[t], th.hs, th.nx, th.ny, th.nz, c->wall_x, c->L, th.tab, tol, c->dFlag + t, c->xperm,
+                        th.noz0, th.noz1);
+    fill_params<float>(c->hPf[t], th.hs, th.nx, th.ny, th.nz, c->wall_x, c->L, th.tab, tol, c->dFlag + t, c->xperm,
+                       th.noz0, th.noz1);
     // the inlet equilibria of every stored lattice, as deviations from f_ref: the
     // initialisation of one node (n = 1, unit scale) at the inlet fields (open x
     // ends: one inlet; opposed jets: one per x face)
@@ -1091,6 +1102,14 @@ extern "C" int mclbm_batch_create(const mclbm_params* tp, int32_t ntubes, void* 
   c->n = lay.n;
   c->nblocks = lay.nblocks;
   c->tubes.resize(ntubes);
+  {
+    const int sl = slaved_of(&tp[0]);
+    int k = 0;
+    for (int a = 0; a < c->M; ++a)
+      if (a != sl) c->xperm[k++] = a;
+    c->xperm[c->M - 1] = sl;
+    for (int a = 0; a < c->M; ++a) c->xperm_identity = c->xperm_identity && c->xperm[a] == a;
+  }
   int64_t base = 0;
   for (int t = 0; t < ntubes; ++t) {
     const mclbm_params* p = &tp[t];
@@ -1100,18 +1119,21 @@ extern "C" int mclbm_batch_create(const mclbm_params* tp, int32_t ntubes, void* 
     th.base = base;
     base += th.n;
     th.hs.M = p->M;
+    // species in the library's order: the caller's, with the slaved species moved last
+    const int* xp = c->xperm;
     for (int a = 0; a < p->M; ++a) {
-      th.hs.m[a] = p->molar_mass[a];
-      th.hs.cv[a] = p->cv[a];
-      th.hs.mu[a] = p->mu[a];
-      th.hs.lam[a] = p->lambda[a];
-      for (int b = 0; b < p->M; ++b) th.hs.D[a][b] = p->D[a * p->M + b];
-      for (int k = 0; k < 4; ++k) th.hs.cvc[a][k] = p->cv_coef ? p->cv_coef[a * 4 + k] : (k == 0 ? p->cv[a] : 0.0);
+      const int ua = xp[a];
+      th.hs.m[a] = p->molar_mass[ua];
+      th.hs.cv[a] = p->cv[ua];
+      th.hs.mu[a] = p->mu[ua];
+      th.hs.lam[a] = p->lambda[ua];
+      for (int b = 0; b < p->M; ++b) th.hs.D[a][b] = p->D[ua * p->M + xp[b]];
+      for (int k = 0; k < 4; ++k) th.hs.cvc[a][k] = p->cv_coef ? p->cv_coef[ua * 4 + k] : (k == 0 ? p->cv[ua] : 0.0);
     }
     th.hs.cvt = p->cv_coef != nullptr;
     for (int a = 0; a < p->M; ++a) {
-      th.hs.s_mu[a] = p->transport_exp ? p->transport_exp[a] : 0.0;
-      th.hs.s_lam[a] = p->transport_exp ? p->transport_exp[p->M + a] : 0.0;
+      th.hs.s_mu[a] = p->transport_exp ? p->transport_exp[xp[a]] : 0.0;
+      th.hs.s_lam[a] = p->transport_exp ? p->transport_exp[p->M + xp[a]] : 0.0;
     }
     th.hs.s_D = p->transport_exp ? p->transport_exp[2 * p->M] : 0.0;
     th.hs.T_ref = p->transport_exp ? p->transport_exp[2 * p->M + 1] : 1.0;
@@ -1303,7 +1325,7 @@ extern "C" int mclbm_init_fields(mclbm_ctx* c, const double* X, const double* p,
         sum[M] += p[th.base + i];
         sum[M + 1] += T[th.base + i];
       }
-      for (int a = 0; a < M; ++a) rs[t].X[a] = sum[a] / n;
+      for (int a = 0; a < M; ++a) rs[t].X[a] = sum[c->xperm[a]] / n;
       rs[t].p = sum[M] / n;
       rs[t].T = sum[M + 1] / n;
     }
@@ -1328,7 +1350,7 @@ extern "C" int mclbm_init_fields(mclbm_ctx* c, const double* X, const double* p,
       const double* s = &sum[(size_t)t * (M + 2)];
       double xs = 0.0;
       for (int a = 0; a < M; ++a) {
-        rs[t].X[a] = s[a] / n;
+        rs[t].X[a] = s[c->xperm[a]] / n;
         xs += rs[t].X[a];
       }
       rs[t].p = s[M] / n;
@@ -1564,7 +1586,8 @@ extern "C" int mclbm_conservation(mclbm_ctx* c, double* out)
   if (rc) return rc;
   bool flagged = false;
   for (int t = 0; t < c->ntubes; ++t) {
-    for (int k = 0; k < c->M + 5; ++k) out[(size_t)t * (c->M + 5) + k] = tmp[(size_t)t * nv + k];
+    for (int k = 0; k < c->M + 5; ++k)
+      out[(size_t)t * (c->M + 5) + (k < c->M ? c->xperm[k] : k)] = tmp[(size_t)t * nv + k];
     flagged = flagged || tmp[(size_t)t * nv + c->M + 5] != 0.0;
   }
   if (flagged) return fail(c, MCLBM_ENAN, "non-finite value or negative slaved density in the state");
@@ -1579,7 +1602,14 @@ extern "C" int mclbm_half_tube_moles(mclbm_ctx* c, double* out)
   c->ops.half_moles(c->dPd, launch_all(c), c->pop[c->cur], c->partial, (unsigned)c->nblocks, c->stream);
   int rc = check_launch(c, "k_half_moles");
   if (rc) return rc;
-  return reduce_to_host(c, nv, out);
+  std::vector<double> tmp((size_t)c->ntubes * nv);
+  rc = reduce_to_host(c, nv, tmp.data());
+  if (rc) return rc;
+  for (int t = 0; t < c->ntubes; ++t)
+    for (int h = 0; h < 2; ++h)
+      for (int a = 0; a < c->M; ++a)
+        out[(size_t)t * nv + h * c->M + c->xperm[a]] = tmp[(size_t)t * nv + h * c->M + a];
+  return MCLBM_OK;
 }
 
 extern "C" int64_t mclbm_step_count(const mclbm_ctx* c) { return c ? c->steps : -1; }
@@ -1590,13 +1620,14 @@ struct CkptHeader {
   int32_t M, wall_x, precision, ntubes;
   int32_t weak, cvt;
   int64_t steps;
+  int32_t slaved, pad;   // the caller's index of the slaved species
 };
 struct CkptTube {
   int32_t nx, ny, nz;
   uint32_t range_flag;   // fixed point: the tube's range flag between two checks
   RefTables tab;
 };
-const char kMagic[8] = "MCLBMv4";
+const char kMagic[8] = "MCLBMv5";
 
 size_t header_bytes(const mclbm_ctx* c) { return sizeof(CkptHeader) + sizeof(CkptTube) * c->ntubes; }
 }  // namespace
@@ -1617,6 +1648,7 @@ extern "C" int mclbm_save(mclbm_ctx* c, void* host_buf, size_t bytes)
   h.M = c->M; h.wall_x = c->wall_x | (c->wall_y << 2);   // the x and y boundary kinds
   h.precision = c->precision; h.ntubes = c->ntubes; h.weak = c->weak; h.cvt = c->cvt;
   h.steps = c->steps;
+  h.slaved = c->xperm[c->M - 1];
   std::vector<uint32_t> flags(c->ntubes, 0);
   if (c->precision == MCLBM_I16) {
     HIP_TRY(c, hipMemcpyAsync(flags.data(), c->dFlag, sizeof(uint32_t) * c->ntubes, hipMemcpyDeviceToHost,
@@ -1648,7 +1680,7 @@ extern "C" int mclbm_load(mclbm_ctx* c, const void* host_buf, size_t bytes)
   std::memcpy(&h, src, sizeof(h));
   if (std::memcmp(h.magic, kMagic, 8) != 0 || h.M != c->M || h.wall_x != (c->wall_x | (c->wall_y << 2)) ||
       h.precision != c->precision ||
-      h.ntubes != c->ntubes || h.weak != c->weak || h.cvt != c->cvt)
+      h.ntubes != c->ntubes || h.weak != c->weak || h.cvt != c->cvt || h.slaved != c->xperm[c->M - 1])
     return fail(c, MCLBM_EARG, "checkpoint does not match this context");
   std::vector<CkptTube> ct(c->ntubes);
   for (int t = 0; t < c->ntubes; ++t) {
@@ -1821,6 +1853,8 @@ extern "C" int mclbm_nn_advance(mclbm_ctx* c, mclbm_nn* net, int32_t K, double r
   if (!net) return fail(c, MCLBM_EARG, "network is NULL");
   if (!c->initialised) return fail(c, MCLBM_EARG, "no state yet");
   if (K < 1) return fail(c, MCLBM_EARG, "K must be positive");
+  if (!c->xperm_identity)
+    return fail(c, MCLBM_EUNSUPPORTED, "the surrogate takes contexts whose slaved species is the last (slaved = 0)");
   const int M = c->M;
   int channels = 0, species = 0;
   std::vector<int> dims;

@@ -1518,7 +1518,7 @@ __host__ __device__ __forceinline__ void read_node(const Params<R>& P, const S* 
   mixture_state<R, M, WEAK, CVT>(P, rho, j, rhoE, rho_s, s);
   if (X)
 #pragma unroll
-    for (int a = 0; a < M; ++a) X[(size_t)a * n + node] = (double)s.X[a];
+    for (int a = 0; a < M; ++a) X[(size_t)P.xperm[a] * n + node] = (double)s.X[a];
   if (rho_o) rho_o[node] = (double)s.rho;
   if (u)
 #pragma unroll
@@ -1540,7 +1540,7 @@ __host__ __device__ __forceinline__ int init_node(const Params<double>& P, const
   double Xa[M], mmix = 0.0;
 #pragma unroll
   for (int a = 0; a < M; ++a) {
-    Xa[a] = X[(size_t)a * n + node];
+    Xa[a] = X[(size_t)P.xperm[a] * n + node];
     mmix += Xa[a] * P.m[a];
   }
   const double Tn = T[node], pn = p[node];

@@ -111,7 +111,8 @@ inline void reference_tables(const HostSpecies& h, int ns, const RefState& rs, R
 // range_flag is the context's device word that fixed-point kernels report to.
 template <typename R>
 inline void fill_params(Params<R>& P, const HostSpecies& h, int nx, int ny, int nz, int wall_x, int L,
-                        const RefTables& t, double absent_tol, uint32_t* range_flag, int noz0 = 0, int noz1 = 0)
+                        const RefTables& t, double absent_tol, uint32_t* range_flag, const int32_t* xperm,
+                        int noz0 = 0, int noz1 = 0)
 {
   std::memset(&P, 0, sizeof(P));
   P.M = h.M;
@@ -150,6 +151,7 @@ inline void fill_params(Params<R>& P, const HostSpecies& h, int nx, int ny, int 
     }
   }
   P.range_flag = range_flag;
+  for (int a = 0; a < MAXM; ++a) P.xperm[a] = a < h.M ? xperm[a] : a;
   P.absent_tol = R(absent_tol);
   P.s_D = R(h.s_D);
   P.trn = h.trn;

@@ -66,6 +66,7 @@ class mclbm_params(C.Structure):
         ("lam", C.POINTER(C.c_double)), ("cv_coef", C.POINTER(C.c_double)),
         ("inlet", C.POINTER(C.c_double)), ("transport_exp", C.POINTER(C.c_double)),
         ("inlet_right", C.POINTER(C.c_double)), ("nozzle_y0", C.c_int32), ("nozzle_y1", C.c_int32),
+        ("slaved", C.c_int32),
     ]
 
 
@@ -170,8 +171,10 @@ def _f64(a) -> np.ndarray:
 
 def make_params(params: dict, precision: int):
     """mclbm_params from a workload dict (``weak``: 1 for weak coupling, default 0;
-    the opposed jets add ``inlet_right`` and ``nozzle`` = (y0, y1)); returns
-    (struct, arrays kept alive)."""
+    ``slaved``: the 0-based index of the slaved species, default the last (the C
+    field is 1-based, 0 meaning the last); the opposed jets
+    add ``inlet_right`` and ``nozzle`` = (y0, y1)); returns (struct, arrays kept
+    alive)."""
     M = int(params["M"])
     arrs = [_f64(params["molar_mass"]), _f64(params["cv"]), _f64(params["D"]).reshape(M * M),
             _f64(params["mu"]), _f64(params["lambda"])]
@@ -191,7 +194,7 @@ def make_params(params: dict, precision: int):
                      int(params.get("wall_y", 0)),
                      *[a.ctypes.data_as(dp) for a in arrs[:5]],
                      *[a.ctypes.data_as(dp) if a is not None else None for a in (cvc, inl, tex, inr)],
-                     int(noz[0]), int(noz[1]))
+                     int(noz[0]), int(noz[1]), 0 if params.get("slaved") is None else int(params["slaved"]) + 1)
     return p, arrs
 
 

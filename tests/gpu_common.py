@@ -6,7 +6,8 @@ import numpy as np
 FIELDS = ("X", "rho", "u", "p", "T")
 
 # Checkpoint written by mclbm_save (see mclbm.hip): a header (magic[8], M,
-# wall_x, precision, ntubes, weak, cvt as int32, int64 step count), then per tube
+# wall_x, precision, ntubes, weak, cvt as int32, int64 step count, the caller's
+# 0-based index of the slaved species and a pad word), then per tube
 # its size, its fixed-point range flag and its reference tables (10 lattices: up
 # to 8 species, f, g; fixed-point factors per lattice and direction class), then
 # the stored populations of all tubes (M-1 species lattices under strong
@@ -14,7 +15,8 @@ FIELDS = ("X", "rho", "u", "p", "T")
 _MAXL = 10
 _NCLS = 8
 _HDR = np.dtype([("magic", "S8"), ("M", "<i4"), ("wall_x", "<i4"), ("precision", "<i4"),
-                 ("ntubes", "<i4"), ("weak", "<i4"), ("cvt", "<i4"), ("steps", "<i8")])
+                 ("ntubes", "<i4"), ("weak", "<i4"), ("cvt", "<i4"), ("steps", "<i8"),
+                 ("slaved", "<i4"), ("pad", "<i4")])
 _TUBE = np.dtype([("nx", "<i4"), ("ny", "<i4"), ("nz", "<i4"), ("range_flag", "<u4"),
                   ("ref", "<f8", (_MAXL, 27)), ("ref0", "<f8", (_MAXL,)), ("ref2", "<f8", (_MAXL, 3)),
                   ("scale", "<f8", (_MAXL,)), ("qs", "<f8", (_MAXL, _NCLS)), ("inv_qs", "<f8", (_MAXL, _NCLS))])
