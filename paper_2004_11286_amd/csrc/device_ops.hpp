@@ -40,6 +40,19 @@ __device__ inline int16_t cvt_sr_i16(float x, uint32_t rnd)
   return (int16_t)min(max(v, -32767), 32767);
 }
 
+// The same rounding in fewer instructions, for the step kernels: y = a b + 32768 +
+// r with r = k / 256 (k the 8 random bits), formed by one FMA whose addend is the
+// float 32768 with k in its low mantissa byte (its unit there is 2^-8: FP32
+// resolves no finer fraction at 2^15 anyway). Truncating y >= 0 is its floor, so
+// the result is floor(a b + r), clamped to +-32767; y itself goes to the caller's
+// range tracking.
+__device__ inline int16_t fma_sr_i16(float a, float b, uint32_t k8, float& y)
+{
+  y = fmaf(a, b, __uint_as_float(0x47000000u | k8));
+  const int u = (int)y;
+  return (int16_t)(min(max(u, 1), 65535) - 32768);
+}
+
 // Convert an FP64 value to FP32 with stochastic rounding: a uniform random
 // number (the upper 24 bits of rnd) is added below the 29 mantissa bits that
 // FP32 drops, and those bits are then cut: the magnitude is rounded up with

@@ -635,13 +635,6 @@ struct Store<__bf16, float> {
   __host__ __device__ static __bf16 cvt(float x, uint32_t rnd) { return cvt_sr_bf16(x, rnd); }
 };
 
-// 16-bit fixed point: a value in units of the storage quantum of its lattice and
-// direction class, rounded stochastically to an integer in [-32767, 32767].
-template <>
-struct Store<int16_t, float> {
-  __host__ __device__ static int16_t cvt(float x, uint32_t rnd) { return cvt_sr_i16(x, rnd); }
-};
-
 template <typename S>
 constexpr bool is_fixed16() { return std::is_same<S, int16_t>::value; }
 
@@ -682,17 +675,31 @@ __host__ __device__ __forceinline__ S init_store(const Params<double>& P, int l,
 // some pairs), which leaves each rounding unbiased but raises the noise of the
 // first moments: FP16 storage of the ternary tube drifted 1.7 times further from
 // the FP64 result over 1000 steps.
-// With fixed-point storage it also keeps the largest magnitude (in storage units)
-// that the lattice's stores rounded, for range_check.
+// Fixed-point storage draws 8 bits per store, the two upper bytes of one word
+// for two stores (next8; the lower bytes of a power-of-two LCG have short
+// periods), and keeps the range of the rounded values (32768 plus the value in
+// storage units) for range_check.
 struct Rng {
   uint32_t s;
-  float amax = 0.0f;
+  uint32_t held = 0;
+  bool have = false;
+  float ymax = 32768.0f, ymin = 32768.0f;
   __host__ __device__ Rng(int64_t node, int l, uint32_t step)
       : s(mix32((uint32_t)node ^ mix32((uint32_t)l * 0x632BE5ABu + step * 0x9E3779B1u))) {}
   __host__ __device__ uint32_t next()
   {
     s = s * 1664525u + 1013904223u;
     return s;
+  }
+  __host__ __device__ uint32_t next8()
+  {
+    if (have) {
+      have = false;
+      return (held >> 16) & 0xFFu;
+    }
+    held = next();
+    have = true;
+    return held >> 24;
   }
 };
 
@@ -701,9 +708,11 @@ template <typename S, typename R>
 __host__ __device__ __forceinline__ S to_store(const Params<R>& P, int l, int i, R dev, Rng& rng)
 {
   if constexpr (is_fixed16<S>()) {
-    const float x = float(dev * P.qs[l][ccls(i)]);
-    rng.amax = __builtin_elementwise_maximum(rng.amax, fabsf(x));   // NaN propagates
-    return Store<S, R>::cvt(x, rng.next());
+    float y;
+    const int16_t v = fma_sr_i16(float(dev), float(P.qs[l][ccls(i)]), rng.next8(), y);
+    rng.ymax = __builtin_elementwise_maximum(rng.ymax, y);   // NaN propagates
+    rng.ymin = __builtin_elementwise_minimum(rng.ymin, y);
+    return v;
   } else {
     return Store<S, R>::cvt(dev * P.scale[l], rng.next());
   }
@@ -718,15 +727,18 @@ __host__ __device__ __forceinline__ R from_store(const Params<R>& P, int l, int 
 // Fixed-point storage: after a lattice's stores, set bit 0 of the context's range
 // flag when a value passed 3/4 of its range (the host then re-ranges the state
 // before the margin is used up), and bits 0 and 1 when one was clamped or not
-// finite (the state is lost). One atomic per wavefront that sets it.
+// finite (the state is lost). One atomic per wavefront that sets it. Called after
+// the pushes: a branch before them would hold every value of the lattice in
+// registers until it (the fused f/g collision took 1.88 instead of 1.30 ms).
 template <typename S, typename R>
 __host__ __device__ __forceinline__ void range_check(const Params<R>& P, const Rng& rng)
 {
   if constexpr (is_fixed16<S>()) {
-    const bool hit = !(rng.amax < 24576.0f);
+    // in storage units: |v| past 24576, or past 32766 (clamped, or about to be)
+    const bool hit = !(rng.ymax < 32768.0f + 24576.0f && rng.ymin > 32768.0f - 24576.0f);
     const uint64_t any = __ballot(hit);
     if (any) {
-      const uint64_t bad = __ballot(hit && !(rng.amax <= 32766.0f));
+      const uint64_t bad = __ballot(hit && !(rng.ymax <= 32768.0f + 32766.0f && rng.ymin >= 32768.0f - 32766.0f));
       if ((int)__lane_id() == __ffsll((unsigned long long)any) - 1) atomicOr(P.range_flag, bad ? 3u : 1u);
     }
   }
@@ -939,9 +951,9 @@ __host__ __device__ __forceinline__ void species_relax(const Params<R>& P, const
   // the collision conserves rho_a: the rest population takes the defect of
   // the arithmetic and of the other 26 values' rounding to storage
   v[13] = to_store<S, R>(P, a, 13, t0 - s0, rng);
-  range_check<S, R>(P, rng);
 #pragma unroll
   for (int i = 0; i < Q; ++i) push<S, R, BC>(P, dst, b, a, i, node, v[i]);
+  range_check<S, R>(P, rng);
 }
 
 // Momentum lattice (stored lattice LF): f' = f + omega (f^eq - f) + A_i . X
@@ -995,9 +1007,9 @@ __host__ __device__ __forceinline__ void momentum_relax(const Params<R>& P, int 
   }
   restore_faces<S, R>(P, LF, face, t1, s1, s0, v, rng);
   v[13] = to_store<S, R>(P, LF, 13, t0 - s0, rng);
-  range_check<S, R>(P, rng);
 #pragma unroll
   for (int i = 0; i < Q; ++i) push<S, R, BC>(P, dst, b, LF, i, node, v[i]);
+  range_check<S, R>(P, rng);
 }
 
 // Energy lattice (stored lattice LG), eq g in the form
@@ -1046,9 +1058,9 @@ __host__ __device__ __forceinline__ void energy_relax(const Params<R>& P, int LG
   }
   // the collision conserves rho E: the rest population takes the defect
   v[13] = to_store<S, R>(P, LG, 13, t0 - s0, rng);
-  range_check<S, R>(P, rng);
 #pragma unroll
   for (int i = 0; i < Q; ++i) push<S, R, BC>(P, dst, b, LG, i, node, v[i]);
+  range_check<S, R>(P, rng);
 }
 
 // Load the Q stored values of lattice l of a node (one at a time: each load is
