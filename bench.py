@@ -318,6 +318,16 @@ def ensemble_bench(mc, steps: int = 50, seq_steps: int = 10, trial_steps: int = 
     b.close()
     del b
     torch.cuda.empty_cache()
+    # the same ensemble with FP32 arithmetic (FP32 storage rounded to nearest), autotuned
+    b = mc.Batch([p for p, _ in tubes], mc.MCLBM_FP32_FP32)
+    b.init_fields([f for _, f in tubes])
+    b.autotune(trial_steps)
+    chosen = b.launch()
+    out["autotuned_fp32_arithmetic"] = timed(steps, **chosen)
+    out["autotuned_fp32_arithmetic"]["launch"] = chosen
+    b.close()
+    del b
+    torch.cuda.empty_cache()
     return out
 
 
