@@ -304,13 +304,17 @@ __global__ __launch_bounds__(256) void k_conv(const NTube* __restrict__ tubes, c
 // The reduction runs over nodes, so both operands are staged transposed in LDS
 // (channel rows, node columns) for 128-node chunks; workgroup (g, (dy, dz)) sums
 // the chunks g, g + G, ... for the taps dx = -1, 0, +1 and writes its partials
-// [g][tap][COUT][CINP].
+// [g][tap][COUT][CINP]. With yz_fixed >= 0 the grid has one (dy, dz) column, that
+// one: when every tube is one node wide in y and z, the y and z shifts wrap onto
+// the node itself and the nine (dy, dz) columns would sum the same products in
+// the same order, so k_wgrad_reduce reads the one for all of them.
 constexpr int WCH = 128;   // nodes per staged chunk
 
 template <int CIN, int COUT>
 __global__ __launch_bounds__(256) void k_wgrad(const NTube* __restrict__ tubes, const int32_t* __restrict__ tile_tube,
                                                int ntubes, int nchunks, const bf16* __restrict__ dY,
-                                               const bf16* __restrict__ X, float* __restrict__ partial)
+                                               const bf16* __restrict__ X, float* __restrict__ partial,
+                                               int yz_fixed)
 {
   constexpr int CINP = CIN < 32 ? 32 : CIN;
   constexpr int S = WCH + 8;
@@ -321,7 +325,7 @@ __global__ __launch_bounds__(256) void k_wgrad(const NTube* __restrict__ tubes, 
   // windows overlap (two of them come from the cache)
   __shared__ __attribute__((aligned(16))) bf16 dyt[COUT * S];
   __shared__ __attribute__((aligned(16))) bf16 xt[3][CINP * S];
-  const int yz = blockIdx.y, g = blockIdx.x, G = gridDim.x;
+  const int yz = yz_fixed >= 0 ? yz_fixed : (int)blockIdx.y, g = blockIdx.x, G = gridDim.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int dy = yz % 3 - 1, dz = yz / 3 - 1;
   const int tap0 = 9 * (dz + 1) + 3 * (dy + 1);   // taps tap0 + k, dx = k - 1
@@ -450,17 +454,19 @@ __global__ __launch_bounds__(256) void k_wgrad(const NTube* __restrict__ tubes, 
 // layer (co < co_r, j < ci_r) from the padded partials [G][tap][COUTP][CINP],
 // fixed order. With second terms (P > 0, layer 0) parameter column j < C also
 // collects column C + j (j < P) divided by 256, and the conditioning
-// parameters j >= C sit at column j + P.
+// parameters j >= C sit at column j + P. With flat != 0 (tubes one node wide in
+// y and z) every tap reads the partials of its dx at dy = dz = 0.
 __global__ void k_wgrad_reduce(const float* __restrict__ partial, int G, int COUTP, int CINP, int co_r, int ci_r,
-                               int C, int P, float* __restrict__ grad)
+                               int C, int P, float* __restrict__ grad, int flat)
 {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= NTAP * co_r * ci_r) return;
   const int j = k % ci_r, co = (k / ci_r) % co_r, tap = k / (ci_r * co_r);
+  const int ptap = flat ? 12 + tap % 3 : tap;      // tap 9 (dz + 1) + 3 (dy + 1) + (dx + 1)
   const int col = (P > 0 && j >= C) ? j + P : j;
   float s = 0.f, s2 = 0.f;
   for (int g = 0; g < G; ++g) {
-    const size_t row = (((size_t)g * NTAP + tap) * COUTP + co) * CINP;
+    const size_t row = (((size_t)g * NTAP + ptap) * COUTP + co) * CINP;
     s += partial[row + col];
     if (P > 0 && j < P) s2 += partial[row + C + j];
   }
@@ -922,6 +928,7 @@ struct mclbm_nn {
   int Ms = 0;                           // species of the conservative output (0: direct output)
   int Cout = 0;                         // output channels: C, or 3 Ms + 4
   int64_t n = 0, ntiles = 0;
+  bool flat_yz = false;                 // every tube is one node wide in y and z
   hipStream_t stream = nullptr;
   std::string err;
   std::vector<NTube> hTubes;
@@ -1111,14 +1118,14 @@ void wgrad(mclbm_nn* net, const bf16* dY, const bf16* X, int layer)
 {
   constexpr int CINP = CIN < 32 ? 32 : CIN;
   const int nchunks = (int)(2 * net->ntiles);
-  hipLaunchKernelGGL((k_wgrad<CIN, COUT>), dim3(net->wG, NTAP / 3), dim3(256), 0, net->stream, net->dTubes,
-                     net->dTileTube, net->ntubes, nchunks, dY, X, net->wpart);
+  hipLaunchKernelGGL((k_wgrad<CIN, COUT>), dim3(net->wG, net->flat_yz ? 1 : NTAP / 3), dim3(256), 0, net->stream,
+                     net->dTubes, net->dTileTube, net->ntubes, nchunks, dY, X, net->wpart, net->flat_yz ? 4 : -1);
   // only the real channels have parameters (the padded ones stay zero)
   const int co_r = net->out_r[layer], ci_r = net->in_r[layer];
   const int n = NTAP * co_r * ci_r;
   hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks_for(n, 256)), dim3(256), 0, net->stream, net->wpart, net->wG,
                      COUT, CINP, co_r, ci_r, layer == 0 ? net->C : ci_r, layer == 0 ? net->P : 0,
-                     net->grad + net->w_off[layer]);
+                     net->grad + net->w_off[layer], net->flat_yz ? 1 : 0);
 }
 
 void bgrad(mclbm_nn* net, const bf16* dY, int C, int layer)
@@ -1234,6 +1241,8 @@ extern "C" int mclbm_nn_create(int32_t channels, int32_t two_term, int32_t condi
     tile += tb.ntiles;
     base += n;
   }
+  net->flat_yz = true;
+  for (const NTube& tb : net->hTubes) net->flat_yz = net->flat_yz && tb.ny == 1 && tb.nz == 1;
   for (int c = 0; c < MAXC; ++c) {
     net->norm.in_shift[c] = 0.f;
     net->norm.in_scale[c] = 1.f;

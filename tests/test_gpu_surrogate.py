@@ -156,6 +156,44 @@ def test_loss_and_gradients_match_oracle(env, Pn, Sn):
             assert rel < GRAD_BOUND, (li, name, rel)
 
 
+def test_gradients_match_oracle_on_one_node_wide_tubes(env):
+    """Tubes one node wide in y and z, as in training: the y and z shifts of every
+    tap wrap onto the node itself, and the weight gradient is summed once per dx
+    and read by all nine (dy, dz) taps; elementwise against the oracle."""
+    _, torch = env
+    depth = 3
+    dims = [(37, 1, 1), (64, 1, 1), (9, 1, 1)]
+    p = S.he_init(C, depth, seed=17, gain=1.0)
+    p += np.random.default_rng(12).normal(0, 0.02, p.size).astype(np.float32)
+    nm = norm_arrays(1)
+    nm64 = {k: np.asarray(v, np.float32).astype(np.float64) for k, v in nm.items()}
+    net = make_net(env, depth, p, nm, dims=dims)
+    fs = [f.astype(np.float32).astype(np.float64) for f in random_fields(13, dims=dims)]
+    rng = np.random.default_rng(14)
+    tg = [(f + 0.05 * rng.normal(size=f.shape)).astype(np.float32).astype(np.float64) for f in fs]
+    w = np.linspace(0.5, 2.0, C).astype(np.float32)
+    net.zero_grad()
+    net.forward(flat(env, fs))
+    loss = net.loss(flat(env, tg), w)
+    net.backward()
+    g_gpu = net.get_grads().astype(np.float64)
+    net.close()
+    L_ref, g_ref = S.loss_and_grad(p, fs, tg, nm64, C, depth, weight=w.astype(np.float64), round_bf16=True)
+    assert loss == pytest.approx(L_ref, rel=5e-3)
+    k = 0
+    for li, (o, i) in enumerate(S.layer_shapes(C, depth)):
+        for name, size in (("W", 27 * o * i), ("b", o)):
+            a, b = g_gpu[k:k + size], g_ref[k:k + size]
+            k += size
+            rel = np.abs(a - b).max() / np.abs(b).max()
+            print("one-node-wide grad layer", li, name, "elementwise rel linf", rel)
+            assert rel < GRAD_BOUND, (li, name, rel)
+            if name == "W":   # the nine (dy, dz) taps of each dx carry the same gradient
+                gw = a.reshape(3, 3, 3, o, i)
+                for dx in range(3):
+                    assert np.all(gw[:, :, dx] == gw[1, 1, dx]), (li, dx)
+
+
 def test_adam_step_matches_oracle(env):
     depth = 3
     p = S.he_init(C, depth, seed=11)
