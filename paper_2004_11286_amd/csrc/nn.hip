@@ -307,7 +307,9 @@ __global__ __launch_bounds__(256) void k_conv(const NTube* __restrict__ tubes, c
 // [g][tap][COUT][CINP]. With yz_fixed >= 0 the grid has one (dy, dz) column, that
 // one: when every tube is one node wide in y and z, the y and z shifts wrap onto
 // the node itself and the nine (dy, dz) columns would sum the same products in
-// the same order, so k_wgrad_reduce reads the one for all of them.
+// the same order, so k_wgrad_reduce reads the one for all of them. The partials
+// are then [g][dx][COUT][CINP], and nine times as many workgroups share the
+// chunks (the same buffer).
 constexpr int WCH = 128;   // nodes per staged chunk
 
 template <int CIN, int COUT>
@@ -445,7 +447,8 @@ __global__ __launch_bounds__(256) void k_wgrad(const NTube* __restrict__ tubes, 
       for (int v = 0; v < 16; ++v) {
         const int row = mb * 32 + 8 * (v / 4) + 4 * (lane >> 5) + (v % 4);
         const int col = cb * 32 + (lane & 31);
-        partial[(((size_t)g * NTAP + tap0 + k) * COUT + row) * CINP + col] = acc[k][q][v];
+        const size_t pt = yz_fixed >= 0 ? (size_t)g * 3 + k : (size_t)g * NTAP + tap0 + k;
+        partial[(pt * COUT + row) * CINP + col] = acc[k][q][v];
       }
     }
 }
@@ -455,38 +458,50 @@ __global__ __launch_bounds__(256) void k_wgrad(const NTube* __restrict__ tubes, 
 // fixed order. With second terms (P > 0, layer 0) parameter column j < C also
 // collects column C + j (j < P) divided by 256, and the conditioning
 // parameters j >= C sit at column j + P. With flat != 0 (tubes one node wide in
-// y and z) every tap reads the partials of its dx at dy = dz = 0.
+// y and z) the partials are [G][dx][COUTP][CINP] and every tap reads its dx.
 __global__ void k_wgrad_reduce(const float* __restrict__ partial, int G, int COUTP, int CINP, int co_r, int ci_r,
                                int C, int P, float* __restrict__ grad, int flat)
 {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= NTAP * co_r * ci_r) return;
   const int j = k % ci_r, co = (k / ci_r) % co_r, tap = k / (ci_r * co_r);
-  const int ptap = flat ? 12 + tap % 3 : tap;      // tap 9 (dz + 1) + 3 (dy + 1) + (dx + 1)
+  const int npt = flat ? 3 : NTAP;
+  const int ptap = flat ? tap % 3 : tap;      // tap 9 (dz + 1) + 3 (dy + 1) + (dx + 1)
   const int col = (P > 0 && j >= C) ? j + P : j;
   float s = 0.f, s2 = 0.f;
   for (int g = 0; g < G; ++g) {
-    const size_t row = (((size_t)g * NTAP + ptap) * COUTP + co) * CINP;
+    const size_t row = (((size_t)g * npt + ptap) * COUTP + co) * CINP;
     s += partial[row + col];
     if (P > 0 && j < P) s2 += partial[row + C + j];
   }
   grad[k] += s + s2 * (1.f / 256.f);
 }
 
-// Bias gradient partials: partial[tile][c] = sum over the tile's nodes of dY[node][c].
+// Bias gradient partials: partial[tile][c] = sum over the tile's nodes of dY[node][c]
+// (C <= WIDTH). The four wavefronts each sum a quarter of the tile's nodes for
+// every channel, then the quarters are added in order.
 __global__ __launch_bounds__(256) void k_bgrad(const NTube* __restrict__ tubes, const int32_t* __restrict__ tile_tube,
                                                int ntubes, int C, const bf16* __restrict__ dY,
                                                float* __restrict__ partial)
 {
+  constexpr int NQ = 256 / WIDTH, QN = TILE / NQ;
+  __shared__ float part[NQ][WIDTH];
   const int tile = blockIdx.x;
   const NTube tb = tube_of(tubes, tile_tube, ntubes, tile);
   const int n_t = tb.nx * tb.ny * tb.nz;
-  const int c = threadIdx.x;
-  if (c >= C) return;
+  const int c = threadIdx.x % WIDTH, q = threadIdx.x / WIDTH;
+  const int n0 = (tile - tb.first_tile) * TILE + q * QN;
   float s = 0.f;
-  const int n0 = (tile - tb.first_tile) * TILE;
-  for (int i = 0; i < TILE && n0 + i < n_t; ++i) s += (float)dY[aidx(tb, tb.base + n0 + i, c)];
-  partial[(size_t)tile * C + c] = s;
+  if (c < C)
+    for (int i = 0; i < QN && n0 + i < n_t; ++i) s += (float)dY[aidx(tb, tb.base + n0 + i, c)];
+  part[q][c] = s;
+  __syncthreads();
+  if (threadIdx.x < C) {
+    float t = 0.f;
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) t += part[k][threadIdx.x];
+    partial[(size_t)tile * C + threadIdx.x] = t;
+  }
 }
 
 // grad[c] += sum_t partial[t][c] for the real channels c < count (row stride C):
@@ -688,8 +703,10 @@ __global__ __launch_bounds__(256) void k_unpack_cons(const NTube* __restrict__ t
 // the target. On a tube with walls and fields uniform in y and z this is the one
 // flux field whose divergence gives the target change (zero through the left
 // wall); it pins the uniform flux offset that the divergence alone cannot see.
-// The thread at the start of a row (x = 0) scans it in FP64. Output fs [n][M].
-__global__ __launch_bounds__(256) void k_flux_target(const NTube* __restrict__ tubes,
+// Two passes: k_flux_change writes each node's n*_s - n_s (formed in FP64) into
+// fs [n][M], one thread per node; k_flux_target then scans every (row, species)
+// in FP64, one thread each, in place.
+__global__ __launch_bounds__(256) void k_flux_change(const NTube* __restrict__ tubes,
                                                      const int32_t* __restrict__ tile_tube, int ntubes, int M,
                                                      const float* __restrict__ f, const float* __restrict__ target,
                                                      float* __restrict__ fs)
@@ -698,16 +715,36 @@ __global__ __launch_bounds__(256) void k_flux_target(const NTube* __restrict__ t
   const NTube tb = tube_of(tubes, tile_tube, ntubes, tile);
   const int n_t = tb.nx * tb.ny * tb.nz;
   const int node = (tile - tb.first_tile) * TILE + threadIdx.x;
-  if (node >= n_t || node % tb.nx != 0) return;
+  if (node >= n_t) return;
   const size_t o = (size_t)(M + 5) * tb.base;
-  for (int s = 0; s < M; ++s) {
-    double acc = 0.0;
-    for (int x = 0; x < tb.nx; ++x) {
-      const int k = node + x;
-      auto at = [&](const float* a, int c) -> double { return (double)a[o + (size_t)c * n_t + k]; };
-      acc -= at(target, M + 4) * at(target, s) / at(target, M) - at(f, M + 4) * at(f, s) / at(f, M);
-      fs[(tb.base + k) * M + s] = (float)acc;
-    }
+  auto at = [&](const float* a, int c) -> double { return (double)a[o + (size_t)c * n_t + node]; };
+  for (int s = 0; s < M; ++s)
+    fs[(tb.base + node) * M + s] =
+        (float)(at(target, M + 4) * at(target, s) / at(target, M) - at(f, M + 4) * at(f, s) / at(f, M));
+}
+
+// Row r of tube t (ny nz rows of nx nodes), species s: thread ((t's first row +
+// r) M + s) of a launch over every row of every tube (row_first[t]: rows of the
+// tubes before t).
+__global__ __launch_bounds__(256) void k_flux_target(const NTube* __restrict__ tubes, const int32_t* __restrict__ row_first,
+                                                     int ntubes, int64_t nrows, int M, float* __restrict__ fs)
+{
+  const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (id >= nrows * M) return;
+  const int64_t row = id / M;
+  const int s = (int)(id % M);
+  int lo = 0, hi = ntubes - 1;                 // the tube: last t with row_first[t] <= row
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (row_first[mid] <= row) lo = mid;
+    else hi = mid - 1;
+  }
+  const NTube tb = tubes[lo];
+  float* p = fs + (tb.base + (row - row_first[lo]) * tb.nx) * M + s;
+  double acc = 0.0;
+  for (int x = 0; x < tb.nx; ++x) {
+    acc -= (double)p[(size_t)x * M];
+    p[(size_t)x * M] = (float)acc;
   }
 }
 
@@ -933,6 +970,7 @@ struct mclbm_nn {
   std::string err;
   std::vector<NTube> hTubes;
   std::vector<int32_t> hTileTube;
+  std::vector<int32_t> hRowFirst;
   Norm norm{};
   // per layer: real and padded sizes, offsets into the parameter arrays
   std::vector<int> in_r, out_r, in_p, out_p;
@@ -942,6 +980,8 @@ struct mclbm_nn {
   // device regions
   NTube* dTubes = nullptr;
   int32_t* dTileTube = nullptr;
+  int32_t* dRowFirst = nullptr;         // x rows of the tubes before each tube
+  int64_t nrows = 0;                    // x rows of all tubes
   float *master = nullptr, *mom1 = nullptr, *mom2 = nullptr, *grad = nullptr;
   std::vector<bf16*> wf, wb;            // packed BF16 weights per layer
   std::vector<float*> bp;               // padded biases per layer
@@ -950,7 +990,8 @@ struct mclbm_nn {
   bf16* dy[2] = {nullptr, nullptr};     // activation gradients (ping-pong), [n][WIDTH]
   bf16* dyl = nullptr;                  // gradient of the last layer's output [n][COUTL]
   float* wpart = nullptr;               // weight-gradient partials
-  int wG = 0;
+  int wG = 0;                           // workgroups along the chunks (nine (dy, dz) columns each)
+  int wGf = 0;                          // the same with one column (flat_yz): up to nine times wG
   float* bpart = nullptr;               // bias-gradient partials [ntiles][WIDTH]
   double* dpart = nullptr;              // loss / residual partials
   float* cond = nullptr;                // [ntubes][S] conditioning values
@@ -980,7 +1021,7 @@ int nn_check(mclbm_nn* net, const char* what)
 }
 
 struct NNLayout {
-  size_t tubes, tile_tube, master, mom1, mom2, grad, wf, wb, bp, act, yout, dy, dyl, wpart, bpart, dpart, cond, fin, fout,
+  size_t tubes, tile_tube, row_first, master, mom1, mom2, grad, wf, wb, bp, act, yout, dy, dyl, wpart, bpart, dpart, cond, fin, fout,
       total;
   int64_t n, ntiles, nparam, nparam_p;
   int wG;
@@ -1052,6 +1093,7 @@ NNLayout nn_layout(int C, int P, int S, int Ms, int depth, const int32_t* dims, 
   auto take = [&](size_t bytes) { size_t o = off; off += align_up(bytes); return o; };
   l.tubes = take(sizeof(NTube) * ntubes);
   l.tile_tube = take(sizeof(int32_t) * l.ntiles);
+  l.row_first = take(sizeof(int32_t) * ntubes);
   l.master = take(sizeof(float) * l.nparam);
   l.mom1 = take(sizeof(float) * l.nparam);
   l.mom2 = take(sizeof(float) * l.nparam);
@@ -1118,12 +1160,13 @@ void wgrad(mclbm_nn* net, const bf16* dY, const bf16* X, int layer)
 {
   constexpr int CINP = CIN < 32 ? 32 : CIN;
   const int nchunks = (int)(2 * net->ntiles);
-  hipLaunchKernelGGL((k_wgrad<CIN, COUT>), dim3(net->wG, net->flat_yz ? 1 : NTAP / 3), dim3(256), 0, net->stream,
+  const int G = net->flat_yz ? net->wGf : net->wG;
+  hipLaunchKernelGGL((k_wgrad<CIN, COUT>), dim3(G, net->flat_yz ? 1 : NTAP / 3), dim3(256), 0, net->stream,
                      net->dTubes, net->dTileTube, net->ntubes, nchunks, dY, X, net->wpart, net->flat_yz ? 4 : -1);
   // only the real channels have parameters (the padded ones stay zero)
   const int co_r = net->out_r[layer], ci_r = net->in_r[layer];
   const int n = NTAP * co_r * ci_r;
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks_for(n, 256)), dim3(256), 0, net->stream, net->wpart, net->wG,
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks_for(n, 256)), dim3(256), 0, net->stream, net->wpart, G,
                      COUT, CINP, co_r, ci_r, layer == 0 ? net->C : ci_r, layer == 0 ? net->P : 0,
                      net->grad + net->w_off[layer], net->flat_yz ? 1 : 0);
 }
@@ -1178,6 +1221,7 @@ extern "C" int mclbm_nn_create(int32_t channels, int32_t two_term, int32_t condi
   net->ntiles = lay.ntiles;
   net->stream = (hipStream_t)hip_stream;
   net->wG = lay.wG;
+  net->wGf = (int)std::min<int64_t>(2 * lay.ntiles, 9 * (int64_t)lay.wG);
   layer_sizes(channels, net->Cout, two_term, conditioning, depth, net->in_r, net->out_r, net->in_p, net->out_p);
   int64_t off = 0;
   for (int k = 0; k < depth; ++k) {
@@ -1190,6 +1234,7 @@ extern "C" int mclbm_nn_create(int32_t channels, int32_t two_term, int32_t condi
   char* ws = (char*)dev_workspace;
   net->dTubes = (NTube*)(ws + lay.tubes);
   net->dTileTube = (int32_t*)(ws + lay.tile_tube);
+  net->dRowFirst = (int32_t*)(ws + lay.row_first);
   net->master = (float*)(ws + lay.master);
   net->mom1 = (float*)(ws + lay.mom1);
   net->mom2 = (float*)(ws + lay.mom2);
@@ -1243,6 +1288,12 @@ extern "C" int mclbm_nn_create(int32_t channels, int32_t two_term, int32_t condi
   }
   net->flat_yz = true;
   for (const NTube& tb : net->hTubes) net->flat_yz = net->flat_yz && tb.ny == 1 && tb.nz == 1;
+  net->hRowFirst.resize(ntubes);
+  net->nrows = 0;
+  for (int t = 0; t < ntubes; ++t) {
+    net->hRowFirst[t] = (int32_t)net->nrows;
+    net->nrows += (int64_t)net->hTubes[t].ny * net->hTubes[t].nz;
+  }
   for (int c = 0; c < MAXC; ++c) {
     net->norm.in_shift[c] = 0.f;
     net->norm.in_scale[c] = 1.f;
@@ -1255,6 +1306,9 @@ extern "C" int mclbm_nn_create(int32_t channels, int32_t two_term, int32_t condi
                                 net->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(net->dTileTube, net->hTileTube.data(), sizeof(int32_t) * lay.ntiles, hipMemcpyHostToDevice,
+                       net->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(net->dRowFirst, net->hRowFirst.data(), sizeof(int32_t) * ntubes, hipMemcpyHostToDevice,
                        net->stream);
   if (e == hipSuccess) {
     // parameters, moments and gradients start at zero (set_params gives the weights)
@@ -1390,8 +1444,10 @@ extern "C" int mclbm_nn_loss(mclbm_nn* net, const float* target, const float* ch
     // activation-gradient buffer (free until backward; WIDTH BF16 = 128 bytes per node)
     float* gnode = (float*)net->dy[0];
     float* fstar = gnode + (size_t)net->n * net->Ms;
-    hipLaunchKernelGGL(k_flux_target, dim3(grid), dim3(256), 0, net->stream, net->dTubes, net->dTileTube,
+    hipLaunchKernelGGL(k_flux_change, dim3(grid), dim3(256), 0, net->stream, net->dTubes, net->dTileTube,
                        net->ntubes, net->Ms, net->fin, target, fstar);
+    hipLaunchKernelGGL(k_flux_target, dim3(blocks_for(net->nrows * net->Ms, 256)), dim3(256), 0, net->stream,
+                       net->dTubes, net->dRowFirst, net->ntubes, net->nrows, net->Ms, fstar);
     hipLaunchKernelGGL(k_loss_cons, dim3(grid), dim3(256), 0, net->stream, net->dTubes, net->dTileTube,
                        net->ntubes, net->Ms, nm, 1.0 / (double)net->n, net->fout, target, net->yout, fstar, gnode,
                        net->dyl, net->dpart);
