@@ -458,23 +458,52 @@ __global__ __launch_bounds__(256) void k_wgrad(const NTube* __restrict__ tubes, 
 // fixed order. With second terms (P > 0, layer 0) parameter column j < C also
 // collects column C + j (j < P) divided by 256, and the conditioning
 // parameters j >= C sit at column j + P. With flat != 0 (tubes one node wide in
-// y and z) the partials are [G][dx][COUTP][CINP] and every tap reads its dx.
-__global__ void k_wgrad_reduce(const float* __restrict__ partial, int G, int COUTP, int CINP, int co_r, int ci_r,
-                               int C, int P, float* __restrict__ grad, int flat)
+// y and z) the partials are [G][dx][COUTP][CINP]: each sum is formed once per dx
+// and added to the gradient of its nine taps.
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ partial, int G, int COUTP,
+                                                      int CINP, int co_r, int ci_r, int C, int P,
+                                                      float* __restrict__ grad, int flat)
 {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= NTAP * co_r * ci_r) return;
-  const int j = k % ci_r, co = (k / ci_r) % co_r, tap = k / (ci_r * co_r);
+  // 32 outputs per workgroup, each summed by 8 threads over a slice of g; the
+  // slices are then added in order (flat: one output per dx, whose nine taps
+  // share the sum; else one per tap)
+  constexpr int NSL = 8;
+  __shared__ float red[NSL][32][2];
+  const int jj = threadIdx.x & 31, sl = threadIdx.x >> 5;
+  const int k = blockIdx.x * 32 + jj;
+  const int nout = (flat ? 3 : NTAP) * co_r * ci_r;
   const int npt = flat ? 3 : NTAP;
-  const int ptap = flat ? tap % 3 : tap;      // tap 9 (dz + 1) + 3 (dy + 1) + (dx + 1)
-  const int col = (P > 0 && j >= C) ? j + P : j;
   float s = 0.f, s2 = 0.f;
-  for (int g = 0; g < G; ++g) {
-    const size_t row = (((size_t)g * npt + ptap) * COUTP + co) * CINP;
-    s += partial[row + col];
-    if (P > 0 && j < P) s2 += partial[row + C + j];
+  int j = 0, co = 0, tap = 0;
+  if (k < nout) {
+    j = k % ci_r;
+    co = (k / ci_r) % co_r;
+    tap = k / (ci_r * co_r);                   // flat: tap = dx + 1
+    const int col = (P > 0 && j >= C) ? j + P : j;
+    const int g0 = (int)((int64_t)G * sl / NSL), g1 = (int)((int64_t)G * (sl + 1) / NSL);
+    for (int g = g0; g < g1; ++g) {
+      const size_t row = (((size_t)g * npt + tap) * COUTP + co) * CINP;
+      s += partial[row + col];
+      if (P > 0 && j < P) s2 += partial[row + C + j];
+    }
   }
-  grad[k] += s + s2 * (1.f / 256.f);
+  red[sl][jj][0] = s;
+  red[sl][jj][1] = s2;
+  __syncthreads();
+  if (sl != 0 || k >= nout) return;
+  float t = 0.f, t2 = 0.f;
+#pragma unroll
+  for (int q = 0; q < NSL; ++q) {
+    t += red[q][jj][0];
+    t2 += red[q][jj][1];
+  }
+  const float v = t + t2 * (1.f / 256.f);
+  if (!flat) {
+    grad[k] += v;
+    return;
+  }
+  for (int yz = 0; yz < 9; ++yz)               // tap 9 (dz + 1) + 3 (dy + 1) + (dx + 1)
+    grad[((size_t)(3 * yz + tap) * co_r + co) * ci_r + j] += v;
 }
 
 // Bias gradient partials: partial[tile][c] = sum over the tile's nodes of dY[node][c]
@@ -1165,8 +1194,8 @@ void wgrad(mclbm_nn* net, const bf16* dY, const bf16* X, int layer)
                      net->dTubes, net->dTileTube, net->ntubes, nchunks, dY, X, net->wpart, net->flat_yz ? 4 : -1);
   // only the real channels have parameters (the padded ones stay zero)
   const int co_r = net->out_r[layer], ci_r = net->in_r[layer];
-  const int n = NTAP * co_r * ci_r;
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks_for(n, 256)), dim3(256), 0, net->stream, net->wpart, G,
+  const int n = (net->flat_yz ? 3 : NTAP) * co_r * ci_r;
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks_for(n, 32)), dim3(256), 0, net->stream, net->wpart, G,
                      COUT, CINP, co_r, ci_r, layer == 0 ? net->C : ci_r, layer == 0 ? net->P : 0,
                      net->grad + net->w_off[layer], net->flat_yz ? 1 : 0);
 }
