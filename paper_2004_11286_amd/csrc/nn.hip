@@ -197,13 +197,16 @@ __global__ __launch_bounds__(256) void k_conv(const NTube* __restrict__ tubes, c
     }
   };
   const int khalf = 8 * (lane >> 5);
+  // a tube one node wide in y and z wraps every (dy, dz) onto the node itself:
+  // the nine groups stage the same rows, so they are staged once
+  const bool restage = tb.ny > 1 || tb.nz > 1;
   sload(0);
   sstore();
   load_w(0);
   store_w(0);
   __syncthreads();
   for (int g = 0; g < 9; ++g) {
-    if (g + 1 < 9) sload(g + 1);
+    if (g + 1 < 9 && restage) sload(g + 1);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const int tap = 3 * g + d;
@@ -254,7 +257,7 @@ __global__ __launch_bounds__(256) void k_conv(const NTube* __restrict__ tubes, c
       if (tap + 1 < NTAP) store_w(buf ^ 1);
       __syncthreads();
     }
-    if (g + 1 < 9) {
+    if (g + 1 < 9 && restage) {
       sstore();
       __syncthreads();
     }
