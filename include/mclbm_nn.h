@@ -138,23 +138,30 @@ int mclbm_nn_mole_residual(mclbm_nn *net, int32_t species, const float *a, const
 
 /* Advance a lattice Boltzmann context by K steps with the network (trained for
  * K steps): read the fields, predict, and form the fields to install (mole
- * fractions clipped at 0 and renormalised). Their residual is the largest
- * relative change, over the tubes, of a species' mass or of the total energy of
- * the local equilibrium those fields define, against the conserved sums of the
- * current populations: the walled or periodic lattice keeps both (Sec. 2.2
- * item 1; the energy of eq g0momTotalEnergy), up to its rounding, and the
- * network, which keeps the moles by construction but predicts T and u directly,
- * does not. If the fields are a feasible state and the residual is at most
- * resid_tol, the populations are re-initialised at the local equilibrium of
- * those fields; otherwise the K lattice steps run instead (*used_fallback = 1).
- * *max_residual receives the residual (HUGE_VAL for an infeasible prediction).
- * The network's tubes must be the context's and its channels M + 5 (X_1..X_M,
- * T, u_x, u_y, u_z, p: the layout of mclbm_read_fields_f32). The step count
- * advances by K. MCLBM_ENAN if the current state is not finite;
- * MCLBM_EUNSUPPORTED for a context whose slaved species is not the last
- * (mclbm_params.slaved other than 0 or M). */
-int mclbm_nn_advance(mclbm_ctx *c, mclbm_nn *net, int32_t K, double resid_tol, int32_t *used_fallback,
-                     double *max_residual);
+ * fractions clipped at 0 and renormalised). Two quantities decide whether the
+ * prediction is used:
+ *  - its residual, the largest relative change, over the tubes, of a species'
+ *    mass or of the total energy of the local equilibrium those fields define,
+ *    against the conserved sums of the current populations: the walled or
+ *    periodic lattice keeps both (Sec. 2.2 item 1; the energy of eq
+ *    g0momTotalEnergy), up to its rounding, and the network, which keeps the
+ *    moles by construction but predicts T and u directly, does not;
+ *  - its change, the largest |X_a(new) - X_a(now)| over the nodes and species:
+ *    a trust region, since the network's error grows with the size of the hop
+ *    it predicts (large where the mixture is far from equilibrium, as just
+ *    after a sharp initial condition), which a conserved sum cannot detect.
+ * If the fields are a feasible state, the residual is at most resid_tol and the
+ * change at most change_tol (HUGE_VAL: no limit), the populations are
+ * re-initialised at the local equilibrium of those fields; otherwise the K
+ * lattice steps run instead (*used_fallback = 1). *max_residual and
+ * *max_change (either may be NULL) receive the two (HUGE_VAL for an infeasible
+ * prediction). The network's tubes must be the context's and its channels
+ * M + 5 (X_1..X_M, T, u_x, u_y, u_z, p: the layout of mclbm_read_fields_f32).
+ * The step count advances by K. MCLBM_EARG for a NaN tolerance; MCLBM_ENAN if
+ * the current state is not finite; MCLBM_EUNSUPPORTED for a context whose
+ * slaved species is not the last (mclbm_params.slaved other than 0 or M). */
+int mclbm_nn_advance(mclbm_ctx *c, mclbm_nn *net, int32_t K, double resid_tol, double change_tol,
+                     int32_t *used_fallback, double *max_residual, double *max_change);
 
 #ifdef __cplusplus
 }

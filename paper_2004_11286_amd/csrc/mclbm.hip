@@ -100,18 +100,24 @@ __global__ __launch_bounds__(BLOCK) void k_pack_f32(Launch ln, const int64_t* __
 // Predicted fields (FP32 [M+5][n_t] per tube: X_1..X_M, T, u, p) -> FP64 fields
 // for mclbm_init_fields: mole fractions clipped at zero and renormalised; a
 // block flags a node whose state the equilibria cannot represent (T <= 0,
-// p <= 0, R_a T + u^2 >= 1 for a species or the mixture, no species left).
+// p <= 0, R_a T + u^2 >= 1 for a species or the mixture, no species left) and
+// writes the largest change of a mole fraction over its nodes, the installed
+// X_a against the network's input fields `in` (same layout as pred).
 __global__ __launch_bounds__(BLOCK) void k_pred_to_state(const Params<double>* __restrict__ P, Launch ln, int M,
-                                                        const float* __restrict__ pred, double* __restrict__ X,
-                                                        double* __restrict__ p, double* __restrict__ T,
-                                                        double* __restrict__ u, int* __restrict__ block_bad)
+                                                        const float* __restrict__ in, const float* __restrict__ pred,
+                                                        double* __restrict__ X, double* __restrict__ p,
+                                                        double* __restrict__ T, double* __restrict__ u,
+                                                        int* __restrict__ block_bad, float* __restrict__ block_chg)
 {
+  __shared__ float wave_chg[BLOCK / 64];
   const kern::Where w = kern::locate(ln);
   const Params<double>& Pt = P[w.t];
   int bad = 0;
+  float chg = 0.0f;
   if (w.node < Pt.n) {
     const int64_t n = Pt.n, b = w.base, i = w.node;
     const float* f = pred + (size_t)(M + 5) * b;
+    const float* x0 = in + (size_t)(M + 5) * b;
     double xs[MAXM], sum = 0.0, mmix = 0.0;
     for (int a = 0; a < M; ++a) {
       xs[a] = fmax((double)f[(size_t)a * n + i], 0.0);
@@ -128,6 +134,7 @@ __global__ __launch_bounds__(BLOCK) void k_pred_to_state(const Params<double>* _
       xs[a] = sum > 0.0 ? xs[a] / sum : 0.0;
       mmix += xs[a] * Pt.m[a];
       if (!(Tn * Pt.inv_m[a] + usq < 1.0)) bad = 1;
+      chg = fmaxf(chg, (float)fabs(xs[a] - (double)x0[(size_t)a * n + i]));
     }
     const double pn = (double)f[(size_t)(M + 4) * n + i];
     if (!(Tn > 0.0) || !(pn > 0.0) || !(mmix > 0.0) || !(Tn / mmix + usq < 1.0)) bad = 1;
@@ -136,8 +143,15 @@ __global__ __launch_bounds__(BLOCK) void k_pred_to_state(const Params<double>* _
     p[b + i] = pn;
     for (int k = 0; k < 3; ++k) u[3 * b + (size_t)k * n + i] = uu[k];
   }
+  for (int off = 32; off > 0; off >>= 1) chg = fmaxf(chg, __shfl_xor(chg, off, 64));
+  if ((threadIdx.x & 63) == 0) wave_chg[threadIdx.x >> 6] = chg;
   bad = __syncthreads_or(bad);
-  if (threadIdx.x == 0) block_bad[w.block] = bad;
+  if (threadIdx.x == 0) {
+    float m = wave_chg[0];
+    for (int k = 1; k < BLOCK / 64; ++k) m = fmaxf(m, wave_chg[k]);
+    block_bad[w.block] = bad;
+    block_chg[w.block] = m;
+  }
 }
 
 // Conserved sums of the state mclbm_init_fields installs for FP64 fields (X, p, T,
@@ -239,6 +253,7 @@ struct mclbm_ctx {
   double* partial = nullptr;
   double* reduced = nullptr;
   int* bad = nullptr;
+  float* chg = nullptr;           // mclbm_nn_advance: largest mole-fraction change per block
   uint32_t* dFlag = nullptr;      // fixed point: range flag per tube (bit 0 re-range, bit 1 a value clamped)
   int32_t* dRange = nullptr;      // fixed point: k_range16 output [ntubes][MAXL][NCLS][2]
   double* dTab = nullptr;         // fixed point: k_rebase16 tables [ntubes][MAXL][NCLS][4]
@@ -273,7 +288,7 @@ struct mclbm_ctx {
 namespace {
 
 struct Layout {
-  size_t pd, pr, tubes, blk, blkT, tube_n, ctr, flag, range, tab, pop, rec, G, staging, partial, reduced, bad, total;
+  size_t pd, pr, tubes, blk, blkT, tube_n, ctr, flag, range, tab, pop, rec, G, staging, partial, reduced, bad, chg, total;
   int64_t n, nblocks, nblocks_tmax;
 };
 
@@ -346,6 +361,7 @@ Layout layout_for(const mclbm_params* tp, int ntubes)
   l.partial = off; off += align_up((size_t)l.nblocks * (MAXM + 6) * sizeof(double));
   l.reduced = off; off += align_up((size_t)ntubes * (MAXM + 6) * sizeof(double));
   l.bad = off; off += align_up((size_t)l.nblocks * sizeof(int));
+  l.chg = off; off += align_up((size_t)l.nblocks * sizeof(float));
   l.total = off;
   return l;
 }
@@ -1177,6 +1193,7 @@ extern "C" int mclbm_batch_create(const mclbm_params* tp, int32_t ntubes, void* 
   c->partial = (double*)(ws + lay.partial);
   c->reduced = (double*)(ws + lay.reduced);
   c->bad = (int*)(ws + lay.bad);
+  c->chg = (float*)(ws + lay.chg);
   c->hPd.resize(ntubes);
   c->hPf.resize(ntubes);
   c->hTubes.resize(ntubes);
@@ -1846,13 +1863,14 @@ extern "C" int mclbm_autotune(mclbm_ctx* c, int32_t trial_steps, char* report, s
   return MCLBM_OK;
 }
 
-extern "C" int mclbm_nn_advance(mclbm_ctx* c, mclbm_nn* net, int32_t K, double resid_tol, int32_t* used_fallback,
-                                double* max_residual)
+extern "C" int mclbm_nn_advance(mclbm_ctx* c, mclbm_nn* net, int32_t K, double resid_tol, double change_tol,
+                                int32_t* used_fallback, double* max_residual, double* max_change)
 {
   if (!c) return MCLBM_EARG;
   if (!net) return fail(c, MCLBM_EARG, "network is NULL");
   if (!c->initialised) return fail(c, MCLBM_EARG, "no state yet");
   if (K < 1) return fail(c, MCLBM_EARG, "K must be positive");
+  if (std::isnan(resid_tol) || std::isnan(change_tol)) return fail(c, MCLBM_EARG, "tolerances must not be NaN");
   if (!c->xperm_identity)
     return fail(c, MCLBM_EUNSUPPORTED, "the surrogate takes contexts whose slaved species is the last (slaved = 0)");
   const int M = c->M;
@@ -1881,14 +1899,22 @@ extern "C" int mclbm_nn_advance(mclbm_ctx* c, mclbm_nn* net, int32_t K, double r
   double *X = st, *p = st + (size_t)M * N, *T = st + (size_t)(M + 1) * N, *u = st + (size_t)(M + 2) * N;
   const unsigned grid = (unsigned)c->nblocks;
   hipLaunchKernelGGL(k_pred_to_state, dim3(grid), dim3(BLOCK), 0, c->stream, (const Params<double>*)c->dPd,
-                     launch_all(c), M, fout, X, p, T, u, c->bad);
+                     launch_all(c), M, fin, fout, X, p, T, u, c->bad, c->chg);
   rc = check_launch(c, "k_pred_to_state");
   if (rc) return rc;
   std::vector<int> bad(c->nblocks);
+  std::vector<float> chg(c->nblocks);
   HIP_TRY(c, hipMemcpyAsync(bad.data(), c->bad, sizeof(int) * c->nblocks, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(chg.data(), c->chg, sizeof(float) * c->nblocks, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   bool ok = true;
   for (int64_t b = 0; b < c->nblocks && ok; ++b) ok = bad[b] == 0;
+  // the size of the hop: the largest change of a mole fraction at any node
+  double change = HUGE_VAL;
+  if (ok) {
+    change = 0.0;
+    for (int64_t b = 0; b < c->nblocks; ++b) change = std::max(change, (double)chg[b]);
+  }
   // residual of the installed state: the largest relative change of a species'
   // mass or of the energy over any tube, which the walled or periodic lattice
   // keeps (to its rounding) and the network, predicting T and u directly, does not
@@ -1912,9 +1938,10 @@ extern "C" int mclbm_nn_advance(mclbm_ctx* c, mclbm_nn* net, int32_t K, double r
       mx = std::max(mx, std::fabs(a1[MAXM] - b0[M + 4]) / std::fabs(b0[M + 4]));
     }
     if (!std::isfinite(mx)) mx = HUGE_VAL;
-    ok = mx <= resid_tol;
+    ok = mx <= resid_tol && change <= change_tol;
   }
   if (max_residual) *max_residual = mx;
+  if (max_change) *max_change = change;
   if (ok) {
     const int64_t steps = c->steps;
     rc = mclbm_init_fields(c, X, p, T, u, 1);

@@ -138,7 +138,7 @@ def _load():
     L.mclbm_nn_adam_step.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float]
     L.mclbm_nn_clip_grad_norm.argtypes = [vp, C.c_double, dp]
     L.mclbm_nn_mole_residual.argtypes = [vp, C.c_int32, vp, vp, dp]
-    L.mclbm_nn_advance.argtypes = [vp, vp, C.c_int32, C.c_double, ip, dp]
+    L.mclbm_nn_advance.argtypes = [vp, vp, C.c_int32, C.c_double, C.c_double, ip, dp, dp]
     L.mclbm_destroy.argtypes = [vp]
     L.mclbm_destroy.restype = None
     L.mclbm_last_error.argtypes = [vp]
@@ -721,11 +721,13 @@ def mclbm_nn_mole_residual(net, species: int, a_ptr: int, b_ptr: int, ntubes: in
     return out
 
 
-def mclbm_nn_advance(ctx, net, K: int, resid_tol: float):
+def mclbm_nn_advance(ctx, net, K: int, resid_tol: float, change_tol: float = float("inf")):
     used = C.c_int32()
     res = C.c_double()
-    _check(ctx, lib.mclbm_nn_advance(ctx, net, int(K), float(resid_tol), C.byref(used), C.byref(res)))
-    return bool(used.value), res.value
+    chg = C.c_double()
+    _check(ctx, lib.mclbm_nn_advance(ctx, net, int(K), float(resid_tol), float(change_tol), C.byref(used),
+                                     C.byref(res), C.byref(chg)))
+    return bool(used.value), res.value, chg.value
 
 
 class Net:
@@ -822,6 +824,6 @@ class Net:
         b = b.reshape(-1).contiguous()
         return mclbm_nn_mole_residual(self.net, species, a.data_ptr(), b.data_ptr(), len(self.dims))
 
-    def advance(self, sim, K: int, resid_tol: float):
-        """Advance a Sim or Batch by K steps; returns (used_fallback, max_residual)."""
-        return mclbm_nn_advance(sim.ctx, self.net, K, resid_tol)
+    def advance(self, sim, K: int, resid_tol: float, change_tol: float = float("inf")):
+        """Advance a Sim or Batch by K steps; returns (used_fallback, max_residual, max_change)."""
+        return mclbm_nn_advance(sim.ctx, self.net, K, resid_tol, change_tol)

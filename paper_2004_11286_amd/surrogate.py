@@ -202,15 +202,16 @@ def train(net, snaps, iters: int, weights, lr: float = LR, seed: int = 0, log_ev
 
 
 def evaluate(params, norm, eval_tubes, K: int = K_DEFAULT, starts=(0, 500, 2000), depth: int = DEPTH,
-             resid_tol: float = 1e-4):
+             resid_tol: float = 1e-4, change_tol: float = float("inf")):
     """Judge the surrogate by the lattice: from the same state at each start
     time, K lattice steps against one network hop. Reports the mole-fraction
     error (L-infinity over all tubes), that of the persistence prediction (no
-    change), the mole residual, the residual the advance entry point gates on
-    (largest relative change of a species' mass or of the energy per tube) for
-    the network and for the K lattice steps, whether the hop was accepted, and
-    the times of the hop (read, forward, residual and re-initialisation through
-    mclbm_nn_advance) and of the K lattice steps."""
+    change), the mole residual, the two quantities the advance entry point
+    gates on (the residual, the largest relative change of a species' mass or
+    of the energy per tube, for the network and for the K lattice steps; the
+    change, the largest mole-fraction change the hop predicts), whether the hop
+    was accepted, and the times of the hop (read, forward, residual and
+    re-initialisation through mclbm_nn_advance) and of the K lattice steps."""
     import torch
 
     b = mc.Batch([p for p, _ in eval_tubes], mc.MCLBM_FP32)
@@ -247,7 +248,7 @@ def evaluate(params, norm, eval_tubes, K: int = K_DEFAULT, starts=(0, 500, 2000)
         res_lattice = net.mole_residual(M, start, want)
         # the advance entry point end to end (timed on the stream)
         e0.record(b.stream)
-        used, res_adv = net.advance(b, K, resid_tol)
+        used, res_adv, chg_adv = net.advance(b, K, resid_tol, change_tol)
         e1.record(b.stream)
         e1.synchronize()
         t_adv = e0.elapsed_time(e1)
@@ -278,7 +279,8 @@ def evaluate(params, norm, eval_tubes, K: int = K_DEFAULT, starts=(0, 500, 2000)
                     "mole_residual_max": float(np.max(res)),
                     "lattice_mole_residual_max": float(np.max(res_lattice)),
                     "state_residual": float(res_adv), "lattice_state_residual": lat_res,
-                    "resid_tol": float(resid_tol), "accepted": not used,
+                    "state_change": float(chg_adv), "resid_tol": float(resid_tol),
+                    "change_tol": float(change_tol), "accepted": not used,
                      "ms_lattice": t_lbm, "ms_advance": t_adv, "ms_forward": t_fwd})
     net.close()
     b.close()

@@ -257,7 +257,7 @@ def test_advance_falls_back_to_the_lattice(env):
     s, params = _tube_sim(mc)
     ref, _ = _tube_sim(mc)
     net = make_net(env, 3, S.he_init(C, 3, seed=4), norm_arrays(), dims=[(32, 4, 4)])
-    used, res = net.advance(s, 20, -1.0)                    # tolerance below any residual
+    used, res, _ = net.advance(s, 20, -1.0)                 # tolerance below any residual
     assert used and s.step_count == 70
     ref.step(20)
     a, b = s.read_moments(), ref.read_moments()
@@ -277,10 +277,10 @@ def test_advance_with_a_null_network_keeps_the_fields(env):
     before = s.read_moments()
     net = mc.Net(C, 3, [(32, 4, 4)])
     net.set_params(np.zeros(net.param_count, np.float32))
-    used, res = net.advance(s, 100, 1e-4)
+    used, res, chg = net.advance(s, 100, 1e-4, 1e-6)
     # the residual of the installed state: the FP32 read-back of the fields only
-    print("null network: residual of the installed state", res)
-    assert not used and res <= 1e-6 and s.step_count == 150
+    print("null network: residual of the installed state", res, "change", chg)
+    assert not used and res <= 1e-6 and chg <= 1e-6 and s.step_count == 150
     after = s.read_moments()
     for k in ("X", "T", "p"):
         np.testing.assert_allclose(after[k], before[k], rtol=2e-6, atol=1e-7)
@@ -313,7 +313,7 @@ def test_advance_rejects_a_hop_that_keeps_the_moles_but_not_the_energy(env, dT_r
     fin = net.fields_in.clone()
     net.forward()
     moles = net.mole_residual(3, fin, net.fields_out)
-    used, res = net.advance(s, 20, 1e-4)
+    used, res, _ = net.advance(s, 20, 1e-4)
     print("dT/T", dT_rel, "mole residual", moles, "state residual", res, "fallback", used)
     assert np.all(moles <= 1e-6)
     assert abs(res - dT_rel) <= 0.05 * dT_rel + 2e-7      # plus the FP32 read-back of the fields
@@ -328,6 +328,51 @@ def test_advance_rejects_a_hop_that_keeps_the_moles_but_not_the_energy(env, dT_r
         np.testing.assert_allclose(got["T"], before["T"] * (1 + dT_rel), rtol=1e-6)
     net.close()
     s.close()
+
+
+@pytest.mark.parametrize("margin,falls_back", [(0.999, True), (1.001, False)])
+def test_advance_trust_region_on_the_mole_fraction_change(env, margin, falls_back):
+    """A conservative network whose only nonzero parameters are the biases of
+    its species-1 x fluxes moves moles of species 1 between neighbouring nodes:
+    every species keeps its moles and T, u are unchanged, so the residual stays
+    at rounding level, but the mole fractions change. The reported change is the
+    largest |X_a(new) - X_a(now)| of the installed (clipped, renormalised) state,
+    recomputed here from the network's own input and output; a change tolerance
+    just below it makes the advance fall back to the lattice (bitwise its K
+    steps), one just above accepts the hop."""
+    mc, _ = env
+    s, params = _tube_sim(mc)
+    ref, _ = _tube_sim(mc)
+    net = mc.Net(C, 3, [(32, 4, 4)], species=3)
+    out_scale = np.array([3e-4] * 9 + [1e-3, 3e-4, 3e-4, 3e-4], np.float32)
+    net.set_norm(np.full(C, 0.3, np.float32), np.ones(C, np.float32), out_scale)
+    p = np.zeros(net.param_count, np.float32)
+    p[-13 + 0] = 2.0                                    # last layer's bias of species 1's x flux
+    net.set_params(p)
+    mc.mclbm_read_fields_f32(s.ctx, net.fields_in.data_ptr(), 1)
+    net.forward()
+    fin = net.fields_in.cpu().numpy().astype(np.float64).reshape(C, -1)
+    fout = net.fields_out.cpu().numpy().astype(np.float64).reshape(C, -1)
+    X = np.maximum(fout[:3], 0.0)
+    X /= X.sum(axis=0)
+    want = float(np.abs(X - fin[:3]).max())
+    used0, res0, chg0 = net.advance(ref, 20, 1.0)       # measure on a twin, accepted
+    print("twin: change", chg0, "recomputed", want, "residual", res0)
+    assert not used0 and chg0 == pytest.approx(want, rel=1e-6, abs=1e-7)
+    assert chg0 > 1e-5                                   # the hop moves the mole fractions
+    ref.close()
+    ref, _ = _tube_sim(mc)
+    used, res, chg = net.advance(s, 20, 1.0, margin * chg0)
+    print("change", chg, "residual", res, "fallback", used)
+    assert bool(used) == falls_back and s.step_count == 70 and chg == chg0
+    if falls_back:
+        ref.step(20)
+        got, want_m = s.read_moments(), ref.read_moments()
+        for k in got:
+            np.testing.assert_array_equal(got[k], want_m[k])
+    net.close()
+    s.close()
+    ref.close()
     ref.close()
 
 
@@ -527,6 +572,13 @@ def test_network_arguments_are_checked(env):
     s.init_fields(**f)
     with pytest.raises(mc.MclbmError):
         net.advance(s, 10, 1e-4)
+    s.close()
+    net.close()
+    net = mc.Net(C, 3, [(16, 2, 2)], species=3)
+    s = mc.Sim(params, mc.MCLBM_FP32)
+    s.init_fields(**f)
+    with pytest.raises(mc.MclbmError):
+        net.advance(s, 10, 1e-4, float("nan"))                        # a NaN tolerance
     s.close()
     net.close()
     with pytest.raises(mc.MclbmError):
