@@ -510,29 +510,52 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ 
 }
 
 // Bias gradient partials: partial[tile][c] = sum over the tile's nodes of dY[node][c]
-// (C <= WIDTH). The four wavefronts each sum a quarter of the tile's nodes for
-// every channel, then the quarters are added in order.
+// (C = 16, 32 or 64). Wave w takes the 16-channel chunk w % (C / 16) of every
+// (4 / (C / 16))-th group of 64 nodes starting at group w / (C / 16): each lane
+// reads the chunk's 32 contiguous bytes of its nodes (a wave covers whole
+// lines), sums them per channel, the lanes are added by a butterfly and the
+// waves of a chunk in order.
 __global__ __launch_bounds__(256) void k_bgrad(const NTube* __restrict__ tubes, const int32_t* __restrict__ tile_tube,
                                                int ntubes, int C, const bf16* __restrict__ dY,
                                                float* __restrict__ partial)
 {
-  constexpr int NQ = 256 / WIDTH, QN = TILE / NQ;
-  __shared__ float part[NQ][WIDTH];
+  __shared__ float red[4][16];
   const int tile = blockIdx.x;
   const NTube tb = tube_of(tubes, tile_tube, ntubes, tile);
   const int n_t = tb.nx * tb.ny * tb.nz;
-  const int c = threadIdx.x % WIDTH, q = threadIdx.x / WIDTH;
-  const int n0 = (tile - tb.first_tile) * TILE + q * QN;
-  float s = 0.f;
-  if (c < C)
-    for (int i = 0; i < QN && n0 + i < n_t; ++i) s += (float)dY[aidx(tb, tb.base + n0 + i, c)];
-  part[q][c] = s;
-  __syncthreads();
-  if (threadIdx.x < C) {
-    float t = 0.f;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nch = C / 16, nparts = 4 / nch;
+  const int ch = wave % nch, part = wave / nch;
+  const int t0 = (tile - tb.first_tile) * TILE;
+  float s[16];
 #pragma unroll
-    for (int k = 0; k < NQ; ++k) t += part[k][threadIdx.x];
-    partial[(size_t)tile * C + threadIdx.x] = t;
+  for (int k = 0; k < 16; ++k) s[k] = 0.f;
+  for (int i = part * 64 + lane; i < TILE; i += 64 * nparts) {
+    if (t0 + i < n_t) {
+      const bf16x8* src = (const bf16x8*)(dY + aidx(tb, tb.base + t0 + i, ch * 16));
+      const bf16x8 a = src[0], b = src[1];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        s[e] += (float)a[e];
+        s[8 + e] += (float)b[e];
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s[k] += __shfl_xor(s[k], off, 64);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) red[wave][k] = s[k];
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < C) {
+    const int c = threadIdx.x;
+    float t = 0.f;
+    for (int p = 0; p < nparts; ++p) t += red[p * nch + c / 16][c % 16];
+    partial[(size_t)tile * C + c] = t;
   }
 }
 
@@ -755,14 +778,17 @@ __global__ __launch_bounds__(256) void k_flux_change(const NTube* __restrict__ t
         (float)(at(target, M + 4) * at(target, s) / at(target, M) - at(f, M + 4) * at(f, s) / at(f, M));
 }
 
-// Row r of tube t (ny nz rows of nx nodes), species s: thread ((t's first row +
-// r) M + s) of a launch over every row of every tube (row_first[t]: rows of the
-// tubes before t).
+// Row r of tube t (ny nz rows of nx nodes), species s: wave ((t's first row + r)
+// M + s) of a launch over every row of every tube (row_first[t]: rows of the
+// tubes before t) turns the row's flux-change values into the x fluxes they
+// imply, F(x) = -sum_{x' <= x} d(x'), an inclusive prefix sum in FP64 over 64
+// nodes at a time with the running total carried between them.
 __global__ __launch_bounds__(256) void k_flux_target(const NTube* __restrict__ tubes, const int32_t* __restrict__ row_first,
                                                      int ntubes, int64_t nrows, int M, float* __restrict__ fs)
 {
-  const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (id >= nrows * M) return;
+  const int64_t id = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (id >= nrows * M) return;                 // uniform over the wave
   const int64_t row = id / M;
   const int s = (int)(id % M);
   int lo = 0, hi = ntubes - 1;                 // the tube: last t with row_first[t] <= row
@@ -773,10 +799,18 @@ __global__ __launch_bounds__(256) void k_flux_target(const NTube* __restrict__ t
   }
   const NTube tb = tubes[lo];
   float* p = fs + (tb.base + (row - row_first[lo]) * tb.nx) * M + s;
-  double acc = 0.0;
-  for (int x = 0; x < tb.nx; ++x) {
-    acc -= (double)p[(size_t)x * M];
-    p[(size_t)x * M] = (float)acc;
+  double carry = 0.0;
+  for (int x0 = 0; x0 < tb.nx; x0 += 64) {
+    const int x = x0 + lane;
+    double v = x < tb.nx ? -(double)p[(size_t)x * M] : 0.0;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const double t = __shfl_up(v, off, 64);
+      if (lane >= off) v += t;
+    }
+    v += carry;
+    if (x < tb.nx) p[(size_t)x * M] = (float)v;
+    carry = __shfl(v, 63, 64);
   }
 }
 
@@ -1478,7 +1512,7 @@ extern "C" int mclbm_nn_loss(mclbm_nn* net, const float* target, const float* ch
     float* fstar = gnode + (size_t)net->n * net->Ms;
     hipLaunchKernelGGL(k_flux_change, dim3(grid), dim3(256), 0, net->stream, net->dTubes, net->dTileTube,
                        net->ntubes, net->Ms, net->fin, target, fstar);
-    hipLaunchKernelGGL(k_flux_target, dim3(blocks_for(net->nrows * net->Ms, 256)), dim3(256), 0, net->stream,
+    hipLaunchKernelGGL(k_flux_target, dim3(blocks_for(net->nrows * net->Ms, 4)), dim3(256), 0, net->stream,
                        net->dTubes, net->dRowFirst, net->ntubes, net->nrows, net->Ms, fstar);
     hipLaunchKernelGGL(k_loss_cons, dim3(grid), dim3(256), 0, net->stream, net->dTubes, net->dTileTube,
                        net->ntubes, net->Ms, nm, 1.0 / (double)net->n, net->fout, target, net->yout, fstar, gnode,
