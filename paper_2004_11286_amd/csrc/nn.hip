@@ -60,6 +60,19 @@ __device__ __forceinline__ size_t aidx(const NTube& tb, int64_t gnode, int c)
   return (size_t)(c >> 4) * (size_t)tb.ntot * 16 + (size_t)gnode * 16 + (size_t)(c & 15);
 }
 
+// Workgroup b of a launch runs on XCD b mod 8, each with its own L2. The
+// convolution of a tile reads the rows one y or z step away, tiles nx / TILE and
+// nx ny / TILE further on; renumbering so that XCD k takes the tiles
+// [k q, (k + 1) q) (q = nb / 8, the last nb mod 8 unchanged) keeps those rows in
+// the L2 of the XCD that staged them.
+__device__ inline int xcd_tile(int b, int nb)
+{
+  constexpr int NXCD = 8;
+  const int q = nb / NXCD;
+  if (b >= q * NXCD) return b;
+  return (b % NXCD) * q + b / NXCD;
+}
+
 // The tube and tube-local node of lane-independent tile `tile`.
 __device__ inline NTube tube_of(const NTube* tubes, const int32_t* tile_tube, int ntubes, int tile)
 {
@@ -112,7 +125,7 @@ __global__ __launch_bounds__(256) void k_conv(const NTube* __restrict__ tubes, c
   __shared__ __attribute__((aligned(16))) bf16 wl[2][COUT * LS];
   __shared__ __attribute__((aligned(16))) bf16 sl[(TILE + 2) * LS];
 
-  const int tile = blockIdx.x;
+  const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
   const NTube tb = tube_of(tubes, tile_tube, ntubes, tile);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int n_t = tb.nx * tb.ny * tb.nz;
