@@ -347,7 +347,7 @@ def finite_or_null(x):
 BF16_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix-core peak
 
 
-def surrogate_bench(train_iters: int = 36000):
+def surrogate_bench(train_iters: int = 72000):
     """The learned surrogate: trained by the library's BF16 MFMA kernels on
     trajectories of a 2048-tube ensemble (every 100 steps up to 5000; the tubes
     are one-dimensional, uniform in y and z, so a one-node cross-section carries
@@ -458,7 +458,7 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-shapes", action="store_true", help="skip the block-shape sweep of the headline context")
-    ap.add_argument("--surrogate-iters", type=int, default=36000)
+    ap.add_argument("--surrogate-iters", type=int, default=72000)
     ap.add_argument("--accuracy-steps", type=int, default=1000,
                     help="steps after which the storage modes are compared with FP32 storage")
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
