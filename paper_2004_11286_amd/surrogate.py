@@ -297,7 +297,7 @@ def conv_flops_per_node(C: int, S: int, out: int, depth: int = DEPTH, width: int
     return float(sum(2 * 27 * o * i for o, i in zip(outs, ins)))
 
 
-def timed_train_step(net, snaps, weights, reps: int = 5):
+def timed_train_step(net, snaps, weights, reps: int = 20):
     """Milliseconds of one forward + loss + backward + Adam step (mean of reps)."""
     import torch
 
