@@ -522,45 +522,6 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ 
     grad[((size_t)(3 * yz + tap) * co_r + co) * ci_r + j] += v;
 }
 
-// The same reduction for layers without tied columns and with ci_r % 4 == 0:
-// a thread sums four consecutive outputs of one row (16-byte loads) over one
-// of 32 slices of g; a workgroup covers 8 such quads, so each group of 8 lanes
-// reads 128 contiguous bytes per g. The slices are added in order.
-__global__ __launch_bounds__(256) void k_wgrad_reduce4(const float* __restrict__ partial, int G, int COUTP,
-                                                       int CINP, int co_r, int ci_r, float* __restrict__ grad,
-                                                       int flat)
-{
-  constexpr int NSL = 32, NQ = 8;
-  __shared__ f32x4 red[NSL][NQ];
-  const int qq = threadIdx.x % NQ, sl = threadIdx.x / NQ;
-  const int k = (blockIdx.x * NQ + qq) * 4;
-  const int npt = flat ? 3 : NTAP;
-  const int nout = npt * co_r * ci_r;
-  f32x4 s = {0.f, 0.f, 0.f, 0.f};
-  int j = 0, co = 0, tap = 0;
-  if (k < nout) {
-    j = k % ci_r;
-    co = (k / ci_r) % co_r;
-    tap = k / (ci_r * co_r);
-    const int g0 = (int)((int64_t)G * sl / NSL), g1 = (int)((int64_t)G * (sl + 1) / NSL);
-    for (int g = g0; g < g1; ++g) s += *(const f32x4*)(partial + (((size_t)g * npt + tap) * COUTP + co) * CINP + j);
-  }
-  red[sl][qq] = s;
-  __syncthreads();
-  if (sl != 0 || k >= nout) return;
-  f32x4 t = red[0][qq];
-#pragma unroll
-  for (int q = 1; q < NSL; ++q) t += red[q][qq];
-  if (!flat) {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) grad[k + e] += t[e];
-    return;
-  }
-  for (int yz = 0; yz < 9; ++yz)               // tap 9 (dz + 1) + 3 (dy + 1) + (dx + 1)
-#pragma unroll
-    for (int e = 0; e < 4; ++e) grad[((size_t)(3 * yz + tap) * co_r + co) * ci_r + j + e] += t[e];
-}
-
 // Bias gradient partials: partial[tile][c] = sum over the tile's nodes of dY[node][c]
 // (C = 16, 32 or 64). Wave w takes the 16-channel chunk w % (C / 16) of every
 // (4 / (C / 16))-th group of 64 nodes starting at group w / (C / 16): each lane
@@ -1284,14 +1245,9 @@ void wgrad(mclbm_nn* net, const bf16* dY, const bf16* X, int layer)
   // only the real channels have parameters (the padded ones stay zero)
   const int co_r = net->out_r[layer], ci_r = net->in_r[layer];
   const int n = (net->flat_yz ? 3 : NTAP) * co_r * ci_r;
-  const int P = layer == 0 ? net->P : 0;
-  if (P == 0 && ci_r % 4 == 0)
-    hipLaunchKernelGGL(k_wgrad_reduce4, dim3(blocks_for(n / 4, 8)), dim3(256), 0, net->stream, net->wpart, G,
-                       COUT, CINP, co_r, ci_r, net->grad + net->w_off[layer], net->flat_yz ? 1 : 0);
-  else
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks_for(n, 32)), dim3(256), 0, net->stream, net->wpart, G,
-                       COUT, CINP, co_r, ci_r, layer == 0 ? net->C : ci_r, P, net->grad + net->w_off[layer],
-                       net->flat_yz ? 1 : 0);
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks_for(n, 32)), dim3(256), 0, net->stream, net->wpart, G,
+                     COUT, CINP, co_r, ci_r, layer == 0 ? net->C : ci_r, layer == 0 ? net->P : 0,
+                     net->grad + net->w_off[layer], net->flat_yz ? 1 : 0);
 }
 
 void bgrad(mclbm_nn* net, const bf16* dY, int C, int layer)
