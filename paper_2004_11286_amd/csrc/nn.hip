@@ -73,6 +73,14 @@ __device__ inline int xcd_tile(int b, int nb)
   return (b % NXCD) * q + b / NXCD;
 }
 
+// The last layer's raw FP32 output is channel-major, [COUTL][n] over the n nodes
+// of all tubes: the kernels that read it take one channel of consecutive nodes
+// per load (node-major rows would put each lane on a cache line of its own).
+__device__ __forceinline__ size_t yidx(const NTube& tb, int64_t gnode, int c)
+{
+  return (size_t)c * (size_t)tb.ntot + (size_t)gnode;
+}
+
 // The tube and tube-local node of lane-independent tile `tile`.
 __device__ inline NTube tube_of(const NTube* tubes, const int32_t* tile_tube, int ntubes, int tile)
 {
@@ -91,7 +99,7 @@ __device__ inline int64_t wrap_index(const NTube& tb, int x, int y, int z)
 // ---------------------------------------------------------------------------
 // Convolution (forward, and backward with respect to the input)
 // ---------------------------------------------------------------------------
-// EPI 0: + bias, ReLU, BF16 out; EPI 1: + bias, FP32 out; EPI 2: times the
+// EPI 0: + bias, ReLU, BF16 out; EPI 1: + bias, FP32 out (channel-major, yidx); EPI 2: times the
 // ReLU mask (mask > 0), BF16 out. EPI 0 and 1 gather forward, in(x + d) with x
 // clamped to the tube (replicate padding at the walls) and y, z wrapped; EPI 2
 // is the adjoint, in(x - d) with nothing from outside the tube, plus, at a wall
@@ -298,10 +306,8 @@ __global__ __launch_bounds__(256) void k_conv(const NTube* __restrict__ tubes, c
           for (int j = 0; j < 4; ++j) o[j] = (bf16)fmaxf(v[j], 0.f);
           *(bf16x4*)((bf16*)out + aidx(tb, gn, co0)) = o;
         } else if (EPI == 1) {
-          f32x4 o;
 #pragma unroll
-          for (int j = 0; j < 4; ++j) o[j] = v[j];
-          *(f32x4*)((float*)out + gn * COUT + co0) = o;
+          for (int j = 0; j < 4; ++j) ((float*)out)[yidx(tb, gn, co0 + j)] = v[j];
         } else {
           const bf16x4 mk = *(const bf16x4*)(mask + aidx(tb, gn, co0));
           bf16x4 o;
@@ -633,7 +639,7 @@ __global__ __launch_bounds__(256) void k_pack_in(const NTube* __restrict__ tubes
   }
 }
 
-// fields_out[c][node] = f[c][node] + y[node][c] out_scale_c.
+// fields_out[c][node] = f[c][node] + y[c][node] out_scale_c.
 __global__ __launch_bounds__(256) void k_unpack_out(const NTube* __restrict__ tubes, const int32_t* __restrict__ tile_tube,
                                                     int ntubes, int C, Norm nm, const float* __restrict__ f,
                                                     const float* __restrict__ y, float* __restrict__ fo)
@@ -645,7 +651,7 @@ __global__ __launch_bounds__(256) void k_unpack_out(const NTube* __restrict__ tu
   if (node >= n_t) return;
   const size_t o = (size_t)C * tb.base;
   for (int c = 0; c < C; ++c)
-    fo[o + (size_t)c * n_t + node] = f[o + (size_t)c * n_t + node] + y[(tb.base + node) * COUTL + c] * nm.out_scale[c];
+    fo[o + (size_t)c * n_t + node] = f[o + (size_t)c * n_t + node] + y[yidx(tb, tb.base + node, c)] * nm.out_scale[c];
 }
 
 // Loss and its gradient with respect to the raw output y: with the target
@@ -670,7 +676,7 @@ __global__ __launch_bounds__(256) void k_loss(const NTube* __restrict__ tubes, c
     for (int c = 0; c < C; ++c) {
       const size_t k = o + (size_t)c * n_t + node;
       const double r = ((double)target[k] - (double)f[k]) / nm.out_scale[c];
-      const double e = (double)y[gn * COUTL + c] - r;
+      const double e = (double)y[yidx(tb, gn, c)] - r;
       l += nm.weight[c] * e * e;
       d[c] = (bf16)(float)(2.0 * nm.weight[c] * e * inv_n);
     }
@@ -750,19 +756,19 @@ __global__ __launch_bounds__(256) void k_unpack_cons(const NTube* __restrict__ t
     double div = 0.0;
     for (int a = 0; a < 3; ++a) {
       const double sc = nm.out_scale[3 * s + a];
-      if (face_open(tb, g, a)) div += (double)y[gn * COUTL + 3 * s + a] * sc;
+      if (face_open(tb, g, a)) div += (double)y[yidx(tb, gn, 3 * s + a)] * sc;
       const bool lower = a != 0 || g.x > 0;
-      if (lower) div -= (double)y[shifted(tb, g, a, -1) * COUTL + 3 * s + a] * sc;
+      if (lower) div -= (double)y[yidx(tb, shifted(tb, g, a, -1), 3 * s + a)] * sc;
     }
     nn[s] = p * fld(s) / T - div;
     sum += nn[s];
   }
-  const double T1 = T + (double)y[gn * COUTL + 3 * M] * nm.out_scale[3 * M];
+  const double T1 = T + (double)y[yidx(tb, gn, 3 * M)] * nm.out_scale[3 * M];
   for (int s = 0; s < M; ++s) fo[o + (size_t)s * n_t + node] = (float)(nn[s] / sum);
   fo[o + (size_t)M * n_t + node] = (float)T1;
   for (int k = 0; k < 3; ++k)
     fo[o + (size_t)(M + 1 + k) * n_t + node] =
-        (float)(fld(M + 1 + k) + (double)y[gn * COUTL + 3 * M + 1 + k] * nm.out_scale[3 * M + 1 + k]);
+        (float)(fld(M + 1 + k) + (double)y[yidx(tb, gn, 3 * M + 1 + k)] * nm.out_scale[3 * M + 1 + k]);
   fo[o + (size_t)(M + 4) * n_t + node] = (float)(T1 * sum);
 }
 
@@ -860,7 +866,7 @@ __global__ __launch_bounds__(256) void k_loss_cons(const NTube* __restrict__ tub
     const double wf = nm.weight[M + 4];
     if (wf != 0.0 && node % tb.nx + 1 < tb.nx) {
       for (int s = 0; s < M; ++s) {
-        const double e = (double)y[gn * COUTL + 3 * s] * nm.out_scale[3 * s] - (double)fs[gn * M + s];
+        const double e = (double)y[yidx(tb, gn, 3 * s)] * nm.out_scale[3 * s] - (double)fs[gn * M + s];
         l += wf * e * e;
       }
     }
@@ -911,7 +917,7 @@ __global__ __launch_bounds__(256) void k_loss_cons_flux(const NTube* __restrict_
     for (int s = 0; s < M; ++s) {
       double v = open ? (double)(gn_in[up * M + s] - gn_in[gn * M + s]) : 0.0;
       if (a == 0 && open && nm.weight[M + 4] != 0.f)
-        v += 2.0 * nm.weight[M + 4] * ((double)y[gn * COUTL + 3 * s] * nm.out_scale[3 * s] - (double)fs[gn * M + s]) *
+        v += 2.0 * nm.weight[M + 4] * ((double)y[yidx(tb, gn, 3 * s)] * nm.out_scale[3 * s] - (double)fs[gn * M + s]) *
              inv_n;
       dY[aidx(tb, gn, 3 * s + a)] = (bf16)(float)(v * nm.out_scale[3 * s + a]);
     }
@@ -1065,7 +1071,7 @@ struct mclbm_nn {
   std::vector<bf16*> wf, wb;            // packed BF16 weights per layer
   std::vector<float*> bp;               // padded biases per layer
   std::vector<bf16*> act;               // act[0] packed input, act[l+1] output of layer l (hidden)
-  float* yout = nullptr;                // raw output of the last layer [n][COUTL]
+  float* yout = nullptr;                // raw output of the last layer [COUTL][n]
   bf16* dy[2] = {nullptr, nullptr};     // activation gradients (ping-pong), [n][WIDTH]
   bf16* dyl = nullptr;                  // gradient of the last layer's output [n][COUTL]
   float* wpart = nullptr;               // weight-gradient partials
