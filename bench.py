@@ -398,11 +398,7 @@ def surrogate_bench(train_iters: int = 72000):
         cal_tubes = W.tube_ensemble(ntubes=8, ny=32, nz=32, lmin=128, lmax=128, seed=seed)
         for r in SG.evaluate(params, norm, cal_tubes, K=100, starts=cal_starts, resid_tol=0.0):
             cal.append(dict(r, seed=seed))
-    good = [r for r in cal if r["X_linf"] <= 1e-3]
-    bad = [r for r in cal if r["X_linf"] > 1e-3]
-    bad_min = min((r["state_change"] for r in bad), default=float("inf"))
-    below = [r["state_change"] for r in good if r["state_change"] < bad_min]
-    change_tol = max(below) if below else 0.0
+    change_tol = SG.calibrate_change_tol(cal, 1e-3)
     resid_tol = 1e-3
     admitted = [r for r in cal if r["state_change"] <= change_tol and r["state_residual"] <= resid_tol]
     calibration = {"tubes": "three sets of 8 held-out ternary tubes 128x32x32 (seeds "

@@ -288,6 +288,18 @@ def evaluate(params, norm, eval_tubes, K: int = K_DEFAULT, starts=(0, 500, 2000)
     return out
 
 
+def calibrate_change_tol(hops, bar: float = 1e-3) -> float:
+    """The advance gate's change threshold from calibration hops judged by the
+    lattice (dicts with "X_linf", the hop's mole-fraction error, and
+    "state_change", the largest change it predicts): the largest change among
+    hops within `bar` that lies strictly below the change of every hop outside
+    it, so that every calibration hop with a change at most the threshold is
+    within the bar; 0 when no hop qualifies."""
+    bad_min = min((h["state_change"] for h in hops if h["X_linf"] > bar), default=float("inf"))
+    below = [h["state_change"] for h in hops if h["X_linf"] <= bar and h["state_change"] < bad_min]
+    return max(below) if below else 0.0
+
+
 def conv_flops_per_node(C: int, S: int, out: int, depth: int = DEPTH, width: int = 64) -> float:
     """Multiply-adds x 2 of one forward pass per node over the real channels
     (layer 0: fields, second terms and conditioning, C + S inputs; last layer:
